@@ -1,0 +1,26 @@
+"""Seeded synthetic inputs: sparse matrices, nonoverlapping partitions and
+right-hand sides.
+
+This package holds no arithmetic of the preconditioner. It only builds the
+problem that the method is given (a sparse matrix A, a partition of the
+unknowns into N sets, and b), so both the CPU oracle and the GPU library can
+be fed the same inputs. Seeds come from NumPy's PCG64 (default_rng).
+"""
+
+from .problems import (  # noqa: F401
+    CONFIGS,
+    Problem,
+    box_partition_2d,
+    box_partition_3d,
+    convdiff_2d,
+    elasticity_q1_3d,
+    fv_diffusion_2d,
+    fv_diffusion_3d,
+    high_contrast_kappa_2d,
+    lognormal_kappa_3d,
+    make_config,
+    poisson_2d,
+    rcb_partition,
+    rhs,
+    worked_example_7x7,
+)
