@@ -1,0 +1,255 @@
+"""Benchmark: time-to-solve (setup + PCG to relative residual 1e-8) and
+preconditioner applies/s of the two-level Schwarz preconditioner on one
+MI355X, mixed precision (FP32 local / FP64 outer and coarse) against plain
+FP64 on the same GPU.
+
+Workload (default): 2D high-contrast finite-volume diffusion on a 1024x1024
+grid (n = 1,048,576), coefficient log-uniform in [1, 1e6] plus 20 channels at
+1e6, 256 subdomains from randomised recursive coordinate bisection (cut ratio
+uniform in [0.3, 0.7]), overlap 2, 16 coarse vectors per subdomain, b ~ N(0,1),
+all seeded and synthetic. A step is one pass of the whole hot path: setup
+(overlap, local matrices, batched factorization, coarse basis, A_0 and its
+factor) plus the PCG solve. Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line. Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solve (rel res 1e-8) + precond applies/s: mixed/batched vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def local_lower_bytes(info, w):
+    """Algorithmic bytes of one forward + one backward sweep over the lower
+    triangles of the local factors, m(m+1)/2 words each:
+    2 * w * sum_i m_i (m_i + 1) / 2 = w * (sum m^2 + sum m)."""
+    return float(w) * (float(info["local_sum_m2"]) + float(info["local_sum_m"]))
+
+
+def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tol=1e-8):
+    import torch
+
+    import paper_2401_03915_amd as tls
+    rp, ci, val, part, b = dev_in
+    A = prob.A
+    n, nnz = A.shape[0], A.nnz
+    stream = torch.cuda.current_stream()
+
+    def make_opt(profile=0):
+        opt = tls.tls_default_options()
+        opt.precision = precision
+        opt.use_graph = use_graph
+        opt.profile = profile
+        opt.stream = stream.cuda_stream or None
+        return opt
+
+    def step(opt):
+        ctx = tls.tls_setup(n, nnz, rp.data_ptr(), ci.data_ptr(), val.data_ptr(), part.data_ptr(), prob.n_parts,
+                            prob.overlap, prob.nev, opt)
+        x = torch.empty_like(b)
+        st, it, rr = tls.tls_solve(ctx, b.data_ptr(), x.data_ptr(), tol)
+        return ctx, x, st, it, rr
+
+    for w in range(warmup):
+        log(f"precision {precision}: warmup {w}")
+        ctx, x, st, it, rr = step(make_opt())
+        tls.tls_destroy(ctx)
+    torch.cuda.synchronize()
+    ctxs = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ctx, x, st, it, rr = step(make_opt())
+        ctxs.append((ctx, st, it, rr))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    ctx, st, it, rr = ctxs[-1]
+    info = tls.tls_info(ctx)
+    log(f"precision {precision}: {ms_per_step:.1f} ms/step, {it} iterations, relres {rr:.2e}, status {st}")
+    for c, *_ in ctxs[:-1]:
+        tls.tls_destroy(c)
+    # applies/s on the last context (plain launches, events on the stream)
+    r = torch.randn(n, dtype=torch.float64, device=b.device, generator=torch.Generator(device=b.device).manual_seed(7))
+    z = torch.empty_like(r)
+    for _ in range(3):
+        tls.tls_apply(ctx, r.data_ptr(), z.data_ptr())
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(n_applies):
+        tls.tls_apply(ctx, r.data_ptr(), z.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1) / n_applies
+    tls.tls_destroy(ctx)
+    # kernel-level timing of the local triangular solves (HIP events inside the library)
+    ctxp = tls.tls_setup(n, nnz, rp.data_ptr(), ci.data_ptr(), val.data_ptr(), part.data_ptr(), prob.n_parts,
+                         prob.overlap, prob.nev, make_opt(profile=1))
+    for _ in range(n_applies):
+        tls.tls_apply(ctxp, r.data_ptr(), z.data_ptr())
+    torch.cuda.synchronize()
+    pinfo = tls.tls_info(ctxp)
+    tls.tls_destroy(ctxp)
+    return {
+        "ms_per_step": ms_per_step,
+        "iters": it,
+        "relres": rr,
+        "status": st,
+        "apply_ms": apply_ms,
+        "applies_per_s": 1e3 / apply_ms,
+        "local_solve_ms": pinfo["t_local_solve_ms"],
+        "apply_ms_profiled": pinfo["t_apply_ms"],
+        "info": info,
+        "z": z,
+    }
+
+
+def cpu_baseline(prob, iters, sample=3, seed=0):
+    """The FP64 oracle on a bounded sample: per-subdomain setup (overlap,
+    local matrix, sparse LU, eq. gevpsvd by ARPACK, coarse block) and one
+    local solve, for `sample` seeded subdomains; scaled to the full
+    time-to-solve as N * mean(setup) + iterations * N * mean(solve)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import schwarz
+    rng = np.random.default_rng(seed)
+    picks = rng.choice(prob.n_parts, size=min(sample, prob.n_parts), replace=False)
+    t_setup, t_solve, sizes = [], [], []
+    with threadpool_limits(1):
+        import scipy.sparse.linalg as spla
+        for i in picks:
+            t0 = time.perf_counter()
+            s = schwarz.overlap(prob.A, prob.part, int(i), prob.overlap)
+            Aii = schwarz.local_matrix(prob.A, s)
+            lu = spla.splu(Aii.tocsc())
+            schwarz.coarse_block(Aii, s, prob.nev, 0, True)
+            t1 = time.perf_counter()
+            lu.solve(np.ones(s.size))
+            t2 = time.perf_counter()
+            t_setup.append(t1 - t0)
+            t_solve.append(t2 - t1)
+            sizes.append(s.size)
+    N = prob.n_parts
+    est = N * float(np.mean(t_setup)) + iters * N * float(np.mean(t_solve))
+    return {
+        "value": est,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{len(picks)} of {N} subdomains (ids {sorted(int(p) for p in picks)}, sizes {sizes}): "
+                   f"per-subdomain oracle setup {np.mean(t_setup):.2f} s, local solve {np.mean(t_solve) * 1e3:.1f} ms; "
+                   f"scaled to N*setup + {iters} iterations * N * solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=None, help="smaller grid side (testing only)")
+    ap.add_argument("--applies", type=int, default=20)
+    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); multi-GPU runs are not part of "
+              "this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from workloads import make_config
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    log("generating workload")
+    prob = make_config(args.config, seed=0, scale=args.scale)
+    A = prob.A
+    dev = torch.device("cuda:0")
+    dev_in = (torch.as_tensor(A.indptr.astype(np.int32), device=dev),
+              torch.as_tensor(A.indices.astype(np.int32), device=dev),
+              torch.as_tensor(A.data.astype(np.float64), device=dev),
+              torch.as_tensor(prob.part.astype(np.int32), device=dev),
+              torch.as_tensor(prob.b, device=dev))
+    torch.cuda.synchronize()
+    log(f"n={A.shape[0]} nnz={A.nnz} parts={prob.n_parts} overlap={prob.overlap} nev={prob.nev}")
+    mixed = run_mode(prob, dev_in, 1, args.steps, args.warmup, args.applies, args.graph)
+    plain = None
+    if not args.no_fp64:
+        plain = run_mode(prob, dev_in, 0, args.steps, args.warmup, args.applies, args.graph)
+    info = mixed["info"]
+    sizes_bytes32 = local_lower_bytes(info, 4)
+    achieved = sizes_bytes32 / (mixed["local_solve_ms"] * 1e-3) / 1e9 if mixed["local_solve_ms"] > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": "k_trsv<float> forward + backward (local solves of one apply)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch_pair": sizes_bytes32, "launch_pair_ms": mixed["local_solve_ms"]}
+    apply_err = None
+    if plain is not None:
+        z32, z64 = mixed["z"], plain["z"]
+        apply_err = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
+    out = {
+        "metric": METRIC,
+        "value": round(mixed["ms_per_step"] / 1e3, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms_per_step"], 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-local/f64-outer",
+        "data": "synthetic (seeded), inputs resident in HBM",
+        "config": {"workload": f"cfg{args.config}: " + ("2D high-contrast FV diffusion 1024x1024, 256 RCB parts, "
+                                                          "overlap 2, nev 16, PCG to 1e-8" if args.config == 2
+                                                          else prob.name),
+                   "n": int(A.shape[0]), "nnz": int(A.nnz), "parts": prob.n_parts, "overlap": prob.overlap,
+                   "nev": prob.nev, "scale": args.scale, "graph": args.graph},
+        "applies_per_s": round(mixed["applies_per_s"], 2),
+        "mixed": {"time_to_solve_s": round(mixed["ms_per_step"] / 1e3, 4), "iters": mixed["iters"],
+                  "relres": mixed["relres"], "applies_per_s": round(mixed["applies_per_s"], 2),
+                  "setup_ms": [round(t, 2) for t in info["t_setup"]], "solve_ms": round(info["t_solve"], 2),
+                  "n_coarse": info["n_coarse"], "gc": info["gc"], "oc": info["oc"],
+                  "eig_resid_max": info["eig_resid_max"], "eig_iters_max": info["eig_iters_max"]},
+        "roofline": roof,
+    }
+    if plain is not None:
+        pinf = plain["info"]
+        b64 = local_lower_bytes(pinf, 8)
+        ach64 = b64 / (plain["local_solve_ms"] * 1e-3) / 1e9 if plain["local_solve_ms"] > 0 else 0.0
+        out["plain_fp64"] = {"time_to_solve_s": round(plain["ms_per_step"] / 1e3, 4), "iters": plain["iters"],
+                             "relres": plain["relres"], "applies_per_s": round(plain["applies_per_s"], 2),
+                             "setup_ms": [round(t, 2) for t in pinf["t_setup"]], "solve_ms": round(pinf["t_solve"], 2),
+                             "n_coarse": pinf["n_coarse"], "local_solve_GBps": round(ach64, 1),
+                             "local_solve_frac": round(ach64 / HBM_PEAK_GBS, 4)}
+        out["speedup_mixed_vs_fp64"] = round(plain["ms_per_step"] / mixed["ms_per_step"], 3)
+        out["apply_rel_diff_mixed_vs_fp64_own_bases"] = apply_err
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(prob, (plain or mixed)["iters"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * tls.h - C ABI of the two-level additive Schwarz library for MI355X (gfx950).
+ *
+ * Method: Al Daas, Jolivet, Nataf, Tournier, "A robust two-level Schwarz
+ * preconditioner for sparse matrices" (arXiv 2401.03915). The library builds,
+ * for a sparse A, a nonoverlapping partition and an overlap width delta, the
+ * preconditioner
+ *
+ *     M^{-1} r = sum_i R_i^T A_ii^{-1} R_i r + R_0^T A_00^{-1} R_0 r
+ *
+ * (Remark after Section 4.4; one-level part eq. onelevelasm), with the
+ * coarse space of eq. coarse_space_2 for SPD A (dominant eigenvectors of
+ * eq. gevpsvd, optionally of eq. uppergevp) or of Section 6 for general A
+ * (dominant left singular vectors of D_i Pi_i), and applies it inside PCG or
+ * right-preconditioned flexible GMRES (Section 7.2).
+ *
+ * Conventions for every entry point:
+ *  - Indices are 0-based int32. CSR columns are sorted and unique in every
+ *    row; A is square n x n; part[j] is in [0, n_parts) and every part is
+ *    non-empty.
+ *  - Matrix and vector pointers passed to tls_setup, tls_apply, tls_solve
+ *    and tls_spmv are DEVICE pointers (memory allocated on the current HIP
+ *    device, e.g. by PyTorch). The library never frees caller memory and
+ *    keeps no pointer to it after the call returns: tls_setup deep-copies A
+ *    and part.
+ *  - All work is ordered on tls_options.stream (a hipStream_t). NULL makes
+ *    the context create its own blocking stream, which the legacy default
+ *    stream waits for and vice versa. tls_setup and tls_solve return after the stream
+ *    has finished their work; tls_apply and tls_spmv are asynchronous on the
+ *    stream.
+ *  - Errors: every call returns a tls_status; no C++ exception crosses the
+ *    ABI. A per-context message is available from tls_last_error. On a
+ *    setup failure *out is set to NULL and the reason is available from
+ *    tls_last_error(NULL) (thread-local).
+ *  - The context is not thread safe: calls on one context must not overlap.
+ */
+#ifndef TLS_H
+#define TLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tls_ctx tls_ctx;
+
+typedef enum {
+  TLS_OK = 0,
+  TLS_E_ARG = 1,       /* invalid argument or malformed input              */
+  TLS_E_NOT_SPD = 2,   /* non-positive pivot in a Cholesky factorization    */
+  TLS_E_SINGULAR = 3,  /* zero (or non-finite) pivot in an LU factorization */
+  TLS_E_NOCONV = 4,    /* Krylov solver hit maxit; best iterate returned    */
+  TLS_E_NOMEM = 5,     /* device allocation failed                          */
+  TLS_E_HIP = 6,       /* a HIP runtime call failed                         */
+  TLS_E_STATE = 7      /* call not valid for this context (e.g. NULL ctx)   */
+} tls_status;
+
+typedef struct {
+  /* 0: every local and global quantity in FP64.
+   * 1: local factorizations, triangular solves and the local eigensolver in
+   *    FP32 (FP32 accumulation); SpMV, Krylov vectors, dot products, the
+   *    coarse basis, A_0 and its factor stay FP64. */
+  int32_t precision;
+  /* 0: A is SPD: Cholesky, eq. gevpsvd (+ eq. uppergevp if nev1 > 0), PCG.
+   * 1: general A: LU without pivoting, Section 6 SVD variant, FGMRES.     */
+  int32_t matrix_kind;
+  /* eq. uppergevp vectors kept per subdomain (those with lambda > nu).
+   * The paper's SPD experiments use none (Section 7); default 0. */
+  int32_t nev1;
+  /* Thresholds: keep lambda^2 > tau^2 (eq. gevpsvd) or sigma > tau
+   * (Section 6), and lambda > nu (eq. uppergevp), each capped by the
+   * count. tau <= 0 means "count only"; nu defaults to 1. */
+  double tau;
+  double nu;
+  int32_t restart;      /* FGMRES restart length m (default 30)            */
+  int32_t maxit;        /* Krylov iteration cap (default 1000; 3000 general) */
+  int32_t eig_maxit;    /* local subspace-iteration cap (default 300)      */
+  double eig_tol;       /* relative eigen-residual tolerance (default 1e-8 FP64, 1e-5 FP32) */
+  int32_t eig_oversample; /* block size p = nev + oversample (default nev) */
+  uint64_t seed;        /* seed of the counter-based start vectors         */
+  int32_t use_graph;    /* capture Krylov iteration chunks in a hipGraph   */
+  int32_t flexible;     /* PCG: Polak-Ribiere beta (default: 1 iff precision == 1) */
+  int32_t jacobi_scale; /* symmetric diagonal scaling of each A_ii before factoring */
+  int32_t profile;      /* tls_apply times its local triangular-solve kernels with HIP
+                           events (and then waits for them); see tls_info_t */
+  void* stream;         /* hipStream_t */
+} tls_options;
+
+typedef struct {
+  int32_t n;
+  int32_t n_parts;
+  int32_t n_coarse;           /* n_C = number of columns of R_0^T            */
+  double gc;                  /* grid complexity 1 + n_C / n (Section 7)     */
+  double oc;                  /* operator complexity 1 + nnz(A_0) / nnz(A)   */
+  int64_t local_sum_m;        /* sum_i #Omega_i                              */
+  int64_t local_sum_m2;       /* sum_i #Omega_i^2                            */
+  int64_t factor_bytes;       /* bytes of the stored local factors           */
+  int32_t max_m;              /* max_i #Omega_i                              */
+  int32_t min_m;              /* min_i #Omega_i                              */
+  double t_setup[8];          /* ms: overlap, gather, factor, eigen, coarse basis, A_0, A_0 factor, total */
+  double t_solve;             /* ms of the last tls_solve                    */
+  int32_t iters;              /* iterations of the last tls_solve            */
+  double relres;              /* true relative residual of the last solve    */
+  double eig_resid_max;       /* max relative eigen-residual over subdomains */
+  int32_t eig_iters_max;      /* max subspace iterations over subdomains     */
+  int32_t n_res_history;      /* entries in res_history                      */
+  int32_t n_profiled;         /* tls_apply calls timed with profile = 1       */
+  double t_local_solve_ms;    /* mean duration of their local forward + backward
+                                 triangular-solve kernels (HIP events)       */
+  double t_apply_ms;          /* mean duration of those whole applies         */
+  const double* res_history;  /* host array: ||r_k|| / ||b|| per iteration   */
+} tls_info_t;
+
+/* Fill *opt with the defaults listed above. */
+void tls_default_options(tls_options* opt);
+
+/* Build the preconditioner (Sections 2-6): overlap layers, local matrices
+ * A_ii = R_i A R_i^T, their factorization, the coarse basis Z, A_0 = Z^T A Z
+ * and its factorization.
+ *   n, nnz        : size and number of stored entries of A
+ *   row_ptr[n+1], col_idx[nnz], val[nnz] : CSR of A (device)
+ *   part[n]       : nonoverlapping partition (device), values in [0, n_parts)
+ *   overlap       : delta >= 0 layers; 0 allows nev = 0 only
+ *   nev           : eq. gevpsvd (SPD) / Section 6 (general) vectors kept per subdomain
+ *   opt           : options (NULL = defaults)
+ *   out           : receives the new context; NULL on failure
+ * Errors: TLS_E_ARG (malformed CSR/partition, overlap 0 with nev > 0, NaN),
+ * TLS_E_NOT_SPD, TLS_E_SINGULAR, TLS_E_NOMEM, TLS_E_HIP. */
+tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                     const double* val, const int32_t* part, int32_t n_parts, int32_t overlap,
+                     int32_t nev, const tls_options* opt, tls_ctx** out);
+
+/* z = M^{-1} r (device vectors of length n, r != z). Asynchronous. */
+tls_status tls_apply(tls_ctx* c, const double* r, double* z);
+
+/* y = A x with the stored CSR copy (device vectors, x != y). Asynchronous. */
+tls_status tls_spmv(tls_ctx* c, const double* x, double* y);
+
+/* Solve A x = b from x0 = 0 with PCG (SPD) or FGMRES(restart) (general),
+ * right preconditioned by M^{-1}, until ||b - A x|| / ||b|| <= tol.
+ * b, x: device vectors (b != x). iters, relres (true residual at exit) may
+ * be NULL. Returns TLS_E_NOCONV with the last iterate if maxit is reached. */
+tls_status tls_solve(tls_ctx* c, const double* b, double* x, double tol, int32_t* iters,
+                     double* relres);
+
+/* Statistics of the context (host struct; res_history stays valid until
+ * the next tls_solve or tls_destroy). */
+tls_status tls_info(const tls_ctx* c, tls_info_t* info);
+
+/* Copy internal setup products to host buffers for inspection (testing and
+ * diagnostics). Each pointer may be NULL to skip it.
+ *   sub_ptr[n_parts+1], sub_idx[sum #Omega_i] : ordered Omega_i lists
+ *   layer_ptr[n_parts*(overlap+2)]            : per subdomain, offsets of I_i,
+ *                                               Gamma_1 .. Gamma_delta, end
+ *   zcol_ptr[n_parts+1]                       : first coarse column per subdomain
+ *   eigvals[n_coarse]                         : kept lambda^2 (SPD) / sigma (general)
+ *   Z[n * n_coarse]                           : dense column-major coarse basis
+ *   A0[n_coarse * n_coarse]                   : dense column-major A_0          */
+tls_status tls_export(const tls_ctx* c, int32_t* sub_ptr, int32_t* sub_idx, int32_t* layer_ptr,
+                      int32_t* zcol_ptr, double* eigvals, double* Z, double* A0);
+
+/* Solve with one local factor: x = A_ii^{-1} b for subdomain i (host
+ * vectors of length #Omega_i, in the Omega_i order). Diagnostics. */
+tls_status tls_local_solve(tls_ctx* c, int32_t i, const double* b, double* x);
+
+/* Last error message of the context (or of the calling thread's last failed
+ * tls_setup when c is NULL). Never NULL. */
+const char* tls_last_error(const tls_ctx* c);
+
+/* Free everything the context owns. NULL is ignored. */
+void tls_destroy(tls_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLS_H */

@@ -1,0 +1,134 @@
+"""MI355X two-level additive Schwarz preconditioner (HIP for gfx950).
+
+The method is the fully algebraic two-level Schwarz preconditioner of
+Al Daas, Jolivet, Nataf and Tournier (arXiv 2401.03915). All of its steps run
+in the HIP library ``libtls.so`` behind the C ABI of ``include/tls.h``; this
+package only moves PyTorch device tensors across that boundary.
+
+``Preconditioner`` is a convenience wrapper: it uploads a SciPy CSR matrix
+and a partition with PyTorch, calls ``tls_setup``, and exposes ``apply``,
+``solve``, ``spmv``, ``info`` and ``export``.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+from ._lib import (TlsError, tls_apply, tls_default_options, tls_destroy, tls_export, tls_info,  # noqa: F401
+                   tls_local_solve, tls_setup, tls_solve, tls_spmv)
+
+__all__ = ["Preconditioner", "TlsError", "tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve",
+           "tls_info", "tls_export", "tls_local_solve", "tls_destroy"]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2401_03915_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+class Preconditioner:
+    """Two-level Schwarz preconditioner of a CSR matrix on ``device``.
+
+    Options are the fields of ``tls_options`` (precision, matrix_kind, nev1,
+    tau, nu, restart, maxit, eig_maxit, eig_tol, eig_oversample, seed,
+    use_graph, flexible, jacobi_scale). ``stream`` may be a torch.cuda.Stream
+    on which all library work is ordered.
+    """
+
+    def __init__(self, A, part, overlap: int, nev: int, device: str = "cuda:0", stream=None, **options):
+        torch = _torch()
+        self.device = torch.device(device)
+        A = A.tocsr()
+        self.n = A.shape[0]
+        self.nnz = A.nnz
+        self.n_parts = int(np.max(part)) + 1
+        self.overlap = overlap
+        self.nev = nev
+        dev = self.device
+        self._rp = torch.as_tensor(np.asarray(A.indptr, dtype=np.int32), device=dev)
+        self._ci = torch.as_tensor(np.asarray(A.indices, dtype=np.int32), device=dev)
+        self._val = torch.as_tensor(np.asarray(A.data, dtype=np.float64), device=dev)
+        self._part = torch.as_tensor(np.asarray(part, dtype=np.int32), device=dev)
+        opt = tls_default_options()
+        for k, v in options.items():
+            if not hasattr(opt, k) or k == "stream":
+                raise TypeError(f"unknown option {k}")
+            setattr(opt, k, v)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        # 0 (the legacy default stream) lets the library create a blocking stream
+        opt.stream = stream.cuda_stream or None
+        torch.cuda.synchronize(dev)
+        self.ctx = tls_setup(self.n, self.nnz, self._rp.data_ptr(), self._ci.data_ptr(), self._val.data_ptr(),
+                             self._part.data_ptr(), self.n_parts, overlap, nev, opt)
+        self.options = opt
+
+    # -- device-side calls -------------------------------------------------
+    def apply(self, r, z=None):
+        """z = M^{-1} r for a float64 device tensor r (asynchronous on the stream)."""
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(r)
+        tls_apply(self.ctx, r.data_ptr(), z.data_ptr())
+        return z
+
+    def spmv(self, x, y=None):
+        torch = _torch()
+        if y is None:
+            y = torch.empty_like(x)
+        tls_spmv(self.ctx, x.data_ptr(), y.data_ptr())
+        return y
+
+    def solve(self, b, tol: float = 1e-8, x=None):
+        """Returns (x, iterations, true relative residual, status)."""
+        torch = _torch()
+        if x is None:
+            x = torch.empty_like(b)
+        st, it, rr = tls_solve(self.ctx, b.data_ptr(), x.data_ptr(), tol)
+        return x, it, rr, st
+
+    def info(self) -> dict:
+        return tls_info(self.ctx)
+
+    def export(self, Z: bool = False, A0: bool = False) -> dict:
+        inf = self.info()
+        N, nC = self.n_parts, inf["n_coarse"]
+        out = {
+            "sub_ptr": np.zeros(N + 1, dtype=np.int32),
+            "layer_ptr": np.zeros(N * (self.overlap + 2), dtype=np.int32),
+            "zcol_ptr": np.zeros(N + 1, dtype=np.int32),
+            "eigvals": np.zeros(max(nC, 1)),
+        }
+        tls_export(self.ctx, sub_ptr=out["sub_ptr"])
+        out["sub_idx"] = np.zeros(int(out["sub_ptr"][-1]), dtype=np.int32)
+        if Z:
+            out["Z"] = np.zeros((nC, self.n))  # row a = coarse column a
+        if A0:
+            out["A0"] = np.zeros((nC, nC))
+        tls_export(self.ctx, sub_ptr=out["sub_ptr"], sub_idx=out["sub_idx"], layer_ptr=out["layer_ptr"],
+                   zcol_ptr=out["zcol_ptr"], eigvals=out["eigvals"], Z=out.get("Z"), A0=out.get("A0"))
+        out["eigvals"] = out["eigvals"][:nC]
+        if Z:
+            out["Z"] = out["Z"].T.copy()  # n x nC
+        return out
+
+    def local_solve(self, i: int, b: np.ndarray) -> np.ndarray:
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros_like(b)
+        tls_local_solve(self.ctx, i, b, x)
+        return x
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            tls_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

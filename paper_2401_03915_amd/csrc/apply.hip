@@ -1,0 +1,101 @@
+// z = M_2^{-1} r = sum_i R_i^T A_ii^{-1} R_i r + R_0^T A_00^{-1} R_0 r
+// (Remark after Section 4.4). Steps on the stream:
+//   1. gather R_i r into the padded local vectors (cast to the local
+//      precision, Jacobi-scaled if enabled) and R_0 r = Z^T r;
+//   2. forward and backward local solves (persistent kernels);
+//   3. coarse forward and backward solves with the FP64 factor of A_0;
+//   4. z = sum over the owners of each row (fixed order, no atomics)
+//      + Z y0 on the rows I_i.
+#include "kernels.hpp"
+
+namespace tls {
+
+namespace {
+
+template <class T>
+__global__ void k_apply_gather(int total, const int* __restrict__ sub_idx, const int* __restrict__ sub_of_pos,
+                               const int* __restrict__ sub_ptr, const int64_t* __restrict__ voff,
+                               const double* __restrict__ scale, const double* __restrict__ r, T* xloc,
+                               const int* __restrict__ done) {
+  if (*done) return;
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  int i = sub_of_pos[p];
+  int64_t pos = voff[i] + (p - sub_ptr[i]);
+  double v = r[sub_idx[p]];
+  if (scale) v *= scale[pos];
+  xloc[pos] = (T)v;
+}
+
+template <class T>
+__global__ void k_apply_scatter(int n, const int* __restrict__ own_ptr, const int64_t* __restrict__ own_pos,
+                                const T* __restrict__ xloc, const double* __restrict__ scale,
+                                const int* __restrict__ part, const int* __restrict__ ipos,
+                                const int* __restrict__ nI, const int* __restrict__ kz,
+                                const int* __restrict__ zcol, const int64_t* __restrict__ zoff,
+                                const double* __restrict__ Z, const double* __restrict__ y0, double* z,
+                                const int* __restrict__ done) {
+  if (*done) return;
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  double s = 0.0;
+  for (int e = own_ptr[g]; e < own_ptr[g + 1]; e++) {
+    int64_t pos = own_pos[e];
+    double v = (double)xloc[pos];
+    if (scale) v *= scale[pos];
+    s += v;
+  }
+  if (y0) {
+    int p = part[g];
+    int k = kz[p];
+    const double* zp = Z + zoff[p] + ipos[g];
+    const double* yp = y0 + zcol[p];
+    const int ld = nI[p];
+    for (int a = 0; a < k; a++) s += zp[(int64_t)a * ld] * yp[a];
+  }
+  z[g] = s;
+}
+
+template <class T>
+void apply_impl(tls_ctx* c, const double* r, double* z, const int* done, T* xloc, bool profile) {
+  hipStream_t s = c->stream;
+  if (profile) {
+    for (auto& e : c->prof_ev)
+      if (!e) TLS_HIP(hipEventCreate(&e));
+    TLS_HIP(hipEventRecord(c->prof_ev[0], s));
+  }
+  const int total = c->h_sub_ptr[c->N];
+  const double* scale = c->opt.jacobi_scale ? c->scale.p : nullptr;
+  hipLaunchKernelGGL(k_apply_gather<T>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
+                     c->sub_of_pos.p, c->sub_ptr.p, c->d_voff.p, scale, r, xloc, done);
+  TLS_LAUNCH_CHECK();
+  coarse_restrict(c, r, done);
+  local_solve(c, done, profile ? c->prof_ev[1] : nullptr, profile ? c->prof_ev[2] : nullptr);
+  coarse_solve(c, done);
+  const bool coarse = c->nC > 0;
+  hipLaunchKernelGGL(k_apply_scatter<T>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->own_ptr.p,
+                     c->own_pos.p, xloc, scale, c->part.p, c->ipos.p, c->d_nI.p, coarse ? c->kz_dev.p : nullptr,
+                     c->zcol.p, c->zoff.p, c->Z.p, coarse ? c->y0.p : nullptr, z, done);
+  TLS_LAUNCH_CHECK();
+  if (profile) {
+    TLS_HIP(hipEventRecord(c->prof_ev[3], s));
+    TLS_HIP(hipEventSynchronize(c->prof_ev[3]));
+    float t_local = 0.f, t_all = 0.f;
+    TLS_HIP(hipEventElapsedTime(&t_local, c->prof_ev[1], c->prof_ev[2]));
+    TLS_HIP(hipEventElapsedTime(&t_all, c->prof_ev[0], c->prof_ev[3]));
+    c->prof_local_ms += t_local;
+    c->prof_apply_ms += t_all;
+    c->prof_count++;
+  }
+}
+
+}  // namespace
+
+void apply_precond(tls_ctx* c, const double* r, double* z, const int* done, bool profile) {
+  if (c->fp32)
+    apply_impl<float>(c, r, z, done, c->xloc32.p, profile);
+  else
+    apply_impl<double>(c, r, z, done, c->xloc64.p, profile);
+}
+
+}  // namespace tls

@@ -1,0 +1,37 @@
+// Batched small dense kernels shared by the coarse-basis and coarse-operator
+// builders: variable-size MFMA GEMM and triangular solves with many
+// right-hand sides.
+#pragma once
+
+#include "common.hpp"
+
+namespace tls {
+
+// C[m + n*ldc] = alpha * sum_k opA(m,k) opB(k,n) + beta * C[m + n*ldc]
+// opA(m,k) = transA ? A[k + m*lda] : A[m + k*lda] (same for B).
+struct GemmDesc {
+  int M, N, K;
+  int lda, ldb;
+  int64_t a_off, b_off, c_off;
+  int64_t ldc;
+};
+
+template <class T>
+void batched_gemm(hipStream_t s, const std::vector<GemmDesc>& d, bool transA, bool transB, const T* A,
+                  const T* B, T* C, T alpha, T beta);
+
+// In-place triangular solves with a column-major n x n triangular matrix
+// (leading dimension n) and nrhs right-hand sides (leading dimension ldb):
+//   LOWER_FWD: M lower, solve M X = B (forward substitution)
+//   UPPER_BWD: M upper, solve M X = B (backward substitution)
+enum TriMode { LOWER_FWD = 0, UPPER_BWD = 1 };
+struct TriDesc {
+  int n, nrhs;
+  int64_t m_off, b_off;
+  int64_t ldb;
+};
+
+template <class T>
+void batched_trsm(hipStream_t s, const std::vector<TriDesc>& d, TriMode mode, const T* M, T* B, int* err);
+
+}  // namespace tls

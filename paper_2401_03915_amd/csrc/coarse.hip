@@ -1,0 +1,232 @@
+// Galerkin coarse operator A_00 = R_0 A R_0^T = Z^T A Z (Section 4.1), its
+// FP64 factorization, and the coarse correction R_0^T A_00^{-1} R_0 r of the
+// apply.
+//
+// Z is block-diagonal over the nonoverlapping partition (D_i is zero outside
+// I_i), so block (p, q) of Z^T A Z is nonzero only for subdomains p, q that
+// are adjacent in graph(A). For each p the rows I_p of A Z restricted to the
+// columns of p's neighbours are formed by a row-owned SpMM (deterministic),
+// then the block row Z_p^T (A Z)_{I_p, .} is one MFMA GEMM.
+#include <algorithm>
+
+#include "batched.hpp"
+#include "kernels.hpp"
+
+namespace tls {
+
+namespace {
+
+__global__ void k_adjacency(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ part,
+                            int N, uint8_t* adj) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  int p = part[g];
+  for (int j = rp[g]; j < rp[g + 1]; j++) adj[(size_t)p * N + part[ci[j]]] = 1;
+}
+
+// W_p[ipos(g) + (slotoff + b) * nI_p] = sum_{c in row g, part c = q} A_gc Z_q[ipos(c), b]
+__global__ void k_az(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
+                     const int* __restrict__ part, const int* __restrict__ ipos, const int* __restrict__ nI,
+                     const int* __restrict__ adj_ptr, const int* __restrict__ adj_q, const int* __restrict__ adj_col,
+                     const int64_t* __restrict__ woff, const int* __restrict__ kz, const int64_t* __restrict__ zoff,
+                     const double* __restrict__ Z, double* W) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int p = part[g];
+  const int j = ipos[g];
+  const int nIp = nI[p];
+  double* Wp = W + woff[p];
+  for (int e = rp[g]; e < rp[g + 1]; e++) {
+    const int c = ci[e];
+    const int q = part[c];
+    const int kq = kz[q];
+    if (kq == 0) continue;
+    int lo = adj_ptr[p], hi = adj_ptr[p + 1] - 1;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (adj_q[mid] < q)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    const int co = adj_col[lo];
+    const double a = val[e];
+    const double* Zq = Z + zoff[q] + ipos[c];
+    const int nIq = nI[q];
+    for (int b = 0; b < kq; b++) Wp[j + (int64_t)(co + b) * nIp] += a * Zq[(int64_t)b * nIq];
+  }
+}
+
+// scatter block row p (k_p x ncols) into the lower tile storage of A_0
+__global__ void k_scatter_a0(int N, const int* __restrict__ kz, const int* __restrict__ zcol,
+                             const int* __restrict__ adj_ptr, const int* __restrict__ adj_q,
+                             const int* __restrict__ adj_col, const int64_t* __restrict__ boff, const double* __restrict__ B,
+                             int nt0, double* A0) {
+  const int p = blockIdx.x;
+  const int kp = kz[p];
+  if (kp == 0) return;
+  for (int s = adj_ptr[p]; s < adj_ptr[p + 1]; s++) {
+    const int q = adj_q[s];
+    const int kq = kz[q];
+    const int co = adj_col[s];
+    for (int e = threadIdx.x; e < kp * kq; e += blockDim.x) {
+      int a = e % kp, b = e / kp;
+      int R = zcol[p] + a, Cc = zcol[q] + b;
+      if (R >= Cc) *elem_ptr(A0, 0, nt0, R, Cc) = B[boff[p] + a + (int64_t)(co + b) * kp];
+    }
+  }
+}
+
+__global__ void k_pad_identity0(int nC, int M0, int nt0, double* A0) {
+  for (int a = nC + blockIdx.x * blockDim.x + threadIdx.x; a < M0; a += gridDim.x * blockDim.x)
+    *elem_ptr(A0, 0, nt0, a, a) = 1.0;
+}
+
+// y0[zcol_p + a] = sum_{j < nI_p} Z_p[j, a] r[I_p[j]]
+__global__ void __launch_bounds__(256) k_restrict(const int* __restrict__ kz, const int* __restrict__ zcol,
+                                                  const int* __restrict__ nI, const int* __restrict__ sub_ptr,
+                                                  const int* __restrict__ sub_idx, const int64_t* __restrict__ zoff,
+                                                  const double* __restrict__ Z, const double* __restrict__ r,
+                                                  double* y0, const int* __restrict__ done) {
+  if (*done) return;
+  const int p = blockIdx.y, a = blockIdx.x;
+  if (a >= kz[p]) return;
+  const int n = nI[p];
+  const double* z = Z + zoff[p] + (int64_t)a * n;
+  const int* idx = sub_idx + sub_ptr[p];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) s += z[j] * r[idx[j]];
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) y0[zcol[p] + a] = red[0] + red[1] + red[2] + red[3];
+}
+
+}  // namespace
+
+void build_coarse_operator(tls_ctx* c) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  if (c->nC == 0) {
+    c->nnz0 = 0;
+    return;
+  }
+  std::vector<int> kz(N);
+  for (int i = 0; i < N; i++) kz[i] = c->h_zcol[i + 1] - c->h_zcol[i];
+  // subdomain adjacency
+  DBuf<uint8_t> adj;
+  adj.alloc((size_t)N * N);
+  TLS_HIP(hipMemsetAsync(adj.p, 0, (size_t)N * N, s));
+  hipLaunchKernelGGL(k_adjacency, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->row_ptr.p, c->col_idx.p,
+                     c->part.p, N, adj.p);
+  TLS_LAUNCH_CHECK();
+  auto h_adj = download(adj.p, (size_t)N * N, s);
+  std::vector<int> adj_ptr(N + 1, 0), adj_q, adj_col;
+  std::vector<int64_t> woff(N + 1, 0), boff(N + 1, 0);
+  int64_t nnz0 = 0;
+  for (int p = 0; p < N; p++) {
+    int col = 0;
+    for (int q = 0; q < N; q++)
+      if (h_adj[(size_t)p * N + q] && kz[q] > 0) {
+        adj_q.push_back(q);
+        adj_col.push_back(col);
+        col += kz[q];
+      }
+    adj_ptr[p + 1] = (int)adj_q.size();
+    woff[p + 1] = woff[p] + (int64_t)c->h_nI[p] * col;
+    boff[p + 1] = boff[p] + (int64_t)kz[p] * col;
+    nnz0 += (int64_t)kz[p] * col;
+  }
+  c->nnz0 = nnz0;
+  DBuf<int> d_adj_ptr, d_adj_q, d_adj_col, d_kz;
+  DBuf<int64_t> d_woff, d_boff;
+  d_adj_ptr.upload(adj_ptr, s);
+  d_adj_q.upload(adj_q, s);
+  d_adj_col.upload(adj_col, s);
+  d_kz.upload(kz, s);
+  d_woff.upload(woff, s);
+  d_boff.upload(boff, s);
+  DBuf<double> W, B;
+  W.alloc(woff[N]);
+  B.alloc(boff[N]);
+  TLS_HIP(hipMemsetAsync(W.p, 0, sizeof(double) * woff[N], s));
+  hipLaunchKernelGGL(k_az, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->row_ptr.p, c->col_idx.p, c->val.p,
+                     c->part.p, c->ipos.p, c->d_nI.p, d_adj_ptr.p, d_adj_q.p, d_adj_col.p, d_woff.p, d_kz.p,
+                     c->zoff.p, c->Z.p, W.p);
+  TLS_LAUNCH_CHECK();
+  // block rows Z_p^T W_p (MFMA fp64)
+  std::vector<GemmDesc> gd;
+  for (int p = 0; p < N; p++) {
+    int ncols = 0;
+    for (int sidx = adj_ptr[p]; sidx < adj_ptr[p + 1]; sidx++) ncols += kz[adj_q[sidx]];
+    if (kz[p] == 0 || ncols == 0) continue;
+    gd.push_back(GemmDesc{kz[p], ncols, c->h_nI[p], c->h_nI[p], c->h_nI[p], c->h_zoff[p], woff[p], boff[p],
+                          (int64_t)kz[p]});
+  }
+  batched_gemm<double>(s, gd, true, false, c->Z.p, W.p, B.p, 1.0, 0.0);
+  W.release();
+  // tile storage of A_0
+  c->M0 = div_up(c->nC, TS) * TS;
+  c->nt0 = c->M0 / TS;
+  const int64_t a0_elems = tiles_of(0, c->nt0) * TS2;
+  c->A0.alloc(a0_elems);
+  TLS_HIP(hipMemsetAsync(c->A0.p, 0, sizeof(double) * a0_elems, s));
+  hipLaunchKernelGGL(k_scatter_a0, dim3(N), dim3(256), 0, s, N, d_kz.p, c->zcol.p, d_adj_ptr.p, d_adj_q.p,
+                     d_adj_col.p, d_boff.p, B.p, c->nt0, c->A0.p);
+  hipLaunchKernelGGL(k_pad_identity0, dim3(1), dim3(64), 0, s, c->nC, c->M0, c->nt0, c->A0.p);
+  TLS_LAUNCH_CHECK();
+  TLS_HIP(hipStreamSynchronize(s));
+  c->kz_dev.upload(kz, s);
+  // single-matrix layout for the coarse factor and solves
+  std::vector<int> one_m{c->nC}, one_nt{c->nt0};
+  std::vector<int64_t> zero64{0, a0_elems}, voff{0, c->M0}, toff{0, c->nt0};
+  c->one_m.upload(one_m, s);
+  c->one_nI.upload(one_m, s);
+  c->one_nP.upload(one_m, s);
+  c->one_nt.upload(one_nt, s);
+  c->one_foff.upload(zero64, s);
+  c->one_voff.upload(voff, s);
+  c->one_toff.upload(toff, s);
+  c->A0_orig.alloc(a0_elems);
+  TLS_HIP(hipMemcpyAsync(c->A0_orig.p, c->A0.p, sizeof(double) * a0_elems, hipMemcpyDeviceToDevice, s));
+  TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
+  factor_tiles_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->errflag.p);
+  if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT)
+    fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
+  std::vector<int2> f, b;
+  make_tasks(one_nt, toff, f, b);
+  c->tasks0_fwd.upload(f, s);
+  c->tasks0_bwd.upload(b, s);
+  c->flags0_fwd.alloc(c->nt0);
+  c->flags0_bwd.alloc(c->nt0);
+  c->counters0.alloc(4);
+  c->y0.alloc(c->M0);
+  TLS_HIP(hipMemsetAsync(c->flags0_fwd.p, 0, sizeof(int) * c->nt0, s));
+  TLS_HIP(hipMemsetAsync(c->flags0_bwd.p, 0, sizeof(int) * c->nt0, s));
+  TLS_HIP(hipMemsetAsync(c->counters0.p, 0, sizeof(int) * 4, s));
+  TLS_HIP(hipMemsetAsync(c->y0.p, 0, sizeof(double) * c->M0, s));
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+void coarse_restrict(tls_ctx* c, const double* r, const int* done) {
+  if (c->nC == 0) return;
+  int kmax = 0;
+  for (int i = 0; i < c->N; i++) kmax = std::max(kmax, c->h_zcol[i + 1] - c->h_zcol[i]);
+  hipLaunchKernelGGL(k_restrict, dim3(kmax, c->N), dim3(256), 0, c->stream, c->kz_dev.p, c->zcol.p, c->d_nI.p,
+                     c->sub_ptr.p, c->sub_idx.p, c->zoff.p, c->Z.p, r, c->y0.p, done);
+  TLS_LAUNCH_CHECK();
+}
+
+void coarse_solve(tls_ctx* c, const int* done) {
+  if (c->nC == 0) return;
+  hipStream_t s = c->stream;
+  solve_begin(s, c->counters0.p, done);
+  const int nt = (int)c->tasks0_fwd.n;
+  trsv_f64(s, false, c->tasks0_fwd.p, nt, c->counters0.p + 0, c->flags0_fwd.p, c->counters0.p + 2, c->layout0(),
+           c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
+  trsv_f64(s, true, c->tasks0_bwd.p, nt, c->counters0.p + 1, c->flags0_bwd.p, c->counters0.p + 2, c->layout0(),
+           c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
+}
+
+}  // namespace tls

@@ -1,0 +1,127 @@
+// Shared definitions of the two-level Schwarz library (gfx950, HIP).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tls.h"
+
+namespace tls {
+
+// ---------------------------------------------------------------------------
+// Errors. Internal code throws TlsError; the C ABI converts it to a status.
+// ---------------------------------------------------------------------------
+struct TlsError {
+  tls_status code;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(tls_status code, const std::string& msg) { throw TlsError{code, msg}; }
+
+#define TLS_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      ::tls::fail(TLS_E_HIP, std::string(#call) + " failed: " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define TLS_LAUNCH_CHECK() TLS_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Device buffer owned by a context (freed on destruction).
+// ---------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(TLS_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    alloc(h.size());
+    if (!h.empty()) TLS_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  operator T*() const { return p; }
+};
+
+template <class T>
+inline std::vector<T> download(const T* d, size_t count, hipStream_t s) {
+  std::vector<T> h(count);
+  if (count) {
+    TLS_HIP(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    TLS_HIP(hipStreamSynchronize(s));
+  }
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// Dense tile storage of the local factors.
+//
+// Subdomain i of padded size M_i = nt_i * TS is stored as square TS x TS
+// tiles, column-major inside a tile. SPD (Cholesky): only the lower tiles
+// (r >= c), packed row by row: tile (r, c) has index r(r+1)/2 + c. General
+// (LU): all nt_i^2 tiles, index r * nt_i + c. The padding rows/columns hold
+// the identity, so the factor of the padded matrix is diag(L, I).
+// ---------------------------------------------------------------------------
+constexpr int TS = 64;
+constexpr int TS2 = TS * TS;
+
+__host__ __device__ inline int64_t tile_index(int kind, int nt, int r, int c) {
+  return kind == 0 ? (int64_t)r * (r + 1) / 2 + c : (int64_t)r * nt + c;
+}
+__host__ __device__ inline int64_t tiles_of(int kind, int nt) {
+  return kind == 0 ? (int64_t)nt * (nt + 1) / 2 : (int64_t)nt * nt;
+}
+// element (a, b) of the padded local matrix stored at base
+template <class T>
+__device__ inline T* elem_ptr(T* base, int kind, int nt, int a, int b) {
+  return base + tile_index(kind, nt, a / TS, b / TS) * TS2 + (b % TS) * TS + (a % TS);
+}
+
+// Per-subdomain layout table shared by the factor, the solves and the
+// eigensolver (device copy of host vectors).
+struct LocalLayout {
+  const int* m;        // #Omega_i
+  const int* nI;       // #I_i
+  const int* nP;       // #Omega_{i,1:delta-1}
+  const int* nt;       // tiles per side
+  const int64_t* foff; // element offset of the factor of i
+  const int64_t* voff; // offset of i's padded vector (M_i entries)
+  const int64_t* toff; // offset of i's first tile row in the flag arrays (= sum nt_j)
+};
+
+// Error bits reported by kernels into a device int.
+enum : int {
+  ERR_CSR = 1,
+  ERR_PART = 2,
+  ERR_NAN = 4,
+  ERR_PIVOT = 8,
+  ERR_WAIT = 16,
+  ERR_EIG = 32,
+};
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace tls

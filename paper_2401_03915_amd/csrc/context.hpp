@@ -1,0 +1,116 @@
+// Library context: everything tls_setup builds and tls_apply / tls_solve use.
+#pragma once
+
+#include "common.hpp"
+
+struct tls_ctx {
+  tls_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // problem
+  int n = 0, nnz = 0, N = 0, delta = 0, nev = 0;
+  int kind = 0;  // 0 SPD / Cholesky, 1 general / LU
+  bool fp32 = false;
+  tls::DBuf<int> row_ptr, col_idx, part;
+  tls::DBuf<double> val;
+  tls::DBuf<int> trow_ptr, tcol_idx;  // pattern of A^T (general matrices)
+  int spmv_group = 4;
+
+  // overlap: Omega_i lists (global ids) in [I, Gamma_1, .., Gamma_delta] order
+  std::vector<int> h_sub_ptr;    // N+1
+  std::vector<int> h_layer_ptr;  // N*(delta+2): per subdomain segment starts (absolute) and end
+  std::vector<int> h_m, h_nI, h_nP, h_nt;
+  std::vector<int64_t> h_foff, h_voff, h_toff;
+  tls::DBuf<int> sub_ptr, sub_idx, layer_ptr, sub_of_pos;
+  tls::DBuf<int> d_m, d_nI, d_nP, d_nt;
+  tls::DBuf<int64_t> d_foff, d_voff, d_toff;
+  int64_t sum_m = 0, sum_m2 = 0, sum_M = 0, sum_nt = 0, fac_elems = 0;
+  int max_nt = 0;
+  tls::DBuf<int> ipos;  // position of each global row inside its interior list
+
+  // scatter map: for each global row, the padded positions holding it
+  tls::DBuf<int> own_ptr;
+  tls::DBuf<int64_t> own_pos;
+
+  // local factors (fp64 or fp32 depending on the precision option)
+  tls::DBuf<double> fac64;
+  tls::DBuf<float> fac32;
+  tls::DBuf<double> scale;  // Jacobi scaling per padded position (or empty)
+
+  // factorization schedule: subdomains sorted by nt (desc); per step prefix tables
+  std::vector<int> h_order;
+  tls::DBuf<int> order;
+  std::vector<int> h_active;  // number of active subdomains at step k
+  std::vector<int64_t> h_pref_off;  // offset into the prefix tables for step k
+  tls::DBuf<int64_t> pref_trsm, pref_upd;
+  std::vector<int64_t> h_cnt_trsm, h_cnt_upd;
+
+  // triangular-solve task lists and flags
+  tls::DBuf<int2> tasks_fwd, tasks_bwd;
+  tls::DBuf<int> flags_fwd, flags_bwd;
+  tls::DBuf<int> counters;  // [0] fwd task counter, [1] bwd task counter, [2] epoch
+  int solve_grid = 1024;
+
+  // work vectors for the apply (padded local layout)
+  tls::DBuf<double> xloc64;
+  tls::DBuf<float> xloc32;
+
+  // coarse space
+  int nC = 0, M0 = 0, nt0 = 0;
+  std::vector<int> h_zcol;  // N+1 column offsets
+  std::vector<double> h_eig;
+  tls::DBuf<int> zcol;
+  tls::DBuf<double> Z;      // per subdomain #I_i x k_i column-major, concatenated
+  std::vector<int64_t> h_zoff;
+  tls::DBuf<int64_t> zoff;
+  tls::DBuf<double> A0;     // tile storage of A_0 (then its factor)
+  tls::DBuf<double> A0_orig;  // lower tiles of A_0 before factorization (export)
+  tls::DBuf<int> kz_dev;    // coarse columns per subdomain
+  tls::DBuf<double> y0;     // coarse vector (padded to M0)
+  tls::DBuf<int2> tasks0_fwd, tasks0_bwd;
+  tls::DBuf<int> flags0_fwd, flags0_bwd;
+  tls::DBuf<int> counters0;
+  tls::DBuf<int> one_m, one_nI, one_nP, one_nt;
+  tls::DBuf<int64_t> one_foff, one_voff, one_toff;
+  double eig_resid_max = 0;
+  int eig_iters_max = 0;
+  int64_t nnz0 = 0;
+
+  // Krylov work
+  tls::DBuf<double> kr;        // vectors
+  tls::DBuf<double> scal;      // device scalars
+  tls::DBuf<double> partial;   // reduction partials
+  tls::DBuf<int> done;         // [0]: converged flag, [1]: iterations
+  tls::DBuf<double> hist;      // residual history
+  std::vector<double> h_hist;
+  tls::DBuf<int> zero_int;     // constant 0 for "not done"
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_chunk = 0, graph_maxit = 0;
+  double graph_tol2 = 0;
+  bool graph_flex = false;
+
+  // diagnostics
+  hipEvent_t prof_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int prof_count = 0;
+  double prof_local_ms = 0, prof_apply_ms = 0;
+  tls::DBuf<int> errflag;
+  double t_setup[8] = {0};
+  double t_solve = 0;
+  int last_iters = 0;
+  double last_relres = 0;
+
+  tls::LocalLayout layout() const {
+    return tls::LocalLayout{d_m, d_nI, d_nP, d_nt, d_foff, d_voff, d_toff};
+  }
+  tls::LocalLayout layout0() const {
+    return tls::LocalLayout{one_m, one_nI, one_nP, one_nt, one_foff, one_voff, one_toff};
+  }
+  ~tls_ctx() {
+    for (auto& e : prof_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};

@@ -1,0 +1,602 @@
+// Local matrices A_ii = R_i A R_i^T (Section 2.3), their batched dense
+// factorization, and the batched triangular solves that apply A_ii^{-1}
+// (eq. onelevelasm) - the HBM-bound hot loop of every preconditioner apply.
+//
+// Factorization: right-looking tiled Cholesky over all subdomains at once.
+// Step k factors the diagonal tile (k,k) of every subdomain with nt_i > k
+// (one workgroup each, in LDS), solves the tiles below it (one wave per
+// tile), then updates every trailing lower tile with a 64x64x64 MFMA
+// product (one workgroup per tile). Subdomains are sorted by size, so the
+// active set at step k is a prefix and tile indices are decoded from
+// per-step prefix tables.
+//
+// Triangular solves: one persistent kernel per direction. A task is one
+// 64-row block of one subdomain; tasks are handed out in dependency order by
+// an atomic counter, a task waits (bounded spin) on per-block ready flags of
+// the blocks it reads, streams its tiles through a 256-thread GEMV and
+// finishes with a one-wave substitution on the diagonal tile.
+#include <algorithm>
+#include <numeric>
+
+#include "kernels.hpp"
+#include "mfma.hpp"
+
+namespace tls {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Gather
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void k_pad_identity(int N, LocalLayout lay, int kind, T* fac) {
+  int i = blockIdx.x;
+  int m = lay.m[i], nt = lay.nt[i];
+  T* base = fac + lay.foff[i];
+  for (int a = m + threadIdx.x; a < nt * TS; a += blockDim.x) *elem_ptr(base, kind, nt, a, a) = T(1);
+}
+
+// scale[voff_i + a] = 1 / sqrt(A[g][g]) for the Jacobi-scaled variant
+__global__ void k_jacobi_scale(int total, const int* __restrict__ sub_idx, const int* __restrict__ sub_of_pos,
+                               const int* __restrict__ sub_ptr, const int64_t* __restrict__ voff,
+                               const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ val, double* scale, int* err) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  int g = sub_idx[p];
+  int i = sub_of_pos[p];
+  double d = 0.0;
+  for (int j = rp[g]; j < rp[g + 1]; j++)
+    if (ci[j] == g) d = val[j];
+  if (!(d > 0.0)) {
+    atomicOr(err, ERR_PIVOT);
+    d = 1.0;
+  }
+  scale[voff[i] + (p - sub_ptr[i])] = 1.0 / sqrt(d);
+}
+
+template <class T>
+__global__ void k_gather(int total, int n, const int* __restrict__ sub_idx, const int* __restrict__ sub_of_pos,
+                         const int* __restrict__ sub_ptr, const int* __restrict__ layer_ptr, int stride,
+                         const uint8_t* __restrict__ dist, const int* __restrict__ rp,
+                         const int* __restrict__ ci, const double* __restrict__ val,
+                         const double* __restrict__ scale, LocalLayout lay, int kind, T* fac) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  int i = sub_of_pos[p];
+  int a = p - sub_ptr[i];
+  int g = sub_idx[p];
+  int nt = lay.nt[i];
+  T* base = fac + lay.foff[i];
+  const uint8_t* drow = dist + (size_t)i * n;
+  const int* lp = layer_ptr + (size_t)i * stride;
+  double sa = scale ? scale[lay.voff[i] + a] : 1.0;
+  for (int j = rp[g]; j < rp[g + 1]; j++) {
+    int c = ci[j];
+    int d = drow[c];
+    if (d == 0xFF) continue;  // c is not in Omega_i
+    // binary search of c in the (ascending) segment of level d
+    int lo = lp[d], hi = lp[d + 1] - 1;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (sub_idx[mid] < c)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    int b = lo - sub_ptr[i];
+    if (kind == 0 && b > a) continue;  // Cholesky stores the lower triangle
+    double v = val[j];
+    if (scale) v *= sa * scale[lay.voff[i] + b];
+    *elem_ptr(base, kind, nt, a, b) = (T)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched tiled Cholesky
+// ---------------------------------------------------------------------------
+
+__device__ inline int find_slot(const int64_t* pref, int count, int64_t bid) {
+  // largest j in [0, count) with pref[j] <= bid
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pref[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_potrf(int k, const int* __restrict__ order, LocalLayout lay, T* fac,
+                                               int* err) {
+  constexpr int LD = TS + 1;
+  __shared__ T s[TS * LD];
+  int i = order[blockIdx.x];
+  int nt = lay.nt[i];
+  T* tile = fac + lay.foff[i] + tile_index(0, nt, k, k) * TS2;
+  const int t = threadIdx.x;
+  for (int e = t; e < TS2; e += 256) s[(e / TS) * LD + (e % TS)] = tile[e];
+  bool bad = false;
+  for (int j = 0; j < TS; j++) {
+    __syncthreads();
+    T d = s[j * LD + j];
+    if (!(d > T(0))) {
+      bad = true;
+      d = T(1);
+    }
+    d = sqrt(d);
+    __syncthreads();
+    if (t == j) s[j * LD + j] = d;
+    if (t > j && t < TS) s[j * LD + t] /= d;
+    __syncthreads();
+    for (int e = t; e < TS2; e += 256) {
+      int a = e % TS, b = e / TS;
+      if (b > j && a >= b) s[b * LD + a] -= s[j * LD + a] * s[j * LD + b];
+    }
+  }
+  __syncthreads();
+  if (bad && t == 0) atomicOr(err, ERR_PIVOT);
+  for (int e = t; e < TS2; e += 256) {
+    int a = e % TS, b = e / TS;
+    tile[e] = a >= b ? s[b * LD + a] : T(0);
+  }
+}
+
+// X L_kk^T = A_rk for one tile below the diagonal; one thread per row.
+template <class T>
+__global__ void __launch_bounds__(64) k_trsm(int k, const int64_t* __restrict__ pref, int nact,
+                                             const int* __restrict__ order, LocalLayout lay, T* fac) {
+  constexpr int LD = TS + 1;
+  __shared__ T Ls[TS * LD];
+  int64_t bid = blockIdx.x;
+  int j = find_slot(pref, nact, bid);
+  int i = order[j];
+  int nt = lay.nt[i];
+  int r = k + 1 + (int)(bid - pref[j]);
+  T* base = fac + lay.foff[i];
+  const T* L = base + tile_index(0, nt, k, k) * TS2;
+  T* A = base + tile_index(0, nt, r, k) * TS2;
+  const int a = threadIdx.x;
+  for (int e = a; e < TS2; e += 64) Ls[(e / TS) * LD + (e % TS)] = L[e];
+  T x[TS];
+#pragma unroll
+  for (int b = 0; b < TS; b++) x[b] = A[b * TS + a];
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < TS; b++) {
+    T sum = x[b];
+#pragma unroll
+    for (int l = 0; l < b; l++) sum -= x[l] * Ls[l * LD + b];
+    x[b] = sum / Ls[b * LD + b];
+  }
+#pragma unroll
+  for (int b = 0; b < TS; b++) A[b * TS + a] = x[b];
+}
+
+template <class T>
+struct LdsLd;
+template <>
+struct LdsLd<float> {
+  static constexpr int v = TS + 16;
+};
+template <>
+struct LdsLd<double> {
+  static constexpr int v = TS;
+};
+
+// C_rc -= L_rk L_ck^T for one trailing lower tile (k < c <= r): MFMA.
+template <class T>
+__global__ void __launch_bounds__(256) k_update(int k, const int64_t* __restrict__ pref, int nact,
+                                                const int* __restrict__ order, LocalLayout lay, T* fac) {
+  constexpr int LD = LdsLd<T>::v;
+  __shared__ T As[TS * LD];
+  __shared__ T Bs[TS * LD];
+  int64_t bid = blockIdx.x;
+  int j = find_slot(pref, nact, bid);
+  int i = order[j];
+  int nt = lay.nt[i];
+  int64_t t = bid - pref[j];
+  int rr = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(rr + 1) * (rr + 2) / 2 <= t) rr++;
+  while ((int64_t)rr * (rr + 1) / 2 > t) rr--;
+  int cc = (int)(t - (int64_t)rr * (rr + 1) / 2);
+  int r = k + 1 + rr, c = k + 1 + cc;
+  T* base = fac + lay.foff[i];
+  const T* Lr = base + tile_index(0, nt, r, k) * TS2;
+  const T* Lc = base + tile_index(0, nt, c, k) * TS2;
+  T* C = base + tile_index(0, nt, r, c) * TS2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TS2; e += 256) {
+    int a = e % TS, b = e / TS;
+    As[b * LD + a] = Lr[e];
+    Bs[b * LD + a] = Lc[e];
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < TS; kk += 4) {
+    T a0 = As[(kk + lk) * LD + wr + li];
+    T a1 = As[(kk + lk) * LD + wr + 16 + li];
+    T b0 = Bs[(kk + lk) * LD + wc + li];
+    T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
+    acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+    acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+    acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+    acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int row = wr + 16 * x + Mfma<T>::row(lane, q);
+        C[col * TS + row] -= acc[x][y][q];
+      }
+    }
+}
+
+template <class T>
+void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, int* err) {
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
+  int maxnt = N ? nt[order[0]] : 0;
+  std::vector<int64_t> pt, pu, off(maxnt + 1, 0), tot_t(maxnt), tot_u(maxnt);
+  std::vector<int> act(maxnt);
+  for (int k = 0; k < maxnt; k++) {
+    off[k] = (int64_t)pt.size();
+    int64_t ct = 0, cu = 0;
+    int a = 0;
+    while (a < N && nt[order[a]] > k) {
+      pt.push_back(ct);
+      pu.push_back(cu);
+      int64_t T_ = nt[order[a]] - k - 1;
+      ct += T_;
+      cu += T_ * (T_ + 1) / 2;
+      a++;
+    }
+    pt.push_back(ct);
+    pu.push_back(cu);
+    act[k] = a;
+    tot_t[k] = ct;
+    tot_u[k] = cu;
+  }
+  DBuf<int> d_order;
+  DBuf<int64_t> d_pt, d_pu;
+  d_order.upload(order, s);
+  d_pt.upload(pt, s);
+  d_pu.upload(pu, s);
+  for (int k = 0; k < maxnt; k++) {
+    hipLaunchKernelGGL(k_potrf<T>, dim3(act[k]), dim3(256), 0, s, k, d_order.p, lay, fac, err);
+    TLS_LAUNCH_CHECK();
+    if (tot_t[k] > 0) {
+      hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)tot_t[k]), dim3(64), 0, s, k, d_pt.p + off[k], act[k],
+                         d_order.p, lay, fac);
+      TLS_LAUNCH_CHECK();
+    }
+    if (tot_u[k] > 0) {
+      hipLaunchKernelGGL(k_update<T>, dim3((unsigned)tot_u[k]), dim3(256), 0, s, k, d_pu.p + off[k], act[k],
+                         d_order.p, lay, fac);
+      TLS_LAUNCH_CHECK();
+    }
+  }
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Persistent triangular solves
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float4 type;
+};
+template <>
+struct Vec4<double> {
+  typedef double4 type;
+};
+
+__device__ inline int load_flag(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr long long SPIN_LIMIT = 1ll << 26;
+
+// TRANS = false: forward substitution L y = b on block rows in ascending
+// order. TRANS = true: backward substitution L^T x = y, descending.
+template <class T, bool TRANS>
+__global__ void __launch_bounds__(256) k_trsv(const int2* __restrict__ tasks, int ntasks, int* counter,
+                                              int* flags, const int* __restrict__ epoch_ptr, LocalLayout lay,
+                                              const T* __restrict__ fac, T* x, int* err,
+                                              const int* __restrict__ done) {
+  if (*done) return;
+  constexpr int LD = TS + 1;
+  typedef typename Vec4<T>::type V4;
+  __shared__ T s_diag[TS * LD];
+  __shared__ T s_red[16 * TS];
+  __shared__ int s_task, s_lim;
+  const int tid = threadIdx.x;
+  const int rg = tid & 15, cg = tid >> 4;
+  const int epoch = *epoch_ptr;
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_task;
+    if (t >= ntasks) break;
+    const int i = tasks[t].x, r = tasks[t].y;
+    const int nt = lay.nt[i];
+    const T* base = fac + lay.foff[i];
+    T* xi = x + lay.voff[i];
+    int* fl = flags + lay.toff[i];
+    // diagonal tile -> LDS (used by wave 0 at the end)
+    const T* dt = base + tile_index(0, nt, r, r) * TS2;
+    for (int e = tid; e < TS2; e += 256) s_diag[(e / TS) * LD + (e % TS)] = dt[e];
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    // blocks this task reads: forward c = 0..r-1, backward c = nt-1..r+1
+    int c = TRANS ? nt - 1 : 0;
+    const int stop = TRANS ? r : r;  // exclusive bound in the walking direction
+    while (TRANS ? (c > stop) : (c < stop)) {
+      if (tid == 0) {
+        int lim = c;
+        long long spins = 0;
+        for (;;) {
+          while ((TRANS ? (lim > stop) : (lim < stop)) && load_flag(&fl[lim]) == epoch) lim += TRANS ? -1 : 1;
+          if (lim != c) break;
+          if (++spins > SPIN_LIMIT) {
+            atomicOr(err, ERR_WAIT);
+            lim += TRANS ? -1 : 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        s_lim = lim;
+      }
+      __syncthreads();
+      const int lim = s_lim;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      for (; TRANS ? (c > lim) : (c < lim); c += TRANS ? -1 : 1) {
+        const T* tile = base + (TRANS ? tile_index(0, nt, c, r) : tile_index(0, nt, r, c)) * TS2;
+        const T* xc = xi + c * TS;
+        if (!TRANS) {
+          // acc[q] (row 4rg+q) += sum_j L[4rg+q][cg+16j] x[cg+16j]
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            int col = cg + 16 * j;
+            V4 v = *reinterpret_cast<const V4*>(tile + col * TS + 4 * rg);
+            T xv = xc[col];
+            acc[0] += v.x * xv;
+            acc[1] += v.y * xv;
+            acc[2] += v.z * xv;
+            acc[3] += v.w * xv;
+          }
+        } else {
+          // acc[j] (col cg+16j) += sum_q L[4rg+q][cg+16j] x[4rg+q]
+          V4 xv = *reinterpret_cast<const V4*>(xc + 4 * rg);
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            int col = cg + 16 * j;
+            V4 v = *reinterpret_cast<const V4*>(tile + col * TS + 4 * rg);
+            acc[j] += v.x * xv.x + v.y * xv.y + v.z * xv.z + v.w * xv.w;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // reduce the partial sums into the right-hand side of the diagonal block
+    if (!TRANS) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = acc[q];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = acc[j];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int lane = tid;
+      T sum = T(0);
+#pragma unroll
+      for (int g = 0; g < 16; g++) sum += s_red[g * TS + lane];
+      T val = xi[r * TS + lane] - sum;
+      if (!TRANS) {
+        for (int b = 0; b < TS; b++) {
+          T xb = __shfl(val, b) / s_diag[b * LD + b];
+          if (lane == b)
+            val = xb;
+          else if (lane > b)
+            val -= s_diag[b * LD + lane] * xb;
+        }
+      } else {
+        for (int b = TS - 1; b >= 0; b--) {
+          T xb = __shfl(val, b) / s_diag[b * LD + b];
+          if (lane == b)
+            val = xb;
+          else if (lane < b)
+            val -= s_diag[lane * LD + b] * xb;
+        }
+      }
+      xi[r * TS + lane] = val;
+      __threadfence();
+      if (lane == 0) __hip_atomic_store(&fl[r], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_solve_begin(int* counters, const int* done) {
+  if (*done) return;
+  counters[0] = 0;
+  counters[1] = 0;
+  counters[2] += 1;
+}
+
+template <class T>
+void trsv(hipStream_t s, bool transpose, const int2* tasks, int ntasks, int* counter, int* flags,
+          const int* epoch, const LocalLayout& lay, const T* fac, T* x, int* err, const int* done, int grid) {
+  grid = std::max(1, std::min(grid, ntasks));
+  if (!transpose)
+    hipLaunchKernelGGL((k_trsv<T, false>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
+                       fac, x, err, done);
+  else
+    hipLaunchKernelGGL((k_trsv<T, true>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
+                       fac, x, err, done);
+  TLS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
+                      int* err) {
+  factor_tiles<double>(s, N, nt, lay, fac, err);
+}
+
+void trsv_f64(hipStream_t s, bool transpose, const int2* tasks, int ntasks, int* counter, int* flags,
+              const int* epoch, const LocalLayout& lay, const double* fac, double* x, int* err, const int* done,
+              int grid) {
+  trsv<double>(s, transpose, tasks, ntasks, counter, flags, epoch, lay, fac, x, err, done, grid);
+}
+
+void solve_begin(hipStream_t s, int* counters, const int* done) {
+  hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(1), 0, s, counters, done);
+  TLS_LAUNCH_CHECK();
+}
+
+void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist) {
+  hipStream_t s = c->stream;
+  const int total = c->h_sub_ptr[c->N];
+  LocalLayout lay = c->layout();
+  const int stride = c->delta + 2;
+  const double* scale = nullptr;
+  if (c->opt.jacobi_scale) {
+    c->scale.alloc(c->sum_M);
+    TLS_HIP(hipMemsetAsync(c->scale.p, 0, sizeof(double) * c->sum_M, s));
+    TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_jacobi_scale, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
+                       c->sub_of_pos.p, c->sub_ptr.p, c->d_voff.p, c->row_ptr.p, c->col_idx.p, c->val.p,
+                       c->scale.p, c->errflag.p);
+    TLS_LAUNCH_CHECK();
+    if (download(c->errflag.p, 1, s)[0]) fail(TLS_E_NOT_SPD, "non-positive diagonal entry (Jacobi scaling)");
+    scale = c->scale.p;
+  }
+  if (c->fp32) {
+    c->fac32.alloc(c->fac_elems);
+    TLS_HIP(hipMemsetAsync(c->fac32.p, 0, sizeof(float) * c->fac_elems, s));
+    hipLaunchKernelGGL(k_pad_identity<float>, dim3(c->N), dim3(64), 0, s, c->N, lay, c->kind, c->fac32.p);
+    TLS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gather<float>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->n, c->sub_idx.p,
+                       c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, dist.p, c->row_ptr.p, c->col_idx.p,
+                       c->val.p, scale, lay, c->kind, c->fac32.p);
+  } else {
+    c->fac64.alloc(c->fac_elems);
+    TLS_HIP(hipMemsetAsync(c->fac64.p, 0, sizeof(double) * c->fac_elems, s));
+    hipLaunchKernelGGL(k_pad_identity<double>, dim3(c->N), dim3(64), 0, s, c->N, lay, c->kind, c->fac64.p);
+    TLS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gather<double>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->n, c->sub_idx.p,
+                       c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, dist.p, c->row_ptr.p, c->col_idx.p,
+                       c->val.p, scale, lay, c->kind, c->fac64.p);
+  }
+  TLS_LAUNCH_CHECK();
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+void factor_local(tls_ctx* c) {
+  if (c->kind != 0) fail(TLS_E_ARG, "general matrices (LU) are not available in this build");
+  TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), c->stream));
+  if (c->fp32)
+    factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->errflag.p);
+  else
+    factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->errflag.p);
+  int err = download(c->errflag.p, 1, c->stream)[0];
+  if (err & ERR_PIVOT) fail(TLS_E_NOT_SPD, "non-positive pivot in a local Cholesky factorization");
+}
+
+void make_tasks(const std::vector<int>& nt, const std::vector<int64_t>& toff, std::vector<int2>& fwd,
+                std::vector<int2>& bwd) {
+  (void)toff;
+  const int N = (int)nt.size();
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
+  int maxnt = N ? nt[order[0]] : 0;
+  fwd.clear();
+  bwd.clear();
+  // step s: block row s of every subdomain with nt > s (largest first);
+  // backward: block row nt-1-s.
+  for (int st = 0; st < maxnt; st++)
+    for (int a = 0; a < N && nt[order[a]] > st; a++) {
+      int i = order[a];
+      fwd.push_back(make_int2(i, st));
+      bwd.push_back(make_int2(i, nt[i] - 1 - st));
+    }
+}
+
+void build_solve_tasks(tls_ctx* c) {
+  std::vector<int2> f, b;
+  make_tasks(c->h_nt, c->h_toff, f, b);
+  c->tasks_fwd.upload(f, c->stream);
+  c->tasks_bwd.upload(b, c->stream);
+  c->flags_fwd.alloc(c->sum_nt);
+  c->flags_bwd.alloc(c->sum_nt);
+  c->counters.alloc(4);
+  TLS_HIP(hipMemsetAsync(c->flags_fwd.p, 0, sizeof(int) * c->sum_nt, c->stream));
+  TLS_HIP(hipMemsetAsync(c->flags_bwd.p, 0, sizeof(int) * c->sum_nt, c->stream));
+  TLS_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(int) * 4, c->stream));
+  // padding entries must stay zero: the padded identity rows then solve to 0
+  if (c->fp32) {
+    c->xloc32.alloc(c->sum_M);
+    TLS_HIP(hipMemsetAsync(c->xloc32.p, 0, sizeof(float) * c->sum_M, c->stream));
+  } else {
+    c->xloc64.alloc(c->sum_M);
+    TLS_HIP(hipMemsetAsync(c->xloc64.p, 0, sizeof(double) * c->sum_M, c->stream));
+  }
+  TLS_HIP(hipStreamSynchronize(c->stream));
+}
+
+void local_backward(tls_ctx* c, float* x, const int* done) {
+  solve_begin(c->stream, c->counters.p, done);
+  trsv<float>(c->stream, true, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
+              c->counters.p + 2, c->layout(), c->fac32.p, x, c->errflag.p, done, c->solve_grid);
+}
+
+void local_backward(tls_ctx* c, double* x, const int* done) {
+  solve_begin(c->stream, c->counters.p, done);
+  trsv<double>(c->stream, true, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
+               c->counters.p + 2, c->layout(), c->fac64.p, x, c->errflag.p, done, c->solve_grid);
+}
+
+void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_end) {
+  hipStream_t s = c->stream;
+  const int ntasks = (int)c->tasks_fwd.n;
+  LocalLayout lay = c->layout();
+  solve_begin(s, c->counters.p, done);
+  if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
+  if (c->fp32) {
+    trsv<float>(s, false, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
+                c->fac32.p, c->xloc32.p, c->errflag.p, done, c->solve_grid);
+    trsv<float>(s, true, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
+                c->fac32.p, c->xloc32.p, c->errflag.p, done, c->solve_grid);
+  } else {
+    trsv<double>(s, false, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
+                 c->fac64.p, c->xloc64.p, c->errflag.p, done, c->solve_grid);
+    trsv<double>(s, true, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
+                 c->fac64.p, c->xloc64.p, c->errflag.p, done, c->solve_grid);
+  }
+  if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));
+}
+
+}  // namespace tls

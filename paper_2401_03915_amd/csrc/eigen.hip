@@ -1,0 +1,710 @@
+// Coarse basis of eq. coarse_space_2 (SPD A): the dominant eigenvectors of
+// Pi_i^T D_i A_ii D_i Pi_i w = lambda^2 A_ii w (eq. gevpsvd), mapped to
+// D_i Pi_i w.
+//
+// Reduction used here (exact, derived from the block form of Pi_i that the
+// paper writes before Proposition gevpsvd). Order Omega_i as
+// [I, G = Gamma_{1:delta-1}, T = Gamma_delta] and let L be the Cholesky
+// factor of A_ii with blocks L_II, L_GI, L_GG, L_TI, L_TG, L_TT. Then
+//   E = -A_{Omega',Omega'}^{-1} A_{Omega',T} (eq. HOp), H = rows I of E,
+//   F := L_II^T H = -L_TI^T + L_GI^T L_GG^{-T} L_TG^T,
+//   Pi_i^T D_i A_ii D_i Pi_i is zero outside its (T,T) block K = F^T F,
+//   and the Schur complement of A_ii onto T is S_T = L_TT L_TT^T.
+// A nonzero eigenpair (lambda^2, w) therefore satisfies K w_T = lambda^2 S_T w_T,
+// i.e. C z = lambda^2 z with C = L_TT^{-1} K L_TT^{-T}, w_T = L_TT^{-T} z, and
+// the coarse vector is D_i Pi_i w = [H w_T; 0] = [L_II^{-T} F w_T; 0].
+// C is #T x #T; its top eigenpairs come from subspace iteration with
+// Rayleigh-Ritz.
+#include <algorithm>
+#include <cmath>
+
+#include "batched.hpp"
+#include "kernels.hpp"
+
+namespace tls {
+
+namespace {
+
+constexpr int PMAX = 48;  // largest subspace block
+
+struct EigLayout {
+  const int* nI;
+  const int* nG;
+  const int* nT;
+  const int* m;
+  const int* nt;
+  const int64_t* foff;
+  const int64_t* o_F;    // nI*nT
+  const int64_t* o_GI;   // nG*nI
+  const int64_t* o_TG;   // nG*nT
+  const int64_t* o_GG;   // nG*nG
+  const int64_t* o_TT;   // nT*nT
+};
+
+// mode 0: F = -L_TI^T (nI x nT)    mode 1: Tm = L_TG^T (nG x nT)
+// mode 2: L_GG^T (upper, nG x nG) mode 3: L_GI (nG x nI)
+// mode 4: L_TT (lower, nT x nT)   mode 5: L_TT^T (upper, nT x nT)
+template <class S, class D>
+__global__ void k_extract(int mode, EigLayout e, const S* __restrict__ fac, D* out) {
+  const int i = blockIdx.y;
+  const int nI = e.nI[i], nG = e.nG[i], nT = e.nT[i], nt = e.nt[i];
+  const int nP = nI + nG;
+  const S* base = fac + e.foff[i];
+  int rows, cols;
+  int64_t off;
+  switch (mode) {
+    case 0: rows = nI; cols = nT; off = e.o_F[i]; break;
+    case 1: rows = nG; cols = nT; off = e.o_TG[i]; break;
+    case 2: rows = nG; cols = nG; off = e.o_GG[i]; break;
+    case 3: rows = nG; cols = nI; off = e.o_GI[i]; break;
+    default: rows = nT; cols = nT; off = e.o_TT[i]; break;
+  }
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    int a = (int)(x % rows), b = (int)(x / rows);
+    S v = S(0);
+    switch (mode) {
+      case 0: v = -*elem_ptr(base, 0, nt, nP + b, a); break;
+      case 1: v = *elem_ptr(base, 0, nt, nP + b, nI + a); break;
+      case 2: v = b >= a ? *elem_ptr(base, 0, nt, nI + b, nI + a) : S(0); break;
+      case 3: v = *elem_ptr(base, 0, nt, nI + a, b); break;
+      case 4: v = a >= b ? *elem_ptr(base, 0, nt, nP + a, nP + b) : S(0); break;
+      default: v = b >= a ? *elem_ptr(base, 0, nt, nP + b, nP + a) : S(0); break;
+    }
+    out[off + x] = (D)v;
+  }
+}
+
+template <class S, class D>
+__global__ void k_convert(int64_t count, const S* __restrict__ in, D* out) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += (int64_t)gridDim.x * blockDim.x)
+    out[x] = (D)in[x];
+}
+
+// C <- (X^T + X)/2 is not what we want; transpose square blocks in place:
+// out = in^T for each subdomain's nT x nT block.
+__global__ void k_transpose_blocks(const int* __restrict__ nT_, const int64_t* __restrict__ off, const double* in,
+                                   double* out, int symmetrize) {
+  const int i = blockIdx.y;
+  const int n = nT_[i];
+  const double* a = in + off[i];
+  double* b = out + off[i];
+  const int64_t total = (int64_t)n * n;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    int r = (int)(x % n), c = (int)(x / n);
+    b[x] = symmetrize ? 0.5 * (a[r + (int64_t)c * n] + a[c + (int64_t)r * n]) : a[c + (int64_t)r * n];
+  }
+}
+
+__device__ inline double hash_uniform(uint64_t seed, uint64_t i, uint64_t r, uint64_t c) {
+  // splitmix64 finalizer over a counter built from (seed, i, r, c)
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * ((i << 42) ^ (c << 32) ^ r ^ 0x5851F42D4C957F2Dull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  // 256 threads: wave shuffle then 4 partials
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+// Y (n x p, leading dim n) <- Y R^{-1} with R from the Cholesky of Y^T Y.
+// Twice (CholQR2). Returns false if the Gram matrix is not positive definite.
+__device__ bool chol_qr(double* Y, int n, int p, double* G, double* red) {
+  const int tid = threadIdx.x;
+  bool ok = true;
+  for (int pass = 0; pass < 2; pass++) {
+    // Gram G = Y^T Y (upper triangle), one entry per thread at a time
+    const int npair = p * (p + 1) / 2;
+    for (int e = tid; e < npair; e += 256) {
+      int a = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while ((a + 1) * (a + 2) / 2 <= e) a++;
+      while (a * (a + 1) / 2 > e) a--;
+      int b = e - a * (a + 1) / 2;  // b <= a
+      const double* ya = Y + (int64_t)a * n;
+      const double* yb = Y + (int64_t)b * n;
+      double s = 0.0;
+      for (int r = 0; r < n; r++) s += ya[r] * yb[r];
+      G[b * PMAX + a] = s;  // row b, col a (upper)
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // in-place upper Cholesky G = R^T R
+      for (int j = 0; j < p; j++) {
+        double d = G[j * PMAX + j];
+        for (int l = 0; l < j; l++) d -= G[l * PMAX + j] * G[l * PMAX + j];
+        if (!(d > 0.0)) {
+          ok = false;
+          d = 1e-300;
+        }
+        d = sqrt(d);
+        G[j * PMAX + j] = d;
+        for (int c = j + 1; c < p; c++) {
+          double s = G[j * PMAX + c];
+          for (int l = 0; l < j; l++) s -= G[l * PMAX + j] * G[l * PMAX + c];
+          G[j * PMAX + c] = s / d;
+        }
+      }
+      red[8] = ok ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    ok = red[8] != 0.0;
+    // rows: y <- y R^{-1}
+    for (int r = tid; r < n; r += 256) {
+      double y[PMAX];
+#pragma unroll
+      for (int c = 0; c < PMAX; c++)
+        if (c < p) y[c] = Y[r + (int64_t)c * n];
+#pragma unroll
+      for (int c = 0; c < PMAX; c++) {
+        if (c < p) {
+          double s = y[c];
+#pragma unroll
+          for (int l = 0; l < PMAX; l++)
+            if (l < c) s -= y[l] * G[l * PMAX + c];
+          y[c] = s / G[c * PMAX + c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < PMAX; c++)
+        if (c < p) Y[r + (int64_t)c * n] = y[c];
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// out (n x p) = in (n x p) * S (p x p, LDS, leading dim PMAX), columns permuted by perm
+__device__ void mul_small(const double* in, double* out, int n, int p, const double* S, const int* perm) {
+  for (int r = threadIdx.x; r < n; r += 256) {
+    double w[PMAX];
+#pragma unroll
+    for (int l = 0; l < PMAX; l++)
+      if (l < p) w[l] = in[r + (int64_t)l * n];
+    for (int c = 0; c < p; c++) {
+      const int pc = perm[c];
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < PMAX; l++)
+        if (l < p) s += w[l] * S[pc * PMAX + l];
+      out[r + (int64_t)c * n] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Cyclic Jacobi on the symmetric p x p matrix H (LDS, leading dim PMAX) with
+// round-robin parallel ordering; S accumulates the rotations.
+__device__ void jacobi_eig(double* H, double* S, int p, double* cs, double* red) {
+  const int tid = threadIdx.x;
+  const int pe = p + (p & 1);  // even number of players; index p is a dummy if p is odd
+  for (int e = tid; e < PMAX * PMAX; e += 256) S[e] = ((e / PMAX) == (e % PMAX)) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; sweep++) {
+    // off-diagonal norm vs total
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < p * p; e += 256) {
+      int a = e % p, b = e / p;
+      double h = H[b * PMAX + a];
+      tot += h * h;
+      if (a != b) off += h * h;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (off <= 1e-30 * tot || tot == 0.0) break;
+    for (int rnd = 0; rnd < pe - 1; rnd++) {
+      const int npairs = pe / 2;
+      if (tid < npairs) {
+        int a, b;
+        if (tid == 0) {
+          a = 0;
+          b = (rnd % (pe - 1)) + 1;
+        } else {
+          a = ((rnd + tid) % (pe - 1)) + 1;
+          b = ((rnd - tid + (pe - 1)) % (pe - 1)) + 1;
+        }
+        if (a > b) {
+          int t = a;
+          a = b;
+          b = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (b < p) {
+          double hab = H[b * PMAX + a];
+          if (hab != 0.0) {
+            double tau = (H[b * PMAX + b] - H[a * PMAX + a]) / (2.0 * hab);
+            double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        cs[4 * tid + 0] = c;
+        cs[4 * tid + 1] = s;
+        cs[4 * tid + 2] = a;
+        cs[4 * tid + 3] = b;
+      }
+      __syncthreads();
+      // columns: H <- H J, S <- S J
+      for (int e = tid; e < npairs * p; e += 256) {
+        int j = e / p, x = e % p;
+        int a = (int)cs[4 * j + 2], b = (int)cs[4 * j + 3];
+        if (b >= p) continue;
+        double c = cs[4 * j], s = cs[4 * j + 1];
+        double ha = H[a * PMAX + x], hb = H[b * PMAX + x];
+        H[a * PMAX + x] = c * ha - s * hb;
+        H[b * PMAX + x] = s * ha + c * hb;
+        double sa = S[a * PMAX + x], sb = S[b * PMAX + x];
+        S[a * PMAX + x] = c * sa - s * sb;
+        S[b * PMAX + x] = s * sa + c * sb;
+      }
+      __syncthreads();
+      // rows: H <- J^T H
+      for (int e = tid; e < npairs * p; e += 256) {
+        int j = e / p, x = e % p;
+        int a = (int)cs[4 * j + 2], b = (int)cs[4 * j + 3];
+        if (b >= p) continue;
+        double c = cs[4 * j], s = cs[4 * j + 1];
+        double ha = H[x * PMAX + a], hb = H[x * PMAX + b];
+        H[x * PMAX + a] = c * ha - s * hb;
+        H[x * PMAX + b] = s * ha + c * hb;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One workgroup per subdomain: top-k eigenpairs of the symmetric PSD matrix
+// C (n x n) by subspace iteration on C + sigma I (sigma = 1e-7 trace C keeps
+// the block full rank) with Rayleigh-Ritz every other step.
+__global__ void __launch_bounds__(256) k_subspace(const int* __restrict__ nT_, const int* __restrict__ kreq_,
+                                                  const int64_t* __restrict__ o_TT, const double* __restrict__ Cm,
+                                                  const int64_t* __restrict__ o_Y, double* Ybuf, double* Wbuf,
+                                                  int over, int maxit, double tol, uint64_t seed,
+                                                  const int64_t* __restrict__ o_Z, double* zv,
+                                                  const int* __restrict__ o_th, double* theta, int* kfound,
+                                                  double* resid, int* iters, double tau2, double floor_rel,
+                                                  int* err) {
+  __shared__ double H[PMAX * PMAX];
+  __shared__ double S[PMAX * PMAX];
+  __shared__ double G[PMAX * PMAX];
+  __shared__ double cs[4 * (PMAX / 2 + 1)];
+  __shared__ double red[16];
+  __shared__ double th[PMAX];
+  __shared__ int perm[PMAX];
+  const int i = blockIdx.x;
+  const int n = nT_[i], k = kreq_[i];
+  const int tid = threadIdx.x;
+  if (k <= 0 || n <= 0) {
+    if (tid == 0) {
+      kfound[i] = 0;
+      resid[i] = 0.0;
+      iters[i] = 0;
+    }
+    return;
+  }
+  int p = min(n, min(PMAX, k + over));
+  const double* C = Cm + o_TT[i];
+  double* Y = Ybuf + o_Y[i];
+  double* W = Wbuf + o_Y[i];
+  // shift
+  double tr = 0.0;
+  for (int r = tid; r < n; r += 256) tr += C[r + (int64_t)r * n];
+  tr = block_sum(tr, red);
+  const double sigma = 1e-7 * tr;
+  for (int64_t e = tid; e < (int64_t)n * p; e += 256) {
+    int r = (int)(e % n), c = (int)(e / n);
+    Y[e] = hash_uniform(seed, i, r, c);
+  }
+  __syncthreads();
+  bool ok = chol_qr(Y, n, p, G, red);
+  if (tid < PMAX) perm[tid] = tid;
+  __syncthreads();
+  double maxres = 0.0;
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= maxit; it++) {
+    // W = (C + sigma I) Y
+    for (int64_t e = tid; e < (int64_t)n * p; e += 256) {
+      int r = (int)(e % n), c = (int)(e / n);
+      const double* yc = Y + (int64_t)c * n;
+      double s = sigma * yc[r];
+      for (int l = 0; l < n; l++) s += C[r + (int64_t)l * n] * yc[l];
+      W[e] = s;
+    }
+    __syncthreads();
+    const bool rr = (it % 2 == 0) || it == maxit || p == n;
+    if (!rr) {
+      for (int64_t e = tid; e < (int64_t)n * p; e += 256) Y[e] = W[e];
+      __syncthreads();
+      ok &= chol_qr(Y, n, p, G, red);
+      continue;
+    }
+    // Rayleigh-Ritz: H = Y^T W (Y orthonormal)
+    for (int e = tid; e < p * p; e += 256) {
+      int a = e % p, b = e / p;
+      const double* ya = Y + (int64_t)a * n;
+      const double* wb = W + (int64_t)b * n;
+      double s = 0.0;
+      for (int r = 0; r < n; r++) s += ya[r] * wb[r];
+      H[b * PMAX + a] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < p * p; e += 256) {
+      int a = e % p, b = e / p;
+      if (a < b) {
+        double v = 0.5 * (H[b * PMAX + a] + H[a * PMAX + b]);
+        H[b * PMAX + a] = v;
+        H[a * PMAX + b] = v;
+      }
+    }
+    __syncthreads();
+    jacobi_eig(H, S, p, cs, red);
+    if (tid == 0) {
+      for (int a = 0; a < p; a++) th[a] = H[a * PMAX + a];
+      for (int a = 0; a < p; a++) perm[a] = a;
+      for (int a = 0; a < p; a++) {
+        int best = a;
+        for (int b = a + 1; b < p; b++)
+          if (th[perm[b]] > th[perm[best]]) best = b;
+        int t = perm[a];
+        perm[a] = perm[best];
+        perm[best] = t;
+      }
+    }
+    __syncthreads();
+    // residuals of the first k Ritz pairs: || W s_j - theta_j Y s_j ||
+    double lres[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; j++) lres[j] = 0.0;
+    for (int r = tid; r < n; r += 256) {
+      double y[PMAX], w[PMAX];
+#pragma unroll
+      for (int l = 0; l < PMAX; l++)
+        if (l < p) {
+          y[l] = Y[r + (int64_t)l * n];
+          w[l] = W[r + (int64_t)l * n];
+        }
+#pragma unroll
+      for (int j = 0; j < PMAX; j++) {
+        if (j < k && j < p) {
+          const int pj = perm[j];
+          double a = 0.0, b = 0.0;
+#pragma unroll
+          for (int l = 0; l < PMAX; l++)
+            if (l < p) {
+              a += w[l] * S[pj * PMAX + l];
+              b += y[l] * S[pj * PMAX + l];
+            }
+          double d = a - th[pj] * b;
+          lres[j] += d * d;
+        }
+      }
+    }
+    maxres = 0.0;
+    const double th0 = fmax(th[perm[0]], 1e-300);
+    const int kp = min(k, p);
+#pragma unroll
+    for (int j = 0; j < PMAX; j++) {
+      if (j < kp) {
+        double v = block_sum(lres[j], red);
+        maxres = fmax(maxres, sqrt(v) / th0);
+      }
+    }
+    conv = (maxres <= tol) || p == n;
+    if (conv || it == maxit) {
+      mul_small(Y, W, n, p, S, perm);  // Ritz vectors
+      break;
+    }
+    mul_small(W, Y, n, p, S, perm);  // power step on the Ritz vectors
+    ok &= chol_qr(Y, n, p, G, red);
+  }
+  if (it > maxit) it = maxit;
+  // selection: Ritz values minus the shift, descending
+  __syncthreads();
+  if (tid == 0) {
+    const double top = th[perm[0]] - sigma;
+    int kf = 0;
+    for (int j = 0; j < min(k, p); j++) {
+      double v = th[perm[j]] - sigma;
+      if (v > floor_rel * top && v > tau2 && top > 0.0)
+        kf++;
+      else
+        break;
+    }
+    for (int j = 0; j < kf; j++) theta[o_th[i] + j] = th[perm[j]] - sigma;
+    kfound[i] = kf;
+    resid[i] = maxres;
+    iters[i] = it;
+    if (!ok || !conv) atomicOr(err, ERR_EIG);
+  }
+  __syncthreads();
+  const int kf = kfound[i];
+  for (int64_t e = tid; e < (int64_t)n * kf; e += 256) zv[o_Z[i] + e] = W[e];
+}
+
+// Orthonormalize the coarse columns of subdomain i (rows I_i), dropping
+// columns that are numerically dependent, and store them as Z_i (fp64).
+template <class T>
+__global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const int* __restrict__ kf_,
+                                              const int64_t* __restrict__ voff, int64_t sumM,
+                                              const T* __restrict__ xr, const double* __restrict__ scale,
+                                              const int64_t* __restrict__ zoff, double* Z, int* kfinal,
+                                              int* keep_idx) {
+  __shared__ double red[16];
+  const int i = blockIdx.x;
+  const int nI = nI_[i], k = kf_[i];
+  double* Zi = Z + zoff[i];
+  const int tid = threadIdx.x;
+  int kept = 0;
+  for (int a = 0; a < k; a++) {
+    double* v = Zi + (int64_t)kept * nI;
+    double n0 = 0.0;
+    for (int r = tid; r < nI; r += 256) {
+      double x = (double)xr[(int64_t)a * sumM + voff[i] + r];
+      if (scale) x *= scale[voff[i] + r];
+      v[r] = x;
+      n0 += x * x;
+    }
+    n0 = sqrt(block_sum(n0, red));
+    for (int pass = 0; pass < 2; pass++) {
+      for (int b = 0; b < kept; b++) {
+        const double* q = Zi + (int64_t)b * nI;
+        double d = 0.0;
+        for (int r = tid; r < nI; r += 256) d += q[r] * v[r];
+        d = block_sum(d, red);
+        for (int r = tid; r < nI; r += 256) v[r] -= d * q[r];
+        __syncthreads();
+      }
+    }
+    double nr = 0.0;
+    for (int r = tid; r < nI; r += 256) nr += v[r] * v[r];
+    nr = sqrt(block_sum(nr, red));
+    if (nr > 1e-10 * n0 && nr > 0.0) {
+      for (int r = tid; r < nI; r += 256) v[r] /= nr;
+      if (tid == 0) keep_idx[i * PMAX + kept] = a;
+      kept++;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) kfinal[i] = kept;
+}
+
+}  // namespace
+
+template <class T>
+static void basis_impl(tls_ctx* c, T* fac) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int> nI(N), nG(N), nT(N), kreq(N);
+  std::vector<int64_t> oF(N + 1, 0), oGI(N + 1, 0), oTG(N + 1, 0), oGG(N + 1, 0), oTT(N + 1, 0), oY(N + 1, 0),
+      oZv(N + 1, 0), oZ(N + 1, 0);
+  std::vector<int> oth(N + 1, 0);
+  int kmax = 0;
+  for (int i = 0; i < N; i++) {
+    nI[i] = c->h_nI[i];
+    nG[i] = c->h_nP[i] - c->h_nI[i];
+    nT[i] = c->h_m[i] - c->h_nP[i];
+    kreq[i] = std::min(std::min(c->nev, nT[i]), PMAX);
+    kmax = std::max(kmax, kreq[i]);
+    int p = std::min(nT[i], std::min(PMAX, kreq[i] + c->opt.eig_oversample));
+    oF[i + 1] = oF[i] + (int64_t)nI[i] * nT[i];
+    oGI[i + 1] = oGI[i] + (int64_t)nG[i] * nI[i];
+    oTG[i + 1] = oTG[i] + (int64_t)nG[i] * nT[i];
+    oGG[i + 1] = oGG[i] + (int64_t)nG[i] * nG[i];
+    oTT[i + 1] = oTT[i] + (int64_t)nT[i] * nT[i];
+    oY[i + 1] = oY[i] + (int64_t)nT[i] * std::max(p, 1);
+    oZv[i + 1] = oZv[i] + (int64_t)nT[i] * kreq[i];
+    oZ[i + 1] = oZ[i] + (int64_t)nI[i] * kreq[i];
+    oth[i + 1] = oth[i] + kreq[i];
+  }
+  if (kmax == 0) {
+    c->nC = 0;
+    c->h_zcol.assign(N + 1, 0);
+    return;
+  }
+  DBuf<int> d_nI, d_nG, d_nT, d_kreq;
+  DBuf<int64_t> d_oF, d_oGI, d_oTG, d_oGG, d_oTT, d_oY, d_oZv, d_oZ;
+  DBuf<int> d_oth;
+  d_nI.upload(nI, s);
+  d_nG.upload(nG, s);
+  d_nT.upload(nT, s);
+  d_kreq.upload(kreq, s);
+  d_oF.upload(oF, s);
+  d_oGI.upload(oGI, s);
+  d_oTG.upload(oTG, s);
+  d_oGG.upload(oGG, s);
+  d_oTT.upload(oTT, s);
+  d_oY.upload(oY, s);
+  d_oZv.upload(oZv, s);
+  d_oZ.upload(oZ, s);
+  d_oth.upload(oth, s);
+  EigLayout el{d_nI.p, d_nG.p, d_nT.p, c->d_m.p, c->d_nt.p, c->d_foff.p, d_oF.p, d_oGI.p, d_oTG.p, d_oGG.p, d_oTT.p};
+
+  DBuf<T> F, GI, TG, GGt, K;
+  DBuf<double> LTT, LTTt, C64, C64b;
+  F.alloc(oF[N]);
+  K.alloc(oTT[N]);
+  LTT.alloc(oTT[N]);
+  LTTt.alloc(oTT[N]);
+  C64.alloc(oTT[N]);
+  C64b.alloc(oTT[N]);
+  const dim3 eg(64, N);
+  hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 0, el, fac, F.p);
+  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
+  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 5, el, fac, LTTt.p);
+  TLS_LAUNCH_CHECK();
+  TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
+  if (oGG[N] > 0) {
+    GI.alloc(oGI[N]);
+    TG.alloc(oTG[N]);
+    GGt.alloc(oGG[N]);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 1, el, fac, TG.p);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 2, el, fac, GGt.p);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 3, el, fac, GI.p);
+    TLS_LAUNCH_CHECK();
+    // Tm = L_GG^{-T} L_TG^T
+    std::vector<TriDesc> td;
+    for (int i = 0; i < N; i++) td.push_back(TriDesc{nG[i], kreq[i] > 0 ? nT[i] : 0, oGG[i], oTG[i], (int64_t)nG[i]});
+    batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
+    // F += L_GI^T Tm
+    std::vector<GemmDesc> gd;
+    for (int i = 0; i < N; i++)
+      if (kreq[i] > 0 && nG[i] > 0)
+        gd.push_back(GemmDesc{nI[i], nT[i], nG[i], nG[i], nG[i], oGI[i], oTG[i], oF[i], (int64_t)nI[i]});
+    batched_gemm<T>(s, gd, true, false, GI.p, TG.p, F.p, T(1), T(1));
+  }
+  // K = F^T F
+  {
+    std::vector<GemmDesc> gd;
+    for (int i = 0; i < N; i++)
+      if (kreq[i] > 0) gd.push_back(GemmDesc{nT[i], nT[i], nI[i], nI[i], nI[i], oF[i], oF[i], oTT[i], (int64_t)nT[i]});
+    batched_gemm<T>(s, gd, true, false, F.p, F.p, K.p, T(1), T(0));
+  }
+  // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)oTT[N], K.p, C64.p);
+  TLS_LAUNCH_CHECK();
+  {
+    std::vector<TriDesc> td;
+    for (int i = 0; i < N; i++) td.push_back(TriDesc{nT[i], kreq[i] > 0 ? nT[i] : 0, oTT[i], oTT[i], (int64_t)nT[i]});
+    batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64.p, c->errflag.p);
+    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, C64.p, C64b.p, 0);
+    TLS_LAUNCH_CHECK();
+    batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64b.p, c->errflag.p);
+    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, C64b.p, C64.p, 1);
+    TLS_LAUNCH_CHECK();
+  }
+  if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_NOT_SPD, "zero pivot in a Schur-complement block");
+
+  // subspace iteration
+  DBuf<double> Yb, Wb, zv, theta, resid;
+  DBuf<int> kfound, its;
+  Yb.alloc(oY[N]);
+  Wb.alloc(oY[N]);
+  zv.alloc(oZv[N]);
+  theta.alloc(oth[N]);
+  resid.alloc(N);
+  kfound.alloc(N);
+  its.alloc(N);
+  const double tol = c->opt.eig_tol > 0 ? c->opt.eig_tol : (c->fp32 ? 1e-6 : 1e-9);
+  const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;
+  hipLaunchKernelGGL(k_subspace, dim3(N), dim3(256), 0, s, d_nT.p, d_kreq.p, d_oTT.p, C64.p, d_oY.p, Yb.p, Wb.p,
+                     c->opt.eig_oversample, c->opt.eig_maxit, tol, (uint64_t)c->opt.seed, d_oZv.p, zv.p, d_oth.p,
+                     theta.p, kfound.p, resid.p, its.p, tau2, 1e-12, c->errflag.p);
+  TLS_LAUNCH_CHECK();
+  auto h_kf = download(kfound.p, N, s);
+  auto h_res = download(resid.p, N, s);
+  auto h_its = download(its.p, N, s);
+  auto h_th = download(theta.p, oth[N], s);
+  c->eig_resid_max = 0;
+  c->eig_iters_max = 0;
+  for (int i = 0; i < N; i++) {
+    c->eig_resid_max = std::max(c->eig_resid_max, h_res[i]);
+    c->eig_iters_max = std::max(c->eig_iters_max, h_its[i]);
+  }
+  // w_T = L_TT^{-T} z
+  {
+    std::vector<TriDesc> td;
+    for (int i = 0; i < N; i++) td.push_back(TriDesc{nT[i], h_kf[i], oTT[i], oZv[i], (int64_t)nT[i]});
+    batched_trsm<double>(s, td, UPPER_BWD, LTTt.p, zv.p, c->errflag.p);
+  }
+  // V = F w_T into padded right-hand sides [V; 0], then x = L^{-T} [V; 0]
+  int kf_max = 0;
+  for (int i = 0; i < N; i++) kf_max = std::max(kf_max, h_kf[i]);
+  DBuf<T> wT, xr;
+  wT.alloc(oZv[N]);
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
+  TLS_LAUNCH_CHECK();
+  xr.alloc((size_t)std::max(kf_max, 1) * c->sum_M);
+  TLS_HIP(hipMemsetAsync(xr.p, 0, sizeof(T) * std::max(kf_max, 1) * c->sum_M, s));
+  {
+    std::vector<GemmDesc> gd;
+    for (int i = 0; i < N; i++)
+      if (h_kf[i] > 0)
+        gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], nI[i], nT[i], oF[i], oZv[i], c->h_voff[i], c->sum_M});
+    batched_gemm<T>(s, gd, false, false, F.p, wT.p, xr.p, T(1), T(0));
+  }
+  F.release();
+  K.release();
+  GI.release();
+  TG.release();
+  GGt.release();
+  for (int j = 0; j < kf_max; j++) {
+    local_backward(c, xr.p + (size_t)j * c->sum_M, c->zero_int.p);
+  }
+  TLS_HIP(hipStreamSynchronize(s));
+  // orthonormalize into Z
+  DBuf<double> Zt;
+  DBuf<int> kfin, keep;
+  Zt.alloc(std::max<int64_t>(oZ[N], 1));
+  kfin.alloc(N);
+  keep.alloc((size_t)N * PMAX);
+  DBuf<int64_t> d_oZ2;
+  hipLaunchKernelGGL(k_orth<T>, dim3(N), dim3(256), 0, s, d_nI.p, kfound.p, c->d_voff.p, c->sum_M, xr.p,
+                     c->opt.jacobi_scale ? c->scale.p : nullptr, d_oZ.p, Zt.p, kfin.p, keep.p);
+  TLS_LAUNCH_CHECK();
+  auto h_kfin = download(kfin.p, N, s);
+  auto h_keep = download(keep.p, (size_t)N * PMAX, s);
+  // compact: Z_i keeps its first kfin columns at oZ[i]; record columns
+  c->h_zcol.assign(N + 1, 0);
+  c->h_zoff = oZ;
+  c->h_eig.clear();
+  for (int i = 0; i < N; i++) {
+    c->h_zcol[i + 1] = c->h_zcol[i] + h_kfin[i];
+    for (int a = 0; a < h_kfin[i]; a++) c->h_eig.push_back(h_th[oth[i] + h_keep[(size_t)i * PMAX + a]]);
+  }
+  c->nC = c->h_zcol[N];
+  c->Z.alloc(std::max<int64_t>(oZ[N], 1));
+  TLS_HIP(hipMemcpyAsync(c->Z.p, Zt.p, sizeof(double) * std::max<int64_t>(oZ[N], 1), hipMemcpyDeviceToDevice, s));
+  c->zcol.upload(c->h_zcol, s);
+  c->zoff.upload(c->h_zoff, s);
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+void build_coarse_basis(tls_ctx* c) {
+  if (c->nev == 0 || c->delta == 0) {
+    c->nC = 0;
+    c->h_zcol.assign(c->N + 1, 0);
+    c->h_zoff.assign(c->N + 1, 0);
+    c->zcol.upload(c->h_zcol, c->stream);
+    c->zoff.upload(c->h_zoff, c->stream);
+    c->Z.alloc(1);
+    return;
+  }
+  if (c->kind != 0) fail(TLS_E_ARG, "the general-matrix coarse space is not available in this build");
+  if (c->opt.nev1 > 0) fail(TLS_E_ARG, "nev1 > 0 (eq. uppergevp vectors) is not available in this build");
+  if (c->fp32)
+    basis_impl<float>(c, c->fac32.p);
+  else
+    basis_impl<double>(c, c->fac64.p);
+}
+
+}  // namespace tls

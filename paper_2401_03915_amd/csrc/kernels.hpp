@@ -1,0 +1,51 @@
+// Internal entry points between the library's translation units.
+#pragma once
+
+#include "context.hpp"
+
+namespace tls {
+
+// setup_index.hip: validation, A^T pattern, overlap layers and maps
+void validate_input(tls_ctx* c);
+void build_transpose(tls_ctx* c);
+void build_overlap(tls_ctx* c, DBuf<uint8_t>& dist);
+void build_layout(tls_ctx* c);
+
+// dense.hip: local matrices, batched factorization, triangular solves
+void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist);
+void factor_local(tls_ctx* c);
+void build_solve_tasks(tls_ctx* c);
+// local solves on the padded vector buffer x (fp64 or fp32 per c->fp32)
+// ev_begin / ev_end (may be null) are recorded right before the forward and
+// right after the backward triangular-solve kernel
+void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+// backward substitution L^T x = x only, on a padded vector of the context's precision
+void local_backward(tls_ctx* c, float* x, const int* done);
+void local_backward(tls_ctx* c, double* x, const int* done);
+// generic pieces reused for the coarse factor (always fp64)
+void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay,
+                      double* fac, int* err);
+void make_tasks(const std::vector<int>& nt, const std::vector<int64_t>& toff, std::vector<int2>& fwd,
+                std::vector<int2>& bwd);
+void trsv_f64(hipStream_t s, bool transpose, const int2* tasks, int ntasks, int* counter, int* flags,
+              const int* epoch, const LocalLayout& lay, const double* fac, double* x, int* err,
+              const int* done, int grid);
+void solve_begin(hipStream_t s, int* counters, const int* done);
+
+// eigen.hip: coarse basis (eq. gevpsvd / Section 6)
+void build_coarse_basis(tls_ctx* c);
+
+// coarse.hip: A_0 = Z^T A Z, its factorization, coarse correction
+void build_coarse_operator(tls_ctx* c);
+void coarse_restrict(tls_ctx* c, const double* r, const int* done);
+void coarse_solve(tls_ctx* c, const int* done);
+
+// apply.hip: z = M^{-1} r
+void apply_precond(tls_ctx* c, const double* r, double* z, const int* done, bool profile = false);
+
+// krylov.hip
+void spmv(tls_ctx* c, const double* x, double* y, const int* done);
+void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres,
+                  bool* converged);
+
+}  // namespace tls

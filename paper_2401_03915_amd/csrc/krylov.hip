@@ -1,0 +1,273 @@
+// CSR SpMV and the outer Krylov solver (FP64): preconditioned conjugate
+// gradients from x0 = 0, stopping on ||r_k|| <= tol ||b|| (the recurrence
+// residual), then reporting the true residual ||b - A x|| / ||b||.
+//
+// Every scalar lives on the device; each kernel of an iteration returns at
+// once when the device "done" flag is set, so a chunk of iterations can be
+// enqueued (or replayed as a captured hipGraph) and the host reads the flag
+// once per chunk. Dot products use a fixed grid and a fixed reduction tree,
+// so results are bitwise reproducible.
+#include <chrono>
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace tls {
+
+namespace {
+
+constexpr int RED_BLOCKS = 512;
+
+template <int G>
+__global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const double* __restrict__ val, const double* __restrict__ x,
+                                              double* __restrict__ y, const int* __restrict__ done) {
+  if (*done) return;
+  const int lane = threadIdx.x % G;
+  const int row = blockIdx.x * (256 / G) + threadIdx.x / G;
+  double s = 0.0;
+  if (row < n) {
+    const int b = rp[row + 1];
+    for (int j = rp[row] + lane; j < b; j += G) s += val[j] * x[ci[j]];
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  if (row < n && lane == 0) y[row] = s;
+}
+
+__device__ inline void block_reduce_store(double v, double* out) {
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void __launch_bounds__(256) k_dot_partial(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                     double* partial, const int* __restrict__ done) {
+  if (*done) return;
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) s += a[i] * b[i];
+  block_reduce_store(s, partial + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ partial, double* out,
+                                                   const int* __restrict__ done) {
+  if (*done) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += partial[i];
+  block_reduce_store(s, out);
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; partial sums of r.r
+__global__ void __launch_bounds__(256) k_pcg_update(int n, double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const double* __restrict__ scal, double* partial,
+                                                    const int* __restrict__ done) {
+  if (*done) return;
+  const double alpha = scal[1] / scal[2];
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) {
+    x[i] += alpha * p[i];
+    double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  block_reduce_store(s, partial + blockIdx.x);
+}
+
+__global__ void k_pq_check(const double* __restrict__ scal, int* done) {
+  if (done[0]) return;
+  if (!(scal[2] > 0.0)) {
+    done[0] = 1;
+    done[3] = 1;
+  }
+}
+
+// record ||r||/||b||, stop on tolerance or iteration cap
+__global__ void k_pcg_check(const double* __restrict__ scal, int* done, double* hist, int maxit, double tol2) {
+  if (done[0]) return;
+  int it = ++done[1];
+  double rr = scal[3], bb = scal[0];
+  hist[it - 1] = sqrt(rr / bb);
+  if (rr <= tol2 * bb) {
+    done[0] = 1;
+    done[2] = 1;
+  } else if (it >= maxit) {
+    done[0] = 1;
+  }
+}
+
+__global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b, const int* __restrict__ done) {
+  if (*done) return;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) b[i] = a[i];
+}
+
+// beta = (r.z - [r.zold]) / rz_prev ; p = z + beta p
+__global__ void k_pcg_p(int n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ scal,
+                        int flexible, const int* __restrict__ done) {
+  if (*done) return;
+  const double beta = (scal[4] - (flexible ? scal[5] : 0.0)) / scal[1];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_pcg_shift(double* scal, const int* __restrict__ done) {
+  if (*done) return;
+  scal[1] = scal[4];
+}
+
+__global__ void k_sub(int n, const double* __restrict__ b, const double* __restrict__ q, double* __restrict__ r) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) r[i] = b[i] - q[i];
+}
+
+void dot(tls_ctx* c, const double* a, const double* b, double* out, const int* done) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->n, a, b, c->partial.p, done);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c->stream, c->partial.p, out, done);
+  TLS_LAUNCH_CHECK();
+}
+
+struct PcgVec {
+  double *x, *r, *z, *p, *q, *zold, *b;
+};
+
+PcgVec vecs(tls_ctx* c) {
+  const size_t n = c->n;
+  double* k = c->kr.p;
+  return PcgVec{k, k + n, k + 2 * n, k + 3 * n, k + 4 * n, k + 5 * n, k + 6 * n};
+}
+
+void pcg_iteration(tls_ctx* c, const PcgVec& v, int maxit, double tol2, bool flexible) {
+  hipStream_t s = c->stream;
+  const int* done = c->done.p;
+  const int n = c->n;
+  const int vg = std::min(4096, div_up(n, 256));
+  spmv(c, v.p, v.q, done);
+  dot(c, v.p, v.q, c->scal.p + 2, done);
+  hipLaunchKernelGGL(k_pq_check, dim3(1), dim3(1), 0, s, c->scal.p, c->done.p);
+  hipLaunchKernelGGL(k_pcg_update, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.x, v.r, v.p, v.q, c->scal.p, c->partial.p,
+                     done);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, c->partial.p, c->scal.p + 3, done);
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1), 0, s, c->scal.p, c->done.p, c->hist.p, maxit, tol2);
+  TLS_LAUNCH_CHECK();
+  if (flexible) hipLaunchKernelGGL(k_copy, dim3(vg), dim3(256), 0, s, n, v.z, v.zold, done);
+  apply_precond(c, v.r, v.z, done);
+  dot(c, v.r, v.z, c->scal.p + 4, done);
+  if (flexible) dot(c, v.r, v.zold, c->scal.p + 5, done);
+  hipLaunchKernelGGL(k_pcg_p, dim3(vg), dim3(256), 0, s, n, v.p, v.z, c->scal.p, flexible ? 1 : 0, done);
+  hipLaunchKernelGGL(k_pcg_shift, dim3(1), dim3(1), 0, s, c->scal.p, done);
+  TLS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void spmv(tls_ctx* c, const double* x, double* y, const int* done) {
+  hipStream_t s = c->stream;
+  const int n = c->n;
+  switch (c->spmv_group) {
+    case 4:
+      hipLaunchKernelGGL(k_spmv<4>, dim3(div_up(n, 64)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
+                         y, done);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_spmv<8>, dim3(div_up(n, 32)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
+                         y, done);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_spmv<16>, dim3(div_up(n, 16)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p,
+                         x, y, done);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_spmv<32>, dim3(div_up(n, 8)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
+                         y, done);
+      break;
+    default:
+      hipLaunchKernelGGL(k_spmv<64>, dim3(div_up(n, 4)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
+                         y, done);
+      break;
+  }
+  TLS_LAUNCH_CHECK();
+}
+
+void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged) {
+  if (c->kind != 0) fail(TLS_E_ARG, "FGMRES for general matrices is not available in this build");
+  hipStream_t s = c->stream;
+  const int n = c->n;
+  const int maxit = c->opt.maxit > 0 ? c->opt.maxit : 1000;
+  const bool flexible = c->opt.flexible != 0;
+  if (c->kr.n < (size_t)7 * n) c->kr.alloc((size_t)7 * n);
+  if (c->scal.n < 16) c->scal.alloc(16);
+  if (c->partial.n < RED_BLOCKS) c->partial.alloc(RED_BLOCKS);
+  if (c->done.n < 4) c->done.alloc(4);
+  if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
+  PcgVec v = vecs(c);
+  const double tol2 = tol * tol;
+  auto t0 = std::chrono::steady_clock::now();
+  TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int) * 4, s));
+  TLS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));
+  TLS_HIP(hipMemcpyAsync(v.b, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  TLS_HIP(hipMemcpyAsync(v.r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  TLS_HIP(hipMemsetAsync(v.zold, 0, sizeof(double) * n, s));
+  dot(c, v.b, v.b, c->scal.p + 0, c->done.p);
+  double bb = download(c->scal.p, 1, s)[0];
+  int it = 0;
+  bool conv = false;
+  if (bb == 0.0) {
+    TLS_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    TLS_HIP(hipStreamSynchronize(s));
+    c->h_hist.clear();
+    *iters = 0;
+    *relres = 0.0;
+    *converged = true;
+    return;
+  }
+  apply_precond(c, v.r, v.z, c->done.p);
+  dot(c, v.r, v.z, c->scal.p + 1, c->done.p);
+  TLS_HIP(hipMemcpyAsync(v.p, v.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  const int chunk = 8;
+  bool use_graph = c->opt.use_graph != 0;
+  if (use_graph && (!c->graph_exec || c->graph_chunk != chunk || c->graph_maxit != maxit ||
+                    c->graph_tol2 != tol2 || c->graph_flex != flexible)) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    hipGraph_t g;
+    TLS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < chunk; j++) pcg_iteration(c, v, maxit, tol2, flexible);
+    TLS_HIP(hipStreamEndCapture(s, &g));
+    TLS_HIP(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    c->graph_chunk = chunk;
+    c->graph_maxit = maxit;
+    c->graph_tol2 = tol2;
+    c->graph_flex = flexible;
+  }
+  std::vector<int> hd(4, 0);
+  for (int launched = 0; launched < maxit + chunk; launched += chunk) {
+    if (use_graph)
+      TLS_HIP(hipGraphLaunch(c->graph_exec, s));
+    else
+      for (int j = 0; j < chunk; j++) pcg_iteration(c, v, maxit, tol2, flexible);
+    hd = download(c->done.p, 4, s);
+    if (hd[0]) break;
+  }
+  it = hd[1];
+  conv = hd[2] != 0;
+  if (hd[3]) fail(TLS_E_NOT_SPD, "PCG breakdown: p^T A p <= 0 (A or M^{-1} not SPD)");
+  // true residual
+  const int* zero = c->zero_int.p;
+  spmv(c, v.x, v.q, zero);
+  hipLaunchKernelGGL(k_sub, dim3(std::min(4096, div_up(n, 256))), dim3(256), 0, s, n, v.b, v.q, v.r);
+  TLS_LAUNCH_CHECK();
+  dot(c, v.r, v.r, c->scal.p + 7, zero);
+  TLS_HIP(hipMemcpyAsync(x, v.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  double rr = download(c->scal.p + 7, 1, s)[0];
+  c->h_hist = download(c->hist.p, it, s);
+  auto t1 = std::chrono::steady_clock::now();
+  c->t_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  *iters = it;
+  *relres = std::sqrt(rr / bb);
+  *converged = conv;
+  int err = download(c->errflag.p, 1, s)[0];
+  if (err & ERR_WAIT) fail(TLS_E_HIP, "a triangular-solve wait exceeded its spin limit");
+}
+
+}  // namespace tls
