@@ -84,6 +84,10 @@ typedef struct {
   int32_t jacobi_scale; /* symmetric diagonal scaling of each A_ii before factoring */
   int32_t profile;      /* tls_apply times its local triangular-solve kernels with HIP
                            events (and then waits for them); see tls_info_t */
+  int32_t solve_wgs;    /* workgroups of the persistent triangular solves (0 = default) */
+  int32_t autotune;     /* 1: at setup, time candidate workgroup counts and keep the fastest */
+  const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
+                             NULL = no persistence. A cached pick is reused without timing. */
   void* stream;         /* hipStream_t */
 } tls_options;
 
@@ -109,6 +113,8 @@ typedef struct {
   double t_local_solve_ms;    /* mean duration of their local forward + backward
                                  triangular-solve kernels (HIP events)       */
   double t_apply_ms;          /* mean duration of those whole applies         */
+  int32_t solve_wgs;          /* workgroups used by the persistent solves     */
+  int32_t tuned;              /* 0 default, 1 timed at setup, 2 read from the cache */
   const double* res_history;  /* host array: ||r_k|| / ||b|| per iteration   */
 } tls_info_t;
 

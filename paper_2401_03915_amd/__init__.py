@@ -114,6 +114,8 @@ class Preconditioner:
         out["eigvals"] = out["eigvals"][:nC]
         if Z:
             out["Z"] = out["Z"].T.copy()  # n x nC
+        if A0:
+            out["A0"] = out["A0"].T.copy()  # the C side writes column-major
         return out
 
     def local_solve(self, i: int, b: np.ndarray) -> np.ndarray:

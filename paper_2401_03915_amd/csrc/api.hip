@@ -54,6 +54,9 @@ void tls_default_options(tls_options* o) {
   o->flexible = -1;
   o->jacobi_scale = 0;
   o->profile = 0;
+  o->solve_wgs = 0;
+  o->autotune = 0;
+  o->tune_cache = nullptr;
   o->stream = nullptr;
 }
 
@@ -101,6 +104,9 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
       c->own_stream = true;
     }
     hipStream_t s = c->stream;
+    TLS_HIP(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+    TLS_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    TLS_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     c->errflag.alloc(4);
     c->zero_int.alloc(4);
     TLS_HIP(hipMemsetAsync(c->zero_int.p, 0, sizeof(int) * 4, s));
@@ -138,6 +144,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     t = clk::now();
     tls::build_coarse_operator(c.get());
     c->t_setup[5] = ms_since(t);
+    tls::choose_solve_grid(c.get());
     TLS_HIP(hipStreamSynchronize(s));
     c->t_setup[7] = ms_since(t_all);
   });
@@ -217,6 +224,8 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->n_profiled = c->prof_count;
   info->t_local_solve_ms = c->prof_count ? c->prof_local_ms / c->prof_count : 0.0;
   info->t_apply_ms = c->prof_count ? c->prof_apply_ms / c->prof_count : 0.0;
+  info->solve_wgs = c->solve_grid;
+  info->tuned = c->tuned;
   return TLS_OK;
 }
 
@@ -247,13 +256,13 @@ tls_status tls_export(const tls_ctx* cc, int32_t* sub_ptr, int32_t* sub_idx, int
     }
     if (A0 && c->nC > 0) {
       auto ht = tls::download(c->A0_orig.p, c->A0_orig.n, s);
-      const int nC = c->nC, nt = c->nt0;
+      const int nC = c->nC, nt = c->nt0, kind = c->kind;
       for (int b = 0; b < nC; b++)
-        for (int a = b; a < nC; a++) {
-          double v = ht[tls::tile_index(0, nt, a / tls::TS, b / tls::TS) * tls::TS2 + (b % tls::TS) * tls::TS +
+        for (int a = (kind == 0 ? b : 0); a < nC; a++) {
+          double v = ht[tls::tile_index(kind, nt, a / tls::TS, b / tls::TS) * tls::TS2 + (b % tls::TS) * tls::TS +
                         (a % tls::TS)];
           A0[(size_t)b * nC + a] = v;
-          A0[(size_t)a * nC + b] = v;
+          if (kind == 0) A0[(size_t)a * nC + b] = v;
         }
     }
   });

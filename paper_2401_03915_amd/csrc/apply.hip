@@ -69,10 +69,21 @@ void apply_impl(tls_ctx* c, const double* r, double* z, const int* done, T* xloc
   hipLaunchKernelGGL(k_apply_gather<T>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
                      c->sub_of_pos.p, c->sub_ptr.p, c->d_voff.p, scale, r, xloc, done);
   TLS_LAUNCH_CHECK();
-  coarse_restrict(c, r, done);
-  local_solve(c, done, profile ? c->prof_ev[1] : nullptr, profile ? c->prof_ev[2] : nullptr);
-  coarse_solve(c, done);
   const bool coarse = c->nC > 0;
+  if (coarse) {
+    // the coarse restriction and solve run on a second stream, overlapped
+    // with the local solves; joined before the final scatter
+    TLS_HIP(hipEventRecord(c->ev_fork, s));
+    TLS_HIP(hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    hipStream_t keep = c->stream;
+    c->stream = c->stream2;
+    coarse_restrict(c, r, done);
+    coarse_solve(c, done);
+    c->stream = keep;
+    TLS_HIP(hipEventRecord(c->ev_join, c->stream2));
+  }
+  local_solve(c, done, profile ? c->prof_ev[1] : nullptr, profile ? c->prof_ev[2] : nullptr);
+  if (coarse) TLS_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
   hipLaunchKernelGGL(k_apply_scatter<T>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->own_ptr.p,
                      c->own_pos.p, xloc, scale, c->part.p, c->ipos.p, c->d_nI.p, coarse ? c->kz_dev.p : nullptr,
                      c->zcol.p, c->zoff.p, c->Z.p, coarse ? c->y0.p : nullptr, z, done);

@@ -61,7 +61,7 @@ __global__ void k_az(int n, const int* __restrict__ rp, const int* __restrict__ 
 __global__ void k_scatter_a0(int N, const int* __restrict__ kz, const int* __restrict__ zcol,
                              const int* __restrict__ adj_ptr, const int* __restrict__ adj_q,
                              const int* __restrict__ adj_col, const int64_t* __restrict__ boff, const double* __restrict__ B,
-                             int nt0, double* A0) {
+                             int nt0, int kind, double* A0) {
   const int p = blockIdx.x;
   const int kp = kz[p];
   if (kp == 0) return;
@@ -72,14 +72,14 @@ __global__ void k_scatter_a0(int N, const int* __restrict__ kz, const int* __res
     for (int e = threadIdx.x; e < kp * kq; e += blockDim.x) {
       int a = e % kp, b = e / kp;
       int R = zcol[p] + a, Cc = zcol[q] + b;
-      if (R >= Cc) *elem_ptr(A0, 0, nt0, R, Cc) = B[boff[p] + a + (int64_t)(co + b) * kp];
+      if (kind == 1 || R >= Cc) *elem_ptr(A0, kind, nt0, R, Cc) = B[boff[p] + a + (int64_t)(co + b) * kp];
     }
   }
 }
 
-__global__ void k_pad_identity0(int nC, int M0, int nt0, double* A0) {
+__global__ void k_pad_identity0(int nC, int M0, int nt0, int kind, double* A0) {
   for (int a = nC + blockIdx.x * blockDim.x + threadIdx.x; a < M0; a += gridDim.x * blockDim.x)
-    *elem_ptr(A0, 0, nt0, a, a) = 1.0;
+    *elem_ptr(A0, kind, nt0, a, a) = 1.0;
 }
 
 // y0[zcol_p + a] = sum_{j < nI_p} Z_p[j, a] r[I_p[j]]
@@ -169,12 +169,12 @@ void build_coarse_operator(tls_ctx* c) {
   // tile storage of A_0
   c->M0 = div_up(c->nC, TS) * TS;
   c->nt0 = c->M0 / TS;
-  const int64_t a0_elems = tiles_of(0, c->nt0) * TS2;
+  const int64_t a0_elems = tiles_of(c->kind, c->nt0) * TS2;
   c->A0.alloc(a0_elems);
   TLS_HIP(hipMemsetAsync(c->A0.p, 0, sizeof(double) * a0_elems, s));
   hipLaunchKernelGGL(k_scatter_a0, dim3(N), dim3(256), 0, s, N, d_kz.p, c->zcol.p, d_adj_ptr.p, d_adj_q.p,
-                     d_adj_col.p, d_boff.p, B.p, c->nt0, c->A0.p);
-  hipLaunchKernelGGL(k_pad_identity0, dim3(1), dim3(64), 0, s, c->nC, c->M0, c->nt0, c->A0.p);
+                     d_adj_col.p, d_boff.p, B.p, c->nt0, c->kind, c->A0.p);
+  hipLaunchKernelGGL(k_pad_identity0, dim3(1), dim3(64), 0, s, c->nC, c->M0, c->nt0, c->kind, c->A0.p);
   TLS_LAUNCH_CHECK();
   TLS_HIP(hipStreamSynchronize(s));
   c->kz_dev.upload(kz, s);
@@ -191,9 +191,14 @@ void build_coarse_operator(tls_ctx* c) {
   c->A0_orig.alloc(a0_elems);
   TLS_HIP(hipMemcpyAsync(c->A0_orig.p, c->A0.p, sizeof(double) * a0_elems, hipMemcpyDeviceToDevice, s));
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
-  factor_tiles_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->errflag.p);
-  if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT)
-    fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
+  if (c->kind == 0)
+    factor_tiles_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->errflag.p);
+  else
+    factor_tiles_lu_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->errflag.p);
+  if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) {
+    if (c->kind == 0) fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
+    fail(TLS_E_SINGULAR, "zero pivot in the LU factorization of the coarse operator Z^T A Z");
+  }
   std::vector<int2> f, b;
   make_tasks(one_nt, toff, f, b);
   c->tasks0_fwd.upload(f, s);
@@ -223,10 +228,10 @@ void coarse_solve(tls_ctx* c, const int* done) {
   hipStream_t s = c->stream;
   solve_begin(s, c->counters0.p, done);
   const int nt = (int)c->tasks0_fwd.n;
-  trsv_f64(s, false, c->tasks0_fwd.p, nt, c->counters0.p + 0, c->flags0_fwd.p, c->counters0.p + 2, c->layout0(),
-           c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
-  trsv_f64(s, true, c->tasks0_bwd.p, nt, c->counters0.p + 1, c->flags0_bwd.p, c->counters0.p + 2, c->layout0(),
-           c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
+  trsv_f64(s, c->kind == 0 ? 0 : 2, c->tasks0_fwd.p, nt, c->counters0.p + 0, c->flags0_fwd.p, c->counters0.p + 2,
+           c->layout0(), c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
+  trsv_f64(s, c->kind == 0 ? 1 : 3, c->tasks0_bwd.p, nt, c->counters0.p + 1, c->flags0_bwd.p, c->counters0.p + 2,
+           c->layout0(), c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
 }
 
 }  // namespace tls

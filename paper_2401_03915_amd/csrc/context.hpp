@@ -7,6 +7,9 @@ struct tls_ctx {
   tls_options opt{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t stream2 = nullptr;             // coarse solve, overlapped with the local solves
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int tuned = 0;
   std::string err;
 
   // problem
@@ -111,6 +114,9 @@ struct tls_ctx {
     for (auto& e : prof_ev)
       if (e) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (stream2) (void)hipStreamDestroy(stream2);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };

@@ -249,6 +249,200 @@ __global__ void __launch_bounds__(256) k_update(int k, const int64_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched tiled LU without pivoting (general A; full tile storage)
+// ---------------------------------------------------------------------------
+
+// A_kk = L_kk U_kk in LDS (L unit lower, U upper, stored together).
+template <class T>
+__global__ void __launch_bounds__(256) k_getrf(int k, const int* __restrict__ order, LocalLayout lay, T* fac,
+                                               int* err) {
+  constexpr int LD = TS + 1;
+  __shared__ T s[TS * LD];
+  int i = order[blockIdx.x];
+  int nt = lay.nt[i];
+  T* tile = fac + lay.foff[i] + tile_index(1, nt, k, k) * TS2;
+  const int t = threadIdx.x;
+  for (int e = t; e < TS2; e += 256) s[(e / TS) * LD + (e % TS)] = tile[e];
+  bool bad = false;
+  for (int j = 0; j < TS; j++) {
+    __syncthreads();
+    T d = s[j * LD + j];
+    if (!(fabs(d) > T(0)) || !isfinite(d)) {
+      bad = true;
+      d = T(1);
+    }
+    __syncthreads();
+    if (t > j && t < TS) s[j * LD + t] /= d;  // column j of L
+    __syncthreads();
+    for (int e = t; e < TS2; e += 256) {
+      int a = e % TS, b = e / TS;
+      if (a > j && b > j) s[b * LD + a] -= s[j * LD + a] * s[b * LD + j];
+    }
+  }
+  __syncthreads();
+  if (bad && t == 0) atomicOr(err, ERR_PIVOT);
+  for (int e = t; e < TS2; e += 256) tile[e] = s[(e / TS) * LD + (e % TS)];
+}
+
+// Panels of step k: the first half of the grid solves U_kc = L_kk^{-1} A_kc
+// (c > k, one thread per column), the second half L_rk = A_rk U_kk^{-1}
+// (r > k, one thread per row).
+template <class T>
+__global__ void __launch_bounds__(64) k_trsm_lu(int k, const int64_t* __restrict__ pref, int nact, int64_t half,
+                                                const int* __restrict__ order, LocalLayout lay, T* fac) {
+  constexpr int LD = TS + 1;
+  __shared__ T Ls[TS * LD];
+  int64_t bid = blockIdx.x;
+  const bool colpanel = bid >= half;
+  if (colpanel) bid -= half;
+  int j = find_slot(pref, nact, bid);
+  int i = order[j];
+  int nt = lay.nt[i];
+  int o = k + 1 + (int)(bid - pref[j]);
+  T* base = fac + lay.foff[i];
+  const T* D = base + tile_index(1, nt, k, k) * TS2;
+  const int a = threadIdx.x;
+  for (int e = a; e < TS2; e += 64) Ls[(e / TS) * LD + (e % TS)] = D[e];
+  __syncthreads();
+  T x[TS];
+  if (!colpanel) {
+    // column a of A_ko: x <- L_kk^{-1} x (unit lower)
+    T* A = base + tile_index(1, nt, k, o) * TS2;
+#pragma unroll
+    for (int b = 0; b < TS; b++) x[b] = A[a * TS + b];
+#pragma unroll
+    for (int b = 0; b < TS; b++) {
+      T sum = x[b];
+#pragma unroll
+      for (int l = 0; l < b; l++) sum -= Ls[l * LD + b] * x[l];
+      x[b] = sum;
+    }
+#pragma unroll
+    for (int b = 0; b < TS; b++) A[a * TS + b] = x[b];
+  } else {
+    // row a of A_ok: x U_kk = row
+    T* A = base + tile_index(1, nt, o, k) * TS2;
+#pragma unroll
+    for (int b = 0; b < TS; b++) x[b] = A[b * TS + a];
+#pragma unroll
+    for (int b = 0; b < TS; b++) {
+      T sum = x[b];
+#pragma unroll
+      for (int l = 0; l < b; l++) sum -= x[l] * Ls[b * LD + l];
+      x[b] = sum / Ls[b * LD + b];
+    }
+#pragma unroll
+    for (int b = 0; b < TS; b++) A[b * TS + a] = x[b];
+  }
+}
+
+// A_rc -= L_rk U_kc for every trailing tile (r, c > k): MFMA.
+template <class T>
+__global__ void __launch_bounds__(256) k_update_lu(int k, const int64_t* __restrict__ pref, int nact,
+                                                   const int* __restrict__ order, LocalLayout lay, T* fac) {
+  constexpr int LD = LdsLd<T>::v;
+  __shared__ T As[TS * LD];
+  __shared__ T Bs[TS * LD];
+  int64_t bid = blockIdx.x;
+  int j = find_slot(pref, nact, bid);
+  int i = order[j];
+  int nt = lay.nt[i];
+  const int Tn = nt - k - 1;
+  int64_t t = bid - pref[j];
+  int r = k + 1 + (int)(t / Tn), c = k + 1 + (int)(t % Tn);
+  T* base = fac + lay.foff[i];
+  const T* Lr = base + tile_index(1, nt, r, k) * TS2;
+  const T* Uc = base + tile_index(1, nt, k, c) * TS2;
+  T* C = base + tile_index(1, nt, r, c) * TS2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TS2; e += 256) {
+    int a = e % TS, b = e / TS;
+    As[b * LD + a] = Lr[e];  // As[k][row] = L(row, k)
+    Bs[a * LD + b] = Uc[e];  // Bs[k][col] = U(k, col)
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < TS; kk += 4) {
+    T a0 = As[(kk + lk) * LD + wr + li];
+    T a1 = As[(kk + lk) * LD + wr + 16 + li];
+    T b0 = Bs[(kk + lk) * LD + wc + li];
+    T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
+    acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+    acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+    acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+    acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int row = wr + 16 * x + Mfma<T>::row(lane, q);
+        C[col * TS + row] -= acc[x][y][q];
+      }
+    }
+}
+
+template <class T>
+void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, int* err) {
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
+  int maxnt = N ? nt[order[0]] : 0;
+  std::vector<int64_t> pt, pu, off(maxnt + 1, 0), tot_t(maxnt), tot_u(maxnt);
+  std::vector<int> act(maxnt);
+  for (int k = 0; k < maxnt; k++) {
+    off[k] = (int64_t)pt.size();
+    int64_t ct = 0, cu = 0;
+    int a = 0;
+    while (a < N && nt[order[a]] > k) {
+      pt.push_back(ct);
+      pu.push_back(cu);
+      int64_t T_ = nt[order[a]] - k - 1;
+      ct += T_;
+      cu += T_ * T_;
+      a++;
+    }
+    pt.push_back(ct);
+    pu.push_back(cu);
+    act[k] = a;
+    tot_t[k] = ct;
+    tot_u[k] = cu;
+  }
+  DBuf<int> d_order;
+  DBuf<int64_t> d_pt, d_pu;
+  d_order.upload(order, s);
+  d_pt.upload(pt, s);
+  d_pu.upload(pu, s);
+  for (int k = 0; k < maxnt; k++) {
+    hipLaunchKernelGGL(k_getrf<T>, dim3(act[k]), dim3(256), 0, s, k, d_order.p, lay, fac, err);
+    TLS_LAUNCH_CHECK();
+    if (tot_t[k] > 0) {
+      hipLaunchKernelGGL(k_trsm_lu<T>, dim3((unsigned)(2 * tot_t[k])), dim3(64), 0, s, k, d_pt.p + off[k], act[k],
+                         tot_t[k], d_order.p, lay, fac);
+      TLS_LAUNCH_CHECK();
+    }
+    if (tot_u[k] > 0) {
+      hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)tot_u[k]), dim3(256), 0, s, k, d_pu.p + off[k], act[k],
+                         d_order.p, lay, fac);
+      TLS_LAUNCH_CHECK();
+    }
+  }
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
 template <class T>
 void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, int* err) {
   std::vector<int> order(N);
@@ -305,27 +499,80 @@ template <class T>
 struct Vec4;
 template <>
 struct Vec4<float> {
-  typedef float4 type;
+  typedef f32x4 type;
 };
 template <>
 struct Vec4<double> {
-  typedef double4 type;
+  typedef f64x4 type;
+};
+
+// Unroll depth of the tile loop: tiles whose loads are issued together.
+template <class T>
+struct TrsvUnroll;
+template <>
+struct TrsvUnroll<float> {
+  static constexpr int v = 4;
+};
+template <>
+struct TrsvUnroll<double> {
+  static constexpr int v = 2;
 };
 
 __device__ inline int load_flag(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Values that other workgroups of the same launch produce are exchanged
+// with device-coherent accesses (relaxed agent-scope atomics: they bypass
+// the per-XCD caches), so publishing a block needs no cache write-back and
+// reading one no invalidation: the producer waits for its coherent stores to
+// complete (s_waitcnt) before it stores the ready flag, and the consumer only
+// issues its coherent loads after it has seen the flag.
+template <class T>
+__device__ inline T load_shared(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline void store_shared(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// broadcast lane `b` of v to the whole wave (b is a compile-time constant
+// after unrolling)
+__device__ inline float bcast(float v, int b) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), b));
+}
+__device__ inline double bcast(double v, int b) {
+  long long u = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), b);
+  int hi = __builtin_amdgcn_readlane((int)(u >> 32), b);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <class V>
+__device__ inline V stream_load(const V* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 constexpr long long SPIN_LIMIT = 1ll << 26;
 
-// TRANS = false: forward substitution L y = b on block rows in ascending
-// order. TRANS = true: backward substitution L^T x = y, descending.
-template <class T, bool TRANS>
+// Solve modes of the persistent triangular-solve kernel.
+//   FWD_L : L y = b, L lower with its diagonal (Cholesky), block rows ascending
+//   BWD_LT: L^T x = y (Cholesky), block rows descending, tiles read transposed
+//   FWD_UL: L y = b, L unit lower (LU), ascending
+//   BWD_U : U x = y, U upper with its diagonal (LU), descending
+enum TrsvMode { FWD_L = 0, BWD_LT = 1, FWD_UL = 2, BWD_U = 3 };
+
+template <class T, int MODE>
 __global__ void __launch_bounds__(256) k_trsv(const int2* __restrict__ tasks, int ntasks, int* counter,
                                               int* flags, const int* __restrict__ epoch_ptr, LocalLayout lay,
                                               const T* __restrict__ fac, T* x, int* err,
                                               const int* __restrict__ done) {
   if (*done) return;
+  constexpr bool BWD = (MODE == BWD_LT || MODE == BWD_U);
+  constexpr bool TRANS = (MODE == BWD_LT);
+  constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
+  constexpr int U = TrsvUnroll<T>::v;
   constexpr int LD = TS + 1;
   typedef typename Vec4<T>::type V4;
   __shared__ T s_diag[TS * LD];
@@ -345,22 +592,22 @@ __global__ void __launch_bounds__(256) k_trsv(const int2* __restrict__ tasks, in
     T* xi = x + lay.voff[i];
     int* fl = flags + lay.toff[i];
     // diagonal tile -> LDS (used by wave 0 at the end)
-    const T* dt = base + tile_index(0, nt, r, r) * TS2;
+    const T* dt = base + tile_index(KIND, nt, r, r) * TS2;
     for (int e = tid; e < TS2; e += 256) s_diag[(e / TS) * LD + (e % TS)] = dt[e];
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    // blocks this task reads: forward c = 0..r-1, backward c = nt-1..r+1
-    int c = TRANS ? nt - 1 : 0;
-    const int stop = TRANS ? r : r;  // exclusive bound in the walking direction
-    while (TRANS ? (c > stop) : (c < stop)) {
+    // blocks this task reads: forward c = 0 .. r-1, backward c = nt-1 .. r+1
+    int c = BWD ? nt - 1 : 0;
+    const int step = BWD ? -1 : 1;
+    while (BWD ? (c > r) : (c < r)) {
       if (tid == 0) {
         int lim = c;
         long long spins = 0;
         for (;;) {
-          while ((TRANS ? (lim > stop) : (lim < stop)) && load_flag(&fl[lim]) == epoch) lim += TRANS ? -1 : 1;
+          while ((BWD ? (lim > r) : (lim < r)) && load_flag(&fl[lim]) == epoch) lim += step;
           if (lim != c) break;
           if (++spins > SPIN_LIMIT) {
             atomicOr(err, ERR_WAIT);
-            lim += TRANS ? -1 : 1;
+            lim += step;
             break;
           }
           __builtin_amdgcn_s_sleep(2);
@@ -369,33 +616,73 @@ __global__ void __launch_bounds__(256) k_trsv(const int2* __restrict__ tasks, in
       }
       __syncthreads();
       const int lim = s_lim;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      for (; TRANS ? (c > lim) : (c < lim); c += TRANS ? -1 : 1) {
-        const T* tile = base + (TRANS ? tile_index(0, nt, c, r) : tile_index(0, nt, r, c)) * TS2;
-        const T* xc = xi + c * TS;
+      const int cnt = BWD ? c - lim : lim - c;
+      int done_tiles = 0;
+      // groups of U tiles: all loads first, then the arithmetic
+      for (; done_tiles + U <= cnt; done_tiles += U) {
+        V4 v[U][4];
+        T xs[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int cc = c + step * (done_tiles + u);
+          const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
+#pragma unroll
+          for (int j = 0; j < 4; j++)
+            v[u][j] = stream_load(reinterpret_cast<const V4*>(tile + (cg + 16 * j) * TS + 4 * rg));
+          const T* xc = xi + cc * TS;
+          if (!TRANS) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) xs[u][j] = load_shared(xc + cg + 16 * j);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; j++) xs[u][j] = load_shared(xc + 4 * rg + j);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          if (!TRANS) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              acc[0] += v[u][j].x * xs[u][j];
+              acc[1] += v[u][j].y * xs[u][j];
+              acc[2] += v[u][j].z * xs[u][j];
+              acc[3] += v[u][j].w * xs[u][j];
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+              acc[j] += v[u][j].x * xs[u][0] + v[u][j].y * xs[u][1] + v[u][j].z * xs[u][2] + v[u][j].w * xs[u][3];
+          }
+        }
+      }
+      for (; done_tiles < cnt; done_tiles++) {
+        const int cc = c + step * done_tiles;
+        const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
+        const T* xc = xi + cc * TS;
         if (!TRANS) {
-          // acc[q] (row 4rg+q) += sum_j L[4rg+q][cg+16j] x[cg+16j]
 #pragma unroll
           for (int j = 0; j < 4; j++) {
             int col = cg + 16 * j;
-            V4 v = *reinterpret_cast<const V4*>(tile + col * TS + 4 * rg);
-            T xv = xc[col];
+            V4 v = stream_load(reinterpret_cast<const V4*>(tile + col * TS + 4 * rg));
+            T xv = load_shared(xc + col);
             acc[0] += v.x * xv;
             acc[1] += v.y * xv;
             acc[2] += v.z * xv;
             acc[3] += v.w * xv;
           }
         } else {
-          // acc[j] (col cg+16j) += sum_q L[4rg+q][cg+16j] x[4rg+q]
-          V4 xv = *reinterpret_cast<const V4*>(xc + 4 * rg);
+          T xv[4];
+#pragma unroll
+          for (int q = 0; q < 4; q++) xv[q] = load_shared(xc + 4 * rg + q);
 #pragma unroll
           for (int j = 0; j < 4; j++) {
             int col = cg + 16 * j;
-            V4 v = *reinterpret_cast<const V4*>(tile + col * TS + 4 * rg);
-            acc[j] += v.x * xv.x + v.y * xv.y + v.z * xv.z + v.w * xv.w;
+            V4 v = stream_load(reinterpret_cast<const V4*>(tile + col * TS + 4 * rg));
+            acc[j] += v.x * xv[0] + v.y * xv[1] + v.z * xv[2] + v.w * xv[3];
           }
         }
       }
+      c = lim;
       __syncthreads();
     }
     // reduce the partial sums into the right-hand side of the diagonal block
@@ -413,26 +700,136 @@ __global__ void __launch_bounds__(256) k_trsv(const int2* __restrict__ tasks, in
 #pragma unroll
       for (int g = 0; g < 16; g++) sum += s_red[g * TS + lane];
       T val = xi[r * TS + lane] - sum;
-      if (!TRANS) {
+      if (MODE == FWD_L || MODE == FWD_UL) {
+#pragma unroll
         for (int b = 0; b < TS; b++) {
-          T xb = __shfl(val, b) / s_diag[b * LD + b];
+          T xb = bcast(val, b);
+          if (MODE == FWD_L) xb *= T(1) / s_diag[b * LD + b];
           if (lane == b)
             val = xb;
           else if (lane > b)
             val -= s_diag[b * LD + lane] * xb;
         }
       } else {
+#pragma unroll
         for (int b = TS - 1; b >= 0; b--) {
-          T xb = __shfl(val, b) / s_diag[b * LD + b];
+          T xb = bcast(val, b) * (T(1) / s_diag[b * LD + b]);
           if (lane == b)
             val = xb;
           else if (lane < b)
-            val -= s_diag[lane * LD + b] * xb;
+            val -= (MODE == BWD_LT ? s_diag[lane * LD + b] : s_diag[b * LD + lane]) * xb;
         }
       }
-      xi[r * TS + lane] = val;
-      __threadfence();
-      if (lane == 0) __hip_atomic_store(&fl[r], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      store_shared(xi + r * TS + lane, val);
+      __builtin_amdgcn_s_waitcnt(0);  // the coherent stores above have completed
+      if (lane == 0) __hip_atomic_store(&fl[r], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+// Triangular solve with many right-hand sides on the tile storage: one
+// workgroup per (subdomain, block of 64 right-hand-side columns) walks the
+// block rows in order; each dependency is a 64x64x64 MFMA product of a
+// factor tile and a solved block, then the diagonal tile is solved for the
+// 64 columns (one thread per column). X_i is column-major with leading
+// dimension M_i (padded size), 64 * nq_i columns.
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) k_trsm_tiles(const int2* __restrict__ tasks, LocalLayout lay,
+                                                    const T* __restrict__ fac, T* X,
+                                                    const int64_t* __restrict__ xoff) {
+  constexpr bool BWD = (MODE == BWD_LT || MODE == BWD_U);
+  constexpr bool TRANS = (MODE == BWD_LT);
+  constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
+  constexpr int LD = LdsLd<T>::v;
+  constexpr int DL = TS + 1;
+  __shared__ T As[TS * LD];
+  __shared__ T Bs[TS * LD];
+  __shared__ T Ds[TS * DL];
+  const int i = tasks[blockIdx.x].x, q = tasks[blockIdx.x].y;
+  const int nt = lay.nt[i];
+  const int64_t M = (int64_t)nt * TS;
+  const T* base = fac + lay.foff[i];
+  T* Xq = X + xoff[i] + (int64_t)q * TS * M;  // column block q: element (row, j) at j*M + row
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  for (int s = 0; s < nt; s++) {
+    const int r = BWD ? nt - 1 - s : s;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+    const int c0 = BWD ? r + 1 : 0, c1 = BWD ? nt : r;
+    for (int c = c0; c < c1; c++) {
+      const T* tile = base + (TRANS ? tile_index(KIND, nt, c, r) : tile_index(KIND, nt, r, c)) * TS2;
+      __syncthreads();
+      for (int e = tid; e < TS2; e += 256) {
+        const int a = e % TS, b = e / TS;
+        if (!TRANS)
+          As[b * LD + a] = tile[e];  // A(row a, k b)
+        else
+          As[a * LD + b] = tile[e];  // A(row b, k a) = tile(a, b)
+        Bs[a * LD + b] = Xq[(int64_t)b * M + c * TS + a];  // B(k a, col b)
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < TS; kk += 4) {
+        T a0 = As[(kk + lk) * LD + wr + li];
+        T a1 = As[(kk + lk) * LD + wr + 16 + li];
+        T b0 = Bs[(kk + lk) * LD + wc + li];
+        T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
+        acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+      }
+    }
+    __syncthreads();
+    // right-hand side of the diagonal block: B_r - acc  (into Bs as [row][col])
+    const T* dt = base + tile_index(KIND, nt, r, r) * TS2;
+    for (int e = tid; e < TS2; e += 256) {
+      const int a = e % TS, b = e / TS;
+      Ds[b * DL + a] = dt[e];
+      Bs[a * LD + b] = Xq[(int64_t)b * M + r * TS + a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++) {
+        const int col = wc + 16 * y + li;
+#pragma unroll
+        for (int qq = 0; qq < 4; qq++) {
+          const int row = wr + 16 * x + Mfma<T>::row(lane, qq);
+          Bs[row * LD + col] -= acc[x][y][qq];
+        }
+      }
+    __syncthreads();
+    if (tid < TS) {
+      const int col = tid;
+      T v[TS];
+#pragma unroll
+      for (int a = 0; a < TS; a++) v[a] = Bs[a * LD + col];
+      if (!BWD) {
+#pragma unroll
+        for (int b = 0; b < TS; b++) {
+          if (MODE == FWD_L) v[b] /= Ds[b * DL + b];
+#pragma unroll
+          for (int a = b + 1; a < TS; a++) v[a] -= Ds[b * DL + a] * v[b];
+        }
+      } else {
+#pragma unroll
+        for (int b = TS - 1; b >= 0; b--) {
+          v[b] /= Ds[b * DL + b];
+#pragma unroll
+          for (int a = 0; a < b; a++) v[a] -= (TRANS ? Ds[a * DL + b] : Ds[b * DL + a]) * v[b];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < TS; a++) Xq[(int64_t)col * M + r * TS + a] = v[a];
     }
     __syncthreads();
   }
@@ -446,15 +843,27 @@ __global__ void k_solve_begin(int* counters, const int* done) {
 }
 
 template <class T>
-void trsv(hipStream_t s, bool transpose, const int2* tasks, int ntasks, int* counter, int* flags,
-          const int* epoch, const LocalLayout& lay, const T* fac, T* x, int* err, const int* done, int grid) {
+void trsv(hipStream_t s, int mode, const int2* tasks, int ntasks, int* counter, int* flags, const int* epoch,
+          const LocalLayout& lay, const T* fac, T* x, int* err, const int* done, int grid) {
   grid = std::max(1, std::min(grid, ntasks));
-  if (!transpose)
-    hipLaunchKernelGGL((k_trsv<T, false>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
-                       fac, x, err, done);
-  else
-    hipLaunchKernelGGL((k_trsv<T, true>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
-                       fac, x, err, done);
+  switch (mode) {
+    case FWD_L:
+      hipLaunchKernelGGL((k_trsv<T, FWD_L>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
+                         fac, x, err, done);
+      break;
+    case BWD_LT:
+      hipLaunchKernelGGL((k_trsv<T, BWD_LT>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
+                         fac, x, err, done);
+      break;
+    case FWD_UL:
+      hipLaunchKernelGGL((k_trsv<T, FWD_UL>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
+                         fac, x, err, done);
+      break;
+    default:
+      hipLaunchKernelGGL((k_trsv<T, BWD_U>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
+                         fac, x, err, done);
+      break;
+  }
   TLS_LAUNCH_CHECK();
 }
 
@@ -465,10 +874,10 @@ void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const Lo
   factor_tiles<double>(s, N, nt, lay, fac, err);
 }
 
-void trsv_f64(hipStream_t s, bool transpose, const int2* tasks, int ntasks, int* counter, int* flags,
+void trsv_f64(hipStream_t s, int mode, const int2* tasks, int ntasks, int* counter, int* flags,
               const int* epoch, const LocalLayout& lay, const double* fac, double* x, int* err, const int* done,
               int grid) {
-  trsv<double>(s, transpose, tasks, ntasks, counter, flags, epoch, lay, fac, x, err, done, grid);
+  trsv<double>(s, mode, tasks, ntasks, counter, flags, epoch, lay, fac, x, err, done, grid);
 }
 
 void solve_begin(hipStream_t s, int* counters, const int* done) {
@@ -515,14 +924,28 @@ void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist) {
 }
 
 void factor_local(tls_ctx* c) {
-  if (c->kind != 0) fail(TLS_E_ARG, "general matrices (LU) are not available in this build");
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), c->stream));
-  if (c->fp32)
-    factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->errflag.p);
-  else
-    factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->errflag.p);
+  if (c->kind == 0) {
+    if (c->fp32)
+      factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->errflag.p);
+    else
+      factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->errflag.p);
+  } else {
+    if (c->fp32)
+      factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->errflag.p);
+    else
+      factor_tiles_lu<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->errflag.p);
+  }
   int err = download(c->errflag.p, 1, c->stream)[0];
-  if (err & ERR_PIVOT) fail(TLS_E_NOT_SPD, "non-positive pivot in a local Cholesky factorization");
+  if (err & ERR_PIVOT) {
+    if (c->kind == 0) fail(TLS_E_NOT_SPD, "non-positive pivot in a local Cholesky factorization");
+    fail(TLS_E_SINGULAR, "zero or non-finite pivot in a local LU factorization (no pivoting)");
+  }
+}
+
+void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
+                         int* err) {
+  factor_tiles_lu<double>(s, N, nt, lay, fac, err);
 }
 
 void make_tasks(const std::vector<int>& nt, const std::vector<int64_t>& toff, std::vector<int2>& fwd,
@@ -569,14 +992,49 @@ void build_solve_tasks(tls_ctx* c) {
 
 void local_backward(tls_ctx* c, float* x, const int* done) {
   solve_begin(c->stream, c->counters.p, done);
-  trsv<float>(c->stream, true, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
+  trsv<float>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
               c->counters.p + 2, c->layout(), c->fac32.p, x, c->errflag.p, done, c->solve_grid);
 }
 
 void local_backward(tls_ctx* c, double* x, const int* done) {
   solve_begin(c->stream, c->counters.p, done);
-  trsv<double>(c->stream, true, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
+  trsv<double>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
                c->counters.p + 2, c->layout(), c->fac64.p, x, c->errflag.p, done, c->solve_grid);
+}
+
+template <class T>
+void trsm_tiles_impl(tls_ctx* c, int mode, T* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+  hipStream_t s = c->stream;
+  std::vector<int2> tasks;
+  // largest subdomains first
+  std::vector<int> order(c->N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->h_nt[a] > c->h_nt[b]; });
+  for (int i : order)
+    for (int q = 0; q < nq[i]; q++) tasks.push_back(make_int2(i, q));
+  if (tasks.empty()) return;
+  DBuf<int2> d_tasks;
+  DBuf<int64_t> d_xoff;
+  d_tasks.upload(tasks, s);
+  d_xoff.upload(xoff, s);
+  const dim3 g((unsigned)tasks.size());
+  LocalLayout lay = c->layout();
+  const T* fac = c->fp32 ? reinterpret_cast<const T*>(c->fac32.p) : reinterpret_cast<const T*>(c->fac64.p);
+  switch (mode) {
+    case FWD_L: hipLaunchKernelGGL((k_trsm_tiles<T, FWD_L>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
+    case BWD_LT: hipLaunchKernelGGL((k_trsm_tiles<T, BWD_LT>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
+    case FWD_UL: hipLaunchKernelGGL((k_trsm_tiles<T, FWD_UL>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
+    default: hipLaunchKernelGGL((k_trsm_tiles<T, BWD_U>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
+  }
+  TLS_LAUNCH_CHECK();
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+void local_trsm_backward(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+  trsm_tiles_impl<float>(c, c->kind == 0 ? BWD_LT : BWD_U, X, nq, xoff);
+}
+void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+  trsm_tiles_impl<double>(c, c->kind == 0 ? BWD_LT : BWD_U, X, nq, xoff);
 }
 
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_end) {
@@ -586,14 +1044,14 @@ void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev
   solve_begin(s, c->counters.p, done);
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
   if (c->fp32) {
-    trsv<float>(s, false, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
+    trsv<float>(s, c->kind == 0 ? FWD_L : FWD_UL, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
                 c->fac32.p, c->xloc32.p, c->errflag.p, done, c->solve_grid);
-    trsv<float>(s, true, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
+    trsv<float>(s, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
                 c->fac32.p, c->xloc32.p, c->errflag.p, done, c->solve_grid);
   } else {
-    trsv<double>(s, false, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
+    trsv<double>(s, c->kind == 0 ? FWD_L : FWD_UL, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
                  c->fac64.p, c->xloc64.p, c->errflag.p, done, c->solve_grid);
-    trsv<double>(s, true, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
+    trsv<double>(s, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
                  c->fac64.p, c->xloc64.p, c->errflag.p, done, c->solve_grid);
   }
   if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));

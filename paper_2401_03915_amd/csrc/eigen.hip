@@ -39,39 +39,57 @@ struct EigLayout {
   const int64_t* o_TG;   // nG*nT
   const int64_t* o_GG;   // nG*nG
   const int64_t* o_TT;   // nT*nT
+  const int64_t* o_X;    // M_i x 64 nq_i right-hand-side blocks (general: H)
+  const int* kreq;
 };
 
-// mode 0: F = -L_TI^T (nI x nT)    mode 1: Tm = L_TG^T (nG x nT)
-// mode 2: L_GG^T (upper, nG x nG) mode 3: L_GI (nG x nI)
-// mode 4: L_TT (lower, nT x nT)   mode 5: L_TT^T (upper, nT x nT)
+// Blocks of the local factor copied to dense column-major buffers.
+// SPD (Cholesky, lower tiles):
+//   mode 0: F = -L_TI^T (nI x nT)    mode 1: Tm = L_TG^T (nG x nT)
+//   mode 2: L_GG^T (upper, nG x nG) mode 3: L_GI (nG x nI)
+//   mode 4: L_TT (lower, nT x nT)   mode 5: L_TT^T (upper, nT x nT)
+// General (LU, full tiles; U upper with its diagonal):
+//   mode 6: U_GT (nG x nT)          mode 7: U_GG (upper, nG x nG)
+//   mode 8: U_IG (nI x nG)          mode 9: -U_IT into rows < nI of X (leading dim M_i)
 template <class S, class D>
 __global__ void k_extract(int mode, EigLayout e, const S* __restrict__ fac, D* out) {
   const int i = blockIdx.y;
   const int nI = e.nI[i], nG = e.nG[i], nT = e.nT[i], nt = e.nt[i];
   const int nP = nI + nG;
   const S* base = fac + e.foff[i];
+  const int kind = mode >= 6 ? 1 : 0;
   int rows, cols;
-  int64_t off;
+  int64_t off, ld;
   switch (mode) {
     case 0: rows = nI; cols = nT; off = e.o_F[i]; break;
     case 1: rows = nG; cols = nT; off = e.o_TG[i]; break;
     case 2: rows = nG; cols = nG; off = e.o_GG[i]; break;
     case 3: rows = nG; cols = nI; off = e.o_GI[i]; break;
+    case 6: rows = nG; cols = nT; off = e.o_TG[i]; break;
+    case 7: rows = nG; cols = nG; off = e.o_GG[i]; break;
+    case 8: rows = nI; cols = nG; off = e.o_GI[i]; break;
+    case 9: rows = nI; cols = nT; off = e.o_X[i]; break;
     default: rows = nT; cols = nT; off = e.o_TT[i]; break;
   }
+  ld = mode == 9 ? (int64_t)nt * TS : rows;
+  if (e.kreq[i] <= 0) return;
   const int64_t total = (int64_t)rows * cols;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     int a = (int)(x % rows), b = (int)(x / rows);
     S v = S(0);
     switch (mode) {
-      case 0: v = -*elem_ptr(base, 0, nt, nP + b, a); break;
-      case 1: v = *elem_ptr(base, 0, nt, nP + b, nI + a); break;
-      case 2: v = b >= a ? *elem_ptr(base, 0, nt, nI + b, nI + a) : S(0); break;
-      case 3: v = *elem_ptr(base, 0, nt, nI + a, b); break;
-      case 4: v = a >= b ? *elem_ptr(base, 0, nt, nP + a, nP + b) : S(0); break;
-      default: v = b >= a ? *elem_ptr(base, 0, nt, nP + b, nP + a) : S(0); break;
+      case 0: v = -*elem_ptr(base, kind, nt, nP + b, a); break;
+      case 1: v = *elem_ptr(base, kind, nt, nP + b, nI + a); break;
+      case 2: v = b >= a ? *elem_ptr(base, kind, nt, nI + b, nI + a) : S(0); break;
+      case 3: v = *elem_ptr(base, kind, nt, nI + a, b); break;
+      case 4: v = a >= b ? *elem_ptr(base, kind, nt, nP + a, nP + b) : S(0); break;
+      case 5: v = b >= a ? *elem_ptr(base, kind, nt, nP + b, nP + a) : S(0); break;
+      case 6: v = *elem_ptr(base, kind, nt, nI + a, nP + b); break;
+      case 7: v = b >= a ? *elem_ptr(base, kind, nt, nI + a, nI + b) : S(0); break;
+      case 8: v = *elem_ptr(base, kind, nt, a, nI + b); break;
+      default: v = -*elem_ptr(base, kind, nt, a, nP + b); break;
     }
-    out[off + x] = (D)v;
+    out[off + a + (int64_t)b * ld] = (D)v;
   }
 }
 
@@ -83,9 +101,10 @@ __global__ void k_convert(int64_t count, const S* __restrict__ in, D* out) {
 
 // C <- (X^T + X)/2 is not what we want; transpose square blocks in place:
 // out = in^T for each subdomain's nT x nT block.
-__global__ void k_transpose_blocks(const int* __restrict__ nT_, const int64_t* __restrict__ off, const double* in,
-                                   double* out, int symmetrize) {
+__global__ void k_transpose_blocks(const int* __restrict__ nT_, const int64_t* __restrict__ off,
+                                   const int* __restrict__ kreq, const double* in, double* out, int symmetrize) {
   const int i = blockIdx.y;
+  if (kreq[i] <= 0) return;
   const int n = nT_[i];
   const double* a = in + off[i];
   double* b = out + off[i];
@@ -455,8 +474,9 @@ __global__ void __launch_bounds__(256) k_subspace(const int* __restrict__ nT_, c
 // columns that are numerically dependent, and store them as Z_i (fp64).
 template <class T>
 __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const int* __restrict__ kf_,
-                                              const int64_t* __restrict__ voff, int64_t sumM,
-                                              const T* __restrict__ xr, const double* __restrict__ scale,
+                                              const int64_t* __restrict__ voff, const int64_t* __restrict__ xoff,
+                                              const int* __restrict__ nt_, const T* __restrict__ xr,
+                                              const double* __restrict__ scale,
                                               const int64_t* __restrict__ zoff, double* Z, int* kfinal,
                                               int* keep_idx) {
   __shared__ double red[16];
@@ -469,7 +489,7 @@ __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const
     double* v = Zi + (int64_t)kept * nI;
     double n0 = 0.0;
     for (int r = tid; r < nI; r += 256) {
-      double x = (double)xr[(int64_t)a * sumM + voff[i] + r];
+      double x = (double)xr[xoff[i] + (int64_t)a * nt_[i] * TS + r];
       if (scale) x *= scale[voff[i] + r];
       v[r] = x;
       n0 += x * x;
@@ -504,9 +524,10 @@ template <class T>
 static void basis_impl(tls_ctx* c, T* fac) {
   hipStream_t s = c->stream;
   const int N = c->N;
-  std::vector<int> nI(N), nG(N), nT(N), kreq(N);
+  const bool general = c->kind == 1;
+  std::vector<int> nI(N), nG(N), nT(N), kreq(N), nqH(N, 0), nqV(N, 0);
   std::vector<int64_t> oF(N + 1, 0), oGI(N + 1, 0), oTG(N + 1, 0), oGG(N + 1, 0), oTT(N + 1, 0), oY(N + 1, 0),
-      oZv(N + 1, 0), oZ(N + 1, 0);
+      oZv(N + 1, 0), oZ(N + 1, 0), oXH(N + 1, 0), oXV(N + 1, 0);
   std::vector<int> oth(N + 1, 0);
   int kmax = 0;
   for (int i = 0; i < N; i++) {
@@ -514,25 +535,36 @@ static void basis_impl(tls_ctx* c, T* fac) {
     nG[i] = c->h_nP[i] - c->h_nI[i];
     nT[i] = c->h_m[i] - c->h_nP[i];
     kreq[i] = std::min(std::min(c->nev, nT[i]), PMAX);
+    if (general) kreq[i] = std::min(kreq[i], nI[i]);
     kmax = std::max(kmax, kreq[i]);
+    const int64_t M = (int64_t)c->h_nt[i] * TS;
     int p = std::min(nT[i], std::min(PMAX, kreq[i] + c->opt.eig_oversample));
-    oF[i + 1] = oF[i] + (int64_t)nI[i] * nT[i];
-    oGI[i + 1] = oGI[i] + (int64_t)nG[i] * nI[i];
-    oTG[i + 1] = oTG[i] + (int64_t)nG[i] * nT[i];
-    oGG[i + 1] = oGG[i] + (int64_t)nG[i] * nG[i];
-    oTT[i + 1] = oTT[i] + (int64_t)nT[i] * nT[i];
-    oY[i + 1] = oY[i] + (int64_t)nT[i] * std::max(p, 1);
+    const bool act = kreq[i] > 0;
+    oF[i + 1] = oF[i] + (act && !general ? (int64_t)nI[i] * nT[i] : 0);
+    oGI[i + 1] = oGI[i] + (act ? (int64_t)nG[i] * nI[i] : 0);
+    oTG[i + 1] = oTG[i] + (act ? (int64_t)nG[i] * nT[i] : 0);
+    oGG[i + 1] = oGG[i] + (act ? (int64_t)nG[i] * nG[i] : 0);
+    oTT[i + 1] = oTT[i] + (act ? (int64_t)nT[i] * nT[i] : 0);
+    oY[i + 1] = oY[i] + (act ? (int64_t)nT[i] * std::max(p, 1) : 0);
     oZv[i + 1] = oZv[i] + (int64_t)nT[i] * kreq[i];
     oZ[i + 1] = oZ[i] + (int64_t)nI[i] * kreq[i];
     oth[i + 1] = oth[i] + kreq[i];
+    nqH[i] = (general && act) ? (nT[i] + TS - 1) / TS : 0;
+    nqV[i] = act ? 1 : 0;
+    oXH[i + 1] = oXH[i] + M * TS * nqH[i];
+    oXV[i + 1] = oXV[i] + M * TS * nqV[i];
   }
   if (kmax == 0) {
     c->nC = 0;
     c->h_zcol.assign(N + 1, 0);
+    c->h_zoff.assign(N + 1, 0);
+    c->zcol.upload(c->h_zcol, s);
+    c->zoff.upload(c->h_zoff, s);
+    c->Z.alloc(1);
     return;
   }
   DBuf<int> d_nI, d_nG, d_nT, d_kreq;
-  DBuf<int64_t> d_oF, d_oGI, d_oTG, d_oGG, d_oTT, d_oY, d_oZv, d_oZ;
+  DBuf<int64_t> d_oF, d_oGI, d_oTG, d_oGG, d_oTT, d_oY, d_oZv, d_oZ, d_oXH, d_oXV;
   DBuf<int> d_oth;
   d_nI.upload(nI, s);
   d_nG.upload(nG, s);
@@ -546,76 +578,121 @@ static void basis_impl(tls_ctx* c, T* fac) {
   d_oY.upload(oY, s);
   d_oZv.upload(oZv, s);
   d_oZ.upload(oZ, s);
+  d_oXH.upload(oXH, s);
+  d_oXV.upload(oXV, s);
   d_oth.upload(oth, s);
-  EigLayout el{d_nI.p, d_nG.p, d_nT.p, c->d_m.p, c->d_nt.p, c->d_foff.p, d_oF.p, d_oGI.p, d_oTG.p, d_oGG.p, d_oTT.p};
-
-  DBuf<T> F, GI, TG, GGt, K;
-  DBuf<double> LTT, LTTt, C64, C64b;
-  F.alloc(oF[N]);
-  K.alloc(oTT[N]);
-  LTT.alloc(oTT[N]);
-  LTTt.alloc(oTT[N]);
-  C64.alloc(oTT[N]);
-  C64b.alloc(oTT[N]);
+  EigLayout el{d_nI.p, d_nG.p,  d_nT.p,  c->d_m.p, c->d_nt.p, c->d_foff.p, d_oF.p,
+               d_oGI.p, d_oTG.p, d_oGG.p, d_oTT.p, d_oXH.p,  d_kreq.p};
   const dim3 eg(64, N);
-  hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 0, el, fac, F.p);
-  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
-  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 5, el, fac, LTTt.p);
-  TLS_LAUNCH_CHECK();
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
+
+  DBuf<T> F, GI, TG, GGt, K, XH;
+  DBuf<double> LTT, LTTt, C64, C64b;
+  K.alloc(oTT[N]);
+  C64.alloc(oTT[N]);
   if (oGG[N] > 0) {
     GI.alloc(oGI[N]);
     TG.alloc(oTG[N]);
     GGt.alloc(oGG[N]);
-    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 1, el, fac, TG.p);
-    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 2, el, fac, GGt.p);
-    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 3, el, fac, GI.p);
-    TLS_LAUNCH_CHECK();
-    // Tm = L_GG^{-T} L_TG^T
-    std::vector<TriDesc> td;
-    for (int i = 0; i < N; i++) td.push_back(TriDesc{nG[i], kreq[i] > 0 ? nT[i] : 0, oGG[i], oTG[i], (int64_t)nG[i]});
-    batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
-    // F += L_GI^T Tm
-    std::vector<GemmDesc> gd;
-    for (int i = 0; i < N; i++)
-      if (kreq[i] > 0 && nG[i] > 0)
-        gd.push_back(GemmDesc{nI[i], nT[i], nG[i], nG[i], nG[i], oGI[i], oTG[i], oF[i], (int64_t)nI[i]});
-    batched_gemm<T>(s, gd, true, false, GI.p, TG.p, F.p, T(1), T(1));
   }
-  // K = F^T F
-  {
+  if (!general) {
+    // ---- SPD: eq. gevpsvd through the Cholesky blocks --------------------
+    F.alloc(oF[N]);
+    LTT.alloc(oTT[N]);
+    LTTt.alloc(oTT[N]);
+    C64b.alloc(oTT[N]);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 0, el, fac, F.p);
+    hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
+    hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 5, el, fac, LTTt.p);
+    TLS_LAUNCH_CHECK();
+    if (oGG[N] > 0) {
+      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 1, el, fac, TG.p);
+      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 2, el, fac, GGt.p);
+      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 3, el, fac, GI.p);
+      TLS_LAUNCH_CHECK();
+      // Tm = L_GG^{-T} L_TG^T ; F += L_GI^T Tm
+      std::vector<TriDesc> td;
+      for (int i = 0; i < N; i++)
+        if (kreq[i] > 0) td.push_back(TriDesc{nG[i], nT[i], oGG[i], oTG[i], (int64_t)nG[i]});
+      batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
+      std::vector<GemmDesc> gd;
+      for (int i = 0; i < N; i++)
+        if (kreq[i] > 0 && nG[i] > 0)
+          gd.push_back(GemmDesc{nI[i], nT[i], nG[i], nG[i], nG[i], oGI[i], oTG[i], oF[i], (int64_t)nI[i]});
+      batched_gemm<T>(s, gd, true, false, GI.p, TG.p, F.p, T(1), T(1));
+    }
+    // K = F^T F
     std::vector<GemmDesc> gd;
     for (int i = 0; i < N; i++)
       if (kreq[i] > 0) gd.push_back(GemmDesc{nT[i], nT[i], nI[i], nI[i], nI[i], oF[i], oF[i], oTT[i], (int64_t)nT[i]});
     batched_gemm<T>(s, gd, true, false, F.p, F.p, K.p, T(1), T(0));
-  }
-  // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
-  hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)oTT[N], K.p, C64.p);
-  TLS_LAUNCH_CHECK();
-  {
+    // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)oTT[N], K.p, C64.p);
+    TLS_LAUNCH_CHECK();
     std::vector<TriDesc> td;
-    for (int i = 0; i < N; i++) td.push_back(TriDesc{nT[i], kreq[i] > 0 ? nT[i] : 0, oTT[i], oTT[i], (int64_t)nT[i]});
+    for (int i = 0; i < N; i++)
+      if (kreq[i] > 0) td.push_back(TriDesc{nT[i], nT[i], oTT[i], oTT[i], (int64_t)nT[i]});
     batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64.p, c->errflag.p);
-    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, C64.p, C64b.p, 0);
+    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, d_kreq.p, C64.p, C64b.p, 0);
     TLS_LAUNCH_CHECK();
     batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64b.p, c->errflag.p);
-    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, C64b.p, C64.p, 1);
+    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, d_kreq.p, C64b.p, C64.p, 1);
+    TLS_LAUNCH_CHECK();
+    if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_NOT_SPD, "zero pivot in a Schur-complement block");
+  } else {
+    // ---- general: Section 6, H = rows I of -A_{O'O'}^{-1} A_{O'T} ---------
+    // with A_ii = L U ordered [I, G, T]: H = U_II^{-1} (-U_IT + U_IG U_GG^{-1} U_GT)
+    XH.alloc(std::max<int64_t>(oXH[N], 1));
+    TLS_HIP(hipMemsetAsync(XH.p, 0, sizeof(T) * std::max<int64_t>(oXH[N], 1), s));
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 9, el, fac, XH.p);
+    TLS_LAUNCH_CHECK();
+    if (oGG[N] > 0) {
+      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 6, el, fac, TG.p);
+      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 7, el, fac, GGt.p);
+      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 8, el, fac, GI.p);
+      TLS_LAUNCH_CHECK();
+      std::vector<TriDesc> td;
+      for (int i = 0; i < N; i++)
+        if (kreq[i] > 0) td.push_back(TriDesc{nG[i], nT[i], oGG[i], oTG[i], (int64_t)nG[i]});
+      batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
+      std::vector<GemmDesc> gd;
+      for (int i = 0; i < N; i++)
+        if (kreq[i] > 0 && nG[i] > 0)
+          gd.push_back(GemmDesc{nI[i], nT[i], nG[i], nI[i], nG[i], oGI[i], oTG[i], oXH[i],
+                                (int64_t)c->h_nt[i] * TS});
+      batched_gemm<T>(s, gd, false, false, GI.p, TG.p, XH.p, T(1), T(1));
+    }
+    if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_SINGULAR, "zero pivot in a local U_GG block");
+    // H = U_II^{-1} X: the backward solve on the whole factor leaves rows G, T zero
+    local_trsm_backward(c, XH.p, nqH, oXH);
+    // K = H^T H
+    std::vector<GemmDesc> gd;
+    for (int i = 0; i < N; i++) {
+      const int M = c->h_nt[i] * TS;
+      if (kreq[i] > 0) gd.push_back(GemmDesc{nT[i], nT[i], nI[i], M, M, oXH[i], oXH[i], oTT[i], (int64_t)nT[i]});
+    }
+    batched_gemm<T>(s, gd, true, false, XH.p, XH.p, K.p, T(1), T(0));
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)oTT[N], K.p, C64.p);
     TLS_LAUNCH_CHECK();
   }
-  if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_NOT_SPD, "zero pivot in a Schur-complement block");
+  K.release();
+  GI.release();
+  TG.release();
+  GGt.release();
 
-  // subspace iteration
+  // ---- subspace iteration on C ----------------------------------------------
   DBuf<double> Yb, Wb, zv, theta, resid;
   DBuf<int> kfound, its;
-  Yb.alloc(oY[N]);
-  Wb.alloc(oY[N]);
-  zv.alloc(oZv[N]);
-  theta.alloc(oth[N]);
+  Yb.alloc(std::max<int64_t>(oY[N], 1));
+  Wb.alloc(std::max<int64_t>(oY[N], 1));
+  zv.alloc(std::max<int64_t>(oZv[N], 1));
+  theta.alloc(std::max(oth[N], 1));
   resid.alloc(N);
   kfound.alloc(N);
   its.alloc(N);
   const double tol = c->opt.eig_tol > 0 ? c->opt.eig_tol : (c->fp32 ? 1e-6 : 1e-9);
-  const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;
+  double tau2 = -1.0;
+  if (c->opt.tau > 0) tau2 = c->opt.tau * c->opt.tau;  // lambda^2 > tau^2 (SPD) or sigma^2 > tau^2 (general)
   hipLaunchKernelGGL(k_subspace, dim3(N), dim3(256), 0, s, d_nT.p, d_kreq.p, d_oTT.p, C64.p, d_oY.p, Yb.p, Wb.p,
                      c->opt.eig_oversample, c->opt.eig_maxit, tol, (uint64_t)c->opt.seed, d_oZv.p, zv.p, d_oth.p,
                      theta.p, kfound.p, resid.p, its.p, tau2, 1e-12, c->errflag.p);
@@ -623,63 +700,68 @@ static void basis_impl(tls_ctx* c, T* fac) {
   auto h_kf = download(kfound.p, N, s);
   auto h_res = download(resid.p, N, s);
   auto h_its = download(its.p, N, s);
-  auto h_th = download(theta.p, oth[N], s);
+  auto h_th = download(theta.p, std::max(oth[N], 1), s);
   c->eig_resid_max = 0;
   c->eig_iters_max = 0;
   for (int i = 0; i < N; i++) {
     c->eig_resid_max = std::max(c->eig_resid_max, h_res[i]);
     c->eig_iters_max = std::max(c->eig_iters_max, h_its[i]);
   }
-  // w_T = L_TT^{-T} z
-  {
+  Yb.release();
+  Wb.release();
+
+  // ---- coarse vectors into X_V (rows I, one 64-column block per subdomain) --
+  DBuf<T> wT, XV;
+  wT.alloc(std::max<int64_t>(oZv[N], 1));
+  XV.alloc(std::max<int64_t>(oXV[N], 1));
+  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
+  if (!general) {
+    // w_T = L_TT^{-T} z ; V = F w_T ; then x = L^{-T} [V; 0] gives rows I = L_II^{-T} V
     std::vector<TriDesc> td;
-    for (int i = 0; i < N; i++) td.push_back(TriDesc{nT[i], h_kf[i], oTT[i], oZv[i], (int64_t)nT[i]});
+    for (int i = 0; i < N; i++)
+      if (h_kf[i] > 0) td.push_back(TriDesc{nT[i], h_kf[i], oTT[i], oZv[i], (int64_t)nT[i]});
     batched_trsm<double>(s, td, UPPER_BWD, LTTt.p, zv.p, c->errflag.p);
-  }
-  // V = F w_T into padded right-hand sides [V; 0], then x = L^{-T} [V; 0]
-  int kf_max = 0;
-  for (int i = 0; i < N; i++) kf_max = std::max(kf_max, h_kf[i]);
-  DBuf<T> wT, xr;
-  wT.alloc(oZv[N]);
-  hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
-  TLS_LAUNCH_CHECK();
-  xr.alloc((size_t)std::max(kf_max, 1) * c->sum_M);
-  TLS_HIP(hipMemsetAsync(xr.p, 0, sizeof(T) * std::max(kf_max, 1) * c->sum_M, s));
-  {
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
+    TLS_LAUNCH_CHECK();
     std::vector<GemmDesc> gd;
     for (int i = 0; i < N; i++)
       if (h_kf[i] > 0)
-        gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], nI[i], nT[i], oF[i], oZv[i], c->h_voff[i], c->sum_M});
-    batched_gemm<T>(s, gd, false, false, F.p, wT.p, xr.p, T(1), T(0));
+        gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], nI[i], nT[i], oF[i], oZv[i], oXV[i], (int64_t)c->h_nt[i] * TS});
+    batched_gemm<T>(s, gd, false, false, F.p, wT.p, XV.p, T(1), T(0));
+    F.release();
+    local_trsm_backward(c, XV.p, nqV, oXV);
+  } else {
+    // left singular directions: V = H v
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
+    TLS_LAUNCH_CHECK();
+    std::vector<GemmDesc> gd;
+    for (int i = 0; i < N; i++) {
+      const int M = c->h_nt[i] * TS;
+      if (h_kf[i] > 0) gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], M, nT[i], oXH[i], oZv[i], oXV[i], (int64_t)M});
+    }
+    batched_gemm<T>(s, gd, false, false, XH.p, wT.p, XV.p, T(1), T(0));
+    XH.release();
   }
-  F.release();
-  K.release();
-  GI.release();
-  TG.release();
-  GGt.release();
-  for (int j = 0; j < kf_max; j++) {
-    local_backward(c, xr.p + (size_t)j * c->sum_M, c->zero_int.p);
-  }
-  TLS_HIP(hipStreamSynchronize(s));
-  // orthonormalize into Z
+  // ---- orthonormalize into Z --------------------------------------------------
   DBuf<double> Zt;
   DBuf<int> kfin, keep;
   Zt.alloc(std::max<int64_t>(oZ[N], 1));
   kfin.alloc(N);
   keep.alloc((size_t)N * PMAX);
-  DBuf<int64_t> d_oZ2;
-  hipLaunchKernelGGL(k_orth<T>, dim3(N), dim3(256), 0, s, d_nI.p, kfound.p, c->d_voff.p, c->sum_M, xr.p,
+  hipLaunchKernelGGL(k_orth<T>, dim3(N), dim3(256), 0, s, d_nI.p, kfound.p, c->d_voff.p, d_oXV.p, c->d_nt.p, XV.p,
                      c->opt.jacobi_scale ? c->scale.p : nullptr, d_oZ.p, Zt.p, kfin.p, keep.p);
   TLS_LAUNCH_CHECK();
   auto h_kfin = download(kfin.p, N, s);
   auto h_keep = download(keep.p, (size_t)N * PMAX, s);
-  // compact: Z_i keeps its first kfin columns at oZ[i]; record columns
   c->h_zcol.assign(N + 1, 0);
   c->h_zoff = oZ;
   c->h_eig.clear();
   for (int i = 0; i < N; i++) {
     c->h_zcol[i + 1] = c->h_zcol[i] + h_kfin[i];
-    for (int a = 0; a < h_kfin[i]; a++) c->h_eig.push_back(h_th[oth[i] + h_keep[(size_t)i * PMAX + a]]);
+    for (int a = 0; a < h_kfin[i]; a++) {
+      double th = h_th[oth[i] + h_keep[(size_t)i * PMAX + a]];
+      c->h_eig.push_back(general ? std::sqrt(std::max(th, 0.0)) : th);
+    }
   }
   c->nC = c->h_zcol[N];
   c->Z.alloc(std::max<int64_t>(oZ[N], 1));
@@ -699,7 +781,6 @@ void build_coarse_basis(tls_ctx* c) {
     c->Z.alloc(1);
     return;
   }
-  if (c->kind != 0) fail(TLS_E_ARG, "the general-matrix coarse space is not available in this build");
   if (c->opt.nev1 > 0) fail(TLS_E_ARG, "nev1 > 0 (eq. uppergevp vectors) is not available in this build");
   if (c->fp32)
     basis_impl<float>(c, c->fac32.p);

@@ -22,12 +22,19 @@ void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hip
 // backward substitution L^T x = x only, on a padded vector of the context's precision
 void local_backward(tls_ctx* c, float* x, const int* done);
 void local_backward(tls_ctx* c, double* x, const int* done);
+// backward substitution (L^T for SPD, U for general) with many right-hand
+// sides: X_i (M_i x 64 nq_i, column-major, at xoff[i]) is overwritten
+void local_trsm_backward(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
+void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
+void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
+                         int* err);
 // generic pieces reused for the coarse factor (always fp64)
 void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay,
                       double* fac, int* err);
 void make_tasks(const std::vector<int>& nt, const std::vector<int64_t>& toff, std::vector<int2>& fwd,
                 std::vector<int2>& bwd);
-void trsv_f64(hipStream_t s, bool transpose, const int2* tasks, int ntasks, int* counter, int* flags,
+// mode: 0 L y = b (Cholesky), 1 L^T x = y, 2 unit-lower L y = b (LU), 3 U x = y
+void trsv_f64(hipStream_t s, int mode, const int2* tasks, int ntasks, int* counter, int* flags,
               const int* epoch, const LocalLayout& lay, const double* fac, double* x, int* err,
               const int* done, int grid);
 void solve_begin(hipStream_t s, int* counters, const int* done);
@@ -39,6 +46,9 @@ void build_coarse_basis(tls_ctx* c);
 void build_coarse_operator(tls_ctx* c);
 void coarse_restrict(tls_ctx* c, const double* r, const int* done);
 void coarse_solve(tls_ctx* c, const int* done);
+
+// tune.hip: workgroup count of the persistent solves (default / timed / cached)
+void choose_solve_grid(tls_ctx* c);
 
 // apply.hip: z = M^{-1} r
 void apply_precond(tls_ctx* c, const double* r, double* z, const int* done, bool profile = false);

@@ -158,6 +158,160 @@ void pcg_iteration(tls_ctx* c, const PcgVec& v, int maxit, double tol2, bool fle
   TLS_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// Flexible GMRES(m), right preconditioned (general A). The Hessenberg matrix,
+// Givens rotations, the inner index j and the stop flags live on the device.
+// ---------------------------------------------------------------------------
+constexpr int MD_BLOCKS = 128;
+// gm layout (doubles): H[(m+1) m] | cs[m] | sn[m] | g[m+1] | y[m] | h1[m+1] | h2[m+1] | misc[8]
+struct GmLayout {
+  int m;
+  int64_t H, cs, sn, g, y, h1, h2, misc, total;
+  explicit GmLayout(int m_) : m(m_) {
+    H = 0;
+    cs = H + (int64_t)(m + 1) * m;
+    sn = cs + m;
+    g = sn + m;
+    y = g + m + 1;
+    h1 = y + m;
+    h2 = h1 + m + 1;
+    misc = h2 + m + 1;
+    total = misc + 8;
+  }
+};
+// gi: [0] j, [1] cycle end
+__device__ inline bool gm_stop(const int* done, const int* gi) { return done[0] || gi[1]; }
+
+__global__ void k_gm_cycle_init(double* gm, int* gi, GmLayout L, const double* __restrict__ rr) {
+  // rr: ||r||^2 of the cycle's start residual
+  gi[0] = 0;
+  gi[1] = 0;
+  double beta = sqrt(rr[0]);
+  for (int k = 0; k <= L.m; k++) gm[L.g + k] = 0.0;
+  gm[L.g] = beta;
+  gm[L.misc + 0] = beta;
+  if (!(beta > 0.0)) gi[1] = 1;
+}
+
+__global__ void k_gm_v0(int n, const double* __restrict__ r, double* V0, const double* __restrict__ gm, GmLayout L) {
+  const double beta = gm[L.misc];
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) V0[i] = r[i] * inv;
+}
+
+// vj = V[:, j]  (or Zb[:, j] <- z)
+__global__ void k_gm_take(int n, const double* __restrict__ V, double* vj, const int* __restrict__ gi,
+                          const int* __restrict__ done) {
+  if (gm_stop(done, gi)) return;
+  const double* src = V + (int64_t)gi[0] * n;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) vj[i] = src[i];
+}
+__global__ void k_gm_put(int n, const double* __restrict__ z, double* Zb, const int* __restrict__ gi,
+                         const int* __restrict__ done) {
+  if (gm_stop(done, gi)) return;
+  double* dst = Zb + (int64_t)gi[0] * n;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = z[i];
+}
+
+// partial dot products V[:, c] . w for c <= j
+__global__ void __launch_bounds__(256) k_gm_multidot(int n, const double* __restrict__ V, const double* __restrict__ w,
+                                                     double* partial, const int* __restrict__ gi,
+                                                     const int* __restrict__ done) {
+  if (gm_stop(done, gi)) return;
+  const int c = blockIdx.y;
+  if (c > gi[0]) return;
+  const double* v = V + (int64_t)c * n;
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += MD_BLOCKS * 256) s += v[i] * w[i];
+  block_reduce_store(s, partial + (int64_t)c * MD_BLOCKS + blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_gm_multidot_final(const double* __restrict__ partial, double* h,
+                                                           const int* __restrict__ gi, const int* __restrict__ done) {
+  if (gm_stop(done, gi)) return;
+  const int c = blockIdx.x;
+  if (c > gi[0]) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < MD_BLOCKS; i += 256) s += partial[(int64_t)c * MD_BLOCKS + i];
+  block_reduce_store(s, h + c);
+}
+// w -= sum_{c <= j} h[c] V[:, c]
+__global__ void k_gm_axpy(int n, const double* __restrict__ V, const double* __restrict__ h, double* w,
+                          const int* __restrict__ gi, const int* __restrict__ done) {
+  if (gm_stop(done, gi)) return;
+  const int j = gi[0];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    double s = 0.0;
+    for (int c = 0; c <= j; c++) s += h[c] * V[(int64_t)c * n + i];
+    w[i] -= s;
+  }
+}
+// V[:, j+1] = w / ||w||
+__global__ void k_gm_vnext(int n, const double* __restrict__ w, double* V, const double* __restrict__ ww,
+                           const int* __restrict__ gi, const int* __restrict__ done) {
+  if (gm_stop(done, gi)) return;
+  const double nw = sqrt(ww[0]);
+  const double inv = nw > 0.0 ? 1.0 / nw : 0.0;
+  double* dst = V + (int64_t)(gi[0] + 1) * n;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = w[i] * inv;
+}
+// column j of H (h1 + h2, ||w||), Givens update, residual check, j++
+__global__ void k_gm_givens(double* gm, GmLayout L, const double* __restrict__ ww, int* gi, int* done, double* hist,
+                            int maxit, double tol2, double bnorm2) {
+  if (gm_stop(done, gi)) return;
+  const int j = gi[0], m = L.m;
+  double* H = gm + L.H;  // column-major (m+1) x m
+  double* col = H + (int64_t)j * (m + 1);
+  for (int k = 0; k <= j; k++) col[k] = gm[L.h1 + k] + gm[L.h2 + k];
+  const double hn = sqrt(ww[0]);
+  col[j + 1] = hn;
+  for (int k = 0; k < j; k++) {
+    const double c = gm[L.cs + k], s = gm[L.sn + k];
+    const double a = col[k], b = col[k + 1];
+    col[k] = c * a + s * b;
+    col[k + 1] = -s * a + c * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double rr = sqrt(a * a + b * b);
+  const double c = rr > 0.0 ? a / rr : 1.0, s = rr > 0.0 ? b / rr : 0.0;
+  gm[L.cs + j] = c;
+  gm[L.sn + j] = s;
+  col[j] = rr;
+  col[j + 1] = 0.0;
+  const double gj = gm[L.g + j];
+  gm[L.g + j] = c * gj;
+  gm[L.g + j + 1] = -s * gj;
+  const double res = fabs(gm[L.g + j + 1]);
+  const int it = ++done[1];
+  hist[it - 1] = sqrt(res * res / bnorm2);
+  gi[0] = j + 1;
+  if (res * res <= tol2 * bnorm2) {
+    done[0] = 1;
+    done[2] = 1;
+  } else if (it >= maxit) {
+    done[0] = 1;
+  }
+  if (j + 1 >= m || !(hn > 0.0)) gi[1] = 1;
+}
+// y = R^{-1} g for the jj = gi[0] completed columns; then x += Zb y
+__global__ void k_gm_solve_y(double* gm, GmLayout L, const int* __restrict__ gi) {
+  const int jj = gi[0], m = L.m;
+  const double* H = gm + L.H;
+  for (int k = jj - 1; k >= 0; k--) {
+    double s = gm[L.g + k];
+    for (int l = k + 1; l < jj; l++) s -= H[(int64_t)l * (m + 1) + k] * gm[L.y + l];
+    gm[L.y + k] = s / H[(int64_t)k * (m + 1) + k];
+  }
+}
+__global__ void k_gm_update_x(int n, double* x, const double* __restrict__ Zb, const double* __restrict__ gm, GmLayout L,
+                              const int* __restrict__ gi) {
+  const int jj = gi[0];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    double s = 0.0;
+    for (int c = 0; c < jj; c++) s += gm[L.y + c] * Zb[(int64_t)c * n + i];
+    x[i] += s;
+  }
+}
+
 }  // namespace
 
 void spmv(tls_ctx* c, const double* x, double* y, const int* done) {
@@ -188,8 +342,13 @@ void spmv(tls_ctx* c, const double* x, double* y, const int* done) {
   TLS_LAUNCH_CHECK();
 }
 
+void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged);
+
 void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged) {
-  if (c->kind != 0) fail(TLS_E_ARG, "FGMRES for general matrices is not available in this build");
+  if (c->kind != 0) {
+    fgmres_solve(c, b, x, tol, iters, relres, converged);
+    return;
+  }
   hipStream_t s = c->stream;
   const int n = c->n;
   const int maxit = c->opt.maxit > 0 ? c->opt.maxit : 1000;
@@ -263,6 +422,121 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   c->h_hist = download(c->hist.p, it, s);
   auto t1 = std::chrono::steady_clock::now();
   c->t_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  *iters = it;
+  *relres = std::sqrt(rr / bb);
+  *converged = conv;
+  int err = download(c->errflag.p, 1, s)[0];
+  if (err & ERR_WAIT) fail(TLS_E_HIP, "a triangular-solve wait exceeded its spin limit");
+}
+
+
+namespace {
+
+struct GmBufs {
+  double *x, *r, *w, *vj, *zj, *b, *V, *Zb;
+};
+
+void fgmres_inner(tls_ctx* c, const GmBufs& B, double* gm, int* gi, const GmLayout& L, double* mdpart, int maxit,
+                  double tol2, double bnorm2) {
+  hipStream_t s = c->stream;
+  const int n = c->n;
+  const int* done = c->done.p;
+  const int vg = std::min(4096, div_up(n, 256));
+  hipLaunchKernelGGL(k_gm_take, dim3(vg), dim3(256), 0, s, n, B.V, B.vj, gi, done);
+  TLS_LAUNCH_CHECK();
+  // the apply and the SpMV are gated by the done flag only; when the cycle has
+  // ended they work on stale vectors whose results nothing reads
+  apply_precond(c, B.vj, B.zj, done);
+  hipLaunchKernelGGL(k_gm_put, dim3(vg), dim3(256), 0, s, n, B.zj, B.Zb, gi, done);
+  spmv(c, B.zj, B.w, done);
+  for (int pass = 0; pass < 2; pass++) {
+    double* h = gm + (pass == 0 ? L.h1 : L.h2);
+    hipLaunchKernelGGL(k_gm_multidot, dim3(MD_BLOCKS, L.m + 1), dim3(256), 0, s, n, B.V, B.w, mdpart, gi, done);
+    hipLaunchKernelGGL(k_gm_multidot_final, dim3(L.m + 1), dim3(256), 0, s, mdpart, h, gi, done);
+    hipLaunchKernelGGL(k_gm_axpy, dim3(vg), dim3(256), 0, s, n, B.V, h, B.w, gi, done);
+    TLS_LAUNCH_CHECK();
+  }
+  dot(c, B.w, B.w, c->scal.p + 8, done);
+  hipLaunchKernelGGL(k_gm_vnext, dim3(vg), dim3(256), 0, s, n, B.w, B.V, c->scal.p + 8, gi, done);
+  hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(1), 0, s, gm, L, c->scal.p + 8, gi, c->done.p, c->hist.p, maxit, tol2,
+                     bnorm2);
+  TLS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged) {
+  hipStream_t s = c->stream;
+  const int n = c->n;
+  const int m = c->opt.restart > 0 ? c->opt.restart : 30;
+  const int maxit = c->opt.maxit > 0 ? c->opt.maxit : 3000;
+  const GmLayout L(m);
+  const size_t need = (size_t)n * (6 + (m + 1) + m);
+  if (c->kr.n < need) c->kr.alloc(need);
+  if (c->scal.n < 16) c->scal.alloc(16);
+  if (c->partial.n < (size_t)std::max(RED_BLOCKS, MD_BLOCKS * (m + 1))) c->partial.alloc(std::max(RED_BLOCKS, MD_BLOCKS * (m + 1)));
+  if (c->done.n < 4) c->done.alloc(4);
+  if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
+  DBuf<double> gmb;
+  DBuf<int> gib;
+  gmb.alloc(L.total);
+  gib.alloc(4);
+  double* k = c->kr.p;
+  GmBufs B{k, k + n, k + 2 * (size_t)n, k + 3 * (size_t)n, k + 4 * (size_t)n, k + 5 * (size_t)n, k + 6 * (size_t)n,
+           k + (6 + (size_t)(m + 1)) * n};
+  auto t0 = std::chrono::steady_clock::now();
+  TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int) * 4, s));
+  TLS_HIP(hipMemsetAsync(B.x, 0, sizeof(double) * n, s));
+  TLS_HIP(hipMemsetAsync(gmb.p, 0, sizeof(double) * L.total, s));
+  TLS_HIP(hipMemcpyAsync(B.b, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  const int* zero = c->zero_int.p;
+  dot(c, B.b, B.b, c->scal.p + 0, zero);
+  const double bb = download(c->scal.p, 1, s)[0];
+  if (bb == 0.0) {
+    TLS_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    TLS_HIP(hipStreamSynchronize(s));
+    c->h_hist.clear();
+    *iters = 0;
+    *relres = 0.0;
+    *converged = true;
+    return;
+  }
+  const double tol2 = tol * tol;
+  const int vg = std::min(4096, div_up(n, 256));
+  bool conv = false;
+  std::vector<int> hd(4, 0);
+  double rr = bb;
+  for (int cycle = 0;; cycle++) {
+    // r = b - A x
+    spmv(c, B.x, B.w, zero);
+    hipLaunchKernelGGL(k_sub, dim3(vg), dim3(256), 0, s, n, B.b, B.w, B.r);
+    dot(c, B.r, B.r, c->scal.p + 9, zero);
+    hipLaunchKernelGGL(k_gm_cycle_init, dim3(1), dim3(1), 0, s, gmb.p, gib.p, L, c->scal.p + 9);
+    hipLaunchKernelGGL(k_gm_v0, dim3(vg), dim3(256), 0, s, n, B.r, B.V, gmb.p, L);
+    TLS_LAUNCH_CHECK();
+    for (int j = 0; j < m; j++) fgmres_inner(c, B, gmb.p, gib.p, L, c->partial.p, maxit, tol2, bb);
+    hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(1), 0, s, gmb.p, L, gib.p);
+    hipLaunchKernelGGL(k_gm_update_x, dim3(vg), dim3(256), 0, s, n, B.x, B.Zb, gmb.p, L, gib.p);
+    TLS_LAUNCH_CHECK();
+    // true residual of the new iterate
+    spmv(c, B.x, B.w, zero);
+    hipLaunchKernelGGL(k_sub, dim3(vg), dim3(256), 0, s, n, B.b, B.w, B.r);
+    dot(c, B.r, B.r, c->scal.p + 7, zero);
+    rr = download(c->scal.p + 7, 1, s)[0];
+    hd = download(c->done.p, 4, s);
+    if (rr <= tol2 * bb) {
+      conv = true;
+      break;
+    }
+    if (hd[1] >= maxit) break;
+    // not converged by the true residual: clear the stop flag and restart
+    TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int) * 1, s));
+    TLS_HIP(hipMemsetAsync(c->done.p + 2, 0, sizeof(int) * 1, s));
+  }
+  TLS_HIP(hipMemcpyAsync(x, B.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  const int it = hd[1];
+  c->h_hist = download(c->hist.p, std::max(it, 0), s);
+  c->t_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *iters = it;
   *relres = std::sqrt(rr / bb);
   *converged = conv;

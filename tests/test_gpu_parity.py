@@ -262,3 +262,125 @@ def test_error_paths():
     with pytest.raises(tls.TlsError) as e:
         _pc(neg.tocsr(), part, 1, 0)
     assert e.value.status == 2
+
+
+# ---------------------------------------------------------------------------
+# general (nonsymmetric) matrices: LU, Section 6 coarse space, FGMRES
+# ---------------------------------------------------------------------------
+
+def _cd_problem(m, p, seed):
+    from workloads import convdiff_2d
+    rng = np.random.default_rng(seed)
+    A, _ = convdiff_2d(m, rng)
+    part = box_partition_2d(m, m, p, p)
+    return A, part
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 2e-4)])
+def test_general_local_solves(precision, tol):
+    A, part = _cd_problem(96, 2, seed=3)  # 4 subdomains of ~2.5k rows, delta 2
+    say("general local solves", precision)
+    pc = _pc(A, part, 2, 0, precision=precision, matrix_kind=1)
+    rng = np.random.default_rng(0)
+    for i in range(4):
+        s = schwarz.overlap(A, part, i, 2)
+        Aii = schwarz.local_matrix(A, s).tocsc()
+        b = rng.standard_normal(s.size)
+        x_ref = spla.spsolve(Aii, b)
+        x = pc.local_solve(i, b)
+        err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+        say("  subdomain", i, "m", s.size, "err", err)
+        assert err <= tol
+    pc.close()
+
+
+def test_general_coarse_space_parity():
+    A, part = _cd_problem(64, 3, seed=4)
+    nev = 5
+    say("general coarse space")
+    pc = _pc(A, part, 2, nev, matrix_kind=1)
+    ex = pc.export(Z=True, A0=True)
+    zc = ex["zcol_ptr"]
+    for i in range(9):
+        s = schwarz.overlap(A, part, i, 2)
+        Aii = schwarz.local_matrix(A, s)
+        sig_all, U = schwarz.svd_variant(Aii, s, s.size)
+        k = zc[i + 1] - zc[i]
+        assert k == min(nev, sig_all.size)
+        assert np.allclose(ex["eigvals"][zc[i]:zc[i + 1]], sig_all[:k], rtol=1e-7)
+        if sig_all.size > k and sig_all[k - 1] / sig_all[k] >= 1 + 1e-3:
+            Zg = ex["Z"][s.idx[:s.n_interior]][:, zc[i]:zc[i + 1]]
+            cos = principal_cosines(U[:s.n_interior, :k], Zg)
+            assert np.all(cos >= 1 - 1e-9), cos
+    Zg = ex["Z"]
+    A0_ref = Zg.T @ (A @ Zg)
+    assert np.allclose(ex["A0"], A0_ref, rtol=1e-12, atol=1e-12 * np.abs(A0_ref).max())
+    pc.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-4)])
+def test_general_apply_with_imported_basis(precision, tol):
+    torch = torch_cuda()
+    A, part = _cd_problem(64, 4, seed=5)
+    say("general apply", precision)
+    pc = _pc(A, part, 2, 6, precision=precision, matrix_kind=1)
+    ex = pc.export(Z=True)
+    h = oracle.setup(A, part, 2, 6, spd=False, Z=ex["Z"])
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for _ in range(5):
+        r = rng.standard_normal(A.shape[0])
+        z = pc.apply(to_dev(r))
+        torch.cuda.synchronize()
+        z_ref = oracle.apply(h, r)
+        worst = max(worst, np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref))
+    say("  worst apply error", worst)
+    assert worst <= tol
+    pc.close()
+
+
+def test_general_fgmres_matches_oracle():
+    torch = torch_cuda()
+    A, part = _cd_problem(64, 4, seed=6)
+    b = np.random.default_rng(3).standard_normal(A.shape[0])
+    say("general fgmres")
+    pc = _pc(A, part, 2, 6, matrix_kind=1, restart=30)
+    x, it, rr, st = pc.solve(to_dev(b), 1e-8)
+    torch.cuda.synchronize()
+    h = oracle.setup(A, part, 2, 6, spd=False)
+    _, it_ref, rr_ref = oracle.solve(h, b)
+    say("  iterations", it, "oracle", it_ref, "relres", rr)
+    assert st == 0 and rr <= 1e-8
+    assert abs(it - it_ref) <= max(1, int(0.05 * it_ref))
+    xs = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
+    pc.close()
+
+
+def test_general_single_subdomain_one_iteration():
+    torch = torch_cuda()
+    A, _ = _cd_problem(40, 1, seed=7)
+    part = np.zeros(A.shape[0], dtype=np.int32)
+    b = np.random.default_rng(1).standard_normal(A.shape[0])
+    say("general N=1")
+    pc = _pc(A, part, 2, 4, matrix_kind=1)
+    x, it, rr, st = pc.solve(to_dev(b), 1e-8)
+    torch.cuda.synchronize()
+    assert it == 1 and rr <= 1e-10
+    pc.close()
+
+
+def test_autotune_cache_reuse(tmp_path):
+    import paper_2401_03915_amd as tls
+    A, part = _hc_problem(96, 3, seed=8)
+    cache = str(tmp_path / "tune.txt")
+    say("autotune cache")
+    pc1 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode())
+    i1 = pc1.info()
+    pc2 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode())
+    i2 = pc2.info()
+    assert i1["tuned"] == 1 and i2["tuned"] == 2
+    assert i1["solve_wgs"] == i2["solve_wgs"] > 0
+    pc1.close()
+    pc2.close()
+    del tls
