@@ -85,6 +85,8 @@ typedef struct {
   int32_t profile;      /* tls_apply times its local triangular-solve kernels with HIP
                            events (and then waits for them); see tls_info_t */
   int32_t solve_wgs;    /* workgroups of the persistent triangular solves (0 = default) */
+  int32_t solve_order;  /* task order of those solves: 1 level by level, 2 by fraction of
+                           the subdomain's rows done (default), 3 longest chain first (0 = default) */
   int32_t autotune;     /* 1: at setup, time candidate workgroup counts and keep the fastest */
   const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
                              NULL = no persistence. A cached pick is reused without timing. */
@@ -114,6 +116,7 @@ typedef struct {
                                  triangular-solve kernels (HIP events)       */
   double t_apply_ms;          /* mean duration of those whole applies         */
   int32_t solve_wgs;          /* workgroups used by the persistent solves     */
+  int32_t solve_order;        /* task order used by those solves (1, 2 or 3)  */
   int32_t tuned;              /* 0 default, 1 timed at setup, 2 read from the cache */
   const double* res_history;  /* host array: ||r_k|| / ||b|| per iteration   */
 } tls_info_t;

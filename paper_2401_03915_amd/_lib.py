@@ -46,6 +46,7 @@ class tls_options(C.Structure):
         ("jacobi_scale", C.c_int32),
         ("profile", C.c_int32),
         ("solve_wgs", C.c_int32),
+        ("solve_order", C.c_int32),
         ("autotune", C.c_int32),
         ("tune_cache", C.c_char_p),
         ("stream", C.c_void_p),
@@ -75,6 +76,7 @@ class tls_info_t(C.Structure):
         ("t_local_solve_ms", C.c_double),
         ("t_apply_ms", C.c_double),
         ("solve_wgs", C.c_int32),
+        ("solve_order", C.c_int32),
         ("tuned", C.c_int32),
         ("res_history", C.POINTER(C.c_double)),
     ]

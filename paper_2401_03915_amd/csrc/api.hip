@@ -55,6 +55,7 @@ void tls_default_options(tls_options* o) {
   o->jacobi_scale = 0;
   o->profile = 0;
   o->solve_wgs = 0;
+  o->solve_order = 0;
   o->autotune = 0;
   o->tune_cache = nullptr;
   o->stream = nullptr;
@@ -82,6 +83,8 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.precision != 0 && c->opt.precision != 1) tls::fail(TLS_E_ARG, "precision must be 0 or 1");
     if (c->opt.matrix_kind != 0 && c->opt.matrix_kind != 1) tls::fail(TLS_E_ARG, "matrix_kind must be 0 or 1");
     if (c->opt.nev1 < 0) tls::fail(TLS_E_ARG, "nev1 must be >= 0");
+    if (c->opt.solve_order < 0 || c->opt.solve_order > 3) tls::fail(TLS_E_ARG, "solve_order must be in [0, 3]");
+    if (c->opt.solve_wgs < 0) tls::fail(TLS_E_ARG, "solve_wgs must be >= 0");
     if (c->opt.eig_oversample < 0) c->opt.eig_oversample = nev;
     if (c->opt.flexible < 0) c->opt.flexible = c->opt.precision == 1 ? 1 : 0;
     if (c->opt.eig_maxit <= 0) c->opt.eig_maxit = 300;
@@ -225,6 +228,7 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->t_local_solve_ms = c->prof_count ? c->prof_local_ms / c->prof_count : 0.0;
   info->t_apply_ms = c->prof_count ? c->prof_apply_ms / c->prof_count : 0.0;
   info->solve_wgs = c->solve_grid;
+  info->solve_order = c->solve_order;
   info->tuned = c->tuned;
   return TLS_OK;
 }

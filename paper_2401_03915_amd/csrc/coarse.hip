@@ -199,16 +199,10 @@ void build_coarse_operator(tls_ctx* c) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
     fail(TLS_E_SINGULAR, "zero pivot in the LU factorization of the coarse operator Z^T A Z");
   }
-  std::vector<int2> f, b;
-  make_tasks(one_nt, toff, f, b);
-  c->tasks0_fwd.upload(f, s);
-  c->tasks0_bwd.upload(b, s);
-  c->flags0_fwd.alloc(c->nt0);
-  c->flags0_bwd.alloc(c->nt0);
+  build_plan(c->plan0_fwd, false, one_nt, toff, 1, s);
+  build_plan(c->plan0_bwd, true, one_nt, toff, 1, s);
   c->counters0.alloc(4);
   c->y0.alloc(c->M0);
-  TLS_HIP(hipMemsetAsync(c->flags0_fwd.p, 0, sizeof(int) * c->nt0, s));
-  TLS_HIP(hipMemsetAsync(c->flags0_bwd.p, 0, sizeof(int) * c->nt0, s));
   TLS_HIP(hipMemsetAsync(c->counters0.p, 0, sizeof(int) * 4, s));
   TLS_HIP(hipMemsetAsync(c->y0.p, 0, sizeof(double) * c->M0, s));
   TLS_HIP(hipStreamSynchronize(s));
@@ -227,11 +221,11 @@ void coarse_solve(tls_ctx* c, const int* done) {
   if (c->nC == 0) return;
   hipStream_t s = c->stream;
   solve_begin(s, c->counters0.p, done);
-  const int nt = (int)c->tasks0_fwd.n;
-  trsv_f64(s, c->kind == 0 ? 0 : 2, c->tasks0_fwd.p, nt, c->counters0.p + 0, c->flags0_fwd.p, c->counters0.p + 2,
-           c->layout0(), c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
-  trsv_f64(s, c->kind == 0 ? 1 : 3, c->tasks0_bwd.p, nt, c->counters0.p + 1, c->flags0_bwd.p, c->counters0.p + 2,
-           c->layout0(), c->A0.p, c->y0.p, c->errflag.p, done, c->nt0);
+  const int grid = std::min(c->plan0_fwd.ntasks, 512);
+  trsv_f64(s, c->kind == 0 ? 0 : 2, c->plan0_fwd, c->counters0.p + 0, c->counters0.p + 2, c->layout0(), c->A0.p,
+           c->y0.p, c->errflag.p, done, grid);
+  trsv_f64(s, c->kind == 0 ? 1 : 3, c->plan0_bwd, c->counters0.p + 1, c->counters0.p + 2, c->layout0(), c->A0.p,
+           c->y0.p, c->errflag.p, done, grid);
 }
 
 }  // namespace tls

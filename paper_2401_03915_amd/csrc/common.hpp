@@ -112,6 +112,16 @@ struct LocalLayout {
   const int64_t* toff; // offset of i's first tile row in the flag arrays (= sum nt_j)
 };
 
+// Work list of one persistent triangular-solve launch: task (x = i, y = r)
+// is block row r of subdomain i; flags[toff_i + r] holds the epoch of the
+// last solve that finished that block row. `order` records the ordering.
+struct SolvePlan {
+  DBuf<int4> tasks;
+  int ntasks = 0;
+  DBuf<int> flags;
+  int order = 0;
+};
+
 // Error bits reported by kernels into a device int.
 enum : int {
   ERR_CSR = 1,

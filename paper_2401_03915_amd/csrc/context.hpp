@@ -50,11 +50,11 @@ struct tls_ctx {
   tls::DBuf<int64_t> pref_trsm, pref_upd;
   std::vector<int64_t> h_cnt_trsm, h_cnt_upd;
 
-  // triangular-solve task lists and flags
-  tls::DBuf<int2> tasks_fwd, tasks_bwd;
-  tls::DBuf<int> flags_fwd, flags_bwd;
+  // triangular-solve work lists
+  tls::SolvePlan plan_fwd, plan_bwd;
   tls::DBuf<int> counters;  // [0] fwd task counter, [1] bwd task counter, [2] epoch
   int solve_grid = 1024;
+  int solve_order = 2;
 
   // work vectors for the apply (padded local layout)
   tls::DBuf<double> xloc64;
@@ -72,8 +72,7 @@ struct tls_ctx {
   tls::DBuf<double> A0_orig;  // lower tiles of A_0 before factorization (export)
   tls::DBuf<int> kz_dev;    // coarse columns per subdomain
   tls::DBuf<double> y0;     // coarse vector (padded to M0)
-  tls::DBuf<int2> tasks0_fwd, tasks0_bwd;
-  tls::DBuf<int> flags0_fwd, flags0_bwd;
+  tls::SolvePlan plan0_fwd, plan0_bwd;
   tls::DBuf<int> counters0;
   tls::DBuf<int> one_m, one_nI, one_nP, one_nt;
   tls::DBuf<int64_t> one_foff, one_voff, one_toff;

@@ -249,6 +249,106 @@ __global__ void __launch_bounds__(256) k_update(int k, const int64_t* __restrict
     }
 }
 
+// Blocked trailing update: C_rc -= sum_{k in [kb, kb+kn)} L_rk L_ck^T with
+// K = 64 kn (MFMA). mode 0: tiles (r, c) with kf <= c <= r < nt (trailing
+// lower triangle from tile column kf); mode 1: tiles (r, c) with
+// kf <= c < kl (a few panel columns), c <= r < nt. The next k-tile pair is
+// prefetched into registers while the current one is multiplied.
+template <class T>
+__global__ void __launch_bounds__(256) k_update_blk(int mode, int kb, int kn, int kf, int kl,
+                                                    const int64_t* __restrict__ pref, int nact,
+                                                    const int* __restrict__ order, LocalLayout lay, T* fac) {
+  constexpr int LD = LdsLd<T>::v;
+  __shared__ T As[TS * LD];
+  __shared__ T Bs[TS * LD];
+  const int64_t bid = blockIdx.x;
+  const int j = find_slot(pref, nact, bid);
+  const int i = order[j];
+  const int nt = lay.nt[i];
+  int64_t t = bid - pref[j];
+  int r, c;
+  if (mode == 0) {
+    int rr = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(rr + 1) * (rr + 2) / 2 <= t) rr++;
+    while ((int64_t)rr * (rr + 1) / 2 > t) rr--;
+    int cc = (int)(t - (int64_t)rr * (rr + 1) / 2);
+    r = kf + rr;
+    c = kf + cc;
+  } else {
+    c = kf;
+    while (t >= nt - c) {
+      t -= nt - c;
+      c++;
+    }
+    r = c + (int)t;
+  }
+  T* base = fac + lay.foff[i];
+  T* C = base + tile_index(0, nt, r, c) * TS2;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  constexpr int PER = TS2 / 256;
+  T pa[PER], pb[PER];
+  {
+    const T* Lr = base + tile_index(0, nt, r, kb) * TS2;
+    const T* Lc = base + tile_index(0, nt, c, kb) * TS2;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      pa[u] = Lr[tid + 256 * u];
+      pb[u] = Lc[tid + 256 * u];
+    }
+  }
+  for (int k = 0; k < kn; k++) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      const int a = e % TS, b = e / TS;
+      As[b * LD + a] = pa[u];
+      Bs[b * LD + a] = pb[u];
+    }
+    __syncthreads();
+    if (k + 1 < kn) {
+      const T* Lr = base + tile_index(0, nt, r, kb + k + 1) * TS2;
+      const T* Lc = base + tile_index(0, nt, c, kb + k + 1) * TS2;
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        pa[u] = Lr[tid + 256 * u];
+        pb[u] = Lc[tid + 256 * u];
+      }
+    }
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+      T a0 = As[(kk + lk) * LD + wr + li];
+      T a1 = As[(kk + lk) * LD + wr + 16 + li];
+      T b0 = Bs[(kk + lk) * LD + wc + li];
+      T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
+      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int row = wr + 16 * x + Mfma<T>::row(lane, q);
+        C[col * TS + row] -= acc[x][y][q];
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched tiled LU without pivoting (general A; full tile storage)
 // ---------------------------------------------------------------------------
@@ -443,50 +543,94 @@ void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const Loc
   TLS_HIP(hipStreamSynchronize(s));
 }
 
+// Right-looking Cholesky blocked by panels of PW tile columns: inside a
+// panel every step updates only the panel's remaining columns; the rest of
+// the trailing matrix is updated once per panel with K = 64 * PW, which cuts
+// its read-modify-write traffic by PW.
 template <class T>
 void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, int* err) {
+  constexpr int PW = 4;
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
-  int maxnt = N ? nt[order[0]] : 0;
-  std::vector<int64_t> pt, pu, off(maxnt + 1, 0), tot_t(maxnt), tot_u(maxnt);
-  std::vector<int> act(maxnt);
-  for (int k = 0; k < maxnt; k++) {
-    off[k] = (int64_t)pt.size();
-    int64_t ct = 0, cu = 0;
+  const int maxnt = N ? nt[order[0]] : 0;
+  struct Launch {
+    int kind;  // 0 potrf, 1 trsm, 2 panel update, 3 trailing update
+    int k, kb, kn, kf, kl, nact;
+    int64_t off, total;
+  };
+  std::vector<Launch> launches;
+  std::vector<int64_t> pref;
+  auto active = [&](int k) {
     int a = 0;
-    while (a < N && nt[order[a]] > k) {
-      pt.push_back(ct);
-      pu.push_back(cu);
-      int64_t T_ = nt[order[a]] - k - 1;
-      ct += T_;
-      cu += T_ * (T_ + 1) / 2;
-      a++;
+    while (a < N && nt[order[a]] > k) a++;
+    return a;
+  };
+  for (int k0 = 0; k0 < maxnt; k0 += PW) {
+    for (int k = k0; k < std::min(k0 + PW, maxnt); k++) {
+      const int act = active(k);
+      launches.push_back(Launch{0, k, 0, 0, 0, 0, act, 0, act});
+      // trsm: tiles (r, k), r > k
+      {
+        int64_t off = (int64_t)pref.size(), tot = 0;
+        for (int a = 0; a < act; a++) {
+          pref.push_back(tot);
+          tot += nt[order[a]] - k - 1;
+        }
+        pref.push_back(tot);
+        if (tot > 0) launches.push_back(Launch{1, k, 0, 0, 0, 0, act, off, tot});
+      }
+      // panel columns c in (k, k0 + PW): tiles (r, c), c <= r
+      {
+        const int kf = k + 1, kl = k0 + PW;
+        int64_t off = (int64_t)pref.size(), tot = 0;
+        for (int a = 0; a < act; a++) {
+          pref.push_back(tot);
+          const int n_ = nt[order[a]];
+          for (int cc = kf; cc < std::min(kl, n_); cc++) tot += n_ - cc;
+        }
+        pref.push_back(tot);
+        if (tot > 0) launches.push_back(Launch{2, k, k, 1, kf, kl, act, off, tot});
+      }
     }
-    pt.push_back(ct);
-    pu.push_back(cu);
-    act[k] = a;
-    tot_t[k] = ct;
-    tot_u[k] = cu;
+    // trailing update from column k0 + PW with the whole panel
+    const int kf = k0 + PW;
+    const int act = active(kf);
+    if (act > 0) {
+      int64_t off = (int64_t)pref.size(), tot = 0;
+      for (int a = 0; a < act; a++) {
+        pref.push_back(tot);
+        const int64_t T_ = nt[order[a]] - kf;
+        tot += T_ * (T_ + 1) / 2;
+      }
+      pref.push_back(tot);
+      if (tot > 0) launches.push_back(Launch{3, kf, k0, PW, kf, 0, act, off, tot});
+    }
   }
+  // the trsm kernel reads its prefix table with the step-local layout
   DBuf<int> d_order;
-  DBuf<int64_t> d_pt, d_pu;
+  DBuf<int64_t> d_pref;
   d_order.upload(order, s);
-  d_pt.upload(pt, s);
-  d_pu.upload(pu, s);
-  for (int k = 0; k < maxnt; k++) {
-    hipLaunchKernelGGL(k_potrf<T>, dim3(act[k]), dim3(256), 0, s, k, d_order.p, lay, fac, err);
+  d_pref.upload(pref, s);
+  for (const Launch& L : launches) {
+    switch (L.kind) {
+      case 0:
+        hipLaunchKernelGGL(k_potrf<T>, dim3(L.nact), dim3(256), 0, s, L.k, d_order.p, lay, fac, err);
+        break;
+      case 1:
+        hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)L.total), dim3(64), 0, s, L.k, d_pref.p + L.off, L.nact,
+                           d_order.p, lay, fac);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_update_blk<T>, dim3((unsigned)L.total), dim3(256), 0, s, 1, L.kb, L.kn, L.kf, L.kl,
+                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        break;
+      default:
+        hipLaunchKernelGGL(k_update_blk<T>, dim3((unsigned)L.total), dim3(256), 0, s, 0, L.kb, L.kn, L.kf, 0,
+                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        break;
+    }
     TLS_LAUNCH_CHECK();
-    if (tot_t[k] > 0) {
-      hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)tot_t[k]), dim3(64), 0, s, k, d_pt.p + off[k], act[k],
-                         d_order.p, lay, fac);
-      TLS_LAUNCH_CHECK();
-    }
-    if (tot_u[k] > 0) {
-      hipLaunchKernelGGL(k_update<T>, dim3((unsigned)tot_u[k]), dim3(256), 0, s, k, d_pu.p + off[k], act[k],
-                         d_order.p, lay, fac);
-      TLS_LAUNCH_CHECK();
-    }
   }
   TLS_HIP(hipStreamSynchronize(s));
 }
@@ -564,7 +708,7 @@ constexpr long long SPIN_LIMIT = 1ll << 26;
 enum TrsvMode { FWD_L = 0, BWD_LT = 1, FWD_UL = 2, BWD_U = 3 };
 
 template <class T, int MODE>
-__global__ void __launch_bounds__(256) k_trsv(const int2* __restrict__ tasks, int ntasks, int* counter,
+__global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, int ntasks, int* counter,
                                               int* flags, const int* __restrict__ epoch_ptr, LocalLayout lay,
                                               const T* __restrict__ fac, T* x, int* err,
                                               const int* __restrict__ done) {
@@ -843,25 +987,27 @@ __global__ void k_solve_begin(int* counters, const int* done) {
 }
 
 template <class T>
-void trsv(hipStream_t s, int mode, const int2* tasks, int ntasks, int* counter, int* flags, const int* epoch,
-          const LocalLayout& lay, const T* fac, T* x, int* err, const int* done, int grid) {
+void trsv(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
+          const T* fac, T* x, int* err, const int* done, int grid) {
+  const int ntasks = p.ntasks;
+  if (ntasks == 0) return;
   grid = std::max(1, std::min(grid, ntasks));
   switch (mode) {
     case FWD_L:
-      hipLaunchKernelGGL((k_trsv<T, FWD_L>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
-                         fac, x, err, done);
+      hipLaunchKernelGGL((k_trsv<T, FWD_L>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,
+                         lay, fac, x, err, done);
       break;
     case BWD_LT:
-      hipLaunchKernelGGL((k_trsv<T, BWD_LT>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
-                         fac, x, err, done);
+      hipLaunchKernelGGL((k_trsv<T, BWD_LT>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
+                         epoch, lay, fac, x, err, done);
       break;
     case FWD_UL:
-      hipLaunchKernelGGL((k_trsv<T, FWD_UL>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
-                         fac, x, err, done);
+      hipLaunchKernelGGL((k_trsv<T, FWD_UL>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
+                         epoch, lay, fac, x, err, done);
       break;
     default:
-      hipLaunchKernelGGL((k_trsv<T, BWD_U>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter, flags, epoch, lay,
-                         fac, x, err, done);
+      hipLaunchKernelGGL((k_trsv<T, BWD_U>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,
+                         lay, fac, x, err, done);
       break;
   }
   TLS_LAUNCH_CHECK();
@@ -874,10 +1020,9 @@ void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const Lo
   factor_tiles<double>(s, N, nt, lay, fac, err);
 }
 
-void trsv_f64(hipStream_t s, int mode, const int2* tasks, int ntasks, int* counter, int* flags,
-              const int* epoch, const LocalLayout& lay, const double* fac, double* x, int* err, const int* done,
-              int grid) {
-  trsv<double>(s, mode, tasks, ntasks, counter, flags, epoch, lay, fac, x, err, done, grid);
+void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
+              const double* fac, double* x, int* err, const int* done, int grid) {
+  trsv<double>(s, mode, p, counter, epoch, lay, fac, x, err, done, grid);
 }
 
 void solve_begin(hipStream_t s, int* counters, const int* done) {
@@ -948,37 +1093,56 @@ void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const
   factor_tiles_lu<double>(s, N, nt, lay, fac, err);
 }
 
-void make_tasks(const std::vector<int>& nt, const std::vector<int64_t>& toff, std::vector<int2>& fwd,
-                std::vector<int2>& bwd) {
-  (void)toff;
+void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::vector<int64_t>& toff, int order,
+                hipStream_t s) {
+  // A task is one block row; row r of subdomain i has "position" r (forward)
+  // or nt_i - 1 - r (backward) in its dependency chain. Every ordering below
+  // sorts a subdomain's rows by position, so a task only ever waits on tasks
+  // handed out before it:
+  //   1 level order         key = position
+  //   2 normalized progress key = position / nt_i
+  //   3 longest chain first key = position + (max nt - nt_i)
   const int N = (int)nt.size();
-  std::vector<int> order(N);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
-  int maxnt = N ? nt[order[0]] : 0;
-  fwd.clear();
-  bwd.clear();
-  // step s: block row s of every subdomain with nt > s (largest first);
-  // backward: block row nt-1-s.
-  for (int st = 0; st < maxnt; st++)
-    for (int a = 0; a < N && nt[order[a]] > st; a++) {
-      int i = order[a];
-      fwd.push_back(make_int2(i, st));
-      bwd.push_back(make_int2(i, nt[i] - 1 - st));
+  int maxnt = 0;
+  for (int v : nt) maxnt = std::max(maxnt, v);
+  struct Item {
+    double key;
+    int i, pos;
+  };
+  std::vector<Item> items;
+  for (int i = 0; i < N; i++)
+    for (int pos = 0; pos < nt[i]; pos++) {
+      double key = order == 2 ? (pos + 0.5) / nt[i] : order == 3 ? (double)(pos + maxnt - nt[i]) : (double)pos;
+      items.push_back(Item{key, i, pos});
     }
+  std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+    if (a.key != b.key) return a.key < b.key;
+    if (nt[a.i] != nt[b.i]) return nt[a.i] > nt[b.i];
+    if (a.i != b.i) return a.i < b.i;
+    return a.pos < b.pos;
+  });
+  std::vector<int4> tasks;
+  tasks.reserve(items.size());
+  for (const Item& it : items) tasks.push_back(make_int4(it.i, bwd ? nt[it.i] - 1 - it.pos : it.pos, 0, 1));
+  const int64_t rows = N ? toff[N] : 0;
+  p.tasks.upload(tasks, s);
+  p.ntasks = (int)tasks.size();
+  p.flags.alloc(std::max<int64_t>(rows, 1));
+  p.order = order;
+  TLS_HIP(hipMemsetAsync(p.flags.p, 0, sizeof(int) * std::max<int64_t>(rows, 1), s));
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+void build_local_plans(tls_ctx* c, int order) {
+  build_plan(c->plan_fwd, false, c->h_nt, c->h_toff, order, c->stream);
+  build_plan(c->plan_bwd, true, c->h_nt, c->h_toff, order, c->stream);
+  c->solve_order = order;
 }
 
 void build_solve_tasks(tls_ctx* c) {
-  std::vector<int2> f, b;
-  make_tasks(c->h_nt, c->h_toff, f, b);
-  c->tasks_fwd.upload(f, c->stream);
-  c->tasks_bwd.upload(b, c->stream);
-  c->flags_fwd.alloc(c->sum_nt);
-  c->flags_bwd.alloc(c->sum_nt);
   c->counters.alloc(4);
-  TLS_HIP(hipMemsetAsync(c->flags_fwd.p, 0, sizeof(int) * c->sum_nt, c->stream));
-  TLS_HIP(hipMemsetAsync(c->flags_bwd.p, 0, sizeof(int) * c->sum_nt, c->stream));
   TLS_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(int) * 4, c->stream));
+  build_local_plans(c, 2);
   // padding entries must stay zero: the padded identity rows then solve to 0
   if (c->fp32) {
     c->xloc32.alloc(c->sum_M);
@@ -992,14 +1156,14 @@ void build_solve_tasks(tls_ctx* c) {
 
 void local_backward(tls_ctx* c, float* x, const int* done) {
   solve_begin(c->stream, c->counters.p, done);
-  trsv<float>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
-              c->counters.p + 2, c->layout(), c->fac32.p, x, c->errflag.p, done, c->solve_grid);
+  trsv<float>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->plan_bwd, c->counters.p + 1, c->counters.p + 2,
+              c->layout(), c->fac32.p, x, c->errflag.p, done, c->solve_grid);
 }
 
 void local_backward(tls_ctx* c, double* x, const int* done) {
   solve_begin(c->stream, c->counters.p, done);
-  trsv<double>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, (int)c->tasks_bwd.n, c->counters.p + 1, c->flags_bwd.p,
-               c->counters.p + 2, c->layout(), c->fac64.p, x, c->errflag.p, done, c->solve_grid);
+  trsv<double>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->plan_bwd, c->counters.p + 1, c->counters.p + 2,
+               c->layout(), c->fac64.p, x, c->errflag.p, done, c->solve_grid);
 }
 
 template <class T>
@@ -1039,20 +1203,20 @@ void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, cons
 
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_end) {
   hipStream_t s = c->stream;
-  const int ntasks = (int)c->tasks_fwd.n;
   LocalLayout lay = c->layout();
   solve_begin(s, c->counters.p, done);
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
+  const int fm = c->kind == 0 ? FWD_L : FWD_UL, bm = c->kind == 0 ? BWD_LT : BWD_U;
   if (c->fp32) {
-    trsv<float>(s, c->kind == 0 ? FWD_L : FWD_UL, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
-                c->fac32.p, c->xloc32.p, c->errflag.p, done, c->solve_grid);
-    trsv<float>(s, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
-                c->fac32.p, c->xloc32.p, c->errflag.p, done, c->solve_grid);
+    trsv<float>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac32.p, c->xloc32.p,
+                c->errflag.p, done, c->solve_grid);
+    trsv<float>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac32.p, c->xloc32.p,
+                c->errflag.p, done, c->solve_grid);
   } else {
-    trsv<double>(s, c->kind == 0 ? FWD_L : FWD_UL, c->tasks_fwd.p, ntasks, c->counters.p + 0, c->flags_fwd.p, c->counters.p + 2, lay,
-                 c->fac64.p, c->xloc64.p, c->errflag.p, done, c->solve_grid);
-    trsv<double>(s, c->kind == 0 ? BWD_LT : BWD_U, c->tasks_bwd.p, ntasks, c->counters.p + 1, c->flags_bwd.p, c->counters.p + 2, lay,
-                 c->fac64.p, c->xloc64.p, c->errflag.p, done, c->solve_grid);
+    trsv<double>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac64.p, c->xloc64.p,
+                 c->errflag.p, done, c->solve_grid);
+    trsv<double>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac64.p, c->xloc64.p,
+                 c->errflag.p, done, c->solve_grid);
   }
   if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));
 }

@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(256) k_subspace(const int* __restrict__ nT_, c
 template <class T>
 __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const int* __restrict__ kf_,
                                               const int64_t* __restrict__ voff, const int64_t* __restrict__ xoff,
-                                              const int* __restrict__ nt_, const T* __restrict__ xr,
+                                              const int* __restrict__ nt_, int64_t colstride, const T* __restrict__ xr,
                                               const double* __restrict__ scale,
                                               const int64_t* __restrict__ zoff, double* Z, int* kfinal,
                                               int* keep_idx) {
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const
     double* v = Zi + (int64_t)kept * nI;
     double n0 = 0.0;
     for (int r = tid; r < nI; r += 256) {
-      double x = (double)xr[xoff[i] + (int64_t)a * nt_[i] * TS + r];
+      double x = (double)xr[xoff[i] + (int64_t)a * (colstride > 0 ? colstride : (int64_t)nt_[i] * TS) + r];
       if (scale) x *= scale[voff[i] + r];
       v[r] = x;
       n0 += x * x;
@@ -713,8 +713,10 @@ static void basis_impl(tls_ctx* c, T* fac) {
   // ---- coarse vectors into X_V (rows I, one 64-column block per subdomain) --
   DBuf<T> wT, XV;
   wT.alloc(std::max<int64_t>(oZv[N], 1));
-  XV.alloc(std::max<int64_t>(oXV[N], 1));
-  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
+  if (general) {
+    XV.alloc(std::max<int64_t>(oXV[N], 1));
+    TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
+  }
   if (!general) {
     // w_T = L_TT^{-T} z ; V = F w_T ; then x = L^{-T} [V; 0] gives rows I = L_II^{-T} V
     std::vector<TriDesc> td;
@@ -723,13 +725,19 @@ static void basis_impl(tls_ctx* c, T* fac) {
     batched_trsm<double>(s, td, UPPER_BWD, LTTt.p, zv.p, c->errflag.p);
     hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
     TLS_LAUNCH_CHECK();
+    // column j of V for every subdomain lives in padded local vector j
+    int kfm = 0;
+    for (int i = 0; i < N; i++) kfm = std::max(kfm, h_kf[i]);
+    XV.alloc((size_t)std::max(kfm, 1) * c->sum_M);
+    TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max(kfm, 1) * c->sum_M, s));
     std::vector<GemmDesc> gd;
     for (int i = 0; i < N; i++)
-      if (h_kf[i] > 0)
-        gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], nI[i], nT[i], oF[i], oZv[i], oXV[i], (int64_t)c->h_nt[i] * TS});
+      if (h_kf[i] > 0) gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], nI[i], nT[i], oF[i], oZv[i], c->h_voff[i], c->sum_M});
     batched_gemm<T>(s, gd, false, false, F.p, wT.p, XV.p, T(1), T(0));
     F.release();
-    local_trsm_backward(c, XV.p, nqV, oXV);
+    // x = L^{-T} [V; 0] per column with the persistent solve: rows I = L_II^{-T} V
+    for (int j = 0; j < kfm; j++) local_backward(c, XV.p + (size_t)j * c->sum_M, c->zero_int.p);
+    TLS_HIP(hipStreamSynchronize(s));
   } else {
     // left singular directions: V = H v
     hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
@@ -748,7 +756,9 @@ static void basis_impl(tls_ctx* c, T* fac) {
   Zt.alloc(std::max<int64_t>(oZ[N], 1));
   kfin.alloc(N);
   keep.alloc((size_t)N * PMAX);
-  hipLaunchKernelGGL(k_orth<T>, dim3(N), dim3(256), 0, s, d_nI.p, kfound.p, c->d_voff.p, d_oXV.p, c->d_nt.p, XV.p,
+  const int64_t colstride = general ? 0 : c->sum_M;
+  hipLaunchKernelGGL(k_orth<T>, dim3(N), dim3(256), 0, s, d_nI.p, kfound.p, c->d_voff.p,
+                     general ? d_oXV.p : c->d_voff.p, c->d_nt.p, colstride, XV.p,
                      c->opt.jacobi_scale ? c->scale.p : nullptr, d_oZ.p, Zt.p, kfin.p, keep.p);
   TLS_LAUNCH_CHECK();
   auto h_kfin = download(kfin.p, N, s);

@@ -31,12 +31,16 @@ void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const
 // generic pieces reused for the coarse factor (always fp64)
 void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay,
                       double* fac, int* err);
-void make_tasks(const std::vector<int>& nt, const std::vector<int64_t>& toff, std::vector<int2>& fwd,
-                std::vector<int2>& bwd);
+// work list of one direction (bwd = descending block rows) in one of the
+// dependency-safe task orderings (1 level, 2 normalized progress,
+// 3 longest chain first)
+void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::vector<int64_t>& toff, int order,
+                hipStream_t s);
 // mode: 0 L y = b (Cholesky), 1 L^T x = y, 2 unit-lower L y = b (LU), 3 U x = y
-void trsv_f64(hipStream_t s, int mode, const int2* tasks, int ntasks, int* counter, int* flags,
-              const int* epoch, const LocalLayout& lay, const double* fac, double* x, int* err,
-              const int* done, int grid);
+void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
+              const double* fac, double* x, int* err, const int* done, int grid);
+// (re)build the local plans for a task ordering
+void build_local_plans(tls_ctx* c, int order);
 void solve_begin(hipStream_t s, int* counters, const int* done);
 
 // eigen.hip: coarse basis (eq. gevpsvd / Section 6)

@@ -1,12 +1,17 @@
-// Workgroup count of the persistent triangular solves.
+// Launch shape of the persistent triangular solves: workgroup count and
+// task order.
 //
 // The solves are bound by HBM bandwidth and by how many tiles are in flight,
-// which depends on how many workgroups are resident. The default is a fixed
-// number per compute unit for each precision (LDS and register use allow
-// about 7 FP32 or 3 FP64 workgroups per CU). With autotune = 1 the setup
-// times the local forward + backward solves for a handful of candidate
-// counts and keeps the fastest; picks are appended to a text cache keyed by
-// the problem's shape and reused without timing when the key is present.
+// which depends on how many workgroups are resident, and, for uneven
+// subdomains, by the dependency chain of the largest one, which depends on
+// when its block rows are handed out. The default is a fixed number of
+// workgroups per compute unit for each precision (LDS and register use allow
+// about 7 FP32 or 3 FP64 workgroups per CU) and rows handed out by the
+// fraction of their subdomain already done (normalized progress).
+// With autotune = 1 the setup times the local forward + backward solves for
+// each order and a handful of workgroup counts and keeps the fastest; picks
+// are appended to a text cache keyed by the problem's shape and reused
+// without timing when the key is present.
 #include <algorithm>
 #include <cstdio>
 #include <fstream>
@@ -20,7 +25,7 @@ namespace {
 
 std::string tune_key(const tls_ctx* c) {
   std::ostringstream k;
-  k << "trsv:v2 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
+  k << "trsv:v4 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
     << " sumM=" << c->sum_M << " maxnt=" << c->max_nt;
   return k.str();
 }
@@ -31,7 +36,7 @@ int cu_count() {
   return cus > 0 ? cus : 256;
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* grid) {
+bool cache_lookup(const char* path, const std::string& key, int* grid, int* order) {
   if (!path) return false;
   std::ifstream f(path);
   std::string line;
@@ -40,17 +45,21 @@ bool cache_lookup(const char* path, const std::string& key, int* grid) {
     auto tab = line.rfind('\t');
     if (tab == std::string::npos) continue;
     if (line.substr(0, tab) == key) {
-      *grid = std::atoi(line.c_str() + tab + 1);
-      found = *grid > 0;
+      int g = 0, ch = 0;
+      if (std::sscanf(line.c_str() + tab + 1, "%d %d", &g, &ch) == 2 && g > 0 && ch >= 1 && ch <= 3) {
+        *grid = g;
+        *order = ch;
+        found = true;
+      }
     }
   }
   return found;
 }
 
-void cache_store(const char* path, const std::string& key, int grid) {
+void cache_store(const char* path, const std::string& key, int grid, int order) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << '\t' << grid << '\n';
+  if (f) f << key << '\t' << grid << ' ' << order << '\n';
 }
 
 double time_local_solves(tls_ctx* c, int grid, int reps) {
@@ -76,36 +85,42 @@ double time_local_solves(tls_ctx* c, int grid, int reps) {
 
 void choose_solve_grid(tls_ctx* c) {
   const int cus = cu_count();
-  const int per_cu = c->fp32 ? 6 : 3;
+  const int per_cu = c->fp32 ? 4 : 3;
   c->solve_grid = cus * per_cu;
   c->tuned = 0;
-  if (c->opt.solve_wgs > 0) {
-    c->solve_grid = c->opt.solve_wgs;
+  if (c->opt.solve_order > 0 && c->opt.solve_order != c->solve_order) build_local_plans(c, c->opt.solve_order);
+  if (c->opt.solve_wgs > 0 || c->opt.solve_order > 0) {
+    if (c->opt.solve_wgs > 0) c->solve_grid = c->opt.solve_wgs;
     return;
   }
   if (!c->opt.autotune) return;
   const std::string key = tune_key(c);
-  int g = 0;
-  if (cache_lookup(c->opt.tune_cache, key, &g)) {
+  int g = 0, ch = 0;
+  if (cache_lookup(c->opt.tune_cache, key, &g, &ch)) {
     c->solve_grid = g;
+    if (ch != c->solve_order) build_local_plans(c, ch);
     c->tuned = 2;
     return;
   }
-  std::vector<int> cand;
   const int maxper = c->fp32 ? 7 : 3;
-  for (int p = 1; p <= maxper; p++) cand.push_back(cus * p);
   double best = 1e300;
-  int best_g = c->solve_grid;
-  for (int cg : cand) {
-    double t = time_local_solves(c, cg, 3);
-    if (t < best) {
-      best = t;
-      best_g = cg;
+  int best_g = c->solve_grid, best_ch = c->solve_order;
+  for (int order : {1, 2, 3}) {
+    build_local_plans(c, order);
+    for (int p = 2; p <= maxper; p += 2) {
+      const int cg = cus * std::min(p, maxper);
+      double t = time_local_solves(c, cg, 3);
+      if (t < best) {
+        best = t;
+        best_g = cg;
+        best_ch = order;
+      }
     }
   }
+  if (best_ch != c->solve_order) build_local_plans(c, best_ch);
   c->solve_grid = best_g;
   c->tuned = 1;
-  cache_store(c->opt.tune_cache, key, best_g);
+  cache_store(c->opt.tune_cache, key, best_g, best_ch);
 }
 
 }  // namespace tls
