@@ -85,9 +85,10 @@ typedef struct {
   int32_t profile;      /* tls_apply times its local triangular-solve kernels with HIP
                            events (and then waits for them); see tls_info_t */
   int32_t solve_wgs;    /* workgroups of the persistent triangular solves (0 = default) */
-  int32_t solve_order;  /* task order of those solves: 1 level by level, 2 by fraction of
-                           the subdomain's rows done (default), 3 longest chain first (0 = default) */
-  int32_t autotune;     /* 1: at setup, time candidate workgroup counts and keep the fastest */
+  int32_t solve_order;  /* task order of those solves: 1 level by level, 2 by the fraction of
+                           the subdomain's rows done, 3 longest chain first; 0 = default (2) */
+  int32_t autotune;     /* 1: at setup, time candidate workgroup counts and task orders and keep
+                           the fastest (ignored when solve_wgs or solve_order is set) */
   const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
                              NULL = no persistence. A cached pick is reused without timing. */
   void* stream;         /* hipStream_t */
