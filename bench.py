@@ -30,8 +30,13 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-solve (rel res 1e-8) + precond applies/s: mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
-FP64_PEAK_TFLOPS = 78.6
+# HBM bytes per launch of the dominant kernel (k_trsv<float, FWD_L> on the
+# default workload) from two rocprofv3 counter runs: median FETCH_SIZE
+# 8,000,347 KiB x 1.99991 + WRITE_SIZE 5,762 KiB x 0.99999, the factors being
+# what the same counters read for a 1 GiB read + 1 GiB write elementwise copy
+# (--copy-probe). Set to None whenever that kernel changes until the counters
+# are taken again.
+TRAFFIC = 16389903970
 
 
 def log(*a):
@@ -39,10 +44,11 @@ def log(*a):
 
 
 def local_lower_bytes(info, w):
-    """Algorithmic bytes of one forward + one backward sweep over the lower
-    triangles of the local factors, m(m+1)/2 words each:
-    2 * w * sum_i m_i (m_i + 1) / 2 = w * (sum m^2 + sum m)."""
-    return float(w) * (float(info["local_sum_m2"]) + float(info["local_sum_m"]))
+    """Algorithmic bytes of ONE triangular-solve launch (forward or
+    backward) over all subdomains: the lower triangle of each local factor,
+    m_i (m_i + 1) / 2 words of w bytes, read once:
+    w * (sum m^2 + sum m) / 2. The vector traffic (2 m_i words) is left out."""
+    return float(w) * (float(info["local_sum_m2"]) + float(info["local_sum_m"])) / 2.0
 
 
 def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_cache, tol=1e-8):
@@ -122,6 +128,8 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         "apply_ms": apply_ms,
         "applies_per_s": 1e3 / apply_ms,
         "local_solve_ms": pinfo["t_local_solve_ms"],
+        "local_fwd_ms": pinfo["t_local_fwd_ms"],
+        "n_profiled": pinfo["n_profiled"],
         "solve_wgs": pinfo["solve_wgs"],
         "solve_order": pinfo["solve_order"],
         "tuned": pinfo["tuned"],
@@ -131,19 +139,33 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
     }
 
 
-def cpu_baseline(prob, iters, sample=3, seed=0):
-    """The FP64 oracle on a bounded sample: per-subdomain setup (overlap,
-    local matrix, sparse LU, eq. gevpsvd by ARPACK, coarse block) and one
-    local solve, for `sample` seeded subdomains; scaled to the full
-    time-to-solve as N * mean(setup) + iterations * N * mean(solve)."""
+def cpu_baseline(prob, iters, sample=32, seed=0):
+    """The FP64 oracle timed on one host thread over a bounded sample of the
+    same workload, scaled to the full time-to-solve.
+
+    Sample: `sample` subdomains stratified by interior size (evenly spaced
+    quantiles of the sorted sizes, so the mean is representative of the
+    uneven RCB parts). For each, the oracle's per-subdomain setup (overlap
+    layers, A_ii, sparse LU, eq. gevpsvd with ARPACK, coarse block) and one
+    local solve (mean of 5). Per iteration the oracle also does one product
+    with A and one coarse solve: the same library calls (CSR product, dense
+    Cholesky solve of order n_coarse) are timed on the workload's A and on a
+    seeded SPD matrix of order n_coarse, whose factorization is part of setup.
+    Estimate = N * setup + chol(n_coarse)
+               + iters * (N * local solve + A x + coarse solve)."""
+    import scipy.linalg as sla
+    import scipy.sparse.linalg as spla
     from threadpoolctl import threadpool_limits
 
     from oracle import schwarz
-    rng = np.random.default_rng(seed)
-    picks = rng.choice(prob.n_parts, size=min(sample, prob.n_parts), replace=False)
+    N = prob.n_parts
+    sizes_int = np.bincount(prob.part, minlength=N)
+    order = np.argsort(sizes_int, kind="stable")
+    k = min(sample, N)
+    picks = order[np.unique(np.linspace(0, N - 1, k).round().astype(int))]
     t_setup, t_solve, sizes = [], [], []
+    t_begin = time.perf_counter()
     with threadpool_limits(1):
-        import scipy.sparse.linalg as spla
         for i in picks:
             t0 = time.perf_counter()
             s = schwarz.overlap(prob.A, prob.part, int(i), prob.overlap)
@@ -151,21 +173,42 @@ def cpu_baseline(prob, iters, sample=3, seed=0):
             lu = spla.splu(Aii.tocsc())
             schwarz.coarse_block(Aii, s, prob.nev, 0, True)
             t1 = time.perf_counter()
-            lu.solve(np.ones(s.size))
+            rhs = np.ones(s.size)
+            for _ in range(5):
+                lu.solve(rhs)
             t2 = time.perf_counter()
             t_setup.append(t1 - t0)
-            t_solve.append(t2 - t1)
+            t_solve.append((t2 - t1) / 5)
             sizes.append(s.size)
-    N = prob.n_parts
-    est = N * float(np.mean(t_setup)) + iters * N * float(np.mean(t_solve))
+        x = np.ones(prob.A.shape[0])
+        t0 = time.perf_counter()
+        for _ in range(5):
+            prob.A @ x
+        t_spmv = (time.perf_counter() - t0) / 5
+        nC = N * prob.nev
+        rng = np.random.default_rng(seed)
+        G = rng.standard_normal((nC, nC))
+        S = G @ G.T + nC * np.eye(nC)
+        t0 = time.perf_counter()
+        f = sla.cho_factor(S, lower=True)
+        t_chol = time.perf_counter() - t0
+        y = np.ones(nC)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            sla.cho_solve(f, y)
+        t_csolve = (time.perf_counter() - t0) / 5
+    work = time.perf_counter() - t_begin
+    est = N * float(np.mean(t_setup)) + t_chol + iters * (N * float(np.mean(t_solve)) + t_spmv + t_csolve)
     return {
-        "value": est,
+        "value": round(est, 2),
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"{len(picks)} of {N} subdomains (ids {sorted(int(p) for p in picks)}, sizes {sizes}): "
-                   f"per-subdomain oracle setup {np.mean(t_setup):.2f} s, local solve {np.mean(t_solve) * 1e3:.1f} ms; "
-                   f"scaled to N*setup + {iters} iterations * N * solve"),
+        "sample": (f"{len(picks)} of {N} subdomains stratified by size (sizes {min(sizes)}..{max(sizes)}): "
+                   f"oracle setup {np.mean(t_setup):.3f} s and local solve {np.mean(t_solve) * 1e3:.2f} ms "
+                   f"per subdomain; A x {t_spmv * 1e3:.1f} ms; Cholesky of order {nC} {t_chol:.2f} s, "
+                   f"its solve {t_csolve * 1e3:.2f} ms; scaled to N * setup + {iters} iterations; "
+                   f"{work:.1f} s of host work"),
     }
 
 
@@ -181,7 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a 1 GiB device-to-device copy (reference kernel for HBM counters)")
+                    help="also run z = 1.0 * x over 1 GiB (reads 1 GiB, writes 1 GiB): the plain copy kernel "
+                         "whose HBM counters scale those of the solve kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); multi-GPU runs are not part of "
@@ -205,7 +249,7 @@ def main():
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     import tempfile
@@ -215,12 +259,20 @@ def main():
     if not args.no_fp64:
         plain = run_mode(prob, dev_in, 0, args.steps, args.warmup, args.applies, args.graph, tune_cache)
     info = mixed["info"]
-    sizes_bytes32 = local_lower_bytes(info, 4)
-    achieved = sizes_bytes32 / (mixed["local_solve_ms"] * 1e-3) / 1e9 if mixed["local_solve_ms"] > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": "k_trsv<float,FWD_L> + k_trsv<float,BWD_LT> (local solves of one apply)",
+    # dominant kernel: the forward persistent triangular solve of the FP32
+    # local factors (the backward one reads the same bytes in about the same
+    # time); its launch duration comes from HIP events recorded by the library
+    # on the stream the kernel runs on
+    bytes_launch = local_lower_bytes(info, 4)
+    t_fwd = mixed["local_fwd_ms"]
+    t_bwd = mixed["local_solve_ms"] - t_fwd
+    achieved = bytes_launch / (t_fwd * 1e-3) / 1e9 if t_fwd > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": "k_trsv<float, FWD_L> (forward local solves of one apply, all subdomains)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_launch_pair": sizes_bytes32, "launch_pair_ms": mixed["local_solve_ms"],
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC,
+            "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4), "launches_timed": mixed["n_profiled"],
+            "backward_launch_ms": round(t_bwd, 4),
+            "backward_GBps": round(bytes_launch / (t_bwd * 1e-3) / 1e9, 1) if t_bwd > 0 else None,
             "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"]}
     apply_err = None
     if plain is not None:
@@ -254,7 +306,7 @@ def main():
     }
     if plain is not None:
         pinf = plain["info"]
-        b64 = local_lower_bytes(pinf, 8)
+        b64 = 2.0 * local_lower_bytes(pinf, 8)
         ach64 = b64 / (plain["local_solve_ms"] * 1e-3) / 1e9 if plain["local_solve_ms"] > 0 else 0.0
         out["plain_fp64"] = {"time_to_solve_s": round(plain["ms_per_step"] / 1e3, 4), "iters": plain["iters"],
                              "relres": plain["relres"], "applies_per_s": round(plain["applies_per_s"], 2),

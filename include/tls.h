@@ -116,6 +116,7 @@ typedef struct {
   double t_local_solve_ms;    /* mean duration of their local forward + backward
                                  triangular-solve kernels (HIP events)       */
   double t_apply_ms;          /* mean duration of those whole applies         */
+  double t_local_fwd_ms;      /* mean duration of their forward solve kernel alone */
   int32_t solve_wgs;          /* workgroups used by the persistent solves     */
   int32_t solve_order;        /* task order used by those solves (1, 2 or 3)  */
   int32_t tuned;              /* 0 default, 1 timed at setup, 2 read from the cache */

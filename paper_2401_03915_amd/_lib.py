@@ -75,6 +75,7 @@ class tls_info_t(C.Structure):
         ("n_profiled", C.c_int32),
         ("t_local_solve_ms", C.c_double),
         ("t_apply_ms", C.c_double),
+        ("t_local_fwd_ms", C.c_double),
         ("solve_wgs", C.c_int32),
         ("solve_order", C.c_int32),
         ("tuned", C.c_int32),

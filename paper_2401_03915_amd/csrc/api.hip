@@ -227,6 +227,7 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->n_profiled = c->prof_count;
   info->t_local_solve_ms = c->prof_count ? c->prof_local_ms / c->prof_count : 0.0;
   info->t_apply_ms = c->prof_count ? c->prof_apply_ms / c->prof_count : 0.0;
+  info->t_local_fwd_ms = c->prof_count ? c->prof_fwd_ms / c->prof_count : 0.0;
   info->solve_wgs = c->solve_grid;
   info->solve_order = c->solve_order;
   info->tuned = c->tuned;

@@ -82,7 +82,8 @@ void apply_impl(tls_ctx* c, const double* r, double* z, const int* done, T* xloc
     c->stream = keep;
     TLS_HIP(hipEventRecord(c->ev_join, c->stream2));
   }
-  local_solve(c, done, profile ? c->prof_ev[1] : nullptr, profile ? c->prof_ev[2] : nullptr);
+  local_solve(c, done, profile ? c->prof_ev[1] : nullptr, profile ? c->prof_ev[4] : nullptr,
+              profile ? c->prof_ev[2] : nullptr);
   if (coarse) TLS_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
   hipLaunchKernelGGL(k_apply_scatter<T>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->own_ptr.p,
                      c->own_pos.p, xloc, scale, c->part.p, c->ipos.p, c->d_nI.p, coarse ? c->kz_dev.p : nullptr,
@@ -91,10 +92,12 @@ void apply_impl(tls_ctx* c, const double* r, double* z, const int* done, T* xloc
   if (profile) {
     TLS_HIP(hipEventRecord(c->prof_ev[3], s));
     TLS_HIP(hipEventSynchronize(c->prof_ev[3]));
-    float t_local = 0.f, t_all = 0.f;
+    float t_local = 0.f, t_fwd = 0.f, t_all = 0.f;
     TLS_HIP(hipEventElapsedTime(&t_local, c->prof_ev[1], c->prof_ev[2]));
+    TLS_HIP(hipEventElapsedTime(&t_fwd, c->prof_ev[1], c->prof_ev[4]));
     TLS_HIP(hipEventElapsedTime(&t_all, c->prof_ev[0], c->prof_ev[3]));
     c->prof_local_ms += t_local;
+    c->prof_fwd_ms += t_fwd;
     c->prof_apply_ms += t_all;
     c->prof_count++;
   }

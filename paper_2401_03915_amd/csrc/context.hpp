@@ -94,9 +94,9 @@ struct tls_ctx {
   bool graph_flex = false;
 
   // diagnostics
-  hipEvent_t prof_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t prof_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int prof_count = 0;
-  double prof_local_ms = 0, prof_apply_ms = 0;
+  double prof_local_ms = 0, prof_fwd_ms = 0, prof_apply_ms = 0;
   tls::DBuf<int> errflag;
   double t_setup[8] = {0};
   double t_solve = 0;

@@ -1201,7 +1201,7 @@ void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, cons
   trsm_tiles_impl<double>(c, c->kind == 0 ? BWD_LT : BWD_U, X, nq, xoff);
 }
 
-void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_end) {
+void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid, hipEvent_t ev_end) {
   hipStream_t s = c->stream;
   LocalLayout lay = c->layout();
   solve_begin(s, c->counters.p, done);
@@ -1210,11 +1210,13 @@ void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev
   if (c->fp32) {
     trsv<float>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac32.p, c->xloc32.p,
                 c->errflag.p, done, c->solve_grid);
+    if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
     trsv<float>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac32.p, c->xloc32.p,
                 c->errflag.p, done, c->solve_grid);
   } else {
     trsv<double>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac64.p, c->xloc64.p,
                  c->errflag.p, done, c->solve_grid);
+    if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
     trsv<double>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac64.p, c->xloc64.p,
                  c->errflag.p, done, c->solve_grid);
   }

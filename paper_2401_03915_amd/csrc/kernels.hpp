@@ -16,9 +16,11 @@ void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist);
 void factor_local(tls_ctx* c);
 void build_solve_tasks(tls_ctx* c);
 // local solves on the padded vector buffer x (fp64 or fp32 per c->fp32)
-// ev_begin / ev_end (may be null) are recorded right before the forward and
-// right after the backward triangular-solve kernel
-void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+// ev_begin / ev_mid / ev_end (may be null) are recorded right before the
+// forward, between the forward and the backward, and right after the
+// backward triangular-solve kernel
+void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_mid = nullptr,
+                 hipEvent_t ev_end = nullptr);
 // backward substitution L^T x = x only, on a padded vector of the context's precision
 void local_backward(tls_ctx* c, float* x, const int* done);
 void local_backward(tls_ctx* c, double* x, const int* done);
