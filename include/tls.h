@@ -65,8 +65,9 @@ typedef struct {
   /* 0: A is SPD: Cholesky, eq. gevpsvd (+ eq. uppergevp if nev1 > 0), PCG.
    * 1: general A: LU without pivoting, Section 6 SVD variant, FGMRES.     */
   int32_t matrix_kind;
-  /* eq. uppergevp vectors kept per subdomain (those with lambda > nu).
-   * The paper's SPD experiments use none (Section 7); default 0. */
+  /* eq. uppergevp vectors kept per subdomain (those with lambda > nu),
+   * SPD only (TLS_E_ARG with matrix_kind 1). The paper's SPD experiments
+   * use none (Section 7); default 0. */
   int32_t nev1;
   /* Thresholds: keep lambda^2 > tau^2 (eq. gevpsvd) or sigma > tau
    * (Section 6), and lambda > nu (eq. uppergevp), each capped by the
@@ -76,8 +77,9 @@ typedef struct {
   int32_t restart;      /* FGMRES restart length m (default 30)            */
   int32_t maxit;        /* Krylov iteration cap (default 1000; 3000 general) */
   int32_t eig_maxit;    /* local subspace-iteration cap (default 300)      */
-  double eig_tol;       /* relative eigen-residual tolerance (default 1e-8 FP64, 1e-5 FP32) */
-  int32_t eig_oversample; /* block size p = nev + oversample (default nev) */
+  double eig_tol;       /* relative eigen-residual tolerance (default 1e-9 FP64, 1e-6 FP32) */
+  int32_t eig_oversample; /* subspace block p = k + oversample, k = nev (eq. gevpsvd) or
+                             nev1 (eq. uppergevp); default (-1): k; p <= 48 */
   uint64_t seed;        /* seed of the counter-based start vectors         */
   int32_t use_graph;    /* capture Krylov iteration chunks in a hipGraph   */
   int32_t flexible;     /* PCG: Polak-Ribiere beta (default: 1 iff precision == 1) */
@@ -165,11 +167,15 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info);
  *   layer_ptr[n_parts*(overlap+2)]            : per subdomain, offsets of I_i,
  *                                               Gamma_1 .. Gamma_delta, end
  *   zcol_ptr[n_parts+1]                       : first coarse column per subdomain
- *   eigvals[n_coarse]                         : kept lambda^2 (SPD) / sigma (general)
+ *   eigvals[n_coarse]                         : per kept column, its eigenvalue: lambda^2
+ *                                               (eq. gevpsvd), lambda (eq. uppergevp) or
+ *                                               sigma (general A, Section 6)
+ *   zsrc[n_coarse]                            : per kept column, where it came from:
+ *                                               0 eq. gevpsvd, 1 eq. uppergevp, 2 Section 6
  *   Z[n * n_coarse]                           : dense column-major coarse basis
  *   A0[n_coarse * n_coarse]                   : dense column-major A_0          */
 tls_status tls_export(const tls_ctx* c, int32_t* sub_ptr, int32_t* sub_idx, int32_t* layer_ptr,
-                      int32_t* zcol_ptr, double* eigvals, double* Z, double* A0);
+                      int32_t* zcol_ptr, double* eigvals, int32_t* zsrc, double* Z, double* A0);
 
 /* Solve with one local factor: x = A_ii^{-1} b for subdomain i (host
  * vectors of length #Omega_i, in the Omega_i order). Diagnostics. */

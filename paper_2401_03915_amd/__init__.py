@@ -102,6 +102,7 @@ class Preconditioner:
             "layer_ptr": np.zeros(N * (self.overlap + 2), dtype=np.int32),
             "zcol_ptr": np.zeros(N + 1, dtype=np.int32),
             "eigvals": np.zeros(max(nC, 1)),
+            "zsrc": np.zeros(max(nC, 1), dtype=np.int32),
         }
         tls_export(self.ctx, sub_ptr=out["sub_ptr"])
         out["sub_idx"] = np.zeros(int(out["sub_ptr"][-1]), dtype=np.int32)
@@ -110,8 +111,10 @@ class Preconditioner:
         if A0:
             out["A0"] = np.zeros((nC, nC))
         tls_export(self.ctx, sub_ptr=out["sub_ptr"], sub_idx=out["sub_idx"], layer_ptr=out["layer_ptr"],
-                   zcol_ptr=out["zcol_ptr"], eigvals=out["eigvals"], Z=out.get("Z"), A0=out.get("A0"))
+                   zcol_ptr=out["zcol_ptr"], eigvals=out["eigvals"], zsrc=out["zsrc"], Z=out.get("Z"),
+                   A0=out.get("A0"))
         out["eigvals"] = out["eigvals"][:nC]
+        out["zsrc"] = out["zsrc"][:nC]
         if Z:
             out["Z"] = out["Z"].T.copy()  # n x nC
         if A0:

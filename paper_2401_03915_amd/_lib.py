@@ -106,7 +106,7 @@ def lib() -> C.CDLL:
         L.tls_solve.restype = C.c_int
         L.tls_info.argtypes = [vp, C.POINTER(tls_info_t)]
         L.tls_info.restype = C.c_int
-        L.tls_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.tls_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.tls_export.restype = C.c_int
         L.tls_local_solve.argtypes = [vp, i32, vp, vp]
         L.tls_local_solve.restype = C.c_int
@@ -170,11 +170,12 @@ def tls_info(ctx) -> dict:
 
 
 def tls_export(ctx, **bufs):
-    """bufs: numpy arrays (or None) for sub_ptr, sub_idx, layer_ptr, zcol_ptr, eigvals, Z, A0."""
+    """bufs: numpy arrays (or None) for sub_ptr, sub_idx, layer_ptr, zcol_ptr, eigvals, zsrc, Z, A0."""
     def p(a):
         return None if a is None else a.ctypes.data
     check(lib().tls_export(ctx, p(bufs.get("sub_ptr")), p(bufs.get("sub_idx")), p(bufs.get("layer_ptr")),
-                           p(bufs.get("zcol_ptr")), p(bufs.get("eigvals")), p(bufs.get("Z")), p(bufs.get("A0"))),
+                           p(bufs.get("zcol_ptr")), p(bufs.get("eigvals")), p(bufs.get("zsrc")), p(bufs.get("Z")),
+                           p(bufs.get("A0"))),
           ctx)
 
 

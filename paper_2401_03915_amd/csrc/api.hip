@@ -83,9 +83,11 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.precision != 0 && c->opt.precision != 1) tls::fail(TLS_E_ARG, "precision must be 0 or 1");
     if (c->opt.matrix_kind != 0 && c->opt.matrix_kind != 1) tls::fail(TLS_E_ARG, "matrix_kind must be 0 or 1");
     if (c->opt.nev1 < 0) tls::fail(TLS_E_ARG, "nev1 must be >= 0");
+    if (c->opt.nev1 > 0 && c->opt.matrix_kind != 0)
+      tls::fail(TLS_E_ARG, "nev1 (eq. uppergevp vectors) applies to SPD matrices only");
+    if (c->opt.nev1 > 0 && overlap == 0) tls::fail(TLS_E_ARG, "overlap 0: nev1 must be 0");
     if (c->opt.solve_order < 0 || c->opt.solve_order > 3) tls::fail(TLS_E_ARG, "solve_order must be in [0, 3]");
     if (c->opt.solve_wgs < 0) tls::fail(TLS_E_ARG, "solve_wgs must be >= 0");
-    if (c->opt.eig_oversample < 0) c->opt.eig_oversample = nev;
     if (c->opt.flexible < 0) c->opt.flexible = c->opt.precision == 1 ? 1 : 0;
     if (c->opt.eig_maxit <= 0) c->opt.eig_maxit = 300;
     if (c->opt.restart <= 0) c->opt.restart = 30;
@@ -235,7 +237,7 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
 }
 
 tls_status tls_export(const tls_ctx* cc, int32_t* sub_ptr, int32_t* sub_idx, int32_t* layer_ptr, int32_t* zcol_ptr,
-                      double* eigvals, double* Z, double* A0) {
+                      double* eigvals, int32_t* zsrc, double* Z, double* A0) {
   tls_ctx* c = const_cast<tls_ctx*>(cc);
   if (!c) return TLS_E_STATE;
   return guard(c, [&]() {
@@ -248,6 +250,7 @@ tls_status tls_export(const tls_ctx* cc, int32_t* sub_ptr, int32_t* sub_idx, int
     if (layer_ptr) std::copy(c->h_layer_ptr.begin(), c->h_layer_ptr.end(), layer_ptr);
     if (zcol_ptr) std::copy(c->h_zcol.begin(), c->h_zcol.end(), zcol_ptr);
     if (eigvals) std::copy(c->h_eig.begin(), c->h_eig.end(), eigvals);
+    if (zsrc) std::copy(c->h_zsrc.begin(), c->h_zsrc.end(), zsrc);
     if (Z && c->nC > 0) {
       int64_t tot = c->h_zoff.empty() ? 0 : c->h_zoff[N];
       auto hz = tls::download(c->Z.p, std::max<int64_t>(tot, 1), s);

@@ -64,6 +64,7 @@ struct tls_ctx {
   int nC = 0, M0 = 0, nt0 = 0;
   std::vector<int> h_zcol;  // N+1 column offsets
   std::vector<double> h_eig;
+  std::vector<int> h_zsrc;  // per coarse column: 0 eq. gevpsvd, 1 eq. uppergevp, 2 Section 6
   tls::DBuf<int> zcol;
   tls::DBuf<double> Z;      // per subdomain #I_i x k_i column-major, concatenated
   std::vector<int64_t> h_zoff;

@@ -25,7 +25,8 @@ namespace tls {
 
 namespace {
 
-constexpr int PMAX = 48;  // largest subspace block
+constexpr int PMAX = 48;      // largest subspace block
+constexpr int KMAX = 2 * PMAX;  // most coarse columns of one subdomain (both eigenproblems)
 
 struct EigLayout {
   const int* nI;
@@ -510,7 +511,7 @@ __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const
     nr = sqrt(block_sum(nr, red));
     if (nr > 1e-10 * n0 && nr > 0.0) {
       for (int r = tid; r < nI; r += 256) v[r] /= nr;
-      if (tid == 0) keep_idx[i * PMAX + kept] = a;
+      if (tid == 0) keep_idx[i * KMAX + kept] = a;
       kept++;
     }
     __syncthreads();
@@ -520,257 +521,243 @@ __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const
 
 }  // namespace
 
-template <class T>
-static void basis_impl(tls_ctx* c, T* fac) {
+// Per-subdomain sizes of one symmetric eigen pass over the blocks
+// [I, G, T] of the local factors, with the offsets of its dense buffers.
+struct PassDims {
+  std::vector<int> nI, nG, nT, kreq;
+  std::vector<int64_t> oF, oGI, oTG, oGG, oTT, oY, oZv;
+  std::vector<int> oth;
+  int kmax = 0;
+  int over = 0;  // subspace block p = k + over (default over = k of the pass)
+};
+
+static PassDims pass_dims(const tls_ctx* c, const std::vector<int>& nG, int nev, bool general) {
+  const int N = c->N;
+  PassDims d;
+  d.nI.resize(N);
+  d.nG = nG;
+  d.nT.resize(N);
+  d.kreq.resize(N);
+  for (auto* v : {&d.oF, &d.oGI, &d.oTG, &d.oGG, &d.oTT, &d.oY, &d.oZv}) v->assign(N + 1, 0);
+  d.oth.assign(N + 1, 0);
+  d.over = c->opt.eig_oversample >= 0 ? c->opt.eig_oversample : nev;
+  for (int i = 0; i < N; i++) {
+    d.nI[i] = c->h_nI[i];
+    d.nT[i] = c->h_m[i] - d.nI[i] - nG[i];
+    int k = std::min(std::min(nev, d.nT[i]), PMAX);
+    if (general) k = std::min(k, d.nI[i]);
+    d.kreq[i] = std::max(k, 0);
+    d.kmax = std::max(d.kmax, d.kreq[i]);
+    const int p = std::min(d.nT[i], std::min(PMAX, d.kreq[i] + d.over));
+    const bool act = d.kreq[i] > 0;
+    d.oF[i + 1] = d.oF[i] + (act && !general ? (int64_t)d.nI[i] * d.nT[i] : 0);
+    d.oGI[i + 1] = d.oGI[i] + (act ? (int64_t)nG[i] * d.nI[i] : 0);
+    d.oTG[i + 1] = d.oTG[i] + (act ? (int64_t)nG[i] * d.nT[i] : 0);
+    d.oGG[i + 1] = d.oGG[i] + (act ? (int64_t)nG[i] * nG[i] : 0);
+    d.oTT[i + 1] = d.oTT[i] + (act ? (int64_t)d.nT[i] * d.nT[i] : 0);
+    d.oY[i + 1] = d.oY[i] + (act ? (int64_t)d.nT[i] * std::max(p, 1) : 0);
+    d.oZv[i + 1] = d.oZv[i] + (int64_t)d.nT[i] * d.kreq[i];
+    d.oth[i + 1] = d.oth[i] + d.kreq[i];
+  }
+  return d;
+}
+
+// Device copies of the per-subdomain tables of a pass.
+struct PassDev {
+  DBuf<int> nI, nG, nT, kreq, oth;
+  DBuf<int64_t> oF, oGI, oTG, oGG, oTT, oY, oZv, oXH;
+  void upload(const PassDims& d, const std::vector<int64_t>& oXH_h, hipStream_t s) {
+    nI.upload(d.nI, s);
+    nG.upload(d.nG, s);
+    nT.upload(d.nT, s);
+    kreq.upload(d.kreq, s);
+    oth.upload(d.oth, s);
+    oF.upload(d.oF, s);
+    oGI.upload(d.oGI, s);
+    oTG.upload(d.oTG, s);
+    oGG.upload(d.oGG, s);
+    oTT.upload(d.oTT, s);
+    oY.upload(d.oY, s);
+    oZv.upload(d.oZv, s);
+    oXH.upload(oXH_h, s);
+  }
+  EigLayout layout(const tls_ctx* c) const {
+    return EigLayout{nI.p, nG.p, nT.p, c->d_m.p, c->d_nt.p, c->d_foff.p, oF.p, oGI.p, oTG.p, oGG.p, oTT.p, oXH.p,
+                     kreq.p};
+  }
+};
+
+// Result of the subspace iteration of one pass (host copies).
+struct PassEig {
+  std::vector<int> kf;         // pairs kept per subdomain
+  std::vector<double> theta;   // their eigenvalues of C, at oth[i] + j
+  double resid_max = 0.0;
+  int iters_max = 0;
+};
+
+// Top eigenpairs of C (nT x nT per subdomain, fp64, in C64) by subspace
+// iteration; the eigenvectors land in zv (nT x kf, offsets oZv).
+static PassEig run_subspace(tls_ctx* c, const PassDims& d, PassDev& dv, const DBuf<double>& C64, DBuf<double>& zv,
+                            double thresh) {
   hipStream_t s = c->stream;
   const int N = c->N;
-  const bool general = c->kind == 1;
-  std::vector<int> nI(N), nG(N), nT(N), kreq(N), nqH(N, 0), nqV(N, 0);
-  std::vector<int64_t> oF(N + 1, 0), oGI(N + 1, 0), oTG(N + 1, 0), oGG(N + 1, 0), oTT(N + 1, 0), oY(N + 1, 0),
-      oZv(N + 1, 0), oZ(N + 1, 0), oXH(N + 1, 0), oXV(N + 1, 0);
-  std::vector<int> oth(N + 1, 0);
-  int kmax = 0;
-  for (int i = 0; i < N; i++) {
-    nI[i] = c->h_nI[i];
-    nG[i] = c->h_nP[i] - c->h_nI[i];
-    nT[i] = c->h_m[i] - c->h_nP[i];
-    kreq[i] = std::min(std::min(c->nev, nT[i]), PMAX);
-    if (general) kreq[i] = std::min(kreq[i], nI[i]);
-    kmax = std::max(kmax, kreq[i]);
-    const int64_t M = (int64_t)c->h_nt[i] * TS;
-    int p = std::min(nT[i], std::min(PMAX, kreq[i] + c->opt.eig_oversample));
-    const bool act = kreq[i] > 0;
-    oF[i + 1] = oF[i] + (act && !general ? (int64_t)nI[i] * nT[i] : 0);
-    oGI[i + 1] = oGI[i] + (act ? (int64_t)nG[i] * nI[i] : 0);
-    oTG[i + 1] = oTG[i] + (act ? (int64_t)nG[i] * nT[i] : 0);
-    oGG[i + 1] = oGG[i] + (act ? (int64_t)nG[i] * nG[i] : 0);
-    oTT[i + 1] = oTT[i] + (act ? (int64_t)nT[i] * nT[i] : 0);
-    oY[i + 1] = oY[i] + (act ? (int64_t)nT[i] * std::max(p, 1) : 0);
-    oZv[i + 1] = oZv[i] + (int64_t)nT[i] * kreq[i];
-    oZ[i + 1] = oZ[i] + (int64_t)nI[i] * kreq[i];
-    oth[i + 1] = oth[i] + kreq[i];
-    nqH[i] = (general && act) ? (nT[i] + TS - 1) / TS : 0;
-    nqV[i] = act ? 1 : 0;
-    oXH[i + 1] = oXH[i] + M * TS * nqH[i];
-    oXV[i + 1] = oXV[i] + M * TS * nqV[i];
-  }
-  if (kmax == 0) {
-    c->nC = 0;
-    c->h_zcol.assign(N + 1, 0);
-    c->h_zoff.assign(N + 1, 0);
-    c->zcol.upload(c->h_zcol, s);
-    c->zoff.upload(c->h_zoff, s);
-    c->Z.alloc(1);
-    return;
-  }
-  DBuf<int> d_nI, d_nG, d_nT, d_kreq;
-  DBuf<int64_t> d_oF, d_oGI, d_oTG, d_oGG, d_oTT, d_oY, d_oZv, d_oZ, d_oXH, d_oXV;
-  DBuf<int> d_oth;
-  d_nI.upload(nI, s);
-  d_nG.upload(nG, s);
-  d_nT.upload(nT, s);
-  d_kreq.upload(kreq, s);
-  d_oF.upload(oF, s);
-  d_oGI.upload(oGI, s);
-  d_oTG.upload(oTG, s);
-  d_oGG.upload(oGG, s);
-  d_oTT.upload(oTT, s);
-  d_oY.upload(oY, s);
-  d_oZv.upload(oZv, s);
-  d_oZ.upload(oZ, s);
-  d_oXH.upload(oXH, s);
-  d_oXV.upload(oXV, s);
-  d_oth.upload(oth, s);
-  EigLayout el{d_nI.p, d_nG.p,  d_nT.p,  c->d_m.p, c->d_nt.p, c->d_foff.p, d_oF.p,
-               d_oGI.p, d_oTG.p, d_oGG.p, d_oTT.p, d_oXH.p,  d_kreq.p};
-  const dim3 eg(64, N);
-  TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
-
-  DBuf<T> F, GI, TG, GGt, K, XH;
-  DBuf<double> LTT, LTTt, C64, C64b;
-  K.alloc(oTT[N]);
-  C64.alloc(oTT[N]);
-  if (oGG[N] > 0) {
-    GI.alloc(oGI[N]);
-    TG.alloc(oTG[N]);
-    GGt.alloc(oGG[N]);
-  }
-  if (!general) {
-    // ---- SPD: eq. gevpsvd through the Cholesky blocks --------------------
-    F.alloc(oF[N]);
-    LTT.alloc(oTT[N]);
-    LTTt.alloc(oTT[N]);
-    C64b.alloc(oTT[N]);
-    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 0, el, fac, F.p);
-    hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
-    hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 5, el, fac, LTTt.p);
-    TLS_LAUNCH_CHECK();
-    if (oGG[N] > 0) {
-      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 1, el, fac, TG.p);
-      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 2, el, fac, GGt.p);
-      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 3, el, fac, GI.p);
-      TLS_LAUNCH_CHECK();
-      // Tm = L_GG^{-T} L_TG^T ; F += L_GI^T Tm
-      std::vector<TriDesc> td;
-      for (int i = 0; i < N; i++)
-        if (kreq[i] > 0) td.push_back(TriDesc{nG[i], nT[i], oGG[i], oTG[i], (int64_t)nG[i]});
-      batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
-      std::vector<GemmDesc> gd;
-      for (int i = 0; i < N; i++)
-        if (kreq[i] > 0 && nG[i] > 0)
-          gd.push_back(GemmDesc{nI[i], nT[i], nG[i], nG[i], nG[i], oGI[i], oTG[i], oF[i], (int64_t)nI[i]});
-      batched_gemm<T>(s, gd, true, false, GI.p, TG.p, F.p, T(1), T(1));
-    }
-    // K = F^T F
-    std::vector<GemmDesc> gd;
-    for (int i = 0; i < N; i++)
-      if (kreq[i] > 0) gd.push_back(GemmDesc{nT[i], nT[i], nI[i], nI[i], nI[i], oF[i], oF[i], oTT[i], (int64_t)nT[i]});
-    batched_gemm<T>(s, gd, true, false, F.p, F.p, K.p, T(1), T(0));
-    // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
-    hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)oTT[N], K.p, C64.p);
-    TLS_LAUNCH_CHECK();
-    std::vector<TriDesc> td;
-    for (int i = 0; i < N; i++)
-      if (kreq[i] > 0) td.push_back(TriDesc{nT[i], nT[i], oTT[i], oTT[i], (int64_t)nT[i]});
-    batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64.p, c->errflag.p);
-    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, d_kreq.p, C64.p, C64b.p, 0);
-    TLS_LAUNCH_CHECK();
-    batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64b.p, c->errflag.p);
-    hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, d_nT.p, d_oTT.p, d_kreq.p, C64b.p, C64.p, 1);
-    TLS_LAUNCH_CHECK();
-    if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_NOT_SPD, "zero pivot in a Schur-complement block");
-  } else {
-    // ---- general: Section 6, H = rows I of -A_{O'O'}^{-1} A_{O'T} ---------
-    // with A_ii = L U ordered [I, G, T]: H = U_II^{-1} (-U_IT + U_IG U_GG^{-1} U_GT)
-    XH.alloc(std::max<int64_t>(oXH[N], 1));
-    TLS_HIP(hipMemsetAsync(XH.p, 0, sizeof(T) * std::max<int64_t>(oXH[N], 1), s));
-    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 9, el, fac, XH.p);
-    TLS_LAUNCH_CHECK();
-    if (oGG[N] > 0) {
-      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 6, el, fac, TG.p);
-      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 7, el, fac, GGt.p);
-      hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 8, el, fac, GI.p);
-      TLS_LAUNCH_CHECK();
-      std::vector<TriDesc> td;
-      for (int i = 0; i < N; i++)
-        if (kreq[i] > 0) td.push_back(TriDesc{nG[i], nT[i], oGG[i], oTG[i], (int64_t)nG[i]});
-      batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
-      std::vector<GemmDesc> gd;
-      for (int i = 0; i < N; i++)
-        if (kreq[i] > 0 && nG[i] > 0)
-          gd.push_back(GemmDesc{nI[i], nT[i], nG[i], nI[i], nG[i], oGI[i], oTG[i], oXH[i],
-                                (int64_t)c->h_nt[i] * TS});
-      batched_gemm<T>(s, gd, false, false, GI.p, TG.p, XH.p, T(1), T(1));
-    }
-    if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_SINGULAR, "zero pivot in a local U_GG block");
-    // H = U_II^{-1} X: the backward solve on the whole factor leaves rows G, T zero
-    local_trsm_backward(c, XH.p, nqH, oXH);
-    // K = H^T H
-    std::vector<GemmDesc> gd;
-    for (int i = 0; i < N; i++) {
-      const int M = c->h_nt[i] * TS;
-      if (kreq[i] > 0) gd.push_back(GemmDesc{nT[i], nT[i], nI[i], M, M, oXH[i], oXH[i], oTT[i], (int64_t)nT[i]});
-    }
-    batched_gemm<T>(s, gd, true, false, XH.p, XH.p, K.p, T(1), T(0));
-    hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)oTT[N], K.p, C64.p);
-    TLS_LAUNCH_CHECK();
-  }
-  K.release();
-  GI.release();
-  TG.release();
-  GGt.release();
-
-  // ---- subspace iteration on C ----------------------------------------------
-  DBuf<double> Yb, Wb, zv, theta, resid;
+  DBuf<double> Yb, Wb, theta, resid;
   DBuf<int> kfound, its;
-  Yb.alloc(std::max<int64_t>(oY[N], 1));
-  Wb.alloc(std::max<int64_t>(oY[N], 1));
-  zv.alloc(std::max<int64_t>(oZv[N], 1));
-  theta.alloc(std::max(oth[N], 1));
+  Yb.alloc(std::max<int64_t>(d.oY[N], 1));
+  Wb.alloc(std::max<int64_t>(d.oY[N], 1));
+  zv.alloc(std::max<int64_t>(d.oZv[N], 1));
+  theta.alloc(std::max(d.oth[N], 1));
   resid.alloc(N);
   kfound.alloc(N);
   its.alloc(N);
   const double tol = c->opt.eig_tol > 0 ? c->opt.eig_tol : (c->fp32 ? 1e-6 : 1e-9);
-  double tau2 = -1.0;
-  if (c->opt.tau > 0) tau2 = c->opt.tau * c->opt.tau;  // lambda^2 > tau^2 (SPD) or sigma^2 > tau^2 (general)
-  hipLaunchKernelGGL(k_subspace, dim3(N), dim3(256), 0, s, d_nT.p, d_kreq.p, d_oTT.p, C64.p, d_oY.p, Yb.p, Wb.p,
-                     c->opt.eig_oversample, c->opt.eig_maxit, tol, (uint64_t)c->opt.seed, d_oZv.p, zv.p, d_oth.p,
-                     theta.p, kfound.p, resid.p, its.p, tau2, 1e-12, c->errflag.p);
+  hipLaunchKernelGGL(k_subspace, dim3(N), dim3(256), 0, s, dv.nT.p, dv.kreq.p, dv.oTT.p, C64.p, dv.oY.p, Yb.p, Wb.p,
+                     d.over, c->opt.eig_maxit, tol, (uint64_t)c->opt.seed, dv.oZv.p, zv.p, dv.oth.p,
+                     theta.p, kfound.p, resid.p, its.p, thresh, 1e-12, c->errflag.p);
   TLS_LAUNCH_CHECK();
-  auto h_kf = download(kfound.p, N, s);
+  PassEig e;
+  e.kf = download(kfound.p, N, s);
   auto h_res = download(resid.p, N, s);
   auto h_its = download(its.p, N, s);
-  auto h_th = download(theta.p, std::max(oth[N], 1), s);
-  c->eig_resid_max = 0;
-  c->eig_iters_max = 0;
+  e.theta = download(theta.p, std::max(d.oth[N], 1), s);
   for (int i = 0; i < N; i++) {
-    c->eig_resid_max = std::max(c->eig_resid_max, h_res[i]);
-    c->eig_iters_max = std::max(c->eig_iters_max, h_its[i]);
+    e.resid_max = std::max(e.resid_max, h_res[i]);
+    e.iters_max = std::max(e.iters_max, h_its[i]);
   }
-  Yb.release();
-  Wb.release();
+  return e;
+}
 
-  // ---- coarse vectors into X_V (rows I, one 64-column block per subdomain) --
-  DBuf<T> wT, XV;
-  wT.alloc(std::max<int64_t>(oZv[N], 1));
-  if (general) {
-    XV.alloc(std::max<int64_t>(oXV[N], 1));
-    TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
-  }
-  if (!general) {
-    // w_T = L_TT^{-T} z ; V = F w_T ; then x = L^{-T} [V; 0] gives rows I = L_II^{-T} V
+// One SPD pass (see the file header): F = -L_TI^T + L_GI^T L_GG^{-T} L_TG^T,
+// C = L_TT^{-1} F^T F L_TT^{-T}, top pairs of C, then the vectors
+// F L_TT^{-T} z written as column colbase[i] + j of the per-column padded
+// buffer XV (column j of every subdomain is padded local vector j, stride
+// sum_M); a backward solve with the whole factor then turns [V; 0] into
+// [L_II^{-T} V; 0].
+template <class T>
+static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thresh, const std::vector<int>& colbase,
+                        T* XV) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  PassDev dv;
+  dv.upload(d, std::vector<int64_t>(N + 1, 0), s);
+  const EigLayout el = dv.layout(c);
+  const dim3 eg(64, N);
+  DBuf<T> F, GI, TG, GGt, K;
+  DBuf<double> LTT, LTTt, C64, C64b;
+  K.alloc(std::max<int64_t>(d.oTT[N], 1));
+  C64.alloc(std::max<int64_t>(d.oTT[N], 1));
+  F.alloc(std::max<int64_t>(d.oF[N], 1));
+  LTT.alloc(std::max<int64_t>(d.oTT[N], 1));
+  LTTt.alloc(std::max<int64_t>(d.oTT[N], 1));
+  C64b.alloc(std::max<int64_t>(d.oTT[N], 1));
+  hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 0, el, fac, F.p);
+  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
+  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 5, el, fac, LTTt.p);
+  TLS_LAUNCH_CHECK();
+  if (d.oGG[N] > 0) {
+    GI.alloc(d.oGI[N]);
+    TG.alloc(d.oTG[N]);
+    GGt.alloc(d.oGG[N]);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 1, el, fac, TG.p);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 2, el, fac, GGt.p);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 3, el, fac, GI.p);
+    TLS_LAUNCH_CHECK();
+    // Tm = L_GG^{-T} L_TG^T ; F += L_GI^T Tm
     std::vector<TriDesc> td;
     for (int i = 0; i < N; i++)
-      if (h_kf[i] > 0) td.push_back(TriDesc{nT[i], h_kf[i], oTT[i], oZv[i], (int64_t)nT[i]});
-    batched_trsm<double>(s, td, UPPER_BWD, LTTt.p, zv.p, c->errflag.p);
-    hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
-    TLS_LAUNCH_CHECK();
-    // column j of V for every subdomain lives in padded local vector j
-    int kfm = 0;
-    for (int i = 0; i < N; i++) kfm = std::max(kfm, h_kf[i]);
-    XV.alloc((size_t)std::max(kfm, 1) * c->sum_M);
-    TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max(kfm, 1) * c->sum_M, s));
+      if (d.kreq[i] > 0 && d.nG[i] > 0) td.push_back(TriDesc{d.nG[i], d.nT[i], d.oGG[i], d.oTG[i], (int64_t)d.nG[i]});
+    batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
     std::vector<GemmDesc> gd;
     for (int i = 0; i < N; i++)
-      if (h_kf[i] > 0) gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], nI[i], nT[i], oF[i], oZv[i], c->h_voff[i], c->sum_M});
-    batched_gemm<T>(s, gd, false, false, F.p, wT.p, XV.p, T(1), T(0));
-    F.release();
-    // x = L^{-T} [V; 0] per column with the persistent solve: rows I = L_II^{-T} V
-    for (int j = 0; j < kfm; j++) local_backward(c, XV.p + (size_t)j * c->sum_M, c->zero_int.p);
-    TLS_HIP(hipStreamSynchronize(s));
-  } else {
-    // left singular directions: V = H v
-    hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
-    TLS_LAUNCH_CHECK();
-    std::vector<GemmDesc> gd;
-    for (int i = 0; i < N; i++) {
-      const int M = c->h_nt[i] * TS;
-      if (h_kf[i] > 0) gd.push_back(GemmDesc{nI[i], h_kf[i], nT[i], M, nT[i], oXH[i], oZv[i], oXV[i], (int64_t)M});
-    }
-    batched_gemm<T>(s, gd, false, false, XH.p, wT.p, XV.p, T(1), T(0));
-    XH.release();
+      if (d.kreq[i] > 0 && d.nG[i] > 0)
+        gd.push_back(GemmDesc{d.nI[i], d.nT[i], d.nG[i], d.nG[i], d.nG[i], d.oGI[i], d.oTG[i], d.oF[i],
+                              (int64_t)d.nI[i]});
+    batched_gemm<T>(s, gd, true, false, GI.p, TG.p, F.p, T(1), T(1));
+    GI.release();
+    TG.release();
+    GGt.release();
   }
-  // ---- orthonormalize into Z --------------------------------------------------
+  // K = F^T F
+  {
+    std::vector<GemmDesc> gd;
+    for (int i = 0; i < N; i++)
+      if (d.kreq[i] > 0)
+        gd.push_back(GemmDesc{d.nT[i], d.nT[i], d.nI[i], d.nI[i], d.nI[i], d.oF[i], d.oF[i], d.oTT[i],
+                              (int64_t)d.nT[i]});
+    batched_gemm<T>(s, gd, true, false, F.p, F.p, K.p, T(1), T(0));
+  }
+  // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)d.oTT[N], K.p, C64.p);
+  TLS_LAUNCH_CHECK();
+  K.release();
+  std::vector<TriDesc> td;
+  for (int i = 0; i < N; i++)
+    if (d.kreq[i] > 0) td.push_back(TriDesc{d.nT[i], d.nT[i], d.oTT[i], d.oTT[i], (int64_t)d.nT[i]});
+  batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64.p, c->errflag.p);
+  hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, C64.p, C64b.p, 0);
+  TLS_LAUNCH_CHECK();
+  batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64b.p, c->errflag.p);
+  hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, C64b.p, C64.p, 1);
+  TLS_LAUNCH_CHECK();
+  if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_NOT_SPD, "zero pivot in a Schur-complement block");
+  LTT.release();
+  C64b.release();
+  DBuf<double> zv;
+  PassEig e = run_subspace(c, d, dv, C64, zv, thresh);
+  C64.release();
+  // w_T = L_TT^{-T} z ; V = F w_T into columns colbase[i] + j of XV
+  std::vector<TriDesc> tw;
+  for (int i = 0; i < N; i++)
+    if (e.kf[i] > 0) tw.push_back(TriDesc{d.nT[i], e.kf[i], d.oTT[i], d.oZv[i], (int64_t)d.nT[i]});
+  batched_trsm<double>(s, tw, UPPER_BWD, LTTt.p, zv.p, c->errflag.p);
+  DBuf<T> wT;
+  wT.alloc(std::max<int64_t>(d.oZv[N], 1));
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)d.oZv[N], zv.p, wT.p);
+  TLS_LAUNCH_CHECK();
+  std::vector<GemmDesc> gd;
+  for (int i = 0; i < N; i++)
+    if (e.kf[i] > 0)
+      gd.push_back(GemmDesc{d.nI[i], e.kf[i], d.nT[i], d.nI[i], d.nT[i], d.oF[i], d.oZv[i],
+                            c->h_voff[i] + (int64_t)colbase[i] * c->sum_M, c->sum_M});
+  batched_gemm<T>(s, gd, false, false, F.p, wT.p, XV, T(1), T(0));
+  TLS_HIP(hipStreamSynchronize(s));
+  return e;
+}
+
+// Orthonormalize the columns of every subdomain into Z (fp64) and record
+// the kept columns, their eigenvalues and which eigenproblem each came from.
+template <class T>
+static void finish_basis(tls_ctx* c, const std::vector<int>& ncols, const std::vector<double>& colval,
+                         const std::vector<int>& colsrc, const std::vector<int64_t>& colval_off,
+                         const DBuf<int64_t>& d_xoff, int64_t colstride, const T* XV) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int64_t> oZ(N + 1, 0);
+  for (int i = 0; i < N; i++) oZ[i + 1] = oZ[i] + (int64_t)c->h_nI[i] * ncols[i];
+  DBuf<int64_t> d_oZ;
+  DBuf<int> d_nI, kf, kfin, keep;
+  d_oZ.upload(oZ, s);
+  d_nI.upload(std::vector<int>(c->h_nI.begin(), c->h_nI.end()), s);
+  kf.upload(ncols, s);
   DBuf<double> Zt;
-  DBuf<int> kfin, keep;
   Zt.alloc(std::max<int64_t>(oZ[N], 1));
   kfin.alloc(N);
-  keep.alloc((size_t)N * PMAX);
-  const int64_t colstride = general ? 0 : c->sum_M;
-  hipLaunchKernelGGL(k_orth<T>, dim3(N), dim3(256), 0, s, d_nI.p, kfound.p, c->d_voff.p,
-                     general ? d_oXV.p : c->d_voff.p, c->d_nt.p, colstride, XV.p,
-                     c->opt.jacobi_scale ? c->scale.p : nullptr, d_oZ.p, Zt.p, kfin.p, keep.p);
+  keep.alloc((size_t)N * KMAX);
+  hipLaunchKernelGGL(k_orth<T>, dim3(N), dim3(256), 0, s, d_nI.p, kf.p, c->d_voff.p, d_xoff.p, c->d_nt.p, colstride,
+                     XV, c->opt.jacobi_scale ? c->scale.p : nullptr, d_oZ.p, Zt.p, kfin.p, keep.p);
   TLS_LAUNCH_CHECK();
   auto h_kfin = download(kfin.p, N, s);
-  auto h_keep = download(keep.p, (size_t)N * PMAX, s);
+  auto h_keep = download(keep.p, (size_t)N * KMAX, s);
   c->h_zcol.assign(N + 1, 0);
   c->h_zoff = oZ;
   c->h_eig.clear();
+  c->h_zsrc.clear();
   for (int i = 0; i < N; i++) {
     c->h_zcol[i + 1] = c->h_zcol[i] + h_kfin[i];
     for (int a = 0; a < h_kfin[i]; a++) {
-      double th = h_th[oth[i] + h_keep[(size_t)i * PMAX + a]];
-      c->h_eig.push_back(general ? std::sqrt(std::max(th, 0.0)) : th);
+      const int src = h_keep[(size_t)i * KMAX + a];
+      c->h_eig.push_back(colval[colval_off[i] + src]);
+      c->h_zsrc.push_back(colsrc[colval_off[i] + src]);
     }
   }
   c->nC = c->h_zcol[N];
@@ -781,21 +768,216 @@ static void basis_impl(tls_ctx* c, T* fac) {
   TLS_HIP(hipStreamSynchronize(s));
 }
 
-void build_coarse_basis(tls_ctx* c) {
-  if (c->nev == 0 || c->delta == 0) {
-    c->nC = 0;
-    c->h_zcol.assign(c->N + 1, 0);
-    c->h_zoff.assign(c->N + 1, 0);
-    c->zcol.upload(c->h_zcol, c->stream);
-    c->zoff.upload(c->h_zoff, c->stream);
-    c->Z.alloc(1);
+static void empty_basis(tls_ctx* c) {
+  c->nC = 0;
+  c->h_zcol.assign(c->N + 1, 0);
+  c->h_zoff.assign(c->N + 1, 0);
+  c->h_eig.clear();
+  c->h_zsrc.clear();
+  c->zcol.upload(c->h_zcol, c->stream);
+  c->zoff.upload(c->h_zoff, c->stream);
+  c->Z.alloc(1);
+}
+
+// SPD: eq. gevpsvd (blocks [I, G, T] with G = Gamma_{1:delta-1},
+// T = Gamma_delta) and, when nev1 > 0, eq. uppergevp. For the latter, with
+// Omega_i = [I, O] and L = [[L_II, 0], [L_OI, L_OO]], the nonzero part of
+// D_i A_ii D_i u = lambda A_ii u is, after u = L^{-T} v, the matrix V V^T
+// with V = [I; -L_OO^{-1} L_OI]: lambda = 1 + kappa where kappa are the
+// eigenvalues of C1 = L_OO^{-1} L_OI L_OI^T L_OO^{-T}, and rows I of the
+// eigenvector are proportional to L_II^{-T} L_OI^T L_OO^{-T} y. That is
+// the same pass with G empty and T = O (F = -L_OI^T); lambda > nu keeps
+// kappa > nu - 1.
+template <class T>
+static void basis_spd(tls_ctx* c, T* fac) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int> nG2(N), nG1(N, 0);
+  for (int i = 0; i < N; i++) nG2[i] = c->h_nP[i] - c->h_nI[i];
+  const PassDims d2 = pass_dims(c, nG2, c->nev, false);
+  const int nev1 = c->opt.nev1;
+  const PassDims d1 = pass_dims(c, nG1, nev1, false);
+  if (d2.kmax == 0 && d1.kmax == 0) {
+    empty_basis(c);
     return;
   }
-  if (c->opt.nev1 > 0) fail(TLS_E_ARG, "nev1 > 0 (eq. uppergevp vectors) is not available in this build");
-  if (c->fp32)
-    basis_impl<float>(c, c->fac32.p);
-  else
-    basis_impl<double>(c, c->fac64.p);
+  int kcols = 0;
+  for (int i = 0; i < N; i++) kcols = std::max(kcols, d2.kreq[i] + d1.kreq[i]);
+  DBuf<T> XV;
+  XV.alloc((size_t)std::max(kcols, 1) * c->sum_M);
+  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max(kcols, 1) * c->sum_M, s));
+  TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
+  const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;  // lambda^2 > tau^2
+  PassEig e2, e1;
+  e2.kf.assign(N, 0);
+  e1.kf.assign(N, 0);
+  if (d2.kmax > 0) e2 = spd_pass<T>(c, fac, d2, tau2, std::vector<int>(N, 0), XV.p);
+  if (d1.kmax > 0) {
+    const double nu = c->opt.nu > 0 ? c->opt.nu : 1.0;
+    e1 = spd_pass<T>(c, fac, d1, nu - 1.0, e2.kf, XV.p);  // lambda = 1 + kappa > nu
+  }
+  c->eig_resid_max = std::max(e2.resid_max, e1.resid_max);
+  c->eig_iters_max = std::max(e2.iters_max, e1.iters_max);
+  // x = L^{-T} [V; 0] per column with the persistent solve: rows I = L_II^{-T} V
+  std::vector<int> ncols(N);
+  int kfm = 0;
+  for (int i = 0; i < N; i++) {
+    ncols[i] = e2.kf[i] + e1.kf[i];
+    kfm = std::max(kfm, ncols[i]);
+  }
+  for (int j = 0; j < kfm; j++) local_backward(c, XV.p + (size_t)j * c->sum_M, c->zero_int.p);
+  // eigenvalue and source of every column: lambda^2 (eq. gevpsvd) or lambda (eq. uppergevp)
+  std::vector<double> colval;
+  std::vector<int> colsrc;
+  std::vector<int64_t> coff(N + 1, 0);
+  for (int i = 0; i < N; i++) {
+    for (int j = 0; j < e2.kf[i]; j++) {
+      colval.push_back(e2.theta[d2.oth[i] + j]);
+      colsrc.push_back(0);
+    }
+    for (int j = 0; j < e1.kf[i]; j++) {
+      colval.push_back(1.0 + e1.theta[d1.oth[i] + j]);
+      colsrc.push_back(1);
+    }
+    coff[i + 1] = colval.size();
+  }
+  finish_basis<T>(c, ncols, colval, colsrc, coff, c->d_voff, c->sum_M, XV.p);
+}
+
+// General A (Section 6): H = rows I of -A_{O'O'}^{-1} A_{O'T}; the dominant
+// right singular vectors v of H from the Gram H^T H, coarse vectors H v.
+template <class T>
+static void basis_general(tls_ctx* c, T* fac) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int> nGv(N);
+  for (int i = 0; i < N; i++) nGv[i] = c->h_nP[i] - c->h_nI[i];
+  const PassDims d = pass_dims(c, nGv, c->nev, true);
+  if (d.kmax == 0) {
+    empty_basis(c);
+    return;
+  }
+  const std::vector<int>& nI = d.nI;
+  const std::vector<int>& nG = d.nG;
+  const std::vector<int>& nT = d.nT;
+  const std::vector<int>& kreq = d.kreq;
+  const std::vector<int64_t>& oGI = d.oGI;
+  const std::vector<int64_t>& oTG = d.oTG;
+  const std::vector<int64_t>& oGG = d.oGG;
+  const std::vector<int64_t>& oTT = d.oTT;
+  const std::vector<int64_t>& oZv = d.oZv;
+  std::vector<int> nqH(N, 0);
+  std::vector<int64_t> oXH(N + 1, 0), oXV(N + 1, 0);
+  for (int i = 0; i < N; i++) {
+    const int64_t M = (int64_t)c->h_nt[i] * TS;
+    nqH[i] = kreq[i] > 0 ? (nT[i] + TS - 1) / TS : 0;
+    oXH[i + 1] = oXH[i] + M * TS * nqH[i];
+    oXV[i + 1] = oXV[i] + M * TS * (kreq[i] > 0 ? 1 : 0);
+  }
+  PassDev dv;
+  dv.upload(d, oXH, s);
+  DBuf<int64_t> d_oXV;
+  d_oXV.upload(oXV, s);
+  const EigLayout el = dv.layout(c);
+  const dim3 eg(64, N);
+  TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
+  DBuf<T> GI, TG, GGt, K, XH;
+  DBuf<double> C64;
+  K.alloc(std::max<int64_t>(oTT[N], 1));
+  C64.alloc(std::max<int64_t>(oTT[N], 1));
+  if (oGG[N] > 0) {
+    GI.alloc(oGI[N]);
+    TG.alloc(oTG[N]);
+    GGt.alloc(oGG[N]);
+  }
+  // with A_ii = L U ordered [I, G, T]: H = U_II^{-1} (-U_IT + U_IG U_GG^{-1} U_GT)
+  XH.alloc(std::max<int64_t>(oXH[N], 1));
+  TLS_HIP(hipMemsetAsync(XH.p, 0, sizeof(T) * std::max<int64_t>(oXH[N], 1), s));
+  hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 9, el, fac, XH.p);
+  TLS_LAUNCH_CHECK();
+  if (oGG[N] > 0) {
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 6, el, fac, TG.p);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 7, el, fac, GGt.p);
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 8, el, fac, GI.p);
+    TLS_LAUNCH_CHECK();
+    std::vector<TriDesc> td;
+    for (int i = 0; i < N; i++)
+      if (kreq[i] > 0) td.push_back(TriDesc{nG[i], nT[i], oGG[i], oTG[i], (int64_t)nG[i]});
+    batched_trsm<T>(s, td, UPPER_BWD, GGt.p, TG.p, c->errflag.p);
+    std::vector<GemmDesc> gd;
+    for (int i = 0; i < N; i++)
+      if (kreq[i] > 0 && nG[i] > 0)
+        gd.push_back(GemmDesc{nI[i], nT[i], nG[i], nI[i], nG[i], oGI[i], oTG[i], oXH[i],
+                              (int64_t)c->h_nt[i] * TS});
+    batched_gemm<T>(s, gd, false, false, GI.p, TG.p, XH.p, T(1), T(1));
+  }
+  if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_SINGULAR, "zero pivot in a local U_GG block");
+  // H = U_II^{-1} X: the backward solve on the whole factor leaves rows G, T zero
+  local_trsm_backward(c, XH.p, nqH, oXH);
+  // K = H^T H
+  std::vector<GemmDesc> gd;
+  for (int i = 0; i < N; i++) {
+    const int M = c->h_nt[i] * TS;
+    if (kreq[i] > 0) gd.push_back(GemmDesc{nT[i], nT[i], nI[i], M, M, oXH[i], oXH[i], oTT[i], (int64_t)nT[i]});
+  }
+  batched_gemm<T>(s, gd, true, false, XH.p, XH.p, K.p, T(1), T(0));
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)oTT[N], K.p, C64.p);
+  TLS_LAUNCH_CHECK();
+  K.release();
+  GI.release();
+  TG.release();
+  GGt.release();
+  // sigma^2 > tau^2 when a threshold is given
+  const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;
+  DBuf<double> zv;
+  PassEig e = run_subspace(c, d, dv, C64, zv, tau2);
+  C64.release();
+  c->eig_resid_max = e.resid_max;
+  c->eig_iters_max = e.iters_max;
+  // left singular directions: V = H v
+  DBuf<T> wT, XV;
+  wT.alloc(std::max<int64_t>(oZv[N], 1));
+  XV.alloc(std::max<int64_t>(oXV[N], 1));
+  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
+  TLS_LAUNCH_CHECK();
+  std::vector<GemmDesc> gv;
+  for (int i = 0; i < N; i++) {
+    const int M = c->h_nt[i] * TS;
+    if (e.kf[i] > 0) gv.push_back(GemmDesc{nI[i], e.kf[i], nT[i], M, nT[i], oXH[i], oZv[i], oXV[i], (int64_t)M});
+  }
+  batched_gemm<T>(s, gv, false, false, XH.p, wT.p, XV.p, T(1), T(0));
+  XH.release();
+  // the reported value of a column is sigma = sqrt(eigenvalue of H^T H)
+  std::vector<double> colval;
+  std::vector<int> colsrc;
+  std::vector<int64_t> coff(N + 1, 0);
+  for (int i = 0; i < N; i++) {
+    for (int j = 0; j < e.kf[i]; j++) {
+      colval.push_back(std::sqrt(std::max(e.theta[d.oth[i] + j], 0.0)));
+      colsrc.push_back(2);
+    }
+    coff[i + 1] = colval.size();
+  }
+  finish_basis<T>(c, e.kf, colval, colsrc, coff, d_oXV, 0, XV.p);
+}
+
+void build_coarse_basis(tls_ctx* c) {
+  if ((c->nev == 0 && c->opt.nev1 == 0) || c->delta == 0) {
+    empty_basis(c);
+    return;
+  }
+  if (c->kind == 1) {
+    if (c->fp32)
+      basis_general<float>(c, c->fac32.p);
+    else
+      basis_general<double>(c, c->fac64.p);
+  } else {
+    if (c->fp32)
+      basis_spd<float>(c, c->fac32.p);
+    else
+      basis_spd<double>(c, c->fac64.p);
+  }
 }
 
 }  // namespace tls

@@ -79,3 +79,26 @@ def test_setup_error_without_pointers(lib):
     st = lib.tls_setup(0, 0, None, None, None, None, 1, 1, 1, None, ctypes.byref(out))
     assert st == _lib.TLS_E_ARG and out.value is None
     assert "positive" in _lib.last_error(None)
+
+
+def test_setup_rejects_nev1_for_general_matrices(lib):
+    """eq. uppergevp vectors are defined for SPD A only: nev1 > 0 with
+    matrix_kind = 1 is an argument error, raised before any device work
+    (the host arrays below are never read)."""
+    import ctypes
+
+    import numpy as np
+    from paper_2401_03915_amd import _lib
+    opt = _lib.tls_options()
+    lib.tls_default_options(ctypes.byref(opt))
+    opt.matrix_kind = 1
+    opt.nev1 = 2
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    ci = np.array([0, 1], dtype=np.int32)
+    val = np.ones(2)
+    part = np.array([0, 1], dtype=np.int32)
+    out = ctypes.c_void_p()
+    st = lib.tls_setup(2, 2, rp.ctypes.data, ci.ctypes.data, val.ctypes.data, part.ctypes.data, 2, 1, 1,
+                       ctypes.byref(opt), ctypes.byref(out))
+    assert st == _lib.TLS_E_ARG and out.value is None
+    assert "SPD" in _lib.last_error(None)

@@ -130,6 +130,99 @@ def test_coarse_eigen_parity(delta):
     pc.close()
 
 
+def test_gevp1_eigen_parity():
+    """eq. uppergevp vectors alone (nev = 0, nev1 > 0, delta = 2): the kept
+    eigenvalues lambda > 1 against the oracle's dense solve of the full
+    pencil, and the spans of D_i u where the gap allows."""
+    A = poisson_2d(48)
+    part = box_partition_2d(48, 48, 3, 3)
+    nev1, delta = 6, 2
+    say("gevp1 parity", delta)
+    pc = _pc(A, part, delta, 0, nev1=nev1)
+    ex = pc.export(Z=True)
+    zc = ex["zcol_ptr"]
+    assert np.all(ex["zsrc"] == 1)
+    for i in range(9):
+        s = schwarz.overlap(A, part, i, delta)
+        Aii = schwarz.local_matrix(A, s)
+        lam_all, U = schwarz.gevp1(Aii, s, s.size, nu=1.0, dense=True)
+        lam_all = lam_all[lam_all > 1 + 1e-10]
+        k = zc[i + 1] - zc[i]
+        assert k == min(nev1, lam_all.size)
+        lam_gpu = ex["eigvals"][zc[i]:zc[i + 1]]
+        assert np.allclose(lam_gpu, lam_all[:k], rtol=1e-8, atol=1e-12), (lam_gpu, lam_all[:k])
+        if lam_all.size > k and lam_all[k - 1] / lam_all[k] >= 1 + 1e-3:
+            Zi, _, _ = schwarz.coarse_block(Aii, s, 0, nev1, True)
+            Zg = ex["Z"][s.idx[:s.n_interior]][:, zc[i]:zc[i + 1]]
+            cos = principal_cosines(Zi, Zg)
+            assert np.all(cos >= 1 - 1e-10), cos
+    pc.close()
+
+
+def test_gevp1_delta1_is_one_plus_gevp2():
+    """For delta = 1 the eq. uppergevp pairs above 1 are the eq. gevpsvd pairs
+    with lambda_1 = 1 + lambda_2^2 and the same vectors (block algebra of the
+    two pencils when Omega' = I_i)."""
+    A, part = _hc_problem(64, 3, seed=5)
+    N = int(part.max()) + 1
+    say("gevp1 vs gevp2 delta 1")
+    p2 = _pc(A, part, 1, 5)
+    p1 = _pc(A, part, 1, 0, nev1=5)
+    e2, e1 = p2.export(Z=True), p1.export(Z=True)
+    assert np.array_equal(e2["zcol_ptr"], e1["zcol_ptr"])
+    assert np.allclose(e1["eigvals"], 1.0 + e2["eigvals"], rtol=1e-9)
+    zc = e2["zcol_ptr"]
+    for i in range(N):
+        lo, hi = zc[i], zc[i + 1]
+        rows = np.flatnonzero(part == i)
+        cos = principal_cosines(e2["Z"][rows][:, lo:hi], e1["Z"][rows][:, lo:hi])
+        assert np.all(cos >= 1 - 1e-9), cos
+    p1.close()
+    p2.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 5e-3)])
+def test_both_eigenproblems_apply_parity(precision, tol):
+    """Z_i = orth([D_i Pi_i W_i, D_i Z_i]) with nev = nev1 = 4 (eq. coarse_space_2):
+    per-subdomain span against the oracle (FP64), then the apply with the
+    library's basis imported into the oracle."""
+    torch = torch_cuda()
+    A = poisson_2d(48)
+    part = box_partition_2d(48, 48, 3, 3)
+    say("gevp1 + gevp2 apply", precision)
+    pc = _pc(A, part, 2, 4, nev1=4, precision=precision)
+    ex = pc.export(Z=True)
+    zc = ex["zcol_ptr"]
+    assert set(np.unique(ex["zsrc"])) == {0, 1}
+    if precision == 0:
+        for i in range(9):
+            s = schwarz.overlap(A, part, i, 2)
+            Aii = schwarz.local_matrix(A, s)
+            lam2, _ = schwarz.gevp2(Aii, s, s.size)
+            lam1, _ = schwarz.gevp1(Aii, s, s.size, nu=1.0, dense=True)
+            lam1 = lam1[lam1 > 1 + 1e-10]
+            gap_ok = (lam2.size <= 4 or lam2[3] / lam2[4] >= 1 + 1e-3) and \
+                     (lam1.size <= 4 or lam1[3] / lam1[4] >= 1 + 1e-3)
+            if gap_ok:
+                Zi, _, _ = schwarz.coarse_block(Aii, s, 4, 4, True)
+                Zg = ex["Z"][s.idx[:s.n_interior]][:, zc[i]:zc[i + 1]]
+                assert Zg.shape[1] == Zi.shape[1]
+                cos = principal_cosines(Zi, Zg)
+                assert np.all(cos >= 1 - 1e-9), cos
+    h = oracle.setup(A, part, 2, 4, nev1=4, Z=ex["Z"])
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for _ in range(5):
+        r = rng.standard_normal(A.shape[0])
+        z = pc.apply(to_dev(r))
+        torch.cuda.synchronize()
+        z_ref = oracle.apply(h, r)
+        worst = max(worst, np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref))
+    say("  worst apply error", worst)
+    assert worst <= tol
+    pc.close()
+
+
 # ---------------------------------------------------------------------------
 # apply (Remark after Section 4.4)
 # ---------------------------------------------------------------------------
