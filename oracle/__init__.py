@@ -16,6 +16,8 @@ It computes the paper's definitions literally, in float64, with NumPy/SciPy:
   variant (Section 6), the coarse space (eq. coarse_space_2), the Galerkin
   coarse operator and the two-level apply (Remark after Section 4.4);
 * ``krylov``   - PCG and right-preconditioned flexible GMRES;
+* ``gnn``      - forward, loss and backward of the warm-start network of
+  the local eigensolver (not in the paper; see its docstring);
 * ``theory``   - brute-force objects for tiny inputs: the SPSD splitting
   (Lemma spsd_splitting), colors k_c, lambda_* (eq. lambda_star), the
   condition-number bounds (Theorems upper_bound_1 and upper_bound_2) and the
@@ -25,5 +27,5 @@ Parity status of each function is stated in its docstring; functions whose
 result nothing independent fixes say "parity unpinned".
 """
 
-from . import krylov, schwarz, theory  # noqa: F401
+from . import gnn, krylov, schwarz, theory  # noqa: F401
 from .schwarz import Handle, apply, setup, solve  # noqa: F401
