@@ -45,6 +45,25 @@ extern "C" {
 
 typedef struct tls_ctx tls_ctx;
 
+/* Learned warm start of the local eigensolver (not part of the paper).
+ * A message-passing network on the graph of each A_ii (edges
+ * e_ab = |a_ab| / sqrt(|a_aa| |a_bb|), 4 input features per node: 1,
+ * in I_i, in Gamma_{i,delta}, log10 of the relative diagonal) with
+ * TLS_GNN_LAYERS layers of width TLS_GNN_HIDDEN,
+ * H_l = tanh(E H_{l-1} Theta_l + H_{l-1} Phi_l + b_l), and a linear read-out
+ * X = H_L Omega of c_out columns, predicts the rows Gamma_{i,delta} of the
+ * eq. gevpsvd eigenvectors; the subspace iteration starts from it.
+ * Weights are one FP32 vector: for each layer Theta_l (c_{l-1} x HIDDEN,
+ * row major), Phi_l (same), b_l (HIDDEN); then Omega (HIDDEN x c_out);
+ * c_0 = TLS_GNN_FEATURES. */
+#define TLS_GNN_LAYERS 4
+#define TLS_GNN_FEATURES 4
+#define TLS_GNN_HIDDEN 32
+#define TLS_GNN_NWEIGHTS(c_out)                                              \
+  (2 * TLS_GNN_FEATURES * TLS_GNN_HIDDEN + TLS_GNN_HIDDEN +                  \
+   (TLS_GNN_LAYERS - 1) * (2 * TLS_GNN_HIDDEN * TLS_GNN_HIDDEN + TLS_GNN_HIDDEN) + \
+   TLS_GNN_HIDDEN * (c_out))
+
 typedef enum {
   TLS_OK = 0,
   TLS_E_ARG = 1,       /* invalid argument or malformed input              */
@@ -93,6 +112,15 @@ typedef struct {
                            the fastest (ignored when solve_wgs or solve_order is set) */
   const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
                              NULL = no persistence. A cached pick is reused without timing. */
+  /* Learned warm start (SPD only): host array of TLS_GNN_NWEIGHTS(gnn_c_out)
+   * floats, read during tls_setup; NULL = random start (default). The first
+   * min(gnn_c_out, p) columns of the eq. gevpsvd start block come from the
+   * network, the rest are random. gnn_c_out in [1, 64]. */
+  const float* gnn_weights;
+  int32_t gnn_c_out;
+  /* 1: keep what tls_gnn_forward / tls_gnn_loss_grad need (the local graphs
+   * and the eq. gevpsvd eigenvectors as training targets). SPD, nev > 0. */
+  int32_t gnn_train;
   void* stream;         /* hipStream_t */
 } tls_options;
 
@@ -107,7 +135,10 @@ typedef struct {
   int64_t factor_bytes;       /* bytes of the stored local factors           */
   int32_t max_m;              /* max_i #Omega_i                              */
   int32_t min_m;              /* min_i #Omega_i                              */
-  double t_setup[8];          /* ms: overlap, gather, factor, eigen, coarse basis, A_0, A_0 factor, total */
+  double t_setup[8];          /* ms: [0] overlap, [1] gather, [2] factorization and solve
+                                 plans, [3] coarse basis (eigensolves, orthonormalization),
+                                 [4] learned warm start (inside [3]), [5] A_0 and its
+                                 factorization, [6] unused, [7] total */
   double t_solve;             /* ms of the last tls_solve                    */
   int32_t iters;              /* iterations of the last tls_solve            */
   double relres;              /* true relative residual of the last solve    */
@@ -184,6 +215,23 @@ tls_status tls_local_solve(tls_ctx* c, int32_t i, const double* b, double* x);
 /* Last error message of the context (or of the calling thread's last failed
  * tls_setup when c is NULL). Never NULL. */
 const char* tls_last_error(const tls_ctx* c);
+
+/* Learned warm start, forward pass: X = network output on every local
+ * graph of the context. weights: host, TLS_GNN_NWEIGHTS(c_out) floats.
+ * X: host, (sum #Omega_i) x c_out floats, row-major, rows in the order of
+ * tls_export's sub_idx. Needs a context set up with gnn_train = 1 or with
+ * gnn_weights. */
+tls_status tls_gnn_forward(tls_ctx* c, const float* weights, int32_t c_out, float* X);
+
+/* Learned warm start, training step: the mean over subdomains of
+ *   f_i = -(1/k_i) tr(G^{-1} X_T^T Q_i Q_i^T X_T),  G = X_T^T X_T,
+ * where X_T are the rows Gamma_{i,delta} of the network output and Q_i an
+ * orthonormal basis of the same rows of the context's own top-k_i
+ * eq. gevpsvd eigenvectors (kept by a setup with gnn_train = 1), and its
+ * gradient with respect to the weights (forward and backward passes on the
+ * device). weights, grad: host arrays of TLS_GNN_NWEIGHTS(c_out) floats;
+ * loss: host scalar. TLS_E_STATE without targets. */
+tls_status tls_gnn_loss_grad(tls_ctx* c, const float* weights, int32_t c_out, float* grad, double* loss);
 
 /* Free everything the context owns. NULL is ignored. */
 void tls_destroy(tls_ctx* c);

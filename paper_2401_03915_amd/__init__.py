@@ -15,11 +15,13 @@ from __future__ import annotations
 import numpy as np
 
 from . import _lib
-from ._lib import (TlsError, tls_apply, tls_default_options, tls_destroy, tls_export, tls_info,  # noqa: F401
-                   tls_local_solve, tls_setup, tls_solve, tls_spmv)
+from ._lib import (TlsError, gnn_n_weights, tls_apply, tls_default_options, tls_destroy,  # noqa: F401
+                   tls_export, tls_gnn_forward, tls_gnn_loss_grad, tls_info, tls_local_solve, tls_setup, tls_solve,
+                   tls_spmv)
 
 __all__ = ["Preconditioner", "TlsError", "tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve",
-           "tls_info", "tls_export", "tls_local_solve", "tls_destroy"]
+           "tls_info", "tls_export", "tls_local_solve", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_destroy",
+           "gnn_n_weights"]
 
 
 def _torch():
@@ -34,8 +36,10 @@ class Preconditioner:
 
     Options are the fields of ``tls_options`` (precision, matrix_kind, nev1,
     tau, nu, restart, maxit, eig_maxit, eig_tol, eig_oversample, seed,
-    use_graph, flexible, jacobi_scale). ``stream`` may be a torch.cuda.Stream
-    on which all library work is ordered.
+    use_graph, flexible, jacobi_scale, gnn_train, ...). ``gnn_weights`` takes a
+    float32 array of trained warm-start weights (its ``gnn_c_out`` is
+    inferred from the length). ``stream`` may be a torch.cuda.Stream on which
+    all library work is ordered.
     """
 
     def __init__(self, A, part, overlap: int, nev: int, device: str = "cuda:0", stream=None, **options):
@@ -53,10 +57,19 @@ class Preconditioner:
         self._val = torch.as_tensor(np.asarray(A.data, dtype=np.float64), device=dev)
         self._part = torch.as_tensor(np.asarray(part, dtype=np.int32), device=dev)
         opt = tls_default_options()
+        w = options.pop("gnn_weights", None)
         for k, v in options.items():
             if not hasattr(opt, k) or k == "stream":
                 raise TypeError(f"unknown option {k}")
             setattr(opt, k, v)
+        self._gnn_w = None
+        if w is not None:
+            self._gnn_w = np.ascontiguousarray(w, dtype=np.float32)
+            c_out = (self._gnn_w.size - gnn_n_weights(0)) // _lib.GNN_HIDDEN
+            if gnn_n_weights(c_out) != self._gnn_w.size:
+                raise ValueError("gnn_weights has a length that no c_out matches")
+            opt.gnn_weights = self._gnn_w.ctypes.data
+            opt.gnn_c_out = c_out
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -120,6 +133,20 @@ class Preconditioner:
         if A0:
             out["A0"] = out["A0"].T.copy()  # the C side writes column-major
         return out
+
+    def gnn_forward(self, weights: np.ndarray, c_out: int) -> np.ndarray:
+        """Network output on every local graph: (sum #Omega_i) x c_out, rows in sub_idx order."""
+        total = int(self.export()["sub_ptr"][-1])
+        X = np.zeros((total, c_out), dtype=np.float32)
+        tls_gnn_forward(self.ctx, np.ascontiguousarray(weights, dtype=np.float32), c_out, X)
+        return X
+
+    def gnn_loss_grad(self, weights: np.ndarray, c_out: int):
+        """(loss, gradient) of the warm-start network against this context's targets."""
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        g = np.zeros_like(w)
+        loss = tls_gnn_loss_grad(self.ctx, w, c_out, g)
+        return loss, g
 
     def local_solve(self, i: int, b: np.ndarray) -> np.ndarray:
         b = np.ascontiguousarray(b, dtype=np.float64)

@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtls.so")
 
@@ -19,7 +21,17 @@ STATUS_NAMES = {0: "TLS_OK", 1: "TLS_E_ARG", 2: "TLS_E_NOT_SPD", 3: "TLS_E_SINGU
 
 # Names declared in include/tls.h (checked by the tests against the header).
 EXPORTED = ["tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve", "tls_info", "tls_export",
-            "tls_local_solve", "tls_last_error", "tls_destroy"]
+            "tls_local_solve", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_last_error", "tls_destroy"]
+
+GNN_LAYERS = 4
+GNN_FEATURES = 4
+GNN_HIDDEN = 32
+
+
+def gnn_n_weights(c_out: int) -> int:
+    """TLS_GNN_NWEIGHTS(c_out) of include/tls.h."""
+    return (2 * GNN_FEATURES * GNN_HIDDEN + GNN_HIDDEN
+            + (GNN_LAYERS - 1) * (2 * GNN_HIDDEN * GNN_HIDDEN + GNN_HIDDEN) + GNN_HIDDEN * c_out)
 
 
 class TlsError(RuntimeError):
@@ -49,6 +61,9 @@ class tls_options(C.Structure):
         ("solve_order", C.c_int32),
         ("autotune", C.c_int32),
         ("tune_cache", C.c_char_p),
+        ("gnn_weights", C.c_void_p),
+        ("gnn_c_out", C.c_int32),
+        ("gnn_train", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -110,6 +125,10 @@ def lib() -> C.CDLL:
         L.tls_export.restype = C.c_int
         L.tls_local_solve.argtypes = [vp, i32, vp, vp]
         L.tls_local_solve.restype = C.c_int
+        L.tls_gnn_forward.argtypes = [vp, vp, i32, vp]
+        L.tls_gnn_forward.restype = C.c_int
+        L.tls_gnn_loss_grad.argtypes = [vp, vp, i32, vp, C.POINTER(C.c_double)]
+        L.tls_gnn_loss_grad.restype = C.c_int
         L.tls_last_error.argtypes = [vp]
         L.tls_last_error.restype = C.c_char_p
         L.tls_destroy.argtypes = [vp]
@@ -181,6 +200,22 @@ def tls_export(ctx, **bufs):
 
 def tls_local_solve(ctx, i, b, x):
     return check(lib().tls_local_solve(ctx, i, b.ctypes.data, x.ctypes.data), ctx)
+
+
+def tls_gnn_forward(ctx, weights, c_out, X):
+    """weights: float32 numpy (gnn_n_weights(c_out)); X: float32 numpy (sum m_i, c_out), filled."""
+    assert weights.dtype == np.float32 and X.dtype == np.float32 and X.flags.c_contiguous
+    assert weights.size == gnn_n_weights(c_out)
+    return check(lib().tls_gnn_forward(ctx, weights.ctypes.data, c_out, X.ctypes.data), ctx)
+
+
+def tls_gnn_loss_grad(ctx, weights, c_out, grad):
+    """Returns the loss; grad (float32 numpy, same size as weights) is filled."""
+    assert weights.dtype == np.float32 and grad.dtype == np.float32
+    assert weights.size == gnn_n_weights(c_out) and grad.size == weights.size
+    loss = C.c_double(0.0)
+    check(lib().tls_gnn_loss_grad(ctx, weights.ctypes.data, c_out, grad.ctypes.data, C.byref(loss)), ctx)
+    return loss.value
 
 
 def tls_destroy(ctx):

@@ -58,6 +58,9 @@ void tls_default_options(tls_options* o) {
   o->solve_order = 0;
   o->autotune = 0;
   o->tune_cache = nullptr;
+  o->gnn_weights = nullptr;
+  o->gnn_c_out = 0;
+  o->gnn_train = 0;
   o->stream = nullptr;
 }
 
@@ -88,6 +91,10 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.nev1 > 0 && overlap == 0) tls::fail(TLS_E_ARG, "overlap 0: nev1 must be 0");
     if (c->opt.solve_order < 0 || c->opt.solve_order > 3) tls::fail(TLS_E_ARG, "solve_order must be in [0, 3]");
     if (c->opt.solve_wgs < 0) tls::fail(TLS_E_ARG, "solve_wgs must be >= 0");
+    if (c->opt.gnn_weights || c->opt.gnn_train) {
+      if (c->opt.matrix_kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");
+      if (c->opt.gnn_weights) tls::gnn_check_weights(c->opt.gnn_c_out);
+    }
     if (c->opt.flexible < 0) c->opt.flexible = c->opt.precision == 1 ? 1 : 0;
     if (c->opt.eig_maxit <= 0) c->opt.eig_maxit = 300;
     if (c->opt.restart <= 0) c->opt.restart = 30;
@@ -153,6 +160,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     TLS_HIP(hipStreamSynchronize(s));
     c->t_setup[7] = ms_since(t_all);
   });
+  c->opt.gnn_weights = nullptr;  // caller memory: read during setup only
   if (st != TLS_OK) return st;
   *out = c.release();
   return TLS_OK;
@@ -274,6 +282,30 @@ tls_status tls_export(const tls_ctx* cc, int32_t* sub_ptr, int32_t* sub_idx, int
         }
     }
   });
+}
+
+tls_status tls_gnn_forward(tls_ctx* c, const float* weights, int32_t c_out, float* X) {
+  if (!c) return TLS_E_STATE;
+  if (!weights || !X) {
+    c->err = "weights and X must not be NULL";
+    return TLS_E_ARG;
+  }
+  return guard(c, [&]() {
+    if (c->kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");
+    tls::gnn_forward(c, weights, c_out, false);
+    const size_t total = (size_t)c->h_sub_ptr[c->N];
+    auto h = tls::download(c->gnn_X.p, total * c_out, c->stream);
+    std::copy(h.begin(), h.end(), X);
+  });
+}
+
+tls_status tls_gnn_loss_grad(tls_ctx* c, const float* weights, int32_t c_out, float* grad, double* loss) {
+  if (!c) return TLS_E_STATE;
+  if (!weights || !grad || !loss) {
+    c->err = "weights, grad and loss must not be NULL";
+    return TLS_E_ARG;
+  }
+  return guard(c, [&]() { *loss = tls::gnn_loss_grad(c, weights, c_out, grad); });
 }
 
 tls_status tls_local_solve(tls_ctx* c, int32_t i, const double* b, double* x) {

@@ -81,6 +81,18 @@ struct tls_ctx {
   int eig_iters_max = 0;
   int64_t nnz0 = 0;
 
+  // learned warm start of the eigensolver: local graphs (CSR over the
+  // positions of the concatenated Omega lists), features, weights, hidden
+  // states (4 layers x positions x 32) and the training targets
+  bool gnn_graph = false;
+  tls::DBuf<int> gnn_ptr, gnn_col;
+  tls::DBuf<float> gnn_w, gnn_feat, gnn_wdev, gnn_H, gnn_M, gnn_X;
+  int gnn_cout = 0;
+  tls::DBuf<double> gnn_tgt;  // orthonormal bases (nT_i x k_i, column-major)
+  std::vector<int64_t> h_gnn_toff;
+  tls::DBuf<int> gnn_nT, gnn_k;
+  tls::DBuf<int64_t> gnn_toff;
+
   // Krylov work
   tls::DBuf<double> kr;        // vectors
   tls::DBuf<double> scal;      // device scalars

@@ -16,6 +16,7 @@
 // C is #T x #T; its top eigenpairs come from subspace iteration with
 // Rayleigh-Ritz.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 #include "batched.hpp"
@@ -312,7 +313,7 @@ __global__ void __launch_bounds__(256) k_subspace(const int* __restrict__ nT_, c
                                                   const int64_t* __restrict__ o_Z, double* zv,
                                                   const int* __restrict__ o_th, double* theta, int* kfound,
                                                   double* resid, int* iters, double tau2, double floor_rel,
-                                                  int* err) {
+                                                  int c0, int* err) {
   __shared__ double H[PMAX * PMAX];
   __shared__ double S[PMAX * PMAX];
   __shared__ double G[PMAX * PMAX];
@@ -340,11 +341,25 @@ __global__ void __launch_bounds__(256) k_subspace(const int* __restrict__ nT_, c
   for (int r = tid; r < n; r += 256) tr += C[r + (int64_t)r * n];
   tr = block_sum(tr, red);
   const double sigma = 1e-7 * tr;
+  // start block: columns c >= cw random; the first cw columns were filled
+  // by the caller (warm start), normalized here with a 1e-3 random
+  // component added so that the block keeps full rank
+  const int cw = min(c0, p);
   for (int64_t e = tid; e < (int64_t)n * p; e += 256) {
     int r = (int)(e % n), c = (int)(e / n);
-    Y[e] = hash_uniform(seed, i, r, c);
+    if (c >= cw) Y[e] = hash_uniform(seed, i, r, c);
   }
   __syncthreads();
+  for (int c = 0; c < cw; c++) {
+    double* y = Y + (int64_t)c * n;
+    double s2 = 0.0;
+    for (int r = tid; r < n; r += 256) s2 += y[r] * y[r];
+    s2 = block_sum(s2, red);
+    const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+    const double rs = 1e-3 * sqrt(3.0 / n);
+    for (int r = tid; r < n; r += 256) y[r] = y[r] * inv + rs * hash_uniform(seed, i, r, c);
+    __syncthreads();
+  }
   bool ok = chol_qr(Y, n, p, G, red);
   if (tid < PMAX) perm[tid] = tid;
   __syncthreads();
@@ -597,13 +612,15 @@ struct PassEig {
 
 // Top eigenpairs of C (nT x nT per subdomain, fp64, in C64) by subspace
 // iteration; the eigenvectors land in zv (nT x kf, offsets oZv).
+// Ypre (optional): start block already holding c0 warm columns per subdomain.
 static PassEig run_subspace(tls_ctx* c, const PassDims& d, PassDev& dv, const DBuf<double>& C64, DBuf<double>& zv,
-                            double thresh) {
+                            double thresh, DBuf<double>* Ypre = nullptr, int c0 = 0) {
   hipStream_t s = c->stream;
   const int N = c->N;
-  DBuf<double> Yb, Wb, theta, resid;
+  DBuf<double> Yown, Wb, theta, resid;
   DBuf<int> kfound, its;
-  Yb.alloc(std::max<int64_t>(d.oY[N], 1));
+  DBuf<double>& Yb = Ypre ? *Ypre : Yown;
+  if (!Ypre) Yown.alloc(std::max<int64_t>(d.oY[N], 1));
   Wb.alloc(std::max<int64_t>(d.oY[N], 1));
   zv.alloc(std::max<int64_t>(d.oZv[N], 1));
   theta.alloc(std::max(d.oth[N], 1));
@@ -613,7 +630,7 @@ static PassEig run_subspace(tls_ctx* c, const PassDims& d, PassDev& dv, const DB
   const double tol = c->opt.eig_tol > 0 ? c->opt.eig_tol : (c->fp32 ? 1e-6 : 1e-9);
   hipLaunchKernelGGL(k_subspace, dim3(N), dim3(256), 0, s, dv.nT.p, dv.kreq.p, dv.oTT.p, C64.p, dv.oY.p, Yb.p, Wb.p,
                      d.over, c->opt.eig_maxit, tol, (uint64_t)c->opt.seed, dv.oZv.p, zv.p, dv.oth.p,
-                     theta.p, kfound.p, resid.p, its.p, thresh, 1e-12, c->errflag.p);
+                     theta.p, kfound.p, resid.p, its.p, thresh, 1e-12, Ypre ? c0 : 0, c->errflag.p);
   TLS_LAUNCH_CHECK();
   PassEig e;
   e.kf = download(kfound.p, N, s);
@@ -633,9 +650,11 @@ static PassEig run_subspace(tls_ctx* c, const PassDims& d, PassDev& dv, const DB
 // buffer XV (column j of every subdomain is padded local vector j, stride
 // sum_M); a backward solve with the whole factor then turns [V; 0] into
 // [L_II^{-T} V; 0].
+// gevp2: the eq. gevpsvd pass (the learned warm start and the training
+// targets belong to it).
 template <class T>
 static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thresh, const std::vector<int>& colbase,
-                        T* XV) {
+                        T* XV, bool gevp2) {
   hipStream_t s = c->stream;
   const int N = c->N;
   PassDev dv;
@@ -703,13 +722,39 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
   LTT.release();
   C64b.release();
   DBuf<double> zv;
-  PassEig e = run_subspace(c, d, dv, C64, zv, thresh);
+  DBuf<double> Ywarm;
+  int c0 = 0;
+  if (gevp2 && c->opt.gnn_weights) {
+    // start block = L_TT^T X_T: the network guesses the rows T of the
+    // eigenvectors w, and z = L_TT^T w_T are the eigenvectors of C
+    const auto t0 = std::chrono::steady_clock::now();
+    gnn_forward(c, c->opt.gnn_weights, c->opt.gnn_c_out, false);
+    c0 = std::min(c->opt.gnn_c_out, PMAX);
+    std::vector<int64_t> oX(N + 1, 0);
+    for (int i = 0; i < N; i++) oX[i + 1] = oX[i] + (d.kreq[i] > 0 ? (int64_t)d.nT[i] * c0 : 0);
+    DBuf<double> Xg;
+    Xg.alloc(std::max<int64_t>(oX[N], 1));
+    gnn_take_rows(c, d.nT, d.kreq, oX, c0, Xg.p);
+    Ywarm.alloc(std::max<int64_t>(d.oY[N], 1));
+    std::vector<GemmDesc> gw;
+    for (int i = 0; i < N; i++) {
+      if (d.kreq[i] <= 0) continue;
+      const int p = std::min(d.nT[i], std::min(PMAX, d.kreq[i] + d.over));
+      const int cw = std::min(c0, p);
+      gw.push_back(GemmDesc{d.nT[i], cw, d.nT[i], d.nT[i], d.nT[i], d.oTT[i], oX[i], d.oY[i], (int64_t)d.nT[i]});
+    }
+    batched_gemm<double>(s, gw, false, false, LTTt.p, Xg.p, Ywarm.p, 1.0, 0.0);
+    TLS_HIP(hipStreamSynchronize(s));
+    c->t_setup[4] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  PassEig e = run_subspace(c, d, dv, C64, zv, thresh, c0 > 0 ? &Ywarm : nullptr, c0);
   C64.release();
   // w_T = L_TT^{-T} z ; V = F w_T into columns colbase[i] + j of XV
   std::vector<TriDesc> tw;
   for (int i = 0; i < N; i++)
     if (e.kf[i] > 0) tw.push_back(TriDesc{d.nT[i], e.kf[i], d.oTT[i], d.oZv[i], (int64_t)d.nT[i]});
   batched_trsm<double>(s, tw, UPPER_BWD, LTTt.p, zv.p, c->errflag.p);
+  if (gevp2 && c->opt.gnn_train) gnn_keep_targets(c, d.nT, e.kf, zv.p, d.oZv);
   DBuf<T> wT;
   wT.alloc(std::max<int64_t>(d.oZv[N], 1));
   hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)d.oZv[N], zv.p, wT.p);
@@ -811,10 +856,10 @@ static void basis_spd(tls_ctx* c, T* fac) {
   PassEig e2, e1;
   e2.kf.assign(N, 0);
   e1.kf.assign(N, 0);
-  if (d2.kmax > 0) e2 = spd_pass<T>(c, fac, d2, tau2, std::vector<int>(N, 0), XV.p);
+  if (d2.kmax > 0) e2 = spd_pass<T>(c, fac, d2, tau2, std::vector<int>(N, 0), XV.p, true);
   if (d1.kmax > 0) {
     const double nu = c->opt.nu > 0 ? c->opt.nu : 1.0;
-    e1 = spd_pass<T>(c, fac, d1, nu - 1.0, e2.kf, XV.p);  // lambda = 1 + kappa > nu
+    e1 = spd_pass<T>(c, fac, d1, nu - 1.0, e2.kf, XV.p, false);  // lambda = 1 + kappa > nu
   }
   c->eig_resid_max = std::max(e2.resid_max, e1.resid_max);
   c->eig_iters_max = std::max(e2.iters_max, e1.iters_max);

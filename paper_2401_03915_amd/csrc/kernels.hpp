@@ -53,6 +53,20 @@ void build_coarse_operator(tls_ctx* c);
 void coarse_restrict(tls_ctx* c, const double* r, const int* done);
 void coarse_solve(tls_ctx* c, const int* done);
 
+// gnn.hip: learned warm start of the eigensolver
+void gnn_check_weights(int c_out);
+int gnn_n_weights(int c_out);
+void gnn_build_graph(tls_ctx* c);
+// X (positions x c_out, FP32) into c->gnn_X; keep = also keep the messages for training
+void gnn_forward(tls_ctx* c, const float* w_host, int c_out, bool keep);
+// keep orthonormal bases of the eq. gevpsvd eigenvectors' rows Gamma_{i,delta}
+void gnn_keep_targets(tls_ctx* c, const std::vector<int>& nT, const std::vector<int>& k, const double* wT,
+                      const std::vector<int64_t>& woff);
+double gnn_loss_grad(tls_ctx* c, const float* w_host, int c_out, float* grad_host);
+// rows Gamma_{i,delta} of c->gnn_X (first c0 columns) -> FP64 nT_i x c0 blocks at off[i] (act[i] > 0 only)
+void gnn_take_rows(tls_ctx* c, const std::vector<int>& nT, const std::vector<int>& act,
+                   const std::vector<int64_t>& off, int c0, double* out);
+
 // tune.hip: workgroup count of the persistent solves (default / timed / cached)
 void choose_solve_grid(tls_ctx* c);
 

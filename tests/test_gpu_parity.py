@@ -477,3 +477,102 @@ def test_autotune_cache_reuse(tmp_path):
     pc1.close()
     pc2.close()
     del tls
+
+
+# ---------------------------------------------------------------------------
+# learned warm start of the eigensolver (network kernels against the oracle)
+# ---------------------------------------------------------------------------
+
+def _gnn_case():
+    A, part = _hc_problem(64, 3, seed=6)
+    return A, part, 2, 4
+
+
+def test_gnn_forward_matches_oracle():
+    from oracle import gnn
+    A, part, delta, nev = _gnn_case()
+    N = int(part.max()) + 1
+    c_out = 6
+    w = 0.3 * np.random.default_rng(21).standard_normal(gnn.n_weights(c_out))
+    say("gnn forward")
+    pc = _pc(A, part, delta, nev, gnn_train=1)
+    X = pc.gnn_forward(w.astype(np.float32), c_out)
+    sp_ = pc.export()["sub_ptr"]
+    worst = 0.0
+    for i in range(N):
+        s = schwarz.overlap(A, part, i, delta)
+        Aii = schwarz.local_matrix(A, s)
+        Xo, _ = gnn.forward(Aii, s.n_interior, s.layer_sizes[-1], w.astype(np.float32).astype(np.float64), c_out)
+        Xg = X[sp_[i]:sp_[i + 1]]
+        worst = max(worst, np.abs(Xg - Xo).max() / np.abs(Xo).max())
+    say("  worst forward error", worst)
+    assert worst <= 1e-5
+    pc.close()
+
+
+def test_gnn_loss_and_gradient_match_oracle():
+    """Loss and weight gradient of the device backward kernels against the
+    oracle's backward pass, with targets from the oracle's dense solve of
+    eq. gevpsvd (the spans agree wherever the gap at k allows; the case is
+    chosen so that it does for every subdomain)."""
+    from oracle import gnn
+    A, part, delta, nev = _gnn_case()
+    N = int(part.max()) + 1
+    c_out = 6
+    w = (0.3 * np.random.default_rng(22).standard_normal(gnn.n_weights(c_out))).astype(np.float32)
+    say("gnn loss/grad")
+    pc = _pc(A, part, delta, nev, gnn_train=1)
+    zc = pc.export()["zcol_ptr"]
+    loss_g, grad_g = pc.gnn_loss_grad(w, c_out)
+    w64 = w.astype(np.float64)
+    tot_f, tot_g, nact = 0.0, np.zeros(w.size), 0
+    for i in range(N):
+        s = schwarz.overlap(A, part, i, delta)
+        Aii = schwarz.local_matrix(A, s)
+        lam, W = schwarz.gevp2(Aii, s, s.size)
+        k = zc[i + 1] - zc[i]
+        if k == 0:
+            continue
+        assert lam.size == k or lam[k - 1] / lam[k] >= 1 + 1e-3, "case must have a spectral gap at k"
+        Q = gnn.target_basis(W[:, :k], s.layer_sizes[-1])
+        f, g = gnn.loss_grad(Aii, s.n_interior, s.layer_sizes[-1], w64, c_out, Q)
+        tot_f += f
+        tot_g += g
+        nact += 1
+    loss_o, grad_o = tot_f / nact, tot_g / nact
+    say("  loss", loss_g, loss_o)
+    assert abs(loss_g - loss_o) <= 1e-4 * abs(loss_o)
+    err = np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o)
+    say("  gradient error", err)
+    assert err <= 1e-3
+    pc.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gnn_warm_start_keeps_the_result(precision):
+    """Any start block (here an untrained network) leads to the same
+    eigenvalues within the eigensolver tolerance, the same coarse space and
+    the same PCG iterations."""
+    torch = torch_cuda()
+    from oracle import gnn
+    A, part, delta, nev = _gnn_case()
+    c_out = 8
+    w = (0.3 * np.random.default_rng(23).standard_normal(gnn.n_weights(c_out))).astype(np.float32)
+    say("gnn warm start", precision)
+    p0 = _pc(A, part, delta, nev, precision=precision)
+    p1 = _pc(A, part, delta, nev, precision=precision, gnn_weights=w)
+    e0, e1 = p0.export(), p1.export()
+    assert np.array_equal(e0["zcol_ptr"], e1["zcol_ptr"])
+    tol = 1e-7 if precision == 0 else 1e-3
+    assert np.allclose(e0["eigvals"], e1["eigvals"], rtol=tol)
+    b = to_dev(np.random.default_rng(24).standard_normal(A.shape[0]))
+    _, it0, rr0, _ = p0.solve(b, 1e-8)
+    _, it1, rr1, _ = p1.solve(b, 1e-8)
+    torch.cuda.synchronize()
+    i0, i1 = p0.info(), p1.info()
+    say("  iterations", it0, it1, "eig iters", i0["eig_iters_max"], i1["eig_iters_max"], "t_gnn", i1["t_setup"][4])
+    assert rr0 <= 1e-8 and rr1 <= 1e-8
+    assert abs(it1 - it0) <= max(1, 0.05 * it0)
+    assert i1["t_setup"][4] > 0.0
+    p0.close()
+    p1.close()
