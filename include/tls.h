@@ -47,8 +47,11 @@ typedef struct tls_ctx tls_ctx;
 
 /* Learned warm start of the local eigensolver (not part of the paper).
  * A message-passing network on the graph of each A_ii (edges
- * e_ab = |a_ab| / sqrt(|a_aa| |a_bb|), 4 input features per node: 1,
- * in I_i, in Gamma_{i,delta}, log10 of the relative diagonal) with
+ * e_ab = |a_ab| / sqrt(|a_aa| |a_bb|), 12 input features per node: 1,
+ * in I_i, in Gamma_{i,delta}, log10 of the relative diagonal, and
+ * TLS_GNN_RANDOM uniform [-1, 1) channels from SplitMix64: channel j of
+ * local node a is 2 (z >> 11) 2^-53 - 1 with z the output 8a + j + 1 from
+ * state 0) with
  * TLS_GNN_LAYERS layers of width TLS_GNN_HIDDEN,
  * H_l = tanh(E H_{l-1} Theta_l + H_{l-1} Phi_l + b_l), and a linear read-out
  * X = H_L Omega of c_out columns, predicts the rows Gamma_{i,delta} of the
@@ -57,7 +60,8 @@ typedef struct tls_ctx tls_ctx;
  * row major), Phi_l (same), b_l (HIDDEN); then Omega (HIDDEN x c_out);
  * c_0 = TLS_GNN_FEATURES. */
 #define TLS_GNN_LAYERS 4
-#define TLS_GNN_FEATURES 4
+#define TLS_GNN_RANDOM 8
+#define TLS_GNN_FEATURES 12
 #define TLS_GNN_HIDDEN 32
 #define TLS_GNN_NWEIGHTS(c_out)                                              \
   (2 * TLS_GNN_FEATURES * TLS_GNN_HIDDEN + TLS_GNN_HIDDEN +                  \
@@ -96,7 +100,8 @@ typedef struct {
   int32_t restart;      /* FGMRES restart length m (default 30)            */
   int32_t maxit;        /* Krylov iteration cap (default 1000; 3000 general) */
   int32_t eig_maxit;    /* local subspace-iteration cap (default 300)      */
-  double eig_tol;       /* relative eigen-residual tolerance (default 1e-9 FP64, 1e-6 FP32) */
+  double eig_tol;       /* relative eigen-residual tolerance (default 1e-9 FP64, 1e-5 FP32);
+                           a residual below 10x that which stalls is accepted */
   int32_t eig_oversample; /* subspace block p = k + oversample, k = nev (eq. gevpsvd) or
                              nev1 (eq. uppergevp); default (-1): k; p <= 48 */
   uint64_t seed;        /* seed of the counter-based start vectors         */
@@ -115,7 +120,8 @@ typedef struct {
   /* Learned warm start (SPD only): host array of TLS_GNN_NWEIGHTS(gnn_c_out)
    * floats, read during tls_setup; NULL = random start (default). The first
    * min(gnn_c_out, p) columns of the eq. gevpsvd start block come from the
-   * network, the rest are random. gnn_c_out in [1, 64]. */
+   * network, the rest are random. gnn_c_out in [1, TLS_GNN_HIDDEN] (the
+   * read-out has rank <= TLS_GNN_HIDDEN). */
   const float* gnn_weights;
   int32_t gnn_c_out;
   /* 1: keep what tls_gnn_forward / tls_gnn_loss_grad need (the local graphs
@@ -144,6 +150,7 @@ typedef struct {
   double relres;              /* true relative residual of the last solve    */
   double eig_resid_max;       /* max relative eigen-residual over subdomains */
   int32_t eig_iters_max;      /* max subspace iterations over subdomains     */
+  double eig_iters_mean;      /* mean subspace iterations over subdomains    */
   int32_t n_res_history;      /* entries in res_history                      */
   int32_t n_profiled;         /* tls_apply calls timed with profile = 1       */
   double t_local_solve_ms;    /* mean duration of their local forward + backward
@@ -224,7 +231,8 @@ const char* tls_last_error(const tls_ctx* c);
 tls_status tls_gnn_forward(tls_ctx* c, const float* weights, int32_t c_out, float* X);
 
 /* Learned warm start, training step: the mean over subdomains of
- *   f_i = -(1/k_i) tr(G^{-1} X_T^T Q_i Q_i^T X_T),  G = X_T^T X_T,
+ *   f_i = -(1/k_i) tr(G^{-1} X_T^T Q_i Q_i^T X_T),
+ *   G = X_T^T X_T + 1e-3 (tr(X_T^T X_T) / c_out) I,
  * where X_T are the rows Gamma_{i,delta} of the network output and Q_i an
  * orthonormal basis of the same rows of the context's own top-k_i
  * eq. gevpsvd eigenvectors (kept by a setup with gnn_train = 1), and its

@@ -13,8 +13,12 @@ a good guess. Definition, for the local matrix A_ii with Omega_i ordered
 
 * graph: nodes Omega_i; an edge (a, b), a != b, wherever (A_ii)_ab != 0,
   weighted e_ab = |a_ab| / sqrt(|a_aa| |a_bb|)  (E: m x m, zero diagonal);
-* features (m x 4): [1, 1{a in I_i}, 1{a in Gamma_{i,delta}},
-  log10(|a_aa| / mean_b |a_bb|)];
+* features (m x 12): [1, 1{a in I_i}, 1{a in Gamma_{i,delta}},
+  log10(|a_aa| / mean_b |a_bb|), r_a0 .. r_a7], where the eight random
+  channels r_aj = 2 u - 1 with u = (z >> 11) 2^-53, z the (8a + j + 1)-th
+  output of SplitMix64 started from state 0 (Steele, Lea and Flood, 2014);
+  they let the network turn noise into smooth, distinct columns, which
+  structural features alone cannot (all nodes of a layer look alike);
 * four layers of width 32: H_l = tanh(E H_{l-1} Theta_l + H_{l-1} Phi_l + b_l),
   H_0 = features;
 * output X = H_4 Omega (m x c_out).
@@ -23,18 +27,21 @@ Training loss for one subdomain, on the rows T = Gamma_{i,delta} (the only
 rows the eigensolver's reduced problem sees), against an orthonormal basis
 Q (#T x k) of the rows T of the top-k eq. gevpsvd eigenvectors:
 
-    f = -(1/k) tr(G^{-1} X_T^T Q Q^T X_T),   G = X_T^T X_T,
+    f = -(1/k) tr(G_e^{-1} X_T^T Q Q^T X_T),
+    G_e = X_T^T X_T + EPS (tr(X_T^T X_T) / c) I,   EPS = 1e-3,
 
-which is -1 exactly when span(X_T) contains span(Q) and is unchanged by
-X_T -> X_T R for any invertible R (it depends on span(X_T) only).
+the fraction of the target span that span(X_T) captures, regularized so
+that nearly dependent columns do not blow up G^{-1}. It is -1/(1 + EPS)
+when X_T = Q, 0 when X_T is orthogonal to Q, and unchanged by
+X_T -> alpha X_T R for alpha != 0 and orthogonal R.
 
 Weights are one flat vector: for l = 1..4, Theta_l (c_{l-1} x 32, row
-major), Phi_l (c_{l-1} x 32), b_l (32); then Omega (32 x c_out); c_0 = 4.
+major), Phi_l (c_{l-1} x 32), b_l (32); then Omega (32 x c_out); c_0 = 12.
 
 Pinned by: central finite differences of the loss (gradient), the loss's
-closed values (-1 on the target span, 0 on its orthogonal complement) and
-its invariance under X_T -> X_T R, permutation equivariance of the forward
-pass, and a three-node graph worked by hand (tests/test_oracle_gnn.py).
+closed values and invariances, the published first outputs of SplitMix64,
+permutation equivariance of the forward pass (features permuted along),
+and a three-node graph worked by hand (tests/test_oracle_gnn.py).
 """
 
 from __future__ import annotations
@@ -43,8 +50,31 @@ import numpy as np
 import scipy.sparse as sp
 
 LAYERS = 4
-FEATURES = 4
+STRUCT = 4            # structural input channels
+RANDOM = 8            # random input channels
+FEATURES = STRUCT + RANDOM
 HIDDEN = 32
+EPS = 1e-3            # loss regularization
+
+
+def splitmix64(counter: np.ndarray) -> np.ndarray:
+    """Output number counter + 1 of SplitMix64 started from state 0, as
+    uint64 (published definition: state += 0x9E3779B97F4A7C15, then the
+    xor-shift-multiply finalizer)."""
+    c = np.asarray(counter, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (c + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def random_channels(m: int) -> np.ndarray:
+    """m x RANDOM uniform values in [-1, 1): channel j of node a from
+    counter RANDOM * a + j."""
+    a = np.arange(m, dtype=np.uint64)[:, None] * np.uint64(RANDOM) + np.arange(RANDOM, dtype=np.uint64)[None, :]
+    z = splitmix64(a)
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53 * 2.0 - 1.0
 
 
 def n_weights(c_out: int) -> int:
@@ -98,7 +128,7 @@ def graph(Aii: sp.spmatrix) -> sp.csr_matrix:
 
 
 def features(Aii: sp.spmatrix, n_interior: int, n_last: int) -> np.ndarray:
-    """[1, in I_i, in Gamma_{i,delta}, log10(|a_aa| / mean |a_bb|)]."""
+    """[1, in I_i, in Gamma_{i,delta}, log10(|a_aa| / mean |a_bb|), random channels]."""
     m = Aii.shape[0]
     d = np.abs(np.asarray(Aii.diagonal(), dtype=np.float64))
     F = np.zeros((m, FEATURES))
@@ -107,14 +137,16 @@ def features(Aii: sp.spmatrix, n_interior: int, n_last: int) -> np.ndarray:
     F[m - n_last:, 2] = 1.0
     mean = d.mean()
     F[:, 3] = np.log10(d / mean)
+    F[:, STRUCT:] = random_channels(m)
     return F
 
 
-def forward(Aii: sp.spmatrix, n_interior: int, n_last: int, w: np.ndarray, c_out: int):
-    """Returns (X, cache) with X = H_4 Omega."""
+def forward(Aii: sp.spmatrix, n_interior: int, n_last: int, w: np.ndarray, c_out: int, feats=None):
+    """Returns (X, cache) with X = H_4 Omega (features from ``features``
+    unless given)."""
     layers, om = unpack(w, c_out)
     E = graph(Aii)
-    H = [features(Aii, n_interior, n_last)]
+    H = [features(Aii, n_interior, n_last) if feats is None else np.asarray(feats, dtype=np.float64)]
     M = []
     for th, ph, b in layers:
         msg = E @ H[-1]
@@ -125,17 +157,21 @@ def forward(Aii: sp.spmatrix, n_interior: int, n_last: int, w: np.ndarray, c_out
 
 
 def loss(X: np.ndarray, n_last: int, Q: np.ndarray):
-    """f = -(1/k) tr(G^{-1} X_T^T Q Q^T X_T) and df/dX (zero outside rows T)."""
+    """f = -(1/k) tr(G_e^{-1} X_T^T Q Q^T X_T) and df/dX (zero outside rows T)."""
     m = X.shape[0]
     k = Q.shape[1]
     XT = X[m - n_last:]
+    c = XT.shape[1]
     G = XT.T @ XT
+    Ge = G + EPS * (np.trace(G) / c) * np.eye(c)
     A1 = Q.T @ XT                     # k x c
     B = A1.T @ A1                     # X_T^T Q Q^T X_T
-    Gi = np.linalg.inv(G)
+    Gi = np.linalg.inv(Ge)
     f = -np.trace(Gi @ B) / k
-    # d tr(G^{-1} B) / dX_T = 2 (Q Q^T X_T G^{-1} - X_T G^{-1} B G^{-1})
-    dXT = -(2.0 / k) * (Q @ (A1 @ Gi) - XT @ (Gi @ B @ Gi))
+    # d tr(G_e^{-1} B) / dX_T = 2 (Q Q^T X_T G_e^{-1} - X_T G_e^{-1} B G_e^{-1})
+    #                           - (2 EPS / c) tr(G_e^{-1} B G_e^{-1}) X_T
+    T2 = Gi @ B @ Gi
+    dXT = -(2.0 / k) * (Q @ (A1 @ Gi) - XT @ T2 - (EPS / c) * np.trace(T2) * XT)
     dX = np.zeros_like(X)
     dX[m - n_last:] = dXT
     return f, dX

@@ -24,7 +24,7 @@ EXPORTED = ["tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_so
             "tls_local_solve", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_last_error", "tls_destroy"]
 
 GNN_LAYERS = 4
-GNN_FEATURES = 4
+GNN_FEATURES = 12
 GNN_HIDDEN = 32
 
 
@@ -86,6 +86,7 @@ class tls_info_t(C.Structure):
         ("relres", C.c_double),
         ("eig_resid_max", C.c_double),
         ("eig_iters_max", C.c_int32),
+        ("eig_iters_mean", C.c_double),
         ("n_res_history", C.c_int32),
         ("n_profiled", C.c_int32),
         ("t_local_solve_ms", C.c_double),

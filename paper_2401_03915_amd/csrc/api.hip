@@ -232,6 +232,7 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->relres = c->last_relres;
   info->eig_resid_max = c->eig_resid_max;
   info->eig_iters_max = c->eig_iters_max;
+  info->eig_iters_mean = c->eig_iters_mean;
   info->n_res_history = (int32_t)c->h_hist.size();
   info->res_history = c->h_hist.empty() ? nullptr : c->h_hist.data();
   info->n_profiled = c->prof_count;

@@ -207,6 +207,42 @@ void batched_gemm(hipStream_t s, const std::vector<GemmDesc>& d, bool transA, bo
   TLS_HIP(hipStreamSynchronize(s));
 }
 
+void gemm_plan(GemmPlan& p, const std::vector<GemmDesc>& d, hipStream_t s) {
+  std::vector<GemmDesc> dd;
+  std::vector<int64_t> pref;
+  int64_t tot = 0;
+  for (const auto& g : d) {
+    if (g.M <= 0 || g.N <= 0) continue;
+    dd.push_back(g);
+    pref.push_back(tot);
+    tot += (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64);
+  }
+  pref.push_back(tot);
+  if (p.desc.n < std::max<size_t>(dd.size(), 1)) p.desc.alloc(std::max<size_t>(dd.size(), 1));
+  if (p.pref.n < pref.size()) p.pref.alloc(pref.size());
+  if (!dd.empty()) TLS_HIP(hipMemcpyAsync(p.desc.p, dd.data(), sizeof(GemmDesc) * dd.size(), hipMemcpyHostToDevice, s));
+  TLS_HIP(hipMemcpyAsync(p.pref.p, pref.data(), sizeof(int64_t) * pref.size(), hipMemcpyHostToDevice, s));
+  TLS_HIP(hipStreamSynchronize(s));  // dd and pref are host temporaries
+  p.nd = (int)dd.size();
+  p.tiles = tot;
+}
+
+template <class T>
+void gemm_run(hipStream_t s, const GemmPlan& p, bool transA, bool transB, const T* A, const T* B, T* C, T alpha,
+              T beta) {
+  if (p.tiles == 0) return;
+  const dim3 g((unsigned)p.tiles);
+  if (!transA && !transB)
+    hipLaunchKernelGGL((k_gemm<T, false, false>), g, dim3(256), 0, s, p.desc.p, p.pref.p, p.nd, A, B, C, alpha, beta);
+  else if (transA && !transB)
+    hipLaunchKernelGGL((k_gemm<T, true, false>), g, dim3(256), 0, s, p.desc.p, p.pref.p, p.nd, A, B, C, alpha, beta);
+  else if (!transA && transB)
+    hipLaunchKernelGGL((k_gemm<T, false, true>), g, dim3(256), 0, s, p.desc.p, p.pref.p, p.nd, A, B, C, alpha, beta);
+  else
+    hipLaunchKernelGGL((k_gemm<T, true, true>), g, dim3(256), 0, s, p.desc.p, p.pref.p, p.nd, A, B, C, alpha, beta);
+  TLS_LAUNCH_CHECK();
+}
+
 template <class T>
 void batched_trsm(hipStream_t s, const std::vector<TriDesc>& d, TriMode mode, const T* M, T* B, int* err) {
   int nmax = 0;
@@ -246,6 +282,10 @@ template void batched_gemm<float>(hipStream_t, const std::vector<GemmDesc>&, boo
                                   float*, float, float);
 template void batched_gemm<double>(hipStream_t, const std::vector<GemmDesc>&, bool, bool, const double*,
                                    const double*, double*, double, double);
+template void gemm_run<float>(hipStream_t, const GemmPlan&, bool, bool, const float*, const float*, float*, float,
+                              float);
+template void gemm_run<double>(hipStream_t, const GemmPlan&, bool, bool, const double*, const double*, double*,
+                               double, double);
 template void batched_trsm<float>(hipStream_t, const std::vector<TriDesc>&, TriMode, const float*, float*, int*);
 template void batched_trsm<double>(hipStream_t, const std::vector<TriDesc>&, TriMode, const double*, double*, int*);
 

@@ -20,6 +20,19 @@ template <class T>
 void batched_gemm(hipStream_t s, const std::vector<GemmDesc>& d, bool transA, bool transB, const T* A,
                   const T* B, T* C, T alpha, T beta);
 
+// A descriptor list kept on the device for repeated launches (the buffers
+// grow as needed and are reused). gemm_run does not synchronize.
+struct GemmPlan {
+  DBuf<GemmDesc> desc;
+  DBuf<int64_t> pref;
+  int nd = 0;
+  int64_t tiles = 0;
+};
+void gemm_plan(GemmPlan& p, const std::vector<GemmDesc>& d, hipStream_t s);
+template <class T>
+void gemm_run(hipStream_t s, const GemmPlan& p, bool transA, bool transB, const T* A, const T* B, T* C, T alpha,
+              T beta);
+
 // In-place triangular solves with a column-major n x n triangular matrix
 // (leading dimension n) and nrhs right-hand sides (leading dimension ldb):
 //   LOWER_FWD: M lower, solve M X = B (forward substitution)

@@ -79,6 +79,7 @@ struct tls_ctx {
   tls::DBuf<int64_t> one_foff, one_voff, one_toff;
   double eig_resid_max = 0;
   int eig_iters_max = 0;
+  double eig_iters_mean = 0;
   int64_t nnz0 = 0;
 
   // learned warm start of the eigensolver: local graphs (CSR over the

@@ -138,91 +138,6 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// Y (n x p, leading dim n) <- Y R^{-1} with R from the Cholesky of Y^T Y.
-// Twice (CholQR2). Returns false if the Gram matrix is not positive definite.
-__device__ bool chol_qr(double* Y, int n, int p, double* G, double* red) {
-  const int tid = threadIdx.x;
-  bool ok = true;
-  for (int pass = 0; pass < 2; pass++) {
-    // Gram G = Y^T Y (upper triangle), one entry per thread at a time
-    const int npair = p * (p + 1) / 2;
-    for (int e = tid; e < npair; e += 256) {
-      int a = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while ((a + 1) * (a + 2) / 2 <= e) a++;
-      while (a * (a + 1) / 2 > e) a--;
-      int b = e - a * (a + 1) / 2;  // b <= a
-      const double* ya = Y + (int64_t)a * n;
-      const double* yb = Y + (int64_t)b * n;
-      double s = 0.0;
-      for (int r = 0; r < n; r++) s += ya[r] * yb[r];
-      G[b * PMAX + a] = s;  // row b, col a (upper)
-    }
-    __syncthreads();
-    if (tid == 0) {
-      // in-place upper Cholesky G = R^T R
-      for (int j = 0; j < p; j++) {
-        double d = G[j * PMAX + j];
-        for (int l = 0; l < j; l++) d -= G[l * PMAX + j] * G[l * PMAX + j];
-        if (!(d > 0.0)) {
-          ok = false;
-          d = 1e-300;
-        }
-        d = sqrt(d);
-        G[j * PMAX + j] = d;
-        for (int c = j + 1; c < p; c++) {
-          double s = G[j * PMAX + c];
-          for (int l = 0; l < j; l++) s -= G[l * PMAX + j] * G[l * PMAX + c];
-          G[j * PMAX + c] = s / d;
-        }
-      }
-      red[8] = ok ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    ok = red[8] != 0.0;
-    // rows: y <- y R^{-1}
-    for (int r = tid; r < n; r += 256) {
-      double y[PMAX];
-#pragma unroll
-      for (int c = 0; c < PMAX; c++)
-        if (c < p) y[c] = Y[r + (int64_t)c * n];
-#pragma unroll
-      for (int c = 0; c < PMAX; c++) {
-        if (c < p) {
-          double s = y[c];
-#pragma unroll
-          for (int l = 0; l < PMAX; l++)
-            if (l < c) s -= y[l] * G[l * PMAX + c];
-          y[c] = s / G[c * PMAX + c];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < PMAX; c++)
-        if (c < p) Y[r + (int64_t)c * n] = y[c];
-    }
-    __syncthreads();
-  }
-  return ok;
-}
-
-// out (n x p) = in (n x p) * S (p x p, LDS, leading dim PMAX), columns permuted by perm
-__device__ void mul_small(const double* in, double* out, int n, int p, const double* S, const int* perm) {
-  for (int r = threadIdx.x; r < n; r += 256) {
-    double w[PMAX];
-#pragma unroll
-    for (int l = 0; l < PMAX; l++)
-      if (l < p) w[l] = in[r + (int64_t)l * n];
-    for (int c = 0; c < p; c++) {
-      const int pc = perm[c];
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l < PMAX; l++)
-        if (l < p) s += w[l] * S[pc * PMAX + l];
-      out[r + (int64_t)c * n] = s;
-    }
-  }
-  __syncthreads();
-}
-
 // Cyclic Jacobi on the symmetric p x p matrix H (LDS, leading dim PMAX) with
 // round-robin parallel ordering; S accumulates the rotations.
 __device__ void jacobi_eig(double* H, double* S, int p, double* cs, double* red) {
@@ -303,187 +218,223 @@ __device__ void jacobi_eig(double* H, double* S, int p, double* cs, double* red)
   }
 }
 
-// One workgroup per subdomain: top-k eigenpairs of the symmetric PSD matrix
-// C (n x n) by subspace iteration on C + sigma I (sigma = 1e-7 trace C keeps
-// the block full rank) with Rayleigh-Ritz every other step.
-__global__ void __launch_bounds__(256) k_subspace(const int* __restrict__ nT_, const int* __restrict__ kreq_,
-                                                  const int64_t* __restrict__ o_TT, const double* __restrict__ Cm,
-                                                  const int64_t* __restrict__ o_Y, double* Ybuf, double* Wbuf,
-                                                  int over, int maxit, double tol, uint64_t seed,
-                                                  const int64_t* __restrict__ o_Z, double* zv,
-                                                  const int* __restrict__ o_th, double* theta, int* kfound,
-                                                  double* resid, int* iters, double tau2, double floor_rel,
-                                                  int c0, int* err) {
-  __shared__ double H[PMAX * PMAX];
-  __shared__ double S[PMAX * PMAX];
-  __shared__ double G[PMAX * PMAX];
-  __shared__ double cs[4 * (PMAX / 2 + 1)];
+// ---------------------------------------------------------------------------
+// Batched subspace iteration with Rayleigh-Ritz for the top-k eigenpairs of
+// the symmetric PSD blocks C_i (n_i x n_i). The products with C_i and the
+// n x p by p x p products are variable-size MFMA GEMMs over all active
+// subdomains (precision T: FP32 in mixed mode, FP64 otherwise); the p x p
+// pieces (Jacobi eigensolver, Cholesky) run one workgroup per subdomain in
+// FP64. Iteration: W = (C + sigma I) Y, H = Y^T W = S Theta S^T, V = W S,
+// U = Y S (Ritz vectors), residuals ||V_j - theta_j U_j||, then
+// Y <- orth(V) (CholQR2 with column equilibration). sigma = 1e-7 trace(C)
+// keeps the block full rank when C has a null space.
+// ---------------------------------------------------------------------------
+
+// C_w = C + sigma I in precision T, and the start block: columns >= cw
+// random, the first cw = min(c0, p) from Ywarm (normalized, with a 1e-3
+// random component so that the block keeps full rank).
+template <class T>
+__global__ void __launch_bounds__(256) k_ss_init(const int* __restrict__ ids, const int* __restrict__ n_,
+                                                 const int* __restrict__ p_, const int64_t* __restrict__ oC,
+                                                 const int64_t* __restrict__ oY, const double* __restrict__ C64,
+                                                 T* Cw, T* Y, const double* __restrict__ Ywarm, int c0,
+                                                 uint64_t seed, double* sigma_out) {
   __shared__ double red[16];
-  __shared__ double th[PMAX];
-  __shared__ int perm[PMAX];
-  const int i = blockIdx.x;
-  const int n = nT_[i], k = kreq_[i];
-  const int tid = threadIdx.x;
-  if (k <= 0 || n <= 0) {
-    if (tid == 0) {
-      kfound[i] = 0;
-      resid[i] = 0.0;
-      iters[i] = 0;
-    }
-    return;
-  }
-  int p = min(n, min(PMAX, k + over));
-  const double* C = Cm + o_TT[i];
-  double* Y = Ybuf + o_Y[i];
-  double* W = Wbuf + o_Y[i];
-  // shift
+  const int i = ids[blockIdx.x];
+  const int n = n_[i], p = p_[i], tid = threadIdx.x;
+  const double* C = C64 + oC[i];
   double tr = 0.0;
   for (int r = tid; r < n; r += 256) tr += C[r + (int64_t)r * n];
   tr = block_sum(tr, red);
   const double sigma = 1e-7 * tr;
-  // start block: columns c >= cw random; the first cw columns were filled
-  // by the caller (warm start), normalized here with a 1e-3 random
-  // component added so that the block keeps full rank
+  T* Ci = Cw + oC[i];
+  for (int64_t e = tid; e < (int64_t)n * n; e += 256) {
+    const int r = (int)(e % n), c = (int)(e / n);
+    Ci[e] = (T)(C[e] + (r == c ? sigma : 0.0));
+  }
+  T* Yi = Y + oY[i];
   const int cw = min(c0, p);
   for (int64_t e = tid; e < (int64_t)n * p; e += 256) {
-    int r = (int)(e % n), c = (int)(e / n);
-    if (c >= cw) Y[e] = hash_uniform(seed, i, r, c);
+    const int r = (int)(e % n), c = (int)(e / n);
+    if (c >= cw) Yi[e] = (T)hash_uniform(seed, i, r, c);
   }
-  __syncthreads();
+  const double rs = 1e-3 * sqrt(3.0 / n);
   for (int c = 0; c < cw; c++) {
-    double* y = Y + (int64_t)c * n;
+    const double* y = Ywarm + oY[i] + (int64_t)c * n;
     double s2 = 0.0;
     for (int r = tid; r < n; r += 256) s2 += y[r] * y[r];
     s2 = block_sum(s2, red);
     const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-    const double rs = 1e-3 * sqrt(3.0 / n);
-    for (int r = tid; r < n; r += 256) y[r] = y[r] * inv + rs * hash_uniform(seed, i, r, c);
-    __syncthreads();
+    for (int r = tid; r < n; r += 256) Yi[r + (int64_t)c * n] = (T)(y[r] * inv + rs * hash_uniform(seed, i, r, c));
   }
-  bool ok = chol_qr(Y, n, p, G, red);
-  if (tid < PMAX) perm[tid] = tid;
+  if (tid == 0) sigma_out[i] = sigma;
+}
+
+// R_i = D R'^{-1} where D = diag(G)^{-1/2} and R'^T R' = D G D (Cholesky of
+// the equilibrated Gram matrix, FP64), so that Y R_i has orthonormal columns.
+template <class T>
+__global__ void __launch_bounds__(64) k_ss_chol(const int* __restrict__ ids, const int* __restrict__ p_,
+                                                const T* __restrict__ G, T* R, int* err) {
+  __shared__ double A[PMAX * PMAX];
+  __shared__ double d[PMAX];
+  const int i = ids[blockIdx.x];
+  const int p = p_[i], tid = threadIdx.x;
+  const T* Gi = G + (int64_t)i * PMAX * PMAX;
+  for (int e = tid; e < p * p; e += 64) A[(e % p) + (e / p) * PMAX] = (double)Gi[e];
   __syncthreads();
-  double maxres = 0.0;
-  int it = 0;
-  bool conv = false;
-  for (it = 1; it <= maxit; it++) {
-    // W = (C + sigma I) Y
-    for (int64_t e = tid; e < (int64_t)n * p; e += 256) {
-      int r = (int)(e % n), c = (int)(e / n);
-      const double* yc = Y + (int64_t)c * n;
-      double s = sigma * yc[r];
-      for (int l = 0; l < n; l++) s += C[r + (int64_t)l * n] * yc[l];
-      W[e] = s;
-    }
-    __syncthreads();
-    const bool rr = (it % 2 == 0) || it == maxit || p == n;
-    if (!rr) {
-      for (int64_t e = tid; e < (int64_t)n * p; e += 256) Y[e] = W[e];
-      __syncthreads();
-      ok &= chol_qr(Y, n, p, G, red);
-      continue;
-    }
-    // Rayleigh-Ritz: H = Y^T W (Y orthonormal)
-    for (int e = tid; e < p * p; e += 256) {
-      int a = e % p, b = e / p;
-      const double* ya = Y + (int64_t)a * n;
-      const double* wb = W + (int64_t)b * n;
-      double s = 0.0;
-      for (int r = 0; r < n; r++) s += ya[r] * wb[r];
-      H[b * PMAX + a] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < p * p; e += 256) {
-      int a = e % p, b = e / p;
-      if (a < b) {
-        double v = 0.5 * (H[b * PMAX + a] + H[a * PMAX + b]);
-        H[b * PMAX + a] = v;
-        H[a * PMAX + b] = v;
-      }
-    }
-    __syncthreads();
-    jacobi_eig(H, S, p, cs, red);
-    if (tid == 0) {
-      for (int a = 0; a < p; a++) th[a] = H[a * PMAX + a];
-      for (int a = 0; a < p; a++) perm[a] = a;
-      for (int a = 0; a < p; a++) {
-        int best = a;
-        for (int b = a + 1; b < p; b++)
-          if (th[perm[b]] > th[perm[best]]) best = b;
-        int t = perm[a];
-        perm[a] = perm[best];
-        perm[best] = t;
-      }
-    }
-    __syncthreads();
-    // residuals of the first k Ritz pairs: || W s_j - theta_j Y s_j ||
-    double lres[PMAX];
-#pragma unroll
-    for (int j = 0; j < PMAX; j++) lres[j] = 0.0;
-    for (int r = tid; r < n; r += 256) {
-      double y[PMAX], w[PMAX];
-#pragma unroll
-      for (int l = 0; l < PMAX; l++)
-        if (l < p) {
-          y[l] = Y[r + (int64_t)l * n];
-          w[l] = W[r + (int64_t)l * n];
-        }
-#pragma unroll
-      for (int j = 0; j < PMAX; j++) {
-        if (j < k && j < p) {
-          const int pj = perm[j];
-          double a = 0.0, b = 0.0;
-#pragma unroll
-          for (int l = 0; l < PMAX; l++)
-            if (l < p) {
-              a += w[l] * S[pj * PMAX + l];
-              b += y[l] * S[pj * PMAX + l];
-            }
-          double d = a - th[pj] * b;
-          lres[j] += d * d;
-        }
-      }
-    }
-    maxres = 0.0;
-    const double th0 = fmax(th[perm[0]], 1e-300);
-    const int kp = min(k, p);
-#pragma unroll
-    for (int j = 0; j < PMAX; j++) {
-      if (j < kp) {
-        double v = block_sum(lres[j], red);
-        maxres = fmax(maxres, sqrt(v) / th0);
-      }
-    }
-    conv = (maxres <= tol) || p == n;
-    if (conv || it == maxit) {
-      mul_small(Y, W, n, p, S, perm);  // Ritz vectors
-      break;
-    }
-    mul_small(W, Y, n, p, S, perm);  // power step on the Ritz vectors
-    ok &= chol_qr(Y, n, p, G, red);
+  if (tid < p) {
+    const double g = A[tid + tid * PMAX];
+    d[tid] = g > 0.0 ? 1.0 / sqrt(g) : 1.0;
   }
-  if (it > maxit) it = maxit;
-  // selection: Ritz values minus the shift, descending
+  __syncthreads();
+  for (int e = tid; e < p * p; e += 64) {
+    const int a = e % p, b = e / p;
+    A[a + b * PMAX] *= d[a] * d[b];
+  }
   __syncthreads();
   if (tid == 0) {
-    const double top = th[perm[0]] - sigma;
+    bool ok = true;
+    // upper Cholesky in place: A = R^T R, R stored in the upper triangle
+    for (int j = 0; j < p; j++) {
+      double v = A[j + j * PMAX];
+      for (int l = 0; l < j; l++) v -= A[l + j * PMAX] * A[l + j * PMAX];
+      if (!(v > 1e-28)) {
+        ok = false;
+        v = 1e-28;
+      }
+      v = sqrt(v);
+      A[j + j * PMAX] = v;
+      for (int c = j + 1; c < p; c++) {
+        double t = A[j + c * PMAX];
+        for (int l = 0; l < j; l++) t -= A[l + j * PMAX] * A[l + c * PMAX];
+        A[j + c * PMAX] = t / v;
+      }
+    }
+    // R^{-1} (upper) in place, column by column from the right
+    for (int j = p - 1; j >= 0; j--) {
+      A[j + j * PMAX] = 1.0 / A[j + j * PMAX];
+      for (int r = j - 1; r >= 0; r--) {
+        double t = 0.0;
+        for (int l = r + 1; l <= j; l++) t += A[r + l * PMAX] * A[l + j * PMAX];
+        A[r + j * PMAX] = -t / A[r + r * PMAX];
+      }
+    }
+    if (!ok) atomicOr(err, ERR_EIG);
+  }
+  __syncthreads();
+  T* Ri = R + (int64_t)i * PMAX * PMAX;
+  for (int e = tid; e < p * p; e += 64) {
+    const int a = e % p, b = e / p;
+    Ri[e] = (T)(a <= b ? d[a] * A[a + b * PMAX] : 0.0);
+  }
+}
+
+// Rayleigh-Ritz on H = Y^T W (p x p): S (eigenvectors, columns sorted by
+// descending eigenvalue) and theta.
+template <class T>
+__global__ void __launch_bounds__(256) k_ss_rr(const int* __restrict__ ids, const int* __restrict__ p_,
+                                               const T* __restrict__ Hm, T* Sout, double* th) {
+  __shared__ double H[PMAX * PMAX];
+  __shared__ double S[PMAX * PMAX];
+  __shared__ double cs[4 * (PMAX / 2 + 1)];
+  __shared__ double red[16];
+  __shared__ int perm[PMAX];
+  const int i = ids[blockIdx.x];
+  const int p = p_[i], tid = threadIdx.x;
+  const T* Hi = Hm + (int64_t)i * PMAX * PMAX;
+  for (int e = tid; e < PMAX * PMAX; e += 256) H[e] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < p * p; e += 256) {
+    const int a = e % p, b = e / p;
+    H[b * PMAX + a] = 0.5 * ((double)Hi[a + b * p] + (double)Hi[b + a * p]);
+  }
+  __syncthreads();
+  jacobi_eig(H, S, p, cs, red);
+  if (tid == 0) {
+    for (int a = 0; a < p; a++) perm[a] = a;
+    for (int a = 0; a < p; a++) {
+      int best = a;
+      for (int b = a + 1; b < p; b++)
+        if (H[perm[b] * PMAX + perm[b]] > H[perm[best] * PMAX + perm[best]]) best = b;
+      const int t = perm[a];
+      perm[a] = perm[best];
+      perm[best] = t;
+    }
+  }
+  __syncthreads();
+  T* Si = Sout + (int64_t)i * PMAX * PMAX;
+  for (int e = tid; e < p * p; e += 256) {
+    const int l = e % p, j = e / p;
+    Si[e] = (T)S[perm[j] * PMAX + l];
+  }
+  if (tid < p) th[(int64_t)i * PMAX + tid] = H[perm[tid] * PMAX + perm[tid]];
+}
+
+// Largest relative residual ||V_j - theta_j U_j|| / theta_0 over the first
+// min(k, p) Ritz pairs; converged when it is <= tol (or when p == n).
+template <class T>
+__global__ void __launch_bounds__(256) k_ss_resid(const int* __restrict__ ids, const int* __restrict__ n_,
+                                                  const int* __restrict__ p_, const int* __restrict__ k_,
+                                                  const int64_t* __restrict__ oY, const T* __restrict__ V,
+                                                  const T* __restrict__ U, const double* __restrict__ th, double tol,
+                                                  double* res, int* conv) {
+  __shared__ double red[16];
+  const int i = ids[blockIdx.x];
+  const int n = n_[i], p = p_[i], kp = min(k_[i], p), tid = threadIdx.x;
+  const double* t = th + (int64_t)i * PMAX;
+  const double th0 = fmax(t[0], 1e-300);
+  const T* Vi = V + oY[i];
+  const T* Ui = U + oY[i];
+  double mx = 0.0;
+  for (int j = 0; j < kp; j++) {
+    double r2 = 0.0;
+    for (int r = tid; r < n; r += 256) {
+      const double dv = (double)Vi[r + (int64_t)j * n] - t[j] * (double)Ui[r + (int64_t)j * n];
+      r2 += dv * dv;
+    }
+    r2 = block_sum(r2, red);
+    mx = fmax(mx, sqrt(r2) / th0);
+  }
+  if (tid == 0) {
+    res[i] = mx;
+    conv[i] = (mx <= tol || p == n) ? 1 : 0;
+  }
+}
+
+__global__ void k_flag_eig(int* err) { atomicOr(err, ERR_EIG); }
+
+// Selection (descending, minus the shift, above floor_rel * top and thresh)
+// and output of the kept eigenvectors (FP64, n x kf at oZ[i]).
+template <class T>
+__global__ void __launch_bounds__(256) k_ss_final(const int* __restrict__ ids, const int* __restrict__ n_,
+                                                  const int* __restrict__ p_, const int* __restrict__ k_,
+                                                  const int64_t* __restrict__ oY, const T* __restrict__ U,
+                                                  const double* __restrict__ th, const double* __restrict__ sigma,
+                                                  double thresh, double floor_rel, const int64_t* __restrict__ oZ,
+                                                  double* zv, const int* __restrict__ o_th, double* theta,
+                                                  int* kfound) {
+  __shared__ int s_kf;
+  const int i = ids[blockIdx.x];
+  const int n = n_[i], p = p_[i], kp = min(k_[i], p), tid = threadIdx.x;
+  const double* t = th + (int64_t)i * PMAX;
+  if (tid == 0) {
+    const double top = t[0] - sigma[i];
     int kf = 0;
-    for (int j = 0; j < min(k, p); j++) {
-      double v = th[perm[j]] - sigma;
-      if (v > floor_rel * top && v > tau2 && top > 0.0)
+    for (int j = 0; j < kp; j++) {
+      const double v = t[j] - sigma[i];
+      if (v > floor_rel * top && v > thresh && top > 0.0)
         kf++;
       else
         break;
     }
-    for (int j = 0; j < kf; j++) theta[o_th[i] + j] = th[perm[j]] - sigma;
+    for (int j = 0; j < kf; j++) theta[o_th[i] + j] = t[j] - sigma[i];
     kfound[i] = kf;
-    resid[i] = maxres;
-    iters[i] = it;
-    if (!ok || !conv) atomicOr(err, ERR_EIG);
+    s_kf = kf;
   }
   __syncthreads();
-  const int kf = kfound[i];
-  for (int64_t e = tid; e < (int64_t)n * kf; e += 256) zv[o_Z[i] + e] = W[e];
+  const int kf = s_kf;
+  const T* Ui = U + oY[i];
+  for (int64_t e = tid; e < (int64_t)n * kf; e += 256) zv[oZ[i] + e] = (double)Ui[e];
 }
 
 // Orthonormalize the coarse columns of subdomain i (rows I_i), dropping
@@ -608,40 +559,148 @@ struct PassEig {
   std::vector<double> theta;   // their eigenvalues of C, at oth[i] + j
   double resid_max = 0.0;
   int iters_max = 0;
+  double iters_sum = 0.0;
+  int n_solved = 0;
 };
 
 // Top eigenpairs of C (nT x nT per subdomain, fp64, in C64) by subspace
 // iteration; the eigenvectors land in zv (nT x kf, offsets oZv).
-// Ypre (optional): start block already holding c0 warm columns per subdomain.
-static PassEig run_subspace(tls_ctx* c, const PassDims& d, PassDev& dv, const DBuf<double>& C64, DBuf<double>& zv,
-                            double thresh, DBuf<double>* Ypre = nullptr, int c0 = 0) {
+// Batched subspace iteration driver (kernels above) in precision T.
+template <class T>
+static PassEig subspace_batched(tls_ctx* c, const PassDims& d, PassDev& dv, const DBuf<double>& C64,
+                                DBuf<double>& zv, double thresh, const double* Ywarm, int c0) {
   hipStream_t s = c->stream;
   const int N = c->N;
-  DBuf<double> Yown, Wb, theta, resid;
-  DBuf<int> kfound, its;
-  DBuf<double>& Yb = Ypre ? *Ypre : Yown;
-  if (!Ypre) Yown.alloc(std::max<int64_t>(d.oY[N], 1));
-  Wb.alloc(std::max<int64_t>(d.oY[N], 1));
-  zv.alloc(std::max<int64_t>(d.oZv[N], 1));
-  theta.alloc(std::max(d.oth[N], 1));
-  resid.alloc(N);
-  kfound.alloc(N);
-  its.alloc(N);
-  const double tol = c->opt.eig_tol > 0 ? c->opt.eig_tol : (c->fp32 ? 1e-6 : 1e-9);
-  hipLaunchKernelGGL(k_subspace, dim3(N), dim3(256), 0, s, dv.nT.p, dv.kreq.p, dv.oTT.p, C64.p, dv.oY.p, Yb.p, Wb.p,
-                     d.over, c->opt.eig_maxit, tol, (uint64_t)c->opt.seed, dv.oZv.p, zv.p, dv.oth.p,
-                     theta.p, kfound.p, resid.p, its.p, thresh, 1e-12, Ypre ? c0 : 0, c->errflag.p);
-  TLS_LAUNCH_CHECK();
-  PassEig e;
-  e.kf = download(kfound.p, N, s);
-  auto h_res = download(resid.p, N, s);
-  auto h_its = download(its.p, N, s);
-  e.theta = download(theta.p, std::max(d.oth[N], 1), s);
+  std::vector<int> p(N, 0), all;
   for (int i = 0; i < N; i++) {
-    e.resid_max = std::max(e.resid_max, h_res[i]);
-    e.iters_max = std::max(e.iters_max, h_its[i]);
+    if (d.kreq[i] <= 0 || d.nT[i] <= 0) continue;
+    p[i] = std::min(d.nT[i], std::min(PMAX, d.kreq[i] + d.over));
+    all.push_back(i);
   }
+  PassEig e;
+  e.kf.assign(N, 0);
+  e.theta.assign(std::max(d.oth[N], 1), 0.0);
+  zv.alloc(std::max<int64_t>(d.oZv[N], 1));
+  if (all.empty()) return e;
+  DBuf<int> d_p, ids, conv, kfound;
+  d_p.upload(p, s);
+  DBuf<T> Cw, Y, W, V, U, Hb, Sb;
+  DBuf<double> th, sig, res, theta;
+  Cw.alloc(std::max<int64_t>(d.oTT[N], 1));
+  for (auto* b : {&Y, &W, &V, &U}) b->alloc(std::max<int64_t>(d.oY[N], 1));
+  Hb.alloc((size_t)N * PMAX * PMAX);
+  Sb.alloc((size_t)N * PMAX * PMAX);
+  th.alloc((size_t)N * PMAX);
+  sig.alloc(N);
+  res.alloc(N);
+  conv.alloc(N);
+  kfound.alloc(N);
+  theta.alloc(std::max(d.oth[N], 1));
+  ids.upload(all, s);
+  DBuf<double> nowarm;
+  if (!Ywarm) nowarm.alloc(1);
+  hipLaunchKernelGGL(k_ss_init<T>, dim3((unsigned)all.size()), dim3(256), 0, s, ids.p, dv.nT.p, d_p.p, dv.oTT.p,
+                     dv.oY.p, C64.p, Cw.p, Y.p, Ywarm ? Ywarm : nowarm.p, Ywarm ? c0 : 0, (uint64_t)c->opt.seed,
+                     sig.p);
+  TLS_LAUNCH_CHECK();
+  GemmPlan pCY, pTN, pNP;  // n x p = C Y;  p x p = X^T Y;  n x p = X (p x p)
+  std::vector<int> act = all;
+  auto plans = [&](const std::vector<int>& a) {
+    std::vector<GemmDesc> g1, g2, g3;
+    for (int i : a) {
+      const int n = d.nT[i], pi = p[i];
+      const int64_t oS = (int64_t)i * PMAX * PMAX;
+      g1.push_back(GemmDesc{n, pi, n, n, n, d.oTT[i], d.oY[i], d.oY[i], (int64_t)n});
+      g2.push_back(GemmDesc{pi, pi, n, n, n, d.oY[i], d.oY[i], oS, (int64_t)pi});
+      g3.push_back(GemmDesc{n, pi, pi, n, pi, d.oY[i], oS, d.oY[i], (int64_t)n});
+    }
+    gemm_plan(pCY, g1, s);
+    gemm_plan(pTN, g2, s);
+    gemm_plan(pNP, g3, s);
+    ids.upload(a, s);
+    TLS_HIP(hipStreamSynchronize(s));
+  };
+  // Y <- orth(X) by CholQR with equilibration, twice; X is overwritten
+  auto orth = [&](T* X) {
+    for (int pass = 0; pass < 2; pass++) {
+      T* src = pass == 0 ? X : Y.p;
+      T* dst = pass == 0 ? Y.p : X;
+      gemm_run<T>(s, pTN, true, false, src, src, Hb.p, T(1), T(0));
+      hipLaunchKernelGGL(k_ss_chol<T>, dim3((unsigned)act.size()), dim3(64), 0, s, ids.p, d_p.p, Hb.p, Sb.p,
+                         c->errflag.p);
+      TLS_LAUNCH_CHECK();
+      gemm_run<T>(s, pNP, false, false, src, Sb.p, dst, T(1), T(0));
+    }
+    // the result of the second pass is in X: copy it back into Y
+    TLS_HIP(hipMemcpyAsync(Y.p, X, sizeof(T) * std::max<int64_t>(d.oY[N], 1), hipMemcpyDeviceToDevice, s));
+  };
+  plans(act);
+  TLS_HIP(hipMemcpyAsync(V.p, Y.p, sizeof(T) * std::max<int64_t>(d.oY[N], 1), hipMemcpyDeviceToDevice, s));
+  orth(V.p);
+  const double tol = c->opt.eig_tol > 0 ? c->opt.eig_tol : (c->fp32 ? 1e-5 : 1e-9);
+  const int maxit = c->opt.eig_maxit;
+  std::vector<int> iters(N, 0);
+  std::vector<double> hres(N, 0.0);
+  std::vector<std::vector<double>> res_hist(N);
+  for (int it = 1; it <= maxit && !act.empty(); it++) {
+    gemm_run<T>(s, pCY, false, false, Cw.p, Y.p, W.p, T(1), T(0));      // W = C Y
+    gemm_run<T>(s, pTN, true, false, Y.p, W.p, Hb.p, T(1), T(0));       // H = Y^T W
+    hipLaunchKernelGGL(k_ss_rr<T>, dim3((unsigned)act.size()), dim3(256), 0, s, ids.p, d_p.p, Hb.p, Sb.p, th.p);
+    TLS_LAUNCH_CHECK();
+    gemm_run<T>(s, pNP, false, false, W.p, Sb.p, V.p, T(1), T(0));      // V = W S
+    gemm_run<T>(s, pNP, false, false, Y.p, Sb.p, U.p, T(1), T(0));      // U = Y S
+    hipLaunchKernelGGL(k_ss_resid<T>, dim3((unsigned)act.size()), dim3(256), 0, s, ids.p, dv.nT.p, d_p.p,
+                       dv.kreq.p, dv.oY.p, V.p, U.p, th.p, tol, res.p, conv.p);
+    TLS_LAUNCH_CHECK();
+    auto h_conv = download(conv.p, N, s);
+    auto h_res = download(res.p, N, s);
+    std::vector<int> next;
+    for (int i : act) {
+      iters[i] = it;
+      hres[i] = h_res[i];
+      if (std::isnan(h_res[i])) fail(TLS_E_NOCONV, "local eigensolver: NaN residual in subdomain " + std::to_string(i));
+      // stagnation at the rounding floor of the working precision: accept a
+      // residual below 10 tol that has not dropped 5% in four iterations
+      auto& hist = res_hist[i];
+      hist.push_back(h_res[i]);
+      if (!h_conv[i] && hist.size() > 4 && h_res[i] <= 10.0 * tol && h_res[i] > 0.95 * hist[hist.size() - 5])
+        h_conv[i] = 1;
+      if (!h_conv[i] && it < maxit) next.push_back(i);
+      if (!h_conv[i] && it == maxit) {
+        hipLaunchKernelGGL(k_flag_eig, dim3(1), dim3(1), 0, s, c->errflag.p);
+        TLS_LAUNCH_CHECK();
+      }
+    }
+    if (next.empty()) break;
+    if (next.size() != act.size()) {
+      act = next;
+      plans(act);
+    }
+    orth(V.p);  // Y <- orth(V)
+  }
+  ids.upload(all, s);
+  hipLaunchKernelGGL(k_ss_final<T>, dim3((unsigned)all.size()), dim3(256), 0, s, ids.p, dv.nT.p, d_p.p, dv.kreq.p,
+                     dv.oY.p, U.p, th.p, sig.p, thresh, 1e-12, dv.oZv.p, zv.p, dv.oth.p, theta.p, kfound.p);
+  TLS_LAUNCH_CHECK();
+  auto kf = download(kfound.p, N, s);
+  auto tt = download(theta.p, std::max(d.oth[N], 1), s);
+  for (int i : all) {
+    e.kf[i] = kf[i];
+    e.resid_max = std::max(e.resid_max, hres[i]);
+    e.iters_max = std::max(e.iters_max, iters[i]);
+    e.iters_sum += iters[i];
+  }
+  e.n_solved = (int)all.size();
+  e.theta = tt;
   return e;
+}
+
+// Ypre (optional): FP64 start block holding c0 warm columns per subdomain.
+static PassEig run_subspace(tls_ctx* c, const PassDims& d, PassDev& dv, const DBuf<double>& C64, DBuf<double>& zv,
+                            double thresh, DBuf<double>* Ypre = nullptr, int c0 = 0) {
+  const double* yw = Ypre ? Ypre->p : nullptr;
+  if (c->fp32) return subspace_batched<float>(c, d, dv, C64, zv, thresh, yw, c0);
+  return subspace_batched<double>(c, d, dv, C64, zv, thresh, yw, c0);
 }
 
 // One SPD pass (see the file header): F = -L_TI^T + L_GI^T L_GG^{-T} L_TG^T,
@@ -863,6 +922,7 @@ static void basis_spd(tls_ctx* c, T* fac) {
   }
   c->eig_resid_max = std::max(e2.resid_max, e1.resid_max);
   c->eig_iters_max = std::max(e2.iters_max, e1.iters_max);
+  c->eig_iters_mean = (e2.iters_sum + e1.iters_sum) / std::max(1, e2.n_solved + e1.n_solved);
   // x = L^{-T} [V; 0] per column with the persistent solve: rows I = L_II^{-T} V
   std::vector<int> ncols(N);
   int kfm = 0;
@@ -979,6 +1039,7 @@ static void basis_general(tls_ctx* c, T* fac) {
   C64.release();
   c->eig_resid_max = e.resid_max;
   c->eig_iters_max = e.iters_max;
+  c->eig_iters_mean = e.iters_sum / std::max(1, e.n_solved);
   // left singular directions: V = H v
   DBuf<T> wT, XV;
   wT.alloc(std::max<int64_t>(oZv[N], 1));

@@ -7,13 +7,17 @@
 //
 // Network (all FP32), Omega_i in its local order [I, Gamma_1, .., Gamma_delta]:
 //   edges   e_ab = |a_ab| / sqrt(|a_aa| |a_bb|) for a != b, (A_ii)_ab != 0
-//   H_0     = [1, 1{a in I_i}, 1{a in Gamma_{i,delta}}, log10(|a_aa| / mean |a_bb|)]
+//   H_0     = [1, 1{a in I_i}, 1{a in Gamma_{i,delta}}, log10(|a_aa| / mean |a_bb|),
+//              r_a0 .. r_a7], r_aj = 2 u - 1, u = (z >> 11) 2^-53, z = output
+//              8a + j + 1 of SplitMix64 from state 0 (a = local index)
 //   H_l     = tanh(E H_{l-1} Theta_l + H_{l-1} Phi_l + b_l),  l = 1..4, width 32
 //   X       = H_4 Omega  (c_out columns)
 // Loss of subdomain i against an orthonormal basis Q_i (#T x k_i) of the
 // rows T = Gamma_{i,delta} of its top-k eigenvectors:
-//   f_i = -(1/k_i) tr(G^{-1} X_T^T Q Q^T X_T),  G = X_T^T X_T,
-//   df_i/dX_T = -(2/k_i) (Q Q^T X_T G^{-1} - X_T G^{-1} B G^{-1}),  B = X_T^T Q Q^T X_T.
+//   f_i = -(1/k_i) tr(G^{-1} B),  G = X_T^T X_T + EPS (tr(X_T^T X_T) / c) I,
+//   B = X_T^T Q Q^T X_T,  EPS = 1e-3,
+//   df_i/dX_T = -(2/k_i) (Q Q^T X_T G^{-1} - X_T T2 - (EPS / c) tr(T2) X_T),
+//   T2 = G^{-1} B G^{-1}.
 //
 // Data layout: every node of every subdomain is one "position" p of the
 // concatenated Omega lists (sub_idx order); node features and hidden
@@ -34,6 +38,8 @@ namespace {
 
 constexpr int HID = TLS_GNN_HIDDEN;
 constexpr int NF = TLS_GNN_FEATURES;
+constexpr int NR = TLS_GNN_RANDOM;  // random input channels (the last NR features)
+constexpr double EPS = 1e-3;        // loss regularization
 constexpr int NL = TLS_GNN_LAYERS;
 constexpr int SLOTS = 256 / HID;  // nodes per workgroup pass
 constexpr int GNN_BLOCKS = 1024;  // persistent workgroups of the node kernels
@@ -117,6 +123,14 @@ __global__ void k_gnn_edges(int mode, int total, const int* __restrict__ sub_idx
   if (!mode) cnt[p] = k;
 }
 
+// output counter + 1 of SplitMix64 started from state 0
+__device__ inline uint64_t splitmix64(uint64_t counter) {
+  uint64_t z = (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // features of every position of subdomain i (one workgroup per subdomain)
 __global__ void k_gnn_features(const int* __restrict__ sub_ptr, const int* __restrict__ nI_,
                                const int* __restrict__ nP_, const float* __restrict__ dg, float* feat) {
@@ -137,6 +151,10 @@ __global__ void k_gnn_features(const int* __restrict__ sub_ptr, const int* __res
     f[1] = a < nI ? 1.f : 0.f;
     f[2] = a >= nP ? 1.f : 0.f;
     f[3] = (d > 0.0 && mean > 0.0) ? (float)log10(d / mean) : 0.f;
+    for (int j = 0; j < NR; j++) {
+      const uint64_t z = splitmix64((uint64_t)a * NR + j);
+      f[NF - NR + j] = (float)((double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0);
+    }
   }
 }
 
@@ -376,6 +394,13 @@ __global__ void __launch_bounds__(256) k_gnn_loss(const int* __restrict__ sub_pt
     B[a + b * CMAX] = s;
   }
   __syncthreads();
+  // G <- G + EPS (tr G / c) I
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int a = 0; a < c; a++) tr += G[a + a * CMAX];
+    for (int a = 0; a < c; a++) G[a + a * CMAX] += EPS * tr / c;
+  }
+  __syncthreads();
   // G^{-1} by Gauss-Jordan on the SPD matrix (no pivoting needed), one thread
   if (tid == 0) {
     int ok = 1;
@@ -437,13 +462,16 @@ __global__ void __launch_bounds__(256) k_gnn_loss(const int* __restrict__ sub_pt
     T2[a + b * CMAX] = s;  // A1 G^{-1} (k x c)
   }
   __syncthreads();
-  // dX_T = -(2/k) scale (Q A1 G^{-1} - X_T G^{-1} B G^{-1})
+  // dX_T = -(2/k) scale (Q A1 G^{-1} - X_T G^{-1} B G^{-1} - (EPS/c) tr(G^{-1} B G^{-1}) X_T)
+  double trT = 0.0;
+  for (int a = 0; a < c; a++) trT += B[a + a * CMAX];
   const double f2 = -2.0 * scale / k;
   for (int64_t x = tid; x < (int64_t)nT * c; x += 256) {
     const int r = (int)(x / c), b = (int)(x % c);
     double s = 0.0;
     for (int q = 0; q < k; q++) s += Qi[r + (int64_t)q * nT] * T2[q + b * CMAX];
     for (int q = 0; q < c; q++) s -= (double)X[(r0 + r) * c + q] * B[q + b * CMAX];
+    s -= (EPS / c) * trT * (double)X[(r0 + r) * c + b];
     dX[(r0 + r) * c + b] = (float)(f2 * s);
   }
 }
@@ -510,7 +538,8 @@ __global__ void k_gnn_take_rows(const int* __restrict__ sub_ptr, const int* __re
 }  // namespace
 
 void gnn_check_weights(int c_out) {
-  if (c_out < 1 || c_out > CMAX) fail(TLS_E_ARG, "gnn c_out must be in [1, 64]");
+  // X = H_4 Omega has rank <= HIDDEN: more columns would be dependent
+  if (c_out < 1 || c_out > HID) fail(TLS_E_ARG, "gnn c_out must be in [1, TLS_GNN_HIDDEN]");
 }
 
 int gnn_n_weights(int c_out) { return woff(c_out).total; }

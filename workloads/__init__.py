@@ -14,9 +14,11 @@ from .problems import (  # noqa: F401
     box_partition_3d,
     convdiff_2d,
     elasticity_q1_3d,
+    elasticity_training_instances,
     fv_diffusion_2d,
     fv_diffusion_3d,
     high_contrast_kappa_2d,
+    layered_elasticity,
     lognormal_kappa_3d,
     make_config,
     poisson_2d,

@@ -369,6 +369,37 @@ def worked_example_7x7() -> tuple[sp.csr_matrix, np.ndarray]:
     return A, part
 
 
+def layered_elasticity(nn: int, thick: int, phase: int) -> tuple[sp.csr_matrix, np.ndarray, int]:
+    """Q1 elasticity on nn^3 nodes with Young's modulus in z-slabs of
+    ``thick`` elements alternating 1 / 1e4 (shifted by ``phase``), nu = 0.3,
+    face x = 0 clamped; partition into boxes of 6^3 nodes. Returns
+    (A, part, n_parts)."""
+    ne = nn - 1
+    zc = np.arange(ne)
+    layer = ((zc + phase) // thick) % 2
+    E1d = np.where(layer == 0, 1.0, 1e4)
+    E = np.broadcast_to(E1d[:, None, None], (ne, ne, ne)).copy()
+    A, node_of_dof = elasticity_q1_3d(nn, E)
+    x = node_of_dof % nn
+    y = (node_of_dof // nn) % nn
+    z = node_of_dof // (nn * nn)
+    pb = max(1, nn // 6)
+    part = box_partition_3d(nn, nn, nn, pb, pb, pb, x, y, z)
+    return A, part, pb ** 3
+
+
+def elasticity_training_instances(count: int, seed0: int = 100, nn: int = 48):
+    """Seeded training instances for the warm-start network: the layered
+    elasticity family with slab thickness uniform in {2..8} and a uniform
+    phase. Yields (seed, thick, phase, A, part, n_parts)."""
+    for j in range(count):
+        rng = np.random.default_rng(seed0 + j)
+        thick = int(rng.integers(2, 9))
+        phase = int(rng.integers(0, thick))
+        A, part, nparts = layered_elasticity(nn, thick, phase)
+        yield seed0 + j, thick, phase, A, part, nparts
+
+
 # --------------------------------------------------------------------------
 # Benchmark configurations
 # --------------------------------------------------------------------------
@@ -414,20 +445,9 @@ def make_config(cfg: int, seed: int = 0, scale: int | None = None) -> Problem:
                        {"grid": (nx, nx, nx), "levels": levels})
     if cfg == 4:
         nn = scale or 48
-        ne = nn - 1
-        thick, phase = 4, 0
-        zc = np.arange(ne)
-        layer = ((zc + phase) // thick) % 2
-        E1d = np.where(layer == 0, 1.0, 1e4)
-        E = np.broadcast_to(E1d[:, None, None], (ne, ne, ne)).copy()
-        A, node_of_dof = elasticity_q1_3d(nn, E)
-        x = node_of_dof % nn
-        y = (node_of_dof // nn) % nn
-        z = node_of_dof // (nn * nn)
-        pb = max(1, nn // 6)
-        part = box_partition_3d(nn, nn, nn, pb, pb, pb, x, y, z)
-        return Problem("cfg4", A, part, pb ** 3, 1, 20, rhs(A.shape[0], seed + 1000), True,
-                       {"nodes": nn, "E_layers": (thick, phase)})
+        A, part, nparts = layered_elasticity(nn, 4, 0)
+        return Problem("cfg4", A, part, nparts, 1, 20, rhs(A.shape[0], seed + 1000), True,
+                       {"nodes": nn, "E_layers": (4, 0)})
     if cfg == 5:
         m = scale or 1024
         A, meta = convdiff_2d(m, rng)
