@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# weights trained by this script with its defaults (see the file's header lines)
+TRAINED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "gnn_layered_elasticity_c32.txt")
+
 
 def init_weights(c_out: int, seed: int) -> np.ndarray:
     """Uniform in +-sqrt(3 / fan_in) per block (variance 1 / fan_in)."""

@@ -576,3 +576,39 @@ def test_gnn_warm_start_keeps_the_result(precision):
     assert i1["t_setup"][4] > 0.0
     p0.close()
     p1.close()
+
+
+def test_gnn_trained_weights_gain_on_layered_elasticity():
+    """The committed weights (trained by paper_2401_03915_amd.gnn_train on
+    seeds 100-103) on the layered-elasticity workload of seed 0, FP64: the
+    training loss is far below that of the initial weights, the warm start
+    takes fewer subspace iterations on average than the random start, and
+    the final PCG iteration counts and eigen-residuals stay within 5% / the
+    tolerance of the method without it."""
+    torch = torch_cuda()
+    from paper_2401_03915_amd.gnn_train import TRAINED, init_weights, load_weights
+    w, c_out = load_weights(TRAINED)
+    p = make_config(4)
+    say("gnn trained weights: loss")
+    pt = _pc(p.A, p.part, p.overlap, p.nev, gnn_train=1)
+    loss_trained, _ = pt.gnn_loss_grad(w, c_out)
+    loss_init, _ = pt.gnn_loss_grad(init_weights(c_out, 100), c_out)
+    pt.close()
+    say("  loss trained / initial", loss_trained, loss_init)
+    assert loss_trained < 2.0 * loss_init  # losses are negative: at least twice the captured span
+    b = to_dev(p.b)
+    out = {}
+    for name, kw in (("random", {}), ("warm", {"gnn_weights": w})):
+        say("gnn trained weights:", name)
+        pc = _pc(p.A, p.part, p.overlap, p.nev, use_graph=1, **kw)
+        _, it, rr, st = pc.solve(b, 1e-8)
+        torch.cuda.synchronize()
+        inf = pc.info()
+        out[name] = (it, rr, inf["eig_iters_mean"], inf["eig_resid_max"])
+        pc.close()
+    say("  (PCG iters, relres, mean eig iters, eig resid)", out)
+    (it0, rr0, e0, res0), (it1, rr1, e1, res1) = out["random"], out["warm"]
+    assert rr0 <= 1e-8 and rr1 <= 1e-8
+    assert abs(it1 - it0) <= 0.05 * it0
+    assert res1 <= 1e-8 and res0 <= 1e-8  # eig_tol 1e-9; a stalled residual up to 10x is accepted
+    assert e1 < e0
