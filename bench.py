@@ -31,12 +31,11 @@ if ROOT not in sys.path:
 METRIC = "time-to-solve (rel res 1e-8) + precond applies/s: mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel (k_trsv<float, FWD_L> on the
-# default workload) from two rocprofv3 counter runs: median FETCH_SIZE
-# 8,000,347 KiB x 1.99991 + WRITE_SIZE 5,762 KiB x 0.99999, the factors being
-# what the same counters read for a 1 GiB read + 1 GiB write elementwise copy
-# (--copy-probe). Set to None whenever that kernel changes until the counters
-# are taken again.
-TRAFFIC = 16389903970
+# default workload) from two rocprofv3 counter runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), scaled by what the same counters read for a
+# 1 GiB read + 1 GiB write elementwise copy (--copy-probe). None whenever that
+# kernel has changed since the counters were taken.
+TRAFFIC = None
 
 
 def log(*a):

@@ -199,6 +199,8 @@ void build_coarse_operator(tls_ctx* c) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
     fail(TLS_E_SINGULAR, "zero pivot in the LU factorization of the coarse operator Z^T A Z");
   }
+  c->dinv0.alloc((size_t)c->nt0 * TS2);
+  diag_inverse_f64(s, 1, c->nt0, c->layout0(), c->kind, c->A0.p, c->dinv0.p);
   build_plan(c->plan0_fwd, false, one_nt, toff, 1, s);
   build_plan(c->plan0_bwd, true, one_nt, toff, 1, s);
   c->counters0.alloc(4);
@@ -223,9 +225,9 @@ void coarse_solve(tls_ctx* c, const int* done) {
   solve_begin(s, c->counters0.p, done);
   const int grid = std::min(c->plan0_fwd.ntasks, 512);
   trsv_f64(s, c->kind == 0 ? 0 : 2, c->plan0_fwd, c->counters0.p + 0, c->counters0.p + 2, c->layout0(), c->A0.p,
-           c->y0.p, c->errflag.p, done, grid);
+           c->dinv0.p, c->y0.p, c->errflag.p, done, grid);
   trsv_f64(s, c->kind == 0 ? 1 : 3, c->plan0_bwd, c->counters0.p + 1, c->counters0.p + 2, c->layout0(), c->A0.p,
-           c->y0.p, c->errflag.p, done, grid);
+           c->dinv0.p, c->y0.p, c->errflag.p, done, grid);
 }
 
 }  // namespace tls

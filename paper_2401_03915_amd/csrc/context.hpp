@@ -41,6 +41,9 @@ struct tls_ctx {
   tls::DBuf<double> fac64;
   tls::DBuf<float> fac32;
   tls::DBuf<double> scale;  // Jacobi scaling per padded position (or empty)
+  // inverses of the diagonal tiles (one per tile row, at (toff_i + r) * 64^2)
+  tls::DBuf<double> dinv64;
+  tls::DBuf<float> dinv32;
 
   // factorization schedule: subdomains sorted by nt (desc); per step prefix tables
   std::vector<int> h_order;
@@ -71,6 +74,7 @@ struct tls_ctx {
   tls::DBuf<int64_t> zoff;
   tls::DBuf<double> A0;     // tile storage of A_0 (then its factor)
   tls::DBuf<double> A0_orig;  // lower tiles of A_0 before factorization (export)
+  tls::DBuf<double> dinv0;    // inverses of the diagonal tiles of the factor of A_0
   tls::DBuf<int> kz_dev;    // coarse columns per subdomain
   tls::DBuf<double> y0;     // coarse vector (padded to M0)
   tls::SolvePlan plan0_fwd, plan0_bwd;

@@ -700,6 +700,70 @@ __device__ inline V stream_load(const V* p) {
 
 constexpr long long SPIN_LIMIT = 1ll << 26;
 
+// Inverse of every diagonal tile of the local factors, one 64-thread
+// workgroup per tile (block row g of the concatenated tile rows), in FP64
+// from the stored factor; thread j computes column j. Cholesky: L_rr^{-1}
+// (lower, zeros above). LU: the unit lower inverse strictly below the
+// diagonal and U_rr^{-1} on and above it, packed like the LU tile.
+template <class T>
+__global__ void __launch_bounds__(64) k_diag_inv(int N, LocalLayout lay, int kind, const T* __restrict__ fac,
+                                                 T* dinv) {
+  constexpr int L1 = TS + 1;
+  __shared__ double Ls[TS * L1];
+  const int64_t g = blockIdx.x;
+  int lo = 0, hi = N - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (lay.toff[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int i = lo;
+  const int r = (int)(g - lay.toff[i]);
+  const int nt = lay.nt[i];
+  const T* dt = fac + lay.foff[i] + tile_index(kind, nt, r, r) * TS2;
+  const int j = threadIdx.x;
+  for (int e = j; e < TS2; e += TS) Ls[(e % TS) + (e / TS) * L1] = (double)dt[e];  // (row, col) at row + col * L1
+  __syncthreads();
+  T* out = dinv + g * TS2 + (int64_t)j * TS;  // column j of the inverse
+  double x[TS];
+  // lower part: L x = e_j (unit diagonal for LU)
+#pragma unroll
+  for (int a = 0; a < TS; a++) {
+    double v = (a == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int b = 0; b < a; b++) v -= Ls[a + b * L1] * x[b];
+    x[a] = a < j ? 0.0 : (kind == 0 ? v / Ls[a + a * L1] : v);
+  }
+  if (kind == 0) {
+#pragma unroll
+    for (int a = 0; a < TS; a++) out[a] = (T)x[a];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < TS; a++)
+    if (a > j) out[a] = (T)x[a];
+  // upper part: U y = e_j, entries a <= j
+#pragma unroll
+  for (int a = TS - 1; a >= 0; a--) {
+    double v = (a == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int b = a + 1; b < TS; b++) v -= Ls[a + b * L1] * x[b];
+    x[a] = a > j ? 0.0 : v / Ls[a + a * L1];
+  }
+#pragma unroll
+  for (int a = 0; a < TS; a++)
+    if (a <= j) out[a] = (T)x[a];
+}
+
+template <class T>
+void diag_inverse(hipStream_t s, int N, int64_t tiles, const LocalLayout& lay, int kind, const T* fac, T* dinv) {
+  if (tiles <= 0) return;
+  hipLaunchKernelGGL(k_diag_inv<T>, dim3((unsigned)tiles), dim3(TS), 0, s, N, lay, kind, fac, dinv);
+  TLS_LAUNCH_CHECK();
+}
+
 // Solve modes of the persistent triangular-solve kernel.
 //   FWD_L : L y = b, L lower with its diagonal (Cholesky), block rows ascending
 //   BWD_LT: L^T x = y (Cholesky), block rows descending, tiles read transposed
@@ -707,20 +771,23 @@ constexpr long long SPIN_LIMIT = 1ll << 26;
 //   BWD_U : U x = y, U upper with its diagonal (LU), descending
 enum TrsvMode { FWD_L = 0, BWD_LT = 1, FWD_UL = 2, BWD_U = 3 };
 
+// The diagonal block is applied through its precomputed inverse (dinv, one
+// 64 x 64 tile per block row, at (toff_i + r) * TS2; see k_diag_inv): the
+// right-hand side is reduced into LDS and multiplied by that tile with all
+// 256 threads, instead of a 64-step substitution on one wave.
 template <class T, int MODE>
 __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, int ntasks, int* counter,
                                               int* flags, const int* __restrict__ epoch_ptr, LocalLayout lay,
-                                              const T* __restrict__ fac, T* x, int* err,
-                                              const int* __restrict__ done) {
+                                              const T* __restrict__ fac, const T* __restrict__ dinv, T* x,
+                                              int* err, const int* __restrict__ done) {
   if (*done) return;
   constexpr bool BWD = (MODE == BWD_LT || MODE == BWD_U);
   constexpr bool TRANS = (MODE == BWD_LT);
   constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
   constexpr int U = TrsvUnroll<T>::v;
-  constexpr int LD = TS + 1;
   typedef typename Vec4<T>::type V4;
-  __shared__ T s_diag[TS * LD];
   __shared__ T s_red[16 * TS];
+  __shared__ T s_rhs[TS];
   __shared__ int s_task, s_lim;
   const int tid = threadIdx.x;
   const int rg = tid & 15, cg = tid >> 4;
@@ -735,9 +802,25 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
     const T* base = fac + lay.foff[i];
     T* xi = x + lay.voff[i];
     int* fl = flags + lay.toff[i];
-    // diagonal tile -> LDS (used by wave 0 at the end)
-    const T* dt = base + tile_index(KIND, nt, r, r) * TS2;
-    for (int e = tid; e < TS2; e += 256) s_diag[(e / TS) * LD + (e % TS)] = dt[e];
+    // inverse of the diagonal tile -> registers (rows 4rg..4rg+3 of columns
+    // cg + 16j), loaded while the task waits; the LU tile packs the unit
+    // lower inverse below the diagonal and the upper inverse on and above it
+    V4 dv[4];
+    {
+      const T* dt = dinv + (lay.toff[i] + r) * TS2;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        dv[j] = stream_load(reinterpret_cast<const V4*>(dt + (cg + 16 * j) * TS + 4 * rg));
+        if (MODE == FWD_UL || MODE == BWD_U) {
+          const int col = cg + 16 * j, r0 = 4 * rg;
+          const bool lower = MODE == FWD_UL;
+          if (lower ? !(r0 + 0 > col) : !(r0 + 0 <= col)) dv[j].x = T(0);
+          if (lower ? !(r0 + 1 > col) : !(r0 + 1 <= col)) dv[j].y = T(0);
+          if (lower ? !(r0 + 2 > col) : !(r0 + 2 <= col)) dv[j].z = T(0);
+          if (lower ? !(r0 + 3 > col) : !(r0 + 3 <= col)) dv[j].w = T(0);
+        }
+      }
+    }
     T acc[4] = {T(0), T(0), T(0), T(0)};
     // blocks this task reads: forward c = 0 .. r-1, backward c = nt-1 .. r+1
     int c = BWD ? nt - 1 : 0;
@@ -839,31 +922,39 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
     }
     __syncthreads();
     if (tid < 64) {
-      const int lane = tid;
       T sum = T(0);
 #pragma unroll
-      for (int g = 0; g < 16; g++) sum += s_red[g * TS + lane];
-      T val = xi[r * TS + lane] - sum;
-      if (MODE == FWD_L || MODE == FWD_UL) {
+      for (int g = 0; g < 16; g++) sum += s_red[g * TS + tid];
+      s_rhs[tid] = xi[r * TS + tid] - sum;
+    }
+    __syncthreads();
+    // x_r = (diagonal tile)^{-1} rhs, or its transpose for BWD_LT
+    T a2[4] = {T(0), T(0), T(0), T(0)};
+    if (!TRANS) {
 #pragma unroll
-        for (int b = 0; b < TS; b++) {
-          T xb = bcast(val, b);
-          if (MODE == FWD_L) xb *= T(1) / s_diag[b * LD + b];
-          if (lane == b)
-            val = xb;
-          else if (lane > b)
-            val -= s_diag[b * LD + lane] * xb;
-        }
-      } else {
-#pragma unroll
-        for (int b = TS - 1; b >= 0; b--) {
-          T xb = bcast(val, b) * (T(1) / s_diag[b * LD + b]);
-          if (lane == b)
-            val = xb;
-          else if (lane < b)
-            val -= (MODE == BWD_LT ? s_diag[lane * LD + b] : s_diag[b * LD + lane]) * xb;
-        }
+      for (int j = 0; j < 4; j++) {
+        const T rv = s_rhs[cg + 16 * j];
+        a2[0] += dv[j].x * rv;
+        a2[1] += dv[j].y * rv;
+        a2[2] += dv[j].z * rv;
+        a2[3] += dv[j].w * rv;
       }
+#pragma unroll
+      for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = a2[q];
+    } else {
+      const T r0 = s_rhs[4 * rg], r1 = s_rhs[4 * rg + 1], r2 = s_rhs[4 * rg + 2], r3 = s_rhs[4 * rg + 3];
+#pragma unroll
+      for (int j = 0; j < 4; j++) a2[j] = dv[j].x * r0 + dv[j].y * r1 + dv[j].z * r2 + dv[j].w * r3;
+#pragma unroll
+      for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = a2[j];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int lane = tid;
+      T val = T(0);
+#pragma unroll
+      for (int g = 0; g < 16; g++) val += s_red[g * TS + lane];
+      if (MODE == FWD_UL) val += s_rhs[lane];  // unit diagonal of L
       store_shared(xi + r * TS + lane, val);
       __builtin_amdgcn_s_waitcnt(0);  // the coherent stores above have completed
       if (lane == 0) __hip_atomic_store(&fl[r], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -988,26 +1079,26 @@ __global__ void k_solve_begin(int* counters, const int* done) {
 
 template <class T>
 void trsv(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
-          const T* fac, T* x, int* err, const int* done, int grid) {
+          const T* fac, const T* dinv, T* x, int* err, const int* done, int grid) {
   const int ntasks = p.ntasks;
   if (ntasks == 0) return;
   grid = std::max(1, std::min(grid, ntasks));
   switch (mode) {
     case FWD_L:
       hipLaunchKernelGGL((k_trsv<T, FWD_L>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,
-                         lay, fac, x, err, done);
+                         lay, fac, dinv, x, err, done);
       break;
     case BWD_LT:
       hipLaunchKernelGGL((k_trsv<T, BWD_LT>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
-                         epoch, lay, fac, x, err, done);
+                         epoch, lay, fac, dinv, x, err, done);
       break;
     case FWD_UL:
       hipLaunchKernelGGL((k_trsv<T, FWD_UL>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
-                         epoch, lay, fac, x, err, done);
+                         epoch, lay, fac, dinv, x, err, done);
       break;
     default:
       hipLaunchKernelGGL((k_trsv<T, BWD_U>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,
-                         lay, fac, x, err, done);
+                         lay, fac, dinv, x, err, done);
       break;
   }
   TLS_LAUNCH_CHECK();
@@ -1021,8 +1112,13 @@ void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const Lo
 }
 
 void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
-              const double* fac, double* x, int* err, const int* done, int grid) {
-  trsv<double>(s, mode, p, counter, epoch, lay, fac, x, err, done, grid);
+              const double* fac, const double* dinv, double* x, int* err, const int* done, int grid) {
+  trsv<double>(s, mode, p, counter, epoch, lay, fac, dinv, x, err, done, grid);
+}
+
+void diag_inverse_f64(hipStream_t s, int N, int64_t tiles, const LocalLayout& lay, int kind, const double* fac,
+                      double* dinv) {
+  diag_inverse<double>(s, N, tiles, lay, kind, fac, dinv);
 }
 
 void solve_begin(hipStream_t s, int* counters, const int* done) {
@@ -1086,6 +1182,15 @@ void factor_local(tls_ctx* c) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "non-positive pivot in a local Cholesky factorization");
     fail(TLS_E_SINGULAR, "zero or non-finite pivot in a local LU factorization (no pivoting)");
   }
+  // inverses of the diagonal tiles for the triangular solves
+  if (c->fp32) {
+    c->dinv32.alloc((size_t)c->sum_nt * TS2);
+    diag_inverse<float>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac32.p, c->dinv32.p);
+  } else {
+    c->dinv64.alloc((size_t)c->sum_nt * TS2);
+    diag_inverse<double>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac64.p, c->dinv64.p);
+  }
+  TLS_HIP(hipStreamSynchronize(c->stream));
 }
 
 void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
@@ -1157,13 +1262,13 @@ void build_solve_tasks(tls_ctx* c) {
 void local_backward(tls_ctx* c, float* x, const int* done) {
   solve_begin(c->stream, c->counters.p, done);
   trsv<float>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->plan_bwd, c->counters.p + 1, c->counters.p + 2,
-              c->layout(), c->fac32.p, x, c->errflag.p, done, c->solve_grid);
+              c->layout(), c->fac32.p, c->dinv32.p, x, c->errflag.p, done, c->solve_grid);
 }
 
 void local_backward(tls_ctx* c, double* x, const int* done) {
   solve_begin(c->stream, c->counters.p, done);
   trsv<double>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->plan_bwd, c->counters.p + 1, c->counters.p + 2,
-               c->layout(), c->fac64.p, x, c->errflag.p, done, c->solve_grid);
+               c->layout(), c->fac64.p, c->dinv64.p, x, c->errflag.p, done, c->solve_grid);
 }
 
 template <class T>
@@ -1208,16 +1313,16 @@ void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
   const int fm = c->kind == 0 ? FWD_L : FWD_UL, bm = c->kind == 0 ? BWD_LT : BWD_U;
   if (c->fp32) {
-    trsv<float>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac32.p, c->xloc32.p,
+    trsv<float>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac32.p, c->dinv32.p, c->xloc32.p,
                 c->errflag.p, done, c->solve_grid);
     if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
-    trsv<float>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac32.p, c->xloc32.p,
+    trsv<float>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac32.p, c->dinv32.p, c->xloc32.p,
                 c->errflag.p, done, c->solve_grid);
   } else {
-    trsv<double>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac64.p, c->xloc64.p,
+    trsv<double>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac64.p, c->dinv64.p, c->xloc64.p,
                  c->errflag.p, done, c->solve_grid);
     if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
-    trsv<double>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac64.p, c->xloc64.p,
+    trsv<double>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac64.p, c->dinv64.p, c->xloc64.p,
                  c->errflag.p, done, c->solve_grid);
   }
   if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));

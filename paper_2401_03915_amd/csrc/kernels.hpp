@@ -40,7 +40,10 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
                 hipStream_t s);
 // mode: 0 L y = b (Cholesky), 1 L^T x = y, 2 unit-lower L y = b (LU), 3 U x = y
 void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
-              const double* fac, double* x, int* err, const int* done, int grid);
+              const double* fac, const double* dinv, double* x, int* err, const int* done, int grid);
+// inverses of the diagonal tiles of a tile factor (tiles = total tile rows)
+void diag_inverse_f64(hipStream_t s, int N, int64_t tiles, const LocalLayout& lay, int kind, const double* fac,
+                      double* dinv);
 // (re)build the local plans for a task ordering
 void build_local_plans(tls_ctx* c, int order);
 void solve_begin(hipStream_t s, int* counters, const int* done);
