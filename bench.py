@@ -30,12 +30,13 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-solve (rel res 1e-8) + precond applies/s: mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # HBM bytes per launch of the dominant kernel (k_trsv<float, FWD_L> on the
 # default workload) from two rocprofv3 counter runs (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch), scaled by what the same counters read for a
 # 1 GiB read + 1 GiB write elementwise copy (--copy-probe). None whenever that
 # kernel has changed since the counters were taken.
-TRAFFIC = None
+TRAFFIC = 16325285029
 
 
 def log(*a):
@@ -48,6 +49,16 @@ def local_lower_bytes(info, w):
     m_i (m_i + 1) / 2 words of w bytes, read once:
     w * (sum m^2 + sum m) / 2. The vector traffic (2 m_i words) is left out."""
     return float(w) * (float(info["local_sum_m2"]) + float(info["local_sum_m"])) / 2.0
+
+
+def factor_flops(ctx, n_parts):
+    """Algorithmic flops of the batched Cholesky: sum_i m_i^3 / 3 over the
+    overlapping subdomain sizes m_i = #Omega_i (from the library's export)."""
+    import paper_2401_03915_amd as tls
+    sp = np.zeros(n_parts + 1, dtype=np.int32)
+    tls.tls_export(ctx, sub_ptr=sp)
+    m = np.diff(sp).astype(np.float64)
+    return float((m ** 3).sum() / 3.0)
 
 
 def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_cache, tol=1e-8):
@@ -93,6 +104,7 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
     ms_per_step = (t1 - t0) * 1e3 / steps
     ctx, st, it, rr = ctxs[-1]
     info = tls.tls_info(ctx)
+    fflops = factor_flops(ctx, prob.n_parts)
     log(f"precision {precision}: {ms_per_step:.1f} ms/step, {it} iterations, relres {rr:.2e}, status {st}")
     for c, *_ in ctxs[:-1]:
         tls.tls_destroy(c)
@@ -134,11 +146,12 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         "tuned": pinfo["tuned"],
         "apply_ms_profiled": pinfo["t_apply_ms"],
         "info": info,
+        "factor_flops": fflops,
         "z": z,
     }
 
 
-def cpu_baseline(prob, iters, sample=32, seed=0):
+def cpu_baseline(prob, iters, sample=64, seed=0):
     """The FP64 oracle timed on one host thread over a bounded sample of the
     same workload, scaled to the full time-to-solve.
 
@@ -273,6 +286,12 @@ def main():
             "backward_launch_ms": round(t_bwd, 4),
             "backward_GBps": round(bytes_launch / (t_bwd * 1e-3) / 1e9, 1) if t_bwd > 0 else None,
             "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"]}
+    def mfma(mode, dt):
+        t = mode["info"]["t_setup"][2] * 1e-3  # factorization and solve plans, ms -> s
+        ach = mode["factor_flops"] / t / 1e12
+        return {"kernel": "batched tiled Cholesky (k_potrf/k_trsm/k_update_blk)", "flops": mode["factor_flops"],
+                "ms": round(t * 1e3, 2), "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                "frac": round(ach / MFMA_PEAK_TFLOPS[dt], 4)}
     apply_err = None
     if plain is not None:
         z32, z64 = mixed["z"], plain["z"]
@@ -302,6 +321,7 @@ def main():
                   "n_coarse": info["n_coarse"], "gc": info["gc"], "oc": info["oc"],
                   "eig_resid_max": info["eig_resid_max"], "eig_iters_max": info["eig_iters_max"]},
         "roofline": roof,
+        "setup_mfma": mfma(mixed, "f32"),
     }
     if plain is not None:
         pinf = plain["info"]
@@ -311,7 +331,8 @@ def main():
                              "relres": plain["relres"], "applies_per_s": round(plain["applies_per_s"], 2),
                              "setup_ms": [round(t, 2) for t in pinf["t_setup"]], "solve_ms": round(pinf["t_solve"], 2),
                              "n_coarse": pinf["n_coarse"], "local_solve_GBps": round(ach64, 1),
-                             "local_solve_frac": round(ach64 / HBM_PEAK_GBS, 4)}
+                             "local_solve_frac": round(ach64 / HBM_PEAK_GBS, 4),
+                             "setup_mfma": mfma(plain, "f64")}
         out["speedup_mixed_vs_fp64"] = round(plain["ms_per_step"] / mixed["ms_per_step"], 3)
         out["apply_rel_diff_mixed_vs_fp64_own_bases"] = apply_err
     if not args.no_cpu_baseline:
