@@ -144,7 +144,8 @@ typedef struct {
   double t_setup[8];          /* ms: [0] overlap, [1] gather, [2] factorization and solve
                                  plans, [3] coarse basis (eigensolves, orthonormalization),
                                  [4] learned warm start (inside [3]), [5] A_0 and its
-                                 factorization, [6] unused, [7] total */
+                                 factorization, [6] batched factorization with the
+                                 diagonal-tile inverses (inside [2]), [7] total */
   double t_solve;             /* ms of the last tls_solve                    */
   int32_t iters;              /* iterations of the last tls_solve            */
   double relres;              /* true relative residual of the last solve    */

@@ -148,6 +148,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     c->t_setup[1] = ms_since(t);
     t = clk::now();
     tls::factor_local(c.get());
+    c->t_setup[6] = ms_since(t);
     tls::build_solve_tasks(c.get());
     c->t_setup[2] = ms_since(t);
     t = clk::now();
