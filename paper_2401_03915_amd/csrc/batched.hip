@@ -118,56 +118,59 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ desc,
     }
 }
 
-// One workgroup per (descriptor, group of RC right-hand sides); the group
-// lives in LDS (dynamic, n * RC elements).
+// Inverse of one diagonal block (w x w, w <= 64) of a column-major
+// triangular matrix per 64-thread workgroup, in FP64; thread j computes
+// column j. Output: 64 x 64 column-major (rows/columns >= w unused).
 template <class T>
-__global__ void __launch_bounds__(256) k_trsm_batched(const TriDesc* __restrict__ desc, const int64_t* __restrict__ pref,
-                                                      int nd, int RC, int mode, const T* __restrict__ Mat, T* Bm,
-                                                      int* err) {
-  extern __shared__ unsigned char smem_raw[];
-  T* Bs = reinterpret_cast<T*>(smem_raw);
-  const int64_t bid = blockIdx.x;
-  const int di = find_desc(pref, nd, bid);
-  const TriDesc d = desc[di];
-  const int g0 = (int)(bid - pref[di]) * RC;
-  const int nc = min(RC, d.nrhs - g0);
-  const int n = d.n;
-  const T* M = Mat + d.m_off;
-  T* B = Bm + d.b_off + (int64_t)g0 * d.ldb;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * nc; e += 256) {
-    int r = e % n, cc = e / n;
-    Bs[r * RC + cc] = B[r + (int64_t)cc * d.ldb];
-  }
-  const int col = tid % RC, rslot = tid / RC, rstride = 256 / RC;
-  bool bad = false;
-  for (int s = 0; s < n; s++) {
-    const int b = mode == LOWER_FWD ? s : n - 1 - s;
-    __syncthreads();
-    if (rslot == 0 && col < nc) {
-      T dg = M[b + (int64_t)b * n];
-      if (!(dg != T(0))) {
-        bad = true;
-        dg = T(1);
-      }
-      Bs[b * RC + col] /= dg;
-    }
-    __syncthreads();
-    if (col < nc && rslot < rstride) {
-      T xb = Bs[b * RC + col];
-      if (mode == LOWER_FWD) {
-        for (int a = b + 1 + rslot; a < n; a += rstride) Bs[a * RC + col] -= M[a + (int64_t)b * n] * xb;
-      } else {
-        for (int a = rslot; a < b; a += rstride) Bs[a * RC + col] -= M[a + (int64_t)b * n] * xb;
-      }
-    }
+__global__ void __launch_bounds__(64) k_tri_inv(const TriDesc* __restrict__ desc, const int2* __restrict__ blk,
+                                                const int64_t* __restrict__ ioff, int mode, const T* __restrict__ Mat,
+                                                T* inv, int* err) {
+  constexpr int L1 = 65;
+  __shared__ double Ls[64 * L1];
+  const int2 bb = blk[blockIdx.x];
+  const TriDesc d = desc[bb.x];
+  const int k0 = 64 * bb.y;
+  const int w = min(64, d.n - k0);
+  const T* M = Mat + d.m_off + k0 + (int64_t)k0 * d.n;
+  const int j = threadIdx.x;
+  for (int e = j; e < w * w; e += 64) {
+    const int a = e % w, c = e / w;
+    Ls[a + c * L1] = (double)M[a + (int64_t)c * d.n];
   }
   __syncthreads();
-  if (bad) atomicOr(err, ERR_PIVOT);
-  for (int e = tid; e < n * nc; e += 256) {
-    int r = e % n, cc = e / n;
-    B[r + (int64_t)cc * d.ldb] = Bs[r * RC + cc];
+  T* out = inv + ioff[blockIdx.x];
+  double x[64];
+  bool bad = false;
+  if (mode == LOWER_FWD) {
+#pragma unroll
+    for (int a = 0; a < 64; a++) {
+      double v = (a == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int b = 0; b < a; b++) v -= Ls[a + b * L1] * x[b];
+      double dg = a < w ? Ls[a + a * L1] : 1.0;
+      if (a < w && !(dg != 0.0)) {
+        bad = true;
+        dg = 1.0;
+      }
+      x[a] = (a < j || a >= w || j >= w) ? 0.0 : v / dg;
+    }
+  } else {
+#pragma unroll
+    for (int a = 63; a >= 0; a--) {
+      double v = (a == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int b = a + 1; b < 64; b++) v -= Ls[a + b * L1] * x[b];
+      double dg = a < w ? Ls[a + a * L1] : 1.0;
+      if (a < w && !(dg != 0.0)) {
+        bad = true;
+        dg = 1.0;
+      }
+      x[a] = (a > j || a >= w || j >= w) ? 0.0 : v / dg;
+    }
   }
+#pragma unroll
+  for (int a = 0; a < 64; a++) out[a + 64 * j] = (T)x[a];
+  if (bad) atomicOr(err, ERR_PIVOT);
 }
 
 }  // namespace
@@ -243,38 +246,69 @@ void gemm_run(hipStream_t s, const GemmPlan& p, bool transA, bool transB, const 
   TLS_LAUNCH_CHECK();
 }
 
+// Blocked triangular solve with many right-hand sides: the diagonal 64 x 64
+// blocks are inverted once (k_tri_inv), then for each block row k (in the
+// solve order) X_k = inv(M_kk) B_k and the rows still to solve get
+// B -= M(:, k) X_k, both as batched MFMA GEMMs over all descriptors. The
+// first GEMM writes X_k over B_k: it has a single 64-row output tile, so
+// each workgroup reads all of its B columns before writing them.
 template <class T>
 void batched_trsm(hipStream_t s, const std::vector<TriDesc>& d, TriMode mode, const T* M, T* B, int* err) {
-  int nmax = 0;
-  for (const auto& t : d)
-    if (t.nrhs > 0) nmax = std::max(nmax, t.n);
-  if (nmax == 0) return;
-  const int lds_cap = 64 * 1024;
-  int RC = std::min<int64_t>(16, lds_cap / ((int64_t)nmax * sizeof(T)));
-  if (RC < 1) fail(TLS_E_ARG, "local block too large for the batched triangular solve (" + std::to_string(nmax) + ")");
-  // power of two dividing 256
-  int rc = 1;
-  while (rc * 2 <= RC) rc *= 2;
-  RC = rc;
   std::vector<TriDesc> dd;
-  std::vector<int64_t> pref;
-  int64_t tot = 0;
-  for (const auto& t : d) {
-    if (t.nrhs <= 0 || t.n <= 0) continue;
-    dd.push_back(t);
-    pref.push_back(tot);
-    tot += (t.nrhs + RC - 1) / RC;
+  for (const auto& t : d)
+    if (t.nrhs > 0 && t.n > 0) dd.push_back(t);
+  if (dd.empty()) return;
+  std::vector<int2> blk;
+  std::vector<int64_t> ioff;
+  std::vector<int64_t> first(dd.size());
+  int maxnb = 0;
+  for (size_t q = 0; q < dd.size(); q++) {
+    const int nb = (dd[q].n + 63) / 64;
+    maxnb = std::max(maxnb, nb);
+    first[q] = (int64_t)blk.size();
+    for (int b = 0; b < nb; b++) {
+      blk.push_back(make_int2((int)q, b));
+      ioff.push_back((int64_t)(blk.size() - 1) * 4096);
+    }
   }
-  if (tot == 0) return;
-  pref.push_back(tot);
   DBuf<TriDesc> ddesc;
-  DBuf<int64_t> dpref;
+  DBuf<int2> dblk;
+  DBuf<int64_t> dioff;
+  DBuf<T> inv;
   ddesc.upload(dd, s);
-  dpref.upload(pref, s);
-  size_t shm = (size_t)nmax * RC * sizeof(T);
-  hipLaunchKernelGGL(k_trsm_batched<T>, dim3((unsigned)tot), dim3(256), shm, s, ddesc.p, dpref.p, (int)dd.size(), RC,
-                     (int)mode, M, B, err);
+  dblk.upload(blk, s);
+  dioff.upload(ioff, s);
+  inv.alloc(blk.size() * 4096);
+  hipLaunchKernelGGL(k_tri_inv<T>, dim3((unsigned)blk.size()), dim3(64), 0, s, ddesc.p, dblk.p, dioff.p, (int)mode, M,
+                     inv.p, err);
   TLS_LAUNCH_CHECK();
+  // inv and M are separate buffers: the GEMMs read the inverse blocks from
+  // inv (A operand, offset into inv) and the off-diagonal blocks from M.
+  GemmPlan p1, p2;
+  for (int step = 0; step < maxnb; step++) {
+    std::vector<GemmDesc> g1, g2;
+    for (size_t q = 0; q < dd.size(); q++) {
+      const TriDesc& t = dd[q];
+      const int nb = (t.n + 63) / 64;
+      if (step >= nb) continue;
+      const int k = mode == LOWER_FWD ? step : nb - 1 - step;
+      const int k0 = 64 * k, w = std::min(64, t.n - k0);
+      // X_k = inv(M_kk) B_k, written over B_k
+      g1.push_back(GemmDesc{w, t.nrhs, w, 64, (int)t.ldb, (first[q] + k) * 4096, t.b_off + k0, t.b_off + k0, t.ldb});
+      // rows still to solve: below (forward) or above (backward) the block
+      const int r0 = mode == LOWER_FWD ? k0 + w : 0;
+      const int rn = mode == LOWER_FWD ? t.n - k0 - w : k0;
+      if (rn > 0)
+        g2.push_back(GemmDesc{rn, t.nrhs, w, t.n, (int)t.ldb, t.m_off + r0 + (int64_t)k0 * t.n, t.b_off + k0,
+                              t.b_off + r0, t.ldb});
+    }
+    gemm_plan(p1, g1, s);
+    gemm_run<T>(s, p1, false, false, inv.p, B, B, T(1), T(0));
+    if (!g2.empty()) {
+      gemm_plan(p2, g2, s);
+      gemm_run<T>(s, p2, false, false, M, B, B, T(-1), T(1));
+    }
+  }
   TLS_HIP(hipStreamSynchronize(s));
 }
 

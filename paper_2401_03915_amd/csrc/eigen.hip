@@ -272,14 +272,19 @@ __global__ void __launch_bounds__(256) k_ss_init(const int* __restrict__ ids, co
 
 // R_i = D R'^{-1} where D = diag(G)^{-1/2} and R'^T R' = D G D (Cholesky of
 // the equilibrated Gram matrix, FP64), so that Y R_i has orthonormal columns.
+// Right-looking Cholesky with the row of R and the trailing update spread
+// over the 64 threads; then thread c solves column c of R'^{-1}.
 template <class T>
 __global__ void __launch_bounds__(64) k_ss_chol(const int* __restrict__ ids, const int* __restrict__ p_,
                                                 const T* __restrict__ G, T* R, int* err) {
   __shared__ double A[PMAX * PMAX];
+  __shared__ double X[PMAX * PMAX];
   __shared__ double d[PMAX];
+  __shared__ int s_bad;
   const int i = ids[blockIdx.x];
   const int p = p_[i], tid = threadIdx.x;
   const T* Gi = G + (int64_t)i * PMAX * PMAX;
+  if (tid == 0) s_bad = 0;
   for (int e = tid; e < p * p; e += 64) A[(e % p) + (e / p) * PMAX] = (double)Gi[e];
   __syncthreads();
   if (tid < p) {
@@ -292,40 +297,44 @@ __global__ void __launch_bounds__(64) k_ss_chol(const int* __restrict__ ids, con
     A[a + b * PMAX] *= d[a] * d[b];
   }
   __syncthreads();
-  if (tid == 0) {
-    bool ok = true;
-    // upper Cholesky in place: A = R^T R, R stored in the upper triangle
-    for (int j = 0; j < p; j++) {
+  // upper Cholesky A = R^T R in place (R in the upper triangle)
+  for (int j = 0; j < p; j++) {
+    if (tid == 0) {
       double v = A[j + j * PMAX];
-      for (int l = 0; l < j; l++) v -= A[l + j * PMAX] * A[l + j * PMAX];
       if (!(v > 1e-28)) {
-        ok = false;
+        s_bad = 1;
         v = 1e-28;
       }
-      v = sqrt(v);
-      A[j + j * PMAX] = v;
-      for (int c = j + 1; c < p; c++) {
-        double t = A[j + c * PMAX];
-        for (int l = 0; l < j; l++) t -= A[l + j * PMAX] * A[l + c * PMAX];
-        A[j + c * PMAX] = t / v;
-      }
+      A[j + j * PMAX] = sqrt(v);
     }
-    // R^{-1} (upper) in place, column by column from the right
-    for (int j = p - 1; j >= 0; j--) {
-      A[j + j * PMAX] = 1.0 / A[j + j * PMAX];
-      for (int r = j - 1; r >= 0; r--) {
-        double t = 0.0;
-        for (int l = r + 1; l <= j; l++) t += A[r + l * PMAX] * A[l + j * PMAX];
-        A[r + j * PMAX] = -t / A[r + r * PMAX];
-      }
+    __syncthreads();
+    const double rjj = A[j + j * PMAX];
+    if (tid > j && tid < p) A[j + tid * PMAX] /= rjj;
+    __syncthreads();
+    const int w = p - j - 1;
+    for (int e = tid; e < w * w; e += 64) {
+      const int a = j + 1 + e % w, c = j + 1 + e / w;
+      if (c >= a) A[a + c * PMAX] -= A[j + a * PMAX] * A[j + c * PMAX];
     }
-    if (!ok) atomicOr(err, ERR_EIG);
+    __syncthreads();
+  }
+  // X = R^{-1} (upper): column c by thread c, rows c down to 0
+  if (tid < p) {
+    const int c = tid;
+    for (int a = p - 1; a > c; a--) X[a + c * PMAX] = 0.0;
+    X[c + c * PMAX] = 1.0 / A[c + c * PMAX];
+    for (int a = c - 1; a >= 0; a--) {
+      double t = 0.0;
+      for (int b = a + 1; b <= c; b++) t += A[a + b * PMAX] * X[b + c * PMAX];
+      X[a + c * PMAX] = -t / A[a + a * PMAX];
+    }
   }
   __syncthreads();
+  if (tid == 0 && s_bad) atomicOr(err, ERR_EIG);
   T* Ri = R + (int64_t)i * PMAX * PMAX;
   for (int e = tid; e < p * p; e += 64) {
     const int a = e % p, b = e / p;
-    Ri[e] = (T)(a <= b ? d[a] * A[a + b * PMAX] : 0.0);
+    Ri[e] = (T)(a <= b ? d[a] * X[a + b * PMAX] : 0.0);
   }
 }
 
