@@ -216,6 +216,13 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info);
 tls_status tls_export(const tls_ctx* c, int32_t* sub_ptr, int32_t* sub_idx, int32_t* layer_ptr,
                       int32_t* zcol_ptr, double* eigvals, int32_t* zsrc, double* Z, double* A0);
 
+/* Copy the coarse basis in its compact form to a host buffer: for each
+ * subdomain i in order, its k_i = zcol_ptr[i+1] - zcol_ptr[i] columns
+ * restricted to the rows I_i, column-major (#I_i x k_i), rows in the order
+ * of sub_idx[sub_ptr[i] .. sub_ptr[i] + #I_i). blocks must hold
+ * sum_i #I_i k_i doubles (Z is zero outside these blocks). */
+tls_status tls_export_zblocks(const tls_ctx* c, double* blocks);
+
 /* Solve with one local factor: x = A_ii^{-1} b for subdomain i (host
  * vectors of length #Omega_i, in the Omega_i order). Diagnostics. */
 tls_status tls_local_solve(tls_ctx* c, int32_t i, const double* b, double* x);

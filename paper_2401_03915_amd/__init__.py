@@ -16,11 +16,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (TlsError, gnn_n_weights, tls_apply, tls_default_options, tls_destroy,  # noqa: F401
-                   tls_export, tls_gnn_forward, tls_gnn_loss_grad, tls_info, tls_local_solve, tls_setup, tls_solve,
-                   tls_spmv)
+                   tls_export, tls_export_zblocks, tls_gnn_forward, tls_gnn_loss_grad, tls_info, tls_local_solve,
+                   tls_setup, tls_solve, tls_spmv)
 
 __all__ = ["Preconditioner", "TlsError", "tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve",
-           "tls_info", "tls_export", "tls_local_solve", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_destroy",
+           "tls_info", "tls_export", "tls_export_zblocks", "tls_local_solve", "tls_gnn_forward",
+           "tls_gnn_loss_grad", "tls_destroy",
            "gnn_n_weights"]
 
 
@@ -133,6 +134,34 @@ class Preconditioner:
         if A0:
             out["A0"] = out["A0"].T.copy()  # the C side writes column-major
         return out
+
+    def z_sparse(self, ex=None):
+        """The coarse basis as a SciPy CSR matrix (n x n_C) from its compact blocks."""
+        import scipy.sparse as sp
+        if ex is None:
+            ex = self.export()
+        zc, spt, lp = ex["zcol_ptr"], ex["sub_ptr"], ex["layer_ptr"]
+        stride = self.overlap + 2
+        nI = np.array([lp[i * stride + 1] - lp[i * stride] for i in range(self.n_parts)])
+        k = np.diff(zc)
+        blocks = np.zeros(int((nI * k).sum()), dtype=np.float64)
+        tls_export_zblocks(self.ctx, blocks)
+        rows, cols, vals = [], [], []
+        off = 0
+        for i in range(self.n_parts):
+            if k[i] == 0:
+                continue
+            B = blocks[off:off + nI[i] * k[i]].reshape(k[i], nI[i]).T  # column-major nI x k
+            off += nI[i] * k[i]
+            idx = ex["sub_idx"][spt[i]:spt[i] + nI[i]]
+            rr, cc = np.meshgrid(idx, np.arange(zc[i], zc[i + 1]), indexing="ij")
+            rows.append(rr.ravel())
+            cols.append(cc.ravel())
+            vals.append(B.ravel())
+        if not rows:
+            return sp.csr_matrix((self.n, 0))
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(self.n, int(zc[-1])))
 
     def gnn_forward(self, weights: np.ndarray, c_out: int) -> np.ndarray:
         """Network output on every local graph: (sum #Omega_i) x c_out, rows in sub_idx order."""

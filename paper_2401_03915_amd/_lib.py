@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "TLS_OK", 1: "TLS_E_ARG", 2: "TLS_E_NOT_SPD", 3: "TLS_E_SINGU
 
 # Names declared in include/tls.h (checked by the tests against the header).
 EXPORTED = ["tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve", "tls_info", "tls_export",
-            "tls_local_solve", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_last_error", "tls_destroy"]
+            "tls_local_solve", "tls_export_zblocks", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_last_error",
+            "tls_destroy"]
 
 GNN_LAYERS = 4
 GNN_FEATURES = 12
@@ -126,6 +127,8 @@ def lib() -> C.CDLL:
         L.tls_export.restype = C.c_int
         L.tls_local_solve.argtypes = [vp, i32, vp, vp]
         L.tls_local_solve.restype = C.c_int
+        L.tls_export_zblocks.argtypes = [vp, vp]
+        L.tls_export_zblocks.restype = C.c_int
         L.tls_gnn_forward.argtypes = [vp, vp, i32, vp]
         L.tls_gnn_forward.restype = C.c_int
         L.tls_gnn_loss_grad.argtypes = [vp, vp, i32, vp, C.POINTER(C.c_double)]
@@ -201,6 +204,12 @@ def tls_export(ctx, **bufs):
 
 def tls_local_solve(ctx, i, b, x):
     return check(lib().tls_local_solve(ctx, i, b.ctypes.data, x.ctypes.data), ctx)
+
+
+def tls_export_zblocks(ctx, blocks):
+    """blocks: float64 numpy of sum_i #I_i k_i entries, filled."""
+    assert blocks.dtype == np.float64 and blocks.flags.c_contiguous
+    return check(lib().tls_export_zblocks(ctx, blocks.ctypes.data), ctx)
 
 
 def tls_gnn_forward(ctx, weights, c_out, X):

@@ -286,6 +286,28 @@ tls_status tls_export(const tls_ctx* cc, int32_t* sub_ptr, int32_t* sub_idx, int
   });
 }
 
+tls_status tls_export_zblocks(const tls_ctx* cc, double* blocks) {
+  tls_ctx* c = const_cast<tls_ctx*>(cc);
+  if (!c) return TLS_E_STATE;
+  if (!blocks) {
+    c->err = "blocks must not be NULL";
+    return TLS_E_ARG;
+  }
+  return guard(c, [&]() {
+    const int64_t tot = c->h_zoff.empty() ? 0 : c->h_zoff[c->N];
+    if (tot > 0) {
+      // stored blocks may hold room for columns dropped by the orthonormalization
+      auto hz = tls::download(c->Z.p, tot, c->stream);
+      int64_t o = 0;
+      for (int i = 0; i < c->N; i++) {
+        const int64_t len = (int64_t)c->h_nI[i] * (c->h_zcol[i + 1] - c->h_zcol[i]);
+        std::copy(hz.begin() + c->h_zoff[i], hz.begin() + c->h_zoff[i] + len, blocks + o);
+        o += len;
+      }
+    }
+  });
+}
+
 tls_status tls_gnn_forward(tls_ctx* c, const float* weights, int32_t c_out, float* X) {
   if (!c) return TLS_E_STATE;
   if (!weights || !X) {
