@@ -112,7 +112,8 @@ typedef struct {
                            events (and then waits for them); see tls_info_t */
   int32_t solve_wgs;    /* workgroups of the persistent triangular solves (0 = default) */
   int32_t solve_order;  /* task order of those solves: 1 level by level, 2 by the fraction of
-                           the subdomain's rows done, 3 longest chain first; 0 = default (2) */
+                           the subdomain's rows done, 3 longest chain first, 4 / 5 as 2 with a
+                           lead of 0.3 / 0.6 x nt_i / max nt for large subdomains; 0 = default (4) */
   int32_t autotune;     /* 1: at setup, time candidate workgroup counts and task orders and keep
                            the fastest (ignored when solve_wgs or solve_order is set) */
   const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
@@ -159,7 +160,7 @@ typedef struct {
   double t_apply_ms;          /* mean duration of those whole applies         */
   double t_local_fwd_ms;      /* mean duration of their forward solve kernel alone */
   int32_t solve_wgs;          /* workgroups used by the persistent solves     */
-  int32_t solve_order;        /* task order used by those solves (1, 2 or 3)  */
+  int32_t solve_order;        /* task order used by those solves (1 .. 5)     */
   int32_t tuned;              /* 0 default, 1 timed at setup, 2 read from the cache */
   const double* res_history;  /* host array: ||r_k|| / ||b|| per iteration   */
 } tls_info_t;

@@ -89,7 +89,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.nev1 > 0 && c->opt.matrix_kind != 0)
       tls::fail(TLS_E_ARG, "nev1 (eq. uppergevp vectors) applies to SPD matrices only");
     if (c->opt.nev1 > 0 && overlap == 0) tls::fail(TLS_E_ARG, "overlap 0: nev1 must be 0");
-    if (c->opt.solve_order < 0 || c->opt.solve_order > 3) tls::fail(TLS_E_ARG, "solve_order must be in [0, 3]");
+    if (c->opt.solve_order < 0 || c->opt.solve_order > 5) tls::fail(TLS_E_ARG, "solve_order must be in [0, 5]");
     if (c->opt.solve_wgs < 0) tls::fail(TLS_E_ARG, "solve_wgs must be >= 0");
     if (c->opt.gnn_weights || c->opt.gnn_train) {
       if (c->opt.matrix_kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");

@@ -57,7 +57,7 @@ struct tls_ctx {
   tls::SolvePlan plan_fwd, plan_bwd;
   tls::DBuf<int> counters;  // [0] fwd task counter, [1] bwd task counter, [2] epoch
   int solve_grid = 1024;
-  int solve_order = 2;
+  int solve_order = 4;
 
   // work vectors for the apply (padded local layout)
   tls::DBuf<double> xloc64;

@@ -825,6 +825,17 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
     // blocks this task reads: forward c = 0 .. r-1, backward c = nt-1 .. r+1
     int c = BWD ? nt - 1 : 0;
     const int step = BWD ? -1 : 1;
+    // the block next to the diagonal is almost always the last dependency:
+    // load it, and this row's right-hand side, while the task waits
+    const int c_last = BWD ? r + 1 : r - 1;
+    const bool has_last = BWD ? (r + 1 < nt) : (r > 0);
+    V4 vlast[4];
+    if (has_last) {
+      const T* tile = base + (TRANS ? tile_index(KIND, nt, c_last, r) : tile_index(KIND, nt, r, c_last)) * TS2;
+#pragma unroll
+      for (int j = 0; j < 4; j++) vlast[j] = stream_load(reinterpret_cast<const V4*>(tile + (cg + 16 * j) * TS + 4 * rg));
+    }
+    const T brow = tid < 64 ? xi[r * TS + tid] : T(0);
     while (BWD ? (c > r) : (c < r)) {
       if (tid == 0) {
         int lim = c;
@@ -853,9 +864,14 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
         for (int u = 0; u < U; u++) {
           const int cc = c + step * (done_tiles + u);
           const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
+          if (cc == c_last) {
 #pragma unroll
-          for (int j = 0; j < 4; j++)
-            v[u][j] = stream_load(reinterpret_cast<const V4*>(tile + (cg + 16 * j) * TS + 4 * rg));
+            for (int j = 0; j < 4; j++) v[u][j] = vlast[j];
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+              v[u][j] = stream_load(reinterpret_cast<const V4*>(tile + (cg + 16 * j) * TS + 4 * rg));
+          }
           const T* xc = xi + cc * TS;
           if (!TRANS) {
 #pragma unroll
@@ -886,11 +902,12 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
         const int cc = c + step * done_tiles;
         const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
         const T* xc = xi + cc * TS;
+        const bool pre = cc == c_last;
         if (!TRANS) {
 #pragma unroll
           for (int j = 0; j < 4; j++) {
             int col = cg + 16 * j;
-            V4 v = stream_load(reinterpret_cast<const V4*>(tile + col * TS + 4 * rg));
+            V4 v = pre ? vlast[j] : stream_load(reinterpret_cast<const V4*>(tile + col * TS + 4 * rg));
             T xv = load_shared(xc + col);
             acc[0] += v.x * xv;
             acc[1] += v.y * xv;
@@ -904,7 +921,7 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
 #pragma unroll
           for (int j = 0; j < 4; j++) {
             int col = cg + 16 * j;
-            V4 v = stream_load(reinterpret_cast<const V4*>(tile + col * TS + 4 * rg));
+            V4 v = pre ? vlast[j] : stream_load(reinterpret_cast<const V4*>(tile + col * TS + 4 * rg));
             acc[j] += v.x * xv[0] + v.y * xv[1] + v.z * xv[2] + v.w * xv[3];
           }
         }
@@ -925,7 +942,7 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
       T sum = T(0);
 #pragma unroll
       for (int g = 0; g < 16; g++) sum += s_red[g * TS + tid];
-      s_rhs[tid] = xi[r * TS + tid] - sum;
+      s_rhs[tid] = brow - sum;
     }
     __syncthreads();
     // x_r = (diagonal tile)^{-1} rhs, or its transpose for BWD_LT
@@ -1207,6 +1224,10 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
   //   1 level order         key = position
   //   2 normalized progress key = position / nt_i
   //   3 longest chain first key = position + (max nt - nt_i)
+  //   4, 5 progress with a lead for large subdomains:
+  //         key = position / nt_i * (1 - lead * nt_i / max nt), lead 0.3 / 0.6,
+  //         so that the long rows of the largest chains are handed out
+  //         before the end and stream most of their tiles early
   const int N = (int)nt.size();
   int maxnt = 0;
   for (int v : nt) maxnt = std::max(maxnt, v);
@@ -1217,7 +1238,15 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
   std::vector<Item> items;
   for (int i = 0; i < N; i++)
     for (int pos = 0; pos < nt[i]; pos++) {
-      double key = order == 2 ? (pos + 0.5) / nt[i] : order == 3 ? (double)(pos + maxnt - nt[i]) : (double)pos;
+      double key;
+      if (order == 2)
+        key = (pos + 0.5) / nt[i];
+      else if (order == 3)
+        key = (double)(pos + maxnt - nt[i]);
+      else if (order >= 4)
+        key = (pos + 0.5) / nt[i] * (1.0 - (order == 4 ? 0.3 : 0.6) * nt[i] / std::max(maxnt, 1));
+      else
+        key = (double)pos;
       items.push_back(Item{key, i, pos});
     }
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
@@ -1247,7 +1276,7 @@ void build_local_plans(tls_ctx* c, int order) {
 void build_solve_tasks(tls_ctx* c) {
   c->counters.alloc(4);
   TLS_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(int) * 4, c->stream));
-  build_local_plans(c, 2);
+  build_local_plans(c, 4);
   // padding entries must stay zero: the padded identity rows then solve to 0
   if (c->fp32) {
     c->xloc32.alloc(c->sum_M);

@@ -7,7 +7,8 @@
 // when its block rows are handed out. The default is a fixed number of
 // workgroups per compute unit for each precision (LDS and register use allow
 // about 7 FP32 or 3 FP64 workgroups per CU) and rows handed out by the
-// fraction of their subdomain already done (normalized progress).
+// fraction of their subdomain already done, with a lead for the largest
+// subdomains (order 4).
 // With autotune = 1 the setup times the local forward + backward solves for
 // each order and a handful of workgroup counts and keeps the fastest; picks
 // are appended to a text cache keyed by the problem's shape and reused
@@ -25,7 +26,7 @@ namespace {
 
 std::string tune_key(const tls_ctx* c) {
   std::ostringstream k;
-  k << "trsv:v4 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
+  k << "trsv:v5 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
     << " sumM=" << c->sum_M << " maxnt=" << c->max_nt;
   return k.str();
 }
@@ -46,7 +47,7 @@ bool cache_lookup(const char* path, const std::string& key, int* grid, int* orde
     if (tab == std::string::npos) continue;
     if (line.substr(0, tab) == key) {
       int g = 0, ch = 0;
-      if (std::sscanf(line.c_str() + tab + 1, "%d %d", &g, &ch) == 2 && g > 0 && ch >= 1 && ch <= 3) {
+      if (std::sscanf(line.c_str() + tab + 1, "%d %d", &g, &ch) == 2 && g > 0 && ch >= 1 && ch <= 5) {
         *grid = g;
         *order = ch;
         found = true;
@@ -105,7 +106,7 @@ void choose_solve_grid(tls_ctx* c) {
   const int maxper = c->fp32 ? 7 : 3;
   double best = 1e300;
   int best_g = c->solve_grid, best_ch = c->solve_order;
-  for (int order : {1, 2, 3}) {
+  for (int order : {1, 2, 3, 4, 5}) {
     build_local_plans(c, order);
     for (int p = 2; p <= maxper; p += 2) {
       const int cg = cus * std::min(p, maxper);
