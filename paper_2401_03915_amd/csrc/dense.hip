@@ -110,71 +110,68 @@ __device__ inline int find_slot(const int64_t* pref, int count, int64_t bid) {
   return lo;
 }
 
+// value of lane b of v, for every lane
+__device__ inline float bcast(float v, int b) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), b));
+}
+__device__ inline double bcast(double v, int b) {
+  long long u = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), b);
+  int hi = __builtin_amdgcn_readlane((int)(u >> 32), b);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky of the diagonal tile (k, k) of every active subdomain by one
+// wavefront: lane a holds row a in registers, and entry (a, j) is formed
+// from the dot product of rows a and j (row j broadcast by readlane), so
+// no barrier is needed. Then the inverse L_kk^{-1} (FP64, lane j computes
+// column j) goes to dinv[(toff_i + k) * 64^2]: it serves the tile
+// triangular solves of column k and the apply's triangular solves.
 template <class T>
-__global__ void __launch_bounds__(256) k_potrf(int k, const int* __restrict__ order, LocalLayout lay, T* fac,
-                                               int* err) {
-  constexpr int LD = TS + 1;
-  __shared__ T s[TS * LD];
-  int i = order[blockIdx.x];
-  int nt = lay.nt[i];
+__global__ void __launch_bounds__(64) k_potrf(int k, const int* __restrict__ order, LocalLayout lay, T* fac,
+                                              T* dinv, int* err) {
+  constexpr int L1 = TS + 1;
+  __shared__ double Ls[TS * L1];
+  const int i = order[blockIdx.x];
+  const int nt = lay.nt[i];
   T* tile = fac + lay.foff[i] + tile_index(0, nt, k, k) * TS2;
-  const int t = threadIdx.x;
-  for (int e = t; e < TS2; e += 256) s[(e / TS) * LD + (e % TS)] = tile[e];
+  const int a = threadIdx.x;
+  T row[TS];
+#pragma unroll
+  for (int b = 0; b < TS; b++) row[b] = tile[b * TS + a];
   bool bad = false;
+#pragma unroll
   for (int j = 0; j < TS; j++) {
-    __syncthreads();
-    T d = s[j * LD + j];
+    T v = row[j];
+#pragma unroll
+    for (int l = 0; l < j; l++) v -= row[l] * bcast(row[l], j);
+    T d = bcast(v, j);
     if (!(d > T(0))) {
       bad = true;
       d = T(1);
     }
     d = sqrt(d);
-    __syncthreads();
-    if (t == j) s[j * LD + j] = d;
-    if (t > j && t < TS) s[j * LD + t] /= d;
-    __syncthreads();
-    for (int e = t; e < TS2; e += 256) {
-      int a = e % TS, b = e / TS;
-      if (b > j && a >= b) s[b * LD + a] -= s[j * LD + a] * s[j * LD + b];
-    }
+    row[j] = a == j ? d : (a > j ? v / d : T(0));
   }
-  __syncthreads();
-  if (bad && t == 0) atomicOr(err, ERR_PIVOT);
-  for (int e = t; e < TS2; e += 256) {
-    int a = e % TS, b = e / TS;
-    tile[e] = a >= b ? s[b * LD + a] : T(0);
-  }
-}
-
-// X L_kk^T = A_rk for one tile below the diagonal; one thread per row.
-template <class T>
-__global__ void __launch_bounds__(64) k_trsm(int k, const int64_t* __restrict__ pref, int nact,
-                                             const int* __restrict__ order, LocalLayout lay, T* fac) {
-  constexpr int LD = TS + 1;
-  __shared__ T Ls[TS * LD];
-  int64_t bid = blockIdx.x;
-  int j = find_slot(pref, nact, bid);
-  int i = order[j];
-  int nt = lay.nt[i];
-  int r = k + 1 + (int)(bid - pref[j]);
-  T* base = fac + lay.foff[i];
-  const T* L = base + tile_index(0, nt, k, k) * TS2;
-  T* A = base + tile_index(0, nt, r, k) * TS2;
-  const int a = threadIdx.x;
-  for (int e = a; e < TS2; e += 64) Ls[(e / TS) * LD + (e % TS)] = L[e];
-  T x[TS];
-#pragma unroll
-  for (int b = 0; b < TS; b++) x[b] = A[b * TS + a];
-  __syncthreads();
+  if (bad && a == 0) atomicOr(err, ERR_PIVOT);
 #pragma unroll
   for (int b = 0; b < TS; b++) {
-    T sum = x[b];
+    tile[b * TS + a] = row[b];
+    Ls[a + b * L1] = (double)row[b];
+  }
+  __syncthreads();
+  const int j = a;
+  T* out = dinv + (lay.toff[i] + k) * TS2 + (int64_t)j * TS;
+  double x[TS];
 #pragma unroll
-    for (int l = 0; l < b; l++) sum -= x[l] * Ls[l * LD + b];
-    x[b] = sum / Ls[b * LD + b];
+  for (int r = 0; r < TS; r++) {
+    double v = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int l = 0; l < r; l++) v -= Ls[r + l * L1] * x[l];
+    x[r] = r < j ? 0.0 : v / Ls[r + r * L1];
   }
 #pragma unroll
-  for (int b = 0; b < TS; b++) A[b * TS + a] = x[b];
+  for (int r = 0; r < TS; r++) out[r] = (T)x[r];
 }
 
 template <class T>
@@ -188,32 +185,27 @@ struct LdsLd<double> {
   static constexpr int v = TS;
 };
 
-// C_rc -= L_rk L_ck^T for one trailing lower tile (k < c <= r): MFMA.
+// X = A_rk L_kk^{-T} for the tiles (r, k), r > k (MFMA with the inverse
+// formed by k_potrf): X(a, b) = sum_l A(a, l) Linv(b, l), written over A_rk.
 template <class T>
-__global__ void __launch_bounds__(256) k_update(int k, const int64_t* __restrict__ pref, int nact,
-                                                const int* __restrict__ order, LocalLayout lay, T* fac) {
+__global__ void __launch_bounds__(256) k_trsm(int k, const int64_t* __restrict__ pref, int nact,
+                                              const int* __restrict__ order, LocalLayout lay, T* fac,
+                                              const T* __restrict__ dinv) {
   constexpr int LD = LdsLd<T>::v;
   __shared__ T As[TS * LD];
   __shared__ T Bs[TS * LD];
-  int64_t bid = blockIdx.x;
-  int j = find_slot(pref, nact, bid);
-  int i = order[j];
-  int nt = lay.nt[i];
-  int64_t t = bid - pref[j];
-  int rr = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(rr + 1) * (rr + 2) / 2 <= t) rr++;
-  while ((int64_t)rr * (rr + 1) / 2 > t) rr--;
-  int cc = (int)(t - (int64_t)rr * (rr + 1) / 2);
-  int r = k + 1 + rr, c = k + 1 + cc;
-  T* base = fac + lay.foff[i];
-  const T* Lr = base + tile_index(0, nt, r, k) * TS2;
-  const T* Lc = base + tile_index(0, nt, c, k) * TS2;
-  T* C = base + tile_index(0, nt, r, c) * TS2;
+  const int64_t bid = blockIdx.x;
+  const int j = find_slot(pref, nact, bid);
+  const int i = order[j];
+  const int nt = lay.nt[i];
+  const int r = k + 1 + (int)(bid - pref[j]);
+  T* A = fac + lay.foff[i] + tile_index(0, nt, r, k) * TS2;
+  const T* Li = dinv + (lay.toff[i] + k) * TS2;
   const int tid = threadIdx.x;
   for (int e = tid; e < TS2; e += 256) {
-    int a = e % TS, b = e / TS;
-    As[b * LD + a] = Lr[e];
-    Bs[b * LD + a] = Lc[e];
+    const int a = e % TS, b = e / TS;
+    As[b * LD + a] = A[e];
+    Bs[b * LD + a] = Li[e];
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
@@ -240,11 +232,11 @@ __global__ void __launch_bounds__(256) k_update(int k, const int64_t* __restrict
   for (int x = 0; x < 2; x++)
 #pragma unroll
     for (int y = 0; y < 2; y++) {
-      int col = wc + 16 * y + li;
+      const int col = wc + 16 * y + li;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        int row = wr + 16 * x + Mfma<T>::row(lane, q);
-        C[col * TS + row] -= acc[x][y][q];
+        const int row = wr + 16 * x + Mfma<T>::row(lane, q);
+        A[col * TS + row] = acc[x][y][q];
       }
     }
 }
@@ -548,7 +540,8 @@ void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const Loc
 // the trailing matrix is updated once per panel with K = 64 * PW, which cuts
 // its read-modify-write traffic by PW.
 template <class T>
-void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, int* err) {
+void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
+                  int* err) {
   constexpr int PW = 4;
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
@@ -615,11 +608,11 @@ void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalL
   for (const Launch& L : launches) {
     switch (L.kind) {
       case 0:
-        hipLaunchKernelGGL(k_potrf<T>, dim3(L.nact), dim3(256), 0, s, L.k, d_order.p, lay, fac, err);
+        hipLaunchKernelGGL(k_potrf<T>, dim3(L.nact), dim3(64), 0, s, L.k, d_order.p, lay, fac, dinv, err);
         break;
       case 1:
-        hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)L.total), dim3(64), 0, s, L.k, d_pref.p + L.off, L.nact,
-                           d_order.p, lay, fac);
+        hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.k, d_pref.p + L.off, L.nact,
+                           d_order.p, lay, fac, dinv);
         break;
       case 2:
         hipLaunchKernelGGL(k_update_blk<T>, dim3((unsigned)L.total), dim3(256), 0, s, 1, L.kb, L.kn, L.kf, L.kl,
@@ -683,15 +676,6 @@ __device__ inline void store_shared(T* p, T v) {
 
 // broadcast lane `b` of v to the whole wave (b is a compile-time constant
 // after unrolling)
-__device__ inline float bcast(float v, int b) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), b));
-}
-__device__ inline double bcast(double v, int b) {
-  long long u = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), b);
-  int hi = __builtin_amdgcn_readlane((int)(u >> 32), b);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 template <class V>
 __device__ inline V stream_load(const V* p) {
@@ -1124,8 +1108,8 @@ void trsv(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch,
 }  // namespace
 
 void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
-                      int* err) {
-  factor_tiles<double>(s, N, nt, lay, fac, err);
+                      double* dinv, int* err) {
+  factor_tiles<double>(s, N, nt, lay, fac, dinv, err);
 }
 
 void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
@@ -1183,11 +1167,16 @@ void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist) {
 
 void factor_local(tls_ctx* c) {
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), c->stream));
+  // the Cholesky path forms the inverses of the diagonal tiles as it goes
+  if (c->fp32)
+    c->dinv32.alloc((size_t)c->sum_nt * TS2);
+  else
+    c->dinv64.alloc((size_t)c->sum_nt * TS2);
   if (c->kind == 0) {
     if (c->fp32)
-      factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->errflag.p);
+      factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p);
     else
-      factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->errflag.p);
+      factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p);
   } else {
     if (c->fp32)
       factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->errflag.p);
@@ -1199,13 +1188,12 @@ void factor_local(tls_ctx* c) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "non-positive pivot in a local Cholesky factorization");
     fail(TLS_E_SINGULAR, "zero or non-finite pivot in a local LU factorization (no pivoting)");
   }
-  // inverses of the diagonal tiles for the triangular solves
-  if (c->fp32) {
-    c->dinv32.alloc((size_t)c->sum_nt * TS2);
-    diag_inverse<float>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac32.p, c->dinv32.p);
-  } else {
-    c->dinv64.alloc((size_t)c->sum_nt * TS2);
-    diag_inverse<double>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac64.p, c->dinv64.p);
+  // inverses of the diagonal tiles of the LU factors for the triangular solves
+  if (c->kind == 1) {
+    if (c->fp32)
+      diag_inverse<float>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac32.p, c->dinv32.p);
+    else
+      diag_inverse<double>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac64.p, c->dinv64.p);
   }
   TLS_HIP(hipStreamSynchronize(c->stream));
 }

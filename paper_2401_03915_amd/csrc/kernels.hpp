@@ -31,8 +31,9 @@ void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, cons
 void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
                          int* err);
 // generic pieces reused for the coarse factor (always fp64)
+// (dinv: inverses of the diagonal tiles, one per tile row, written as it goes)
 void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay,
-                      double* fac, int* err);
+                      double* fac, double* dinv, int* err);
 // work list of one direction (bwd = descending block rows) in one of the
 // dependency-safe task orderings (1 level, 2 normalized progress,
 // 3 longest chain first)
