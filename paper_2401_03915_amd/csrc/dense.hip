@@ -674,9 +674,6 @@ __device__ inline void store_shared(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// broadcast lane `b` of v to the whole wave (b is a compile-time constant
-// after unrolling)
-
 template <class V>
 __device__ inline V stream_load(const V* p) {
   return __builtin_nontemporal_load(p);
