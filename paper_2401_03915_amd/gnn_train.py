@@ -6,11 +6,11 @@ steps on the 7-8 thousand weights).
 Recipe: layered-elasticity instances (48^3 nodes, 512 boxes of 6^3 nodes,
 overlap 1; slab thickness uniform in {2..8}, random phase; seeds 100..),
 each set up in FP64 with nev = 20 so that its eq. gevpsvd eigenvectors are
-exact to 1e-9 and serve as targets; Adam (lr 3e-3, betas 0.9 / 0.999) on the
+exact to 1e-9 and serve as targets; Adam (lr 2e-3, betas 0.9 / 0.999) on the
 mean loss over all subdomains of all instances.
 
     python -m paper_2401_03915_amd.gnn_train --out weights.txt [--instances 4]
-        [--steps 400] [--c-out 32] [--nev 20]
+        [--steps 2000] [--c-out 32] [--nev 20]
 
 Writes the weights as text (one float per line after '#' header lines) and
 prints one JSON line per 20 steps.
@@ -84,10 +84,10 @@ def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--instances", type=int, default=4)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--c-out", type=int, default=32)
     ap.add_argument("--nev", type=int, default=20)
-    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--nodes", type=int, default=48)
     ap.add_argument("--seed", type=int, default=100)
     args = ap.parse_args()
