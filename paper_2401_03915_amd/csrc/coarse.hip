@@ -195,12 +195,11 @@ void build_coarse_operator(tls_ctx* c) {
   if (c->kind == 0)
     factor_tiles_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->dinv0.p, c->errflag.p);
   else
-    factor_tiles_lu_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->errflag.p);
+    factor_tiles_lu_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->dinv0.p, c->errflag.p);
   if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
     fail(TLS_E_SINGULAR, "zero pivot in the LU factorization of the coarse operator Z^T A Z");
   }
-  if (c->kind == 1) diag_inverse_f64(s, 1, c->nt0, c->layout0(), c->kind, c->A0.p, c->dinv0.p);
   build_plan(c->plan0_fwd, false, one_nt, toff, 1, s);
   build_plan(c->plan0_bwd, true, one_nt, toff, 1, s);
   c->counters0.alloc(4);

@@ -345,113 +345,107 @@ __global__ void __launch_bounds__(256) k_update_blk(int mode, int kb, int kn, in
 // Batched tiled LU without pivoting (general A; full tile storage)
 // ---------------------------------------------------------------------------
 
-// A_kk = L_kk U_kk in LDS (L unit lower, U upper, stored together).
+// A_kk = L_kk U_kk (L unit lower, U upper, stored together) by one
+// wavefront: lane a holds row a in registers; at step j the multipliers of
+// column j are formed and row j (broadcast by readlane) is eliminated from
+// the rows below, with no barrier. Then the inverses (FP64, lane j computes
+// column j) go to dinv[(toff_i + k) * 64^2], packed like the tile: the unit
+// lower inverse strictly below the diagonal, the upper inverse on and above.
 template <class T>
-__global__ void __launch_bounds__(256) k_getrf(int k, const int* __restrict__ order, LocalLayout lay, T* fac,
-                                               int* err) {
-  constexpr int LD = TS + 1;
-  __shared__ T s[TS * LD];
-  int i = order[blockIdx.x];
-  int nt = lay.nt[i];
+__global__ void __launch_bounds__(64) k_getrf(int k, const int* __restrict__ order, LocalLayout lay, T* fac,
+                                              T* dinv, int* err) {
+  constexpr int L1 = TS + 1;
+  __shared__ double Ls[TS * L1];
+  const int i = order[blockIdx.x];
+  const int nt = lay.nt[i];
   T* tile = fac + lay.foff[i] + tile_index(1, nt, k, k) * TS2;
-  const int t = threadIdx.x;
-  for (int e = t; e < TS2; e += 256) s[(e / TS) * LD + (e % TS)] = tile[e];
+  const int a = threadIdx.x;
+  T row[TS];
+#pragma unroll
+  for (int b = 0; b < TS; b++) row[b] = tile[b * TS + a];
   bool bad = false;
+#pragma unroll
   for (int j = 0; j < TS; j++) {
-    __syncthreads();
-    T d = s[j * LD + j];
+    T d = bcast(row[j], j);
     if (!(fabs(d) > T(0)) || !isfinite(d)) {
       bad = true;
       d = T(1);
     }
-    __syncthreads();
-    if (t > j && t < TS) s[j * LD + t] /= d;  // column j of L
-    __syncthreads();
-    for (int e = t; e < TS2; e += 256) {
-      int a = e % TS, b = e / TS;
-      if (a > j && b > j) s[b * LD + a] -= s[j * LD + a] * s[b * LD + j];
+    const T l = row[j] / d;
+#pragma unroll
+    for (int c = j + 1; c < TS; c++) {
+      const T u = bcast(row[c], j);
+      if (a > j) row[c] -= l * u;
     }
+    if (a > j) row[j] = l;
+  }
+  if (bad && a == 0) atomicOr(err, ERR_PIVOT);
+#pragma unroll
+  for (int b = 0; b < TS; b++) {
+    tile[b * TS + a] = row[b];
+    Ls[a + b * L1] = (double)row[b];
   }
   __syncthreads();
-  if (bad && t == 0) atomicOr(err, ERR_PIVOT);
-  for (int e = t; e < TS2; e += 256) tile[e] = s[(e / TS) * LD + (e % TS)];
+  const int j = a;
+  T* out = dinv + (lay.toff[i] + k) * TS2 + (int64_t)j * TS;
+  double x[TS];
+  // unit lower part: L x = e_j, entries below the diagonal
+#pragma unroll
+  for (int r = 0; r < TS; r++) {
+    double v = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int l = 0; l < r; l++) v -= Ls[r + l * L1] * x[l];
+    x[r] = r < j ? 0.0 : v;
+  }
+#pragma unroll
+  for (int r = 0; r < TS; r++)
+    if (r > j) out[r] = (T)x[r];
+  // upper part: U y = e_j, entries on and above the diagonal
+#pragma unroll
+  for (int r = TS - 1; r >= 0; r--) {
+    double v = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int l = r + 1; l < TS; l++) v -= Ls[r + l * L1] * x[l];
+    x[r] = r > j ? 0.0 : v / Ls[r + r * L1];
+  }
+#pragma unroll
+  for (int r = 0; r < TS; r++)
+    if (r <= j) out[r] = (T)x[r];
 }
 
-// Panels of step k: the first half of the grid solves U_kc = L_kk^{-1} A_kc
-// (c > k, one thread per column), the second half L_rk = A_rk U_kk^{-1}
-// (r > k, one thread per row).
+// Panels of step k with the inverses from k_getrf (MFMA): the first half of
+// the grid forms U_kc = L_kk^{-1} A_kc (c > k), the second half
+// L_rk = A_rk U_kk^{-1} (r > k); the result overwrites the tile.
 template <class T>
-__global__ void __launch_bounds__(64) k_trsm_lu(int k, const int64_t* __restrict__ pref, int nact, int64_t half,
-                                                const int* __restrict__ order, LocalLayout lay, T* fac) {
-  constexpr int LD = TS + 1;
-  __shared__ T Ls[TS * LD];
+__global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restrict__ pref, int nact, int64_t half,
+                                                 const int* __restrict__ order, LocalLayout lay, T* fac,
+                                                 const T* __restrict__ dinv) {
+  constexpr int LD = LdsLd<T>::v;
+  __shared__ T As[TS * LD];  // As[kk * LD + row] = left operand (row, kk)
+  __shared__ T Bs[TS * LD];  // Bs[kk * LD + col] = right operand (kk, col)
   int64_t bid = blockIdx.x;
   const bool colpanel = bid >= half;
   if (colpanel) bid -= half;
-  int j = find_slot(pref, nact, bid);
-  int i = order[j];
-  int nt = lay.nt[i];
-  int o = k + 1 + (int)(bid - pref[j]);
+  const int j = find_slot(pref, nact, bid);
+  const int i = order[j];
+  const int nt = lay.nt[i];
+  const int o = k + 1 + (int)(bid - pref[j]);
   T* base = fac + lay.foff[i];
-  const T* D = base + tile_index(1, nt, k, k) * TS2;
-  const int a = threadIdx.x;
-  for (int e = a; e < TS2; e += 64) Ls[(e / TS) * LD + (e % TS)] = D[e];
-  __syncthreads();
-  T x[TS];
-  if (!colpanel) {
-    // column a of A_ko: x <- L_kk^{-1} x (unit lower)
-    T* A = base + tile_index(1, nt, k, o) * TS2;
-#pragma unroll
-    for (int b = 0; b < TS; b++) x[b] = A[a * TS + b];
-#pragma unroll
-    for (int b = 0; b < TS; b++) {
-      T sum = x[b];
-#pragma unroll
-      for (int l = 0; l < b; l++) sum -= Ls[l * LD + b] * x[l];
-      x[b] = sum;
-    }
-#pragma unroll
-    for (int b = 0; b < TS; b++) A[a * TS + b] = x[b];
-  } else {
-    // row a of A_ok: x U_kk = row
-    T* A = base + tile_index(1, nt, o, k) * TS2;
-#pragma unroll
-    for (int b = 0; b < TS; b++) x[b] = A[b * TS + a];
-#pragma unroll
-    for (int b = 0; b < TS; b++) {
-      T sum = x[b];
-#pragma unroll
-      for (int l = 0; l < b; l++) sum -= x[l] * Ls[b * LD + l];
-      x[b] = sum / Ls[b * LD + b];
-    }
-#pragma unroll
-    for (int b = 0; b < TS; b++) A[b * TS + a] = x[b];
-  }
-}
-
-// A_rc -= L_rk U_kc for every trailing tile (r, c > k): MFMA.
-template <class T>
-__global__ void __launch_bounds__(256) k_update_lu(int k, const int64_t* __restrict__ pref, int nact,
-                                                   const int* __restrict__ order, LocalLayout lay, T* fac) {
-  constexpr int LD = LdsLd<T>::v;
-  __shared__ T As[TS * LD];
-  __shared__ T Bs[TS * LD];
-  int64_t bid = blockIdx.x;
-  int j = find_slot(pref, nact, bid);
-  int i = order[j];
-  int nt = lay.nt[i];
-  const int Tn = nt - k - 1;
-  int64_t t = bid - pref[j];
-  int r = k + 1 + (int)(t / Tn), c = k + 1 + (int)(t % Tn);
-  T* base = fac + lay.foff[i];
-  const T* Lr = base + tile_index(1, nt, r, k) * TS2;
-  const T* Uc = base + tile_index(1, nt, k, c) * TS2;
-  T* C = base + tile_index(1, nt, r, c) * TS2;
+  const T* Di = dinv + (lay.toff[i] + k) * TS2;
+  T* X = base + (colpanel ? tile_index(1, nt, o, k) : tile_index(1, nt, k, o)) * TS2;
   const int tid = threadIdx.x;
   for (int e = tid; e < TS2; e += 256) {
-    int a = e % TS, b = e / TS;
-    As[b * LD + a] = Lr[e];  // As[k][row] = L(row, k)
-    Bs[a * LD + b] = Uc[e];  // Bs[k][col] = U(k, col)
+    const int a = e % TS, b = e / TS;  // element (a, b) of a column-major tile
+    const T d = Di[e];
+    if (!colpanel) {
+      // left: unit lower inverse (a > b; 1 on the diagonal); right: A_ko
+      As[b * LD + a] = a > b ? d : (a == b ? T(1) : T(0));
+      Bs[a * LD + b] = X[e];
+    } else {
+      // left: A_ok; right: upper inverse (a <= b)
+      As[b * LD + a] = X[e];
+      Bs[a * LD + b] = a <= b ? d : T(0);
+    }
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
@@ -478,59 +472,200 @@ __global__ void __launch_bounds__(256) k_update_lu(int k, const int64_t* __restr
   for (int x = 0; x < 2; x++)
 #pragma unroll
     for (int y = 0; y < 2; y++) {
-      int col = wc + 16 * y + li;
+      const int col = wc + 16 * y + li;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        int row = wr + 16 * x + Mfma<T>::row(lane, q);
+        const int row = wr + 16 * x + Mfma<T>::row(lane, q);
+        X[col * TS + row] = acc[x][y][q];
+      }
+    }
+}
+
+// Blocked LU update: C_rc -= sum_{k in [kb, kb+kn)} L_rk U_kc (MFMA, the
+// next k-tile pair prefetched into registers). mode 0: the trailing square
+// r, c >= kl (kl clipped to nt); mode 1 (kn = 1, k = kb): the rest of the
+// panel, rows k < r < kl with every column c > k, and rows r >= kl with
+// panel columns k < c < kl.
+template <class T>
+__global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int kl, const int64_t* __restrict__ pref,
+                                                   int nact, const int* __restrict__ order, LocalLayout lay, T* fac) {
+  constexpr int LD = LdsLd<T>::v;
+  __shared__ T As[TS * LD];
+  __shared__ T Bs[TS * LD];
+  const int64_t bid = blockIdx.x;
+  const int j = find_slot(pref, nact, bid);
+  const int i = order[j];
+  const int nt = lay.nt[i];
+  const int kli = min(kl, nt);
+  int64_t t = bid - pref[j];
+  int r, c;
+  if (mode == 0) {
+    const int w = nt - kli;
+    r = kli + (int)(t / w);
+    c = kli + (int)(t % w);
+  } else {
+    const int k = kb;
+    const int64_t ra = kli - k - 1, ca = nt - k - 1;
+    if (t < ra * ca) {
+      r = k + 1 + (int)(t / ca);
+      c = k + 1 + (int)(t % ca);
+    } else {
+      t -= ra * ca;
+      const int cb = kli - k - 1;
+      r = kli + (int)(t / cb);
+      c = k + 1 + (int)(t % cb);
+    }
+  }
+  T* base = fac + lay.foff[i];
+  T* C = base + tile_index(1, nt, r, c) * TS2;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  constexpr int PER = TS2 / 256;
+  T pa[PER], pb[PER];
+  {
+    const T* Lr = base + tile_index(1, nt, r, kb) * TS2;
+    const T* Uc = base + tile_index(1, nt, kb, c) * TS2;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      pa[u] = Lr[tid + 256 * u];
+      pb[u] = Uc[tid + 256 * u];
+    }
+  }
+  for (int k = 0; k < kn; k++) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      const int a = e % TS, b = e / TS;
+      As[b * LD + a] = pa[u];  // As[kk][row] = L(row, kk)
+      Bs[a * LD + b] = pb[u];  // Bs[kk][col] = U(kk, col)
+    }
+    __syncthreads();
+    if (k + 1 < kn) {
+      const T* Lr = base + tile_index(1, nt, r, kb + k + 1) * TS2;
+      const T* Uc = base + tile_index(1, nt, kb + k + 1, c) * TS2;
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        pa[u] = Lr[tid + 256 * u];
+        pb[u] = Uc[tid + 256 * u];
+      }
+    }
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+      T a0 = As[(kk + lk) * LD + wr + li];
+      T a1 = As[(kk + lk) * LD + wr + 16 + li];
+      T b0 = Bs[(kk + lk) * LD + wc + li];
+      T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
+      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int row = wr + 16 * x + Mfma<T>::row(lane, q);
         C[col * TS + row] -= acc[x][y][q];
       }
     }
 }
 
+// Right-looking LU blocked by panels of PW tile columns (as the Cholesky
+// path): for each k of the panel, the diagonal tile (k_getrf), the row and
+// column strips (k_trsm_lu) and the rest of the panel (k_update_lu mode 1);
+// then the trailing square once with K = 64 PW (mode 0).
 template <class T>
-void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, int* err) {
+void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
+                     int* err) {
+  constexpr int PW = 8;
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
-  int maxnt = N ? nt[order[0]] : 0;
-  std::vector<int64_t> pt, pu, off(maxnt + 1, 0), tot_t(maxnt), tot_u(maxnt);
-  std::vector<int> act(maxnt);
-  for (int k = 0; k < maxnt; k++) {
-    off[k] = (int64_t)pt.size();
-    int64_t ct = 0, cu = 0;
+  const int maxnt = N ? nt[order[0]] : 0;
+  struct Launch {
+    int kind, k, kb, kn, kl, nact;
+    int64_t off, total, half;
+  };
+  std::vector<Launch> launches;
+  std::vector<int64_t> pref;
+  auto active = [&](int k) {
     int a = 0;
-    while (a < N && nt[order[a]] > k) {
-      pt.push_back(ct);
-      pu.push_back(cu);
-      int64_t T_ = nt[order[a]] - k - 1;
-      ct += T_;
-      cu += T_ * T_;
-      a++;
+    while (a < N && nt[order[a]] > k) a++;
+    return a;
+  };
+  for (int k0 = 0; k0 < maxnt; k0 += PW) {
+    const int kl = k0 + PW;
+    for (int k = k0; k < std::min(kl, maxnt); k++) {
+      const int act = active(k);
+      launches.push_back(Launch{0, k, 0, 0, 0, act, 0, 0, 0});
+      {
+        int64_t off = (int64_t)pref.size(), tot = 0;
+        for (int a = 0; a < act; a++) {
+          pref.push_back(tot);
+          tot += nt[order[a]] - k - 1;
+        }
+        pref.push_back(tot);
+        if (tot > 0) launches.push_back(Launch{1, k, 0, 0, 0, act, off, 2 * tot, tot});
+      }
+      {
+        int64_t off = (int64_t)pref.size(), tot = 0;
+        for (int a = 0; a < act; a++) {
+          pref.push_back(tot);
+          const int64_t n_ = nt[order[a]], kli = std::min<int64_t>(kl, n_);
+          tot += (kli - k - 1) * (n_ - k - 1) + (n_ - kli) * (kli - k - 1);
+        }
+        pref.push_back(tot);
+        if (tot > 0) launches.push_back(Launch{2, k, k, 1, kl, act, off, tot, 0});
+      }
     }
-    pt.push_back(ct);
-    pu.push_back(cu);
-    act[k] = a;
-    tot_t[k] = ct;
-    tot_u[k] = cu;
+    const int act = active(kl);
+    if (act > 0) {
+      int64_t off = (int64_t)pref.size(), tot = 0;
+      for (int a = 0; a < act; a++) {
+        pref.push_back(tot);
+        const int64_t w = nt[order[a]] - kl;
+        tot += w * w;
+      }
+      pref.push_back(tot);
+      if (tot > 0) launches.push_back(Launch{3, kl, k0, PW, kl, act, off, tot, 0});
+    }
   }
   DBuf<int> d_order;
-  DBuf<int64_t> d_pt, d_pu;
+  DBuf<int64_t> d_pref;
   d_order.upload(order, s);
-  d_pt.upload(pt, s);
-  d_pu.upload(pu, s);
-  for (int k = 0; k < maxnt; k++) {
-    hipLaunchKernelGGL(k_getrf<T>, dim3(act[k]), dim3(256), 0, s, k, d_order.p, lay, fac, err);
+  d_pref.upload(pref, s);
+  for (const Launch& L : launches) {
+    switch (L.kind) {
+      case 0:
+        hipLaunchKernelGGL(k_getrf<T>, dim3(L.nact), dim3(64), 0, s, L.k, d_order.p, lay, fac, dinv, err);
+        break;
+      case 1:
+        hipLaunchKernelGGL(k_trsm_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.k, d_pref.p + L.off, L.nact,
+                           L.half, d_order.p, lay, fac, dinv);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, 1, L.kb, L.kn, L.kl,
+                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        break;
+      default:
+        hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, 0, L.kb, L.kn, L.kl,
+                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        break;
+    }
     TLS_LAUNCH_CHECK();
-    if (tot_t[k] > 0) {
-      hipLaunchKernelGGL(k_trsm_lu<T>, dim3((unsigned)(2 * tot_t[k])), dim3(64), 0, s, k, d_pt.p + off[k], act[k],
-                         tot_t[k], d_order.p, lay, fac);
-      TLS_LAUNCH_CHECK();
-    }
-    if (tot_u[k] > 0) {
-      hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)tot_u[k]), dim3(256), 0, s, k, d_pu.p + off[k], act[k],
-                         d_order.p, lay, fac);
-      TLS_LAUNCH_CHECK();
-    }
   }
   TLS_HIP(hipStreamSynchronize(s));
 }
@@ -542,7 +677,7 @@ void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const Loc
 template <class T>
 void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
                   int* err) {
-  constexpr int PW = 4;
+  constexpr int PW = 8;
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
@@ -681,70 +816,6 @@ __device__ inline V stream_load(const V* p) {
 
 constexpr long long SPIN_LIMIT = 1ll << 26;
 
-// Inverse of every diagonal tile of the local factors, one 64-thread
-// workgroup per tile (block row g of the concatenated tile rows), in FP64
-// from the stored factor; thread j computes column j. Cholesky: L_rr^{-1}
-// (lower, zeros above). LU: the unit lower inverse strictly below the
-// diagonal and U_rr^{-1} on and above it, packed like the LU tile.
-template <class T>
-__global__ void __launch_bounds__(64) k_diag_inv(int N, LocalLayout lay, int kind, const T* __restrict__ fac,
-                                                 T* dinv) {
-  constexpr int L1 = TS + 1;
-  __shared__ double Ls[TS * L1];
-  const int64_t g = blockIdx.x;
-  int lo = 0, hi = N - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (lay.toff[mid] <= g)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const int i = lo;
-  const int r = (int)(g - lay.toff[i]);
-  const int nt = lay.nt[i];
-  const T* dt = fac + lay.foff[i] + tile_index(kind, nt, r, r) * TS2;
-  const int j = threadIdx.x;
-  for (int e = j; e < TS2; e += TS) Ls[(e % TS) + (e / TS) * L1] = (double)dt[e];  // (row, col) at row + col * L1
-  __syncthreads();
-  T* out = dinv + g * TS2 + (int64_t)j * TS;  // column j of the inverse
-  double x[TS];
-  // lower part: L x = e_j (unit diagonal for LU)
-#pragma unroll
-  for (int a = 0; a < TS; a++) {
-    double v = (a == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int b = 0; b < a; b++) v -= Ls[a + b * L1] * x[b];
-    x[a] = a < j ? 0.0 : (kind == 0 ? v / Ls[a + a * L1] : v);
-  }
-  if (kind == 0) {
-#pragma unroll
-    for (int a = 0; a < TS; a++) out[a] = (T)x[a];
-    return;
-  }
-#pragma unroll
-  for (int a = 0; a < TS; a++)
-    if (a > j) out[a] = (T)x[a];
-  // upper part: U y = e_j, entries a <= j
-#pragma unroll
-  for (int a = TS - 1; a >= 0; a--) {
-    double v = (a == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int b = a + 1; b < TS; b++) v -= Ls[a + b * L1] * x[b];
-    x[a] = a > j ? 0.0 : v / Ls[a + a * L1];
-  }
-#pragma unroll
-  for (int a = 0; a < TS; a++)
-    if (a <= j) out[a] = (T)x[a];
-}
-
-template <class T>
-void diag_inverse(hipStream_t s, int N, int64_t tiles, const LocalLayout& lay, int kind, const T* fac, T* dinv) {
-  if (tiles <= 0) return;
-  hipLaunchKernelGGL(k_diag_inv<T>, dim3((unsigned)tiles), dim3(TS), 0, s, N, lay, kind, fac, dinv);
-  TLS_LAUNCH_CHECK();
-}
-
 // Solve modes of the persistent triangular-solve kernel.
 //   FWD_L : L y = b, L lower with its diagonal (Cholesky), block rows ascending
 //   BWD_LT: L^T x = y (Cholesky), block rows descending, tiles read transposed
@@ -753,7 +824,7 @@ void diag_inverse(hipStream_t s, int N, int64_t tiles, const LocalLayout& lay, i
 enum TrsvMode { FWD_L = 0, BWD_LT = 1, FWD_UL = 2, BWD_U = 3 };
 
 // The diagonal block is applied through its precomputed inverse (dinv, one
-// 64 x 64 tile per block row, at (toff_i + r) * TS2; see k_diag_inv): the
+// 64 x 64 tile per block row, at (toff_i + r) * TS2, formed by k_potrf or k_getrf): the
 // right-hand side is reduced into LDS and multiplied by that tile with all
 // 256 threads, instead of a 64-step substitution on one wave.
 template <class T, int MODE>
@@ -1114,10 +1185,6 @@ void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* ep
   trsv<double>(s, mode, p, counter, epoch, lay, fac, dinv, x, err, done, grid);
 }
 
-void diag_inverse_f64(hipStream_t s, int N, int64_t tiles, const LocalLayout& lay, int kind, const double* fac,
-                      double* dinv) {
-  diag_inverse<double>(s, N, tiles, lay, kind, fac, dinv);
-}
 
 void solve_begin(hipStream_t s, int* counters, const int* done) {
   hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(1), 0, s, counters, done);
@@ -1164,7 +1231,7 @@ void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist) {
 
 void factor_local(tls_ctx* c) {
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), c->stream));
-  // the Cholesky path forms the inverses of the diagonal tiles as it goes
+  // both factorizations form the inverses of the diagonal tiles as they go
   if (c->fp32)
     c->dinv32.alloc((size_t)c->sum_nt * TS2);
   else
@@ -1176,28 +1243,21 @@ void factor_local(tls_ctx* c) {
       factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p);
   } else {
     if (c->fp32)
-      factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->errflag.p);
+      factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p);
     else
-      factor_tiles_lu<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->errflag.p);
+      factor_tiles_lu<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p);
   }
   int err = download(c->errflag.p, 1, c->stream)[0];
   if (err & ERR_PIVOT) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "non-positive pivot in a local Cholesky factorization");
     fail(TLS_E_SINGULAR, "zero or non-finite pivot in a local LU factorization (no pivoting)");
   }
-  // inverses of the diagonal tiles of the LU factors for the triangular solves
-  if (c->kind == 1) {
-    if (c->fp32)
-      diag_inverse<float>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac32.p, c->dinv32.p);
-    else
-      diag_inverse<double>(c->stream, c->N, c->sum_nt, c->layout(), c->kind, c->fac64.p, c->dinv64.p);
-  }
   TLS_HIP(hipStreamSynchronize(c->stream));
 }
 
 void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
-                         int* err) {
-  factor_tiles_lu<double>(s, N, nt, lay, fac, err);
+                         double* dinv, int* err) {
+  factor_tiles_lu<double>(s, N, nt, lay, fac, dinv, err);
 }
 
 void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::vector<int64_t>& toff, int order,

@@ -29,7 +29,7 @@ void local_backward(tls_ctx* c, double* x, const int* done);
 void local_trsm_backward(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
 void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
 void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
-                         int* err);
+                         double* dinv, int* err);
 // generic pieces reused for the coarse factor (always fp64)
 // (dinv: inverses of the diagonal tiles, one per tile row, written as it goes)
 void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay,
@@ -42,9 +42,6 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
 // mode: 0 L y = b (Cholesky), 1 L^T x = y, 2 unit-lower L y = b (LU), 3 U x = y
 void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
               const double* fac, const double* dinv, double* x, int* err, const int* done, int grid);
-// inverses of the diagonal tiles of a tile factor (tiles = total tile rows)
-void diag_inverse_f64(hipStream_t s, int N, int64_t tiles, const LocalLayout& lay, int kind, const double* fac,
-                      double* dinv);
 // (re)build the local plans for a task ordering
 void build_local_plans(tls_ctx* c, int order);
 void solve_begin(hipStream_t s, int* counters, const int* done);
