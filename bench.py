@@ -51,17 +51,18 @@ def local_lower_bytes(info, w):
     return float(w) * (float(info["local_sum_m2"]) + float(info["local_sum_m"])) / 2.0
 
 
-def factor_flops(ctx, n_parts):
-    """Algorithmic flops of the batched Cholesky: sum_i m_i^3 / 3 over the
-    overlapping subdomain sizes m_i = #Omega_i (from the library's export)."""
+def factor_flops(ctx, n_parts, spd=True):
+    """Algorithmic flops of the batched factorization over the overlapping
+    subdomain sizes m_i = #Omega_i (from the library's export): Cholesky
+    sum_i m_i^3 / 3, LU sum_i 2 m_i^3 / 3."""
     import paper_2401_03915_amd as tls
     sp = np.zeros(n_parts + 1, dtype=np.int32)
     tls.tls_export(ctx, sub_ptr=sp)
     m = np.diff(sp).astype(np.float64)
-    return float((m ** 3).sum() / 3.0)
+    return float((m ** 3).sum() / 3.0) * (1.0 if spd else 2.0)
 
 
-def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_cache, tol=1e-8):
+def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_cache, composition=0, tol=1e-8):
     import torch
 
     import paper_2401_03915_amd as tls
@@ -73,6 +74,8 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
     def make_opt(profile=0):
         opt = tls.tls_default_options()
         opt.precision = precision
+        opt.matrix_kind = 0 if prob.spd else 1
+        opt.composition = composition
         opt.use_graph = use_graph
         opt.profile = profile
         # the first setup times the solve launch shapes and records the pick in
@@ -104,7 +107,7 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
     ms_per_step = (t1 - t0) * 1e3 / steps
     ctx, st, it, rr = ctxs[-1]
     info = tls.tls_info(ctx)
-    fflops = factor_flops(ctx, prob.n_parts)
+    fflops = factor_flops(ctx, prob.n_parts, prob.spd)
     log(f"precision {precision}: {ms_per_step:.1f} ms/step, {it} iterations, relres {rr:.2e}, status {st}")
     for c, *_ in ctxs[:-1]:
         tls.tls_destroy(c)
@@ -151,20 +154,21 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
     }
 
 
-def cpu_baseline(prob, iters, sample=64, seed=0):
+def cpu_baseline(prob, iters, sample=64, seed=0, composition=0):
     """The FP64 oracle timed on one host thread over a bounded sample of the
     same workload, scaled to the full time-to-solve.
 
     Sample: `sample` subdomains stratified by interior size (evenly spaced
     quantiles of the sorted sizes, so the mean is representative of the
     uneven RCB parts). For each, the oracle's per-subdomain setup (overlap
-    layers, A_ii, sparse LU, eq. gevpsvd with ARPACK, coarse block) and one
-    local solve (mean of 5). Per iteration the oracle also does one product
-    with A and one coarse solve: the same library calls (CSR product, dense
-    Cholesky solve of order n_coarse) are timed on the workload's A and on a
-    seeded SPD matrix of order n_coarse, whose factorization is part of setup.
-    Estimate = N * setup + chol(n_coarse)
-               + iters * (N * local solve + A x + coarse solve)."""
+    layers, A_ii, sparse LU, eq. gevpsvd with ARPACK or the Section 6 SVD,
+    coarse block) and one local solve (mean of 5). Per iteration the oracle
+    also does one product with A (two with the deflated composition) and one
+    coarse solve: the same library calls (CSR product, dense Cholesky or LU
+    solve of order n_coarse) are timed on the workload's A and on a seeded
+    SPD matrix of order n_coarse, whose factorization is part of setup.
+    Estimate = N * setup + factor(n_coarse)
+               + iters * (N * local solve + (1 + composition) A x + coarse solve)."""
     import scipy.linalg as sla
     import scipy.sparse.linalg as spla
     from threadpoolctl import threadpool_limits
@@ -183,7 +187,7 @@ def cpu_baseline(prob, iters, sample=64, seed=0):
             s = schwarz.overlap(prob.A, prob.part, int(i), prob.overlap)
             Aii = schwarz.local_matrix(prob.A, s)
             lu = spla.splu(Aii.tocsc())
-            schwarz.coarse_block(Aii, s, prob.nev, 0, True)
+            schwarz.coarse_block(Aii, s, prob.nev, 0, prob.spd)
             t1 = time.perf_counter()
             rhs = np.ones(s.size)
             for _ in range(5):
@@ -202,15 +206,17 @@ def cpu_baseline(prob, iters, sample=64, seed=0):
         G = rng.standard_normal((nC, nC))
         S = G @ G.T + nC * np.eye(nC)
         t0 = time.perf_counter()
-        f = sla.cho_factor(S, lower=True)
+        f = sla.cho_factor(S, lower=True) if prob.spd else sla.lu_factor(S)
         t_chol = time.perf_counter() - t0
         y = np.ones(nC)
         t0 = time.perf_counter()
         for _ in range(5):
-            sla.cho_solve(f, y)
+            sla.cho_solve(f, y) if prob.spd else sla.lu_solve(f, y)
         t_csolve = (time.perf_counter() - t0) / 5
     work = time.perf_counter() - t_begin
-    est = N * float(np.mean(t_setup)) + t_chol + iters * (N * float(np.mean(t_solve)) + t_spmv + t_csolve)
+    # the deflated composition does one more product with A per apply
+    est = N * float(np.mean(t_setup)) + t_chol + iters * (N * float(np.mean(t_solve)) + (1 + composition) * t_spmv
+                                                         + t_csolve)
     return {
         "value": round(est, 2),
         "unit": "s",
@@ -218,7 +224,8 @@ def cpu_baseline(prob, iters, sample=64, seed=0):
         "kind": "oracle",
         "sample": (f"{len(picks)} of {N} subdomains stratified by size (sizes {min(sizes)}..{max(sizes)}): "
                    f"oracle setup {np.mean(t_setup):.3f} s and local solve {np.mean(t_solve) * 1e3:.2f} ms "
-                   f"per subdomain; A x {t_spmv * 1e3:.1f} ms; Cholesky of order {nC} {t_chol:.2f} s, "
+                   f"per subdomain; A x {t_spmv * 1e3:.1f} ms; {'Cholesky' if prob.spd else 'LU'} of order {nC} "
+                   f"{t_chol:.2f} s, "
                    f"its solve {t_csolve * 1e3:.2f} ms; scaled to N * setup + {iters} iterations; "
                    f"{work:.1f} s of host work"),
     }
@@ -233,6 +240,8 @@ def main():
     ap.add_argument("--scale", type=int, default=None, help="smaller grid side (testing only)")
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--composition", type=int, default=0,
+                    help="0: additive one-level + coarse (PCG for SPD); 1: RAS + deflated coarse correction (FGMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -266,10 +275,12 @@ def main():
         del src, dst
     import tempfile
     tune_cache = os.path.join(tempfile.mkdtemp(prefix="tls_tune_"), "tune.txt")
-    mixed = run_mode(prob, dev_in, 1, args.steps, args.warmup, args.applies, args.graph, tune_cache)
+    mixed = run_mode(prob, dev_in, 1, args.steps, args.warmup, args.applies, args.graph, tune_cache,
+                     args.composition)
     plain = None
     if not args.no_fp64:
-        plain = run_mode(prob, dev_in, 0, args.steps, args.warmup, args.applies, args.graph, tune_cache)
+        plain = run_mode(prob, dev_in, 0, args.steps, args.warmup, args.applies, args.graph, tune_cache,
+                         args.composition)
     info = mixed["info"]
     # dominant kernel: the forward persistent triangular solve of the FP32
     # local factors (the backward one reads the same bytes in about the same
@@ -281,7 +292,8 @@ def main():
     achieved = bytes_launch / (t_fwd * 1e-3) / 1e9 if t_fwd > 0 else 0.0
     roof = {"bound": "hbm", "kernel": "k_trsv<float, FWD_L> (forward local solves of one apply, all subdomains)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": TRAFFIC if (args.config == 2 and args.scale is None) else None,
             "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4), "launches_timed": mixed["n_profiled"],
             "backward_launch_ms": round(t_bwd, 4),
             "backward_GBps": round(bytes_launch / (t_bwd * 1e-3) / 1e9, 1) if t_bwd > 0 else None,
@@ -289,7 +301,9 @@ def main():
     def mfma(mode, dt):
         t = mode["info"]["t_setup"][6] * 1e-3  # batched factorization (+ diagonal-tile inverses), ms -> s
         ach = mode["factor_flops"] / t / 1e12
-        return {"kernel": "batched tiled Cholesky (k_potrf/k_trsm/k_update_blk)", "flops": mode["factor_flops"],
+        kern = ("batched tiled Cholesky (k_potrf/k_trsm/k_update_blk)" if prob.spd
+                else "batched tiled LU (k_getrf/k_trsm_lu/k_update_lu)")
+        return {"kernel": kern, "flops": mode["factor_flops"],
                 "ms": round(t * 1e3, 2), "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                 "frac": round(ach / MFMA_PEAK_TFLOPS[dt], 4)}
     apply_err = None
@@ -313,7 +327,8 @@ def main():
                                                           "overlap 2, nev 16, PCG to 1e-8" if args.config == 2
                                                           else prob.name),
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "parts": prob.n_parts, "overlap": prob.overlap,
-                   "nev": prob.nev, "scale": args.scale, "graph": args.graph},
+                   "nev": prob.nev, "scale": args.scale, "graph": args.graph,
+                   "composition": ["additive", "ras_deflated"][args.composition]},
         "applies_per_s": round(mixed["applies_per_s"], 2),
         "mixed": {"time_to_solve_s": round(mixed["ms_per_step"] / 1e3, 4), "iters": mixed["iters"],
                   "relres": mixed["relres"], "applies_per_s": round(mixed["applies_per_s"], 2),
@@ -337,7 +352,7 @@ def main():
         out["apply_rel_diff_mixed_vs_fp64_own_bases"] = apply_err
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(prob, (plain or mixed)["iters"])
+        out["cpu_baseline"] = cpu_baseline(prob, (plain or mixed)["iters"], composition=args.composition)
     print(json.dumps(out), flush=True)
 
 

@@ -128,6 +128,15 @@ typedef struct {
   /* 1: keep what tls_gnn_forward / tls_gnn_loss_grad need (the local graphs
    * and the eq. gevpsvd eigenvectors as training targets). SPD, nev > 0. */
   int32_t gnn_train;
+  /* How the one-level and coarse parts combine (Q = R_0^T A_00^{-1} R_0):
+   * 0: additive, z = sum_i R_i^T A_ii^{-1} R_i r + Q r (eq. onelevelasm plus
+   *    the coarse correction, the operator of the theory; symmetric for SPD
+   *    A, so PCG is used there);
+   * 1: restricted additive Schwarz (eq. onelevelras) with the deflated
+   *    coarse correction the experiments of Section 7.2 use,
+   *    z = Q r + M_RAS^{-1} (r - A Q r); not symmetric, so tls_solve runs
+   *    FGMRES for every matrix_kind. Default 0. */
+  int32_t composition;
   void* stream;         /* hipStream_t */
 } tls_options;
 

@@ -361,31 +361,71 @@ def coarse_solve(h: Handle, y: np.ndarray) -> np.ndarray:
     return sla.cho_solve(f, y) if kind == "chol" else sla.lu_solve(f, y)
 
 
-def apply(h: Handle, r: np.ndarray, *, coarse: bool = True, restricted: bool = False) -> np.ndarray:
-    """z = M_2^{-1} r = sum_i R_i^T A_ii^{-1} R_i r + R_0^T A_00^{-1} R_0 r
-    (Remark after Section 4.3; one-level part eq. onelevelasm).
-
-    ``restricted=True`` gives the one-level RAS weighting D_i of
-    eq. onelevelras in the local part instead (parity unpinned for the
-    two-level combination)."""
+def one_level(h: Handle, r: np.ndarray, *, restricted: bool = False) -> np.ndarray:
+    """sum_i R_i^T A_ii^{-1} R_i r (eq. onelevelasm), or with the partition
+    of unity D_i between the local solve and the prolongation,
+    sum_i R_i^T D_i A_ii^{-1} R_i r (eq. onelevelras, restricted=True)."""
     z = np.zeros_like(r, dtype=np.float64)
     for s, lu in zip(h.subs, h.local_lu):
         zi = lu.solve(r[s.idx])
         if restricted:
             zi = zi * s.D()
         np.add.at(z, s.idx, zi)
-    if coarse and h.n_coarse:
-        z += h.Z @ coarse_solve(h, h.Z.T @ r)
     return z
 
 
-def solve(h: Handle, b: np.ndarray, tol: float = 1e-8, maxit: int | None = None, restart: int = 30):
-    """x0 = 0; PCG for SPD A, right-preconditioned FGMRES(restart) otherwise,
-    stopping on the unpreconditioned relative residual ||b - A x|| / ||b||
-    (Section 7.2). Returns (x, iterations, true relative residual)."""
+def coarse_correction(h: Handle, r: np.ndarray) -> np.ndarray:
+    """Q r = R_0^T A_00^{-1} R_0 r with R_0 = Z^T (Section 4.1)."""
+    if not h.n_coarse:
+        return np.zeros_like(r, dtype=np.float64)
+    return h.Z @ coarse_solve(h, h.Z.T @ r)
+
+
+COMPOSITIONS = ("additive", "ras_deflated")
+
+
+def apply(h: Handle, r: np.ndarray, *, coarse: bool = True, restricted: bool = False,
+          composition: str = "additive") -> np.ndarray:
+    """The two-level preconditioner applied to r.
+
+    composition="additive" (the theory's operator, Remark after Section 4.3):
+        z = M_2^{-1} r = sum_i R_i^T A_ii^{-1} R_i r + Q r;
+    ``restricted=True`` puts D_i into the one-level part (eq. onelevelras)
+    of that sum.
+
+    composition="ras_deflated" (what the experiments of Section 7.2 run,
+    where the coarse correction is "deflated" by citation only; read as
+    the standard deflated two-level form):
+        z = Q r + M_RAS^{-1} (r - A Q r),
+    with M_RAS^{-1} of eq. onelevelras. It is not symmetric, so it goes
+    with (F)GMRES. Pinned by: M^{-1} A Z = Z (the coarse space is solved
+    exactly), the one-level part equal to one step of the parallel Schwarz
+    method (Efstathiou and Gander, 2003), N = 1 giving A^{-1}.
+
+    ``coarse=False`` drops Q in either form."""
+    if composition not in COMPOSITIONS:
+        raise ValueError(f"composition must be one of {COMPOSITIONS}")
+    use_q = coarse and h.n_coarse > 0
+    if composition == "additive":
+        z = one_level(h, r, restricted=restricted)
+        if use_q:
+            z += coarse_correction(h, r)
+        return z
+    if not use_q:
+        return one_level(h, r, restricted=True)
+    t = coarse_correction(h, r)
+    return t + one_level(h, r - h.A @ t, restricted=True)
+
+
+def solve(h: Handle, b: np.ndarray, tol: float = 1e-8, maxit: int | None = None, restart: int = 30,
+          composition: str = "additive"):
+    """x0 = 0; PCG for SPD A with the (symmetric) additive composition,
+    right-preconditioned FGMRES(restart) otherwise, stopping on the
+    unpreconditioned relative residual ||b - A x|| / ||b|| (Section 7.2).
+    Returns (x, iterations, true relative residual)."""
     Amv = lambda v: h.A @ v  # noqa: E731
-    Mv = lambda v: apply(h, v)  # noqa: E731
-    if h.spd:
+    Mv = lambda v: apply(h, v, composition=composition)  # noqa: E731
+    if h.spd and composition == "additive":
         return krylov.pcg(Amv, Mv, b, tol, maxit or 1000)
     return krylov.fgmres(Amv, Mv, b, tol, restart, maxit or 3000)
 

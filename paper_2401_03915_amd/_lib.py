@@ -65,6 +65,7 @@ class tls_options(C.Structure):
         ("gnn_weights", C.c_void_p),
         ("gnn_c_out", C.c_int32),
         ("gnn_train", C.c_int32),
+        ("composition", C.c_int32),
         ("stream", C.c_void_p),
     ]
 

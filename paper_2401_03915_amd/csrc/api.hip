@@ -61,6 +61,7 @@ void tls_default_options(tls_options* o) {
   o->gnn_weights = nullptr;
   o->gnn_c_out = 0;
   o->gnn_train = 0;
+  o->composition = 0;
   o->stream = nullptr;
 }
 
@@ -91,6 +92,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.nev1 > 0 && overlap == 0) tls::fail(TLS_E_ARG, "overlap 0: nev1 must be 0");
     if (c->opt.solve_order < 0 || c->opt.solve_order > 5) tls::fail(TLS_E_ARG, "solve_order must be in [0, 5]");
     if (c->opt.solve_wgs < 0) tls::fail(TLS_E_ARG, "solve_wgs must be >= 0");
+    if (c->opt.composition != 0 && c->opt.composition != 1) tls::fail(TLS_E_ARG, "composition must be 0 or 1");
     if (c->opt.gnn_weights || c->opt.gnn_train) {
       if (c->opt.matrix_kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");
       if (c->opt.gnn_weights) tls::gnn_check_weights(c->opt.gnn_c_out);
@@ -157,6 +159,10 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     t = clk::now();
     tls::build_coarse_operator(c.get());
     c->t_setup[5] = ms_since(t);
+    if (c->opt.composition == 1) {
+      c->ras_t.alloc(n);
+      c->ras_u.alloc(n);
+    }
     tls::choose_solve_grid(c.get());
     TLS_HIP(hipStreamSynchronize(s));
     c->t_setup[7] = ms_since(t_all);

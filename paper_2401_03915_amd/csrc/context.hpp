@@ -77,6 +77,8 @@ struct tls_ctx {
   tls::DBuf<double> dinv0;    // inverses of the diagonal tiles of the factor of A_0
   tls::DBuf<int> kz_dev;    // coarse columns per subdomain
   tls::DBuf<double> y0;     // coarse vector (padded to M0)
+  tls::DBuf<double> ras_t;  // composition 1: Q r (n)
+  tls::DBuf<double> ras_u;  // composition 1: r - A Q r (n)
   tls::SolvePlan plan0_fwd, plan0_bwd;
   tls::DBuf<int> counters0;
   tls::DBuf<int> one_m, one_nI, one_nP, one_nt;

@@ -356,6 +356,7 @@ __global__ void __launch_bounds__(64) k_getrf(int k, const int* __restrict__ ord
                                               T* dinv, int* err) {
   constexpr int L1 = TS + 1;
   __shared__ double Ls[TS * L1];
+  __shared__ double Xs[TS * L1];
   const int i = order[blockIdx.x];
   const int nt = lay.nt[i];
   T* tile = fac + lay.foff[i] + tile_index(1, nt, k, k) * TS2;
@@ -386,31 +387,29 @@ __global__ void __launch_bounds__(64) k_getrf(int k, const int* __restrict__ ord
     Ls[a + b * L1] = (double)row[b];
   }
   __syncthreads();
+  // thread j forms column j of both inverses; the column lives in LDS (Xs,
+  // column j owned by thread j), since two 64-entry FP64 columns in
+  // registers spill
   const int j = a;
   T* out = dinv + (lay.toff[i] + k) * TS2 + (int64_t)j * TS;
-  double x[TS];
   // unit lower part: L x = e_j, entries below the diagonal
-#pragma unroll
   for (int r = 0; r < TS; r++) {
     double v = (r == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int l = 0; l < r; l++) v -= Ls[r + l * L1] * x[l];
-    x[r] = r < j ? 0.0 : v;
+#pragma unroll 8
+    for (int l = 0; l < r; l++) v -= Ls[r + l * L1] * Xs[l * L1 + j];
+    Xs[r * L1 + j] = r < j ? 0.0 : v;
+    if (r > j) out[r] = (T)v;
   }
-#pragma unroll
-  for (int r = 0; r < TS; r++)
-    if (r > j) out[r] = (T)x[r];
-  // upper part: U y = e_j, entries on and above the diagonal
-#pragma unroll
+  // upper part: U y = e_j, entries on and above the diagonal; rows below r
+  // of Xs already hold y when row r is formed
   for (int r = TS - 1; r >= 0; r--) {
     double v = (r == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int l = r + 1; l < TS; l++) v -= Ls[r + l * L1] * x[l];
-    x[r] = r > j ? 0.0 : v / Ls[r + r * L1];
+#pragma unroll 8
+    for (int l = r + 1; l < TS; l++) v -= Ls[r + l * L1] * Xs[l * L1 + j];
+    v = r > j ? 0.0 : v / Ls[r + r * L1];
+    Xs[r * L1 + j] = v;
+    if (r <= j) out[r] = (T)v;
   }
-#pragma unroll
-  for (int r = 0; r < TS; r++)
-    if (r <= j) out[r] = (T)x[r];
 }
 
 // Panels of step k with the inverses from k_getrf (MFMA): the first half of
@@ -421,8 +420,9 @@ __global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restric
                                                  const int* __restrict__ order, LocalLayout lay, T* fac,
                                                  const T* __restrict__ dinv) {
   constexpr int LD = LdsLd<T>::v;
-  __shared__ T As[TS * LD];  // As[kk * LD + row] = left operand (row, kk)
-  __shared__ T Bs[TS * LD];  // Bs[kk * LD + col] = right operand (kk, col)
+  constexpr int LDB = TS + 4;   // conflict-free store and MFMA read of Bs
+  __shared__ T As[TS * LD];     // As[kk * LD + row] = left operand (row, kk)
+  __shared__ T Bs[TS * LDB];    // Bs[col * LDB + kk] = right operand (kk, col)
   int64_t bid = blockIdx.x;
   const bool colpanel = bid >= half;
   if (colpanel) bid -= half;
@@ -440,11 +440,11 @@ __global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restric
     if (!colpanel) {
       // left: unit lower inverse (a > b; 1 on the diagonal); right: A_ko
       As[b * LD + a] = a > b ? d : (a == b ? T(1) : T(0));
-      Bs[a * LD + b] = X[e];
+      Bs[b * LDB + a] = X[e];
     } else {
       // left: A_ok; right: upper inverse (a <= b)
       As[b * LD + a] = X[e];
-      Bs[a * LD + b] = a <= b ? d : T(0);
+      Bs[b * LDB + a] = a <= b ? d : T(0);
     }
   }
   __syncthreads();
@@ -461,8 +461,8 @@ __global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restric
   for (int kk = 0; kk < TS; kk += 4) {
     T a0 = As[(kk + lk) * LD + wr + li];
     T a1 = As[(kk + lk) * LD + wr + 16 + li];
-    T b0 = Bs[(kk + lk) * LD + wc + li];
-    T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
+    T b0 = Bs[(wc + li) * LDB + kk + lk];
+    T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
     acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
     acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
     acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
@@ -490,8 +490,11 @@ template <class T>
 __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int kl, const int64_t* __restrict__ pref,
                                                    int nact, const int* __restrict__ order, LocalLayout lay, T* fac) {
   constexpr int LD = LdsLd<T>::v;
+  // U_kc is kept as stored (k fastest): pitch TS + 4 puts the 64 lanes of
+  // both the store and the MFMA read on distinct banks
+  constexpr int LDB = TS + 4;
   __shared__ T As[TS * LD];
-  __shared__ T Bs[TS * LD];
+  __shared__ T Bs[TS * LDB];
   const int64_t bid = blockIdx.x;
   const int j = find_slot(pref, nact, bid);
   const int i = order[j];
@@ -545,8 +548,8 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
     for (int u = 0; u < PER; u++) {
       const int e = tid + 256 * u;
       const int a = e % TS, b = e / TS;
-      As[b * LD + a] = pa[u];  // As[kk][row] = L(row, kk)
-      Bs[a * LD + b] = pb[u];  // Bs[kk][col] = U(kk, col)
+      As[b * LD + a] = pa[u];   // As[kk][row] = L(row, kk)
+      Bs[b * LDB + a] = pb[u];  // Bs[col][kk] = U(kk, col)
     }
     __syncthreads();
     if (k + 1 < kn) {
@@ -562,8 +565,8 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
     for (int kk = 0; kk < TS; kk += 4) {
       T a0 = As[(kk + lk) * LD + wr + li];
       T a1 = As[(kk + lk) * LD + wr + 16 + li];
-      T b0 = Bs[(kk + lk) * LD + wc + li];
-      T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
+      T b0 = Bs[(wc + li) * LDB + kk + lk];
+      T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
       acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
       acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
       acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
@@ -1032,111 +1035,190 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
   }
 }
 
-// Triangular solve with many right-hand sides on the tile storage: one
-// workgroup per (subdomain, block of 64 right-hand-side columns) walks the
-// block rows in order; each dependency is a 64x64x64 MFMA product of a
-// factor tile and a solved block, then the diagonal tile is solved for the
-// 64 columns (one thread per column). X_i is column-major with leading
-// dimension M_i (padded size), 64 * nq_i columns.
-template <class T, int MODE>
-__global__ void __launch_bounds__(256) k_trsm_tiles(const int2* __restrict__ tasks, LocalLayout lay,
-                                                    const T* __restrict__ fac, T* X,
-                                                    const int64_t* __restrict__ xoff) {
-  constexpr bool BWD = (MODE == BWD_LT || MODE == BWD_U);
-  constexpr bool TRANS = (MODE == BWD_LT);
-  constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
+// Backward solve with the LU factor's upper block U_II and many right-hand
+// sides, on the tile storage: X_i is column-major with leading dimension
+// M_i = 64 nt_i, its 64 q-th columns one "column block". Subdomain i has
+// nb_i = ceil(#I_i / 64) tile rows; a global step s stands for its tile row
+// k = nb_i - 1 - s, so all subdomains start from their own last row. Rows
+// of the last tile that belong to G have zero right-hand sides and stay
+// zero, so solving with the whole diagonal tile is exact.
+
+// X_k <- U_kk^{-1} X_k (packed inverse from k_getrf, upper part), one
+// workgroup per (subdomain, column block); MFMA.
+template <class T>
+__global__ void __launch_bounds__(256) k_bsolve_diag(int s, const int64_t* __restrict__ pref, int nact,
+                                                     const int* __restrict__ order, LocalLayout lay,
+                                                     const int* __restrict__ nb, const int64_t* __restrict__ xoff,
+                                                     const T* __restrict__ dinv, T* X) {
   constexpr int LD = LdsLd<T>::v;
-  constexpr int DL = TS + 1;
-  __shared__ T As[TS * LD];
-  __shared__ T Bs[TS * LD];
-  __shared__ T Ds[TS * DL];
-  const int i = tasks[blockIdx.x].x, q = tasks[blockIdx.x].y;
+  constexpr int LDB = TS + 4;
+  __shared__ T As[TS * LD];   // As[kk * LD + row] = U_kk^{-1}(row, kk)
+  __shared__ T Bs[TS * LDB];  // Bs[col * LDB + kk] = X_k(kk, col)
+  const int64_t bid = blockIdx.x;
+  const int j = find_slot(pref, nact, bid);
+  const int i = order[j];
+  const int q = (int)(bid - pref[j]);
+  const int k = nb[i] - 1 - s;
+  const int64_t M = (int64_t)lay.nt[i] * TS;
+  T* Xk = X + xoff[i] + (int64_t)q * TS * M + (int64_t)k * TS;
+  const T* Di = dinv + (lay.toff[i] + k) * TS2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TS2; e += 256) {
+    const int a = e % TS, b = e / TS;
+    As[b * LD + a] = a <= b ? Di[e] : T(0);
+    Bs[b * LDB + a] = Xk[(int64_t)b * M + a];
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+#pragma unroll 4
+  for (int kk = 0; kk < TS; kk += 4) {
+    T a0 = As[(kk + lk) * LD + wr + li];
+    T a1 = As[(kk + lk) * LD + wr + 16 + li];
+    T b0 = Bs[(wc + li) * LDB + kk + lk];
+    T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+    acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+    acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+    acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+    acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int qq = 0; qq < 4; qq++) {
+        const int row = wr + 16 * x + Mfma<T>::row(lane, qq);
+        Xk[(int64_t)col * M + row] = acc[x][y][qq];
+      }
+    }
+}
+
+// Row ranges of one update launch for subdomain i, in its tile rows:
+// mode 0 (step s inside the panel starting at s0): rows [lo, k) with
+// k = nb - 1 - s, the panel's rows not yet solved, from the single solved
+// block X_k; mode 1 (after the panel): rows [0, k0) from the panel's
+// blocks X_{k0..k1-1}, k1 = nb - s0, k0 = max(0, k1 - pw).
+struct BsolveRange {
+  int jlo, jhi, klo, khi;
+};
+__host__ __device__ inline BsolveRange bsolve_range(int mode, int s, int s0, int pw, int nb) {
+  BsolveRange r;
+  const int k1 = nb - s0;
+  const int k0 = k1 - pw > 0 ? k1 - pw : 0;
+  if (mode == 0) {
+    const int k = nb - 1 - s;
+    r.jlo = k0;
+    r.jhi = k;
+    r.klo = k;
+    r.khi = k + 1;
+  } else {
+    r.jlo = 0;
+    r.jhi = k0;
+    r.klo = k0;
+    r.khi = k1;
+  }
+  return r;
+}
+
+// X_j -= sum_{k in [klo, khi)} U_jk X_k for the rows j of bsolve_range, one
+// workgroup per (subdomain, row, column block); MFMA, the next tile pair
+// prefetched into registers.
+template <class T>
+__global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, int pw,
+                                                       const int64_t* __restrict__ pref, int nact,
+                                                       const int* __restrict__ order, LocalLayout lay,
+                                                       const int* __restrict__ nb, const int* __restrict__ nq,
+                                                       const int64_t* __restrict__ xoff, const T* __restrict__ fac,
+                                                       T* X) {
+  constexpr int LD = LdsLd<T>::v;
+  constexpr int LDB = TS + 4;
+  __shared__ T As[TS * LD];   // As[kk * LD + row] = U_jk(row, kk)
+  __shared__ T Bs[TS * LDB];  // Bs[col * LDB + kk] = X_k(kk, col)
+  const int64_t bid = blockIdx.x;
+  const int slot = find_slot(pref, nact, bid);
+  const int i = order[slot];
+  const int64_t t = bid - pref[slot];
+  const BsolveRange rg = bsolve_range(mode, s, s0, pw, nb[i]);
+  const int q = (int)(t % nq[i]);
+  const int j = rg.jlo + (int)(t / nq[i]);
   const int nt = lay.nt[i];
   const int64_t M = (int64_t)nt * TS;
   const T* base = fac + lay.foff[i];
-  T* Xq = X + xoff[i] + (int64_t)q * TS * M;  // column block q: element (row, j) at j*M + row
+  T* Xq = X + xoff[i] + (int64_t)q * TS * M;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
   typedef typename Mfma<T>::acc_t acc_t;
-  for (int s = 0; s < nt; s++) {
-    const int r = BWD ? nt - 1 - s : s;
-    acc_t acc[2][2];
+  acc_t acc[2][2];
 #pragma unroll
-    for (int x = 0; x < 2; x++)
+  for (int x = 0; x < 2; x++)
 #pragma unroll
-      for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
-    const int c0 = BWD ? r + 1 : 0, c1 = BWD ? nt : r;
-    for (int c = c0; c < c1; c++) {
-      const T* tile = base + (TRANS ? tile_index(KIND, nt, c, r) : tile_index(KIND, nt, r, c)) * TS2;
-      __syncthreads();
-      for (int e = tid; e < TS2; e += 256) {
-        const int a = e % TS, b = e / TS;
-        if (!TRANS)
-          As[b * LD + a] = tile[e];  // A(row a, k b)
-        else
-          As[a * LD + b] = tile[e];  // A(row b, k a) = tile(a, b)
-        Bs[a * LD + b] = Xq[(int64_t)b * M + c * TS + a];  // B(k a, col b)
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < TS; kk += 4) {
-        T a0 = As[(kk + lk) * LD + wr + li];
-        T a1 = As[(kk + lk) * LD + wr + 16 + li];
-        T b0 = Bs[(kk + lk) * LD + wc + li];
-        T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
-        acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
-      }
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  constexpr int PER = TS2 / 256;
+  T pa[PER], pb[PER];
+  {
+    const T* U = base + tile_index(1, nt, j, rg.klo) * TS2;
+    const T* Xk = Xq + (int64_t)rg.klo * TS;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      pa[u] = U[e];
+      pb[u] = Xk[(int64_t)(e / TS) * M + e % TS];
     }
-    __syncthreads();
-    // right-hand side of the diagonal block: B_r - acc  (into Bs as [row][col])
-    const T* dt = base + tile_index(KIND, nt, r, r) * TS2;
-    for (int e = tid; e < TS2; e += 256) {
-      const int a = e % TS, b = e / TS;
-      Ds[b * DL + a] = dt[e];
-      Bs[a * LD + b] = Xq[(int64_t)b * M + r * TS + a];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int x = 0; x < 2; x++)
-#pragma unroll
-      for (int y = 0; y < 2; y++) {
-        const int col = wc + 16 * y + li;
-#pragma unroll
-        for (int qq = 0; qq < 4; qq++) {
-          const int row = wr + 16 * x + Mfma<T>::row(lane, qq);
-          Bs[row * LD + col] -= acc[x][y][qq];
-        }
-      }
-    __syncthreads();
-    if (tid < TS) {
-      const int col = tid;
-      T v[TS];
-#pragma unroll
-      for (int a = 0; a < TS; a++) v[a] = Bs[a * LD + col];
-      if (!BWD) {
-#pragma unroll
-        for (int b = 0; b < TS; b++) {
-          if (MODE == FWD_L) v[b] /= Ds[b * DL + b];
-#pragma unroll
-          for (int a = b + 1; a < TS; a++) v[a] -= Ds[b * DL + a] * v[b];
-        }
-      } else {
-#pragma unroll
-        for (int b = TS - 1; b >= 0; b--) {
-          v[b] /= Ds[b * DL + b];
-#pragma unroll
-          for (int a = 0; a < b; a++) v[a] -= (TRANS ? Ds[a * DL + b] : Ds[b * DL + a]) * v[b];
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < TS; a++) Xq[(int64_t)col * M + r * TS + a] = v[a];
-    }
-    __syncthreads();
   }
+  for (int k = rg.klo; k < rg.khi; k++) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      const int a = e % TS, b = e / TS;
+      As[b * LD + a] = pa[u];
+      Bs[b * LDB + a] = pb[u];
+    }
+    __syncthreads();
+    if (k + 1 < rg.khi) {
+      const T* U = base + tile_index(1, nt, j, k + 1) * TS2;
+      const T* Xk = Xq + (int64_t)(k + 1) * TS;
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        const int e = tid + 256 * u;
+        pa[u] = U[e];
+        pb[u] = Xk[(int64_t)(e / TS) * M + e % TS];
+      }
+    }
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+      T a0 = As[(kk + lk) * LD + wr + li];
+      T a1 = As[(kk + lk) * LD + wr + 16 + li];
+      T b0 = Bs[(wc + li) * LDB + kk + lk];
+      T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+  }
+  T* Xj = Xq + (int64_t)j * TS;
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int qq = 0; qq < 4; qq++) {
+        const int row = wr + 16 * x + Mfma<T>::row(lane, qq);
+        Xj[(int64_t)col * M + row] -= acc[x][y][qq];
+      }
+    }
 }
 
 __global__ void k_solve_begin(int* counters, const int* done) {
@@ -1346,38 +1428,83 @@ void local_backward(tls_ctx* c, double* x, const int* done) {
 }
 
 template <class T>
-void trsm_tiles_impl(tls_ctx* c, int mode, T* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+void bsolve_upper_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+  constexpr int PW = 8;
   hipStream_t s = c->stream;
-  std::vector<int2> tasks;
-  // largest subdomains first
-  std::vector<int> order(c->N);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->h_nt[a] > c->h_nt[b]; });
-  for (int i : order)
-    for (int q = 0; q < nq[i]; q++) tasks.push_back(make_int2(i, q));
-  if (tasks.empty()) return;
-  DBuf<int2> d_tasks;
-  DBuf<int64_t> d_xoff;
-  d_tasks.upload(tasks, s);
+  const int N = c->N;
+  std::vector<int> nb(N), order;
+  for (int i = 0; i < N; i++) {
+    nb[i] = nq[i] > 0 ? (c->h_nI[i] + TS - 1) / TS : 0;
+    if (nb[i] > 0) order.push_back(i);
+  }
+  if (order.empty()) return;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nb[a] > nb[b]; });
+  const int maxnb = nb[order[0]];
+  struct Launch {
+    int kind, s, s0, nact;
+    int64_t off, total;
+  };
+  std::vector<Launch> launches;
+  std::vector<int64_t> pref;
+  auto active = [&](int step) {
+    int a = 0;
+    while (a < (int)order.size() && nb[order[a]] > step) a++;
+    return a;
+  };
+  auto add_update = [&](int mode, int step, int s0) {
+    const int act = active(mode == 0 ? step : s0);
+    const int64_t off = (int64_t)pref.size();
+    int64_t tot = 0;
+    for (int a = 0; a < act; a++) {
+      const int i = order[a];
+      pref.push_back(tot);
+      const BsolveRange rg = bsolve_range(mode, step, s0, PW, nb[i]);
+      if (rg.jhi > rg.jlo) tot += (int64_t)(rg.jhi - rg.jlo) * nq[i];
+    }
+    pref.push_back(tot);
+    if (tot > 0) launches.push_back(Launch{1 + mode, step, s0, act, off, tot});
+  };
+  for (int s0 = 0; s0 < maxnb; s0 += PW) {
+    for (int st = s0; st < std::min(s0 + PW, maxnb); st++) {
+      const int act = active(st);
+      const int64_t off = (int64_t)pref.size();
+      int64_t tot = 0;
+      for (int a = 0; a < act; a++) {
+        pref.push_back(tot);
+        tot += nq[order[a]];
+      }
+      pref.push_back(tot);
+      launches.push_back(Launch{0, st, s0, act, off, tot});
+      add_update(0, st, s0);
+    }
+    add_update(1, 0, s0);
+  }
+  DBuf<int> d_order, d_nb, d_nq;
+  DBuf<int64_t> d_pref, d_xoff;
+  d_order.upload(order, s);
+  d_nb.upload(nb, s);
+  d_nq.upload(nq, s);
+  d_pref.upload(pref, s);
   d_xoff.upload(xoff, s);
-  const dim3 g((unsigned)tasks.size());
   LocalLayout lay = c->layout();
   const T* fac = c->fp32 ? reinterpret_cast<const T*>(c->fac32.p) : reinterpret_cast<const T*>(c->fac64.p);
-  switch (mode) {
-    case FWD_L: hipLaunchKernelGGL((k_trsm_tiles<T, FWD_L>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
-    case BWD_LT: hipLaunchKernelGGL((k_trsm_tiles<T, BWD_LT>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
-    case FWD_UL: hipLaunchKernelGGL((k_trsm_tiles<T, FWD_UL>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
-    default: hipLaunchKernelGGL((k_trsm_tiles<T, BWD_U>), g, dim3(256), 0, s, d_tasks.p, lay, fac, X, d_xoff.p); break;
+  for (const Launch& L : launches) {
+    if (L.kind == 0)
+      hipLaunchKernelGGL(k_bsolve_diag<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.s, d_pref.p + L.off, L.nact,
+                         d_order.p, lay, d_nb.p, d_xoff.p, dinv, X);
+    else
+      hipLaunchKernelGGL(k_bsolve_update<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.kind - 1, L.s, L.s0, PW,
+                         d_pref.p + L.off, L.nact, d_order.p, lay, d_nb.p, d_nq.p, d_xoff.p, fac, X);
+    TLS_LAUNCH_CHECK();
   }
-  TLS_LAUNCH_CHECK();
   TLS_HIP(hipStreamSynchronize(s));
 }
 
-void local_trsm_backward(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
-  trsm_tiles_impl<float>(c, c->kind == 0 ? BWD_LT : BWD_U, X, nq, xoff);
+void local_bsolve_upper(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+  bsolve_upper_impl<float>(c, c->dinv32.p, X, nq, xoff);
 }
-void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
-  trsm_tiles_impl<double>(c, c->kind == 0 ? BWD_LT : BWD_U, X, nq, xoff);
+void local_bsolve_upper(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+  bsolve_upper_impl<double>(c, c->dinv64.p, X, nq, xoff);
 }
 
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid, hipEvent_t ev_end) {

@@ -1026,8 +1026,8 @@ static void basis_general(tls_ctx* c, T* fac) {
     batched_gemm<T>(s, gd, false, false, GI.p, TG.p, XH.p, T(1), T(1));
   }
   if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_SINGULAR, "zero pivot in a local U_GG block");
-  // H = U_II^{-1} X: the backward solve on the whole factor leaves rows G, T zero
-  local_trsm_backward(c, XH.p, nqH, oXH);
+  // H = U_II^{-1} X (rows I); rows G, T of XH stay zero
+  local_bsolve_upper(c, XH.p, nqH, oXH);
   // K = H^T H
   std::vector<GemmDesc> gd;
   for (int i = 0; i < N; i++) {

@@ -24,10 +24,12 @@ void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hip
 // backward substitution L^T x = x only, on a padded vector of the context's precision
 void local_backward(tls_ctx* c, float* x, const int* done);
 void local_backward(tls_ctx* c, double* x, const int* done);
-// backward substitution (L^T for SPD, U for general) with many right-hand
-// sides: X_i (M_i x 64 nq_i, column-major, at xoff[i]) is overwritten
-void local_trsm_backward(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
-void local_trsm_backward(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
+// general A: X_i <- U_II^{-1} X_i with the leading block U_II (rows and
+// columns I_i) of the LU factor, many right-hand sides: X_i (M_i x 64 nq_i,
+// column-major, at xoff[i]) is overwritten on its rows I_i; rows beyond I_i
+// must be zero in the tile that holds the last rows of I_i
+void local_bsolve_upper(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
+void local_bsolve_upper(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
 void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
                          double* dinv, int* err);
 // generic pieces reused for the coarse factor (always fp64)
@@ -76,6 +78,8 @@ void apply_precond(tls_ctx* c, const double* r, double* z, const int* done, bool
 
 // krylov.hip
 void spmv(tls_ctx* c, const double* x, double* y, const int* done);
+// y = f - A x
+void spmv_residual(tls_ctx* c, const double* f, const double* x, double* y, const int* done);
 void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres,
                   bool* converged);
 

@@ -18,10 +18,12 @@ namespace {
 
 constexpr int RED_BLOCKS = 512;
 
+// y = A x, or y = f - A x when f is given; G lanes per row
 template <int G>
 __global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                               const double* __restrict__ val, const double* __restrict__ x,
-                                              double* __restrict__ y, const int* __restrict__ done) {
+                                              double* __restrict__ y, const int* __restrict__ done,
+                                              const double* __restrict__ f) {
   if (*done) return;
   const int lane = threadIdx.x % G;
   const int row = blockIdx.x * (256 / G) + threadIdx.x / G;
@@ -32,7 +34,7 @@ __global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp,
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
-  if (row < n && lane == 0) y[row] = s;
+  if (row < n && lane == 0) y[row] = f ? f[row] - s : s;
 }
 
 __device__ inline void block_reduce_store(double v, double* out) {
@@ -314,38 +316,41 @@ __global__ void k_gm_update_x(int n, double* x, const double* __restrict__ Zb, c
 
 }  // namespace
 
-void spmv(tls_ctx* c, const double* x, double* y, const int* done) {
+void spmv_residual(tls_ctx* c, const double* f, const double* x, double* y, const int* done) {
   hipStream_t s = c->stream;
   const int n = c->n;
-  switch (c->spmv_group) {
+  const int G = c->spmv_group;
+  const unsigned grid = div_up(n, 256 / G);
+  switch (G) {
     case 4:
-      hipLaunchKernelGGL(k_spmv<4>, dim3(div_up(n, 64)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
-                         y, done);
+      hipLaunchKernelGGL(k_spmv<4>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done, f);
       break;
     case 8:
-      hipLaunchKernelGGL(k_spmv<8>, dim3(div_up(n, 32)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
-                         y, done);
+      hipLaunchKernelGGL(k_spmv<8>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done, f);
       break;
     case 16:
-      hipLaunchKernelGGL(k_spmv<16>, dim3(div_up(n, 16)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p,
-                         x, y, done);
+      hipLaunchKernelGGL(k_spmv<16>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done,
+                         f);
       break;
     case 32:
-      hipLaunchKernelGGL(k_spmv<32>, dim3(div_up(n, 8)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
-                         y, done);
+      hipLaunchKernelGGL(k_spmv<32>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done,
+                         f);
       break;
     default:
-      hipLaunchKernelGGL(k_spmv<64>, dim3(div_up(n, 4)), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x,
-                         y, done);
+      hipLaunchKernelGGL(k_spmv<64>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done,
+                         f);
       break;
   }
   TLS_LAUNCH_CHECK();
 }
 
+void spmv(tls_ctx* c, const double* x, double* y, const int* done) { spmv_residual(c, nullptr, x, y, done); }
+
 void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged);
 
 void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged) {
-  if (c->kind != 0) {
+  // PCG needs a symmetric preconditioner: SPD A with the additive composition
+  if (c->kind != 0 || c->opt.composition != 0) {
     fgmres_solve(c, b, x, tol, iters, relres, converged);
     return;
   }

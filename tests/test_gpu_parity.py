@@ -355,6 +355,9 @@ def test_error_paths():
     with pytest.raises(tls.TlsError) as e:
         _pc(neg.tocsr(), part, 1, 0)
     assert e.value.status == 2
+    with pytest.raises(tls.TlsError) as e:
+        _pc(A, part, 1, 4, composition=2)
+    assert e.value.status == 1
 
 
 # ---------------------------------------------------------------------------
@@ -461,6 +464,106 @@ def test_general_single_subdomain_one_iteration():
     torch.cuda.synchronize()
     assert it == 1 and rr <= 1e-10
     pc.close()
+
+
+# ---------------------------------------------------------------------------
+# RAS (eq. onelevelras) with the deflated coarse correction (Section 7.2)
+# ---------------------------------------------------------------------------
+
+def _ras_case(kind):
+    if kind == "spd":
+        p = make_config(1)
+        return p.A, p.part, 1, 8, True
+    A, part = _cd_problem(64, 4, seed=5)
+    return A, part, 2, 6, False
+
+
+@pytest.mark.parametrize("kind,precision,scale,tol", [("spd", 0, 0, 1e-10), ("spd", 0, 1, 1e-10),
+                                                     ("spd", 1, 0, 5e-3), ("general", 0, 0, 1e-10),
+                                                     ("general", 1, 0, 1e-4)])
+def test_ras_deflated_apply_with_imported_basis(kind, precision, scale, tol):
+    """z = Q r + M_RAS^{-1}(r - A Q r) with the library's own Z imported
+    into the oracle, over several seeded r."""
+    torch = torch_cuda()
+    A, part, delta, nev, spd = _ras_case(kind)
+    say("ras+deflated apply", kind, precision, scale)
+    pc = _pc(A, part, delta, nev, precision=precision, matrix_kind=0 if spd else 1, composition=1,
+             jacobi_scale=scale)
+    ex = pc.export(Z=True)
+    h = oracle.setup(A, part, delta, nev, spd=spd, Z=ex["Z"])
+    rng = np.random.default_rng(13)
+    worst = 0.0
+    for _ in range(5):
+        r = rng.standard_normal(A.shape[0])
+        z = pc.apply(to_dev(r))
+        torch.cuda.synchronize()
+        z_ref = oracle.apply(h, r, composition="ras_deflated")
+        worst = max(worst, np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref))
+    say("  worst apply error", worst)
+    assert worst <= tol
+    # M^{-1} A Z = Z: columns of the library's Z come back through A
+    if precision == 0:
+        Z = ex["Z"]
+        for j in (0, Z.shape[1] // 2, Z.shape[1] - 1):
+            z = pc.apply(to_dev(A @ Z[:, j]))
+            torch.cuda.synchronize()
+            assert np.allclose(z.cpu().numpy(), Z[:, j], rtol=1e-9, atol=1e-9 * np.abs(Z[:, j]).max())
+    pc.close()
+
+
+@pytest.mark.parametrize("kind", ["spd", "general"])
+def test_ras_one_level_and_single_subdomain(kind):
+    """nev = 0 leaves plain RAS; N = 1 gives A^{-1} and one FGMRES step."""
+    torch = torch_cuda()
+    A, part, delta, _, spd = _ras_case(kind)
+    mk = 0 if spd else 1
+    say("ras one-level", kind)
+    pc = _pc(A, part, delta, 0, matrix_kind=mk, composition=1)
+    h = oracle.setup(A, part, delta, 0, spd=spd)
+    r = np.random.default_rng(14).standard_normal(A.shape[0])
+    z = pc.apply(to_dev(r))
+    torch.cuda.synchronize()
+    z_ref = oracle.apply(h, r, composition="ras_deflated")
+    assert np.allclose(z.cpu().numpy(), z_ref, rtol=1e-10, atol=1e-12 * np.abs(z_ref).max())
+    pc.close()
+    one = np.zeros(A.shape[0], dtype=np.int32)
+    pc = _pc(A, one, delta, 4, matrix_kind=mk, composition=1)
+    x, it, rr, st = pc.solve(to_dev(r), 1e-8)
+    torch.cuda.synchronize()
+    assert st == 0 and it == 1 and rr <= 1e-10
+    pc.close()
+
+
+@pytest.mark.parametrize("kind", ["spd", "general"])
+def test_ras_deflated_fgmres_matches_oracle(kind):
+    """FGMRES(30) with the composition converges like the oracle's (CGS2 on
+    the GPU, MGS in the oracle), graph-captured and eager runs give the
+    same iterates, and it needs fewer iterations than the additive
+    composition on these problems."""
+    torch = torch_cuda()
+    A, part, delta, nev, spd = _ras_case(kind)
+    mk = 0 if spd else 1
+    b = np.random.default_rng(15).standard_normal(A.shape[0])
+    say("ras+deflated fgmres", kind)
+    pc = _pc(A, part, delta, nev, matrix_kind=mk, composition=1, use_graph=1)
+    x, it, rr, st = pc.solve(to_dev(b), 1e-8)
+    x2, it2, _, _ = pc.solve(to_dev(b), 1e-8)
+    torch.cuda.synchronize()
+    pc.close()
+    pe = _pc(A, part, delta, nev, matrix_kind=mk, composition=1, use_graph=0)
+    xe, ite, _, _ = pe.solve(to_dev(b), 1e-8)
+    torch.cuda.synchronize()
+    pe.close()
+    h = oracle.setup(A, part, delta, nev, spd=spd)
+    _, it_ref, _ = oracle.solve(h, b, composition="ras_deflated")
+    _, it_add, _ = oracle.solve(h, b)
+    say("  iterations", it, "oracle", it_ref, "additive (oracle)", it_add, "relres", rr)
+    assert st == 0 and rr <= 1e-8
+    assert abs(it - it_ref) <= max(1, int(0.05 * it_ref))
+    assert it == it2 == ite and torch.equal(x, x2) and torch.equal(x, xe)
+    assert it_ref < it_add
+    xs = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
 
 
 def test_autotune_cache_reuse(tmp_path):

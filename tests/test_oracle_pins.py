@@ -342,6 +342,92 @@ def test_basis_freedom():
     assert np.allclose(oracle.apply(h, r), oracle.apply(h2, r), rtol=1e-8, atol=1e-10)
 
 
+# ----------------------------------------------------------------------------
+# RAS (eq. onelevelras) and the deflated coarse correction of Section 7.2
+# ----------------------------------------------------------------------------
+
+def _parallel_schwarz_step(A, subs, b, x):
+    """One step of the parallel Schwarz method, written from its own
+    definition: subdomain i solves its Dirichlet problem on Omega_i with
+    the current iterate as data outside Omega_i, and the new iterate takes
+    each subdomain's values on its own I_i. Dense numpy solves."""
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    xn = np.full(n, np.nan)
+    for s in subs:
+        out = np.ones(n, dtype=bool)
+        out[s.idx] = False
+        u = np.linalg.solve(Ad[np.ix_(s.idx, s.idx)], b[s.idx] - Ad[np.ix_(s.idx, out)] @ x[out])
+        xn[s.idx[: s.n_interior]] = u[: s.n_interior]
+    return xn
+
+
+@pytest.mark.parametrize("delta", [1, 2])
+def test_ras_step_is_parallel_schwarz_step(delta):
+    """x + M_RAS^{-1}(b - A x) equals one parallel Schwarz step from x
+    when D_i is the 0/1 partition of unity (Efstathiou and Gander, 2003);
+    the additive weighting of eq. onelevelasm does not."""
+    rng = np.random.default_rng(8)
+    A, part = _small_hc(16)
+    h = oracle.setup(A, part, delta, 0)
+    b, x = rng.standard_normal((2, A.shape[0]))
+    want = _parallel_schwarz_step(A, h.subs, b, x)
+    got = x + schwarz.one_level(h, b - A @ x, restricted=True)
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-12)
+    asm = x + schwarz.one_level(h, b - A @ x)
+    assert not np.allclose(asm, want, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("spd", [True, False])
+def test_ras_deflated_is_exact_on_the_coarse_space(spd):
+    """M^{-1} = Q + M_RAS^{-1}(I - A Q) gives M^{-1} A Z = Z: the coarse
+    residual is removed exactly before the one-level part sees it. The
+    additive composition does not have this property."""
+    rng = np.random.default_rng(9)
+    if spd:
+        A, part = _small_hc(16)
+    else:
+        A, _ = convdiff_2d(16, rng)
+        part = box_partition_2d(16, 16, 2, 2)
+    h = oracle.setup(A, part, 2, 4, spd=spd)
+    assert h.n_coarse > 0
+    AZ = A @ h.Z
+    got = np.column_stack([oracle.apply(h, AZ[:, j], composition="ras_deflated") for j in range(h.n_coarse)])
+    assert np.allclose(got, h.Z, rtol=1e-9, atol=1e-10)
+    add = np.column_stack([oracle.apply(h, AZ[:, j]) for j in range(h.n_coarse)])
+    assert not np.allclose(add, h.Z, rtol=1e-6, atol=1e-6)
+    # without coarse vectors the composition is plain RAS
+    h0 = oracle.setup(A, part, 2, 0, spd=spd)
+    r = rng.standard_normal(A.shape[0])
+    assert np.allclose(oracle.apply(h0, r, composition="ras_deflated"),
+                       _parallel_schwarz_step(A, h0.subs, r, np.zeros_like(r)), rtol=1e-10, atol=1e-12)
+
+
+def test_ras_deflated_single_subdomain_and_iterations():
+    """N = 1: D_1 = I, no coarse space, M^{-1} = A^{-1} and FGMRES stops
+    after one step. On a 32 x 32 convection-diffusion problem with 16 boxes
+    (delta = 2, nev = 16) RAS with the deflated correction needs fewer
+    FGMRES iterations than the additive composition (Section 7.2 uses it
+    for that reason)."""
+    rng = np.random.default_rng(4)
+    A, _ = convdiff_2d(12, rng)
+    part = np.zeros(A.shape[0], dtype=np.int32)
+    h = oracle.setup(A, part, 2, 4, spd=False)
+    b = rng.standard_normal(A.shape[0])
+    assert np.allclose(oracle.apply(h, b, composition="ras_deflated"), spla.spsolve(A.tocsc(), b),
+                       rtol=1e-10, atol=1e-12)
+    _, it, rr = oracle.solve(h, b, composition="ras_deflated")
+    assert it == 1 and rr <= 1e-10
+    A, _ = convdiff_2d(32, np.random.default_rng(5))
+    part = box_partition_2d(32, 32, 4, 4)
+    h = oracle.setup(A, part, 2, 16, spd=False)
+    b = np.random.default_rng(6).standard_normal(A.shape[0])
+    _, it_add, rr_add = oracle.solve(h, b)
+    _, it_ras, rr_ras = oracle.solve(h, b, composition="ras_deflated")
+    assert rr_add <= 1e-8 and rr_ras <= 1e-8
+    assert it_ras < it_add
+
+
 def test_relabeling_covariance():
     """A global relabeling P (which changes the ascending order inside every
     layer) gives M'^{-1} = P M^{-1} P^T: the method is independent of the
