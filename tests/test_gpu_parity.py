@@ -467,6 +467,120 @@ def test_general_single_subdomain_one_iteration():
 
 
 # ---------------------------------------------------------------------------
+# eigenvalue decay against the overlap (Section 7, Fig. 1) and threshold
+# selection (lambda^2 > tau^2 in eq. gevpsvd, lambda > nu in eq. uppergevp,
+# sigma > tau in Section 6)
+# ---------------------------------------------------------------------------
+
+def _diffusion_3d(nx, levels, seed):
+    from workloads import fv_diffusion_3d, lognormal_kappa_3d
+    rng = np.random.default_rng(seed)
+    A = fv_diffusion_3d(lognormal_kappa_3d(nx, rng)).tocsr()
+    part = rcb_partition((nx, nx, nx), levels, rng, (0.45, 0.55))
+    return A, part
+
+
+def _gap_threshold(spectra, lo=0.3, hi=0.7):
+    """A threshold inside the spread of the given eigenvalues (between the
+    lo and hi quantiles of their logarithms) as far as possible, relatively,
+    from every one of them; returns it and that distance (log10)."""
+    lv = np.log10(np.concatenate([v[v > 0] for v in spectra]))
+    xs = np.linspace(np.quantile(lv, lo), np.quantile(lv, hi), 4001)
+    dist = np.array([np.min(np.abs(lv - x)) for x in xs])
+    b = int(np.argmax(dist))
+    return 10.0 ** xs[b], dist[b]
+
+
+def test_eigenvalue_decay_faster_with_more_layers():
+    """3D lognormal diffusion, 8 RCB parts: the 24 largest eq. gevpsvd
+    eigenvalues per subdomain for delta = 1, 3, 5 match the oracle's dense
+    solve, and their decay lambda_j^2 / lambda_1^2 is faster for larger
+    delta (Section 7, Fig. 1). With one threshold tau for all three, fewer
+    vectors are kept as delta grows."""
+    A, part = _diffusion_3d(16, 3, seed=21)
+    N, nev = 8, 24
+    med, spectra = {}, {}
+    for delta in (1, 3, 5):
+        say("decay delta", delta)
+        pc = _pc(A, part, delta, nev)
+        ex = pc.export()
+        zc = ex["zcol_ptr"]
+        ratios, spectra[delta] = [], []
+        for i in range(N):
+            s = schwarz.overlap(A, part, i, delta)
+            lam, _ = schwarz.gevp2(schwarz.local_matrix(A, s), s, nev)
+            got = ex["eigvals"][zc[i]:zc[i + 1]]
+            assert got.size == lam.size == nev
+            assert np.allclose(got, lam, rtol=1e-7), (delta, i, np.max(np.abs(got / lam - 1)))
+            ratios.append(got / got[0])
+            spectra[delta].append(lam)
+        med[delta] = np.median(np.array(ratios), axis=0)
+        pc.close()
+    say("  median decay at j = 8, 16, 23:", {d: med[d][[8, 16, 23]] for d in med})
+    for j in (8, 16, 23):
+        assert med[1][j] > med[3][j] > med[5][j]
+    tau2, margin = _gap_threshold(spectra[3])
+    assert margin >= np.log10(1.01)
+    kept = {}
+    for delta in (1, 3, 5):
+        pc = _pc(A, part, delta, nev, tau=float(np.sqrt(tau2)))
+        ex = pc.export()
+        kept[delta] = int(ex["zcol_ptr"][-1])
+        if delta == 3:
+            zc = ex["zcol_ptr"]
+            for i in range(N):
+                want = spectra[3][i][spectra[3][i] > tau2]
+                assert zc[i + 1] - zc[i] == want.size
+                assert np.allclose(ex["eigvals"][zc[i]:zc[i + 1]], want, rtol=1e-7)
+        pc.close()
+    say("  kept with tau^2 =", tau2, kept)
+    assert kept[1] > kept[3] > kept[5]
+
+
+def test_threshold_selection_gevp1_and_general():
+    """lambda > nu for eq. uppergevp (nev = 0, cap nev1) and sigma > tau for
+    the Section 6 variant: per-subdomain counts and values equal the
+    oracle's with the threshold placed in a spectral gap."""
+    # eq. uppergevp, delta = 2
+    A = poisson_2d(48)
+    part = box_partition_2d(48, 48, 3, 3)
+    spec = []
+    for i in range(9):
+        s = schwarz.overlap(A, part, i, 2)
+        lam, _ = schwarz.gevp1(schwarz.local_matrix(A, s), s, s.size, nu=1.0, dense=True)
+        spec.append(lam[lam > 1 + 1e-10][:24])
+    nu, margin = _gap_threshold(spec)
+    assert margin >= np.log10(1.001)
+    say("gevp1 threshold nu =", nu)
+    pc = _pc(A, part, 2, 0, nev1=24, nu=float(nu))
+    ex = pc.export()
+    zc = ex["zcol_ptr"]
+    for i in range(9):
+        want = spec[i][spec[i] > nu]
+        assert zc[i + 1] - zc[i] == want.size
+        assert np.allclose(ex["eigvals"][zc[i]:zc[i + 1]], want, rtol=1e-8)
+    pc.close()
+    # Section 6 singular values, general A
+    A, part = _cd_problem(64, 4, seed=5)
+    spec = []
+    for i in range(16):
+        s = schwarz.overlap(A, part, i, 2)
+        sig, _ = schwarz.svd_variant(schwarz.local_matrix(A, s), s, 24)
+        spec.append(sig)
+    tau, margin = _gap_threshold(spec)
+    assert margin >= np.log10(1.001)
+    say("svd threshold tau =", tau)
+    pc = _pc(A, part, 2, 24, matrix_kind=1, tau=float(tau))
+    ex = pc.export()
+    zc = ex["zcol_ptr"]
+    for i in range(16):
+        want = spec[i][spec[i] > tau]
+        assert zc[i + 1] - zc[i] == want.size
+        assert np.allclose(ex["eigvals"][zc[i]:zc[i + 1]], want, rtol=1e-8)
+    pc.close()
+
+
+# ---------------------------------------------------------------------------
 # RAS (eq. onelevelras) with the deflated coarse correction (Section 7.2)
 # ---------------------------------------------------------------------------
 

@@ -342,6 +342,28 @@ def test_basis_freedom():
     assert np.allclose(oracle.apply(h, r), oracle.apply(h2, r), rtol=1e-8, atol=1e-10)
 
 
+def test_eigenvalue_decay_faster_with_more_layers():
+    """Section 7 (Fig. 1): more overlap layers make the eq. gevpsvd
+    eigenvalues decay faster, so a fixed tau keeps fewer vectors. 3D
+    lognormal diffusion on 12^3 cells, 8 RCB parts, delta = 1, 3, 5."""
+    from workloads import fv_diffusion_3d, lognormal_kappa_3d
+    rng = np.random.default_rng(21)
+    A = fv_diffusion_3d(lognormal_kappa_3d(12, rng)).tocsr()
+    part = rcb_partition((12, 12, 12), 3, rng, (0.45, 0.55))
+    med, counts = {}, {}
+    for delta in (1, 3, 5):
+        spec = []
+        for i in range(8):
+            s = schwarz.overlap(A, part, i, delta)
+            lam, _ = schwarz.gevp2(schwarz.local_matrix(A, s), s, 16, dense=True)
+            spec.append(lam)
+        med[delta] = np.median(np.array([l / l[0] for l in spec]), axis=0)
+        counts[delta] = sum(int(np.sum(l / l[0] > 1e-2)) for l in spec)
+    for j in (6, 10, 15):
+        assert med[1][j] > med[3][j] > med[5][j]
+    assert counts[1] > counts[3] > counts[5]
+
+
 # ----------------------------------------------------------------------------
 # RAS (eq. onelevelras) and the deflated coarse correction of Section 7.2
 # ----------------------------------------------------------------------------
