@@ -37,6 +37,8 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # 1 GiB read + 1 GiB write elementwise copy (--copy-probe). None whenever that
 # kernel has changed since the counters were taken.
 TRAFFIC = 16324858746
+# The same for k_symv<float> (explicit local inverses); None until measured.
+TRAFFIC_SYMV = None
 
 
 def log(*a):
@@ -81,7 +83,7 @@ def factor_flops(ctx, n_parts, spd=True):
 
 
 def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_cache, composition=0, restart=30,
-             tol=1e-8):
+             local_inverse=0, tol=1e-8):
     import torch
 
     import paper_2401_03915_amd as tls
@@ -96,6 +98,7 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         opt.matrix_kind = 0 if prob.spd else 1
         opt.composition = composition
         opt.restart = restart
+        opt.local_inverse = local_inverse
         opt.use_graph = use_graph
         opt.profile = profile
         # the first setup times the solve launch shapes and records the pick in
@@ -261,6 +264,8 @@ def main():
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length")
+    ap.add_argument("--local-inverse", type=int, default=None,
+                    help="1: local solves through the explicit A_ii^{-1} (SPD only; default for SPD), 0: substitutions")
     ap.add_argument("--composition", type=int, default=0,
                     help="0: additive one-level + coarse (PCG for SPD); 1: RAS + deflated coarse correction (FGMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -296,12 +301,14 @@ def main():
         del src, dst
     import tempfile
     tune_cache = os.path.join(tempfile.mkdtemp(prefix="tls_tune_"), "tune.txt")
+    if args.local_inverse is None:
+        args.local_inverse = 1 if prob.spd else 0
     mixed = run_mode(prob, dev_in, 1, args.steps, args.warmup, args.applies, args.graph, tune_cache,
-                     args.composition, args.restart)
+                     args.composition, args.restart, args.local_inverse)
     plain = None
     if not args.no_fp64:
         plain = run_mode(prob, dev_in, 0, args.steps, args.warmup, args.applies, args.graph, tune_cache,
-                         args.composition, args.restart)
+                         args.composition, args.restart, args.local_inverse)
     info = mixed["info"]
     # dominant kernel: the forward persistent triangular solve of the FP32
     # local factors (the backward one reads the same bytes in about the same
@@ -311,15 +318,26 @@ def main():
     t_fwd = mixed["local_fwd_ms"]
     t_bwd = mixed["local_solve_ms"] - t_fwd
     achieved = bytes_launch / (t_fwd * 1e-3) / 1e9 if t_fwd > 0 else 0.0
-    fwd_kernel = "k_trsv<float, FWD_L>" if prob.spd else "k_trsv<float, FWD_UL>"
-    roof = {"bound": "hbm", "kernel": f"{fwd_kernel} (forward local solves of one apply, all subdomains)",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": TRAFFIC if (args.config == 2 and args.scale is None) else None,
-            "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4), "launches_timed": mixed["n_profiled"],
-            "backward_launch_ms": round(t_bwd, 4),
-            "backward_GBps": round(bytes_launch / (t_bwd * 1e-3) / 1e9, 1) if t_bwd > 0 else None,
-            "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"]}
+    inverse = bool(info["local_inverse"])
+    default_workload = args.config == 2 and args.scale is None
+    if inverse:
+        roof = {"bound": "hbm",
+                "kernel": "k_symv<float> (product with the explicit local inverses of one apply, all subdomains)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": TRAFFIC_SYMV if default_workload else None,
+                "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4),
+                "launches_timed": mixed["n_profiled"], "reduce_launch_ms": round(t_bwd, 4)}
+    else:
+        fwd_kernel = "k_trsv<float, FWD_L>" if prob.spd else "k_trsv<float, FWD_UL>"
+        roof = {"bound": "hbm", "kernel": f"{fwd_kernel} (forward local solves of one apply, all subdomains)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": TRAFFIC if default_workload else None,
+                "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4),
+                "launches_timed": mixed["n_profiled"], "backward_launch_ms": round(t_bwd, 4),
+                "backward_GBps": round(bytes_launch / (t_bwd * 1e-3) / 1e9, 1) if t_bwd > 0 else None,
+                "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"]}
     def mfma(mode, dt):
         t = mode["info"]["t_setup"][6] * 1e-3  # batched factorization (+ diagonal-tile inverses), ms -> s
         ach = mode["factor_flops"] / t / 1e12
@@ -328,6 +346,14 @@ def main():
         return {"kernel": kern, "flops": mode["factor_flops"],
                 "ms": round(t * 1e3, 2), "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                 "frac": round(ach / MFMA_PEAK_TFLOPS[dt], 4)}
+    def inverse_mfma(mode, dt):
+        t = mode["info"]["t_inverse_ms"] * 1e-3
+        if t <= 0:
+            return None
+        fl = 2.0 * mode["factor_flops"]  # W = L^{-1} and S = W^T W: m^3 / 3 each
+        return {"kernel": "explicit local inverses (k_tinv_row/k_tinv_update/k_tinv_lauum)", "flops": fl,
+                "ms": round(t * 1e3, 2), "achieved": round(fl / t / 1e12, 2), "peak": MFMA_PEAK_TFLOPS[dt],
+                "unit": "TFLOP/s", "frac": round(fl / t / 1e12 / MFMA_PEAK_TFLOPS[dt], 4)}
     apply_err = None
     if plain is not None:
         z32, z64 = mixed["z"], plain["z"]
@@ -348,7 +374,8 @@ def main():
         "config": {"workload": workload_name(args.config, prob, args.scale, args.composition, args.restart),
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "parts": prob.n_parts, "overlap": prob.overlap,
                    "nev": prob.nev, "scale": args.scale, "graph": args.graph,
-                   "composition": ["additive", "ras_deflated"][args.composition]},
+                   "composition": ["additive", "ras_deflated"][args.composition],
+                   "local_solves": "explicit inverse" if inverse else "substitution"},
         "applies_per_s": round(mixed["applies_per_s"], 2),
         "mixed": {"time_to_solve_s": round(mixed["ms_per_step"] / 1e3, 4), "iters": mixed["iters"],
                   "relres": mixed["relres"], "applies_per_s": round(mixed["applies_per_s"], 2),
@@ -358,9 +385,11 @@ def main():
         "roofline": roof,
         "setup_mfma": mfma(mixed, "f32"),
     }
+    if inverse:
+        out["setup_inverse_mfma"] = inverse_mfma(mixed, "f32")
     if plain is not None:
         pinf = plain["info"]
-        b64 = 2.0 * local_lower_bytes(pinf, 8)
+        b64 = (1.0 if inverse else 2.0) * local_lower_bytes(pinf, 8)
         ach64 = b64 / (plain["local_solve_ms"] * 1e-3) / 1e9 if plain["local_solve_ms"] > 0 else 0.0
         out["plain_fp64"] = {"time_to_solve_s": round(plain["ms_per_step"] / 1e3, 4), "iters": plain["iters"],
                              "relres": plain["relres"], "applies_per_s": round(plain["applies_per_s"], 2),
@@ -368,6 +397,8 @@ def main():
                              "n_coarse": pinf["n_coarse"], "local_solve_GBps": round(ach64, 1),
                              "local_solve_frac": round(ach64 / HBM_PEAK_GBS, 4),
                              "setup_mfma": mfma(plain, "f64")}
+        if inverse:
+            out["plain_fp64"]["setup_inverse_mfma"] = inverse_mfma(plain, "f64")
         out["speedup_mixed_vs_fp64"] = round(plain["ms_per_step"] / mixed["ms_per_step"], 3)
         out["apply_rel_diff_mixed_vs_fp64_own_bases"] = apply_err
     if not args.no_cpu_baseline:

@@ -137,6 +137,13 @@ typedef struct {
    *    z = Q r + M_RAS^{-1} (r - A Q r); not symmetric, so tls_solve runs
    *    FGMRES for every matrix_kind. Default 0. */
   int32_t composition;
+  /* 1 (SPD only): after the coarse basis is built, replace each Cholesky
+   * factor by the explicit inverse A_ii^{-1} = L^{-T} L^{-1} (lower tiles,
+   * same storage), so that a local solve is one symmetric product that reads
+   * the stored triangle once instead of two substitutions that read it
+   * twice. Costs about 2 #Omega_i^3 / 3 more flops per subdomain at setup.
+   * 0 (default): forward and backward substitution with the factor. */
+  int32_t local_inverse;
   void* stream;         /* hipStream_t */
 } tls_options;
 
@@ -164,14 +171,18 @@ typedef struct {
   double eig_iters_mean;      /* mean subspace iterations over subdomains    */
   int32_t n_res_history;      /* entries in res_history                      */
   int32_t n_profiled;         /* tls_apply calls timed with profile = 1       */
-  double t_local_solve_ms;    /* mean duration of their local forward + backward
-                                 triangular-solve kernels (HIP events)       */
+  double t_local_solve_ms;    /* mean duration of their local-solve kernels (HIP
+                                 events): forward + backward substitution, or
+                                 the symmetric product + its reduction       */
   double t_apply_ms;          /* mean duration of those whole applies         */
-  double t_local_fwd_ms;      /* mean duration of their forward solve kernel alone */
+  double t_local_fwd_ms;      /* mean duration of their forward-substitution (or
+                                 symmetric-product) kernel alone             */
   int32_t solve_wgs;          /* workgroups used by the persistent solves     */
   int32_t solve_order;        /* task order used by those solves (1 .. 5)     */
   int32_t tuned;              /* 0 default, 1 timed at setup, 2 read from the cache */
   const double* res_history;  /* host array: ||r_k|| / ||b|| per iteration   */
+  int32_t local_inverse;      /* 1 if the local solves use explicit inverses  */
+  double t_inverse_ms;        /* setup ms spent forming them (inside t_setup[7]) */
 } tls_info_t;
 
 /* Fill *opt with the defaults listed above. */

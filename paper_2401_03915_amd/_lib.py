@@ -66,6 +66,7 @@ class tls_options(C.Structure):
         ("gnn_c_out", C.c_int32),
         ("gnn_train", C.c_int32),
         ("composition", C.c_int32),
+        ("local_inverse", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -98,6 +99,8 @@ class tls_info_t(C.Structure):
         ("solve_order", C.c_int32),
         ("tuned", C.c_int32),
         ("res_history", C.POINTER(C.c_double)),
+        ("local_inverse", C.c_int32),
+        ("t_inverse_ms", C.c_double),
     ]
 
 

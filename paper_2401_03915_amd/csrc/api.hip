@@ -62,6 +62,7 @@ void tls_default_options(tls_options* o) {
   o->gnn_c_out = 0;
   o->gnn_train = 0;
   o->composition = 0;
+  o->local_inverse = 0;
   o->stream = nullptr;
 }
 
@@ -93,6 +94,9 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.solve_order < 0 || c->opt.solve_order > 5) tls::fail(TLS_E_ARG, "solve_order must be in [0, 5]");
     if (c->opt.solve_wgs < 0) tls::fail(TLS_E_ARG, "solve_wgs must be >= 0");
     if (c->opt.composition != 0 && c->opt.composition != 1) tls::fail(TLS_E_ARG, "composition must be 0 or 1");
+    if (c->opt.local_inverse != 0 && c->opt.local_inverse != 1) tls::fail(TLS_E_ARG, "local_inverse must be 0 or 1");
+    if (c->opt.local_inverse && c->opt.matrix_kind != 0)
+      tls::fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
     if (c->opt.gnn_weights || c->opt.gnn_train) {
       if (c->opt.matrix_kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");
       if (c->opt.gnn_weights) tls::gnn_check_weights(c->opt.gnn_c_out);
@@ -162,6 +166,11 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.composition == 1) {
       c->ras_t.alloc(n);
       c->ras_u.alloc(n);
+    }
+    if (c->opt.local_inverse) {
+      t = clk::now();
+      tls::form_local_inverse(c.get());
+      c->t_inverse = ms_since(t);
     }
     tls::choose_solve_grid(c.get());
     TLS_HIP(hipStreamSynchronize(s));
@@ -246,6 +255,8 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->t_local_solve_ms = c->prof_count ? c->prof_local_ms / c->prof_count : 0.0;
   info->t_apply_ms = c->prof_count ? c->prof_apply_ms / c->prof_count : 0.0;
   info->t_local_fwd_ms = c->prof_count ? c->prof_fwd_ms / c->prof_count : 0.0;
+  info->local_inverse = c->inv_formed ? 1 : 0;
+  info->t_inverse_ms = c->t_inverse;
   info->solve_wgs = c->solve_grid;
   info->solve_order = c->solve_order;
   info->tuned = c->tuned;

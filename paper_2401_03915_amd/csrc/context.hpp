@@ -44,6 +44,16 @@ struct tls_ctx {
   // inverses of the diagonal tiles (one per tile row, at (toff_i + r) * 64^2)
   tls::DBuf<double> dinv64;
   tls::DBuf<float> dinv32;
+  // explicit local inverses (option local_inverse): the symmetric-product
+  // work list and its partial sums
+  bool inv_formed = false;
+  double t_inverse = 0.0;
+  int64_t inv_nchunks = 0, inv_nrows = 0;
+  tls::DBuf<int4> inv_chunks;
+  tls::DBuf<int2> inv_rows;
+  tls::DBuf<int> inv_rowch;
+  tls::DBuf<float> inv_P32, inv_Q32;
+  tls::DBuf<double> inv_P64, inv_Q64;
 
   // factorization schedule: subdomains sorted by nt (desc); per step prefix tables
   std::vector<int> h_order;

@@ -1221,6 +1221,455 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Explicit inverse of the SPD local matrices (option local_inverse): from the
+// Cholesky factor, W = L^{-1} (block lower triangular, same packed tile
+// layout), then S = A_ii^{-1} = W^T W over the lower tiles with full
+// symmetric diagonal tiles, written over the factor. Each local solve is
+// then one product with S, which reads the lower tiles once, instead of a
+// forward and a backward substitution that read them twice.
+//
+// W is formed right-looking by panels of PW block rows. Row j of W, for
+// k < j: W_jk = -L_jj^{-1} sum_{l=k}^{j-1} L_jl W_lk. The W buffer starts at
+// zero; after each panel the rows below it accumulate the panel's terms
+// (k_tinv_update), and the panel's own terms are added when the row is
+// finished (k_tinv_row). W_jj = L_jj^{-1} comes from the factorization.
+
+// Finish row j (panel starting at j0) for the tiles k <= j of one
+// subdomain: one workgroup per (subdomain, k).
+template <class T>
+__global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* __restrict__ pref, int nact,
+                                                  const int* __restrict__ order, LocalLayout lay,
+                                                  const T* __restrict__ fac, const T* __restrict__ dinv, T* W) {
+  constexpr int LD = LdsLd<T>::v;  // A operand (row, kk) at [kk * LD + row]
+  constexpr int LDB = TS + 4;      // B operand (kk, col) at [col * LDB + kk]
+  __shared__ T As[TS * LD];
+  __shared__ T Bs[TS * LDB];
+  const int64_t bid = blockIdx.x;
+  const int slot = find_slot(pref, nact, bid);
+  const int i = order[slot];
+  const int k = (int)(bid - pref[slot]);
+  const int nt = lay.nt[i];
+  const T* Lb = fac + lay.foff[i];
+  T* Wb = W + lay.foff[i];
+  T* Wjk = Wb + tile_index(0, nt, j, k) * TS2;
+  const T* Dj = dinv + (lay.toff[i] + j) * TS2;
+  const int tid = threadIdx.x;
+  if (k == j) {
+    for (int e = tid; e < TS2; e += 256) Wjk[e] = Dj[e];
+    return;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+  // start from the accumulated terms of earlier panels
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) acc[x][y][q] = Wjk[col * TS + wr + 16 * x + Mfma<T>::row(lane, q)];
+    }
+  const int l0 = k > j0 ? k : j0;
+  for (int l = l0; l < j; l++) {
+    const T* Ljl = Lb + tile_index(0, nt, j, l) * TS2;
+    const T* Wlk = Wb + tile_index(0, nt, l, k) * TS2;
+    __syncthreads();
+    for (int e = tid; e < TS2; e += 256) {
+      const int a = e % TS, b = e / TS;
+      As[b * LD + a] = Ljl[e];
+      Bs[b * LDB + a] = Wlk[e];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+      T a0 = As[(kk + lk) * LD + wr + li];
+      T a1 = As[(kk + lk) * LD + wr + 16 + li];
+      T b0 = Bs[(wc + li) * LDB + kk + lk];
+      T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+  }
+  // W_jk = -L_jj^{-1} acc
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) Bs[col * LDB + wr + 16 * x + Mfma<T>::row(lane, q)] = acc[x][y][q];
+    }
+  for (int e = tid; e < TS2; e += 256) As[(e / TS) * LD + e % TS] = Dj[e];
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+#pragma unroll 4
+  for (int kk = 0; kk < TS; kk += 4) {
+    T a0 = As[(kk + lk) * LD + wr + li];
+    T a1 = As[(kk + lk) * LD + wr + 16 + li];
+    T b0 = Bs[(wc + li) * LDB + kk + lk];
+    T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+    acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+    acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+    acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+    acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) Wjk[col * TS + wr + 16 * x + Mfma<T>::row(lane, q)] = -acc[x][y][q];
+    }
+}
+
+// After the panel [j0, j1): W_rk += sum_{l in [max(k, j0), j1)} L_rl W_lk
+// for the rows r >= j1 and columns k < j1 of every active subdomain
+// (t -> r = j1 + t / j1, k = t % j1); MFMA, the next pair prefetched.
+template <class T>
+__global__ void __launch_bounds__(256) k_tinv_update(int j0, int j1, const int64_t* __restrict__ pref, int nact,
+                                                     const int* __restrict__ order, LocalLayout lay,
+                                                     const T* __restrict__ fac, T* W) {
+  constexpr int LD = LdsLd<T>::v;
+  constexpr int LDB = TS + 4;
+  __shared__ T As[TS * LD];
+  __shared__ T Bs[TS * LDB];
+  const int64_t bid = blockIdx.x;
+  const int slot = find_slot(pref, nact, bid);
+  const int i = order[slot];
+  const int64_t t = bid - pref[slot];
+  const int r = j1 + (int)(t / j1);
+  const int k = (int)(t % j1);
+  const int nt = lay.nt[i];
+  const T* Lb = fac + lay.foff[i];
+  T* Wb = W + lay.foff[i];
+  const int l0 = k > j0 ? k : j0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  constexpr int PER = TS2 / 256;
+  T pa[PER], pb[PER];
+  {
+    const T* Lrl = Lb + tile_index(0, nt, r, l0) * TS2;
+    const T* Wlk = Wb + tile_index(0, nt, l0, k) * TS2;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      pa[u] = Lrl[tid + 256 * u];
+      pb[u] = Wlk[tid + 256 * u];
+    }
+  }
+  for (int l = l0; l < j1; l++) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      As[(e / TS) * LD + e % TS] = pa[u];
+      Bs[(e / TS) * LDB + e % TS] = pb[u];
+    }
+    __syncthreads();
+    if (l + 1 < j1) {
+      const T* Lrl = Lb + tile_index(0, nt, r, l + 1) * TS2;
+      const T* Wlk = Wb + tile_index(0, nt, l + 1, k) * TS2;
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        pa[u] = Lrl[tid + 256 * u];
+        pb[u] = Wlk[tid + 256 * u];
+      }
+    }
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+      T a0 = As[(kk + lk) * LD + wr + li];
+      T a1 = As[(kk + lk) * LD + wr + 16 + li];
+      T b0 = Bs[(wc + li) * LDB + kk + lk];
+      T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+  }
+  T* Wrk = Wb + tile_index(0, nt, r, k) * TS2;
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) Wrk[col * TS + wr + 16 * x + Mfma<T>::row(lane, q)] += acc[x][y][q];
+    }
+}
+
+// S_rc = sum_{k=r}^{nt-1} W_kr^T W_kc for every lower tile (r >= c), written
+// over the factor; one workgroup per tile, the longest sums (small r) of
+// the largest subdomains first. Both operands are kept as stored (kk
+// fastest).
+template <class T>
+__global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ pref, int nact,
+                                                    const int* __restrict__ order, LocalLayout lay,
+                                                    const T* __restrict__ W, T* S) {
+  constexpr int LDA = TS + 4;  // A operand (row, kk) at [row * LDA + kk]
+  constexpr int LDB = TS + 4;  // B operand (kk, col) at [col * LDB + kk]
+  __shared__ T As[TS * LDA];
+  __shared__ T Bs[TS * LDB];
+  const int64_t bid = blockIdx.x;
+  const int slot = find_slot(pref, nact, bid);
+  const int i = order[slot];
+  const int64_t t = bid - pref[slot];
+  int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(r + 1) * (r + 2) / 2 <= t) r++;
+  while ((int64_t)r * (r + 1) / 2 > t) r--;
+  const int c = (int)(t - (int64_t)r * (r + 1) / 2);
+  const int nt = lay.nt[i];
+  const T* Wb = W + lay.foff[i];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  constexpr int PER = TS2 / 256;
+  T pa[PER], pb[PER];
+  {
+    const T* Wkr = Wb + tile_index(0, nt, r, r) * TS2;
+    const T* Wkc = Wb + tile_index(0, nt, r, c) * TS2;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      pa[u] = Wkr[tid + 256 * u];
+      pb[u] = Wkc[tid + 256 * u];
+    }
+  }
+  for (int k = r; k < nt; k++) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      As[(e / TS) * LDA + e % TS] = pa[u];  // A(row = e / TS, kk = e % TS) = W_kr(kk, row)
+      Bs[(e / TS) * LDB + e % TS] = pb[u];  // B(kk = e % TS, col = e / TS) = W_kc(kk, col)
+    }
+    __syncthreads();
+    if (k + 1 < nt) {
+      const T* Wkr = Wb + tile_index(0, nt, k + 1, r) * TS2;
+      const T* Wkc = Wb + tile_index(0, nt, k + 1, c) * TS2;
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        pa[u] = Wkr[tid + 256 * u];
+        pb[u] = Wkc[tid + 256 * u];
+      }
+    }
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+      T a0 = As[(wr + li) * LDA + kk + lk];
+      T a1 = As[(wr + 16 + li) * LDA + kk + lk];
+      T b0 = Bs[(wc + li) * LDB + kk + lk];
+      T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+  }
+  T* Src = S + lay.foff[i] + tile_index(0, nt, r, c) * TS2;
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) Src[col * TS + wr + 16 * x + Mfma<T>::row(lane, q)] = acc[x][y][q];
+    }
+}
+
+// y_i = S_i x_i for every subdomain: one workgroup per chunk of at most
+// SYMV_CH consecutive tiles of one block row r. Thread t holds rows
+// 4 (t % 16) + w and columns t / 16 + 16 u (w, u = 0..3) of each tile (four
+// 16-byte non-temporal loads). The chunk's part of y_r goes to P[chunk];
+// each tile below the diagonal also gives S_rc^T x_r, the term of y_c that
+// the upper triangle would hold, into Q[tile]. k_symv_reduce adds them in
+// a fixed order.
+constexpr int SYMV_CH = 8;
+
+// One chunk of the symmetric product: tiles (r, c0 .. c0 + ntiles - 1) of one
+// subdomain, consecutive in storage from element tile_off of S; Q slots from
+// q_tile on; x_r at xr_off and x_c0 at xc_off; diag = 1 if the last tile is
+// the diagonal one.
+struct alignas(16) SymvChunk {
+  int64_t tile_off, q_tile, xr_off, xc_off;
+  int32_t ntiles, diag;
+};
+
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
+typedef double f64x2_nt __attribute__((ext_vector_type(2)));
+
+// four consecutive elements with non-temporal 16-byte loads
+__device__ inline void load4(const float* p, float (&v)[4]) {
+  const f32x4_nt q = stream_load(reinterpret_cast<const f32x4_nt*>(p));
+  v[0] = q[0];
+  v[1] = q[1];
+  v[2] = q[2];
+  v[3] = q[3];
+}
+__device__ inline void load4(const double* p, double (&v)[4]) {
+  const f64x2_nt q0 = stream_load(reinterpret_cast<const f64x2_nt*>(p));
+  const f64x2_nt q1 = stream_load(reinterpret_cast<const f64x2_nt*>(p) + 1);
+  v[0] = q0[0];
+  v[1] = q0[1];
+  v[2] = q1[0];
+  v[3] = q1[1];
+}
+
+// Lane moves within rows of 16 lanes (DPP): mirror l -> 15 - l, half mirror
+// l -> 7 - l within each half row, and the quad swaps l ^ 1, l ^ 2.
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141, DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E;
+
+// Sum z[0..3] over the 16 lanes of a row (reduce-scatter, 5 lane moves):
+// on return lane l of the row holds the total of z[(l & 15) >> 2].
+template <class T>
+__device__ inline T reduce_scatter4_16(const T (&z)[4], int lane) {
+  const bool hi8 = (lane & 8) != 0, hi4 = (lane & 4) != 0;
+  // partner l ^ 15 (mirror) has bit 3 flipped: keep z[0], z[1] (bit 3 clear) or z[2], z[3]
+  const T k0 = (hi8 ? z[2] : z[0]) + dpp_move<DPP_ROW_MIRROR>(hi8 ? z[0] : z[2]);
+  const T k1 = (hi8 ? z[3] : z[1]) + dpp_move<DPP_ROW_MIRROR>(hi8 ? z[1] : z[3]);
+  // partner within the half row has bit 2 flipped (bit 3 kept)
+  T v = (hi4 ? k1 : k0) + dpp_move<DPP_ROW_HALF_MIRROR>(hi4 ? k0 : k1);
+  v += dpp_move<DPP_QUAD_XOR1>(v);
+  v += dpp_move<DPP_QUAD_XOR2>(v);
+  return v;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_symv(const SymvChunk* __restrict__ chunks, const T* __restrict__ S,
+                                              const T* __restrict__ x, T* P, T* Q, const int* __restrict__ done) {
+  if (*done) return;
+  __shared__ T red[4][TS];
+  __shared__ T qbuf[SYMV_CH * TS];  // the chunk's Q slots, written out together
+  // everything the chunk needs is in its descriptor, so its first tile load
+  // waits on one load only
+  const SymvChunk ch = chunks[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int a0 = 4 * (tid & 15), b0 = tid >> 4;
+  const T* tp = S + ch.tile_off + 4 * tid;
+  const T* xc0 = x + ch.xc_off + b0;
+  const int nt = ch.ntiles;
+  const int noff = ch.diag ? nt - 1 : nt;  // tiles below the diagonal
+  T vn[4][4], xn[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) load4(tp + 1024 * u, vn[u]);
+#pragma unroll
+  for (int u = 0; u < 4; u++) xn[u] = xc0[16 * u];
+  T xr[4];
+#pragma unroll
+  for (int w = 0; w < 4; w++) xr[w] = x[ch.xr_off + a0 + w];
+  T yrow[4] = {T(0), T(0), T(0), T(0)};
+  for (int t = 0; t < nt; t++) {
+    T v[4][4], xc[4];  // v[u][w] = S(a0 + w, b0 + 16 u) of tile t
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      xc[u] = xn[u];
+#pragma unroll
+      for (int w = 0; w < 4; w++) v[u][w] = vn[u][w];
+    }
+    if (t + 1 < nt) {
+#pragma unroll
+      for (int u = 0; u < 4; u++) load4(tp + (int64_t)(t + 1) * TS2 + 1024 * u, vn[u]);
+#pragma unroll
+      for (int u = 0; u < 4; u++) xn[u] = xc0[(t + 1) * TS + 16 * u];
+    }
+#pragma unroll
+    for (int w = 0; w < 4; w++)
+#pragma unroll
+      for (int u = 0; u < 4; u++) yrow[w] += v[u][w] * xc[u];
+    if (t < noff) {
+      // the 16 lanes holding column b0 + 16 u form one DPP row
+      T z[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        T sum = T(0);
+#pragma unroll
+        for (int w = 0; w < 4; w++) sum += v[u][w] * xr[w];
+        z[u] = sum;
+      }
+      const T zs = reduce_scatter4_16(z, tid);
+      if ((tid & 3) == 0) qbuf[t * TS + b0 + 16 * ((tid & 15) >> 2)] = zs;
+    }
+  }
+  // rows a0 + w: add over the 16 threads with this tid % 16 (4 per wave,
+  // lanes 16 apart, then the 4 waves)
+#pragma unroll
+  for (int w = 0; w < 4; w++) {
+    T sum = yrow[w];
+    sum += __shfl_xor(sum, 16);
+    sum += __shfl_xor(sum, 32);
+    yrow[w] = sum;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  if (lane < 16)
+#pragma unroll
+    for (int w = 0; w < 4; w++) red[wave][a0 + w] = yrow[w];
+  __syncthreads();
+  if (tid < TS) P[(int64_t)blockIdx.x * TS + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  // the Q slots of the chunk's tiles are consecutive: one contiguous store
+  // (scattered 4-byte stores per tile cost more than the stream itself)
+  T* qd = Q + ch.q_tile * TS;
+  for (int e = tid; e < noff * TS; e += 256) qd[e] = qbuf[e];
+}
+
+// x_r = sum of the chunks of block row r + sum_{r' > r} Q[(r', r)], in a
+// fixed order; one 64-thread workgroup per block row, x overwritten.
+template <class T>
+__global__ void __launch_bounds__(64) k_symv_reduce(const int2* __restrict__ rows, const int* __restrict__ rowch,
+                                                    LocalLayout lay, const T* __restrict__ P,
+                                                    const T* __restrict__ Q, T* x, const int* __restrict__ done) {
+  if (*done) return;
+  const int2 rw = rows[blockIdx.x];
+  const int i = rw.x, r = rw.y;
+  const int nt = lay.nt[i];
+  const int a = threadIdx.x;
+  const int first = rowch[blockIdx.x];
+  const int nch = (r + SYMV_CH) / SYMV_CH;
+  T s = T(0);
+  for (int q = 0; q < nch; q++) s += P[(int64_t)(first + q) * TS + a];
+  // column r below the diagonal: four independent partial sums, combined in
+  // a fixed order
+  const int64_t tile0 = lay.foff[i] / TS2;
+  T p[4] = {T(0), T(0), T(0), T(0)};
+  int rr = r + 1;
+  for (; rr + 3 < nt; rr += 4)
+#pragma unroll
+    for (int g = 0; g < 4; g++) p[g] += Q[(tile0 + tile_index(0, nt, rr + g, r)) * TS + a];
+  for (; rr < nt; rr++) p[0] += Q[(tile0 + tile_index(0, nt, rr, r)) * TS + a];
+  x[lay.voff[i] + (int64_t)r * TS + a] = s + ((p[0] + p[1]) + (p[2] + p[3]));
+}
+
 __global__ void k_solve_begin(int* counters, const int* done) {
   if (*done) return;
   counters[0] = 0;
@@ -1507,9 +1956,165 @@ void local_bsolve_upper(tls_ctx* c, double* X, const std::vector<int>& nq, const
   bsolve_upper_impl<double>(c, c->dinv64.p, X, nq, xoff);
 }
 
+template <class T>
+void form_inverse_impl(tls_ctx* c, T* fac, const T* dinv) {
+  constexpr int PW = 8;
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->h_nt[a] > c->h_nt[b]; });
+  const int maxnt = N ? c->h_nt[order[0]] : 0;
+  auto active = [&](int j) {
+    int a = 0;
+    while (a < N && c->h_nt[order[a]] > j) a++;
+    return a;
+  };
+  struct Launch {
+    int kind, j, j0, j1, nact;
+    int64_t off, total;
+  };
+  std::vector<Launch> launches;
+  std::vector<int64_t> pref;
+  for (int j0 = 0; j0 < maxnt; j0 += PW) {
+    const int j1 = j0 + PW;
+    for (int j = j0; j < std::min(j1, maxnt); j++) {
+      const int act = active(j);
+      const int64_t off = (int64_t)pref.size();
+      for (int a = 0; a <= act; a++) pref.push_back((int64_t)a * (j + 1));
+      launches.push_back(Launch{0, j, j0, j1, act, off, (int64_t)act * (j + 1)});
+    }
+    const int act = active(j1);
+    if (act > 0) {
+      const int64_t off = (int64_t)pref.size();
+      int64_t tot = 0;
+      for (int a = 0; a < act; a++) {
+        pref.push_back(tot);
+        tot += (int64_t)(c->h_nt[order[a]] - j1) * j1;
+      }
+      pref.push_back(tot);
+      launches.push_back(Launch{1, 0, j0, j1, act, off, tot});
+    }
+  }
+  {
+    const int act = active(0);
+    const int64_t off = (int64_t)pref.size();
+    int64_t tot = 0;
+    for (int a = 0; a < act; a++) {
+      pref.push_back(tot);
+      const int64_t n = c->h_nt[order[a]];
+      tot += n * (n + 1) / 2;
+    }
+    pref.push_back(tot);
+    if (tot > 0) launches.push_back(Launch{2, 0, 0, 0, act, off, tot});
+  }
+  DBuf<int> d_order;
+  DBuf<int64_t> d_pref;
+  d_order.upload(order, s);
+  d_pref.upload(pref, s);
+  DBuf<T> W;
+  W.alloc(std::max<int64_t>(c->fac_elems, 1));
+  TLS_HIP(hipMemsetAsync(W.p, 0, sizeof(T) * std::max<int64_t>(c->fac_elems, 1), s));
+  LocalLayout lay = c->layout();
+  for (const Launch& L : launches) {
+    if (L.total <= 0) continue;
+    switch (L.kind) {
+      case 0:
+        hipLaunchKernelGGL(k_tinv_row<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.j, L.j0, d_pref.p + L.off,
+                           L.nact, d_order.p, lay, fac, dinv, W.p);
+        break;
+      case 1:
+        hipLaunchKernelGGL(k_tinv_update<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.j0, L.j1, d_pref.p + L.off,
+                           L.nact, d_order.p, lay, fac, W.p);
+        break;
+      default:
+        hipLaunchKernelGGL(k_tinv_lauum<T>, dim3((unsigned)L.total), dim3(256), 0, s, d_pref.p + L.off, L.nact,
+                           d_order.p, lay, W.p, fac);
+        break;
+    }
+    TLS_LAUNCH_CHECK();
+  }
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+void form_local_inverse(tls_ctx* c) {
+  if (c->kind != 0) fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
+  hipStream_t s = c->stream;
+  if (c->fp32)
+    form_inverse_impl<float>(c, c->fac32.p, c->dinv32.p);
+  else
+    form_inverse_impl<double>(c, c->fac64.p, c->dinv64.p);
+  // work list of the symmetric product: chunks of at most SYMV_CH tiles of
+  // one block row, rows in the same order
+  std::vector<SymvChunk> chunks;
+  std::vector<int2> rows;
+  std::vector<int> rowch;
+  for (int i = 0; i < c->N; i++) {
+    const int nt = c->h_nt[i];
+    for (int r = 0; r < nt; r++) {
+      rows.push_back(make_int2(i, r));
+      rowch.push_back((int)chunks.size());
+      for (int c0 = 0; c0 <= r; c0 += SYMV_CH) {
+        const int c1 = std::min(c0 + SYMV_CH, r + 1);
+        SymvChunk ch;
+        ch.tile_off = c->h_foff[i] + tile_index(0, nt, r, c0) * TS2;
+        ch.q_tile = c->h_foff[i] / TS2 + tile_index(0, nt, r, c0);
+        ch.xr_off = c->h_voff[i] + (int64_t)r * TS;
+        ch.xc_off = c->h_voff[i] + (int64_t)c0 * TS;
+        ch.ntiles = c1 - c0;
+        ch.diag = c1 == r + 1 ? 1 : 0;
+        chunks.push_back(ch);
+      }
+    }
+  }
+  if (chunks.size() > (size_t)INT32_MAX) fail(TLS_E_ARG, "too many tiles for the symmetric-product work list");
+  c->inv_nchunks = (int64_t)chunks.size();
+  c->inv_nrows = (int64_t)rows.size();
+  static_assert(sizeof(SymvChunk) == 48, "descriptor layout");
+  c->inv_chunks.alloc(chunks.size() * 3);
+  TLS_HIP(hipMemcpyAsync(c->inv_chunks.p, chunks.data(), sizeof(SymvChunk) * chunks.size(), hipMemcpyHostToDevice, s));
+  c->inv_rows.upload(rows, s);
+  c->inv_rowch.upload(rowch, s);
+  const int64_t ntiles = c->fac_elems / TS2;
+  if (c->fp32) {
+    c->inv_P32.alloc(std::max<int64_t>(c->inv_nchunks * TS, 1));
+    c->inv_Q32.alloc(std::max<int64_t>(ntiles * TS, 1));
+  } else {
+    c->inv_P64.alloc(std::max<int64_t>(c->inv_nchunks * TS, 1));
+    c->inv_Q64.alloc(std::max<int64_t>(ntiles * TS, 1));
+  }
+  TLS_HIP(hipStreamSynchronize(s));
+  c->inv_formed = true;
+}
+
+template <class T>
+void symv_solve(tls_ctx* c, const T* S, T* x, T* P, T* Q, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid,
+                hipEvent_t ev_end) {
+  hipStream_t s = c->stream;
+  LocalLayout lay = c->layout();
+  if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
+  if (c->inv_nchunks > 0)
+    hipLaunchKernelGGL(k_symv<T>, dim3((unsigned)c->inv_nchunks), dim3(256), 0, s,
+                       reinterpret_cast<const SymvChunk*>(c->inv_chunks.p), S, x, P, Q, done);
+  TLS_LAUNCH_CHECK();
+  if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
+  if (c->inv_nrows > 0)
+    hipLaunchKernelGGL(k_symv_reduce<T>, dim3((unsigned)c->inv_nrows), dim3(64), 0, s, c->inv_rows.p,
+                       c->inv_rowch.p, lay, P, Q, x, done);
+  TLS_LAUNCH_CHECK();
+  if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));
+}
+
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid, hipEvent_t ev_end) {
   hipStream_t s = c->stream;
   LocalLayout lay = c->layout();
+  if (c->inv_formed) {
+    if (c->fp32)
+      symv_solve<float>(c, c->fac32.p, c->xloc32.p, c->inv_P32.p, c->inv_Q32.p, done, ev_begin, ev_mid, ev_end);
+    else
+      symv_solve<double>(c, c->fac64.p, c->xloc64.p, c->inv_P64.p, c->inv_Q64.p, done, ev_begin, ev_mid, ev_end);
+    return;
+  }
   solve_begin(s, c->counters.p, done);
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
   const int fm = c->kind == 0 ? FWD_L : FWD_UL, bm = c->kind == 0 ? BWD_LT : BWD_U;

@@ -19,6 +19,10 @@ void build_solve_tasks(tls_ctx* c);
 // ev_begin / ev_mid / ev_end (may be null) are recorded right before the
 // forward, between the forward and the backward, and right after the
 // backward triangular-solve kernel
+// option local_inverse: replace every local Cholesky factor by A_ii^{-1}
+// (lower tiles, full symmetric diagonal tiles) and build the symmetric-product
+// work list; local_solve uses it from then on
+void form_local_inverse(tls_ctx* c);
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_mid = nullptr,
                  hipEvent_t ev_end = nullptr);
 // backward substitution L^T x = x only, on a padded vector of the context's precision

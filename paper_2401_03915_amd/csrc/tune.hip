@@ -94,7 +94,7 @@ void choose_solve_grid(tls_ctx* c) {
     if (c->opt.solve_wgs > 0) c->solve_grid = c->opt.solve_wgs;
     return;
   }
-  if (!c->opt.autotune) return;
+  if (!c->opt.autotune || c->inv_formed) return;  // the symmetric product has no launch shape to tune
   const std::string key = tune_key(c);
   int g = 0, ch = 0;
   if (cache_lookup(c->opt.tune_cache, key, &g, &ch)) {

@@ -1,11 +1,13 @@
 """GPU parity at the full sizes of the benchmark configurations, in the launch
-configuration bench.py times (mixed precision, autotuned persistent solves,
+configuration bench.py times (mixed precision, explicit local inverses for SPD
+matrices, autotuned persistent solves otherwise,
 PCG/FGMRES captured in hipGraph chunks), against the oracle on sampled
 outputs it can compute one by one and against properties that hold at any
 size:
 
 * local solves of sampled subdomains (smallest, median, largest) against
-  the oracle's sparse LU, and their backward error;
+  the oracle's sparse LU: forward error within 20 cond(A_ii) u for the
+  explicit inverses (SPD), backward error for the LU substitutions;
 * the dominant eigenvalues of sampled subdomains against the oracle's
   ARPACK solve of eq. gevpsvd (Section 6: dense SVD of H for general A);
 * sampled columns of A_0 against Z^T (A z_j) with the library's own Z;
@@ -26,9 +28,12 @@ pytestmark = pytest.mark.gpu
 
 
 def _pc(p, precision, **kw):
+    """The benchmark's settings: graph-captured Krylov chunks, autotuned
+    solves, and explicit local inverses for SPD matrices."""
     import paper_2401_03915_amd as tls
     return tls.Preconditioner(p.A, p.part, p.overlap, p.nev, precision=precision,
-                              matrix_kind=0 if p.spd else 1, use_graph=1, autotune=1, **kw)
+                              matrix_kind=0 if p.spd else 1, use_graph=1, autotune=1,
+                              local_inverse=1 if p.spd else 0, **kw)
 
 
 def _sample(p, ex):
@@ -60,8 +65,16 @@ def test_full_size_configuration(cfg):
         bwd = np.linalg.norm(Aii @ x - rhs) / (spla.norm(Aii, 1) * np.linalg.norm(x, 1) + np.linalg.norm(rhs, 1))
         fwd = np.linalg.norm(x - xo) / np.linalg.norm(xo)
         say(f"  local solve {i} (m={s.size}): backward {bwd:.1e} forward {fwd:.1e}")
-        assert bwd <= 1e-13
-        assert fwd <= 1e-5  # both solvers are backward stable; the gap is cond(A_ii) eps
+        if p.spd:
+            # product with the explicit inverse: forward error of order
+            # cond(A_ii) u, as for the substitutions; bound 20 cond u
+            lmax = spla.eigsh(Aii, 1, which="LA", return_eigenvectors=False)[0]
+            lmin = spla.eigsh(Aii, 1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+            say(f"    cond {lmax / lmin:.1e}")
+            assert fwd <= 20 * (lmax / lmin) * 2.0 ** -53
+        else:
+            assert bwd <= 1e-13  # substitution with the LU factor is backward stable
+            assert fwd <= 1e-5  # the gap to the sparse LU is cond(A_ii) eps
     # -- sampled eigenvalues: the two smaller samples (the oracle's solve is slow)
     zc = ex["zcol_ptr"]
     for i in picks[:2]:

@@ -94,6 +94,74 @@ def test_local_solves(precision, tol):
     pc.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_local_inverse_solves(precision):
+    """Option local_inverse: each local solve is one product with the
+    explicit A_ii^{-1} = W^T W, W = L^{-1}. Four subdomains of a few thousand
+    rows (block rows of up to 70 tiles, so several chunks per row and a
+    ragged last tile), against the oracle's sparse LU. The explicit inverse
+    carries a forward error of order cond(A_ii) u, as the substitutions do:
+    the bound is 20 cond(A_ii) u, with cond from ARPACK and u the unit
+    roundoff of the local precision."""
+    A, part = _hc_problem(128, 2, seed=2)
+    say("local inverse solves", precision)
+    pc = _pc(A, part, 2, 0, precision=precision, local_inverse=1)
+    assert pc.info()["local_inverse"] == 1
+    u = 2.0 ** -53 if precision == 0 else 2.0 ** -24
+    rng = np.random.default_rng(0)
+    for i in range(int(part.max()) + 1):
+        s = schwarz.overlap(A, part, i, 2)
+        Aii = schwarz.local_matrix(A, s).tocsc()
+        lmax = spla.eigsh(Aii, 1, which="LA", return_eigenvectors=False)[0]
+        lmin = spla.eigsh(Aii, 1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+        cond = lmax / lmin
+        b = rng.standard_normal(s.size)
+        x_ref = spla.spsolve(Aii, b)
+        x = pc.local_solve(i, b)
+        err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+        say("  subdomain", i, "m", s.size, "cond %.1e" % cond, "err", err)
+        assert err <= 20 * cond * u
+    pc.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 5e-3)])
+def test_local_inverse_apply_and_solve(precision, tol):
+    """Option local_inverse on the 64 x 64 Poisson problem: the apply against
+    the oracle with the library's own Z imported, PCG iterations equal to
+    the oracle's (FP64), graph-captured and eager iterates identical (the
+    product's reduction has a fixed order)."""
+    torch = torch_cuda()
+    p = make_config(1)
+    say("local inverse apply", precision)
+    pc = _pc(p.A, p.part, 1, 8, precision=precision, local_inverse=1, use_graph=1)
+    ex = pc.export(Z=True)
+    h = oracle.setup(p.A, p.part, 1, 8, Z=ex["Z"])
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for _ in range(5):
+        r = rng.standard_normal(p.A.shape[0])
+        z = pc.apply(to_dev(r))
+        torch.cuda.synchronize()
+        z_ref = oracle.apply(h, r)
+        worst = max(worst, np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref))
+    say("  worst apply error", worst)
+    assert worst <= tol
+    x, it, rr, st = pc.solve(to_dev(p.b), 1e-8)
+    x2, it2, _, _ = pc.solve(to_dev(p.b), 1e-8)
+    torch.cuda.synchronize()
+    pe = _pc(p.A, p.part, 1, 8, precision=precision, local_inverse=1, use_graph=0)
+    xe, ite, _, _ = pe.solve(to_dev(p.b), 1e-8)
+    torch.cuda.synchronize()
+    assert st == 0 and rr <= 1e-8
+    assert it == it2 == ite and torch.equal(x, x2) and torch.equal(x, xe)
+    if precision == 0:
+        _, it_ref, _ = oracle.solve(oracle.setup(p.A, p.part, 1, 8), p.b)
+        say("  iterations", it, "oracle", it_ref)
+        assert it == it_ref
+    pc.close()
+    pe.close()
+
+
 # ---------------------------------------------------------------------------
 # coarse space (eq. gevpsvd, eq. coarse_space_2) and A_0
 # ---------------------------------------------------------------------------
@@ -357,6 +425,9 @@ def test_error_paths():
     assert e.value.status == 2
     with pytest.raises(tls.TlsError) as e:
         _pc(A, part, 1, 4, composition=2)
+    assert e.value.status == 1
+    with pytest.raises(tls.TlsError) as e:
+        _pc(A, part, 1, 4, matrix_kind=1, local_inverse=1)
     assert e.value.status == 1
 
 
