@@ -45,13 +45,13 @@ struct tls_ctx {
   tls::DBuf<double> dinv64;
   tls::DBuf<float> dinv32;
   // explicit local inverses (option local_inverse): the symmetric-product
-  // work list and its partial sums
+  // work list (block and row descriptors, 16-byte words) and its row and
+  // column partial sums
   bool inv_formed = false;
   double t_inverse = 0.0;
   int64_t inv_nchunks = 0, inv_nrows = 0;
   tls::DBuf<int4> inv_chunks;
-  tls::DBuf<int2> inv_rows;
-  tls::DBuf<int> inv_rowch;
+  tls::DBuf<int4> inv_rows;
   tls::DBuf<float> inv_P32, inv_Q32;
   tls::DBuf<double> inv_P64, inv_Q64;
 

@@ -1498,22 +1498,27 @@ __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ 
     }
 }
 
-// y_i = S_i x_i for every subdomain: one workgroup per chunk of at most
-// SYMV_CH consecutive tiles of one block row r. Thread t holds rows
-// 4 (t % 16) + w and columns t / 16 + 16 u (w, u = 0..3) of each tile (four
-// 16-byte non-temporal loads). The chunk's part of y_r goes to P[chunk];
-// each tile below the diagonal also gives S_rc^T x_r, the term of y_c that
-// the upper triangle would hold, into Q[tile]. k_symv_reduce adds them in
-// a fixed order.
-constexpr int SYMV_CH = 8;
+// y_i = S_i x_i for every subdomain. The lower tiles are cut into blocks of
+// SYMV_B x SYMV_B tiles (block row R, block column C <= R); one workgroup
+// streams one block row by row (the tiles of a row are consecutive in
+// storage). Thread t holds rows 4 (t % 16) + w and columns t / 16 + 16 u
+// (w, u = 0..3) of each tile (four 16-byte non-temporal loads). For each
+// tile row r of the block it writes the block's part of y_r; for each tile
+// column c it writes the sum of S_rc^T x_r over the block's tiles below the
+// diagonal (the terms of y_c that the upper triangle would hold). Partial
+// sums per block rather than per tile keep the writes to about 2 / SYMV_B of
+// a 64-value vector per tile: interleaved with the read stream, writes cost
+// far more than their size. k_symv_reduce adds the partial sums of each row
+// in a fixed order.
+constexpr int SYMV_B = 8;
 
-// One chunk of the symmetric product: tiles (r, c0 .. c0 + ntiles - 1) of one
-// subdomain, consecutive in storage from element tile_off of S; Q slots from
-// q_tile on; x_r at xr_off and x_c0 at xc_off; diag = 1 if the last tile is
-// the diagonal one.
-struct alignas(16) SymvChunk {
-  int64_t tile_off, q_tile, xr_off, xc_off;
-  int32_t ntiles, diag;
+// One block: subdomain factor at foff, x at voff; tile rows [r0, r1), tile
+// columns [c0, c1) (only c <= r is stored); its partial sums at
+// out * SYMV_B * TS in the row and column arrays.
+struct alignas(16) SymvBlock {
+  int64_t foff, voff;
+  int32_t r0, r1, c0, c1;
+  int32_t out, pad_;
 };
 
 typedef float f32x4_nt __attribute__((ext_vector_type(4)));
@@ -1567,108 +1572,119 @@ __device__ inline T reduce_scatter4_16(const T (&z)[4], int lane) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_symv(const SymvChunk* __restrict__ chunks, const T* __restrict__ S,
-                                              const T* __restrict__ x, T* P, T* Q, const int* __restrict__ done) {
+__global__ void __launch_bounds__(256) k_symv(const SymvBlock* __restrict__ blocks, const T* __restrict__ S,
+                                              const T* __restrict__ x, T* RP, T* CP,
+                                              const int* __restrict__ done) {
   if (*done) return;
   __shared__ T red[4][TS];
-  __shared__ T qbuf[SYMV_CH * TS];  // the chunk's Q slots, written out together
-  // everything the chunk needs is in its descriptor, so its first tile load
-  // waits on one load only
-  const SymvChunk ch = chunks[blockIdx.x];
-  const int tid = threadIdx.x;
+  __shared__ T rbuf[SYMV_B * TS];  // row partial sums of the block
+  __shared__ T cbuf[SYMV_B * TS];  // column partial sums of the block
+  const SymvBlock bk = blocks[blockIdx.x];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int a0 = 4 * (tid & 15), b0 = tid >> 4;
-  const T* tp = S + ch.tile_off + 4 * tid;
-  const T* xc0 = x + ch.xc_off + b0;
-  const int nt = ch.ntiles;
-  const int noff = ch.diag ? nt - 1 : nt;  // tiles below the diagonal
-  T vn[4][4], xn[4];
+  const T* Sb = S + bk.foff + 4 * tid;
+  const T* xi = x + bk.voff;
+  T cacc[SYMV_B][4];
 #pragma unroll
-  for (int u = 0; u < 4; u++) load4(tp + 1024 * u, vn[u]);
+  for (int k = 0; k < SYMV_B; k++)
 #pragma unroll
-  for (int u = 0; u < 4; u++) xn[u] = xc0[16 * u];
-  T xr[4];
+    for (int u = 0; u < 4; u++) cacc[k][u] = T(0);
+  for (int r = bk.r0; r < bk.r1; r++) {
+    const int ce = r + 1 < bk.c1 ? r + 1 : bk.c1;  // tiles c0 .. ce - 1 of row r
+    const T* rowp = Sb + ((int64_t)r * (r + 1) / 2 + bk.c0) * TS2;
+    T xr[4];
 #pragma unroll
-  for (int w = 0; w < 4; w++) xr[w] = x[ch.xr_off + a0 + w];
-  T yrow[4] = {T(0), T(0), T(0), T(0)};
-  for (int t = 0; t < nt; t++) {
-    T v[4][4], xc[4];  // v[u][w] = S(a0 + w, b0 + 16 u) of tile t
+    for (int w = 0; w < 4; w++) xr[w] = xi[r * TS + a0 + w];
+    T yrow[4] = {T(0), T(0), T(0), T(0)};
+    T vn[4][4], xn[4];
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      xc[u] = xn[u];
+    for (int u = 0; u < 4; u++) load4(rowp + 1024 * u, vn[u]);
 #pragma unroll
-      for (int w = 0; w < 4; w++) v[u][w] = vn[u][w];
-    }
-    if (t + 1 < nt) {
+    for (int u = 0; u < 4; u++) xn[u] = xi[bk.c0 * TS + b0 + 16 * u];
 #pragma unroll
-      for (int u = 0; u < 4; u++) load4(tp + (int64_t)(t + 1) * TS2 + 1024 * u, vn[u]);
+    for (int k = 0; k < SYMV_B; k++) {
+      const int c = bk.c0 + k;
+      if (c < ce) {
+        T v[4][4], xc[4];  // v[u][w] = S(a0 + w, b0 + 16 u) of tile (r, c)
 #pragma unroll
-      for (int u = 0; u < 4; u++) xn[u] = xc0[(t + 1) * TS + 16 * u];
-    }
+        for (int u = 0; u < 4; u++) {
+          xc[u] = xn[u];
 #pragma unroll
-    for (int w = 0; w < 4; w++)
+          for (int w = 0; w < 4; w++) v[u][w] = vn[u][w];
+        }
+        if (c + 1 < ce) {
 #pragma unroll
-      for (int u = 0; u < 4; u++) yrow[w] += v[u][w] * xc[u];
-    if (t < noff) {
-      // the 16 lanes holding column b0 + 16 u form one DPP row
-      T z[4];
+          for (int u = 0; u < 4; u++) load4(rowp + (int64_t)(k + 1) * TS2 + 1024 * u, vn[u]);
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        T sum = T(0);
+          for (int u = 0; u < 4; u++) xn[u] = xi[(c + 1) * TS + b0 + 16 * u];
+        }
 #pragma unroll
-        for (int w = 0; w < 4; w++) sum += v[u][w] * xr[w];
-        z[u] = sum;
+        for (int w = 0; w < 4; w++)
+#pragma unroll
+          for (int u = 0; u < 4; u++) yrow[w] += v[u][w] * xc[u];
+        if (c < r) {
+#pragma unroll
+          for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int w = 0; w < 4; w++) cacc[k][u] += v[u][w] * xr[w];
+        }
       }
-      const T zs = reduce_scatter4_16(z, tid);
-      if ((tid & 3) == 0) qbuf[t * TS + b0 + 16 * ((tid & 15) >> 2)] = zs;
     }
-  }
-  // rows a0 + w: add over the 16 threads with this tid % 16 (4 per wave,
-  // lanes 16 apart, then the 4 waves)
+    // rows a0 + w of y_r: add over the 16 threads with this tid % 16 (4 per
+    // wave, lanes 16 apart, then the 4 waves)
 #pragma unroll
-  for (int w = 0; w < 4; w++) {
-    T sum = yrow[w];
-    sum += __shfl_xor(sum, 16);
-    sum += __shfl_xor(sum, 32);
-    yrow[w] = sum;
-  }
-  const int wave = tid >> 6, lane = tid & 63;
-  if (lane < 16)
+    for (int w = 0; w < 4; w++) {
+      T sum = yrow[w];
+      sum += __shfl_xor(sum, 16);
+      sum += __shfl_xor(sum, 32);
+      yrow[w] = sum;
+    }
+    if (lane < 16)
 #pragma unroll
-    for (int w = 0; w < 4; w++) red[wave][a0 + w] = yrow[w];
+      for (int w = 0; w < 4; w++) red[wave][a0 + w] = yrow[w];
+    __syncthreads();
+    if (tid < TS) rbuf[(r - bk.r0) * TS + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    __syncthreads();
+  }
+  // column sums: the 16 lanes holding column b0 + 16 u of a tile form one
+  // DPP row
+#pragma unroll
+  for (int k = 0; k < SYMV_B; k++) {
+    const T zs = reduce_scatter4_16(cacc[k], tid);
+    if ((tid & 3) == 0) cbuf[k * TS + b0 + 16 * ((tid & 15) >> 2)] = zs;
+  }
   __syncthreads();
-  if (tid < TS) P[(int64_t)blockIdx.x * TS + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-  // the Q slots of the chunk's tiles are consecutive: one contiguous store
-  // (scattered 4-byte stores per tile cost more than the stream itself)
-  T* qd = Q + ch.q_tile * TS;
-  for (int e = tid; e < noff * TS; e += 256) qd[e] = qbuf[e];
+  const int nr = bk.r1 - bk.r0, nc = bk.c1 - bk.c0;
+  T* rp = RP + (int64_t)bk.out * SYMV_B * TS;
+  T* cp = CP + (int64_t)bk.out * SYMV_B * TS;
+  for (int e = tid; e < nr * TS; e += 256) rp[e] = rbuf[e];
+  for (int e = tid; e < nc * TS; e += 256) cp[e] = cbuf[e];
 }
 
-// x_r = sum of the chunks of block row r + sum_{r' > r} Q[(r', r)], in a
-// fixed order; one 64-thread workgroup per block row, x overwritten.
+// y_r = sum over the blocks of block row R = r / SYMV_B of their row partial
+// sum for r, plus sum over the blocks of block column R (block rows R' >= R)
+// of their column partial sum for r; fixed order, x overwritten. One
+// 64-thread workgroup per tile row; blk0 = first block of the subdomain.
+struct alignas(16) SymvRow {
+  int64_t voff;
+  int32_t r, nbr, blk0, pad_;
+};
+
 template <class T>
-__global__ void __launch_bounds__(64) k_symv_reduce(const int2* __restrict__ rows, const int* __restrict__ rowch,
-                                                    LocalLayout lay, const T* __restrict__ P,
-                                                    const T* __restrict__ Q, T* x, const int* __restrict__ done) {
+__global__ void __launch_bounds__(64) k_symv_reduce(const SymvRow* __restrict__ rows, const T* __restrict__ RP,
+                                                    const T* __restrict__ CP, T* x, const int* __restrict__ done) {
   if (*done) return;
-  const int2 rw = rows[blockIdx.x];
-  const int i = rw.x, r = rw.y;
-  const int nt = lay.nt[i];
+  const SymvRow rw = rows[blockIdx.x];
   const int a = threadIdx.x;
-  const int first = rowch[blockIdx.x];
-  const int nch = (r + SYMV_CH) / SYMV_CH;
-  T s = T(0);
-  for (int q = 0; q < nch; q++) s += P[(int64_t)(first + q) * TS + a];
-  // column r below the diagonal: four independent partial sums, combined in
-  // a fixed order
-  const int64_t tile0 = lay.foff[i] / TS2;
-  T p[4] = {T(0), T(0), T(0), T(0)};
-  int rr = r + 1;
-  for (; rr + 3 < nt; rr += 4)
-#pragma unroll
-    for (int g = 0; g < 4; g++) p[g] += Q[(tile0 + tile_index(0, nt, rr + g, r)) * TS + a];
-  for (; rr < nt; rr++) p[0] += Q[(tile0 + tile_index(0, nt, rr, r)) * TS + a];
-  x[lay.voff[i] + (int64_t)r * TS + a] = s + ((p[0] + p[1]) + (p[2] + p[3]));
+  const int R = rw.r / SYMV_B, rho = rw.r % SYMV_B;
+  T s0 = T(0), s1 = T(0);
+  for (int C = 0; C <= R; C++)
+    s0 += RP[((int64_t)(rw.blk0 + R * (R + 1) / 2 + C) * SYMV_B + rho) * TS + a];
+  for (int Rp = R; Rp < rw.nbr; Rp++)
+    s1 += CP[((int64_t)(rw.blk0 + Rp * (Rp + 1) / 2 + R) * SYMV_B + rho) * TS + a];
+  x[rw.voff + (int64_t)rw.r * TS + a] = s0 + s1;
 }
+
 
 __global__ void k_solve_begin(int* counters, const int* done) {
   if (*done) return;
@@ -2044,63 +2060,84 @@ void form_local_inverse(tls_ctx* c) {
     form_inverse_impl<float>(c, c->fac32.p, c->dinv32.p);
   else
     form_inverse_impl<double>(c, c->fac64.p, c->dinv64.p);
-  // work list of the symmetric product: chunks of at most SYMV_CH tiles of
-  // one block row, rows in the same order
-  std::vector<SymvChunk> chunks;
-  std::vector<int2> rows;
-  std::vector<int> rowch;
+  // work list of the symmetric product: blocks of SYMV_B x SYMV_B tiles, the
+  // largest subdomains first; one reduction row per tile row
+  std::vector<int> order(c->N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->h_nt[a] > c->h_nt[b]; });
+  std::vector<int> blk0(c->N, 0);
+  int64_t nblk = 0;
+  for (int i = 0; i < c->N; i++) {
+    const int64_t nbr = (c->h_nt[i] + SYMV_B - 1) / SYMV_B;
+    blk0[i] = (int)nblk;
+    nblk += nbr * (nbr + 1) / 2;
+  }
+  if (nblk > (int64_t)INT32_MAX / SYMV_B) fail(TLS_E_ARG, "too many tiles for the symmetric-product work list");
+  std::vector<SymvBlock> blocks;
+  std::vector<SymvRow> rows;
+  blocks.reserve(nblk);
+  for (int i : order) {
+    const int nt = c->h_nt[i];
+    const int nbr = (nt + SYMV_B - 1) / SYMV_B;
+    for (int R = 0; R < nbr; R++)
+      for (int C = 0; C <= R; C++) {
+        SymvBlock bk;
+        bk.foff = c->h_foff[i];
+        bk.voff = c->h_voff[i];
+        bk.r0 = R * SYMV_B;
+        bk.r1 = std::min(nt, (R + 1) * SYMV_B);
+        bk.c0 = C * SYMV_B;
+        bk.c1 = std::min(nt, (C + 1) * SYMV_B);
+        bk.out = blk0[i] + R * (R + 1) / 2 + C;
+        bk.pad_ = 0;
+        blocks.push_back(bk);
+      }
+  }
   for (int i = 0; i < c->N; i++) {
     const int nt = c->h_nt[i];
     for (int r = 0; r < nt; r++) {
-      rows.push_back(make_int2(i, r));
-      rowch.push_back((int)chunks.size());
-      for (int c0 = 0; c0 <= r; c0 += SYMV_CH) {
-        const int c1 = std::min(c0 + SYMV_CH, r + 1);
-        SymvChunk ch;
-        ch.tile_off = c->h_foff[i] + tile_index(0, nt, r, c0) * TS2;
-        ch.q_tile = c->h_foff[i] / TS2 + tile_index(0, nt, r, c0);
-        ch.xr_off = c->h_voff[i] + (int64_t)r * TS;
-        ch.xc_off = c->h_voff[i] + (int64_t)c0 * TS;
-        ch.ntiles = c1 - c0;
-        ch.diag = c1 == r + 1 ? 1 : 0;
-        chunks.push_back(ch);
-      }
+      SymvRow rw;
+      rw.voff = c->h_voff[i];
+      rw.r = r;
+      rw.nbr = (nt + SYMV_B - 1) / SYMV_B;
+      rw.blk0 = blk0[i];
+      rw.pad_ = 0;
+      rows.push_back(rw);
     }
   }
-  if (chunks.size() > (size_t)INT32_MAX) fail(TLS_E_ARG, "too many tiles for the symmetric-product work list");
-  c->inv_nchunks = (int64_t)chunks.size();
+  static_assert(sizeof(SymvBlock) == 48 && sizeof(SymvRow) == 32, "descriptor layout");
+  c->inv_nchunks = (int64_t)blocks.size();
   c->inv_nrows = (int64_t)rows.size();
-  static_assert(sizeof(SymvChunk) == 48, "descriptor layout");
-  c->inv_chunks.alloc(chunks.size() * 3);
-  TLS_HIP(hipMemcpyAsync(c->inv_chunks.p, chunks.data(), sizeof(SymvChunk) * chunks.size(), hipMemcpyHostToDevice, s));
-  c->inv_rows.upload(rows, s);
-  c->inv_rowch.upload(rowch, s);
-  const int64_t ntiles = c->fac_elems / TS2;
+  c->inv_chunks.alloc(blocks.size() * 3);
+  TLS_HIP(hipMemcpyAsync(c->inv_chunks.p, blocks.data(), sizeof(SymvBlock) * blocks.size(), hipMemcpyHostToDevice,
+                         s));
+  c->inv_rows.alloc(rows.size() * 2);
+  TLS_HIP(hipMemcpyAsync(c->inv_rows.p, rows.data(), sizeof(SymvRow) * rows.size(), hipMemcpyHostToDevice, s));
+  const int64_t npart = std::max<int64_t>(nblk * SYMV_B * TS, 1);
   if (c->fp32) {
-    c->inv_P32.alloc(std::max<int64_t>(c->inv_nchunks * TS, 1));
-    c->inv_Q32.alloc(std::max<int64_t>(ntiles * TS, 1));
+    c->inv_P32.alloc(npart);
+    c->inv_Q32.alloc(npart);
   } else {
-    c->inv_P64.alloc(std::max<int64_t>(c->inv_nchunks * TS, 1));
-    c->inv_Q64.alloc(std::max<int64_t>(ntiles * TS, 1));
+    c->inv_P64.alloc(npart);
+    c->inv_Q64.alloc(npart);
   }
   TLS_HIP(hipStreamSynchronize(s));
   c->inv_formed = true;
 }
 
 template <class T>
-void symv_solve(tls_ctx* c, const T* S, T* x, T* P, T* Q, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid,
+void symv_solve(tls_ctx* c, const T* S, T* x, T* RP, T* CP, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid,
                 hipEvent_t ev_end) {
   hipStream_t s = c->stream;
-  LocalLayout lay = c->layout();
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
   if (c->inv_nchunks > 0)
     hipLaunchKernelGGL(k_symv<T>, dim3((unsigned)c->inv_nchunks), dim3(256), 0, s,
-                       reinterpret_cast<const SymvChunk*>(c->inv_chunks.p), S, x, P, Q, done);
+                       reinterpret_cast<const SymvBlock*>(c->inv_chunks.p), S, x, RP, CP, done);
   TLS_LAUNCH_CHECK();
   if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
   if (c->inv_nrows > 0)
-    hipLaunchKernelGGL(k_symv_reduce<T>, dim3((unsigned)c->inv_nrows), dim3(64), 0, s, c->inv_rows.p,
-                       c->inv_rowch.p, lay, P, Q, x, done);
+    hipLaunchKernelGGL(k_symv_reduce<T>, dim3((unsigned)c->inv_nrows), dim3(64), 0, s,
+                       reinterpret_cast<const SymvRow*>(c->inv_rows.p), RP, CP, x, done);
   TLS_LAUNCH_CHECK();
   if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));
 }
