@@ -36,9 +36,9 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # WRITE_SIZE, KiB per dispatch), scaled by what the same counters read for a
 # 1 GiB read + 1 GiB write elementwise copy (--copy-probe). None whenever that
 # kernel has changed since the counters were taken.
-TRAFFIC = 16324858746
-# The same for k_symv<float> (explicit local inverses); None until measured.
-TRAFFIC_SYMV = None
+TRAFFIC = 16323093978
+# The same for k_symv<float> (explicit local inverses, the default for SPD).
+TRAFFIC_SYMV = 16347135206
 
 
 def log(*a):
