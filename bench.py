@@ -120,20 +120,22 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         ctx, x, st, it, rr = step(make_opt())
         tls.tls_destroy(ctx)
     torch.cuda.synchronize()
-    ctxs = []
+    # each step frees the previous step's preconditioner before building its
+    # own (as an application replacing it would); holding several of them at
+    # once would make later steps map fresh device memory
+    prev = None
     t0 = time.perf_counter()
     for k in range(steps):
+        if prev is not None:
+            tls.tls_destroy(prev)
         ctx, x, st, it, rr = step(make_opt())
-        ctxs.append((ctx, st, it, rr))
+        prev = ctx
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / steps
-    ctx, st, it, rr = ctxs[-1]
     info = tls.tls_info(ctx)
     fflops = factor_flops(ctx, prob.n_parts, prob.spd)
     log(f"precision {precision}: {ms_per_step:.1f} ms/step, {it} iterations, relres {rr:.2e}, status {st}")
-    for c, *_ in ctxs[:-1]:
-        tls.tls_destroy(c)
     # applies/s on the last context (plain launches, events on the stream)
     r = torch.randn(n, dtype=torch.float64, device=b.device, generator=torch.Generator(device=b.device).manual_seed(7))
     z = torch.empty_like(r)
