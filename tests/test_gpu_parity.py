@@ -663,17 +663,19 @@ def _ras_case(kind):
     return A, part, 2, 6, False
 
 
-@pytest.mark.parametrize("kind,precision,scale,tol", [("spd", 0, 0, 1e-10), ("spd", 0, 1, 1e-10),
-                                                     ("spd", 1, 0, 5e-3), ("general", 0, 0, 1e-10),
-                                                     ("general", 1, 0, 1e-4)])
-def test_ras_deflated_apply_with_imported_basis(kind, precision, scale, tol):
+@pytest.mark.parametrize("kind,precision,scale,inv,tol", [("spd", 0, 0, 0, 1e-10), ("spd", 0, 1, 0, 1e-10),
+                                                         ("spd", 1, 0, 0, 5e-3), ("spd", 0, 0, 1, 1e-10),
+                                                         ("spd", 1, 1, 1, 5e-3), ("general", 0, 0, 0, 1e-10),
+                                                         ("general", 1, 0, 0, 1e-4)])
+def test_ras_deflated_apply_with_imported_basis(kind, precision, scale, inv, tol):
     """z = Q r + M_RAS^{-1}(r - A Q r) with the library's own Z imported
-    into the oracle, over several seeded r."""
+    into the oracle, over several seeded r; for SPD also with the explicit
+    local inverses and with Jacobi scaling."""
     torch = torch_cuda()
     A, part, delta, nev, spd = _ras_case(kind)
-    say("ras+deflated apply", kind, precision, scale)
+    say("ras+deflated apply", kind, precision, scale, inv)
     pc = _pc(A, part, delta, nev, precision=precision, matrix_kind=0 if spd else 1, composition=1,
-             jacobi_scale=scale)
+             jacobi_scale=scale, local_inverse=inv)
     ex = pc.export(Z=True)
     h = oracle.setup(A, part, delta, nev, spd=spd, Z=ex["Z"])
     rng = np.random.default_rng(13)
