@@ -140,6 +140,10 @@ struct tls_ctx {
     return tls::LocalLayout{one_m, one_nI, one_nP, one_nt, one_foff, one_voff, one_toff};
   }
   ~tls_ctx() {
+    // work may still be queued when setup fails part-way; wait for it before
+    // the buffers are freed
+    if (stream2) (void)hipStreamSynchronize(stream2);
+    if (stream) (void)hipStreamSynchronize(stream);
     for (auto& e : prof_ev)
       if (e) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
