@@ -200,6 +200,13 @@ void build_coarse_operator(tls_ctx* c) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
     fail(TLS_E_SINGULAR, "zero pivot in the LU factorization of the coarse operator Z^T A Z");
   }
+  if (c->kind == 0 && c->opt.local_inverse) {
+    // explicit A_0^{-1}: the coarse solve becomes one streaming product
+    // instead of two chains of nt0 dependent block rows
+    form_inverse_f64(s, 1, one_nt, c->layout0(), a0_elems, c->A0.p, c->dinv0.p);
+    build_symv_work(c->inv0_work, s, 1, one_nt, std::vector<int64_t>{0}, std::vector<int64_t>{0}, false);
+    c->inv0_formed = true;
+  }
   build_plan(c->plan0_fwd, false, one_nt, toff, 1, s);
   build_plan(c->plan0_bwd, true, one_nt, toff, 1, s);
   c->counters0.alloc(4);
@@ -221,6 +228,10 @@ void coarse_restrict(tls_ctx* c, const double* r, const int* done) {
 void coarse_solve(tls_ctx* c, const int* done) {
   if (c->nC == 0) return;
   hipStream_t s = c->stream;
+  if (c->inv0_formed) {
+    symv_solve_f64(s, c->inv0_work, c->A0.p, c->y0.p, done);
+    return;
+  }
   solve_begin(s, c->counters0.p, done);
   const int grid = std::min(c->plan0_fwd.ntasks, 512);
   trsv_f64(s, c->kind == 0 ? 0 : 2, c->plan0_fwd, c->counters0.p + 0, c->counters0.p + 2, c->layout0(), c->A0.p,

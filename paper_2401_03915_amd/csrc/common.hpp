@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,7 +35,78 @@ struct TlsError {
 #define TLS_LAUNCH_CHECK() TLS_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------------------
-// Device buffer owned by a context (freed on destruction).
+// Large device blocks (>= 32 MiB) are kept for reuse instead of being freed.
+// Freeing and allocating again the tens of GB a setup uses slowed the
+// kernels of the following setups several-fold (freed device memory is
+// cleared in the background and mapped again on the next allocation). The
+// blocks are kept per device; when an allocation fails, all kept blocks are
+// freed and the allocation is tried once more. Releasing a large block
+// waits for the device, as freeing it would, so no queued work still uses
+// it when it is handed out again.
+// ---------------------------------------------------------------------------
+namespace devmem {
+constexpr size_t kMin = size_t(32) << 20;
+constexpr size_t kGrain = size_t(2) << 20;
+
+struct Pool {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void*>> free;  // device -> (size, block)
+};
+inline Pool& pool() {
+  static Pool* p = new Pool;  // never destroyed: buffers may be released during process teardown
+  return *p;
+}
+inline size_t rounded(size_t bytes) { return (bytes + kGrain - 1) / kGrain * kGrain; }
+
+inline void trim() {
+  Pool& pl = pool();
+  std::lock_guard<std::mutex> lock(pl.mu);
+  for (auto& d : pl.free)
+    for (auto& b : d.second) (void)hipFree(b.second);
+  pl.free.clear();
+}
+
+inline hipError_t alloc(void** p, size_t bytes) {
+  if (bytes < kMin) return hipMalloc(p, bytes);
+  const size_t want = rounded(bytes);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    Pool& pl = pool();
+    std::lock_guard<std::mutex> lock(pl.mu);
+    auto& fl = pl.free[dev];
+    auto it = fl.lower_bound(want);
+    if (it != fl.end() && it->first <= want + want / 4) {  // no large block for a much smaller request
+      *p = it->second;
+      fl.erase(it);
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipMalloc(p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    e = hipMalloc(p, want);
+  }
+  return e;
+}
+
+inline void release(void* p, size_t bytes) {
+  if (bytes < kMin) {
+    (void)hipFree(p);
+    return;
+  }
+  (void)hipDeviceSynchronize();
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  Pool& pl = pool();
+  std::lock_guard<std::mutex> lock(pl.mu);
+  pl.free[dev].insert({rounded(bytes), p});  // never more than the block holds
+}
+}  // namespace devmem
+
+// ---------------------------------------------------------------------------
+// Device buffer owned by a context (released on destruction).
 // ---------------------------------------------------------------------------
 template <class T>
 struct DBuf {
@@ -44,14 +117,14 @@ struct DBuf {
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) devmem::release(p, n * sizeof(T));
     p = nullptr;
     n = 0;
   }
   void alloc(size_t count) {
     release();
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    hipError_t e = devmem::alloc(reinterpret_cast<void**>(&p), count * sizeof(T));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
@@ -110,6 +183,15 @@ struct LocalLayout {
   const int64_t* foff; // element offset of the factor of i
   const int64_t* voff; // offset of i's padded vector (M_i entries)
   const int64_t* toff; // offset of i's first tile row in the flag arrays (= sum nt_j)
+};
+
+// Work list of the symmetric product with explicit inverses (block and row
+// descriptors in 16-byte words) and its row and column partial sums.
+struct SymvWork {
+  DBuf<int4> blocks, rows;
+  int64_t nblocks = 0, nrows = 0;
+  DBuf<float> RP32, CP32;
+  DBuf<double> RP64, CP64;
 };
 
 // Work list of one persistent triangular-solve launch: task (x = i, y = r)

@@ -44,16 +44,11 @@ struct tls_ctx {
   // inverses of the diagonal tiles (one per tile row, at (toff_i + r) * 64^2)
   tls::DBuf<double> dinv64;
   tls::DBuf<float> dinv32;
-  // explicit local inverses (option local_inverse): the symmetric-product
-  // work list (block and row descriptors, 16-byte words) and its row and
-  // column partial sums
-  bool inv_formed = false;
+  // explicit inverses (option local_inverse): the symmetric-product work
+  // lists of the local matrices and of A_0
+  bool inv_formed = false, inv0_formed = false;
   double t_inverse = 0.0;
-  int64_t inv_nchunks = 0, inv_nrows = 0;
-  tls::DBuf<int4> inv_chunks;
-  tls::DBuf<int4> inv_rows;
-  tls::DBuf<float> inv_P32, inv_Q32;
-  tls::DBuf<double> inv_P64, inv_Q64;
+  tls::SymvWork inv_work, inv0_work;
 
   // factorization schedule: subdomains sorted by nt (desc); per step prefix tables
   std::vector<int> h_order;

@@ -1972,18 +1972,20 @@ void local_bsolve_upper(tls_ctx* c, double* X, const std::vector<int>& nq, const
   bsolve_upper_impl<double>(c, c->dinv64.p, X, nq, xoff);
 }
 
+// S = A^{-1} over the lower tiles of N Cholesky factors (tile counts nt,
+// layout lay, elems elements in all), from their factors and diagonal-tile
+// inverses; a scratch buffer of the factors' size holds W = L^{-1}.
 template <class T>
-void form_inverse_impl(tls_ctx* c, T* fac, const T* dinv) {
+void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, int64_t elems,
+                        T* fac, const T* dinv) {
   constexpr int PW = 8;
-  hipStream_t s = c->stream;
-  const int N = c->N;
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->h_nt[a] > c->h_nt[b]; });
-  const int maxnt = N ? c->h_nt[order[0]] : 0;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
+  const int maxnt = N ? nt[order[0]] : 0;
   auto active = [&](int j) {
     int a = 0;
-    while (a < N && c->h_nt[order[a]] > j) a++;
+    while (a < N && nt[order[a]] > j) a++;
     return a;
   };
   struct Launch {
@@ -2006,7 +2008,7 @@ void form_inverse_impl(tls_ctx* c, T* fac, const T* dinv) {
       int64_t tot = 0;
       for (int a = 0; a < act; a++) {
         pref.push_back(tot);
-        tot += (int64_t)(c->h_nt[order[a]] - j1) * j1;
+        tot += (int64_t)(nt[order[a]] - j1) * j1;
       }
       pref.push_back(tot);
       launches.push_back(Launch{1, 0, j0, j1, act, off, tot});
@@ -2018,7 +2020,7 @@ void form_inverse_impl(tls_ctx* c, T* fac, const T* dinv) {
     int64_t tot = 0;
     for (int a = 0; a < act; a++) {
       pref.push_back(tot);
-      const int64_t n = c->h_nt[order[a]];
+      const int64_t n = nt[order[a]];
       tot += n * (n + 1) / 2;
     }
     pref.push_back(tot);
@@ -2029,9 +2031,8 @@ void form_inverse_impl(tls_ctx* c, T* fac, const T* dinv) {
   d_order.upload(order, s);
   d_pref.upload(pref, s);
   DBuf<T> W;
-  W.alloc(std::max<int64_t>(c->fac_elems, 1));
-  TLS_HIP(hipMemsetAsync(W.p, 0, sizeof(T) * std::max<int64_t>(c->fac_elems, 1), s));
-  LocalLayout lay = c->layout();
+  W.alloc(std::max<int64_t>(elems, 1));
+  TLS_HIP(hipMemsetAsync(W.p, 0, sizeof(T) * std::max<int64_t>(elems, 1), s));
   for (const Launch& L : launches) {
     if (L.total <= 0) continue;
     switch (L.kind) {
@@ -2053,22 +2054,18 @@ void form_inverse_impl(tls_ctx* c, T* fac, const T* dinv) {
   TLS_HIP(hipStreamSynchronize(s));
 }
 
-void form_local_inverse(tls_ctx* c) {
-  if (c->kind != 0) fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
-  hipStream_t s = c->stream;
-  if (c->fp32)
-    form_inverse_impl<float>(c, c->fac32.p, c->dinv32.p);
-  else
-    form_inverse_impl<double>(c, c->fac64.p, c->dinv64.p);
-  // work list of the symmetric product: blocks of SYMV_B x SYMV_B tiles, the
-  // largest subdomains first; one reduction row per tile row
-  std::vector<int> order(c->N);
+// Work list of the symmetric product over N matrices (tile counts nt,
+// factor offsets foff, vector offsets voff): blocks of SYMV_B x SYMV_B
+// tiles, the largest matrices first, one reduction row per tile row.
+void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& nt,
+                     const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32) {
+  std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->h_nt[a] > c->h_nt[b]; });
-  std::vector<int> blk0(c->N, 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
+  std::vector<int> blk0(N, 0);
   int64_t nblk = 0;
-  for (int i = 0; i < c->N; i++) {
-    const int64_t nbr = (c->h_nt[i] + SYMV_B - 1) / SYMV_B;
+  for (int i = 0; i < N; i++) {
+    const int64_t nbr = (nt[i] + SYMV_B - 1) / SYMV_B;
     blk0[i] = (int)nblk;
     nblk += nbr * (nbr + 1) / 2;
   }
@@ -2077,79 +2074,94 @@ void form_local_inverse(tls_ctx* c) {
   std::vector<SymvRow> rows;
   blocks.reserve(nblk);
   for (int i : order) {
-    const int nt = c->h_nt[i];
-    const int nbr = (nt + SYMV_B - 1) / SYMV_B;
+    const int nbr = (nt[i] + SYMV_B - 1) / SYMV_B;
     for (int R = 0; R < nbr; R++)
       for (int C = 0; C <= R; C++) {
         SymvBlock bk;
-        bk.foff = c->h_foff[i];
-        bk.voff = c->h_voff[i];
+        bk.foff = foff[i];
+        bk.voff = voff[i];
         bk.r0 = R * SYMV_B;
-        bk.r1 = std::min(nt, (R + 1) * SYMV_B);
+        bk.r1 = std::min(nt[i], (R + 1) * SYMV_B);
         bk.c0 = C * SYMV_B;
-        bk.c1 = std::min(nt, (C + 1) * SYMV_B);
+        bk.c1 = std::min(nt[i], (C + 1) * SYMV_B);
         bk.out = blk0[i] + R * (R + 1) / 2 + C;
         bk.pad_ = 0;
         blocks.push_back(bk);
       }
   }
-  for (int i = 0; i < c->N; i++) {
-    const int nt = c->h_nt[i];
-    for (int r = 0; r < nt; r++) {
+  for (int i = 0; i < N; i++)
+    for (int r = 0; r < nt[i]; r++) {
       SymvRow rw;
-      rw.voff = c->h_voff[i];
+      rw.voff = voff[i];
       rw.r = r;
-      rw.nbr = (nt + SYMV_B - 1) / SYMV_B;
+      rw.nbr = (nt[i] + SYMV_B - 1) / SYMV_B;
       rw.blk0 = blk0[i];
       rw.pad_ = 0;
       rows.push_back(rw);
     }
-  }
   static_assert(sizeof(SymvBlock) == 48 && sizeof(SymvRow) == 32, "descriptor layout");
-  c->inv_nchunks = (int64_t)blocks.size();
-  c->inv_nrows = (int64_t)rows.size();
-  c->inv_chunks.alloc(blocks.size() * 3);
-  TLS_HIP(hipMemcpyAsync(c->inv_chunks.p, blocks.data(), sizeof(SymvBlock) * blocks.size(), hipMemcpyHostToDevice,
-                         s));
-  c->inv_rows.alloc(rows.size() * 2);
-  TLS_HIP(hipMemcpyAsync(c->inv_rows.p, rows.data(), sizeof(SymvRow) * rows.size(), hipMemcpyHostToDevice, s));
+  w.nblocks = (int64_t)blocks.size();
+  w.nrows = (int64_t)rows.size();
+  w.blocks.alloc(blocks.size() * 3);
+  TLS_HIP(hipMemcpyAsync(w.blocks.p, blocks.data(), sizeof(SymvBlock) * blocks.size(), hipMemcpyHostToDevice, s));
+  w.rows.alloc(rows.size() * 2);
+  TLS_HIP(hipMemcpyAsync(w.rows.p, rows.data(), sizeof(SymvRow) * rows.size(), hipMemcpyHostToDevice, s));
   const int64_t npart = std::max<int64_t>(nblk * SYMV_B * TS, 1);
-  if (c->fp32) {
-    c->inv_P32.alloc(npart);
-    c->inv_Q32.alloc(npart);
+  if (fp32) {
+    w.RP32.alloc(npart);
+    w.CP32.alloc(npart);
   } else {
-    c->inv_P64.alloc(npart);
-    c->inv_Q64.alloc(npart);
+    w.RP64.alloc(npart);
+    w.CP64.alloc(npart);
   }
   TLS_HIP(hipStreamSynchronize(s));
+}
+
+void form_local_inverse(tls_ctx* c) {
+  if (c->kind != 0) fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
+  hipStream_t s = c->stream;
+  if (c->fp32)
+    form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac_elems, c->fac32.p, c->dinv32.p);
+  else
+    form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac_elems, c->fac64.p, c->dinv64.p);
+  build_symv_work(c->inv_work, s, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32);
   c->inv_formed = true;
 }
 
+void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, int64_t elems,
+                      double* fac, const double* dinv) {
+  form_inverse_tiles<double>(s, N, nt, lay, elems, fac, dinv);
+}
+
 template <class T>
-void symv_solve(tls_ctx* c, const T* S, T* x, T* RP, T* CP, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid,
-                hipEvent_t ev_end) {
-  hipStream_t s = c->stream;
+void symv_solve_t(hipStream_t s, const SymvWork& w, const T* S, T* x, T* RP, T* CP, const int* done,
+                  hipEvent_t ev_begin, hipEvent_t ev_mid, hipEvent_t ev_end) {
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
-  if (c->inv_nchunks > 0)
-    hipLaunchKernelGGL(k_symv<T>, dim3((unsigned)c->inv_nchunks), dim3(256), 0, s,
-                       reinterpret_cast<const SymvBlock*>(c->inv_chunks.p), S, x, RP, CP, done);
+  if (w.nblocks > 0)
+    hipLaunchKernelGGL(k_symv<T>, dim3((unsigned)w.nblocks), dim3(256), 0, s,
+                       reinterpret_cast<const SymvBlock*>(w.blocks.p), S, x, RP, CP, done);
   TLS_LAUNCH_CHECK();
   if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
-  if (c->inv_nrows > 0)
-    hipLaunchKernelGGL(k_symv_reduce<T>, dim3((unsigned)c->inv_nrows), dim3(64), 0, s,
-                       reinterpret_cast<const SymvRow*>(c->inv_rows.p), RP, CP, x, done);
+  if (w.nrows > 0)
+    hipLaunchKernelGGL(k_symv_reduce<T>, dim3((unsigned)w.nrows), dim3(64), 0, s,
+                       reinterpret_cast<const SymvRow*>(w.rows.p), RP, CP, x, done);
   TLS_LAUNCH_CHECK();
   if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));
+}
+
+void symv_solve_f64(hipStream_t s, SymvWork& w, const double* S, double* x, const int* done) {
+  symv_solve_t<double>(s, w, S, x, w.RP64.p, w.CP64.p, done, nullptr, nullptr, nullptr);
 }
 
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev_mid, hipEvent_t ev_end) {
   hipStream_t s = c->stream;
   LocalLayout lay = c->layout();
   if (c->inv_formed) {
+    SymvWork& w = c->inv_work;
     if (c->fp32)
-      symv_solve<float>(c, c->fac32.p, c->xloc32.p, c->inv_P32.p, c->inv_Q32.p, done, ev_begin, ev_mid, ev_end);
+      symv_solve_t<float>(s, w, c->fac32.p, c->xloc32.p, w.RP32.p, w.CP32.p, done, ev_begin, ev_mid, ev_end);
     else
-      symv_solve<double>(c, c->fac64.p, c->xloc64.p, c->inv_P64.p, c->inv_Q64.p, done, ev_begin, ev_mid, ev_end);
+      symv_solve_t<double>(s, w, c->fac64.p, c->xloc64.p, w.RP64.p, w.CP64.p, done, ev_begin, ev_mid, ev_end);
     return;
   }
   solve_begin(s, c->counters.p, done);

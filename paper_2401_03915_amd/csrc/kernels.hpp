@@ -23,6 +23,13 @@ void build_solve_tasks(tls_ctx* c);
 // (lower tiles, full symmetric diagonal tiles) and build the symmetric-product
 // work list; local_solve uses it from then on
 void form_local_inverse(tls_ctx* c);
+// the same for N FP64 Cholesky factors in any tile layout (A_0), and the
+// work list and product of the symmetric product over them
+void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, int64_t elems,
+                      double* fac, const double* dinv);
+void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& nt,
+                     const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32);
+void symv_solve_f64(hipStream_t s, SymvWork& w, const double* S, double* x, const int* done);
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_mid = nullptr,
                  hipEvent_t ev_end = nullptr);
 // backward substitution L^T x = x only, on a padded vector of the context's precision
