@@ -21,25 +21,33 @@ __device__ inline int find_desc(const int64_t* pref, int count, int64_t bid) {
 }
 
 template <class T>
-struct GemmPad;
+struct GemmPadK;
 template <>
-struct GemmPad<float> {
-  static constexpr int v = 16;
+struct GemmPadK<float> {
+  static constexpr int v = 4;
 };
 template <>
-struct GemmPad<double> {
-  static constexpr int v = 0;
+struct GemmPadK<double> {
+  static constexpr int v = 2;
 };
 
-// One 64x64 tile of C per 256-thread workgroup; K in chunks of 16.
+// One 64x64 tile of C per 256-thread workgroup; K in chunks of KC = 32, the
+// next chunk loaded into registers while the current one is used. An
+// operand whose consecutive elements in memory run along m (or n) is staged
+// m-fastest ([k][m], pitch PM); one whose elements run along k is staged
+// k-fastest ([m][k], pitch PK). Either way the LDS stores and the MFMA reads
+// fall on distinct banks (for FP64 per half wave). C may be B's storage when
+// M <= 64: each workgroup reads all of K before it writes its tile.
 template <class T, bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ desc, const int64_t* __restrict__ pref,
                                               int nd, const T* __restrict__ A, const T* __restrict__ B, T* C,
                                               T alpha, T beta) {
-  constexpr int KC = 16;
-  constexpr int LD = 64 + GemmPad<T>::v;
-  __shared__ T As[KC * LD];
-  __shared__ T Bs[KC * LD];
+  constexpr int KC = 32;
+  constexpr int PM = 64 + 16;
+  constexpr int PK = KC + GemmPadK<T>::v;
+  constexpr int PER = 64 * KC / 256;  // elements of each operand per thread and chunk
+  __shared__ T As[TA ? 64 * PK : KC * PM];
+  __shared__ T Bs[TB ? KC * PM : 64 * PK];
   const int64_t bid = blockIdx.x;
   const int di = find_desc(pref, nd, bid);
   const GemmDesc g = desc[di];
@@ -55,50 +63,70 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ desc,
   for (int x = 0; x < 2; x++)
 #pragma unroll
     for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
-  for (int k0 = 0; k0 < g.K; k0 += KC) {
+  T ra[PER], rb[PER];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      int e = tid + 256 * q;
+    for (int q = 0; q < PER; q++) {
+      const int e = tid + 256 * q;
       int m, k;
       if (!TA) {
         m = e & 63;
         k = e >> 6;
       } else {
-        k = e & 15;
-        m = e >> 4;
+        k = e & (KC - 1);
+        m = e / KC;
       }
-      int gm = bm + m, gk = k0 + k;
+      const int gm = bm + m, gk = k0 + k;
       T v = T(0);
       if (gm < g.M && gk < g.K)
         v = TA ? A[g.a_off + gk + (int64_t)gm * g.lda] : A[g.a_off + gm + (int64_t)gk * g.lda];
-      As[k * LD + m] = v;
+      ra[q] = v;
       int n2, k2;
       if (!TB) {
-        k2 = e & 15;
-        n2 = e >> 4;
+        k2 = e & (KC - 1);
+        n2 = e / KC;
       } else {
         n2 = e & 63;
         k2 = e >> 6;
       }
-      int gn = bn + n2, gk2 = k0 + k2;
+      const int gn = bn + n2, gk2 = k0 + k2;
       T w = T(0);
       if (gn < g.N && gk2 < g.K)
         w = TB ? B[g.b_off + gn + (int64_t)gk2 * g.ldb] : B[g.b_off + gk2 + (int64_t)gn * g.ldb];
-      Bs[k2 * LD + n2] = w;
+      rb[q] = w;
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += KC) {
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      T a0 = As[(kk + lk) * LD + wr + li];
-      T a1 = As[(kk + lk) * LD + wr + 16 + li];
-      T b0 = Bs[(kk + lk) * LD + wc + li];
-      T b1 = Bs[(kk + lk) * LD + wc + 16 + li];
-      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    for (int q = 0; q < PER; q++) {
+      const int e = tid + 256 * q;
+      if (!TA)
+        As[(e >> 6) * PM + (e & 63)] = ra[q];
+      else
+        As[(e / KC) * PK + (e & (KC - 1))] = ra[q];
+      if (!TB)
+        Bs[(e / KC) * PK + (e & (KC - 1))] = rb[q];
+      else
+        Bs[(e >> 6) * PM + (e & 63)] = rb[q];
     }
     __syncthreads();
+    if (k0 + KC < g.K) load(k0 + KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; x++)
+        a[x] = TA ? As[(wr + 16 * x + li) * PK + kk + lk] : As[(kk + lk) * PM + wr + 16 * x + li];
+#pragma unroll
+      for (int y = 0; y < 2; y++)
+        b[y] = TB ? Bs[(kk + lk) * PM + wc + 16 * y + li] : Bs[(wc + 16 * y + li) * PK + kk + lk];
+      acc[0][0] = Mfma<T>::mac(a[0], b[0], acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a[0], b[1], acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a[1], b[0], acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a[1], b[1], acc[1][1]);
+    }
   }
 #pragma unroll
   for (int x = 0; x < 2; x++)
