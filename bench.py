@@ -9,7 +9,11 @@ grid (n = 1,048,576), coefficient log-uniform in [1, 1e6] plus 20 channels at
 uniform in [0.3, 0.7]), overlap 2, 16 coarse vectors per subdomain, b ~ N(0,1),
 all seeded and synthetic. A step is one pass of the whole hot path: setup
 (overlap, local matrices, batched factorization, coarse basis, A_0 and its
-factor) plus the PCG solve. Inputs are resident in HBM before timing starts.
+factor, and for SPD matrices the explicit inverses of the local matrices and
+of A_0) plus the PCG solve. Inputs are resident in HBM before timing starts.
+Other configurations (--config 1..5), the RAS + deflated composition
+(--composition 1, FGMRES) and local solves by substitution
+(--local-inverse 0) are options.
 
 Prints ONE JSON line. Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """

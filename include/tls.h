@@ -142,7 +142,8 @@ typedef struct {
    * same storage), so that a local solve is one symmetric product that reads
    * the stored triangle once instead of two substitutions that read it
    * twice. Costs about 2 #Omega_i^3 / 3 more flops per subdomain at setup.
-   * 0 (default): forward and backward substitution with the factor. */
+   * A_0 is inverted the same way, so the coarse solve is one product too.
+   * 0 (default): forward and backward substitution with the factors. */
   int32_t local_inverse;
   void* stream;         /* hipStream_t */
 } tls_options;
@@ -182,7 +183,8 @@ typedef struct {
   int32_t tuned;              /* 0 default, 1 timed at setup, 2 read from the cache */
   const double* res_history;  /* host array: ||r_k|| / ||b|| per iteration   */
   int32_t local_inverse;      /* 1 if the local solves use explicit inverses  */
-  double t_inverse_ms;        /* setup ms spent forming them (inside t_setup[7]) */
+  double t_inverse_ms;        /* setup ms spent forming them (inside t_setup[7]; the
+                                 inverse of A_0 is inside t_setup[5]) */
 } tls_info_t;
 
 /* Fill *opt with the defaults listed above. */
