@@ -22,13 +22,16 @@ __device__ inline int find_desc(const int64_t* pref, int count, int64_t bid) {
 
 template <class T>
 struct GemmPadK;
+// k-fastest pitch KC + pad: LDS has 32 four-byte banks, 32-bit reads are
+// served per half wave and 64-bit reads per 16 lanes; 34 (= 2 mod 32) and
+// the odd 33 keep those on distinct banks
 template <>
 struct GemmPadK<float> {
-  static constexpr int v = 4;
+  static constexpr int v = 2;
 };
 template <>
 struct GemmPadK<double> {
-  static constexpr int v = 2;
+  static constexpr int v = 1;
 };
 
 // One 64x64 tile of C per 256-thread workgroup; K in chunks of KC = 32, the
@@ -36,7 +39,7 @@ struct GemmPadK<double> {
 // operand whose consecutive elements in memory run along m (or n) is staged
 // m-fastest ([k][m], pitch PM); one whose elements run along k is staged
 // k-fastest ([m][k], pitch PK). Either way the LDS stores and the MFMA reads
-// fall on distinct banks (for FP64 per half wave). C may be B's storage when
+// fall on distinct banks. C may be B's storage when
 // M <= 64: each workgroup reads all of K before it writes its tile.
 template <class T, bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ desc, const int64_t* __restrict__ pref,

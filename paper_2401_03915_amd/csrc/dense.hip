@@ -185,6 +185,24 @@ struct LdsLd<double> {
   static constexpr int v = TS;
 };
 
+// Pitch of a tile staged "k fastest" in LDS (operand (i, kk) at [i * P + kk]),
+// read by the MFMA loops with lanes li (16 rows or columns) and lk (4 k).
+// LDS has 32 four-byte banks; 32-bit reads are served per half wave (lk in
+// {0, 1} or {2, 3}), 64-bit reads per 16 lanes. P = 66 (= 2 mod 32) puts a
+// half wave's FP32 reads on 32 distinct banks, an odd P = 65 gives 16
+// distinct bank pairs for FP64. (A pitch of 68 put lanes li and li + 8 on one
+// bank: 1-2 conflict cycles per FP32 read, 6-12 per FP64 read, measured.)
+template <class T>
+struct KfPitch;
+template <>
+struct KfPitch<float> {
+  static constexpr int v = TS + 2;
+};
+template <>
+struct KfPitch<double> {
+  static constexpr int v = TS + 1;
+};
+
 // X = A_rk L_kk^{-T} for the tiles (r, k), r > k (MFMA with the inverse
 // formed by k_potrf): X(a, b) = sum_l A(a, l) Linv(b, l), written over A_rk.
 template <class T>
@@ -420,7 +438,7 @@ __global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restric
                                                  const int* __restrict__ order, LocalLayout lay, T* fac,
                                                  const T* __restrict__ dinv) {
   constexpr int LD = LdsLd<T>::v;
-  constexpr int LDB = TS + 4;   // conflict-free store and MFMA read of Bs
+  constexpr int LDB = KfPitch<T>::v;  // conflict-free store and MFMA read of Bs
   __shared__ T As[TS * LD];     // As[kk * LD + row] = left operand (row, kk)
   __shared__ T Bs[TS * LDB];    // Bs[col * LDB + kk] = right operand (kk, col)
   int64_t bid = blockIdx.x;
@@ -490,9 +508,9 @@ template <class T>
 __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int kl, const int64_t* __restrict__ pref,
                                                    int nact, const int* __restrict__ order, LocalLayout lay, T* fac) {
   constexpr int LD = LdsLd<T>::v;
-  // U_kc is kept as stored (k fastest): pitch TS + 4 puts the 64 lanes of
-  // both the store and the MFMA read on distinct banks
-  constexpr int LDB = TS + 4;
+  // U_kc is kept as stored (k fastest), with the conflict-free pitch for
+  // both the store and the MFMA read
+  constexpr int LDB = KfPitch<T>::v;
   __shared__ T As[TS * LD];
   __shared__ T Bs[TS * LDB];
   const int64_t bid = blockIdx.x;
@@ -1051,7 +1069,7 @@ __global__ void __launch_bounds__(256) k_bsolve_diag(int s, const int64_t* __res
                                                      const int* __restrict__ nb, const int64_t* __restrict__ xoff,
                                                      const T* __restrict__ dinv, T* X) {
   constexpr int LD = LdsLd<T>::v;
-  constexpr int LDB = TS + 4;
+  constexpr int LDB = KfPitch<T>::v;
   __shared__ T As[TS * LD];   // As[kk * LD + row] = U_kk^{-1}(row, kk)
   __shared__ T Bs[TS * LDB];  // Bs[col * LDB + kk] = X_k(kk, col)
   const int64_t bid = blockIdx.x;
@@ -1140,7 +1158,7 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
                                                        const int64_t* __restrict__ xoff, const T* __restrict__ fac,
                                                        T* X) {
   constexpr int LD = LdsLd<T>::v;
-  constexpr int LDB = TS + 4;
+  constexpr int LDB = KfPitch<T>::v;
   __shared__ T As[TS * LD];   // As[kk * LD + row] = U_jk(row, kk)
   __shared__ T Bs[TS * LDB];  // Bs[col * LDB + kk] = X_k(kk, col)
   const int64_t bid = blockIdx.x;
@@ -1242,7 +1260,7 @@ __global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* 
                                                   const int* __restrict__ order, LocalLayout lay,
                                                   const T* __restrict__ fac, const T* __restrict__ dinv, T* W) {
   constexpr int LD = LdsLd<T>::v;  // A operand (row, kk) at [kk * LD + row]
-  constexpr int LDB = TS + 4;      // B operand (kk, col) at [col * LDB + kk]
+  constexpr int LDB = KfPitch<T>::v;  // B operand (kk, col) at [col * LDB + kk]
   __shared__ T As[TS * LD];
   __shared__ T Bs[TS * LDB];
   const int64_t bid = blockIdx.x;
@@ -1341,7 +1359,7 @@ __global__ void __launch_bounds__(256) k_tinv_update(int j0, int j1, const int64
                                                      const int* __restrict__ order, LocalLayout lay,
                                                      const T* __restrict__ fac, T* W) {
   constexpr int LD = LdsLd<T>::v;
-  constexpr int LDB = TS + 4;
+  constexpr int LDB = KfPitch<T>::v;
   __shared__ T As[TS * LD];
   __shared__ T Bs[TS * LDB];
   const int64_t bid = blockIdx.x;
@@ -1423,8 +1441,8 @@ template <class T>
 __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ pref, int nact,
                                                     const int* __restrict__ order, LocalLayout lay,
                                                     const T* __restrict__ W, T* S) {
-  constexpr int LDA = TS + 4;  // A operand (row, kk) at [row * LDA + kk]
-  constexpr int LDB = TS + 4;  // B operand (kk, col) at [col * LDB + kk]
+  constexpr int LDA = KfPitch<T>::v;  // A operand (row, kk) at [row * LDA + kk]
+  constexpr int LDB = KfPitch<T>::v;  // B operand (kk, col) at [col * LDB + kk]
   __shared__ T As[TS * LDA];
   __shared__ T Bs[TS * LDB];
   const int64_t bid = blockIdx.x;
