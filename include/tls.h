@@ -272,8 +272,15 @@ tls_status tls_gnn_forward(tls_ctx* c, const float* weights, int32_t c_out, floa
  * loss: host scalar. TLS_E_STATE without targets. */
 tls_status tls_gnn_loss_grad(tls_ctx* c, const float* weights, int32_t c_out, float* grad, double* loss);
 
-/* Free everything the context owns. NULL is ignored. */
+/* Free everything the context owns. NULL is ignored. Device blocks of
+ * 32 MiB and more are not handed back to the driver but kept for the next
+ * contexts of the process (freeing and mapping tens of GB per setup slowed
+ * the following setups several-fold); tls_trim hands them back. */
 void tls_destroy(tls_ctx* c);
+
+/* Free the device blocks kept for reuse (all devices). Safe at any time:
+ * blocks in use by live contexts are not affected. */
+void tls_trim(void);
 
 #ifdef __cplusplus
 }

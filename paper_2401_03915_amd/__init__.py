@@ -17,11 +17,11 @@ import numpy as np
 from . import _lib
 from ._lib import (TlsError, gnn_n_weights, tls_apply, tls_default_options, tls_destroy,  # noqa: F401
                    tls_export, tls_export_zblocks, tls_gnn_forward, tls_gnn_loss_grad, tls_info, tls_local_solve,
-                   tls_setup, tls_solve, tls_spmv)
+                   tls_setup, tls_solve, tls_spmv, tls_trim)
 
 __all__ = ["Preconditioner", "TlsError", "tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve",
            "tls_info", "tls_export", "tls_export_zblocks", "tls_local_solve", "tls_gnn_forward",
-           "tls_gnn_loss_grad", "tls_destroy",
+           "tls_gnn_loss_grad", "tls_destroy", "tls_trim",
            "gnn_n_weights"]
 
 

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "TLS_OK", 1: "TLS_E_ARG", 2: "TLS_E_NOT_SPD", 3: "TLS_E_SINGU
 # Names declared in include/tls.h (checked by the tests against the header).
 EXPORTED = ["tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve", "tls_info", "tls_export",
             "tls_local_solve", "tls_export_zblocks", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_last_error",
-            "tls_destroy"]
+            "tls_destroy", "tls_trim"]
 
 GNN_LAYERS = 4
 GNN_FEATURES = 12
@@ -141,6 +141,8 @@ def lib() -> C.CDLL:
         L.tls_last_error.restype = C.c_char_p
         L.tls_destroy.argtypes = [vp]
         L.tls_destroy.restype = None
+        L.tls_trim.argtypes = []
+        L.tls_trim.restype = None
         _lib = L
     return _lib
 
@@ -235,3 +237,8 @@ def tls_gnn_loss_grad(ctx, weights, c_out, grad):
 def tls_destroy(ctx):
     if ctx:
         lib().tls_destroy(ctx)
+
+
+def tls_trim():
+    """Hand the device blocks the library keeps for reuse back to the driver."""
+    lib().tls_trim()

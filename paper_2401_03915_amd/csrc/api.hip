@@ -392,4 +392,6 @@ void tls_destroy(tls_ctx* c) {
   delete c;
 }
 
+void tls_trim(void) { tls::devmem::trim(); }
+
 }  // extern "C"

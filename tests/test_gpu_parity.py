@@ -753,6 +753,27 @@ def test_ras_deflated_fgmres_matches_oracle(kind):
     assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
 
 
+def test_reused_device_blocks_and_trim():
+    """Contexts built on device blocks kept from earlier contexts (not zeroed)
+    and after tls_trim solve bit for bit alike."""
+    import paper_2401_03915_amd as tls
+    torch = torch_cuda()
+    A, part = _hc_problem(128, 2, seed=9)
+    b = np.random.default_rng(2).standard_normal(A.shape[0])
+    xs = []
+    for k in range(3):
+        if k == 2:
+            tls.tls_trim()
+        pc = _pc(A, part, 2, 8, local_inverse=1)
+        x, it, rr, st = pc.solve(to_dev(b), 1e-8)
+        torch.cuda.synchronize()
+        assert st == 0 and rr <= 1e-8
+        xs.append((x, it))
+        pc.close()
+    assert xs[0][1] == xs[1][1] == xs[2][1]
+    assert torch.equal(xs[0][0], xs[1][0]) and torch.equal(xs[0][0], xs[2][0])
+
+
 def test_autotune_cache_reuse(tmp_path):
     import paper_2401_03915_amd as tls
     A, part = _hc_problem(96, 3, seed=8)
