@@ -203,7 +203,7 @@ void build_coarse_operator(tls_ctx* c) {
   if (c->kind == 0 && c->opt.local_inverse) {
     // explicit A_0^{-1}: the coarse solve becomes one streaming product
     // instead of two chains of nt0 dependent block rows
-    form_inverse_f64(s, 1, one_nt, c->layout0(), a0_elems, c->A0.p, c->dinv0.p);
+    form_inverse_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->dinv0.p);
     build_symv_work(c->inv0_work, s, 1, one_nt, std::vector<int64_t>{0}, std::vector<int64_t>{0}, false);
     c->inv0_formed = true;
   }

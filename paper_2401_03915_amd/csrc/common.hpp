@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -89,6 +90,30 @@ inline hipError_t alloc(void** p, size_t bytes) {
     e = hipMalloc(p, want);
   }
   return e;
+}
+
+// Bytes that allocations on the current device can still obtain: what the
+// driver reports free plus the blocks kept here for reuse, capped by the
+// environment variable TLS_MEMORY_LIMIT (bytes) when it is set. Set-up steps
+// that can work on groups of subdomains size their groups by it.
+inline size_t available() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    Pool& pl = pool();
+    std::lock_guard<std::mutex> lock(pl.mu);
+    for (const auto& b : pl.free[dev]) fr += b.first;
+  }
+  if (const char* lim = std::getenv("TLS_MEMORY_LIMIT")) {
+    const unsigned long long v = std::strtoull(lim, nullptr, 10);
+    if (v > 0 && v < fr) fr = (size_t)v;
+  }
+  return fr;
 }
 
 inline void release(void* p, size_t bytes) {

@@ -1258,7 +1258,8 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
 template <class T>
 __global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* __restrict__ pref, int nact,
                                                   const int* __restrict__ order, LocalLayout lay,
-                                                  const T* __restrict__ fac, const T* __restrict__ dinv, T* W) {
+                                                  const int64_t* __restrict__ woff, const T* __restrict__ fac,
+                                                  const T* __restrict__ dinv, T* W) {
   constexpr int LD = LdsLd<T>::v;  // A operand (row, kk) at [kk * LD + row]
   constexpr int LDB = KfPitch<T>::v;  // B operand (kk, col) at [col * LDB + kk]
   __shared__ T As[TS * LD];
@@ -1269,7 +1270,7 @@ __global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* 
   const int k = (int)(bid - pref[slot]);
   const int nt = lay.nt[i];
   const T* Lb = fac + lay.foff[i];
-  T* Wb = W + lay.foff[i];
+  T* Wb = W + woff[i];
   T* Wjk = Wb + tile_index(0, nt, j, k) * TS2;
   const T* Dj = dinv + (lay.toff[i] + j) * TS2;
   const int tid = threadIdx.x;
@@ -1357,7 +1358,8 @@ __global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* 
 template <class T>
 __global__ void __launch_bounds__(256) k_tinv_update(int j0, int j1, const int64_t* __restrict__ pref, int nact,
                                                      const int* __restrict__ order, LocalLayout lay,
-                                                     const T* __restrict__ fac, T* W) {
+                                                     const int64_t* __restrict__ woff, const T* __restrict__ fac,
+                                                     T* W) {
   constexpr int LD = LdsLd<T>::v;
   constexpr int LDB = KfPitch<T>::v;
   __shared__ T As[TS * LD];
@@ -1370,7 +1372,7 @@ __global__ void __launch_bounds__(256) k_tinv_update(int j0, int j1, const int64
   const int k = (int)(t % j1);
   const int nt = lay.nt[i];
   const T* Lb = fac + lay.foff[i];
-  T* Wb = W + lay.foff[i];
+  T* Wb = W + woff[i];
   const int l0 = k > j0 ? k : j0;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
@@ -1440,7 +1442,8 @@ __global__ void __launch_bounds__(256) k_tinv_update(int j0, int j1, const int64
 template <class T>
 __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ pref, int nact,
                                                     const int* __restrict__ order, LocalLayout lay,
-                                                    const T* __restrict__ W, T* S) {
+                                                    const int64_t* __restrict__ woff, const T* __restrict__ W,
+                                                    T* S) {
   constexpr int LDA = KfPitch<T>::v;  // A operand (row, kk) at [row * LDA + kk]
   constexpr int LDB = KfPitch<T>::v;  // B operand (kk, col) at [col * LDB + kk]
   __shared__ T As[TS * LDA];
@@ -1454,7 +1457,7 @@ __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ 
   while ((int64_t)r * (r + 1) / 2 > t) r--;
   const int c = (int)(t - (int64_t)r * (r + 1) / 2);
   const int nt = lay.nt[i];
-  const T* Wb = W + lay.foff[i];
+  const T* Wb = W + woff[i];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
@@ -1993,13 +1996,13 @@ void local_bsolve_upper(tls_ctx* c, double* X, const std::vector<int>& nq, const
 // S = A^{-1} over the lower tiles of N Cholesky factors (tile counts nt,
 // layout lay, elems elements in all), from their factors and diagonal-tile
 // inverses; a scratch buffer of the factors' size holds W = L^{-1}.
+// One group of subdomains (ids in `order`, largest first) whose W blocks
+// sit at woff[i] of W.
 template <class T>
-void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, int64_t elems,
-                        T* fac, const T* dinv) {
+static void inverse_group(hipStream_t s, const std::vector<int>& order, const std::vector<int>& nt,
+                          const LocalLayout& lay, const int64_t* woff, T* fac, const T* dinv, T* W) {
   constexpr int PW = 8;
-  std::vector<int> order(N);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
+  const int N = (int)order.size();
   const int maxnt = N ? nt[order[0]] : 0;
   auto active = [&](int j) {
     int a = 0;
@@ -2048,28 +2051,60 @@ void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const 
   DBuf<int64_t> d_pref;
   d_order.upload(order, s);
   d_pref.upload(pref, s);
-  DBuf<T> W;
-  W.alloc(std::max<int64_t>(elems, 1));
-  TLS_HIP(hipMemsetAsync(W.p, 0, sizeof(T) * std::max<int64_t>(elems, 1), s));
   for (const Launch& L : launches) {
     if (L.total <= 0) continue;
     switch (L.kind) {
       case 0:
         hipLaunchKernelGGL(k_tinv_row<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.j, L.j0, d_pref.p + L.off,
-                           L.nact, d_order.p, lay, fac, dinv, W.p);
+                           L.nact, d_order.p, lay, woff, fac, dinv, W);
         break;
       case 1:
         hipLaunchKernelGGL(k_tinv_update<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.j0, L.j1, d_pref.p + L.off,
-                           L.nact, d_order.p, lay, fac, W.p);
+                           L.nact, d_order.p, lay, woff, fac, W);
         break;
       default:
         hipLaunchKernelGGL(k_tinv_lauum<T>, dim3((unsigned)L.total), dim3(256), 0, s, d_pref.p + L.off, L.nact,
-                           d_order.p, lay, W.p, fac);
+                           d_order.p, lay, woff, W, fac);
         break;
     }
     TLS_LAUNCH_CHECK();
   }
   TLS_HIP(hipStreamSynchronize(s));
+}
+
+// W holds the blocks of one group of subdomains at a time. The groups
+// (largest subdomains first) are cut so that W fits in 90% of the device
+// memory still available; when everything fits there is one group.
+template <class T>
+void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac,
+                        const T* dinv) {
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
+  const int64_t budget = (int64_t)(0.9 * (double)devmem::available() / sizeof(T));
+  std::vector<std::vector<int>> groups;
+  std::vector<int64_t> woff(N, 0);
+  int64_t wmax = 1, tot = 0;
+  for (int a = 0; a < N; a++) {
+    const int i = order[a];
+    const int64_t e = tiles_of(0, nt[i]) * TS2;
+    if (groups.empty() || tot + e > budget) {
+      groups.emplace_back();
+      tot = 0;
+    }
+    groups.back().push_back(i);
+    woff[i] = tot;
+    tot += e;
+    wmax = std::max(wmax, tot);
+  }
+  DBuf<int64_t> d_woff;
+  d_woff.upload(woff, s);
+  DBuf<T> W;
+  W.alloc(wmax);
+  for (const auto& g : groups) {
+    TLS_HIP(hipMemsetAsync(W.p, 0, sizeof(T) * wmax, s));
+    inverse_group<T>(s, g, nt, lay, d_woff.p, fac, dinv, W.p);
+  }
 }
 
 // Work list of the symmetric product over N matrices (tile counts nt,
@@ -2139,16 +2174,16 @@ void form_local_inverse(tls_ctx* c) {
   if (c->kind != 0) fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
   hipStream_t s = c->stream;
   if (c->fp32)
-    form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac_elems, c->fac32.p, c->dinv32.p);
+    form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p);
   else
-    form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac_elems, c->fac64.p, c->dinv64.p);
+    form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p);
   build_symv_work(c->inv_work, s, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32);
   c->inv_formed = true;
 }
 
-void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, int64_t elems,
-                      double* fac, const double* dinv) {
-  form_inverse_tiles<double>(s, N, nt, lay, elems, fac, dinv);
+void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
+                      const double* dinv) {
+  form_inverse_tiles<double>(s, N, nt, lay, fac, dinv);
 }
 
 template <class T>

@@ -504,7 +504,30 @@ struct PassDims {
   std::vector<int> oth;
   int kmax = 0;
   int over = 0;  // subspace block p = k + over (default over = k of the pass)
+  bool general = false;
 };
+
+// Buffer offsets from the sizes and kreq (subdomains with kreq = 0 take no room).
+static void pass_offsets(PassDims& d) {
+  const int N = (int)d.nI.size();
+  for (auto* v : {&d.oF, &d.oGI, &d.oTG, &d.oGG, &d.oTT, &d.oY, &d.oZv}) v->assign(N + 1, 0);
+  d.oth.assign(N + 1, 0);
+  d.kmax = 0;
+  for (int i = 0; i < N; i++) {
+    d.kmax = std::max(d.kmax, d.kreq[i]);
+    const int p = std::min(d.nT[i], std::min(PMAX, d.kreq[i] + d.over));
+    const bool act = d.kreq[i] > 0;
+    const int64_t nG = d.nG[i];
+    d.oF[i + 1] = d.oF[i] + (act && !d.general ? (int64_t)d.nI[i] * d.nT[i] : 0);
+    d.oGI[i + 1] = d.oGI[i] + (act ? nG * d.nI[i] : 0);
+    d.oTG[i + 1] = d.oTG[i] + (act ? nG * d.nT[i] : 0);
+    d.oGG[i + 1] = d.oGG[i] + (act ? nG * nG : 0);
+    d.oTT[i + 1] = d.oTT[i] + (act ? (int64_t)d.nT[i] * d.nT[i] : 0);
+    d.oY[i + 1] = d.oY[i] + (act ? (int64_t)d.nT[i] * std::max(p, 1) : 0);
+    d.oZv[i + 1] = d.oZv[i] + (int64_t)d.nT[i] * d.kreq[i];
+    d.oth[i + 1] = d.oth[i] + d.kreq[i];
+  }
+}
 
 static PassDims pass_dims(const tls_ctx* c, const std::vector<int>& nG, int nev, bool general) {
   const int N = c->N;
@@ -513,8 +536,7 @@ static PassDims pass_dims(const tls_ctx* c, const std::vector<int>& nG, int nev,
   d.nG = nG;
   d.nT.resize(N);
   d.kreq.resize(N);
-  for (auto* v : {&d.oF, &d.oGI, &d.oTG, &d.oGG, &d.oTT, &d.oY, &d.oZv}) v->assign(N + 1, 0);
-  d.oth.assign(N + 1, 0);
+  d.general = general;
   d.over = c->opt.eig_oversample >= 0 ? c->opt.eig_oversample : nev;
   for (int i = 0; i < N; i++) {
     d.nI[i] = c->h_nI[i];
@@ -522,19 +544,18 @@ static PassDims pass_dims(const tls_ctx* c, const std::vector<int>& nG, int nev,
     int k = std::min(std::min(nev, d.nT[i]), PMAX);
     if (general) k = std::min(k, d.nI[i]);
     d.kreq[i] = std::max(k, 0);
-    d.kmax = std::max(d.kmax, d.kreq[i]);
-    const int p = std::min(d.nT[i], std::min(PMAX, d.kreq[i] + d.over));
-    const bool act = d.kreq[i] > 0;
-    d.oF[i + 1] = d.oF[i] + (act && !general ? (int64_t)d.nI[i] * d.nT[i] : 0);
-    d.oGI[i + 1] = d.oGI[i] + (act ? (int64_t)nG[i] * d.nI[i] : 0);
-    d.oTG[i + 1] = d.oTG[i] + (act ? (int64_t)nG[i] * d.nT[i] : 0);
-    d.oGG[i + 1] = d.oGG[i] + (act ? (int64_t)nG[i] * nG[i] : 0);
-    d.oTT[i + 1] = d.oTT[i] + (act ? (int64_t)d.nT[i] * d.nT[i] : 0);
-    d.oY[i + 1] = d.oY[i] + (act ? (int64_t)d.nT[i] * std::max(p, 1) : 0);
-    d.oZv[i + 1] = d.oZv[i] + (int64_t)d.nT[i] * d.kreq[i];
-    d.oth[i + 1] = d.oth[i] + d.kreq[i];
   }
+  pass_offsets(d);
   return d;
+}
+
+// The same pass restricted to the subdomains [i0, i1).
+static PassDims pass_restrict(const PassDims& d, int i0, int i1) {
+  PassDims r = d;
+  for (int i = 0; i < (int)d.kreq.size(); i++)
+    if (i < i0 || i >= i1) r.kreq[i] = 0;
+  pass_offsets(r);
+  return r;
 }
 
 // Device copies of the per-subdomain tables of a pass.
@@ -731,15 +752,13 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
   const dim3 eg(64, N);
   DBuf<T> F, GI, TG, GGt, K;
   DBuf<double> LTT, LTTt, C64, C64b;
+  // buffers are taken as late and given back as early as the steps allow:
+  // the nT x nT blocks dominate the memory of a pass
   K.alloc(std::max<int64_t>(d.oTT[N], 1));
-  C64.alloc(std::max<int64_t>(d.oTT[N], 1));
   F.alloc(std::max<int64_t>(d.oF[N], 1));
   LTT.alloc(std::max<int64_t>(d.oTT[N], 1));
-  LTTt.alloc(std::max<int64_t>(d.oTT[N], 1));
-  C64b.alloc(std::max<int64_t>(d.oTT[N], 1));
   hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 0, el, fac, F.p);
   hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
-  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 5, el, fac, LTTt.p);
   TLS_LAUNCH_CHECK();
   if (d.oGG[N] > 0) {
     GI.alloc(d.oGI[N]);
@@ -774,9 +793,11 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
     batched_gemm<T>(s, gd, true, false, F.p, F.p, K.p, T(1), T(0));
   }
   // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
+  C64.alloc(std::max<int64_t>(d.oTT[N], 1));
   hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)d.oTT[N], K.p, C64.p);
   TLS_LAUNCH_CHECK();
   K.release();
+  C64b.alloc(std::max<int64_t>(d.oTT[N], 1));
   std::vector<TriDesc> td;
   for (int i = 0; i < N; i++)
     if (d.kreq[i] > 0) td.push_back(TriDesc{d.nT[i], d.nT[i], d.oTT[i], d.oTT[i], (int64_t)d.nT[i]});
@@ -789,6 +810,9 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
   if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_NOT_SPD, "zero pivot in a Schur-complement block");
   LTT.release();
   C64b.release();
+  LTTt.alloc(std::max<int64_t>(d.oTT[N], 1));
+  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 5, el, fac, LTTt.p);
+  TLS_LAUNCH_CHECK();
   DBuf<double> zv;
   DBuf<double> Ywarm;
   int c0 = 0;
@@ -834,6 +858,57 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
                             c->h_voff[i] + (int64_t)colbase[i] * c->sum_M, c->sum_M});
   batched_gemm<T>(s, gd, false, false, F.p, wT.p, XV, T(1), T(0));
   TLS_HIP(hipStreamSynchronize(s));
+  return e;
+}
+
+// Peak device bytes of subdomain i in an SPD pass: the nT x nT blocks (K,
+// two FP64 copies of C, L_TT and the working copy Cw), F, the G blocks, the
+// subspace blocks and the eigenvectors.
+static int64_t spd_pass_bytes(const PassDims& d, int i, int64_t tsz) {
+  if (d.kreq[i] <= 0) return 0;
+  const int64_t tt = (int64_t)d.nT[i] * d.nT[i], nG = d.nG[i];
+  return tt * (24 + 2 * tsz) + ((int64_t)d.nI[i] * d.nT[i] + nG * (nG + d.nI[i] + d.nT[i])) * tsz +
+         (d.oY[i + 1] - d.oY[i]) * 4 * tsz + (d.oZv[i + 1] - d.oZv[i]) * (8 + tsz);
+}
+
+// spd_pass over groups of consecutive subdomains whose buffers fit in 90%
+// of the device memory still available (one group when all fit). The
+// learned warm start and its training targets work on all subdomains at
+// once, so a pass that uses them is not split.
+template <class T>
+static PassEig spd_pass_grouped(tls_ctx* c, const T* fac, const PassDims& d, double thresh,
+                                const std::vector<int>& colbase, T* XV, bool gevp2) {
+  const int N = c->N;
+  const bool whole = gevp2 && (c->opt.gnn_weights || c->opt.gnn_train);
+  const int64_t budget = (int64_t)(0.9 * (double)devmem::available());
+  std::vector<std::pair<int, int>> groups;
+  int64_t acc = 0;
+  for (int i = 0; i < N; i++) {
+    const int64_t b = spd_pass_bytes(d, i, sizeof(T));
+    if (groups.empty() || (!whole && acc + b > budget)) {
+      groups.push_back({i, i});
+      acc = 0;
+    }
+    groups.back().second = i + 1;
+    acc += b;
+  }
+  if (groups.size() <= 1) return spd_pass<T>(c, fac, d, thresh, colbase, XV, gevp2);
+  PassEig e;
+  e.kf.assign(N, 0);
+  e.theta.assign(std::max(d.oth[N], 1), 0.0);
+  for (const auto& g : groups) {
+    const PassDims dg = pass_restrict(d, g.first, g.second);
+    if (dg.kmax == 0) continue;
+    const PassEig eg = spd_pass<T>(c, fac, dg, thresh, colbase, XV, gevp2);
+    for (int i = g.first; i < g.second; i++) {
+      e.kf[i] = eg.kf[i];
+      for (int j = 0; j < eg.kf[i]; j++) e.theta[d.oth[i] + j] = eg.theta[dg.oth[i] + j];
+    }
+    e.resid_max = std::max(e.resid_max, eg.resid_max);
+    e.iters_max = std::max(e.iters_max, eg.iters_max);
+    e.iters_sum += eg.iters_sum;
+    e.n_solved += eg.n_solved;
+  }
   return e;
 }
 
@@ -924,10 +999,10 @@ static void basis_spd(tls_ctx* c, T* fac) {
   PassEig e2, e1;
   e2.kf.assign(N, 0);
   e1.kf.assign(N, 0);
-  if (d2.kmax > 0) e2 = spd_pass<T>(c, fac, d2, tau2, std::vector<int>(N, 0), XV.p, true);
+  if (d2.kmax > 0) e2 = spd_pass_grouped<T>(c, fac, d2, tau2, std::vector<int>(N, 0), XV.p, true);
   if (d1.kmax > 0) {
     const double nu = c->opt.nu > 0 ? c->opt.nu : 1.0;
-    e1 = spd_pass<T>(c, fac, d1, nu - 1.0, e2.kf, XV.p, false);  // lambda = 1 + kappa > nu
+    e1 = spd_pass_grouped<T>(c, fac, d1, nu - 1.0, e2.kf, XV.p, false);  // lambda = 1 + kappa > nu
   }
   c->eig_resid_max = std::max(e2.resid_max, e1.resid_max);
   c->eig_iters_max = std::max(e2.iters_max, e1.iters_max);

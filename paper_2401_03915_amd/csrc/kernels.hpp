@@ -25,8 +25,8 @@ void build_solve_tasks(tls_ctx* c);
 void form_local_inverse(tls_ctx* c);
 // the same for N FP64 Cholesky factors in any tile layout (A_0), and the
 // work list and product of the symmetric product over them
-void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, int64_t elems,
-                      double* fac, const double* dinv);
+void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
+                      const double* dinv);
 void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& nt,
                      const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32);
 void symv_solve_f64(hipStream_t s, SymvWork& w, const double* S, double* x, const int* done);

@@ -774,6 +774,34 @@ def test_reused_device_blocks_and_trim():
     assert torch.equal(xs[0][0], xs[1][0]) and torch.equal(xs[0][0], xs[2][0])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_grouped_setup_is_bitwise_identical(monkeypatch, precision):
+    """With TLS_MEMORY_LIMIT=1 every eigen pass (both eigenproblems) and the
+    formation of the explicit inverses run one subdomain at a time; the
+    coarse basis, its eigenvalues and the preconditioner are bit for bit
+    those of the set-up that does all subdomains at once."""
+    torch = torch_cuda()
+    A, part = _diffusion_3d(14, 3, seed=21)
+    r = to_dev(np.random.default_rng(4).standard_normal(A.shape[0]))
+    out = []
+    for lim in (None, "1"):
+        if lim:
+            monkeypatch.setenv("TLS_MEMORY_LIMIT", lim)
+        say(f"grouped set-up: precision {precision}, limit {lim}")
+        pc = _pc(A, part, 2, 6, nev1=2, precision=precision, local_inverse=1)
+        ex = pc.export(Z=True)
+        z = pc.apply(r)
+        torch.cuda.synchronize()
+        out.append((ex, z.cpu().numpy()))
+        pc.close()
+        monkeypatch.delenv("TLS_MEMORY_LIMIT", raising=False)
+    (e0, z0), (e1, z1) = out
+    assert e0["zsrc"].tolist().count(1) > 0  # the eq. uppergevp pass kept columns
+    for key in ("zcol_ptr", "zsrc", "eigvals", "Z"):
+        assert np.array_equal(e0[key], e1[key]), key
+    assert np.array_equal(z0, z1)
+
+
 def test_autotune_cache_reuse(tmp_path):
     import paper_2401_03915_amd as tls
     A, part = _hc_problem(96, 3, seed=8)

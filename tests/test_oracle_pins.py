@@ -364,6 +364,27 @@ def test_eigenvalue_decay_faster_with_more_layers():
     assert counts[1] > counts[3] > counts[5]
 
 
+def test_weak_scaling_two_level_iterations_stay_flat():
+    """Section 7 (Table diffusion-3d): under weak scaling of the constant-
+    coefficient 3D Poisson problem (fixed unknowns per subdomain, N grows)
+    the two-level PCG iteration count stays nearly flat while the one-level
+    count keeps growing; the condition-number bound of the two-level method
+    depends on N only through lambda_*. 250 unknowns per part, delta = 1,
+    8 eq. gevpsvd vectors per subdomain, rtol 1e-10, N = 4, 16, 64."""
+    from workloads import weak_scaling_poisson_3d
+    two, one = {}, {}
+    for N in (4, 16, 64):
+        p = weak_scaling_poisson_3d(N, per_part=250)
+        for nev, out in ((8, two), (0, one)):
+            h = schwarz.setup(p.A, p.part, 1, nev)
+            x, it, rr = schwarz.solve(h, p.b, 1e-10)
+            assert rr <= 1e-10
+            out[N] = it
+    assert two[64] <= 1.35 * two[4]
+    assert one[64] >= 1.6 * one[4]
+    assert two[64] <= 0.75 * one[64]
+
+
 # ----------------------------------------------------------------------------
 # RAS (eq. onelevelras) and the deflated coarse correction of Section 7.2
 # ----------------------------------------------------------------------------

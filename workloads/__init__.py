@@ -24,5 +24,6 @@ from .problems import (  # noqa: F401
     poisson_2d,
     rcb_partition,
     rhs,
+    weak_scaling_poisson_3d,
     worked_example_7x7,
 )

@@ -413,6 +413,24 @@ CONFIGS = {
 }
 
 
+def weak_scaling_poisson_3d(n_parts: int, seed: int = 0, per_part: float = 29791 / 2, overlap: int = 1,
+                            nev: int = 12) -> Problem:
+    """Weak-scaling instance: the constant-coefficient 3D Poisson problem (the
+    7-point finite-volume Laplacian of kappa = 1 with Dirichlet faces) on a
+    cube of side round((per_part * N)^(1/3)) cells, cut by exact recursive
+    bisection into N = 2^L boxes of about per_part unknowns (the default
+    gives the 31^3 grid with 2 parts and the 191^3 grid with 512). b is
+    seeded as in make_config."""
+    levels = int(round(np.log2(n_parts)))
+    if 2 ** levels != n_parts:
+        raise ValueError("n_parts must be a power of two")
+    side = int(round((per_part * n_parts) ** (1.0 / 3.0)))
+    A = fv_diffusion_3d(np.ones((side, side, side)))
+    part = rcb_partition((side, side, side), levels, np.random.default_rng(seed), (0.5, 0.5))
+    return Problem(f"weak{n_parts}", A, part, n_parts, overlap, nev, rhs(A.shape[0], seed + 1000), True,
+                   {"grid": (side, side, side), "levels": levels})
+
+
 def make_config(cfg: int, seed: int = 0, scale: int | None = None) -> Problem:
     """Build benchmark configuration ``cfg`` (1..5).
 
