@@ -304,7 +304,8 @@ def weak_scaling(parts, steps, warmup, local_inverse):
                      "relres": float(f"{rr:.3e}"), "n_coarse": inf["n_coarse"], "gc": round(inf["gc"], 4),
                      "oc": round(inf["oc"], 4), "time_to_solve_s": round(t_last, 3),
                      "setup_ms": round(inf["t_setup"][7], 1),
-                     "setup_split_ms": {"factor": round(inf["t_setup"][2], 1), "basis": round(inf["t_setup"][3], 1),
+                     "setup_split_ms": {"overlap": round(inf["t_setup"][0], 1), "gather": round(inf["t_setup"][1], 1),
+                                        "factor": round(inf["t_setup"][2], 1), "basis": round(inf["t_setup"][3], 1),
                                         "coarse": round(inf["t_setup"][5], 1),
                                         "inverse": round(inf["t_inverse_ms"], 1)},
                      "solve_ms": round(inf["t_solve"], 1),
@@ -355,7 +356,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.weak_scaling:
         parts = [int(a) for a in args.weak_scaling.split(",")]
-        li = 1 if args.local_inverse is None else args.local_inverse
+        # substitutions by default: at ~30-40 iterations the explicit inverses
+        # (twice the factorization's flops) do not pay for themselves
+        li = 0 if args.local_inverse is None else args.local_inverse
         print(json.dumps(weak_scaling(parts, args.steps, args.warmup, li)), flush=True)
         return
     log("generating workload")

@@ -1053,38 +1053,44 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
   }
 }
 
-// Backward solve with the LU factor's upper block U_II and many right-hand
-// sides, on the tile storage: X_i is column-major with leading dimension
-// M_i = 64 nt_i, its 64 q-th columns one "column block". Subdomain i has
-// nb_i = ceil(#I_i / 64) tile rows; a global step s stands for its tile row
-// k = nb_i - 1 - s, so all subdomains start from their own last row. Rows
-// of the last tile that belong to G have zero right-hand sides and stay
-// zero, so solving with the whole diagonal tile is exact.
+// Backward solve with many right-hand sides on the tile storage, with the
+// upper block U_II of an LU factor or, LT = true, with L_II^T of a Cholesky
+// factor (U_jk = L_kj^T, read from the lower tile (k, j)). X_i is
+// column-major with leading dimension ldx (M_i = 64 nt_i when ldx = 0), its
+// 64 q-th columns one "column block". Subdomain i has nb_i = ceil(#I_i / 64)
+// tile rows; a global step s stands for its tile row k = nb_i - 1 - s, so
+// all subdomains start from their own last row. Rows of the last tile that
+// lie outside I have zero right-hand sides and stay zero, so solving with
+// the whole diagonal tile is exact.
 
-// X_k <- U_kk^{-1} X_k (packed inverse from k_getrf, upper part), one
+// X_k <- U_kk^{-1} X_k (packed inverse from the factorization: the upper
+// part for LU, the transpose of the lower part for Cholesky), one
 // workgroup per (subdomain, column block); MFMA.
-template <class T>
+template <class T, bool LT>
 __global__ void __launch_bounds__(256) k_bsolve_diag(int s, const int64_t* __restrict__ pref, int nact,
                                                      const int* __restrict__ order, LocalLayout lay,
                                                      const int* __restrict__ nb, const int64_t* __restrict__ xoff,
-                                                     const T* __restrict__ dinv, T* X) {
+                                                     int64_t ldx, const T* __restrict__ dinv, T* X) {
   constexpr int LD = LdsLd<T>::v;
-  constexpr int LDB = KfPitch<T>::v;
-  __shared__ T As[TS * LD];   // As[kk * LD + row] = U_kk^{-1}(row, kk)
-  __shared__ T Bs[TS * LDB];  // Bs[col * LDB + kk] = X_k(kk, col)
+  constexpr int LDK = KfPitch<T>::v;
+  __shared__ T As[TS * (LD > LDK ? LD : LDK)];  // A = U_kk^{-1}: LT As[row * LDK + kk], else As[kk * LD + row]
+  __shared__ T Bs[TS * LDK];                    // Bs[col * LDK + kk] = X_k(kk, col)
   const int64_t bid = blockIdx.x;
   const int j = find_slot(pref, nact, bid);
   const int i = order[j];
   const int q = (int)(bid - pref[j]);
   const int k = nb[i] - 1 - s;
-  const int64_t M = (int64_t)lay.nt[i] * TS;
+  const int64_t M = ldx > 0 ? ldx : (int64_t)lay.nt[i] * TS;
   T* Xk = X + xoff[i] + (int64_t)q * TS * M + (int64_t)k * TS;
   const T* Di = dinv + (lay.toff[i] + k) * TS2;
   const int tid = threadIdx.x;
   for (int e = tid; e < TS2; e += 256) {
     const int a = e % TS, b = e / TS;
-    As[b * LD + a] = a <= b ? Di[e] : T(0);
-    Bs[b * LDB + a] = Xk[(int64_t)b * M + a];
+    if (LT)
+      As[b * LDK + a] = a >= b ? Di[e] : T(0);  // A(b, a) = L_kk^{-1}(a, b)
+    else
+      As[b * LD + a] = a <= b ? Di[e] : T(0);
+    Bs[b * LDK + a] = Xk[(int64_t)b * M + a];
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
@@ -1098,10 +1104,10 @@ __global__ void __launch_bounds__(256) k_bsolve_diag(int s, const int64_t* __res
     for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
 #pragma unroll 4
   for (int kk = 0; kk < TS; kk += 4) {
-    T a0 = As[(kk + lk) * LD + wr + li];
-    T a1 = As[(kk + lk) * LD + wr + 16 + li];
-    T b0 = Bs[(wc + li) * LDB + kk + lk];
-    T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+    T a0 = LT ? As[(wr + li) * LDK + kk + lk] : As[(kk + lk) * LD + wr + li];
+    T a1 = LT ? As[(wr + 16 + li) * LDK + kk + lk] : As[(kk + lk) * LD + wr + 16 + li];
+    T b0 = Bs[(wc + li) * LDK + kk + lk];
+    T b1 = Bs[(wc + 16 + li) * LDK + kk + lk];
     acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
     acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
     acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
@@ -1150,17 +1156,17 @@ __host__ __device__ inline BsolveRange bsolve_range(int mode, int s, int s0, int
 // X_j -= sum_{k in [klo, khi)} U_jk X_k for the rows j of bsolve_range, one
 // workgroup per (subdomain, row, column block); MFMA, the next tile pair
 // prefetched into registers.
-template <class T>
+template <class T, bool LT>
 __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, int pw,
                                                        const int64_t* __restrict__ pref, int nact,
                                                        const int* __restrict__ order, LocalLayout lay,
                                                        const int* __restrict__ nb, const int* __restrict__ nq,
-                                                       const int64_t* __restrict__ xoff, const T* __restrict__ fac,
-                                                       T* X) {
+                                                       const int64_t* __restrict__ xoff, int64_t ldx,
+                                                       const T* __restrict__ fac, T* X) {
   constexpr int LD = LdsLd<T>::v;
   constexpr int LDB = KfPitch<T>::v;
-  __shared__ T As[TS * LD];   // As[kk * LD + row] = U_jk(row, kk)
-  __shared__ T Bs[TS * LDB];  // Bs[col * LDB + kk] = X_k(kk, col)
+  __shared__ T As[TS * (LD > LDB ? LD : LDB)];  // A = U_jk: LT As[row * LDB + kk], else As[kk * LD + row]
+  __shared__ T Bs[TS * LDB];                    // Bs[col * LDB + kk] = X_k(kk, col)
   const int64_t bid = blockIdx.x;
   const int slot = find_slot(pref, nact, bid);
   const int i = order[slot];
@@ -1169,7 +1175,7 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
   const int q = (int)(t % nq[i]);
   const int j = rg.jlo + (int)(t / nq[i]);
   const int nt = lay.nt[i];
-  const int64_t M = (int64_t)nt * TS;
+  const int64_t M = ldx > 0 ? ldx : (int64_t)nt * TS;
   const T* base = fac + lay.foff[i];
   T* Xq = X + xoff[i] + (int64_t)q * TS * M;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1184,7 +1190,7 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
   constexpr int PER = TS2 / 256;
   T pa[PER], pb[PER];
   {
-    const T* U = base + tile_index(1, nt, j, rg.klo) * TS2;
+    const T* U = base + (LT ? tile_index(0, nt, rg.klo, j) : tile_index(1, nt, j, rg.klo)) * TS2;
     const T* Xk = Xq + (int64_t)rg.klo * TS;
 #pragma unroll
     for (int u = 0; u < PER; u++) {
@@ -1199,12 +1205,15 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
     for (int u = 0; u < PER; u++) {
       const int e = tid + 256 * u;
       const int a = e % TS, b = e / TS;
-      As[b * LD + a] = pa[u];
+      if (LT)
+        As[b * LDB + a] = pa[u];  // L_kj(a, b) = U_jk(b, a)
+      else
+        As[b * LD + a] = pa[u];
       Bs[b * LDB + a] = pb[u];
     }
     __syncthreads();
     if (k + 1 < rg.khi) {
-      const T* U = base + tile_index(1, nt, j, k + 1) * TS2;
+      const T* U = base + (LT ? tile_index(0, nt, k + 1, j) : tile_index(1, nt, j, k + 1)) * TS2;
       const T* Xk = Xq + (int64_t)(k + 1) * TS;
 #pragma unroll
       for (int u = 0; u < PER; u++) {
@@ -1215,8 +1224,8 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
     }
 #pragma unroll 4
     for (int kk = 0; kk < TS; kk += 4) {
-      T a0 = As[(kk + lk) * LD + wr + li];
-      T a1 = As[(kk + lk) * LD + wr + 16 + li];
+      T a0 = LT ? As[(wr + li) * LDB + kk + lk] : As[(kk + lk) * LD + wr + li];
+      T a1 = LT ? As[(wr + 16 + li) * LDB + kk + lk] : As[(kk + lk) * LD + wr + 16 + li];
       T b0 = Bs[(wc + li) * LDB + kk + lk];
       T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
       acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
@@ -1901,20 +1910,9 @@ void build_solve_tasks(tls_ctx* c) {
   TLS_HIP(hipStreamSynchronize(c->stream));
 }
 
-void local_backward(tls_ctx* c, float* x, const int* done) {
-  solve_begin(c->stream, c->counters.p, done);
-  trsv<float>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->plan_bwd, c->counters.p + 1, c->counters.p + 2,
-              c->layout(), c->fac32.p, c->dinv32.p, x, c->errflag.p, done, c->solve_grid);
-}
-
-void local_backward(tls_ctx* c, double* x, const int* done) {
-  solve_begin(c->stream, c->counters.p, done);
-  trsv<double>(c->stream, c->kind == 0 ? BWD_LT : BWD_U, c->plan_bwd, c->counters.p + 1, c->counters.p + 2,
-               c->layout(), c->fac64.p, c->dinv64.p, x, c->errflag.p, done, c->solve_grid);
-}
-
 template <class T>
-void bsolve_upper_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
+void bsolve_interior_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int>& nq,
+                          const std::vector<int64_t>& xoff, int64_t ldx) {
   constexpr int PW = 8;
   hipStream_t s = c->stream;
   const int N = c->N;
@@ -1974,23 +1972,28 @@ void bsolve_upper_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int>& 
   d_xoff.upload(xoff, s);
   LocalLayout lay = c->layout();
   const T* fac = c->fp32 ? reinterpret_cast<const T*>(c->fac32.p) : reinterpret_cast<const T*>(c->fac64.p);
+  const bool lt = c->kind == 0;
+  auto diag = lt ? k_bsolve_diag<T, true> : k_bsolve_diag<T, false>;
+  auto update = lt ? k_bsolve_update<T, true> : k_bsolve_update<T, false>;
   for (const Launch& L : launches) {
     if (L.kind == 0)
-      hipLaunchKernelGGL(k_bsolve_diag<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.s, d_pref.p + L.off, L.nact,
-                         d_order.p, lay, d_nb.p, d_xoff.p, dinv, X);
+      hipLaunchKernelGGL(diag, dim3((unsigned)L.total), dim3(256), 0, s, L.s, d_pref.p + L.off, L.nact, d_order.p,
+                         lay, d_nb.p, d_xoff.p, ldx, dinv, X);
     else
-      hipLaunchKernelGGL(k_bsolve_update<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.kind - 1, L.s, L.s0, PW,
-                         d_pref.p + L.off, L.nact, d_order.p, lay, d_nb.p, d_nq.p, d_xoff.p, fac, X);
+      hipLaunchKernelGGL(update, dim3((unsigned)L.total), dim3(256), 0, s, L.kind - 1, L.s, L.s0, PW,
+                         d_pref.p + L.off, L.nact, d_order.p, lay, d_nb.p, d_nq.p, d_xoff.p, ldx, fac, X);
     TLS_LAUNCH_CHECK();
   }
   TLS_HIP(hipStreamSynchronize(s));
 }
 
-void local_bsolve_upper(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
-  bsolve_upper_impl<float>(c, c->dinv32.p, X, nq, xoff);
+void local_bsolve_interior(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff,
+                           int64_t ldx) {
+  bsolve_interior_impl<float>(c, c->dinv32.p, X, nq, xoff, ldx);
 }
-void local_bsolve_upper(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff) {
-  bsolve_upper_impl<double>(c, c->dinv64.p, X, nq, xoff);
+void local_bsolve_interior(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff,
+                           int64_t ldx) {
+  bsolve_interior_impl<double>(c, c->dinv64.p, X, nq, xoff, ldx);
 }
 
 // S = A^{-1} over the lower tiles of N Cholesky factors (tile counts nt,

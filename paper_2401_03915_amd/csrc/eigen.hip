@@ -991,9 +991,10 @@ static void basis_spd(tls_ctx* c, T* fac) {
   }
   int kcols = 0;
   for (int i = 0; i < N; i++) kcols = std::max(kcols, d2.kreq[i] + d1.kreq[i]);
+  kcols = (std::max(kcols, 1) + TS - 1) / TS * TS;  // whole column blocks for the backward solve
   DBuf<T> XV;
-  XV.alloc((size_t)std::max(kcols, 1) * c->sum_M);
-  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max(kcols, 1) * c->sum_M, s));
+  XV.alloc((size_t)kcols * c->sum_M);
+  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * kcols * c->sum_M, s));
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
   const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;  // lambda^2 > tau^2
   PassEig e2, e1;
@@ -1007,14 +1008,14 @@ static void basis_spd(tls_ctx* c, T* fac) {
   c->eig_resid_max = std::max(e2.resid_max, e1.resid_max);
   c->eig_iters_max = std::max(e2.iters_max, e1.iters_max);
   c->eig_iters_mean = (e2.iters_sum + e1.iters_sum) / std::max(1, e2.n_solved + e1.n_solved);
-  // x = L^{-T} [V; 0] per column with the persistent solve: rows I = L_II^{-T} V
-  std::vector<int> ncols(N);
-  int kfm = 0;
+  // x = L^{-T} [V; 0]: rows I are L_II^{-T} V (the rows outside I stay
+  // zero), all columns of a subdomain at once by the blocked MFMA solve
+  std::vector<int> ncols(N), nq(N);
   for (int i = 0; i < N; i++) {
     ncols[i] = e2.kf[i] + e1.kf[i];
-    kfm = std::max(kfm, ncols[i]);
+    nq[i] = (ncols[i] + TS - 1) / TS;
   }
-  for (int j = 0; j < kfm; j++) local_backward(c, XV.p + (size_t)j * c->sum_M, c->zero_int.p);
+  local_bsolve_interior(c, XV.p, nq, c->h_voff, c->sum_M);
   // eigenvalue and source of every column: lambda^2 (eq. gevpsvd) or lambda (eq. uppergevp)
   std::vector<double> colval;
   std::vector<int> colsrc;
@@ -1102,7 +1103,7 @@ static void basis_general(tls_ctx* c, T* fac) {
   }
   if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_SINGULAR, "zero pivot in a local U_GG block");
   // H = U_II^{-1} X (rows I); rows G, T of XH stay zero
-  local_bsolve_upper(c, XH.p, nqH, oXH);
+  local_bsolve_interior(c, XH.p, nqH, oXH, 0);
   // K = H^T H
   std::vector<GemmDesc> gd;
   for (int i = 0; i < N; i++) {

@@ -32,15 +32,16 @@ void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& 
 void symv_solve_f64(hipStream_t s, SymvWork& w, const double* S, double* x, const int* done);
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_mid = nullptr,
                  hipEvent_t ev_end = nullptr);
-// backward substitution L^T x = x only, on a padded vector of the context's precision
-void local_backward(tls_ctx* c, float* x, const int* done);
-void local_backward(tls_ctx* c, double* x, const int* done);
-// general A: X_i <- U_II^{-1} X_i with the leading block U_II (rows and
-// columns I_i) of the LU factor, many right-hand sides: X_i (M_i x 64 nq_i,
-// column-major, at xoff[i]) is overwritten on its rows I_i; rows beyond I_i
-// must be zero in the tile that holds the last rows of I_i
-void local_bsolve_upper(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
-void local_bsolve_upper(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff);
+// X_i <- U_II^{-1} X_i with the leading block (rows and columns I_i) of the
+// local factor: U_II of the LU factor (general A) or L_II^T of the Cholesky
+// factor (SPD), many right-hand sides. X_i (64 nq_i columns, column-major
+// with leading dimension ldx, or M_i when ldx = 0, at xoff[i]) is
+// overwritten on its rows I_i; rows beyond I_i must be zero in the tile that
+// holds the last rows of I_i
+void local_bsolve_interior(tls_ctx* c, float* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff,
+                           int64_t ldx);
+void local_bsolve_interior(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff,
+                           int64_t ldx);
 void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
                          double* dinv, int* err);
 // generic pieces reused for the coarse factor (always fp64)
