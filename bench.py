@@ -261,7 +261,7 @@ def cpu_baseline(prob, iters, sample=64, seed=0, composition=0):
 
 
 WEAK_TAU2 = 0.41  # eq. gevpsvd threshold on lambda^2 (about 12 vectors per part at N = 2)
-WEAK_CAP = 48
+WEAK_CAP = 40
 
 
 def weak_scaling(parts, steps, warmup, local_inverse):

@@ -102,8 +102,9 @@ typedef struct {
   int32_t eig_maxit;    /* local subspace-iteration cap (default 300)      */
   double eig_tol;       /* relative eigen-residual tolerance (default 1e-9 FP64, 1e-5 FP32);
                            a residual below 10x that which stalls is accepted */
-  int32_t eig_oversample; /* subspace block p = k + oversample, k = nev (eq. gevpsvd) or
-                             nev1 (eq. uppergevp); default (-1): k; p <= 48 */
+  int32_t eig_oversample; /* subspace block p = min(k + oversample, 48), k = min(nev, 40)
+                             (eq. gevpsvd) or min(nev1, 40) (eq. uppergevp), so at most
+                             40 vectors per subdomain and eigenproblem; default (-1): k */
   uint64_t seed;        /* seed of the counter-based start vectors         */
   int32_t use_graph;    /* capture Krylov iteration chunks in a hipGraph   */
   int32_t flexible;     /* PCG: Polak-Ribiere beta (default: 1 iff precision == 1) */

@@ -27,6 +27,7 @@ namespace tls {
 namespace {
 
 constexpr int PMAX = 48;      // largest subspace block
+constexpr int OVER_MIN = 8;   // the block keeps at least this many extra vectors: k <= PMAX - OVER_MIN
 constexpr int KMAX = 2 * PMAX;  // most coarse columns of one subdomain (both eigenproblems)
 
 struct EigLayout {
@@ -380,17 +381,28 @@ __global__ void __launch_bounds__(256) k_ss_rr(const int* __restrict__ ids, cons
 }
 
 // Largest relative residual ||V_j - theta_j U_j|| / theta_0 over the first
-// min(k, p) Ritz pairs; converged when it is <= tol (or when p == n).
+// min(k, p) Ritz pairs; converged when it is <= tol (or when p == n). With a
+// selection threshold (thresh > 0) only the pairs that may be kept count:
+// those whose shifted Ritz value is above 0.9 thresh (Ritz values grow
+// towards the eigenvalues as the iteration proceeds), and always the first.
 template <class T>
 __global__ void __launch_bounds__(256) k_ss_resid(const int* __restrict__ ids, const int* __restrict__ n_,
                                                   const int* __restrict__ p_, const int* __restrict__ k_,
                                                   const int64_t* __restrict__ oY, const T* __restrict__ V,
-                                                  const T* __restrict__ U, const double* __restrict__ th, double tol,
+                                                  const T* __restrict__ U, const double* __restrict__ th,
+                                                  const double* __restrict__ sigma, double thresh, double tol,
                                                   double* res, int* conv) {
   __shared__ double red[16];
   const int i = ids[blockIdx.x];
-  const int n = n_[i], p = p_[i], kp = min(k_[i], p), tid = threadIdx.x;
+  const int n = n_[i], p = p_[i], tid = threadIdx.x;
   const double* t = th + (int64_t)i * PMAX;
+  int kp = min(k_[i], p);
+  if (thresh > 0.0)
+    for (int j = 1; j < kp; j++)
+      if (t[j] - sigma[i] <= 0.9 * thresh) {
+        kp = j;
+        break;
+      }
   const double th0 = fmax(t[0], 1e-300);
   const T* Vi = V + oY[i];
   const T* Ui = U + oY[i];
@@ -541,7 +553,7 @@ static PassDims pass_dims(const tls_ctx* c, const std::vector<int>& nG, int nev,
   for (int i = 0; i < N; i++) {
     d.nI[i] = c->h_nI[i];
     d.nT[i] = c->h_m[i] - d.nI[i] - nG[i];
-    int k = std::min(std::min(nev, d.nT[i]), PMAX);
+    int k = std::min(std::min(nev, d.nT[i]), PMAX - OVER_MIN);
     if (general) k = std::min(k, d.nI[i]);
     d.kreq[i] = std::max(k, 0);
   }
@@ -680,7 +692,7 @@ static PassEig subspace_batched(tls_ctx* c, const PassDims& d, PassDev& dv, cons
     gemm_run<T>(s, pNP, false, false, W.p, Sb.p, V.p, T(1), T(0));      // V = W S
     gemm_run<T>(s, pNP, false, false, Y.p, Sb.p, U.p, T(1), T(0));      // U = Y S
     hipLaunchKernelGGL(k_ss_resid<T>, dim3((unsigned)act.size()), dim3(256), 0, s, ids.p, dv.nT.p, d_p.p,
-                       dv.kreq.p, dv.oY.p, V.p, U.p, th.p, tol, res.p, conv.p);
+                       dv.kreq.p, dv.oY.p, V.p, U.p, th.p, sig.p, thresh, tol, res.p, conv.p);
     TLS_LAUNCH_CHECK();
     auto h_conv = download(conv.p, N, s);
     auto h_res = download(res.p, N, s);

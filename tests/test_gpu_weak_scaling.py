@@ -15,7 +15,7 @@ from workloads import weak_scaling_poisson_3d
 pytestmark = pytest.mark.gpu
 
 TAU2 = 0.41  # eq. gevpsvd threshold on lambda^2: about 12 vectors per part at N = 2
-CAP = 48
+CAP = 40
 
 
 def _solve(p, nev, **opts):
