@@ -264,60 +264,58 @@ WEAK_TAU2 = 0.41  # eq. gevpsvd threshold on lambda^2 (about 12 vectors per part
 WEAK_CAP = 40
 
 
-def weak_scaling(parts, steps, warmup, local_inverse):
+def weak_scaling(N, steps, warmup, local_inverse):
     """Single-GPU analog of the weak-scaling study of Section 7 (Table
-    diffusion-3d): the constant-coefficient 3D Poisson problem with about
-    15k unknowns per subdomain, the grid growing with N, delta = 1,
-    rtol 1e-10, mixed precision. Per N: two-level iterations (threshold
-    selection), one-level iterations, n_C, GC, OC, and the time to solve
-    (set-up + PCG, inputs resident in HBM)."""
+    diffusion-3d), one subdomain count N: the constant-coefficient 3D
+    Poisson problem with about 15k unknowns per subdomain, the grid growing
+    with N, delta = 1, rtol 1e-10, mixed precision. Returns the two-level
+    iterations (threshold selection), the one-level iterations, n_C, GC, OC
+    and the time to solve (set-up + PCG, inputs resident in HBM)."""
     import torch
 
     import paper_2401_03915_amd as tls
     from workloads import weak_scaling_poisson_3d
     dev = torch.device("cuda:0")
-    rows = []
-    t_last = 0.0
-    for N in parts:
-        log(f"weak scaling: N={N}")
-        p = weak_scaling_poisson_3d(N)
-        b = torch.as_tensor(p.b, device=dev)
-        li = local_inverse
+    log(f"weak scaling: N={N}")
+    p = weak_scaling_poisson_3d(N)
+    b = torch.as_tensor(p.b, device=dev)
 
-        def run(nev, **kw):
-            pc = tls.Preconditioner(p.A, p.part, p.overlap, nev, precision=1, local_inverse=li, **kw)
-            x, it, rr, st = pc.solve(b, 1e-10)
-            torch.cuda.synchronize()
-            inf = pc.info()
-            pc.close()
-            return it, rr, st, inf
+    def run(nev, **kw):
+        pc = tls.Preconditioner(p.A, p.part, p.overlap, nev, precision=1, local_inverse=local_inverse, **kw)
+        x, it, rr, st = pc.solve(b, 1e-10)
+        torch.cuda.synchronize()
+        inf = pc.info()
+        pc.close()
+        return it, rr, st, inf
 
-        tau = float(np.sqrt(WEAK_TAU2))
-        for _ in range(warmup if N == parts[0] else 0):
-            run(WEAK_CAP, tau=tau)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            it, rr, st, inf = run(WEAK_CAP, tau=tau)
-        t_last = (time.perf_counter() - t0) / steps
-        it1, rr1, st1, _ = run(0)
-        rows.append({"N": N, "n": int(p.A.shape[0]), "grid": list(p.meta["grid"]), "iters": it, "status": st,
-                     "relres": float(f"{rr:.3e}"), "n_coarse": inf["n_coarse"], "gc": round(inf["gc"], 4),
-                     "oc": round(inf["oc"], 4), "time_to_solve_s": round(t_last, 3),
-                     "setup_ms": round(inf["t_setup"][7], 1),
-                     "setup_split_ms": {"overlap": round(inf["t_setup"][0], 1), "gather": round(inf["t_setup"][1], 1),
-                                        "factor": round(inf["t_setup"][2], 1), "basis": round(inf["t_setup"][3], 1),
-                                        "coarse": round(inf["t_setup"][5], 1),
-                                        "inverse": round(inf["t_inverse_ms"], 1)},
-                     "solve_ms": round(inf["t_solve"], 1),
-                     "one_level_iters": it1, "one_level_status": st1})
-        log(f"  two-level {it} its (n_C {inf['n_coarse']}, GC {inf['gc']:.4f}) in {t_last:.2f} s; one-level {it1}")
+    tau = float(np.sqrt(WEAK_TAU2))
+    for _ in range(warmup):
+        run(WEAK_CAP, tau=tau)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        it, rr, st, inf = run(WEAK_CAP, tau=tau)
+    t = (time.perf_counter() - t0) / steps
+    it1, rr1, st1, _ = run(0)
+    log(f"  two-level {it} its (n_C {inf['n_coarse']}, GC {inf['gc']:.4f}) in {t:.2f} s; one-level {it1}")
+    ts = inf["t_setup"]
+    return {"N": N, "n": int(p.A.shape[0]), "grid": list(p.meta["grid"]), "iters": it, "status": st,
+            "relres": float(f"{rr:.3e}"), "n_coarse": inf["n_coarse"], "gc": round(inf["gc"], 4),
+            "oc": round(inf["oc"], 4), "time_to_solve_s": round(t, 3), "setup_ms": round(ts[7], 1),
+            "setup_split_ms": {"overlap": round(ts[0], 1), "gather": round(ts[1], 1), "factor": round(ts[2], 1),
+                               "basis": round(ts[3], 1), "coarse": round(ts[5], 1),
+                               "inverse": round(inf["t_inverse_ms"], 1)},
+            "solve_ms": round(inf["t_solve"], 1), "one_level_iters": it1, "one_level_status": st1}
+
+
+def weak_summary(rows, steps, warmup, local_inverse):
+    t_last = rows[-1]["time_to_solve_s"]
     return {
         "metric": "weak scaling, 3D Poisson with ~15k unknowns per subdomain (rel res 1e-10): time-to-solve at the "
                   "largest N; two-level and one-level PCG iterations per N",
-        "value": round(t_last, 4), "unit": "s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "value": t_last, "unit": "s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": round(t_last * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 local / f64 outer", "data": "synthetic",
-        "config": {"workload": f"3D Poisson weak scaling, N = {parts[0]}..{parts[-1]}, delta 1, "
+        "config": {"workload": f"3D Poisson weak scaling, N = {rows[0]['N']}..{rows[-1]['N']}, delta 1, "
                                f"tau^2 {WEAK_TAU2} (at most {WEAK_CAP} per part)",
                    "local_solves": "explicit inverse" if local_inverse else "substitution"},
         "table": rows,
@@ -344,22 +342,39 @@ def main():
                     help="also run z = 1.0 * x over 1 GiB (reads 1 GiB, writes 1 GiB): the plain copy kernel "
                          "whose HBM counters scale those of the solve kernels")
     ap.add_argument("--weak-scaling", type=str, default=None,
-                    help="comma-separated subdomain counts (powers of two): run the weak-scaling analog instead")
+                    help="comma-separated subdomain counts (powers of two): run the weak-scaling analog instead, "
+                         "each count in a process of its own")
+    ap.add_argument("--weak-scaling-one", type=int, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); multi-GPU runs are not part of "
               "this build", file=sys.stderr)
         sys.exit(2)
+    # substitutions by default in the weak-scaling study: at ~30-40 iterations
+    # the explicit inverses (twice the factorization's flops) do not pay
+    li = 0 if args.local_inverse is None else args.local_inverse
+    if args.weak_scaling:
+        # one process per N, as separate jobs would run: a process that has
+        # held the previous N's buffers would free and map them again
+        import subprocess
+        rows = []
+        for N in [int(a) for a in args.weak_scaling.split(",")]:
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--weak-scaling-one", str(N), "--steps",
+                                str(args.steps), "--warmup", str(args.warmup), "--local-inverse", str(li)],
+                               stdout=subprocess.PIPE, text=True)
+            if r.returncode != 0:
+                log(f"weak scaling N={N} failed with status {r.returncode}")
+                sys.exit(r.returncode)
+            rows.append(json.loads(r.stdout.strip().splitlines()[-1]))
+        out = weak_summary(rows, args.steps, args.warmup, li)
+        print(json.dumps(out), flush=True)
+        return
     import torch
 
     from workloads import make_config
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    if args.weak_scaling:
-        parts = [int(a) for a in args.weak_scaling.split(",")]
-        # substitutions by default: at ~30-40 iterations the explicit inverses
-        # (twice the factorization's flops) do not pay for themselves
-        li = 0 if args.local_inverse is None else args.local_inverse
-        print(json.dumps(weak_scaling(parts, args.steps, args.warmup, li)), flush=True)
+    if args.weak_scaling_one:
+        print(json.dumps(weak_scaling(args.weak_scaling_one, args.steps, args.warmup, li)), flush=True)
         return
     log("generating workload")
     prob = make_config(args.config, seed=0, scale=args.scale)

@@ -283,6 +283,12 @@ void tls_destroy(tls_ctx* c);
  * blocks in use by live contexts are not affected. */
 void tls_trim(void);
 
+/* Memory planning. tls_setup runs the local eigen passes and the formation
+ * of the explicit inverses on groups of subdomains whose buffers fit in 90%
+ * of the device memory still available (free memory plus the kept blocks);
+ * the results do not depend on the grouping. The environment variable
+ * TLS_MEMORY_LIMIT (bytes, read at each setup) lowers that figure. */
+
 #ifdef __cplusplus
 }
 #endif
