@@ -63,6 +63,8 @@ WORKLOADS = {
     3: "3D lognormal FV diffusion 128^3, 1024 RCB parts, overlap 1, nev 12",
     4: "3D layered Q1 elasticity 48^3 nodes, 512 boxes, overlap 1, nev 20",
     5: "2D upwind convection-diffusion 1024x1024, 256 boxes, overlap 2, nev 16 (Section 6 basis, LU)",
+    6: "2D Stokes lid-driven cavity, MAC 694x694 cells (1,443,520 unknowns, saddle point), 256 boxes, overlap 6, "
+       "nev 16 (Section 6 basis, LU)",
 }
 
 
@@ -334,8 +336,9 @@ def main():
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length")
     ap.add_argument("--local-inverse", type=int, default=None,
                     help="1: local solves through the explicit A_ii^{-1} (SPD only; default for SPD), 0: substitutions")
-    ap.add_argument("--composition", type=int, default=0,
-                    help="0: additive one-level + coarse (PCG for SPD); 1: RAS + deflated coarse correction (FGMRES)")
+    ap.add_argument("--composition", type=int, default=None,
+                    help="0: additive one-level + coarse (PCG for SPD); 1: RAS + deflated coarse correction (FGMRES); "
+                         "default 1 for the saddle-point config 6, else 0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -378,6 +381,8 @@ def main():
         return
     log("generating workload")
     prob = make_config(args.config, seed=0, scale=args.scale)
+    if args.composition is None:
+        args.composition = 1 if args.config == 6 else 0
     A = prob.A
     dev = torch.device("cuda:0")
     dev_in = (torch.as_tensor(A.indptr.astype(np.int32), device=dev),

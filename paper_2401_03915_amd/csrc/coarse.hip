@@ -103,7 +103,200 @@ __global__ void __launch_bounds__(256) k_restrict(const int* __restrict__ kz, co
   if (threadIdx.x == 0) y0[zcol[p] + a] = red[0] + red[1] + red[2] + red[3];
 }
 
+// ---------------------------------------------------------------------------
+// LU with partial pivoting of A_0 for general A. The coarse operator of an
+// indefinite or nonsymmetric A (for instance a saddle-point matrix) can
+// have arbitrarily small leading minors, so its rows are pivoted: P A_0 =
+// L U by right-looking panels of 64 columns on a dense column-major copy D
+// (leading dimension M0), then L and U go back into the tile storage with
+// the inverses of their diagonal tiles, and every coarse solve permutes its
+// right-hand side first.
+// ---------------------------------------------------------------------------
+__global__ void k_tiles_to_dense(int nt, int64_t M0, const double* __restrict__ tiles, double* D, int to_dense) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M0 * M0; x += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(x % M0), b = (int)(x / M0);
+    const int64_t t = ((int64_t)(a / TS) * nt + b / TS) * TS2 + (b % TS) * TS + a % TS;
+    if (to_dense)
+      D[x] = tiles[t];
+    else
+      const_cast<double*>(tiles)[t] = D[x];
+  }
+}
+
+// Columns [j0, j1) of D, rows [j0, n): pivot search, row interchange inside
+// the panel, multipliers and the rank-1 updates of the panel, one column
+// after the other; one workgroup.
+__global__ void __launch_bounds__(1024) k_lu_panel(int n, int64_t ld, int j0, int j1, double* D, int* piv, int* err) {
+  __shared__ double s_v[16];
+  __shared__ int s_i[16];
+  __shared__ int s_p;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = j0; j < j1; j++) {
+    double best = -1.0;
+    int bi = j;
+    for (int i = j + tid; i < n; i += 1024) {
+      const double v = fabs(D[i + j * ld]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_v[wave] = best;
+      s_i[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = s_v[0];
+      int p = s_i[0];
+      for (int w = 1; w < 16; w++)
+        if (s_v[w] > b || (s_v[w] == b && s_i[w] < p)) {
+          b = s_v[w];
+          p = s_i[w];
+        }
+      s_p = p;
+      piv[j] = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j && tid < j1 - j0) {
+      const int64_t c = (int64_t)(j0 + tid) * ld;
+      const double t = D[j + c];
+      D[j + c] = D[p + c];
+      D[p + c] = t;
+    }
+    __syncthreads();
+    double d = D[j + j * ld];
+    if (!(fabs(d) > 0.0) || !isfinite(d)) {
+      if (tid == 0) atomicOr(err, ERR_PIVOT);
+      d = 1.0;
+    }
+    const double inv = 1.0 / d;
+    for (int i = j + 1 + tid; i < n; i += 1024) {
+      const double l = D[i + j * ld] * inv;
+      D[i + j * ld] = l;
+      for (int c = j + 1; c < j1; c++) D[i + c * ld] -= l * D[j + c * ld];
+    }
+    __syncthreads();
+  }
+}
+
+// The panel's interchanges applied, in order, to every column outside it.
+__global__ void k_lu_swap_rest(int n, int64_t ld, int j0, int j1, const int* __restrict__ piv, double* D) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n || (col >= j0 && col < j1)) return;
+  double* Dc = D + (int64_t)col * ld;
+  for (int j = j0; j < j1; j++) {
+    const int p = piv[j];
+    if (p != j) {
+      const double t = Dc[j];
+      Dc[j] = Dc[p];
+      Dc[p] = t;
+    }
+  }
+}
+
+// U_12 = L_11^{-1} A_12 for the columns [j1, n) (L_11 unit lower, rows and
+// columns [j0, j1)); one thread per column.
+__global__ void k_lu_trsm_row(int n, int64_t ld, int j0, int j1, double* D) {
+  const int col = j1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n) return;
+  double* Dc = D + (int64_t)col * ld;
+  for (int r = j0 + 1; r < j1; r++) {
+    double acc = Dc[r];
+    for (int k = j0; k < r; k++) acc -= D[r + (int64_t)k * ld] * Dc[k];
+    Dc[r] = acc;
+  }
+}
+
+// Inverses of the diagonal tiles of the LU factor in the layout the
+// substitutions read: strictly below the diagonal the unit-lower L_kk^{-1},
+// on and above it U_kk^{-1}. One workgroup of 64 per tile.
+__global__ void __launch_bounds__(64) k_lu_tile_inverses(int nt, const double* __restrict__ tiles, double* dinv) {
+  constexpr int L1 = TS + 1;
+  __shared__ double Ls[TS * L1];
+  __shared__ double Xs[TS * L1];
+  const int k = blockIdx.x, j = threadIdx.x;
+  const double* t = tiles + ((int64_t)k * nt + k) * TS2;
+  for (int b = 0; b < TS; b++) Ls[j + b * L1] = t[b * TS + j];
+  __syncthreads();
+  double* out = dinv + (int64_t)k * TS2 + (int64_t)j * TS;
+  for (int r = 0; r < TS; r++) {
+    double v = (r == j) ? 1.0 : 0.0;
+    for (int l = 0; l < r; l++) v -= Ls[r + l * L1] * Xs[l * L1 + j];
+    Xs[r * L1 + j] = r < j ? 0.0 : v;
+    if (r > j) out[r] = v;
+  }
+  for (int r = TS - 1; r >= 0; r--) {
+    double v = (r == j) ? 1.0 : 0.0;
+    for (int l = r + 1; l < TS; l++) v -= Ls[r + l * L1] * Xs[l * L1 + j];
+    v = r > j ? 0.0 : v / Ls[r + r * L1];
+    Xs[r * L1 + j] = v;
+    if (r <= j) out[r] = v;
+  }
+}
+
+// dst[i] = src[perm[i]] (skipped once the Krylov loop has converged)
+__global__ void k_permute(int n, const int* __restrict__ perm, const double* __restrict__ src, double* dst,
+                          const int* __restrict__ done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
+__global__ void k_copy_vec(int n, const double* __restrict__ src, double* dst, const int* __restrict__ done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 }  // namespace
+
+// P A_0 = L U (see the kernels above); A_0's tiles are overwritten by L and
+// U, dinv0 receives the inverses of the diagonal tiles, perm0 the row order.
+static void factor_coarse_lu_pivoted(tls_ctx* c) {
+  hipStream_t s = c->stream;
+  const int n = c->M0, nt = c->nt0;
+  const int64_t ld = n;
+  DBuf<double> D;
+  DBuf<int> piv;
+  D.alloc((size_t)n * n);
+  piv.alloc(n);
+  hipLaunchKernelGGL(k_tiles_to_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 1);
+  TLS_LAUNCH_CHECK();
+  for (int j0 = 0; j0 < n; j0 += TS) {
+    const int j1 = std::min(j0 + TS, n);
+    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, n, ld, j0, j1, D.p, piv.p, c->errflag.p);
+    hipLaunchKernelGGL(k_lu_swap_rest, dim3(div_up(n, 256)), dim3(256), 0, s, n, ld, j0, j1, piv.p, D.p);
+    TLS_LAUNCH_CHECK();
+    if (j1 < n) {
+      hipLaunchKernelGGL(k_lu_trsm_row, dim3(div_up(n - j1, 256)), dim3(256), 0, s, n, ld, j0, j1, D.p);
+      TLS_LAUNCH_CHECK();
+      std::vector<GemmDesc> gd{GemmDesc{n - j1, n - j1, j1 - j0, n, n, j1 + (int64_t)j0 * ld, j0 + (int64_t)j1 * ld,
+                                        j1 + (int64_t)j1 * ld, ld}};
+      batched_gemm<double>(s, gd, false, false, D.p, D.p, D.p, -1.0, 1.0);
+    }
+  }
+  hipLaunchKernelGGL(k_tiles_to_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 0);
+  hipLaunchKernelGGL(k_lu_tile_inverses, dim3(nt), dim3(64), 0, s, nt, c->A0.p, c->dinv0.p);
+  TLS_LAUNCH_CHECK();
+  // the interchanges in order give the row order of P
+  const std::vector<int> hp = download(piv.p, n, s);
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; i++) perm[i] = i;
+  for (int j = 0; j < n; j++) std::swap(perm[j], perm[hp[j]]);
+  c->perm0.upload(perm, s);
+  c->y0t.alloc(n);
+  TLS_HIP(hipStreamSynchronize(s));
+}
 
 void build_coarse_operator(tls_ctx* c) {
   hipStream_t s = c->stream;
@@ -195,7 +388,7 @@ void build_coarse_operator(tls_ctx* c) {
   if (c->kind == 0)
     factor_tiles_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->dinv0.p, c->errflag.p);
   else
-    factor_tiles_lu_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->dinv0.p, c->errflag.p);
+    factor_coarse_lu_pivoted(c);
   if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) {
     if (c->kind == 0) fail(TLS_E_NOT_SPD, "coarse operator Z^T A Z is not positive definite");
     fail(TLS_E_SINGULAR, "zero pivot in the LU factorization of the coarse operator Z^T A Z");
@@ -231,6 +424,13 @@ void coarse_solve(tls_ctx* c, const int* done) {
   if (c->inv0_formed) {
     symv_solve_f64(s, c->inv0_work, c->A0.p, c->y0.p, done);
     return;
+  }
+  if (c->kind == 1) {
+    // y0 <- P y0 before L U y = P r
+    hipLaunchKernelGGL(k_permute, dim3(div_up(c->M0, 256)), dim3(256), 0, s, c->M0, c->perm0.p, c->y0.p, c->y0t.p,
+                       done);
+    hipLaunchKernelGGL(k_copy_vec, dim3(div_up(c->M0, 256)), dim3(256), 0, s, c->M0, c->y0t.p, c->y0.p, done);
+    TLS_LAUNCH_CHECK();
   }
   solve_begin(s, c->counters0.p, done);
   const int grid = std::min(c->plan0_fwd.ntasks, 512);

@@ -80,6 +80,8 @@ struct tls_ctx {
   tls::DBuf<double> A0;     // tile storage of A_0 (then its factor)
   tls::DBuf<double> A0_orig;  // lower tiles of A_0 before factorization (export)
   tls::DBuf<double> dinv0;    // inverses of the diagonal tiles of the factor of A_0
+  tls::DBuf<int> perm0;       // general A: row order of the pivoted LU of A_0 (P r)[i] = r[perm0[i]]
+  tls::DBuf<double> y0t;      // general A: the permuted coarse right-hand side
   tls::DBuf<int> kz_dev;    // coarse columns per subdomain
   tls::DBuf<double> y0;     // coarse vector (padded to M0)
   tls::DBuf<double> ras_t;  // composition 1: Q r (n)

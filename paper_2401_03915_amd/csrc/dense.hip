@@ -1832,11 +1832,6 @@ void factor_local(tls_ctx* c) {
   TLS_HIP(hipStreamSynchronize(c->stream));
 }
 
-void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
-                         double* dinv, int* err) {
-  factor_tiles_lu<double>(s, N, nt, lay, fac, dinv, err);
-}
-
 void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::vector<int64_t>& toff, int order,
                 hipStream_t s) {
   // A task is one block row; row r of subdomain i has "position" r (forward)

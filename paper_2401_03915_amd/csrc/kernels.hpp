@@ -42,8 +42,6 @@ void local_bsolve_interior(tls_ctx* c, float* X, const std::vector<int>& nq, con
                            int64_t ldx);
 void local_bsolve_interior(tls_ctx* c, double* X, const std::vector<int>& nq, const std::vector<int64_t>& xoff,
                            int64_t ldx);
-void factor_tiles_lu_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
-                         double* dinv, int* err);
 // generic pieces reused for the coarse factor (always fp64)
 // (dinv: inverses of the diagonal tiles, one per tile row, written as it goes)
 void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay,

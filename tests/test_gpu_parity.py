@@ -659,6 +659,11 @@ def _ras_case(kind):
     if kind == "spd":
         p = make_config(1)
         return p.A, p.part, 1, 8, True
+    if kind == "saddle":
+        # symmetric indefinite: MAC Stokes cavity, 48 x 48 cells, 16 boxes
+        from workloads import stokes_cavity_2d
+        K, part, _ = stokes_cavity_2d(48, 4, 4)
+        return K, part, 4, 16, False
     A, part = _cd_problem(64, 4, seed=5)
     return A, part, 2, 6, False
 
@@ -666,7 +671,8 @@ def _ras_case(kind):
 @pytest.mark.parametrize("kind,precision,scale,inv,tol", [("spd", 0, 0, 0, 1e-10), ("spd", 0, 1, 0, 1e-10),
                                                          ("spd", 1, 0, 0, 5e-3), ("spd", 0, 0, 1, 1e-10),
                                                          ("spd", 1, 1, 1, 5e-3), ("general", 0, 0, 0, 1e-10),
-                                                         ("general", 1, 0, 0, 1e-4)])
+                                                         ("general", 1, 0, 0, 1e-4), ("saddle", 0, 0, 0, 1e-10),
+                                                         ("saddle", 1, 0, 0, 1e-4)])
 def test_ras_deflated_apply_with_imported_basis(kind, precision, scale, inv, tol):
     """z = Q r + M_RAS^{-1}(r - A Q r) with the library's own Z imported
     into the oracle, over several seeded r; for SPD also with the explicit
@@ -698,7 +704,7 @@ def test_ras_deflated_apply_with_imported_basis(kind, precision, scale, inv, tol
     pc.close()
 
 
-@pytest.mark.parametrize("kind", ["spd", "general"])
+@pytest.mark.parametrize("kind", ["spd", "general", "saddle"])
 def test_ras_one_level_and_single_subdomain(kind):
     """nev = 0 leaves plain RAS; N = 1 gives A^{-1} and one FGMRES step."""
     torch = torch_cuda()
@@ -721,7 +727,7 @@ def test_ras_one_level_and_single_subdomain(kind):
     pc.close()
 
 
-@pytest.mark.parametrize("kind", ["spd", "general"])
+@pytest.mark.parametrize("kind", ["spd", "general", "saddle"])
 def test_ras_deflated_fgmres_matches_oracle(kind):
     """FGMRES(30) with the composition converges like the oracle's (CGS2 on
     the GPU, MGS in the oracle), graph-captured and eager runs give the

@@ -24,6 +24,7 @@ from .problems import (  # noqa: F401
     poisson_2d,
     rcb_partition,
     rhs,
+    stokes_cavity_2d,
     weak_scaling_poisson_3d,
     worked_example_7x7,
 )

@@ -210,6 +210,79 @@ def convdiff_2d(m: int, rng: np.random.Generator, eps: float = 0.01,
 
 
 # --------------------------------------------------------------------------
+# 2D Stokes, lid-driven cavity (saddle point)
+# --------------------------------------------------------------------------
+
+def stokes_cavity_2d(m: int, px: int, py: int, eps: float = 1e-2) -> tuple[sp.csr_matrix, np.ndarray, np.ndarray]:
+    """Lid-driven cavity on the unit square with the staggered (MAC) finite
+    differences of -Lap u + grad p = 0, div u = 0 on m x m cells, h = 1/m,
+    in the symmetric saddle-point form
+
+        K = [[A, G], [G^T, -eps I]],
+
+    A the 5-point velocity Laplacians (1/h^2; the wall values enter through
+    ghost values, the walls normal to a component eliminate it), G the
+    pressure gradient (1/h) and G^T = -div; the small pressure block -eps I
+    (pressure stabilization) fixes the constant pressure mode and makes K
+    quasi-definite. Unknowns: u on the (m-1) x m interior vertical faces,
+    then v on the m x (m-1) interior horizontal faces, then p on the m^2
+    cells (velocities numbered first). b carries the moving lid (u = 1 on
+    y = 1). The partition is px x py boxes of cells; a face belongs to the
+    box of the cell to its left (u) or below (v).
+    Returns (K, part, b)."""
+    h = 1.0 / m
+    nu, nv, npr = (m - 1) * m, m * (m - 1), m * m
+    iu = lambda i, j: j * (m - 1) + i          # u face (i+1/2, j), i in [0, m-1)
+    iv = lambda i, j: nu + j * m + i           # v face (i, j+1/2), j in [0, m-1)
+    ip = lambda i, j: nu + nv + j * m + i      # cell (i, j)
+    rows, cols, vals = [], [], []
+    b = np.zeros(nu + nv + npr)
+    d = 1.0 / (h * h)
+    # u: neighbours along x are faces (the walls x = 0, 1 hold u = 0, no
+    # ghost); along y the walls y = 0, 1 use ghost values u_g = 2 u_w - u
+    I, J = np.meshgrid(np.arange(m - 1), np.arange(m), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    k = iu(I, J)
+    diag = np.full(k.size, 4.0 * d)
+    diag += np.where((J == 0) | (J == m - 1), d, 0.0)
+    rows.append(k); cols.append(k); vals.append(diag)
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        ok = (I + di >= 0) & (I + di < m - 1) & (J + dj >= 0) & (J + dj < m)
+        rows.append(k[ok]); cols.append(iu(I[ok] + di, J[ok] + dj)); vals.append(np.full(ok.sum(), -d))
+    b[iu(I[J == m - 1], J[J == m - 1])] += 2.0 * d * 1.0  # lid u_w = 1
+    # v: symmetric roles; all walls at rest
+    I, J = np.meshgrid(np.arange(m), np.arange(m - 1), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    k = iv(I, J)
+    diag = np.full(k.size, 4.0 * d)
+    diag += np.where((I == 0) | (I == m - 1), d, 0.0)
+    rows.append(k); cols.append(k); vals.append(diag)
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        ok = (I + di >= 0) & (I + di < m) & (J + dj >= 0) & (J + dj < m - 1)
+        rows.append(k[ok]); cols.append(iv(I[ok] + di, J[ok] + dj)); vals.append(np.full(ok.sum(), -d))
+    # gradient: (grad p)_u(i+1/2, j) = (p(i+1, j) - p(i, j)) / h, and v alike
+    I, J = np.meshgrid(np.arange(m - 1), np.arange(m), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    for src, sign in ((ip(I + 1, J), 1.0), (ip(I, J), -1.0)):
+        rows += [iu(I, J), src]; cols += [src, iu(I, J)]; vals += [np.full(I.size, sign / h)] * 2
+    I, J = np.meshgrid(np.arange(m), np.arange(m - 1), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    for src, sign in ((ip(I, J + 1), 1.0), (ip(I, J), -1.0)):
+        rows += [iv(I, J), src]; cols += [src, iv(I, J)]; vals += [np.full(I.size, sign / h)] * 2
+    kp = np.arange(npr) + nu + nv
+    rows.append(kp); cols.append(kp); vals.append(np.full(npr, -eps))
+    K = _finish(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), nu + nv + npr)
+    box = lambda i, j: (j * py // m) * px + (i * px // m)
+    I, J = np.meshgrid(np.arange(m - 1), np.arange(m), indexing="ij")
+    pu = np.empty(nu, dtype=np.int32); pu[iu(I.ravel(), J.ravel())] = box(I.ravel(), J.ravel())
+    I, J = np.meshgrid(np.arange(m), np.arange(m - 1), indexing="ij")
+    pv = np.empty(nv, dtype=np.int32); pv[iv(I.ravel(), J.ravel()) - nu] = box(I.ravel(), J.ravel())
+    I, J = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    pp = np.empty(npr, dtype=np.int32); pp[ip(I.ravel(), J.ravel()) - nu - nv] = box(I.ravel(), J.ravel())
+    return K, np.concatenate([pu, pv, pp]).astype(np.int32), b
+
+
+# --------------------------------------------------------------------------
 # 3D linear elasticity, trilinear hexahedra
 # --------------------------------------------------------------------------
 
@@ -410,6 +483,8 @@ CONFIGS = {
     3: "3D lognormal FV diffusion 128^3, 1024 RCB parts, overlap 1, nev 12 (SPD, PCG)",
     4: "3D Q1 elasticity 48^3 nodes, 512 boxes, overlap 1, nev 20 (SPD, PCG)",
     5: "2D upwind convection-diffusion 1024x1024, 256 boxes, overlap 2, nev 16 (general, FGMRES(30))",
+    6: "2D Stokes lid-driven cavity, MAC 694x694 cells (1,443,520 unknowns), 256 boxes, overlap 6, nev 16 "
+       "(symmetric indefinite saddle point, general path, RAS + deflated, FGMRES(30))",
 }
 
 
@@ -432,7 +507,7 @@ def weak_scaling_poisson_3d(n_parts: int, seed: int = 0, per_part: float = 29791
 
 
 def make_config(cfg: int, seed: int = 0, scale: int | None = None) -> Problem:
-    """Build benchmark configuration ``cfg`` (1..5).
+    """Build benchmark configuration ``cfg`` (1..6).
 
     ``scale`` shrinks the grid side (and the partition accordingly) for tests
     while keeping the structure: e.g. ``make_config(2, scale=128)`` is a
@@ -473,4 +548,11 @@ def make_config(cfg: int, seed: int = 0, scale: int | None = None) -> Problem:
         part = box_partition_2d(m, m, p, p)
         return Problem("cfg5", A, part, p * p, 2, 16, rhs(A.shape[0], seed + 1000), False,
                        {"grid": (m, m)})
+    if cfg == 6:
+        # the paper's 2D lid-driven cavity has 1,444,003 Taylor-Hood unknowns;
+        # 694^2 MAC cells give 1,443,520. b is the lid (deterministic).
+        m = scale or 694
+        p = 16 if scale is None else max(2, m // 43)
+        K, part, b = stokes_cavity_2d(m, p, p)
+        return Problem("cfg6", K, part, p * p, 6, 16, b, False, {"grid": (m, m), "saddle_point": True})
     raise ValueError(f"unknown configuration {cfg}")
