@@ -86,7 +86,10 @@ typedef struct {
    *    coarse basis, A_0 and its factor stay FP64. */
   int32_t precision;
   /* 0: A is SPD: Cholesky, eq. gevpsvd (+ eq. uppergevp if nev1 > 0), PCG.
-   * 1: general A: LU without pivoting, Section 6 SVD variant, FGMRES.     */
+   * 1: general A: local LU without pivoting (nonzero pivots are needed:
+   *    e.g. M-matrices, or quasi-definite saddle points [[A, B^T], [B, -C]]
+   *    with A and C positive definite), LU with partial pivoting for A_0,
+   *    Section 6 SVD variant, FGMRES.                                     */
   int32_t matrix_kind;
   /* eq. uppergevp vectors kept per subdomain (those with lambda > nu),
    * SPD only (TLS_E_ARG with matrix_kind 1). The paper's SPD experiments
