@@ -336,6 +336,52 @@ def weak_summary(rows, steps, warmup, local_inverse):
     }
 
 
+def decay_study():
+    """Section 7, Fig. 1 at N = 256: the leading values of eq. gevpsvd
+    (lambda, for a 3D lognormal diffusion of 80^3 cells in 256 RCB parts)
+    and of the Section 6 variant (sigma, for the MAC Stokes cavity of
+    config 6, 256 boxes) for delta = 1, 3, 5, each normalized by the
+    subdomain's first value, for the subdomains 0, 64, 128 and 192 (the
+    paper plots subdomains 1, 65, 129 and 193, counted from 1). At most 40
+    values per subdomain are computed (the first 200 in the paper)."""
+    import torch
+
+    import paper_2401_03915_amd as tls
+    from workloads import fv_diffusion_3d, lognormal_kappa_3d, make_config, rcb_partition
+    rng = np.random.default_rng(0)
+    A3 = fv_diffusion_3d(lognormal_kappa_3d(80, rng))
+    part3 = rcb_partition((80, 80, 80), 8, rng, (0.45, 0.55))
+    st = make_config(6)
+    picks = (0, 64, 128, 192)
+    out = {}
+    for name, A, part, kind in (("diffusion_3d", A3, part3, 0), ("stokes_2d", st.A, st.part, 1)):
+        out[name] = {}
+        for delta in (1, 3, 5):
+            log(f"decay study: {name}, delta {delta}")
+            t0 = time.perf_counter()
+            pc = tls.Preconditioner(A, part, delta, 40, precision=1, matrix_kind=kind)
+            ex = pc.export()
+            torch.cuda.synchronize()
+            pc.close()
+            zc, ev = ex["zcol_ptr"], ex["eigvals"]
+            curves = {}
+            for i in picks:
+                v = np.asarray(ev[zc[i]:zc[i + 1]], dtype=np.float64)
+                v = np.sqrt(v) if kind == 0 else v  # lambda from lambda^2; sigma as is
+                curves[str(i)] = [float(f"{x:.4e}") for x in v / v[0]] if v.size else []
+            allv = [np.asarray(ev[zc[i]:zc[i + 1]]) for i in range(len(zc) - 1)]
+            norm = [np.sqrt(v / v[0]) if kind == 0 else v / v[0] for v in allv if v.size]
+            out[name][f"delta{delta}"] = {
+                "curves": curves,
+                "median_at": {str(j + 1): round(float(np.median([v[j] for v in norm if v.size > j])), 4)
+                              for j in (4, 9, 19, 39)},
+                "setup_s": round(time.perf_counter() - t0, 2)}
+    return {"metric": "decay of the eq. gevpsvd eigenvalues and Section 6 singular values vs overlap (Fig. 1 analog, "
+                      "N = 256)", "value": None, "unit": None, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "3D lognormal FV diffusion 80^3, 256 RCB parts; MAC Stokes cavity 694^2, 256 "
+                                   "boxes; delta 1, 3, 5; first 40 values"}, "decay": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +406,8 @@ def main():
                     help="comma-separated subdomain counts (powers of two): run the weak-scaling analog instead, "
                          "each count in a process of its own")
     ap.add_argument("--weak-scaling-one", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--decay", action="store_true",
+                    help="run the eigenvalue / singular value decay study against the overlap instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); multi-GPU runs are not part of "
@@ -390,6 +438,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.weak_scaling_one:
         print(json.dumps(weak_scaling(args.weak_scaling_one, args.steps, args.warmup, li)), flush=True)
+        return
+    if args.decay:
+        print(json.dumps(decay_study()), flush=True)
         return
     log("generating workload")
     prob = make_config(args.config, seed=0, scale=args.scale)
