@@ -112,14 +112,16 @@ __global__ void __launch_bounds__(256) k_restrict(const int* __restrict__ kz, co
 // the inverses of their diagonal tiles, and every coarse solve permutes its
 // right-hand side first.
 // ---------------------------------------------------------------------------
-__global__ void k_tiles_to_dense(int nt, int64_t M0, const double* __restrict__ tiles, double* D, int to_dense) {
+// Copy between the full tile storage (tile (r, c) at r nt + c) and the
+// dense column-major matrix: to_dense = 1 tiles -> D, 0 D -> tiles.
+__global__ void k_tiles_dense(int nt, int64_t M0, double* tiles, double* D, int to_dense) {
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M0 * M0; x += (int64_t)gridDim.x * blockDim.x) {
     const int a = (int)(x % M0), b = (int)(x / M0);
     const int64_t t = ((int64_t)(a / TS) * nt + b / TS) * TS2 + (b % TS) * TS + a % TS;
     if (to_dense)
       D[x] = tiles[t];
     else
-      const_cast<double*>(tiles)[t] = D[x];
+      tiles[t] = D[x];
   }
 }
 
@@ -270,7 +272,7 @@ static void factor_coarse_lu_pivoted(tls_ctx* c) {
   DBuf<int> piv;
   D.alloc((size_t)n * n);
   piv.alloc(n);
-  hipLaunchKernelGGL(k_tiles_to_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 1);
+  hipLaunchKernelGGL(k_tiles_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 1);
   TLS_LAUNCH_CHECK();
   for (int j0 = 0; j0 < n; j0 += TS) {
     const int j1 = std::min(j0 + TS, n);
@@ -285,7 +287,7 @@ static void factor_coarse_lu_pivoted(tls_ctx* c) {
       batched_gemm<double>(s, gd, false, false, D.p, D.p, D.p, -1.0, 1.0);
     }
   }
-  hipLaunchKernelGGL(k_tiles_to_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 0);
+  hipLaunchKernelGGL(k_tiles_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 0);
   hipLaunchKernelGGL(k_lu_tile_inverses, dim3(nt), dim3(64), 0, s, nt, c->A0.p, c->dinv0.p);
   TLS_LAUNCH_CHECK();
   // the interchanges in order give the row order of P
