@@ -410,8 +410,8 @@ def main():
                     help="run the eigenvalue / singular value decay study against the overlap instead")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); multi-GPU runs are not part of "
-              "this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     # substitutions by default in the weak-scaling study: at ~30-40 iterations
     # the explicit inverses (twice the factorization's flops) do not pay
