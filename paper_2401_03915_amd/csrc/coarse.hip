@@ -125,67 +125,102 @@ __global__ void k_tiles_dense(int nt, int64_t M0, double* tiles, double* D, int 
   }
 }
 
-// Columns [j0, j1) of D, rows [j0, n): pivot search, row interchange inside
-// the panel, multipliers and the rank-1 updates of the panel, one column
-// after the other; one workgroup.
-__global__ void __launch_bounds__(1024) k_lu_panel(int n, int64_t ld, int j0, int j1, double* D, int* piv, int* err) {
-  __shared__ double s_v[16];
-  __shared__ int s_i[16];
+// Columns [j0, j1) of D, rows [j0, n), one workgroup: in groups of 8
+// columns, each column's pivot search, the row interchange across the whole
+// panel, the multipliers and the update of the rest of its group; then the
+// group's rows of the later panel columns (unit-lower solve) and the rank-8
+// update of the rows below.
+constexpr int LU_PANEL_THREADS = 1024;
+constexpr int LU_GROUP = 8;
+
+__global__ void __launch_bounds__(LU_PANEL_THREADS) k_lu_panel(int n, int64_t ld, int j0, int j1, double* D, int* piv,
+                                                               int* err) {
+  constexpr int NW = LU_PANEL_THREADS / 64;
+  __shared__ double s_v[NW];
+  __shared__ int s_i[NW];
   __shared__ int s_p;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = j0; j < j1; j++) {
-    double best = -1.0;
-    int bi = j;
-    for (int i = j + tid; i < n; i += 1024) {
-      const double v = fabs(D[i + j * ld]);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o);
-      const int oi = __shfl_xor(bi, o);
-      if (ov > best || (ov == best && oi < bi)) {
-        best = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      s_v[wave] = best;
-      s_i[wave] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double b = s_v[0];
-      int p = s_i[0];
-      for (int w = 1; w < 16; w++)
-        if (s_v[w] > b || (s_v[w] == b && s_i[w] < p)) {
-          b = s_v[w];
-          p = s_i[w];
+  for (int c0 = j0; c0 < j1; c0 += LU_GROUP) {
+    const int c1 = min(c0 + LU_GROUP, j1);
+    for (int j = c0; j < c1; j++) {
+      double best = -1.0;
+      int bi = j;
+      for (int i = j + tid; i < n; i += LU_PANEL_THREADS) {
+        const double v = fabs(D[i + j * ld]);
+        if (v > best) {
+          best = v;
+          bi = i;
         }
-      s_p = p;
-      piv[j] = p;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_v[wave] = best;
+        s_i[wave] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double bv = s_v[0];
+        int p = s_i[0];
+        for (int w = 1; w < NW; w++)
+          if (s_v[w] > bv || (s_v[w] == bv && s_i[w] < p)) {
+            bv = s_v[w];
+            p = s_i[w];
+          }
+        s_p = p;
+        piv[j] = p;
+      }
+      __syncthreads();
+      const int p = s_p;
+      if (p != j && tid < j1 - j0) {
+        const int64_t c = (int64_t)(j0 + tid) * ld;
+        const double t = D[j + c];
+        D[j + c] = D[p + c];
+        D[p + c] = t;
+      }
+      __syncthreads();
+      double d = D[j + j * ld];
+      if (!(fabs(d) > 0.0) || !isfinite(d)) {
+        if (tid == 0) atomicOr(err, ERR_PIVOT);
+        d = 1.0;
+      }
+      const double inv = 1.0 / d;
+      for (int i = j + 1 + tid; i < n; i += LU_PANEL_THREADS) {
+        const double l = D[i + j * ld] * inv;
+        D[i + j * ld] = l;
+        for (int c = j + 1; c < c1; c++) D[i + c * ld] -= l * D[j + c * ld];
+      }
+      __syncthreads();
+    }
+    if (c1 >= j1) break;
+    // rows [c0, c1) of the columns [c1, j1): unit-lower solve with the group's L
+    if (tid < j1 - c1) {
+      double* Dc = D + (int64_t)(c1 + tid) * ld;
+      for (int r = c0 + 1; r < c1; r++) {
+        double acc = Dc[r];
+        for (int k = c0; k < r; k++) acc -= D[r + (int64_t)k * ld] * Dc[k];
+        Dc[r] = acc;
+      }
     }
     __syncthreads();
-    const int p = s_p;
-    if (p != j && tid < j1 - j0) {
-      const int64_t c = (int64_t)(j0 + tid) * ld;
-      const double t = D[j + c];
-      D[j + c] = D[p + c];
-      D[p + c] = t;
-    }
-    __syncthreads();
-    double d = D[j + j * ld];
-    if (!(fabs(d) > 0.0) || !isfinite(d)) {
-      if (tid == 0) atomicOr(err, ERR_PIVOT);
-      d = 1.0;
-    }
-    const double inv = 1.0 / d;
-    for (int i = j + 1 + tid; i < n; i += 1024) {
-      const double l = D[i + j * ld] * inv;
-      D[i + j * ld] = l;
-      for (int c = j + 1; c < j1; c++) D[i + c * ld] -= l * D[j + c * ld];
+    // rows [c1, n) of the columns [c1, j1): minus L_(rows, group) U_(group, cols)
+    for (int i = c1 + tid; i < n; i += LU_PANEL_THREADS) {
+      double l[LU_GROUP];
+#pragma unroll
+      for (int k = 0; k < LU_GROUP; k++) l[k] = c0 + k < c1 ? D[i + (int64_t)(c0 + k) * ld] : 0.0;
+      for (int c = c1; c < j1; c++) {
+        double acc = D[i + (int64_t)c * ld];
+#pragma unroll
+        for (int k = 0; k < LU_GROUP; k++)
+          if (c0 + k < c1) acc -= l[k] * D[c0 + k + (int64_t)c * ld];
+        D[i + (int64_t)c * ld] = acc;
+      }
     }
     __syncthreads();
   }
@@ -207,16 +242,28 @@ __global__ void k_lu_swap_rest(int n, int64_t ld, int j0, int j1, const int* __r
 }
 
 // U_12 = L_11^{-1} A_12 for the columns [j1, n) (L_11 unit lower, rows and
-// columns [j0, j1)); one thread per column.
-__global__ void k_lu_trsm_row(int n, int64_t ld, int j0, int j1, double* D) {
-  const int col = j1 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= n) return;
-  double* Dc = D + (int64_t)col * ld;
-  for (int r = j0 + 1; r < j1; r++) {
-    double acc = Dc[r];
-    for (int k = j0; k < r; k++) acc -= D[r + (int64_t)k * ld] * Dc[k];
-    Dc[r] = acc;
+// columns [j0, j1), j1 - j0 <= 64): one workgroup of 64 per 64 columns, the
+// blocks staged in LDS, thread t solving column t.
+__global__ void __launch_bounds__(64) k_lu_trsm_row(int n, int64_t ld, int j0, int j1, double* D) {
+  constexpr int P = TS + 1;
+  __shared__ double Ls[TS * P];
+  __shared__ double Xs[TS * P];
+  const int w = j1 - j0, t = threadIdx.x;
+  const int cb = j1 + blockIdx.x * TS;
+  const int nc = min(TS, n - cb);
+  for (int c = 0; c < w; c++) Ls[t + c * P] = t < w ? D[j0 + t + (int64_t)(j0 + c) * ld] : 0.0;
+  for (int c = 0; c < nc; c++) Xs[t + c * P] = t < w ? D[j0 + t + (int64_t)(cb + c) * ld] : 0.0;
+  __syncthreads();
+  if (t < nc) {
+    for (int r = 1; r < w; r++) {
+      double acc = Xs[r + t * P];
+      for (int k = 0; k < r; k++) acc -= Ls[r + k * P] * Xs[k + t * P];
+      Xs[r + t * P] = acc;
+    }
   }
+  __syncthreads();
+  for (int c = 0; c < nc; c++)
+    if (t < w) D[j0 + t + (int64_t)(cb + c) * ld] = Xs[t + c * P];
 }
 
 // Inverses of the diagonal tiles of the LU factor in the layout the
@@ -276,11 +323,11 @@ static void factor_coarse_lu_pivoted(tls_ctx* c) {
   TLS_LAUNCH_CHECK();
   for (int j0 = 0; j0 < n; j0 += TS) {
     const int j1 = std::min(j0 + TS, n);
-    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, n, ld, j0, j1, D.p, piv.p, c->errflag.p);
+    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(LU_PANEL_THREADS), 0, s, n, ld, j0, j1, D.p, piv.p, c->errflag.p);
     hipLaunchKernelGGL(k_lu_swap_rest, dim3(div_up(n, 256)), dim3(256), 0, s, n, ld, j0, j1, piv.p, D.p);
     TLS_LAUNCH_CHECK();
     if (j1 < n) {
-      hipLaunchKernelGGL(k_lu_trsm_row, dim3(div_up(n - j1, 256)), dim3(256), 0, s, n, ld, j0, j1, D.p);
+      hipLaunchKernelGGL(k_lu_trsm_row, dim3(div_up(n - j1, TS)), dim3(64), 0, s, n, ld, j0, j1, D.p);
       TLS_LAUNCH_CHECK();
       std::vector<GemmDesc> gd{GemmDesc{n - j1, n - j1, j1 - j0, n, n, j1 + (int64_t)j0 * ld, j0 + (int64_t)j1 * ld,
                                         j1 + (int64_t)j1 * ld, ld}};
