@@ -226,6 +226,157 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS) k_lu_panel(int n, int64_t ld
   }
 }
 
+// The same panel factorization with the group's columns held in registers
+// (rows c0 + t + 1024 q, q < R, by thread t) for n - j0 <= 1024 R, R <= 4 (no
+// spills at 1024 threads per workgroup): the pivot
+// search, the row interchange and the updates inside the group then cost no
+// global-memory round trips. Same operations in the same order as
+// k_lu_panel.
+template <int R>
+__global__ void __launch_bounds__(LU_PANEL_THREADS) k_lu_panel_reg(int n, int64_t ld, int j0, int j1, double* D,
+                                                                   int* piv, int* err) {
+  constexpr int NT = LU_PANEL_THREADS, NW = NT / 64, G = LU_GROUP;
+  __shared__ double s_v[NW];
+  __shared__ int s_i[NW];
+  __shared__ int s_p;
+  __shared__ double s_rj[G], s_rp[G];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int c0 = j0; c0 < j1; c0 += G) {
+    const int c1 = min(c0 + G, j1), g = c1 - c0;
+    double x[R][G];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const int r = c0 + tid + NT * q;
+#pragma unroll
+      for (int k = 0; k < G; k++) x[q][k] = (r < n && k < g) ? D[r + (int64_t)(c0 + k) * ld] : 0.0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < G; jj++) {
+      if (jj >= g) break;
+      const int j = c0 + jj;
+      double best = -1.0;
+      int bi = j;
+#pragma unroll
+      for (int q = 0; q < R; q++) {
+        const int r = c0 + tid + NT * q;
+        const double v = fabs(x[q][jj]);
+        if (r >= j && r < n && v > best) {
+          best = v;
+          bi = r;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_v[wave] = best;
+        s_i[wave] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double bv = s_v[0];
+        int p = s_i[0];
+        for (int w = 1; w < NW; w++)
+          if (s_v[w] > bv || (s_v[w] == bv && s_i[w] < p)) {
+            bv = s_v[w];
+            p = s_i[w];
+          }
+        s_p = p;
+        piv[j] = p;
+      }
+      __syncthreads();
+      const int p = s_p;
+      // the owners of rows j and p publish their group rows
+#pragma unroll
+      for (int q = 0; q < R; q++) {
+        const int r = c0 + tid + NT * q;
+        if (r == j)
+#pragma unroll
+          for (int k = 0; k < G; k++) s_rj[k] = x[q][k];
+        if (r == p)
+#pragma unroll
+          for (int k = 0; k < G; k++) s_rp[k] = x[q][k];
+      }
+      // the interchange in the panel columns outside the group (global)
+      if (p != j && tid < j1 - j0 && (j0 + tid < c0 || j0 + tid >= c1)) {
+        const int64_t c = (int64_t)(j0 + tid) * ld;
+        const double t = D[j + c];
+        D[j + c] = D[p + c];
+        D[p + c] = t;
+      }
+      __syncthreads();
+      // new row j = old row p, new row p = old row j
+#pragma unroll
+      for (int q = 0; q < R; q++) {
+        const int r = c0 + tid + NT * q;
+        if (r == j)
+#pragma unroll
+          for (int k = 0; k < G; k++) x[q][k] = s_rp[k];
+        if (r == p && p != j)
+#pragma unroll
+          for (int k = 0; k < G; k++) x[q][k] = s_rj[k];
+      }
+      double d = s_rp[jj];
+      if (!(fabs(d) > 0.0) || !isfinite(d)) {
+        if (tid == 0) atomicOr(err, ERR_PIVOT);
+        d = 1.0;
+      }
+      const double inv = 1.0 / d;
+#pragma unroll
+      for (int q = 0; q < R; q++) {
+        const int r = c0 + tid + NT * q;
+        if (r > j && r < n) {
+          const double l = x[q][jj] * inv;
+          x[q][jj] = l;
+#pragma unroll
+          for (int k = jj + 1; k < G; k++)
+            if (k < g) x[q][k] -= l * s_rp[k];
+        }
+      }
+      __syncthreads();  // s_rj / s_rp are reused by the next column
+    }
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const int r = c0 + tid + NT * q;
+      if (r < n)
+#pragma unroll
+        for (int k = 0; k < G; k++)
+          if (k < g) D[r + (int64_t)(c0 + k) * ld] = x[q][k];
+    }
+    __syncthreads();
+    if (c1 >= j1) break;
+    // rows [c0, c1) of the columns [c1, j1): unit-lower solve with the group's L
+    if (tid < j1 - c1) {
+      double* Dc = D + (int64_t)(c1 + tid) * ld;
+      for (int r = c0 + 1; r < c1; r++) {
+        double acc = Dc[r];
+        for (int k = c0; k < r; k++) acc -= D[r + (int64_t)k * ld] * Dc[k];
+        Dc[r] = acc;
+      }
+    }
+    __syncthreads();
+    // rows [c1, n) of the columns [c1, j1): minus L_(rows, group) U_(group, cols)
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const int i = c0 + tid + NT * q;
+      if (i >= c1 && i < n)
+        for (int c = c1; c < j1; c++) {
+          double acc = D[i + (int64_t)c * ld];
+#pragma unroll
+          for (int k = 0; k < G; k++)
+            if (c0 + k < c1) acc -= x[q][k] * D[c0 + k + (int64_t)c * ld];
+          D[i + (int64_t)c * ld] = acc;
+        }
+    }
+    __syncthreads();
+  }
+}
+
 // The panel's interchanges applied, in order, to every column outside it.
 __global__ void k_lu_swap_rest(int n, int64_t ld, int j0, int j1, const int* __restrict__ piv, double* D) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,19 +470,35 @@ static void factor_coarse_lu_pivoted(tls_ctx* c) {
   DBuf<int> piv;
   D.alloc((size_t)n * n);
   piv.alloc(n);
+  // the trailing-update descriptors of every panel, on the device before
+  // the loop, so that the panels run back to back without host waits
+  const int npan = div_up(n, TS);
+  std::vector<GemmPlan> plans(npan);
+  for (int k = 0; k + 1 < npan; k++) {
+    const int j0 = k * TS, j1 = j0 + TS;
+    gemm_plan(plans[k], {GemmDesc{n - j1, n - j1, j1 - j0, n, n, j1 + (int64_t)j0 * ld, j0 + (int64_t)j1 * ld,
+                                  j1 + (int64_t)j1 * ld, ld}},
+              s);
+  }
   hipLaunchKernelGGL(k_tiles_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 1);
   TLS_LAUNCH_CHECK();
-  for (int j0 = 0; j0 < n; j0 += TS) {
-    const int j1 = std::min(j0 + TS, n);
-    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(LU_PANEL_THREADS), 0, s, n, ld, j0, j1, D.p, piv.p, c->errflag.p);
+  for (int k = 0; k < npan; k++) {
+    const int j0 = k * TS, j1 = std::min(j0 + TS, n);
+    const int rows = n - j0;
+    if (rows <= 2 * LU_PANEL_THREADS)
+      hipLaunchKernelGGL(k_lu_panel_reg<2>, dim3(1), dim3(LU_PANEL_THREADS), 0, s, n, ld, j0, j1, D.p, piv.p,
+                         c->errflag.p);
+    else if (rows <= 4 * LU_PANEL_THREADS)
+      hipLaunchKernelGGL(k_lu_panel_reg<4>, dim3(1), dim3(LU_PANEL_THREADS), 0, s, n, ld, j0, j1, D.p, piv.p,
+                         c->errflag.p);
+    else  // more rows than 4 per thread would not fit the registers of a 1024-thread workgroup
+      hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(LU_PANEL_THREADS), 0, s, n, ld, j0, j1, D.p, piv.p, c->errflag.p);
     hipLaunchKernelGGL(k_lu_swap_rest, dim3(div_up(n, 256)), dim3(256), 0, s, n, ld, j0, j1, piv.p, D.p);
     TLS_LAUNCH_CHECK();
     if (j1 < n) {
       hipLaunchKernelGGL(k_lu_trsm_row, dim3(div_up(n - j1, TS)), dim3(64), 0, s, n, ld, j0, j1, D.p);
       TLS_LAUNCH_CHECK();
-      std::vector<GemmDesc> gd{GemmDesc{n - j1, n - j1, j1 - j0, n, n, j1 + (int64_t)j0 * ld, j0 + (int64_t)j1 * ld,
-                                        j1 + (int64_t)j1 * ld, ld}};
-      batched_gemm<double>(s, gd, false, false, D.p, D.p, D.p, -1.0, 1.0);
+      gemm_run<double>(s, plans[k], false, false, D.p, D.p, D.p, -1.0, 1.0);
     }
   }
   hipLaunchKernelGGL(k_tiles_dense, dim3(2048), dim3(256), 0, s, nt, (int64_t)n, c->A0.p, D.p, 0);
