@@ -111,6 +111,7 @@ struct tls_ctx {
   tls::DBuf<double> kr;        // vectors
   tls::DBuf<double> scal;      // device scalars
   tls::DBuf<double> partial;   // reduction partials
+  tls::DBuf<unsigned> redctr;  // blocks done in the current one-launch reduction (0 between launches)
   tls::DBuf<int> done;         // [0]: converged flag, [1]: iterations
   tls::DBuf<double> hist;      // residual history
   std::vector<double> h_hist;

@@ -45,28 +45,64 @@ __device__ inline void block_reduce_store(double v, double* out) {
   if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void __launch_bounds__(256) k_dot_partial(int n, const double* __restrict__ a, const double* __restrict__ b,
-                                                     double* partial, const int* __restrict__ done) {
-  if (*done) return;
-  double s = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) s += a[i] * b[i];
-  block_reduce_store(s, partial + blockIdx.x);
+// Dot products in one launch of RED_BLOCKS blocks: each block stores its
+// partial sum; the last block to finish (counted in *ctr, which it resets)
+// adds the partials in index order and stores the result, so the value
+// does not depend on the order in which the blocks ran.
+__device__ inline bool last_block(unsigned* ctr) {
+  __shared__ bool s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // this block's partial is visible before it is counted
+    s_last = atomicAdd(ctr, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();  // every counted partial is visible to the last block
+    if (threadIdx.x == 0) *ctr = 0u;
+  }
+  return s_last;
 }
 
-__global__ void __launch_bounds__(256) k_dot_final(const double* __restrict__ partial, double* out,
-                                                   const int* __restrict__ done) {
-  if (*done) return;
+__device__ inline void sum_partials(const double* partial, double* out) {
   double s = 0.0;
   for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += partial[i];
   block_reduce_store(s, out);
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; partial sums of r.r
+__global__ void __launch_bounds__(256) k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                             double* partial, unsigned* ctr, double* out,
+                                             const int* __restrict__ done) {
+  if (*done) return;
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) s += a[i] * b[i];
+  block_reduce_store(s, partial + blockIdx.x);
+  if (last_block(ctr)) sum_partials(partial, out);
+}
+
+// pq = p.q into scal[2]; a non-positive pq stops the iteration (breakdown)
+__global__ void __launch_bounds__(256) k_dot_pq(int n, const double* __restrict__ p, const double* __restrict__ q,
+                                                double* partial, unsigned* ctr, double* scal, int* done) {
+  if (done[0]) return;
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) s += p[i] * q[i];
+  block_reduce_store(s, partial + blockIdx.x);
+  if (last_block(ctr)) {
+    sum_partials(partial, scal + 2);
+    if (threadIdx.x == 0 && !(scal[2] > 0.0)) {
+      done[0] = 1;
+      done[3] = 1;
+    }
+  }
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; r.r into scal[3]; then the
+// last block records ||r||/||b|| and stops on the tolerance or the cap
 __global__ void __launch_bounds__(256) k_pcg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                     const double* __restrict__ p, const double* __restrict__ q,
-                                                    const double* __restrict__ scal, double* partial,
-                                                    const int* __restrict__ done) {
-  if (*done) return;
+                                                    double* scal, double* partial, unsigned* ctr, int* done,
+                                                    double* hist, int maxit, double tol2) {
+  if (done[0]) return;
   const double alpha = scal[1] / scal[2];
   double s = 0.0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) {
@@ -76,27 +112,19 @@ __global__ void __launch_bounds__(256) k_pcg_update(int n, double* __restrict__ 
     s += ri * ri;
   }
   block_reduce_store(s, partial + blockIdx.x);
-}
-
-__global__ void k_pq_check(const double* __restrict__ scal, int* done) {
-  if (done[0]) return;
-  if (!(scal[2] > 0.0)) {
-    done[0] = 1;
-    done[3] = 1;
-  }
-}
-
-// record ||r||/||b||, stop on tolerance or iteration cap
-__global__ void k_pcg_check(const double* __restrict__ scal, int* done, double* hist, int maxit, double tol2) {
-  if (done[0]) return;
-  int it = ++done[1];
-  double rr = scal[3], bb = scal[0];
-  hist[it - 1] = sqrt(rr / bb);
-  if (rr <= tol2 * bb) {
-    done[0] = 1;
-    done[2] = 1;
-  } else if (it >= maxit) {
-    done[0] = 1;
+  if (last_block(ctr)) {
+    sum_partials(partial, scal + 3);
+    if (threadIdx.x == 0) {
+      const int it = ++done[1];
+      const double rr = scal[3], bb = scal[0];
+      hist[it - 1] = sqrt(rr / bb);
+      if (rr <= tol2 * bb) {
+        done[0] = 1;
+        done[2] = 1;
+      } else if (it >= maxit) {
+        done[0] = 1;
+      }
+    }
   }
 }
 
@@ -123,8 +151,8 @@ __global__ void k_sub(int n, const double* __restrict__ b, const double* __restr
 }
 
 void dot(tls_ctx* c, const double* a, const double* b, double* out, const int* done) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->n, a, b, c->partial.p, done);
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c->stream, c->partial.p, out, done);
+  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->n, a, b, c->partial.p, c->redctr.p, out,
+                     done);
   TLS_LAUNCH_CHECK();
 }
 
@@ -144,12 +172,10 @@ void pcg_iteration(tls_ctx* c, const PcgVec& v, int maxit, double tol2, bool fle
   const int n = c->n;
   const int vg = std::min(4096, div_up(n, 256));
   spmv(c, v.p, v.q, done);
-  dot(c, v.p, v.q, c->scal.p + 2, done);
-  hipLaunchKernelGGL(k_pq_check, dim3(1), dim3(1), 0, s, c->scal.p, c->done.p);
+  hipLaunchKernelGGL(k_dot_pq, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.p, v.q, c->partial.p, c->redctr.p, c->scal.p,
+                     c->done.p);
   hipLaunchKernelGGL(k_pcg_update, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.x, v.r, v.p, v.q, c->scal.p, c->partial.p,
-                     done);
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, c->partial.p, c->scal.p + 3, done);
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1), 0, s, c->scal.p, c->done.p, c->hist.p, maxit, tol2);
+                     c->redctr.p, c->done.p, c->hist.p, maxit, tol2);
   TLS_LAUNCH_CHECK();
   if (flexible) hipLaunchKernelGGL(k_copy, dim3(vg), dim3(256), 0, s, n, v.z, v.zold, done);
   apply_precond(c, v.r, v.z, done);
@@ -363,6 +389,8 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   if (c->partial.n < RED_BLOCKS) c->partial.alloc(RED_BLOCKS);
   if (c->done.n < 4) c->done.alloc(4);
   if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
+  if (c->redctr.n < 1) c->redctr.alloc(1);
+  TLS_HIP(hipMemsetAsync(c->redctr.p, 0, sizeof(unsigned), s));  // outside any captured graph
   PcgVec v = vecs(c);
   const double tol2 = tol * tol;
   auto t0 = std::chrono::steady_clock::now();
@@ -482,6 +510,8 @@ void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   if (c->partial.n < (size_t)std::max(RED_BLOCKS, MD_BLOCKS * (m + 1))) c->partial.alloc(std::max(RED_BLOCKS, MD_BLOCKS * (m + 1)));
   if (c->done.n < 4) c->done.alloc(4);
   if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
+  if (c->redctr.n < 1) c->redctr.alloc(1);
+  TLS_HIP(hipMemsetAsync(c->redctr.p, 0, sizeof(unsigned), s));  // outside any captured graph
   DBuf<double> gmb;
   DBuf<int> gib;
   gmb.alloc(L.total);
