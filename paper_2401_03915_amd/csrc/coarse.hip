@@ -613,7 +613,9 @@ void build_coarse_operator(tls_ctx* c) {
     // explicit A_0^{-1}: the coarse solve becomes one streaming product
     // instead of two chains of nt0 dependent block rows
     form_inverse_f64(s, 1, one_nt, c->layout0(), c->A0.p, c->dinv0.p);
-    build_symv_work(c->inv0_work, s, 1, one_nt, std::vector<int64_t>{0}, std::vector<int64_t>{0}, false);
+    // blocks of 4 x 4 tiles: a single matrix needs more workgroups to
+    // stream at full rate next to the local products
+    build_symv_work(c->inv0_work, s, 1, one_nt, std::vector<int64_t>{0}, std::vector<int64_t>{0}, false, 4);
     c->inv0_formed = true;
   }
   build_plan(c->plan0_fwd, false, one_nt, toff, 1, s);

@@ -215,6 +215,7 @@ struct LocalLayout {
 struct SymvWork {
   DBuf<int4> blocks, rows;
   int64_t nblocks = 0, nrows = 0;
+  int block = 8;  // block side in tiles (8, or 4 for a single matrix that needs more workgroups)
   DBuf<float> RP32, CP32;
   DBuf<double> RP64, CP64;
 };

@@ -1529,14 +1529,15 @@ __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ 
 }
 
 // y_i = S_i x_i for every subdomain. The lower tiles are cut into blocks of
-// SYMV_B x SYMV_B tiles (block row R, block column C <= R); one workgroup
+// B x B tiles (block row R, block column C <= R; B = SYMV_B, or 4 for a
+// single matrix, which then has enough blocks to fill the GPU); one workgroup
 // streams one block row by row (the tiles of a row are consecutive in
 // storage). Thread t holds rows 4 (t % 16) + w and columns t / 16 + 16 u
 // (w, u = 0..3) of each tile (four 16-byte non-temporal loads). For each
 // tile row r of the block it writes the block's part of y_r; for each tile
 // column c it writes the sum of S_rc^T x_r over the block's tiles below the
 // diagonal (the terms of y_c that the upper triangle would hold). Partial
-// sums per block rather than per tile keep the writes to about 2 / SYMV_B of
+// sums per block rather than per tile keep the writes to about 2 / B of
 // a 64-value vector per tile: interleaved with the read stream, writes cost
 // far more than their size. k_symv_reduce adds the partial sums of each row
 // in a fixed order.
@@ -1544,7 +1545,7 @@ constexpr int SYMV_B = 8;
 
 // One block: subdomain factor at foff, x at voff; tile rows [r0, r1), tile
 // columns [c0, c1) (only c <= r is stored); its partial sums at
-// out * SYMV_B * TS in the row and column arrays.
+// out * B * TS in the row and column arrays.
 struct alignas(16) SymvBlock {
   int64_t foff, voff;
   int32_t r0, r1, c0, c1;
@@ -1601,22 +1602,22 @@ __device__ inline T reduce_scatter4_16(const T (&z)[4], int lane) {
   return v;
 }
 
-template <class T>
+template <class T, int B>
 __global__ void __launch_bounds__(256) k_symv(const SymvBlock* __restrict__ blocks, const T* __restrict__ S,
                                               const T* __restrict__ x, T* RP, T* CP,
                                               const int* __restrict__ done) {
   if (*done) return;
   __shared__ T red[4][TS];
-  __shared__ T rbuf[SYMV_B * TS];  // row partial sums of the block
-  __shared__ T cbuf[SYMV_B * TS];  // column partial sums of the block
+  __shared__ T rbuf[B * TS];  // row partial sums of the block
+  __shared__ T cbuf[B * TS];  // column partial sums of the block
   const SymvBlock bk = blocks[blockIdx.x];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int a0 = 4 * (tid & 15), b0 = tid >> 4;
   const T* Sb = S + bk.foff + 4 * tid;
   const T* xi = x + bk.voff;
-  T cacc[SYMV_B][4];
+  T cacc[B][4];
 #pragma unroll
-  for (int k = 0; k < SYMV_B; k++)
+  for (int k = 0; k < B; k++)
 #pragma unroll
     for (int u = 0; u < 4; u++) cacc[k][u] = T(0);
   for (int r = bk.r0; r < bk.r1; r++) {
@@ -1632,7 +1633,7 @@ __global__ void __launch_bounds__(256) k_symv(const SymvBlock* __restrict__ bloc
 #pragma unroll
     for (int u = 0; u < 4; u++) xn[u] = xi[bk.c0 * TS + b0 + 16 * u];
 #pragma unroll
-    for (int k = 0; k < SYMV_B; k++) {
+    for (int k = 0; k < B; k++) {
       const int c = bk.c0 + k;
       if (c < ce) {
         T v[4][4], xc[4];  // v[u][w] = S(a0 + w, b0 + 16 u) of tile (r, c)
@@ -1679,19 +1680,19 @@ __global__ void __launch_bounds__(256) k_symv(const SymvBlock* __restrict__ bloc
   // column sums: the 16 lanes holding column b0 + 16 u of a tile form one
   // DPP row
 #pragma unroll
-  for (int k = 0; k < SYMV_B; k++) {
+  for (int k = 0; k < B; k++) {
     const T zs = reduce_scatter4_16(cacc[k], tid);
     if ((tid & 3) == 0) cbuf[k * TS + b0 + 16 * ((tid & 15) >> 2)] = zs;
   }
   __syncthreads();
   const int nr = bk.r1 - bk.r0, nc = bk.c1 - bk.c0;
-  T* rp = RP + (int64_t)bk.out * SYMV_B * TS;
-  T* cp = CP + (int64_t)bk.out * SYMV_B * TS;
+  T* rp = RP + (int64_t)bk.out * B * TS;
+  T* cp = CP + (int64_t)bk.out * B * TS;
   for (int e = tid; e < nr * TS; e += 256) rp[e] = rbuf[e];
   for (int e = tid; e < nc * TS; e += 256) cp[e] = cbuf[e];
 }
 
-// y_r = sum over the blocks of block row R = r / SYMV_B of their row partial
+// y_r = sum over the blocks of block row R = r / B of their row partial
 // sum for r, plus sum over the blocks of block column R (block rows R' >= R)
 // of their column partial sum for r; fixed order, x overwritten. One
 // 64-thread workgroup per tile row; blk0 = first block of the subdomain.
@@ -1700,18 +1701,18 @@ struct alignas(16) SymvRow {
   int32_t r, nbr, blk0, pad_;
 };
 
-template <class T>
+template <class T, int B>
 __global__ void __launch_bounds__(64) k_symv_reduce(const SymvRow* __restrict__ rows, const T* __restrict__ RP,
                                                     const T* __restrict__ CP, T* x, const int* __restrict__ done) {
   if (*done) return;
   const SymvRow rw = rows[blockIdx.x];
   const int a = threadIdx.x;
-  const int R = rw.r / SYMV_B, rho = rw.r % SYMV_B;
+  const int R = rw.r / B, rho = rw.r % B;
   T s0 = T(0), s1 = T(0);
   for (int C = 0; C <= R; C++)
-    s0 += RP[((int64_t)(rw.blk0 + R * (R + 1) / 2 + C) * SYMV_B + rho) * TS + a];
+    s0 += RP[((int64_t)(rw.blk0 + R * (R + 1) / 2 + C) * B + rho) * TS + a];
   for (int Rp = R; Rp < rw.nbr; Rp++)
-    s1 += CP[((int64_t)(rw.blk0 + Rp * (Rp + 1) / 2 + R) * SYMV_B + rho) * TS + a];
+    s1 += CP[((int64_t)(rw.blk0 + Rp * (Rp + 1) / 2 + R) * B + rho) * TS + a];
   x[rw.voff + (int64_t)rw.r * TS + a] = s0 + s1;
 }
 
@@ -2106,35 +2107,38 @@ void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const 
 }
 
 // Work list of the symmetric product over N matrices (tile counts nt,
-// factor offsets foff, vector offsets voff): blocks of SYMV_B x SYMV_B
+// factor offsets foff, vector offsets voff): blocks of block x block
 // tiles, the largest matrices first, one reduction row per tile row.
 void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& nt,
-                     const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32) {
+                     const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32, int block) {
+  if (block != 4 && block != SYMV_B) fail(TLS_E_ARG, "symmetric-product blocks of 4 or 8 tiles");
+  const int SB = block;
+  w.block = block;
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
   std::vector<int> blk0(N, 0);
   int64_t nblk = 0;
   for (int i = 0; i < N; i++) {
-    const int64_t nbr = (nt[i] + SYMV_B - 1) / SYMV_B;
+    const int64_t nbr = (nt[i] + SB - 1) / SB;
     blk0[i] = (int)nblk;
     nblk += nbr * (nbr + 1) / 2;
   }
-  if (nblk > (int64_t)INT32_MAX / SYMV_B) fail(TLS_E_ARG, "too many tiles for the symmetric-product work list");
+  if (nblk > (int64_t)INT32_MAX / SB) fail(TLS_E_ARG, "too many tiles for the symmetric-product work list");
   std::vector<SymvBlock> blocks;
   std::vector<SymvRow> rows;
   blocks.reserve(nblk);
   for (int i : order) {
-    const int nbr = (nt[i] + SYMV_B - 1) / SYMV_B;
+    const int nbr = (nt[i] + SB - 1) / SB;
     for (int R = 0; R < nbr; R++)
       for (int C = 0; C <= R; C++) {
         SymvBlock bk;
         bk.foff = foff[i];
         bk.voff = voff[i];
-        bk.r0 = R * SYMV_B;
-        bk.r1 = std::min(nt[i], (R + 1) * SYMV_B);
-        bk.c0 = C * SYMV_B;
-        bk.c1 = std::min(nt[i], (C + 1) * SYMV_B);
+        bk.r0 = R * SB;
+        bk.r1 = std::min(nt[i], (R + 1) * SB);
+        bk.c0 = C * SB;
+        bk.c1 = std::min(nt[i], (C + 1) * SB);
         bk.out = blk0[i] + R * (R + 1) / 2 + C;
         bk.pad_ = 0;
         blocks.push_back(bk);
@@ -2145,7 +2149,7 @@ void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& 
       SymvRow rw;
       rw.voff = voff[i];
       rw.r = r;
-      rw.nbr = (nt[i] + SYMV_B - 1) / SYMV_B;
+      rw.nbr = (nt[i] + SB - 1) / SB;
       rw.blk0 = blk0[i];
       rw.pad_ = 0;
       rows.push_back(rw);
@@ -2157,7 +2161,7 @@ void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& 
   TLS_HIP(hipMemcpyAsync(w.blocks.p, blocks.data(), sizeof(SymvBlock) * blocks.size(), hipMemcpyHostToDevice, s));
   w.rows.alloc(rows.size() * 2);
   TLS_HIP(hipMemcpyAsync(w.rows.p, rows.data(), sizeof(SymvRow) * rows.size(), hipMemcpyHostToDevice, s));
-  const int64_t npart = std::max<int64_t>(nblk * SYMV_B * TS, 1);
+  const int64_t npart = std::max<int64_t>(nblk * SB * TS, 1);
   if (fp32) {
     w.RP32.alloc(npart);
     w.CP32.alloc(npart);
@@ -2188,13 +2192,15 @@ template <class T>
 void symv_solve_t(hipStream_t s, const SymvWork& w, const T* S, T* x, T* RP, T* CP, const int* done,
                   hipEvent_t ev_begin, hipEvent_t ev_mid, hipEvent_t ev_end) {
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
+  auto prod = w.block == 4 ? k_symv<T, 4> : k_symv<T, SYMV_B>;
+  auto reduce = w.block == 4 ? k_symv_reduce<T, 4> : k_symv_reduce<T, SYMV_B>;
   if (w.nblocks > 0)
-    hipLaunchKernelGGL(k_symv<T>, dim3((unsigned)w.nblocks), dim3(256), 0, s,
+    hipLaunchKernelGGL(prod, dim3((unsigned)w.nblocks), dim3(256), 0, s,
                        reinterpret_cast<const SymvBlock*>(w.blocks.p), S, x, RP, CP, done);
   TLS_LAUNCH_CHECK();
   if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
   if (w.nrows > 0)
-    hipLaunchKernelGGL(k_symv_reduce<T>, dim3((unsigned)w.nrows), dim3(64), 0, s,
+    hipLaunchKernelGGL(reduce, dim3((unsigned)w.nrows), dim3(64), 0, s,
                        reinterpret_cast<const SymvRow*>(w.rows.p), RP, CP, x, done);
   TLS_LAUNCH_CHECK();
   if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));

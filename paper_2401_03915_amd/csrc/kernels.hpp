@@ -28,7 +28,7 @@ void form_local_inverse(tls_ctx* c);
 void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,
                       const double* dinv);
 void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& nt,
-                     const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32);
+                     const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32, int block = 8);
 void symv_solve_f64(hipStream_t s, SymvWork& w, const double* S, double* x, const int* done);
 void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_mid = nullptr,
                  hipEvent_t ev_end = nullptr);
