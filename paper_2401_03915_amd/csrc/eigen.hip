@@ -102,19 +102,36 @@ __global__ void k_convert(int64_t count, const S* __restrict__ in, D* out) {
     out[x] = (D)in[x];
 }
 
-// C <- (X^T + X)/2 is not what we want; transpose square blocks in place:
-// out = in^T for each subdomain's nT x nT block.
-__global__ void k_transpose_blocks(const int* __restrict__ nT_, const int64_t* __restrict__ off,
-                                   const int* __restrict__ kreq, const double* in, double* out, int symmetrize) {
+// out = in^T (symmetrize = 0) or out = (in + in^T) / 2 (symmetrize = 1) for
+// each subdomain's nT x nT column-major block; 64 x 64 tiles staged through
+// LDS so that both the reads and the writes are contiguous.
+__global__ void __launch_bounds__(256) k_transpose_blocks(const int* __restrict__ nT_, const int64_t* __restrict__ off,
+                                                          const int* __restrict__ kreq, const double* in, double* out,
+                                                          int symmetrize) {
   const int i = blockIdx.y;
   if (kreq[i] <= 0) return;
   const int n = nT_[i];
+  const int nb = (n + TS - 1) / TS;
   const double* a = in + off[i];
   double* b = out + off[i];
-  const int64_t total = (int64_t)n * n;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-    int r = (int)(x % n), c = (int)(x / n);
-    b[x] = symmetrize ? 0.5 * (a[r + (int64_t)c * n] + a[c + (int64_t)r * n]) : a[c + (int64_t)r * n];
+  __shared__ double t[TS][TS + 1];
+  for (int tile = blockIdx.x; tile < nb * nb; tile += gridDim.x) {
+    const int tr = tile % nb, tc = tile / nb;  // output tile: rows tr, columns tc
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS2; e += 256) {
+      const int x = e % TS, y = e / TS;
+      const int r = tc * TS + x, c = tr * TS + y;  // t[y][x] = in(tc 64 + x, tr 64 + y)
+      t[y][x] = (r < n && c < n) ? a[r + (int64_t)c * n] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS2; e += 256) {
+      const int x = e % TS, y = e / TS;
+      const int r = tr * TS + x, c = tc * TS + y;
+      if (r < n && c < n) {
+        const double tv = t[x][y];  // in(c, r)
+        b[r + (int64_t)c * n] = symmetrize ? 0.5 * (a[r + (int64_t)c * n] + tv) : tv;
+      }
+    }
   }
 }
 
