@@ -315,29 +315,51 @@ void batched_trsm(hipStream_t s, const std::vector<TriDesc>& d, TriMode mode, co
   TLS_LAUNCH_CHECK();
   // inv and M are separate buffers: the GEMMs read the inverse blocks from
   // inv (A operand, offset into inv) and the off-diagonal blocks from M.
-  GemmPlan p1, p2;
+  // The block rows are taken in panels of PW: inside a panel each solved
+  // block updates only the panel's rows still to solve; when the panel is
+  // done, one GEMM with K = the panel's rows updates every row outside it,
+  // so the right-hand sides are read and written once per panel instead of
+  // once per block row.
+  constexpr int PW = 8;
+  GemmPlan p1, p2, p3;
   for (int step = 0; step < maxnb; step++) {
-    std::vector<GemmDesc> g1, g2;
+    std::vector<GemmDesc> g1, g2, g3;
     for (size_t q = 0; q < dd.size(); q++) {
       const TriDesc& t = dd[q];
       const int nb = (t.n + 63) / 64;
       if (step >= nb) continue;
       const int k = mode == LOWER_FWD ? step : nb - 1 - step;
       const int k0 = 64 * k, w = std::min(64, t.n - k0);
+      // rows of this step's panel: steps [ps0, ps1) of the solve order
+      const int ps0 = step / PW * PW, ps1 = std::min(ps0 + PW, nb);
+      const int pr0 = mode == LOWER_FWD ? 64 * ps0 : 64 * (nb - ps1);
+      const int pr1 = mode == LOWER_FWD ? std::min(t.n, 64 * ps1) : std::min(t.n, 64 * (nb - ps0));
       // X_k = inv(M_kk) B_k, written over B_k
       g1.push_back(GemmDesc{w, t.nrhs, w, 64, (int)t.ldb, (first[q] + k) * 4096, t.b_off + k0, t.b_off + k0, t.ldb});
-      // rows still to solve: below (forward) or above (backward) the block
-      const int r0 = mode == LOWER_FWD ? k0 + w : 0;
-      const int rn = mode == LOWER_FWD ? t.n - k0 - w : k0;
+      // the panel's rows still to solve: below (forward) or above (backward) the block
+      const int r0 = mode == LOWER_FWD ? k0 + w : pr0;
+      const int rn = mode == LOWER_FWD ? pr1 - k0 - w : k0 - pr0;
       if (rn > 0)
         g2.push_back(GemmDesc{rn, t.nrhs, w, t.n, (int)t.ldb, t.m_off + r0 + (int64_t)k0 * t.n, t.b_off + k0,
                               t.b_off + r0, t.ldb});
+      // the panel is solved: the rows after it in the solve order
+      if (step == ps1 - 1) {
+        const int o0 = mode == LOWER_FWD ? pr1 : 0;
+        const int on = mode == LOWER_FWD ? t.n - pr1 : pr0;
+        if (on > 0)
+          g3.push_back(GemmDesc{on, t.nrhs, pr1 - pr0, t.n, (int)t.ldb, t.m_off + o0 + (int64_t)pr0 * t.n,
+                                t.b_off + pr0, t.b_off + o0, t.ldb});
+      }
     }
     gemm_plan(p1, g1, s);
     gemm_run<T>(s, p1, false, false, inv.p, B, B, T(1), T(0));
     if (!g2.empty()) {
       gemm_plan(p2, g2, s);
       gemm_run<T>(s, p2, false, false, M, B, B, T(-1), T(1));
+    }
+    if (!g3.empty()) {
+      gemm_plan(p3, g3, s);
+      gemm_run<T>(s, p3, false, false, M, B, B, T(-1), T(1));
     }
   }
   TLS_HIP(hipStreamSynchronize(s));
