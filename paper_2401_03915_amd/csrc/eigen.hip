@@ -96,6 +96,36 @@ __global__ void k_extract(int mode, EigLayout e, const S* __restrict__ fac, D* o
   }
 }
 
+// F = -L_TI^T (nI x nT, column-major; SPD tile storage) as k_extract mode 0
+// does, through 64 x 64 chunks staged in LDS: the factor is read down its
+// columns (contiguous inside a tile) and F written down its columns.
+template <class T>
+__global__ void __launch_bounds__(256) k_extract_f(EigLayout e, const T* __restrict__ fac, T* out) {
+  const int i = blockIdx.y;
+  if (e.kreq[i] <= 0) return;
+  const int nI = e.nI[i], nT = e.nT[i], nt = e.nt[i];
+  const int nP = nI + e.nG[i];
+  const T* base = fac + e.foff[i];
+  T* F = out + e.o_F[i];
+  const int na = (nI + TS - 1) / TS, nbk = (nT + TS - 1) / TS;
+  __shared__ T t[TS][TS + 1];
+  for (int chunk = blockIdx.x; chunk < na * nbk; chunk += gridDim.x) {
+    const int A0 = (chunk % na) * TS, B0 = (chunk / na) * TS;
+    __syncthreads();
+    for (int x = threadIdx.x; x < TS2; x += 256) {
+      const int bb = x % TS, aa = x / TS;  // factor element (nP + B0 + bb, A0 + aa)
+      const int a = A0 + aa, b = B0 + bb;
+      t[aa][bb] = (a < nI && b < nT) ? -*elem_ptr(base, 0, nt, nP + b, a) : T(0);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < TS2; x += 256) {
+      const int aa = x % TS, bb = x / TS;
+      const int a = A0 + aa, b = B0 + bb;
+      if (a < nI && b < nT) F[a + (int64_t)b * nI] = t[aa][bb];
+    }
+  }
+}
+
 template <class S, class D>
 __global__ void k_convert(int64_t count, const S* __restrict__ in, D* out) {
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += (int64_t)gridDim.x * blockDim.x)
@@ -786,7 +816,7 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
   K.alloc(std::max<int64_t>(d.oTT[N], 1));
   F.alloc(std::max<int64_t>(d.oF[N], 1));
   LTT.alloc(std::max<int64_t>(d.oTT[N], 1));
-  hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 0, el, fac, F.p);
+  hipLaunchKernelGGL(k_extract_f<T>, eg, dim3(256), 0, s, el, fac, F.p);
   hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
   TLS_LAUNCH_CHECK();
   if (d.oGG[N] > 0) {
