@@ -8,7 +8,7 @@
  *
  *     M^{-1} r = sum_i R_i^T A_ii^{-1} R_i r + R_0^T A_00^{-1} R_0 r
  *
- * (Remark after Section 4.4; one-level part eq. onelevelasm), with the
+ * (Remark in Section 4.3; one-level part eq. onelevelasm), with the
  * coarse space of eq. coarse_space_2 for SPD A (dominant eigenvectors of
  * eq. gevpsvd, optionally of eq. uppergevp) or of Section 6 for general A
  * (dominant left singular vectors of D_i Pi_i), and applies it inside PCG or
@@ -149,6 +149,13 @@ typedef struct {
    * A_0 is inverted the same way, so the coarse solve is one product too.
    * 0 (default): forward and backward substitution with the factors. */
   int32_t local_inverse;
+  /* FP32 mode (precision 1) only: steps of iterative refinement after each
+   * local solve, in [0, 8]. A step forms the residual b_i - A_ii x_i in FP64
+   * from the sparse rows of A_ii, solves for the correction with the same
+   * FP32 factor (or explicit inverse) and adds it in FP64; each step costs
+   * one more pass over the local factors. 0 (default): none. Ignored in
+   * FP64 mode. */
+  int32_t local_refine;
   void* stream;         /* hipStream_t */
 } tls_options;
 
@@ -189,6 +196,11 @@ typedef struct {
   int32_t local_inverse;      /* 1 if the local solves use explicit inverses  */
   double t_inverse_ms;        /* setup ms spent forming them (inside t_setup[7]; the
                                  inverse of A_0 is inside t_setup[5]) */
+  int32_t wait_timeout;       /* 1 if a tls_apply since the previous tls_info or tls_solve
+                                 of this context ran a triangular-solve wait past its spin
+                                 limit (its z is not valid); reading it clears it. tls_info
+                                 waits for the context's stream to read it. */
+  int32_t local_refine;       /* refinement steps of each local solve (option local_refine) */
 } tls_info_t;
 
 /* Fill *opt with the defaults listed above. */
@@ -210,14 +222,23 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
                      const double* val, const int32_t* part, int32_t n_parts, int32_t overlap,
                      int32_t nev, const tls_options* opt, tls_ctx** out);
 
-/* z = M^{-1} r (device vectors of length n, r != z). Asynchronous. */
+/* z = M^{-1} r (device vectors of length n, r != z): the two-level operator
+ * M_2^{-1} of the Remark in Section 4.3 (one-level part eq. onelevelasm), or
+ * with composition = 1 the restricted one-level part of eq. onelevelras
+ * with the deflated coarse correction of Section 7.2. Asynchronous: errors
+ * that only the device sees (a wait past its spin limit) are reported by
+ * the next tls_info (wait_timeout) and do not fail later solves. */
 tls_status tls_apply(tls_ctx* c, const double* r, double* z);
 
 /* y = A x with the stored CSR copy (device vectors, x != y). Asynchronous. */
 tls_status tls_spmv(tls_ctx* c, const double* x, double* y);
 
-/* Solve A x = b from x0 = 0 with PCG (SPD) or FGMRES(restart) (general),
- * right preconditioned by M^{-1}, until ||b - A x|| / ||b|| <= tol.
+/* Solve A x = b (eq. Ax=b, Section 1) from x0 = 0 with PCG (SPD A, additive
+ * composition: Section 1 and its CG bound) or right-preconditioned flexible
+ * GMRES(restart) (general A or composition = 1: Section 7.2), until the
+ * true relative residual ||b - A x|| / ||b|| <= tol (Section 7.2 stops at
+ * 1e-8). PCG stops on its recurrence residual, then restarts from x (at most
+ * four times) while the true residual is above tol.
  * b, x: device vectors (b != x). iters, relres (true residual at exit) may
  * be NULL. Returns TLS_E_NOCONV with the last iterate if maxit is reached. */
 tls_status tls_solve(tls_ctx* c, const double* b, double* x, double tol, int32_t* iters,

@@ -14,7 +14,7 @@ It computes the paper's definitions literally, in float64, with NumPy/SciPy:
   Schwarz (Section 2.3), the harmonic operator (eq. HOp), the two local
   generalized eigenproblems (eq. uppergevp, eq. gevpsvd), the nonsymmetric
   variant (Section 6), the coarse space (eq. coarse_space_2), the Galerkin
-  coarse operator and the two-level apply (Remark after Section 4.4);
+  coarse operator and the two-level apply (Remark in Section 4.3);
 * ``krylov``   - PCG and right-preconditioned flexible GMRES;
 * ``gnn``      - forward, loss and backward of the warm-start network of
   the local eigensolver (not in the paper; see its docstring);

@@ -67,6 +67,7 @@ class tls_options(C.Structure):
         ("gnn_train", C.c_int32),
         ("composition", C.c_int32),
         ("local_inverse", C.c_int32),
+        ("local_refine", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -101,6 +102,8 @@ class tls_info_t(C.Structure):
         ("res_history", C.POINTER(C.c_double)),
         ("local_inverse", C.c_int32),
         ("t_inverse_ms", C.c_double),
+        ("wait_timeout", C.c_int32),
+        ("local_refine", C.c_int32),
     ]
 
 

@@ -63,6 +63,7 @@ void tls_default_options(tls_options* o) {
   o->gnn_train = 0;
   o->composition = 0;
   o->local_inverse = 0;
+  o->local_refine = 0;
   o->stream = nullptr;
 }
 
@@ -97,6 +98,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.local_inverse != 0 && c->opt.local_inverse != 1) tls::fail(TLS_E_ARG, "local_inverse must be 0 or 1");
     if (c->opt.local_inverse && c->opt.matrix_kind != 0)
       tls::fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
+    if (c->opt.local_refine < 0 || c->opt.local_refine > 8) tls::fail(TLS_E_ARG, "local_refine must be in [0, 8]");
     if (c->opt.gnn_weights || c->opt.gnn_train) {
       if (c->opt.matrix_kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");
       if (c->opt.gnn_weights) tls::gnn_check_weights(c->opt.gnn_c_out);
@@ -172,6 +174,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
       tls::form_local_inverse(c.get());
       c->t_inverse = ms_since(t);
     }
+    tls::build_refine(c.get());
     tls::choose_solve_grid(c.get());
     TLS_HIP(hipStreamSynchronize(s));
     c->t_setup[7] = ms_since(t_all);
@@ -260,6 +263,12 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->solve_wgs = c->solve_grid;
   info->solve_order = c->solve_order;
   info->tuned = c->tuned;
+  info->local_refine = c->refine;
+  tls_ctx* cm = const_cast<tls_ctx*>(c);
+  bool wt = cm->apply_wait_seen;
+  if (guard(cm, [&]() { wt = tls::take_wait_flag(cm) || wt; }) != TLS_OK) return TLS_E_HIP;
+  cm->apply_wait_seen = false;
+  info->wait_timeout = wt ? 1 : 0;
   return TLS_OK;
 }
 
@@ -367,9 +376,18 @@ tls_status tls_local_solve(tls_ctx* c, int32_t i, const double* b, double* x) {
       std::vector<float> hb(c->sum_M, 0.f);
       for (int j = 0; j < m; j++) hb[off + j] = (float)(b[j] * sc[j]);
       TLS_HIP(hipMemcpyAsync(c->xloc32.p, hb.data(), sizeof(float) * c->sum_M, hipMemcpyHostToDevice, s));
-      tls::local_solve(c, c->zero_int.p);
-      auto hx = tls::download(c->xloc32.p + off, m, s);
-      for (int j = 0; j < m; j++) x[j] = (double)hx[j] * sc[j];
+      if (c->refine > 0) {
+        std::vector<double> hb64(c->sum_M, 0.0);
+        for (int j = 0; j < m; j++) hb64[off + j] = b[j] * sc[j];
+        TLS_HIP(hipMemcpyAsync(c->bref64.p, hb64.data(), sizeof(double) * c->sum_M, hipMemcpyHostToDevice, s));
+      }
+      if (tls::local_solve_refined(c, c->zero_int.p)) {
+        auto hx = tls::download(c->xref64.p + off, m, s);
+        for (int j = 0; j < m; j++) x[j] = hx[j] * sc[j];
+      } else {
+        auto hx = tls::download(c->xloc32.p + off, m, s);
+        for (int j = 0; j < m; j++) x[j] = (double)hx[j] * sc[j];
+      }
     } else {
       std::vector<double> hb(c->sum_M, 0.0);
       for (int j = 0; j < m; j++) hb[off + j] = b[j] * sc[j];

@@ -1,6 +1,6 @@
 // The two-level preconditioner on the stream, Q = R_0^T A_00^{-1} R_0.
 //
-// Additive composition (Remark after Section 4.4):
+// Additive composition (Remark in Section 4.3, the operator M_2^{-1}):
 //   z = sum_i R_i^T A_ii^{-1} R_i r + Q r
 //   1. gather R_i r into the padded local vectors (cast to the local
 //      precision, Jacobi-scaled if enabled); R_0 r = Z^T r and the coarse
@@ -25,7 +25,7 @@ template <class T>
 __global__ void k_apply_gather(int total, const int* __restrict__ sub_idx, const int* __restrict__ sub_of_pos,
                                const int* __restrict__ sub_ptr, const int64_t* __restrict__ voff,
                                const double* __restrict__ scale, const double* __restrict__ r, T* xloc,
-                               const int* __restrict__ done) {
+                               double* b64, const int* __restrict__ done) {
   if (*done) return;
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= total) return;
@@ -34,6 +34,7 @@ __global__ void k_apply_gather(int total, const int* __restrict__ sub_idx, const
   double v = r[sub_idx[p]];
   if (scale) v *= scale[pos];
   xloc[pos] = (T)v;
+  if (b64) b64[pos] = v;  // FP64 right-hand side of the refinement steps
 }
 
 template <class T>
@@ -109,6 +110,7 @@ void apply_impl(tls_ctx* c, const double* r, double* z, const int* done, T* xloc
   }
   const int total = c->h_sub_ptr[c->N];
   const double* scale = c->opt.jacobi_scale ? c->scale.p : nullptr;
+  double* b64 = c->refine > 0 ? c->bref64.p : nullptr;
   if (c->opt.composition == 1) {
     const bool coarse = c->nC > 0;
     const double* rl = r;
@@ -122,16 +124,20 @@ void apply_impl(tls_ctx* c, const double* r, double* z, const int* done, T* xloc
       rl = c->ras_u.p;
     }
     hipLaunchKernelGGL(k_apply_gather<T>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
-                       c->sub_of_pos.p, c->sub_ptr.p, c->d_voff.p, scale, rl, xloc, done);
+                       c->sub_of_pos.p, c->sub_ptr.p, c->d_voff.p, scale, rl, xloc, b64, done);
     TLS_LAUNCH_CHECK();
-    local_solve(c, done, profile ? c->prof_ev[1] : nullptr, profile ? c->prof_ev[4] : nullptr,
-                profile ? c->prof_ev[2] : nullptr);
-    hipLaunchKernelGGL(k_apply_scatter_ras<T>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->part.p, c->ipos.p,
-                       c->d_voff.p, xloc, scale, coarse ? c->ras_t.p : nullptr, z, done);
+    const bool refined = local_solve_refined(c, done, profile ? c->prof_ev[1] : nullptr,
+                                             profile ? c->prof_ev[4] : nullptr, profile ? c->prof_ev[2] : nullptr);
+    if (refined)
+      hipLaunchKernelGGL(k_apply_scatter_ras<double>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->part.p,
+                         c->ipos.p, c->d_voff.p, c->xref64.p, scale, coarse ? c->ras_t.p : nullptr, z, done);
+    else
+      hipLaunchKernelGGL(k_apply_scatter_ras<T>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->part.p,
+                         c->ipos.p, c->d_voff.p, xloc, scale, coarse ? c->ras_t.p : nullptr, z, done);
     TLS_LAUNCH_CHECK();
   } else {
     hipLaunchKernelGGL(k_apply_gather<T>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
-                       c->sub_of_pos.p, c->sub_ptr.p, c->d_voff.p, scale, r, xloc, done);
+                       c->sub_of_pos.p, c->sub_ptr.p, c->d_voff.p, scale, r, xloc, b64, done);
     TLS_LAUNCH_CHECK();
     const bool coarse = c->nC > 0;
     if (coarse) {
@@ -146,12 +152,18 @@ void apply_impl(tls_ctx* c, const double* r, double* z, const int* done, T* xloc
       c->stream = keep;
       TLS_HIP(hipEventRecord(c->ev_join, c->stream2));
     }
-    local_solve(c, done, profile ? c->prof_ev[1] : nullptr, profile ? c->prof_ev[4] : nullptr,
-                profile ? c->prof_ev[2] : nullptr);
+    const bool refined = local_solve_refined(c, done, profile ? c->prof_ev[1] : nullptr,
+                                             profile ? c->prof_ev[4] : nullptr, profile ? c->prof_ev[2] : nullptr);
     if (coarse) TLS_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
-    hipLaunchKernelGGL(k_apply_scatter<T>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->own_ptr.p,
-                       c->own_pos.p, xloc, scale, c->part.p, c->ipos.p, c->d_nI.p, coarse ? c->kz_dev.p : nullptr,
-                       c->zcol.p, c->zoff.p, c->Z.p, coarse ? c->y0.p : nullptr, z, done);
+    if (refined)
+      hipLaunchKernelGGL(k_apply_scatter<double>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->own_ptr.p,
+                         c->own_pos.p, c->xref64.p, scale, c->part.p, c->ipos.p, c->d_nI.p,
+                         coarse ? c->kz_dev.p : nullptr, c->zcol.p, c->zoff.p, c->Z.p, coarse ? c->y0.p : nullptr, z,
+                         done);
+    else
+      hipLaunchKernelGGL(k_apply_scatter<T>, dim3(div_up(c->n, 256)), dim3(256), 0, s, c->n, c->own_ptr.p,
+                         c->own_pos.p, xloc, scale, c->part.p, c->ipos.p, c->d_nI.p, coarse ? c->kz_dev.p : nullptr,
+                         c->zcol.p, c->zoff.p, c->Z.p, coarse ? c->y0.p : nullptr, z, done);
     TLS_LAUNCH_CHECK();
   }
   if (profile) {

@@ -198,6 +198,26 @@ __device__ inline T* elem_ptr(T* base, int kind, int nt, int a, int b) {
   return base + tile_index(kind, nt, a / TS, b / TS) * TS2 + (b % TS) * TS + (a % TS);
 }
 
+// Position of global row g in the concatenated Omega lists of one
+// subdomain, given the absolute starts of its nseg ascending segments
+// (I_i, Gamma_1, ..., Gamma_delta) in lp[0..nseg]; -1 if g is not in Omega_i.
+__device__ inline int find_local_pos(int g, const int* __restrict__ sub_idx, const int* __restrict__ lp, int nseg) {
+  for (int d = 0; d < nseg; d++) {
+    int lo = lp[d], hi = lp[d + 1] - 1;
+    if (lo > hi) continue;
+    if (g < sub_idx[lo] || g > sub_idx[hi]) continue;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (sub_idx[mid] < g)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (sub_idx[lo] == g) return lo;
+  }
+  return -1;
+}
+
 // Per-subdomain layout table shared by the factor, the solves and the
 // eigensolver (device copy of host vectors).
 struct LocalLayout {

@@ -67,6 +67,12 @@ struct tls_ctx {
   // work vectors for the apply (padded local layout)
   tls::DBuf<double> xloc64;
   tls::DBuf<float> xloc32;
+  // iterative refinement of the FP32 local solves (option local_refine):
+  // sparse rows of every A_ii (CSR over the positions of the Omega lists,
+  // local column indices), the FP64 local right-hand sides and solutions
+  int refine = 0;
+  tls::DBuf<int> lref_ptr, lref_col;
+  tls::DBuf<double> lref_val, bref64, xref64;
 
   // coarse space
   int nC = 0, M0 = 0, nt0 = 0;
@@ -126,6 +132,7 @@ struct tls_ctx {
   int prof_count = 0;
   double prof_local_ms = 0, prof_fwd_ms = 0, prof_apply_ms = 0;
   tls::DBuf<int> errflag;
+  bool apply_wait_seen = false;  // a wait of an earlier tls_apply timed out (reported once by tls_info)
   double t_setup[8] = {0};
   double t_solve = 0;
   int last_iters = 0;

@@ -67,23 +67,6 @@ inline WOff woff(int c_out) {
 }
 
 // position of global row g inside Omega_i (segments ascending), or -1
-__device__ inline int find_pos(int g, const int* __restrict__ sub_idx, const int* __restrict__ lp, int nseg) {
-  for (int d = 0; d < nseg; d++) {
-    int lo = lp[d], hi = lp[d + 1] - 1;
-    if (lo > hi) continue;
-    if (g < sub_idx[lo] || g > sub_idx[hi]) continue;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (sub_idx[mid] < g)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    if (sub_idx[lo] == g) return lo;
-  }
-  return -1;
-}
-
 __global__ void k_gnn_diag(int total, const int* __restrict__ sub_idx, const int* __restrict__ rp,
                            const int* __restrict__ ci, const double* __restrict__ val, float* dg) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,7 +94,7 @@ __global__ void k_gnn_edges(int mode, int total, const int* __restrict__ sub_idx
   for (int j = rp[g]; j < rp[g + 1]; j++) {
     const int c = ci[j];
     if (c == g) continue;
-    const int q = find_pos(c, sub_idx, lp, nseg);
+    const int q = find_local_pos(c, sub_idx, lp, nseg);
     if (q < 0) continue;
     if (mode) {
       const float sb = dg[q];

@@ -83,6 +83,14 @@ void gnn_take_rows(tls_ctx* c, const std::vector<int>& nT, const std::vector<int
 // tune.hip: workgroup count of the persistent solves (default / timed / cached)
 void choose_solve_grid(tls_ctx* c);
 
+// refine.hip: iterative refinement of the FP32 local solves (option local_refine)
+void build_refine(tls_ctx* c);
+// local_solve on xloc32/xloc64, then c->refine refinement steps against the
+// FP64 right-hand sides in c->bref64; returns true when the solutions are in
+// c->xref64 (FP64) instead of the local-precision buffer
+bool local_solve_refined(tls_ctx* c, const int* done, hipEvent_t ev_begin = nullptr, hipEvent_t ev_mid = nullptr,
+                         hipEvent_t ev_end = nullptr);
+
 // apply.hip: z = M^{-1} r
 void apply_precond(tls_ctx* c, const double* r, double* z, const int* done, bool profile = false);
 
@@ -90,6 +98,9 @@ void apply_precond(tls_ctx* c, const double* r, double* z, const int* done, bool
 void spmv(tls_ctx* c, const double* x, double* y, const int* done);
 // y = f - A x
 void spmv_residual(tls_ctx* c, const double* f, const double* x, double* y, const int* done);
+// Reads the device error word (synchronizing the stream); if a triangular-solve
+// wait ran past its spin limit since the last call, clears it and returns true.
+bool take_wait_flag(tls_ctx* c);
 void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres,
                   bool* converged);
 

@@ -150,6 +150,18 @@ __global__ void k_sub(int n, const double* __restrict__ b, const double* __restr
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) r[i] = b[i] - q[i];
 }
 
+}  // namespace
+
+bool take_wait_flag(tls_ctx* c) {
+  const int err = download(c->errflag.p, 1, c->stream)[0];
+  if (!(err & ERR_WAIT)) return false;
+  TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), c->stream));
+  TLS_HIP(hipStreamSynchronize(c->stream));
+  return true;
+}
+
+namespace {
+
 void dot(tls_ctx* c, const double* a, const double* b, double* out, const int* done) {
   hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->n, a, b, c->partial.p, c->redctr.p, out,
                      done);
@@ -391,6 +403,7 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
   if (c->redctr.n < 1) c->redctr.alloc(1);
   TLS_HIP(hipMemsetAsync(c->redctr.p, 0, sizeof(unsigned), s));  // outside any captured graph
+  if (take_wait_flag(c)) c->apply_wait_seen = true;  // from an earlier tls_apply: reported by tls_info
   PcgVec v = vecs(c);
   const double tol2 = tol * tol;
   auto t0 = std::chrono::steady_clock::now();
@@ -433,33 +446,51 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
     c->graph_flex = flexible;
   }
   std::vector<int> hd(4, 0);
-  for (int launched = 0; launched < maxit + chunk; launched += chunk) {
-    if (use_graph)
-      TLS_HIP(hipGraphLaunch(c->graph_exec, s));
-    else
-      for (int j = 0; j < chunk; j++) pcg_iteration(c, v, maxit, tol2, flexible);
-    hd = download(c->done.p, 4, s);
-    if (hd[0]) break;
-  }
-  it = hd[1];
-  conv = hd[2] != 0;
-  if (hd[3]) fail(TLS_E_NOT_SPD, "PCG breakdown: p^T A p <= 0 (A or M^{-1} not SPD)");
-  // true residual
   const int* zero = c->zero_int.p;
-  spmv(c, v.x, v.q, zero);
-  hipLaunchKernelGGL(k_sub, dim3(std::min(4096, div_up(n, 256))), dim3(256), 0, s, n, v.b, v.q, v.r);
-  TLS_LAUNCH_CHECK();
-  dot(c, v.r, v.r, c->scal.p + 7, zero);
+  double rr = 0.0;
+  // The recurrence residual decides when to stop iterating; convergence is
+  // only reported when the true residual b - A x meets the tolerance too.
+  // Otherwise PCG restarts from the current x (at most kRestarts times).
+  constexpr int kRestarts = 4;
+  for (int restart = 0;; restart++) {
+    for (int launched = 0; launched < maxit + chunk; launched += chunk) {
+      if (use_graph)
+        TLS_HIP(hipGraphLaunch(c->graph_exec, s));
+      else
+        for (int j = 0; j < chunk; j++) pcg_iteration(c, v, maxit, tol2, flexible);
+      hd = download(c->done.p, 4, s);
+      if (hd[0]) break;
+    }
+    it = hd[1];
+    conv = hd[2] != 0;
+    if (hd[3]) fail(TLS_E_NOT_SPD, "PCG breakdown: p^T A p <= 0 (A or M^{-1} not SPD)");
+    // true residual r = b - A x
+    spmv(c, v.x, v.q, zero);
+    hipLaunchKernelGGL(k_sub, dim3(std::min(4096, div_up(n, 256))), dim3(256), 0, s, n, v.b, v.q, v.r);
+    TLS_LAUNCH_CHECK();
+    dot(c, v.r, v.r, c->scal.p + 7, zero);
+    rr = download(c->scal.p + 7, 1, s)[0];
+    if (!conv || rr <= tol2 * bb) break;
+    if (restart == kRestarts || it >= maxit) {
+      conv = false;
+      break;
+    }
+    // restart from x with the true residual: z = M^{-1} r, p = z
+    TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int), s));
+    TLS_HIP(hipMemsetAsync(c->done.p + 2, 0, sizeof(int), s));
+    TLS_HIP(hipMemsetAsync(v.zold, 0, sizeof(double) * n, s));
+    apply_precond(c, v.r, v.z, c->done.p);
+    dot(c, v.r, v.z, c->scal.p + 1, c->done.p);
+    TLS_HIP(hipMemcpyAsync(v.p, v.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
   TLS_HIP(hipMemcpyAsync(x, v.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  double rr = download(c->scal.p + 7, 1, s)[0];
   c->h_hist = download(c->hist.p, it, s);
   auto t1 = std::chrono::steady_clock::now();
   c->t_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
   *iters = it;
   *relres = std::sqrt(rr / bb);
   *converged = conv;
-  int err = download(c->errflag.p, 1, s)[0];
-  if (err & ERR_WAIT) fail(TLS_E_HIP, "a triangular-solve wait exceeded its spin limit");
+  if (take_wait_flag(c)) fail(TLS_E_HIP, "a triangular-solve wait of this solve exceeded its spin limit");
 }
 
 
@@ -512,6 +543,7 @@ void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
   if (c->redctr.n < 1) c->redctr.alloc(1);
   TLS_HIP(hipMemsetAsync(c->redctr.p, 0, sizeof(unsigned), s));  // outside any captured graph
+  if (take_wait_flag(c)) c->apply_wait_seen = true;  // from an earlier tls_apply: reported by tls_info
   DBuf<double> gmb;
   DBuf<int> gib;
   gmb.alloc(L.total);
@@ -575,8 +607,7 @@ void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   *iters = it;
   *relres = std::sqrt(rr / bb);
   *converged = conv;
-  int err = download(c->errflag.p, 1, s)[0];
-  if (err & ERR_WAIT) fail(TLS_E_HIP, "a triangular-solve wait exceeded its spin limit");
+  if (take_wait_flag(c)) fail(TLS_E_HIP, "a triangular-solve wait of this solve exceeded its spin limit");
 }
 
 }  // namespace tls

@@ -14,7 +14,8 @@ import scipy.sparse.linalg as spla
 import oracle
 from oracle import schwarz
 from tests.gpu_helpers import principal_cosines, say, to_dev, torch_cuda
-from workloads import box_partition_2d, fv_diffusion_2d, high_contrast_kappa_2d, make_config, poisson_2d, rcb_partition
+from workloads import (box_partition_2d, fv_diffusion_2d, high_contrast_kappa_2d, make_config, one_way_convection_2d,
+                       poisson_2d, rcb_partition)
 
 pytestmark = pytest.mark.gpu
 
@@ -72,15 +73,69 @@ def test_worked_example_on_gpu():
         pc.close()
 
 
+@pytest.mark.parametrize("delta,precision,tol", [(1, 0, 1e-10), (2, 0, 1e-10), (3, 0, 1e-10), (2, 1, 1e-5)])
+def test_structurally_nonsymmetric_pattern(delta, precision, tol):
+    """graph(A + A^T) (Section 2.1) on a matrix whose pattern is not
+    symmetric (one-way upwind coupling in x): the overlap lists and layer
+    sizes equal the oracle's exactly, some of them hold unknowns reached only
+    through A^T (so the transposed pattern changes Omega_i), and the apply of
+    the Section 6 two-level method with the library's basis imported into
+    the oracle matches it."""
+    torch = torch_cuda()
+    m = 48
+    A = one_way_convection_2d(m, np.random.default_rng(7))
+    part = box_partition_2d(m, m, 3, 3)
+    say("nonsymmetric pattern", delta, precision)
+    pc = _pc(A, part, delta, 4, matrix_kind=1, precision=precision)
+    ex = pc.export(Z=True)
+    through_t = False
+    for i in range(9):
+        s = schwarz.overlap(A, part, i, delta)
+        a, b = ex["sub_ptr"][i], ex["sub_ptr"][i + 1]
+        assert np.array_equal(ex["sub_idx"][a:b], s.idx)
+        sizes = np.diff(ex["layer_ptr"][i * (delta + 2):(i + 1) * (delta + 2)])
+        assert sizes[0] == s.n_interior and list(sizes[1:]) == s.layer_sizes
+        # layer-1 nodes that no row of I_i references: reached through A^T only
+        interior = s.idx[:s.n_interior]
+        by_rows = np.unique(A[interior].indices)
+        layer1 = s.idx[s.n_interior:s.n_interior + s.layer_sizes[0]]
+        only_t = np.setdiff1d(layer1, by_rows)
+        if only_t.size:
+            # each such node's own row references I_i: an edge of A^T
+            assert np.all(A[only_t][:, interior].getnnz(axis=1) > 0)
+            through_t = True
+    assert through_t
+    h = oracle.setup(A, part, delta, 4, spd=False, Z=ex["Z"])
+    rng = np.random.default_rng(16)
+    worst = 0.0
+    for _ in range(5):
+        r = rng.standard_normal(A.shape[0])
+        z = pc.apply(to_dev(r))
+        torch.cuda.synchronize()
+        z_ref = oracle.apply(h, r)
+        worst = max(worst, np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref))
+    say("  worst apply error", worst)
+    assert worst <= tol
+    pc.close()
+
+
 # ---------------------------------------------------------------------------
 # local factorization and solves (Section 2.3)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 2e-3)])
-def test_local_solves(precision, tol):
-    A, part = _hc_problem(128, 2, seed=2)  # subdomains of a few thousand rows: many tiles + ragged tail
-    say("local solves", precision)
-    pc = _pc(A, part, 2, 0, precision=precision)
+@pytest.mark.parametrize("precision,refine", [(0, 0), (1, 0), (1, 1), (1, 2)])
+def test_local_solves(precision, refine):
+    """Local solves by substitution against the oracle's sparse LU on
+    high-contrast subdomains of a few thousand rows (many tiles and a ragged
+    tail). FP64: 1e-11. FP32: the forward error of a backward-stable solve,
+    bounded by 20 cond(A_ii) u_32. With local_refine steps (FP64 residual
+    from the sparse A_ii, FP32 correction) the error contracts by about
+    cond(A_ii) u_32 per step: at most 1e-8 after one step and 1e-10 after
+    two on these subdomains."""
+    A, part = _hc_problem(128, 2, seed=2)
+    say("local solves", precision, refine)
+    pc = _pc(A, part, 2, 0, precision=precision, local_refine=refine)
+    assert pc.info()["local_refine"] == refine
     rng = np.random.default_rng(0)
     for i in range(int(part.max()) + 1):
         s = schwarz.overlap(A, part, i, 2)
@@ -89,7 +144,15 @@ def test_local_solves(precision, tol):
         x_ref = spla.spsolve(Aii, b)
         x = pc.local_solve(i, b)
         err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
-        say("  subdomain", i, "m", s.size, "err", err)
+        if precision == 0:
+            tol = 1e-11
+        elif refine == 0:
+            lmax = spla.eigsh(Aii, 1, which="LA", return_eigenvectors=False)[0]
+            lmin = spla.eigsh(Aii, 1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+            tol = 20 * (lmax / lmin) * 2.0 ** -24
+        else:
+            tol = 1e-8 if refine == 1 else 1e-10
+        say("  subdomain", i, "m", s.size, "err", err, "bound", tol)
         assert err <= tol
     pc.close()
 
@@ -124,7 +187,7 @@ def test_local_inverse_solves(precision):
     pc.close()
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 5e-3)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
 def test_local_inverse_apply_and_solve(precision, tol):
     """Option local_inverse on the 64 x 64 Poisson problem: the apply against
     the oracle with the library's own Z imported, PCG iterations equal to
@@ -198,6 +261,43 @@ def test_coarse_eigen_parity(delta):
     pc.close()
 
 
+@pytest.mark.parametrize("case", ["poisson_d1", "poisson_d2", "hc64_d2"])
+def test_coarse_eigen_parity_fp32(case):
+    """eq. gevpsvd in FP32 mode (FP32 factor, FP32 subspace iteration, FP64
+    Rayleigh-Ritz) against the oracle's FP64 dense solve of the full pencil:
+    relative eigenvalue error <= 1e-4 for every kept pair and largest
+    principal angle <= 1e-3 wherever lambda_k / lambda_{k+1} >= 1 + 1e-3."""
+    if case.startswith("poisson"):
+        A = poisson_2d(48)
+        part = box_partition_2d(48, 48, 3, 3)
+        delta, nev = (1 if case.endswith("d1") else 2), 6
+    else:
+        A, part = _hc_problem(64, 3, seed=4)
+        delta, nev = 2, 6
+    say("eigen parity fp32", case)
+    pc = _pc(A, part, delta, nev, precision=1)
+    ex = pc.export(Z=True)
+    zc = ex["zcol_ptr"]
+    worst_l = worst_a = 0.0
+    for i in range(int(part.max()) + 1):
+        s = schwarz.overlap(A, part, i, delta)
+        Aii = schwarz.local_matrix(A, s)
+        lam_all, _ = schwarz.gevp2(Aii, s, s.size, dense=True)
+        k = zc[i + 1] - zc[i]
+        assert k == min(nev, lam_all.size)
+        lam_gpu = ex["eigvals"][zc[i]:zc[i + 1]]
+        worst_l = max(worst_l, np.max(np.abs(lam_gpu - lam_all[:k]) / lam_all[:k]))
+        if lam_all.size > k and lam_all[k - 1] / lam_all[k] >= 1 + 1e-3:
+            Zi, _, _ = schwarz.coarse_block(Aii, s, nev, 0, True, dense=True)
+            Zg = ex["Z"][s.idx[:s.n_interior]][:, zc[i]:zc[i + 1]]
+            cos = np.clip(principal_cosines(Zi, Zg), -1.0, 1.0)
+            worst_a = max(worst_a, float(np.arccos(cos.min())))
+    say("  worst relative eigenvalue error", worst_l, "worst angle", worst_a)
+    assert worst_l <= 1e-4
+    assert worst_a <= 1e-3
+    pc.close()
+
+
 def test_gevp1_eigen_parity():
     """eq. uppergevp vectors alone (nev = 0, nev1 > 0, delta = 2): the kept
     eigenvalues lambda > 1 against the oracle's dense solve of the full
@@ -249,7 +349,7 @@ def test_gevp1_delta1_is_one_plus_gevp2():
     p2.close()
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 5e-3)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
 def test_both_eigenproblems_apply_parity(precision, tol):
     """Z_i = orth([D_i Pi_i W_i, D_i Z_i]) with nev = nev1 = 4 (eq. coarse_space_2):
     per-subdomain span against the oracle (FP64), then the apply with the
@@ -292,10 +392,10 @@ def test_both_eigenproblems_apply_parity(precision, tol):
 
 
 # ---------------------------------------------------------------------------
-# apply (Remark after Section 4.4)
+# apply (Remark in Section 4.3: the operator M_2^{-1})
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 5e-3)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
 def test_apply_with_imported_basis(precision, tol):
     torch = torch_cuda()
     p = make_config(1)
@@ -312,6 +412,37 @@ def test_apply_with_imported_basis(precision, tol):
         z_ref = oracle.apply(h, r)
         worst = max(worst, np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref))
     say("  worst apply error", worst)
+    assert worst <= tol
+    pc.close()
+
+
+@pytest.mark.parametrize("composition", [0, 1])
+@pytest.mark.parametrize("refine,inv,scale", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 0, 1), (2, 0, 0)])
+def test_high_contrast_fp32_apply(refine, inv, scale, composition):
+    """FP32 mode on high-contrast diffusion (kappa log-uniform in [1, 1e6]
+    with 1e6 channels, 16 RCB parts, delta 2): the apply with the library's
+    basis imported into the FP64 oracle. The FP32 local solves carry a
+    forward error of about cond(A_ii) u_32, which on these subdomains puts
+    the apply error at 1.0-1.3e-5 (bound 3e-5 without refinement); one
+    local refinement step (FP64 residual from the sparse A_ii) brings it
+    under the 1e-5 bound for FP32 mode, two under 1e-8."""
+    torch = torch_cuda()
+    A, part = _hc_problem(128, 4, seed=6)
+    say("high-contrast fp32 apply", refine, inv, scale, composition)
+    pc = _pc(A, part, 2, 8, precision=1, local_refine=refine, local_inverse=inv, jacobi_scale=scale,
+             composition=composition)
+    ex = pc.export(Z=True)
+    h = oracle.setup(A, part, 2, 8, Z=ex["Z"])
+    rng = np.random.default_rng(17)
+    worst = 0.0
+    for _ in range(5):
+        r = rng.standard_normal(A.shape[0])
+        z = pc.apply(to_dev(r))
+        torch.cuda.synchronize()
+        z_ref = oracle.apply(h, r, composition="ras_deflated" if composition else "additive")
+        worst = max(worst, np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref))
+    tol = {0: 3e-5, 1: 1e-5, 2: 1e-8}[refine]
+    say("  worst apply error", worst, "bound", tol)
     assert worst <= tol
     pc.close()
 
@@ -385,19 +516,23 @@ def test_graph_and_eager_iterates_identical():
     pc2.close()
 
 
-def test_fp32_mode_converges():
+@pytest.mark.parametrize("refine", [0, 1])
+def test_fp32_mode_converges(refine):
+    """FP32 local factors, solves and eigensolver under the FP64 flexible
+    PCG reach the 1e-8 true residual within 5% of the plain FP64 method's
+    iterations (high-contrast diffusion, 16 parts, delta 2, nev 8)."""
     torch = torch_cuda()
     A, part = _hc_problem(128, 4, seed=6)
     b = np.random.default_rng(2).standard_normal(A.shape[0])
-    say("fp32 solve")
-    pc = _pc(A, part, 2, 8, precision=1)
+    say("fp32 solve", refine)
+    pc = _pc(A, part, 2, 8, precision=1, local_refine=refine)
     x, it, rr, st = pc.solve(to_dev(b), 1e-8)
     torch.cuda.synchronize()
     pc64 = _pc(A, part, 2, 8, precision=0)
     _, it64, rr64, _ = pc64.solve(to_dev(b), 1e-8)
     say("  fp32 its", it, rr, "fp64 its", it64, rr64)
     assert st == 0 and rr <= 1e-8 and rr64 <= 1e-8
-    assert it <= 1.5 * it64 + 2
+    assert abs(it - it64) <= max(1, int(0.05 * it64))
     pc.close()
     pc64.close()
 
@@ -443,7 +578,7 @@ def _cd_problem(m, p, seed):
     return A, part
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 2e-4)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 2e-5)])
 def test_general_local_solves(precision, tol):
     A, part = _cd_problem(96, 2, seed=3)  # 4 subdomains of ~2.5k rows, delta 2
     say("general local solves", precision)
@@ -461,11 +596,16 @@ def test_general_local_solves(precision, tol):
     pc.close()
 
 
-def test_general_coarse_space_parity():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_general_coarse_space_parity(precision):
+    """Section 6 coarse vectors against a dense SVD: singular values to 1e-7
+    (FP64) or 1e-4 (FP32 mode), spans to 1 - 1e-9 in cosine (FP64) or a
+    largest principal angle of 1e-3 (FP32) where the gap allows; A_0 = Z^T A Z
+    with the library's own Z to 1e-12."""
     A, part = _cd_problem(64, 3, seed=4)
     nev = 5
-    say("general coarse space")
-    pc = _pc(A, part, 2, nev, matrix_kind=1)
+    say("general coarse space", precision)
+    pc = _pc(A, part, 2, nev, matrix_kind=1, precision=precision)
     ex = pc.export(Z=True, A0=True)
     zc = ex["zcol_ptr"]
     for i in range(9):
@@ -474,18 +614,21 @@ def test_general_coarse_space_parity():
         sig_all, U = schwarz.svd_variant(Aii, s, s.size)
         k = zc[i + 1] - zc[i]
         assert k == min(nev, sig_all.size)
-        assert np.allclose(ex["eigvals"][zc[i]:zc[i + 1]], sig_all[:k], rtol=1e-7)
+        assert np.allclose(ex["eigvals"][zc[i]:zc[i + 1]], sig_all[:k], rtol=1e-7 if precision == 0 else 1e-4)
         if sig_all.size > k and sig_all[k - 1] / sig_all[k] >= 1 + 1e-3:
             Zg = ex["Z"][s.idx[:s.n_interior]][:, zc[i]:zc[i + 1]]
             cos = principal_cosines(U[:s.n_interior, :k], Zg)
-            assert np.all(cos >= 1 - 1e-9), cos
+            if precision == 0:
+                assert np.all(cos >= 1 - 1e-9), cos
+            else:
+                assert np.arccos(np.clip(cos.min(), -1.0, 1.0)) <= 1e-3, cos
     Zg = ex["Z"]
     A0_ref = Zg.T @ (A @ Zg)
     assert np.allclose(ex["A0"], A0_ref, rtol=1e-12, atol=1e-12 * np.abs(A0_ref).max())
     pc.close()
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-4)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
 def test_general_apply_with_imported_basis(precision, tol):
     torch = torch_cuda()
     A, part = _cd_problem(64, 4, seed=5)
@@ -669,10 +812,10 @@ def _ras_case(kind):
 
 
 @pytest.mark.parametrize("kind,precision,scale,inv,tol", [("spd", 0, 0, 0, 1e-10), ("spd", 0, 1, 0, 1e-10),
-                                                         ("spd", 1, 0, 0, 5e-3), ("spd", 0, 0, 1, 1e-10),
-                                                         ("spd", 1, 1, 1, 5e-3), ("general", 0, 0, 0, 1e-10),
-                                                         ("general", 1, 0, 0, 1e-4), ("saddle", 0, 0, 0, 1e-10),
-                                                         ("saddle", 1, 0, 0, 1e-4)])
+                                                         ("spd", 1, 0, 0, 1e-5), ("spd", 0, 0, 1, 1e-10),
+                                                         ("spd", 1, 1, 1, 1e-5), ("general", 0, 0, 0, 1e-10),
+                                                         ("general", 1, 0, 0, 1e-5), ("saddle", 0, 0, 0, 1e-10),
+                                                         ("saddle", 1, 0, 0, 1e-5)])
 def test_ras_deflated_apply_with_imported_basis(kind, precision, scale, inv, tol):
     """z = Q r + M_RAS^{-1}(r - A Q r) with the library's own Z imported
     into the oracle, over several seeded r; for SPD also with the explicit

@@ -16,7 +16,7 @@ import scipy.sparse.linalg as spla
 import oracle
 from oracle import krylov, schwarz, theory
 from workloads import (box_partition_2d, convdiff_2d, fv_diffusion_2d, high_contrast_kappa_2d,
-                       poisson_2d, rcb_partition, worked_example_7x7)
+                       one_way_convection_2d, poisson_2d, rcb_partition, worked_example_7x7)
 
 
 def _dense_pi_d(A, sub):
@@ -86,6 +86,37 @@ def test_overlap_layers_brute_force_distance():
             assert np.all(np.diff(layer) > 0)  # ascending within a layer
             start += size
         assert np.all(np.diff(s.idx[:s.n_interior]) > 0)
+
+
+@pytest.mark.parametrize("delta", [1, 2, 3])
+def test_overlap_layers_on_a_structurally_nonsymmetric_pattern(delta):
+    """Section 2.1 grows the overlap on graph(A + A^T). On a matrix whose
+    pattern is not symmetric (one-way upwind coupling in x), the layers must
+    follow the edges of A and of A^T: checked against breadth-first
+    distances on the boolean pattern (A != 0) | (A != 0)^T formed here, and
+    shown to differ from the layers that A's own rows (or A^T's) would give,
+    so that a search on one of the two patterns fails this test."""
+    A = one_way_convection_2d(12, np.random.default_rng(7))
+    part = box_partition_2d(12, 12, 3, 3)
+    P = (A != 0).astype(np.int8)
+    assert (P != P.T).nnz > 0
+    U = ((P + P.T) > 0).astype(np.int8)
+    d_sym = sp.csgraph.shortest_path(U, unweighted=True)
+    d_row = sp.csgraph.shortest_path(P, unweighted=True, directed=True)
+    d_col = sp.csgraph.shortest_path(P.T.tocsr(), unweighted=True, directed=True)
+    differs_row = differs_col = False
+    for i in range(int(part.max()) + 1):
+        s = schwarz.overlap(A, part, i, delta)
+        d = d_sym[part == i].min(axis=0)
+        start = s.n_interior
+        for l, size in enumerate(s.layer_sizes, start=1):
+            layer = s.idx[start:start + size]
+            assert np.array_equal(layer, np.flatnonzero(d == l))
+            start += size
+        assert np.array_equal(np.sort(s.idx), np.flatnonzero(d <= delta))
+        differs_row |= not np.array_equal(np.sort(s.idx), np.flatnonzero(d_row[part == i].min(axis=0) <= delta))
+        differs_col |= not np.array_equal(np.sort(s.idx), np.flatnonzero(d_col[part == i].min(axis=0) <= delta))
+    assert differs_row and differs_col
 
 
 # ----------------------------------------------------------------------------
@@ -275,7 +306,7 @@ def test_svd_variant_against_dense_svd():
 
 
 # ----------------------------------------------------------------------------
-# P8-P12: the two-level operator (eq. onelevelasm, Remark in Section 4.4)
+# P8-P12: the two-level operator (eq. onelevelasm, Remark in Section 4.3)
 # ----------------------------------------------------------------------------
 
 def test_single_subdomain_is_exact_inverse():

@@ -21,6 +21,7 @@ from .problems import (  # noqa: F401
     layered_elasticity,
     lognormal_kappa_3d,
     make_config,
+    one_way_convection_2d,
     poisson_2d,
     rcb_partition,
     rhs,

@@ -29,6 +29,7 @@ __all__ = [
     "high_contrast_kappa_2d",
     "lognormal_kappa_3d",
     "convdiff_2d",
+    "one_way_convection_2d",
     "elasticity_q1_3d",
     "box_partition_2d",
     "box_partition_3d",
@@ -207,6 +208,31 @@ def convdiff_2d(m: int, rng: np.random.Generator, eps: float = 0.01,
         vals.append(coef[inside])
     A = _finish(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), m * m)
     return A, {"wx": wx, "wy": wy, "eps": eps, "h": h}
+
+
+def one_way_convection_2d(m: int, rng: np.random.Generator) -> sp.csr_matrix:
+    """A structurally nonsymmetric M-matrix on an m x m grid: diffusion in y
+    (coupling to (x, y+-1) both ways) and pure upwind convection in x with no
+    x-diffusion, so row (x, y) couples to (x-1, y) where the wind blows in +x
+    (rows y < m/2) and to (x+1, y) where it blows in -x (rows y >= m/2), and
+    never the other way. Wind speeds are U(0.5, 2) per node; the diagonal is
+    2 + speed + 0.1, so the matrix is a strictly row diagonally dominant
+    Z-matrix: it and every principal submatrix are nonsingular M-matrices,
+    and Gaussian elimination without pivoting keeps that property in every
+    Schur complement (positive pivots)."""
+    k = np.arange(m * m)
+    ix, iy = k % m, k // m
+    c = rng.uniform(0.5, 2.0, size=m * m)
+    east = iy < m // 2
+    rows, cols, vals = [k], [k], [2.0 + c + 0.1]
+    for dx, dy, coef, sel in ((-1, 0, -c, east), (1, 0, -c, ~east),
+                              (0, -1, -np.ones(m * m), np.ones(m * m, dtype=bool)),
+                              (0, 1, -np.ones(m * m), np.ones(m * m, dtype=bool))):
+        inside = sel & (ix + dx >= 0) & (ix + dx < m) & (iy + dy >= 0) & (iy + dy < m)
+        rows.append(k[inside])
+        cols.append(k[inside] + dx + m * dy)
+        vals.append(coef[inside])
+    return _finish(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), m * m)
 
 
 # --------------------------------------------------------------------------
