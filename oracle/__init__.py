@@ -16,6 +16,8 @@ It computes the paper's definitions literally, in float64, with NumPy/SciPy:
   variant (Section 6), the coarse space (eq. coarse_space_2), the Galerkin
   coarse operator and the two-level apply (Remark in Section 4.3);
 * ``krylov``   - PCG and right-preconditioned flexible GMRES;
+* ``pool``     - the same setup, apply and solve with the per-subdomain work
+  spread over worker processes (for the benchmark-size configurations);
 * ``gnn``      - forward, loss and backward of the warm-start network of
   the local eigensolver (not in the paper; see its docstring);
 * ``theory``   - brute-force objects for tiny inputs: the SPSD splitting
@@ -27,5 +29,5 @@ Parity status of each function is stated in its docstring; functions whose
 result nothing independent fixes say "parity unpinned".
 """
 
-from . import gnn, krylov, schwarz, theory  # noqa: F401
+from . import gnn, krylov, pool, schwarz, theory  # noqa: F401
 from .schwarz import Handle, apply, setup, solve  # noqa: F401

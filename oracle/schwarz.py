@@ -64,13 +64,14 @@ def sym_pattern(A: sp.spmatrix) -> sp.csr_matrix:
     return P
 
 
-def overlap(A: sp.spmatrix, part: np.ndarray, i: int, delta: int) -> Subdomain:
+def overlap(A: sp.spmatrix, part: np.ndarray, i: int, delta: int, G: sp.csr_matrix | None = None) -> Subdomain:
     """Omega_{i,1:delta} by breadth-first layers on graph(A + A^T)
     (Section 2.1): layer l holds the nodes not in I_i and not in an earlier
     layer that are adjacent to layer l-1 (layer 0 = I_i). Within I_i and
     within each layer, nodes are in ascending global order (the paper leaves
-    that order free; the worked example of Section 2.1 uses it)."""
-    G = sym_pattern(A)
+    that order free; the worked example of Section 2.1 uses it). ``G`` may
+    pass sym_pattern(A) when it is already formed."""
+    G = sym_pattern(A) if G is None else G
     n = A.shape[0]
     interior = np.flatnonzero(part == i)
     seen = np.zeros(n, dtype=bool)
@@ -328,8 +329,9 @@ def setup(A: sp.spmatrix, part: np.ndarray, overlap_layers: int, nev: int, *, ne
     if overlap_layers == 0 and nev > 0:
         raise ValueError("overlap 0 leaves Gamma_{i,delta} empty: no coarse space can be built")
     subs, lus, eig, eig1, blocks = [], [], [], [], []
+    G = sym_pattern(A)
     for i in range(n_parts):
-        s = overlap(A, part, i, overlap_layers)
+        s = overlap(A, part, i, overlap_layers, G)
         Aii = local_matrix(A, s)
         subs.append(s)
         lus.append(spla.splu(Aii.tocsc()))
