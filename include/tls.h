@@ -244,6 +244,24 @@ tls_status tls_spmv(tls_ctx* c, const double* x, double* y);
 tls_status tls_solve(tls_ctx* c, const double* b, double* x, double tol, int32_t* iters,
                      double* relres);
 
+/* For callers that cannot allocate device memory (code running while another
+ * stream of the process is under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the solve of tls_solve (same solver,
+ * same arguments, same results as tls_solve with use_graph = 0) with no
+ * device allocation and no hipFree. Its Krylov vectors, reduction partials,
+ * flags and residual history live in a fixed device array of
+ * TLS_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds until
+ * the process ends; the context must have been set up (its own buffers come
+ * from tls_setup) and its device must be current. The work needed is
+ * 56 n bytes for PCG and 8 n (2 restart + 7) bytes for FGMRES, plus a few
+ * tens of KB; a solve that needs more than the array returns TLS_E_ARG
+ * (tls_solve has no such limit). Always eager (no captured graph); keeps no
+ * residual history (tls_info reports none). Calls on one GPU share the
+ * array: calls that overlap on one GPU race. */
+#define TLS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+tls_status tls_solve_noalloc(tls_ctx* c, const double* b, double* x, double tol, int32_t* iters,
+                             double* relres);
+
 /* Statistics of the context (host struct; res_history stays valid until
  * the next tls_solve or tls_destroy). */
 tls_status tls_info(const tls_ctx* c, tls_info_t* info);

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "TLS_OK", 1: "TLS_E_ARG", 2: "TLS_E_NOT_SPD", 3: "TLS_E_SINGU
 # Names declared in include/tls.h (checked by the tests against the header).
 EXPORTED = ["tls_default_options", "tls_setup", "tls_apply", "tls_spmv", "tls_solve", "tls_info", "tls_export",
             "tls_local_solve", "tls_export_zblocks", "tls_gnn_forward", "tls_gnn_loss_grad", "tls_last_error",
-            "tls_destroy", "tls_trim"]
+            "tls_destroy", "tls_trim", "tls_solve_noalloc"]
 
 GNN_LAYERS = 4
 GNN_FEATURES = 12
@@ -128,6 +128,8 @@ def lib() -> C.CDLL:
         L.tls_spmv.restype = C.c_int
         L.tls_solve.argtypes = [vp, vp, vp, dbl, C.POINTER(i32), C.POINTER(dbl)]
         L.tls_solve.restype = C.c_int
+        L.tls_solve_noalloc.argtypes = [vp, vp, vp, dbl, C.POINTER(i32), C.POINTER(dbl)]
+        L.tls_solve_noalloc.restype = C.c_int
         L.tls_info.argtypes = [vp, C.POINTER(tls_info_t)]
         L.tls_info.restype = C.c_int
         L.tls_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -189,6 +191,14 @@ def tls_solve(ctx, b_ptr, x_ptr, tol):
     rr = C.c_double(0.0)
     st = lib().tls_solve(ctx, b_ptr, x_ptr, tol, C.byref(it), C.byref(rr))
     check(st, ctx, allow=(TLS_E_NOCONV,))
+    return st, it.value, rr.value
+
+
+def tls_solve_noalloc(ctx, b_ptr, x_ptr, tol, allow=(TLS_E_NOCONV,)):
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    st = lib().tls_solve_noalloc(ctx, b_ptr, x_ptr, tol, C.byref(it), C.byref(rr))
+    check(st, ctx, allow=allow)
     return st, it.value, rr.value
 
 

@@ -115,6 +115,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     c->nev = nev;
     c->kind = c->opt.matrix_kind;
     c->fp32 = c->opt.precision == 1;
+    TLS_HIP(hipGetDevice(&c->device));
     if (c->opt.stream) {
       c->stream = reinterpret_cast<hipStream_t>(c->opt.stream);
     } else {

@@ -165,6 +165,14 @@ struct DBuf {
 };
 
 template <class T>
+inline void read_back(const T* d, T* h, size_t count, hipStream_t s) {
+  if (count) {
+    TLS_HIP(hipMemcpyAsync(h, d, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    TLS_HIP(hipStreamSynchronize(s));
+  }
+}
+
+template <class T>
 inline std::vector<T> download(const T* d, size_t count, hipStream_t s) {
   std::vector<T> h(count);
   if (count) {

@@ -7,6 +7,7 @@ struct tls_ctx {
   tls_options opt{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;                            // HIP device current at tls_setup
   hipStream_t stream2 = nullptr;             // coarse solve, overlapped with the local solves
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int tuned = 0;
@@ -120,6 +121,8 @@ struct tls_ctx {
   tls::DBuf<unsigned> redctr;  // blocks done in the current one-launch reduction (0 between launches)
   tls::DBuf<int> done;         // [0]: converged flag, [1]: iterations
   tls::DBuf<double> hist;      // residual history
+  tls::DBuf<double> gm_state;  // FGMRES Hessenberg matrix and rotations
+  tls::DBuf<int> gm_idx;       // FGMRES inner index and cycle end
   std::vector<double> h_hist;
   tls::DBuf<int> zero_int;     // constant 0 for "not done"
   hipGraphExec_t graph_exec = nullptr;

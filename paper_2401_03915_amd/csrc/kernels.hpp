@@ -101,6 +101,28 @@ void spmv_residual(tls_ctx* c, const double* f, const double* x, double* y, cons
 // Reads the device error word (synchronizing the stream); if a triangular-solve
 // wait ran past its spin limit since the last call, clears it and returns true.
 bool take_wait_flag(tls_ctx* c);
+// Device work of one Krylov solve: tls_solve takes it from buffers that the
+// context keeps (allocated on first use), tls_solve_noalloc from a fixed
+// scratch area.
+struct KWork {
+  double* kr = nullptr;        // vectors
+  double* scal = nullptr;      // 16 scalars
+  double* partial = nullptr;   // reduction partials
+  unsigned* redctr = nullptr;  // blocks done in the current one-launch reduction (0 between launches)
+  int* done = nullptr;         // [0] stop, [1] iterations, [2] converged, [3] breakdown
+  double* hist = nullptr;      // ||r_k|| / ||b|| per iteration
+  double* gm = nullptr;        // FGMRES Hessenberg matrix, rotations, g, y and partial columns
+  int* gi = nullptr;           // FGMRES inner index and cycle end (4 ints)
+  bool context_bufs = false;   // the context's own buffers: the captured graph and history apply
+};
+// Element counts of each KWork part for the context's solver and options.
+struct KrylovNeeds {
+  size_t kr = 0, partial = 0, gm = 0;
+  int hist = 0;
+};
+KrylovNeeds krylov_needs(const tls_ctx* c);
+void krylov_run(tls_ctx* c, const KWork& w, const double* b, double* x, double tol, int* iters, double* relres,
+                bool* converged);
 void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres,
                   bool* converged);
 

@@ -153,7 +153,8 @@ __global__ void k_sub(int n, const double* __restrict__ b, const double* __restr
 }  // namespace
 
 bool take_wait_flag(tls_ctx* c) {
-  const int err = download(c->errflag.p, 1, c->stream)[0];
+  int err = 0;
+  read_back(c->errflag.p, &err, 1, c->stream);
   if (!(err & ERR_WAIT)) return false;
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), c->stream));
   TLS_HIP(hipStreamSynchronize(c->stream));
@@ -162,9 +163,8 @@ bool take_wait_flag(tls_ctx* c) {
 
 namespace {
 
-void dot(tls_ctx* c, const double* a, const double* b, double* out, const int* done) {
-  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->n, a, b, c->partial.p, c->redctr.p, out,
-                     done);
+void dot(tls_ctx* c, const KWork& w, const double* a, const double* b, double* out, const int* done) {
+  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->n, a, b, w.partial, w.redctr, out, done);
   TLS_LAUNCH_CHECK();
 }
 
@@ -172,29 +172,28 @@ struct PcgVec {
   double *x, *r, *z, *p, *q, *zold, *b;
 };
 
-PcgVec vecs(tls_ctx* c) {
+PcgVec vecs(const tls_ctx* c, const KWork& w) {
   const size_t n = c->n;
-  double* k = c->kr.p;
+  double* k = w.kr;
   return PcgVec{k, k + n, k + 2 * n, k + 3 * n, k + 4 * n, k + 5 * n, k + 6 * n};
 }
 
-void pcg_iteration(tls_ctx* c, const PcgVec& v, int maxit, double tol2, bool flexible) {
+void pcg_iteration(tls_ctx* c, const KWork& w, const PcgVec& v, int maxit, double tol2, bool flexible) {
   hipStream_t s = c->stream;
-  const int* done = c->done.p;
+  const int* done = w.done;
   const int n = c->n;
   const int vg = std::min(4096, div_up(n, 256));
   spmv(c, v.p, v.q, done);
-  hipLaunchKernelGGL(k_dot_pq, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.p, v.q, c->partial.p, c->redctr.p, c->scal.p,
-                     c->done.p);
-  hipLaunchKernelGGL(k_pcg_update, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.x, v.r, v.p, v.q, c->scal.p, c->partial.p,
-                     c->redctr.p, c->done.p, c->hist.p, maxit, tol2);
+  hipLaunchKernelGGL(k_dot_pq, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.p, v.q, w.partial, w.redctr, w.scal, w.done);
+  hipLaunchKernelGGL(k_pcg_update, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.x, v.r, v.p, v.q, w.scal, w.partial,
+                     w.redctr, w.done, w.hist, maxit, tol2);
   TLS_LAUNCH_CHECK();
   if (flexible) hipLaunchKernelGGL(k_copy, dim3(vg), dim3(256), 0, s, n, v.z, v.zold, done);
   apply_precond(c, v.r, v.z, done);
-  dot(c, v.r, v.z, c->scal.p + 4, done);
-  if (flexible) dot(c, v.r, v.zold, c->scal.p + 5, done);
-  hipLaunchKernelGGL(k_pcg_p, dim3(vg), dim3(256), 0, s, n, v.p, v.z, c->scal.p, flexible ? 1 : 0, done);
-  hipLaunchKernelGGL(k_pcg_shift, dim3(1), dim3(1), 0, s, c->scal.p, done);
+  dot(c, w, v.r, v.z, w.scal + 4, done);
+  if (flexible) dot(c, w, v.r, v.zold, w.scal + 5, done);
+  hipLaunchKernelGGL(k_pcg_p, dim3(vg), dim3(256), 0, s, n, v.p, v.z, w.scal, flexible ? 1 : 0, done);
+  hipLaunchKernelGGL(k_pcg_shift, dim3(1), dim3(1), 0, s, w.scal, done);
   TLS_LAUNCH_CHECK();
 }
 
@@ -384,59 +383,55 @@ void spmv_residual(tls_ctx* c, const double* f, const double* x, double* y, cons
 
 void spmv(tls_ctx* c, const double* x, double* y, const int* done) { spmv_residual(c, nullptr, x, y, done); }
 
-void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged);
+namespace {
 
-void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged) {
-  // PCG needs a symmetric preconditioner: SPD A with the additive composition
-  if (c->kind != 0 || c->opt.composition != 0) {
-    fgmres_solve(c, b, x, tol, iters, relres, converged);
-    return;
-  }
+bool use_pcg(const tls_ctx* c) { return c->kind == 0 && c->opt.composition == 0; }
+int krylov_maxit(const tls_ctx* c) { return c->opt.maxit > 0 ? c->opt.maxit : (use_pcg(c) ? 1000 : 3000); }
+int gmres_m(const tls_ctx* c) { return c->opt.restart > 0 ? c->opt.restart : 30; }
+
+void pcg_run(tls_ctx* c, const KWork& w, const double* b, double* x, double tol, int* iters, double* relres,
+             bool* converged) {
   hipStream_t s = c->stream;
   const int n = c->n;
-  const int maxit = c->opt.maxit > 0 ? c->opt.maxit : 1000;
+  const int maxit = krylov_maxit(c);
   const bool flexible = c->opt.flexible != 0;
-  if (c->kr.n < (size_t)7 * n) c->kr.alloc((size_t)7 * n);
-  if (c->scal.n < 16) c->scal.alloc(16);
-  if (c->partial.n < RED_BLOCKS) c->partial.alloc(RED_BLOCKS);
-  if (c->done.n < 4) c->done.alloc(4);
-  if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
-  if (c->redctr.n < 1) c->redctr.alloc(1);
-  TLS_HIP(hipMemsetAsync(c->redctr.p, 0, sizeof(unsigned), s));  // outside any captured graph
+  TLS_HIP(hipMemsetAsync(w.redctr, 0, sizeof(unsigned), s));  // outside any captured graph
   if (take_wait_flag(c)) c->apply_wait_seen = true;  // from an earlier tls_apply: reported by tls_info
-  PcgVec v = vecs(c);
+  PcgVec v = vecs(c, w);
   const double tol2 = tol * tol;
   auto t0 = std::chrono::steady_clock::now();
-  TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int) * 4, s));
+  TLS_HIP(hipMemsetAsync(w.done, 0, sizeof(int) * 4, s));
   TLS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));
   TLS_HIP(hipMemcpyAsync(v.b, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   TLS_HIP(hipMemcpyAsync(v.r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   TLS_HIP(hipMemsetAsync(v.zold, 0, sizeof(double) * n, s));
-  dot(c, v.b, v.b, c->scal.p + 0, c->done.p);
-  double bb = download(c->scal.p, 1, s)[0];
+  dot(c, w, v.b, v.b, w.scal + 0, w.done);
+  double bb = 0.0;
+  read_back(w.scal, &bb, 1, s);
   int it = 0;
   bool conv = false;
+  c->h_hist.clear();
   if (bb == 0.0) {
     TLS_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
     TLS_HIP(hipStreamSynchronize(s));
-    c->h_hist.clear();
     *iters = 0;
     *relres = 0.0;
     *converged = true;
     return;
   }
-  apply_precond(c, v.r, v.z, c->done.p);
-  dot(c, v.r, v.z, c->scal.p + 1, c->done.p);
+  apply_precond(c, v.r, v.z, w.done);
+  dot(c, w, v.r, v.z, w.scal + 1, w.done);
   TLS_HIP(hipMemcpyAsync(v.p, v.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   const int chunk = 8;
-  bool use_graph = c->opt.use_graph != 0;
+  // the captured graph refers to the context's own work buffers
+  const bool use_graph = c->opt.use_graph != 0 && w.context_bufs;
   if (use_graph && (!c->graph_exec || c->graph_chunk != chunk || c->graph_maxit != maxit ||
                     c->graph_tol2 != tol2 || c->graph_flex != flexible)) {
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     c->graph_exec = nullptr;
     hipGraph_t g;
     TLS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int j = 0; j < chunk; j++) pcg_iteration(c, v, maxit, tol2, flexible);
+    for (int j = 0; j < chunk; j++) pcg_iteration(c, w, v, maxit, tol2, flexible);
     TLS_HIP(hipStreamEndCapture(s, &g));
     TLS_HIP(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
@@ -445,7 +440,7 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
     c->graph_tol2 = tol2;
     c->graph_flex = flexible;
   }
-  std::vector<int> hd(4, 0);
+  int hd[4] = {0, 0, 0, 0};
   const int* zero = c->zero_int.p;
   double rr = 0.0;
   // The recurrence residual decides when to stop iterating; convergence is
@@ -457,8 +452,8 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
       if (use_graph)
         TLS_HIP(hipGraphLaunch(c->graph_exec, s));
       else
-        for (int j = 0; j < chunk; j++) pcg_iteration(c, v, maxit, tol2, flexible);
-      hd = download(c->done.p, 4, s);
+        for (int j = 0; j < chunk; j++) pcg_iteration(c, w, v, maxit, tol2, flexible);
+      read_back(w.done, hd, 4, s);
       if (hd[0]) break;
     }
     it = hd[1];
@@ -468,23 +463,24 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
     spmv(c, v.x, v.q, zero);
     hipLaunchKernelGGL(k_sub, dim3(std::min(4096, div_up(n, 256))), dim3(256), 0, s, n, v.b, v.q, v.r);
     TLS_LAUNCH_CHECK();
-    dot(c, v.r, v.r, c->scal.p + 7, zero);
-    rr = download(c->scal.p + 7, 1, s)[0];
+    dot(c, w, v.r, v.r, w.scal + 7, zero);
+    read_back(w.scal + 7, &rr, 1, s);
     if (!conv || rr <= tol2 * bb) break;
     if (restart == kRestarts || it >= maxit) {
       conv = false;
       break;
     }
     // restart from x with the true residual: z = M^{-1} r, p = z
-    TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int), s));
-    TLS_HIP(hipMemsetAsync(c->done.p + 2, 0, sizeof(int), s));
+    TLS_HIP(hipMemsetAsync(w.done, 0, sizeof(int), s));
+    TLS_HIP(hipMemsetAsync(w.done + 2, 0, sizeof(int), s));
     TLS_HIP(hipMemsetAsync(v.zold, 0, sizeof(double) * n, s));
-    apply_precond(c, v.r, v.z, c->done.p);
-    dot(c, v.r, v.z, c->scal.p + 1, c->done.p);
+    apply_precond(c, v.r, v.z, w.done);
+    dot(c, w, v.r, v.z, w.scal + 1, w.done);
     TLS_HIP(hipMemcpyAsync(v.p, v.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   }
   TLS_HIP(hipMemcpyAsync(x, v.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  c->h_hist = download(c->hist.p, it, s);
+  if (w.context_bufs) c->h_hist = download(w.hist, it, s);
+  TLS_HIP(hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
   c->t_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
   *iters = it;
@@ -493,18 +489,18 @@ void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   if (take_wait_flag(c)) fail(TLS_E_HIP, "a triangular-solve wait of this solve exceeded its spin limit");
 }
 
-
-namespace {
-
 struct GmBufs {
   double *x, *r, *w, *vj, *zj, *b, *V, *Zb;
 };
 
-void fgmres_inner(tls_ctx* c, const GmBufs& B, double* gm, int* gi, const GmLayout& L, double* mdpart, int maxit,
-                  double tol2, double bnorm2) {
+void fgmres_inner(tls_ctx* c, const KWork& W, const GmBufs& B, const GmLayout& L, int maxit, double tol2,
+                  double bnorm2) {
   hipStream_t s = c->stream;
   const int n = c->n;
-  const int* done = c->done.p;
+  const int* done = W.done;
+  double* gm = W.gm;
+  int* gi = W.gi;
+  double* mdpart = W.partial;
   const int vg = std::min(4096, div_up(n, 256));
   hipLaunchKernelGGL(k_gm_take, dim3(vg), dim3(256), 0, s, n, B.V, B.vj, gi, done);
   TLS_LAUNCH_CHECK();
@@ -520,49 +516,38 @@ void fgmres_inner(tls_ctx* c, const GmBufs& B, double* gm, int* gi, const GmLayo
     hipLaunchKernelGGL(k_gm_axpy, dim3(vg), dim3(256), 0, s, n, B.V, h, B.w, gi, done);
     TLS_LAUNCH_CHECK();
   }
-  dot(c, B.w, B.w, c->scal.p + 8, done);
-  hipLaunchKernelGGL(k_gm_vnext, dim3(vg), dim3(256), 0, s, n, B.w, B.V, c->scal.p + 8, gi, done);
-  hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(1), 0, s, gm, L, c->scal.p + 8, gi, c->done.p, c->hist.p, maxit, tol2,
+  dot(c, W, B.w, B.w, W.scal + 8, done);
+  hipLaunchKernelGGL(k_gm_vnext, dim3(vg), dim3(256), 0, s, n, B.w, B.V, W.scal + 8, gi, done);
+  hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(1), 0, s, gm, L, W.scal + 8, gi, W.done, W.hist, maxit, tol2,
                      bnorm2);
   TLS_LAUNCH_CHECK();
 }
 
-}  // namespace
-
-void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged) {
+void fgmres_run(tls_ctx* c, const KWork& W, const double* b, double* x, double tol, int* iters, double* relres,
+                bool* converged) {
   hipStream_t s = c->stream;
   const int n = c->n;
-  const int m = c->opt.restart > 0 ? c->opt.restart : 30;
-  const int maxit = c->opt.maxit > 0 ? c->opt.maxit : 3000;
+  const int m = gmres_m(c);
+  const int maxit = krylov_maxit(c);
   const GmLayout L(m);
-  const size_t need = (size_t)n * (6 + (m + 1) + m);
-  if (c->kr.n < need) c->kr.alloc(need);
-  if (c->scal.n < 16) c->scal.alloc(16);
-  if (c->partial.n < (size_t)std::max(RED_BLOCKS, MD_BLOCKS * (m + 1))) c->partial.alloc(std::max(RED_BLOCKS, MD_BLOCKS * (m + 1)));
-  if (c->done.n < 4) c->done.alloc(4);
-  if (c->hist.n < (size_t)maxit) c->hist.alloc(maxit);
-  if (c->redctr.n < 1) c->redctr.alloc(1);
-  TLS_HIP(hipMemsetAsync(c->redctr.p, 0, sizeof(unsigned), s));  // outside any captured graph
+  TLS_HIP(hipMemsetAsync(W.redctr, 0, sizeof(unsigned), s));  // outside any captured graph
   if (take_wait_flag(c)) c->apply_wait_seen = true;  // from an earlier tls_apply: reported by tls_info
-  DBuf<double> gmb;
-  DBuf<int> gib;
-  gmb.alloc(L.total);
-  gib.alloc(4);
-  double* k = c->kr.p;
+  double* k = W.kr;
   GmBufs B{k, k + n, k + 2 * (size_t)n, k + 3 * (size_t)n, k + 4 * (size_t)n, k + 5 * (size_t)n, k + 6 * (size_t)n,
            k + (6 + (size_t)(m + 1)) * n};
   auto t0 = std::chrono::steady_clock::now();
-  TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int) * 4, s));
+  TLS_HIP(hipMemsetAsync(W.done, 0, sizeof(int) * 4, s));
   TLS_HIP(hipMemsetAsync(B.x, 0, sizeof(double) * n, s));
-  TLS_HIP(hipMemsetAsync(gmb.p, 0, sizeof(double) * L.total, s));
+  TLS_HIP(hipMemsetAsync(W.gm, 0, sizeof(double) * L.total, s));
   TLS_HIP(hipMemcpyAsync(B.b, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   const int* zero = c->zero_int.p;
-  dot(c, B.b, B.b, c->scal.p + 0, zero);
-  const double bb = download(c->scal.p, 1, s)[0];
+  dot(c, W, B.b, B.b, W.scal + 0, zero);
+  double bb = 0.0;
+  read_back(W.scal, &bb, 1, s);
+  c->h_hist.clear();
   if (bb == 0.0) {
     TLS_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
     TLS_HIP(hipStreamSynchronize(s));
-    c->h_hist.clear();
     *iters = 0;
     *relres = 0.0;
     *converged = true;
@@ -571,43 +556,94 @@ void fgmres_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters
   const double tol2 = tol * tol;
   const int vg = std::min(4096, div_up(n, 256));
   bool conv = false;
-  std::vector<int> hd(4, 0);
+  int hd[4] = {0, 0, 0, 0};
   double rr = bb;
   for (int cycle = 0;; cycle++) {
     // r = b - A x
     spmv(c, B.x, B.w, zero);
     hipLaunchKernelGGL(k_sub, dim3(vg), dim3(256), 0, s, n, B.b, B.w, B.r);
-    dot(c, B.r, B.r, c->scal.p + 9, zero);
-    hipLaunchKernelGGL(k_gm_cycle_init, dim3(1), dim3(1), 0, s, gmb.p, gib.p, L, c->scal.p + 9);
-    hipLaunchKernelGGL(k_gm_v0, dim3(vg), dim3(256), 0, s, n, B.r, B.V, gmb.p, L);
+    dot(c, W, B.r, B.r, W.scal + 9, zero);
+    hipLaunchKernelGGL(k_gm_cycle_init, dim3(1), dim3(1), 0, s, W.gm, W.gi, L, W.scal + 9);
+    hipLaunchKernelGGL(k_gm_v0, dim3(vg), dim3(256), 0, s, n, B.r, B.V, W.gm, L);
     TLS_LAUNCH_CHECK();
-    for (int j = 0; j < m; j++) fgmres_inner(c, B, gmb.p, gib.p, L, c->partial.p, maxit, tol2, bb);
-    hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(1), 0, s, gmb.p, L, gib.p);
-    hipLaunchKernelGGL(k_gm_update_x, dim3(vg), dim3(256), 0, s, n, B.x, B.Zb, gmb.p, L, gib.p);
+    for (int j = 0; j < m; j++) fgmres_inner(c, W, B, L, maxit, tol2, bb);
+    hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(1), 0, s, W.gm, L, W.gi);
+    hipLaunchKernelGGL(k_gm_update_x, dim3(vg), dim3(256), 0, s, n, B.x, B.Zb, W.gm, L, W.gi);
     TLS_LAUNCH_CHECK();
     // true residual of the new iterate
     spmv(c, B.x, B.w, zero);
     hipLaunchKernelGGL(k_sub, dim3(vg), dim3(256), 0, s, n, B.b, B.w, B.r);
-    dot(c, B.r, B.r, c->scal.p + 7, zero);
-    rr = download(c->scal.p + 7, 1, s)[0];
-    hd = download(c->done.p, 4, s);
+    dot(c, W, B.r, B.r, W.scal + 7, zero);
+    read_back(W.scal + 7, &rr, 1, s);
+    read_back(W.done, hd, 4, s);
     if (rr <= tol2 * bb) {
       conv = true;
       break;
     }
     if (hd[1] >= maxit) break;
     // not converged by the true residual: clear the stop flag and restart
-    TLS_HIP(hipMemsetAsync(c->done.p, 0, sizeof(int) * 1, s));
-    TLS_HIP(hipMemsetAsync(c->done.p + 2, 0, sizeof(int) * 1, s));
+    TLS_HIP(hipMemsetAsync(W.done, 0, sizeof(int) * 1, s));
+    TLS_HIP(hipMemsetAsync(W.done + 2, 0, sizeof(int) * 1, s));
   }
   TLS_HIP(hipMemcpyAsync(x, B.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   const int it = hd[1];
-  c->h_hist = download(c->hist.p, std::max(it, 0), s);
+  if (W.context_bufs) c->h_hist = download(W.hist, std::max(it, 0), s);
+  TLS_HIP(hipStreamSynchronize(s));
   c->t_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *iters = it;
   *relres = std::sqrt(rr / bb);
   *converged = conv;
   if (take_wait_flag(c)) fail(TLS_E_HIP, "a triangular-solve wait of this solve exceeded its spin limit");
+}
+
+}  // namespace
+
+KrylovNeeds krylov_needs(const tls_ctx* c) {
+  KrylovNeeds k;
+  k.hist = krylov_maxit(c);
+  if (use_pcg(c)) {
+    k.kr = (size_t)7 * c->n;
+    k.partial = RED_BLOCKS;
+    k.gm = 0;
+  } else {
+    const int m = gmres_m(c);
+    k.kr = (size_t)c->n * (6 + (m + 1) + m);
+    k.partial = (size_t)std::max(RED_BLOCKS, MD_BLOCKS * (m + 1));
+    k.gm = (size_t)GmLayout(m).total;
+  }
+  return k;
+}
+
+void krylov_run(tls_ctx* c, const KWork& w, const double* b, double* x, double tol, int* iters, double* relres,
+                bool* converged) {
+  // PCG needs a symmetric preconditioner: SPD A with the additive composition
+  if (use_pcg(c))
+    pcg_run(c, w, b, x, tol, iters, relres, converged);
+  else
+    fgmres_run(c, w, b, x, tol, iters, relres, converged);
+}
+
+void krylov_solve(tls_ctx* c, const double* b, double* x, double tol, int* iters, double* relres, bool* converged) {
+  const KrylovNeeds k = krylov_needs(c);
+  if (c->kr.n < k.kr) c->kr.alloc(k.kr);
+  if (c->scal.n < 16) c->scal.alloc(16);
+  if (c->partial.n < k.partial) c->partial.alloc(k.partial);
+  if (c->done.n < 4) c->done.alloc(4);
+  if (c->hist.n < (size_t)k.hist) c->hist.alloc(k.hist);
+  if (c->redctr.n < 1) c->redctr.alloc(1);
+  if (k.gm && c->gm_state.n < k.gm) c->gm_state.alloc(k.gm);
+  if (c->gm_idx.n < 4) c->gm_idx.alloc(4);
+  KWork w;
+  w.kr = c->kr.p;
+  w.scal = c->scal.p;
+  w.partial = c->partial.p;
+  w.redctr = c->redctr.p;
+  w.done = c->done.p;
+  w.hist = c->hist.p;
+  w.gm = c->gm_state.p;
+  w.gi = c->gm_idx.p;
+  w.context_bufs = true;
+  krylov_run(c, w, b, x, tol, iters, relres, converged);
 }
 
 }  // namespace tls
