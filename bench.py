@@ -89,7 +89,7 @@ def factor_flops(ctx, n_parts, spd=True):
 
 
 def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_cache, composition=0, restart=30,
-             local_inverse=0, tol=1e-8):
+             local_inverse=0, tol=1e-8, local_refine=0):
     import torch
 
     import paper_2401_03915_amd as tls
@@ -105,6 +105,7 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         opt.composition = composition
         opt.restart = restart
         opt.local_inverse = local_inverse
+        opt.local_refine = local_refine
         opt.use_graph = use_graph
         opt.profile = profile
         # the first setup times the solve launch shapes and records the pick in
@@ -185,81 +186,79 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
     }
 
 
-def cpu_baseline(prob, iters, sample=64, seed=0, composition=0):
-    """The FP64 oracle timed on one host thread over a bounded sample of the
-    same workload, scaled to the full time-to-solve.
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
 
-    Sample: `sample` subdomains stratified by interior size (evenly spaced
-    quantiles of the sorted sizes, so the mean is representative of the
-    uneven RCB parts). For each, the oracle's per-subdomain setup (overlap
-    layers, A_ii, sparse LU, eq. gevpsvd with ARPACK or the Section 6 SVD,
-    coarse block) and one local solve (mean of 5). Per iteration the oracle
-    also does one product with A (two with the deflated composition) and one
-    coarse solve: the same library calls (CSR product, dense Cholesky or LU
-    solve of order n_coarse) are timed on the workload's A and on a seeded
-    SPD matrix of order n_coarse, whose factorization is part of setup.
-    Estimate = N * setup + factor(n_coarse)
-               + iters * (N * local solve + (1 + composition) A x + coarse solve)."""
-    import scipy.linalg as sla
-    import scipy.sparse.linalg as spla
-    from threadpoolctl import threadpool_limits
 
-    from oracle import schwarz
-    N = prob.n_parts
-    sizes_int = np.bincount(prob.part, minlength=N)
-    order = np.argsort(sizes_int, kind="stable")
-    k = min(sample, N)
-    picks = order[np.unique(np.linspace(0, N - 1, k).round().astype(int))]
-    t_setup, t_solve, sizes = [], [], []
-    t_begin = time.perf_counter()
-    with threadpool_limits(1):
-        for i in picks:
-            t0 = time.perf_counter()
-            s = schwarz.overlap(prob.A, prob.part, int(i), prob.overlap)
-            Aii = schwarz.local_matrix(prob.A, s)
-            lu = spla.splu(Aii.tocsc())
-            schwarz.coarse_block(Aii, s, prob.nev, 0, prob.spd)
-            t1 = time.perf_counter()
-            rhs = np.ones(s.size)
-            for _ in range(5):
-                lu.solve(rhs)
-            t2 = time.perf_counter()
-            t_setup.append(t1 - t0)
-            t_solve.append((t2 - t1) / 5)
-            sizes.append(s.size)
-        x = np.ones(prob.A.shape[0])
-        t0 = time.perf_counter()
-        for _ in range(5):
-            prob.A @ x
-        t_spmv = (time.perf_counter() - t0) / 5
-        nC = N * prob.nev
-        rng = np.random.default_rng(seed)
-        G = rng.standard_normal((nC, nC))
-        S = G @ G.T + nC * np.eye(nC)
-        t0 = time.perf_counter()
-        f = sla.cho_factor(S, lower=True) if prob.spd else sla.lu_factor(S)
-        t_chol = time.perf_counter() - t0
-        y = np.ones(nC)
-        t0 = time.perf_counter()
-        for _ in range(5):
-            sla.cho_solve(f, y) if prob.spd else sla.lu_solve(f, y)
-        t_csolve = (time.perf_counter() - t0) / 5
-    work = time.perf_counter() - t_begin
-    # the deflated composition does one more product with A per apply
-    est = N * float(np.mean(t_setup)) + t_chol + iters * (N * float(np.mean(t_solve)) + (1 + composition) * t_spmv
-                                                         + t_csolve)
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, cfg, composition=0, contexts=(), sample_iters=30):
+    """The FP64 oracle (oracle.pool: its per-subdomain work in one worker
+    process per host core, at most 16) on the same workload, and the apply
+    parity of the timed GPU contexts against it.
+
+    Timed: the oracle's full setup (overlap layers, A_ii, sparse LU, the
+    eq. gevpsvd / Section 6 coarse blocks of every subdomain, A_00 and its
+    factor) and `sample_iters` iterations of its own Krylov solve; the
+    solve time is scaled to the oracle's own iteration count on this
+    workload, read from tests/golden/oracle_fullsize.json (written by the
+    oracle alone), or to the measured count when the sample converges.
+
+    Then, for each (name, Preconditioner) in `contexts`: the library's own
+    coarse basis is imported into the oracle and the relative apply error
+    ||z_gpu - z_oracle|| / ||z_oracle|| is measured over three seeded r."""
+    import torch
+
+    from oracle import pool
+    t0 = time.perf_counter()
+    pl = pool.Pool(prob.A, prob.part, prob.overlap, prob.nev, spd=prob.spd)
+    t_setup = time.perf_counter() - t0
+    nc_oracle = pl.n_coarse
+    comp = "ras_deflated" if composition == 1 else "additive"
+    t0 = time.perf_counter()
+    _, it_s, rr_s = pl.solve(prob.b, 1e-8, maxit=sample_iters, composition=comp)
+    t_it = (time.perf_counter() - t0) / max(it_s, 1)
+    gold = None
+    if os.path.exists(GOLDEN) and prob.A.shape[0] == json.load(open(GOLDEN))["configs"].get(str(cfg), {}).get("n"):
+        gold = json.load(open(GOLDEN))["configs"][str(cfg)]
+    if rr_s <= 1e-8:
+        its, src = it_s, "converged within the sample"
+    elif gold is not None:
+        its, src = gold["iterations"], "the oracle's own full run (tests/golden/oracle_fullsize.json)"
+    else:
+        its, src = None, "unknown"
+    errors = {}
+    for name, pc in contexts:
+        pl.with_basis(pc.z_sparse())
+        worst = 0.0
+        for sd in (101, 102, 103):
+            r = np.random.default_rng(sd).standard_normal(prob.A.shape[0])
+            z = pc.apply(torch.as_tensor(r, device=pc.device))
+            torch.cuda.synchronize()
+            z_ref = pl.apply(r, comp)
+            worst = max(worst, float(np.linalg.norm(z.cpu().numpy() - z_ref) / np.linalg.norm(z_ref)))
+        errors[name] = worst
+    workers = pl.workers
+    pl.close()
+    value = round(t_setup + t_it * its, 2) if its is not None else None
     return {
-        "value": round(est, 2),
+        "value": value,
         "unit": "s",
-        "cores": 1,
+        "cores": workers,
         "kind": "oracle",
-        "sample": (f"{len(picks)} of {N} subdomains stratified by size (sizes {min(sizes)}..{max(sizes)}): "
-                   f"oracle setup {np.mean(t_setup):.3f} s and local solve {np.mean(t_solve) * 1e3:.2f} ms "
-                   f"per subdomain; A x {t_spmv * 1e3:.1f} ms; {'Cholesky' if prob.spd else 'LU'} of order {nC} "
-                   f"{t_chol:.2f} s, "
-                   f"its solve {t_csolve * 1e3:.2f} ms; scaled to N * setup + {iters} iterations; "
-                   f"{work:.1f} s of host work"),
-    }
+        "cpu": cpu_model(),
+        "sample": (f"full oracle setup of all {prob.n_parts} subdomains (coarse space n_C = {nc_oracle}) on "
+                   f"{workers} worker processes: {t_setup:.1f} s; {it_s} of its Krylov iterations: "
+                   f"{t_it * 1e3:.0f} ms each, scaled to {its} iterations ({src})"),
+        "oracle_iters": its,
+    }, errors
 
 
 WEAK_TAU2 = 0.41  # eq. gevpsvd threshold on lambda^2 (about 12 vectors per part at N = 2)
@@ -382,6 +381,54 @@ def decay_study():
                                    "boxes; delta 1, 3, 5; first 40 values"}, "decay": out}
 
 
+def warm_start_study(steps, warmup, precision):
+    """The learned warm start on config 4 (layered Q1 elasticity, 48^3 nodes,
+    512 boxes, overlap 1, nev 20) against the random start, each setup with
+    the benchmark's settings: the coarse-basis phase of the set-up (its
+    eigensolves and orthonormalization, and the network's inference when the
+    network is used), the subspace iterations, the eigen-residuals, the
+    whole set-up and the final PCG iterations. Times are medians over
+    `steps` setups after `warmup`."""
+    import torch
+
+    import paper_2401_03915_amd as tls
+    from paper_2401_03915_amd.gnn_train import TRAINED, load_weights
+    from workloads import make_config
+    w, c_out = load_weights(TRAINED)
+    p = make_config(4)
+    b = torch.as_tensor(p.b, device="cuda:0")
+    rows = {}
+    for name, kw in (("random_start", {}), ("learned_warm_start", {"gnn_weights": w})):
+        basis, infer, setup = [], [], []
+        for k in range(warmup + steps):
+            log(f"warm start study: {name} {k}")
+            pc = tls.Preconditioner(p.A, p.part, p.overlap, p.nev, precision=precision, local_inverse=1,
+                                    use_graph=1, **kw)
+            inf = pc.info()
+            if k >= warmup:
+                basis.append(inf["t_setup"][3])
+                infer.append(inf["t_setup"][4])
+                setup.append(inf["t_setup"][7])
+            if k == warmup + steps - 1:
+                _, it, rr, st = pc.solve(b, 1e-8)
+                torch.cuda.synchronize()
+                rows[name] = {"basis_phase_ms": round(float(np.median(basis)), 2),
+                              "inference_ms": round(float(np.median(infer)), 2),
+                              "setup_ms": round(float(np.median(setup)), 2),
+                              "eig_iters_mean": round(inf["eig_iters_mean"], 2), "eig_iters_max": inf["eig_iters_max"],
+                              "eig_resid_max": inf["eig_resid_max"], "pcg_iters": it, "relres": rr, "status": st}
+            pc.close()
+    r0, r1 = rows["random_start"], rows["learned_warm_start"]
+    return {"metric": "coarse-basis phase of the set-up with the learned warm start vs random start (cfg4)",
+            "value": r1["basis_phase_ms"], "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "higher_is_better": False, "data": "synthetic (seeded)",
+            "dtype": "f32-local/f64-outer" if precision == 1 else "f64",
+            "config": {"workload": WORKLOADS[4] + "; network 4 layers, hidden 32, "
+                                                  f"{c_out} output columns, trained on seeds 100-103"},
+            "random_start": r0, "learned_warm_start": r1,
+            "basis_phase_gain_ms": round(r0["basis_phase_ms"] - r1["basis_phase_ms"], 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -397,7 +444,10 @@ def main():
     ap.add_argument("--composition", type=int, default=None,
                     help="0: additive one-level + coarse (PCG for SPD); 1: RAS + deflated coarse correction (FGMRES); "
                          "default 1 for the saddle-point config 6, else 0")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the apply errors against the oracle)")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the mixed-precision run with one local refinement step")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run z = 1.0 * x over 1 GiB (reads 1 GiB, writes 1 GiB): the plain copy kernel "
@@ -406,6 +456,8 @@ def main():
                     help="comma-separated subdomain counts (powers of two): run the weak-scaling analog instead, "
                          "each count in a process of its own")
     ap.add_argument("--weak-scaling-one", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--warm-start", action="store_true",
+                    help="run the learned warm start against the random start on config 4 instead")
     ap.add_argument("--decay", action="store_true",
                     help="run the eigenvalue / singular value decay study against the overlap instead")
     args = ap.parse_args()
@@ -442,6 +494,9 @@ def main():
     if args.decay:
         print(json.dumps(decay_study()), flush=True)
         return
+    if args.warm_start:
+        print(json.dumps(warm_start_study(max(args.steps, 3), args.warmup, 1)), flush=True)
+        return
     log("generating workload")
     prob = make_config(args.config, seed=0, scale=args.scale)
     if args.composition is None:
@@ -471,6 +526,41 @@ def main():
     if not args.no_fp64:
         plain = run_mode(prob, dev_in, 0, args.steps, args.warmup, args.applies, args.graph, tune_cache,
                          args.composition, args.restart, args.local_inverse)
+    refined = None
+    if not args.no_refined:
+        refined = run_mode(prob, dev_in, 1, min(args.steps, 2), 1, args.applies, args.graph, tune_cache,
+                           args.composition, args.restart, args.local_inverse, local_refine=1)
+    import paper_2401_03915_amd as tls
+
+    def measured_ctx(precision, refine=0):
+        """A context with the timed run's options, for the SpMV timing and
+        the apply errors against the oracle."""
+        return tls.Preconditioner(A, prob.part, prob.overlap, prob.nev, precision=precision,
+                                  matrix_kind=0 if prob.spd else 1, composition=args.composition,
+                                  restart=args.restart, local_inverse=args.local_inverse, local_refine=refine,
+                                  use_graph=args.graph, autotune=1, tune_cache=tune_cache.encode())
+    # SpMV (one per Krylov iteration): launch time from events on the stream it runs on
+    pcm = measured_ctx(1)
+    xs = torch.randn(A.shape[0], dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(3))
+    ys = torch.empty_like(xs)
+    for _ in range(5):
+        pcm.spmv(xs, ys)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(pcm.stream)
+    n_spmv = 200
+    for _ in range(n_spmv):
+        pcm.spmv(xs, ys)
+    e1.record(pcm.stream)
+    torch.cuda.synchronize()
+    spmv_us = e0.elapsed_time(e1) * 1e3 / n_spmv
+    spmv_bytes = 12.0 * A.nnz + 4.0 * (A.shape[0] + 1) + 16.0 * A.shape[0]
+    spmv = {"kernel": "k_spmv (y = A x, CSR, FP64)", "bytes_per_launch": spmv_bytes,
+            "launch_us": round(spmv_us, 2), "launches_timed": n_spmv,
+            "achieved": round(spmv_bytes / (spmv_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(spmv_bytes / (spmv_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"spmv {spmv_us:.2f} us, {spmv['achieved']} GB/s")
     info = mixed["info"]
     # dominant kernel: the forward persistent triangular solve of the FP32
     # local factors (the backward one reads the same bytes in about the same
@@ -484,7 +574,7 @@ def main():
     default_workload = args.config == 2 and args.scale is None
     if inverse:
         roof = {"bound": "hbm",
-                "kernel": "k_symv<float> (product with the explicit local inverses of one apply, all subdomains)",
+                "kernel": "k_symv<float, 8> (product with the explicit local inverses of one apply, all subdomains)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": TRAFFIC_SYMV if default_workload else None,
@@ -563,9 +653,24 @@ def main():
             out["plain_fp64"]["setup_inverse_mfma"] = inverse_mfma(plain, "f64")
         out["speedup_mixed_vs_fp64"] = round(plain["ms_per_step"] / mixed["ms_per_step"], 3)
         out["apply_rel_diff_mixed_vs_fp64_own_bases"] = apply_err
+    if refined is not None:
+        out["mixed_refined"] = {"local_refine": 1, "time_to_solve_s": round(refined["ms_per_step"] / 1e3, 4),
+                                "iters": refined["iters"], "relres": refined["relres"],
+                                "applies_per_s": round(refined["applies_per_s"], 2)}
+    out["spmv"] = spmv
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(prob, (plain or mixed)["iters"], composition=args.composition)
+        log("cpu baseline (oracle) and apply errors against the oracle")
+        ctxs = [("mixed", pcm)]
+        if plain is not None:
+            ctxs.append(("plain_fp64", measured_ctx(0)))
+        if refined is not None:
+            ctxs.append(("mixed_refined", measured_ctx(1, 1)))
+        out["cpu_baseline"], errs = cpu_baseline(prob, args.config, args.composition, ctxs)
+        for name, _ in ctxs:
+            out[name]["apply_error_vs_oracle"] = errs[name]
+        for name, pc in ctxs[1:]:
+            pc.close()
+    pcm.close()
     print(json.dumps(out), flush=True)
 
 

@@ -118,8 +118,11 @@ typedef struct {
   int32_t solve_order;  /* task order of those solves: 1 level by level, 2 by the fraction of
                            the subdomain's rows done, 3 longest chain first, 4 / 5 as 2 with a
                            lead of 0.3 / 0.6 x nt_i / max nt for large subdomains; 0 = default (4) */
-  int32_t autotune;     /* 1: at setup, time candidate workgroup counts and task orders and keep
-                           the fastest (ignored when solve_wgs or solve_order is set) */
+  int32_t autotune;     /* 1: at setup, time candidates and keep the fastest: the panel width of
+                           the batched factorization (4, 8 or 16 tiles), the block side of the
+                           product with the local inverses (4, 6 or 8 tiles), and the workgroup
+                           count and task order of the persistent solves (not when solve_wgs or
+                           solve_order is set) */
   const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
                              NULL = no persistence. A cached pick is reused without timing. */
   /* Learned warm start (SPD only): host array of TLS_GNN_NWEIGHTS(gnn_c_out)
@@ -201,6 +204,10 @@ typedef struct {
                                  limit (its z is not valid); reading it clears it. tls_info
                                  waits for the context's stream to read it. */
   int32_t local_refine;       /* refinement steps of each local solve (option local_refine) */
+  int32_t symv_block;         /* block side (tiles) of the product with the local inverses
+                                 (4, 6 or 8; autotuned; 0 without local_inverse) */
+  int32_t factor_panel;       /* panel width (tiles) of the batched factorization
+                                 (4, 8 or 16; autotuned) */
 } tls_info_t;
 
 /* Fill *opt with the defaults listed above. */

@@ -23,6 +23,7 @@ rows I_i of each subdomain's block), so the configurations of the benchmark
 
 from __future__ import annotations
 
+import mmap
 import multiprocessing as mp
 import os
 
@@ -37,9 +38,16 @@ from . import krylov, schwarz
 _JOB: dict = {}
 
 
-def _worker(conn, ids):
+def _worker(conn, w, ids):
+    # one BLAS thread per worker: the workers already use every core
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:  # pragma: no cover
+        pass
     j = _JOB
     A, part, delta = j["A"], j["part"], j["delta"]
+    r, zw = j["r"], j["z"][w]
     G = schwarz.sym_pattern(A)
     subs, lus, out = [], [], []
     for i in ids:
@@ -51,21 +59,27 @@ def _worker(conn, ids):
         if j["blocks"]:
             blk = schwarz.coarse_block(Aii, s, j["nev"], j["nev1"], j["spd"], j["tau"], j["nu"], j["dense"])
         out.append((i, s.idx, s.n_interior, list(s.layer_sizes), blk))
-    conn.send(out)
-    n = A.shape[0]
+    touched = np.unique(np.concatenate([s.idx for s in subs])) if subs else np.zeros(0, dtype=np.int64)
+    conn.send((out, touched))
     while True:
-        msg = conn.recv()
-        if msg is None:
+        restricted = conn.recv()
+        if restricted is None:
             break
-        r, restricted = msg
-        z = np.zeros(n)
+        # this worker's sum, written to its own row of the shared array
+        zw[touched] = 0.0
         for s, lu in zip(subs, lus):
             zi = lu.solve(r[s.idx])
             if restricted:
                 zi = zi * s.D()
-            z[s.idx] += zi  # indices are distinct within one subdomain
-        conn.send(z)
+            zw[s.idx] += zi  # indices are distinct within one subdomain
+        conn.send(True)
     conn.close()
+
+
+def _shared(count: int) -> np.ndarray:
+    """float64 array in anonymous shared memory (shared with forked workers)."""
+    buf = mmap.mmap(-1, max(count, 1) * 8)
+    return np.frombuffer(buf, dtype=np.float64, count=count)
 
 
 def default_workers() -> int:
@@ -99,21 +113,28 @@ class Pool:
         sizes = np.bincount(part, minlength=N)
         order = np.argsort(-sizes, kind="stable")
         ids = [order[w::self.workers].tolist() for w in range(self.workers)]
+        # r and the workers' partial sums live in shared memory; the pipes
+        # carry only the set-up results and one flag per apply
+        self._r = _shared(self.n)
+        self._z = _shared(self.workers * self.n).reshape(self.workers, self.n)
         _JOB.clear()
         _JOB.update(A=A, part=part, delta=overlap_layers, nev=nev, nev1=nev1, spd=spd, tau=tau, nu=nu,
-                    dense=dense, blocks=Z is None)
+                    dense=dense, blocks=Z is None, r=self._r, z=self._z)
         ctx = mp.get_context("fork")
         self._conns, self._procs = [], []
         for w in range(self.workers):
             a, b = ctx.Pipe()
-            p = ctx.Process(target=_worker, args=(b, ids[w]), daemon=True)
+            p = ctx.Process(target=_worker, args=(b, w, ids[w]), daemon=True)
             p.start()
             b.close()
             self._conns.append(a)
             self._procs.append(p)
         got = {}
+        self._touched = []
         for c in self._conns:
-            for i, idx, nI, layers, blk in c.recv():
+            out, touched = c.recv()
+            self._touched.append(touched)
+            for i, idx, nI, layers, blk in out:
                 got[i] = (schwarz.Subdomain(idx, nI, layers), blk)
         _JOB.clear()
         self.subs = [got[i][0] for i in range(N)]
@@ -157,12 +178,14 @@ class Pool:
     def one_level(self, r: np.ndarray, restricted: bool = False) -> np.ndarray:
         """sum_i R_i^T A_ii^{-1} R_i r (eq. onelevelasm), or with D_i
         (eq. onelevelras)."""
-        r = np.ascontiguousarray(r, dtype=np.float64)
+        self._r[:] = r
         for c in self._conns:
-            c.send((r, restricted))
+            c.send(bool(restricted))
+        for c in self._conns:
+            c.recv()
         z = np.zeros(self.n)
-        for c in self._conns:
-            z += c.recv()
+        for w, t in enumerate(self._touched):
+            z[t] += self._z[w, t]
         return z
 
     def coarse_correction(self, r: np.ndarray) -> np.ndarray:

@@ -104,6 +104,8 @@ class tls_info_t(C.Structure):
         ("t_inverse_ms", C.c_double),
         ("wait_timeout", C.c_int32),
         ("local_refine", C.c_int32),
+        ("symv_block", C.c_int32),
+        ("factor_panel", C.c_int32),
     ]
 
 

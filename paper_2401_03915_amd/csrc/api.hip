@@ -142,7 +142,8 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     }
     TLS_HIP(hipMemcpyAsync(c->part.p, part, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
     double avg = (double)nnz / n;
-    c->spmv_group = avg <= 6 ? 4 : avg <= 12 ? 8 : avg <= 24 ? 16 : avg <= 48 ? 32 : 64;
+    // short rows: row blocks streamed through LDS (0); longer ones: G lanes per row
+    c->spmv_group = avg <= 12 ? 0 : avg <= 24 ? 16 : avg <= 48 ? 32 : 64;
 
     auto t = clk::now();
     tls::validate_input(c.get());
@@ -153,10 +154,10 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     c->t_setup[0] = ms_since(t);
     t = clk::now();
     tls::gather_local(c.get(), dist);
-    dist.release();
     c->t_setup[1] = ms_since(t);
     t = clk::now();
-    tls::factor_local(c.get());
+    tls::factor_local_tuned(c.get(), dist);
+    dist.release();
     c->t_setup[6] = ms_since(t);
     tls::build_solve_tasks(c.get());
     c->t_setup[2] = ms_since(t);
@@ -177,6 +178,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     }
     tls::build_refine(c.get());
     tls::choose_solve_grid(c.get());
+    tls::choose_symv_block(c.get());
     TLS_HIP(hipStreamSynchronize(s));
     c->t_setup[7] = ms_since(t_all);
   });
@@ -265,6 +267,8 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->solve_order = c->solve_order;
   info->tuned = c->tuned;
   info->local_refine = c->refine;
+  info->symv_block = c->inv_formed ? c->symv_block : 0;
+  info->factor_panel = c->factor_panel;
   tls_ctx* cm = const_cast<tls_ctx*>(c);
   bool wt = cm->apply_wait_seen;
   if (guard(cm, [&]() { wt = tls::take_wait_flag(cm) || wt; }) != TLS_OK) return TLS_E_HIP;

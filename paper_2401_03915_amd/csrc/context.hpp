@@ -20,7 +20,7 @@ struct tls_ctx {
   tls::DBuf<int> row_ptr, col_idx, part;
   tls::DBuf<double> val;
   tls::DBuf<int> trow_ptr, tcol_idx;  // pattern of A^T (general matrices)
-  int spmv_group = 4;
+  int spmv_group = 0;  // 0: row-block SpMV through LDS; G > 0: G lanes per row
 
   // overlap: Omega_i lists (global ids) in [I, Gamma_1, .., Gamma_delta] order
   std::vector<int> h_sub_ptr;    // N+1
@@ -48,6 +48,8 @@ struct tls_ctx {
   // explicit inverses (option local_inverse): the symmetric-product work
   // lists of the local matrices and of A_0
   bool inv_formed = false, inv0_formed = false;
+  int symv_block = 8;      // block side (tiles) of the symmetric product with the local inverses
+  int factor_panel = 8;    // panel width (tiles) of the batched factorization
   double t_inverse = 0.0;
   tls::SymvWork inv_work, inv0_work;
 

@@ -610,8 +610,7 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
 // then the trailing square once with K = 64 PW (mode 0).
 template <class T>
 void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
-                     int* err) {
-  constexpr int PW = 8;
+                     int* err, int PW = 8) {
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
@@ -697,8 +696,7 @@ void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const Loc
 // its read-modify-write traffic by PW.
 template <class T>
 void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
-                  int* err) {
-  constexpr int PW = 8;
+                  int* err, int PW = 8) {
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
@@ -1529,8 +1527,9 @@ __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ 
 }
 
 // y_i = S_i x_i for every subdomain. The lower tiles are cut into blocks of
-// B x B tiles (block row R, block column C <= R; B = SYMV_B, or 4 for a
-// single matrix, which then has enough blocks to fill the GPU); one workgroup
+// B x B tiles (block row R, block column C <= R; B = 8 by default, or 4 for
+// a single matrix, which then has enough blocks to fill the GPU; the
+// autotuner may pick 4, 6 or 8 for the local inverses); one workgroup
 // streams one block row by row (the tiles of a row are consecutive in
 // storage). Thread t holds rows 4 (t % 16) + w and columns t / 16 + 16 u
 // (w, u = 0..3) of each tile (four 16-byte non-temporal loads). For each
@@ -1541,8 +1540,6 @@ __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ 
 // a 64-value vector per tile: interleaved with the read stream, writes cost
 // far more than their size. k_symv_reduce adds the partial sums of each row
 // in a fixed order.
-constexpr int SYMV_B = 8;
-
 // One block: subdomain factor at foff, x at voff; tile rows [r0, r1), tile
 // columns [c0, c1) (only c <= r is stored); its partial sums at
 // out * B * TS in the row and column arrays.
@@ -1816,14 +1813,18 @@ void factor_local(tls_ctx* c) {
     c->dinv64.alloc((size_t)c->sum_nt * TS2);
   if (c->kind == 0) {
     if (c->fp32)
-      factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p);
+      factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p,
+                          c->factor_panel);
     else
-      factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p);
+      factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p,
+                           c->factor_panel);
   } else {
     if (c->fp32)
-      factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p);
+      factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p,
+                             c->factor_panel);
     else
-      factor_tiles_lu<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p);
+      factor_tiles_lu<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p,
+                              c->factor_panel);
   }
   int err = download(c->errflag.p, 1, c->stream)[0];
   if (err & ERR_PIVOT) {
@@ -2111,7 +2112,7 @@ void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const 
 // tiles, the largest matrices first, one reduction row per tile row.
 void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& nt,
                      const std::vector<int64_t>& foff, const std::vector<int64_t>& voff, bool fp32, int block) {
-  if (block != 4 && block != SYMV_B) fail(TLS_E_ARG, "symmetric-product blocks of 4 or 8 tiles");
+  if (block != 4 && block != 6 && block != 8) fail(TLS_E_ARG, "symmetric-product blocks of 4, 6 or 8 tiles");
   const int SB = block;
   w.block = block;
   std::vector<int> order(N);
@@ -2179,7 +2180,7 @@ void form_local_inverse(tls_ctx* c) {
     form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p);
   else
     form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p);
-  build_symv_work(c->inv_work, s, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32);
+  build_symv_work(c->inv_work, s, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32, c->symv_block);
   c->inv_formed = true;
 }
 
@@ -2192,8 +2193,8 @@ template <class T>
 void symv_solve_t(hipStream_t s, const SymvWork& w, const T* S, T* x, T* RP, T* CP, const int* done,
                   hipEvent_t ev_begin, hipEvent_t ev_mid, hipEvent_t ev_end) {
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
-  auto prod = w.block == 4 ? k_symv<T, 4> : k_symv<T, SYMV_B>;
-  auto reduce = w.block == 4 ? k_symv_reduce<T, 4> : k_symv_reduce<T, SYMV_B>;
+  auto prod = w.block == 4 ? k_symv<T, 4> : w.block == 6 ? k_symv<T, 6> : k_symv<T, 8>;
+  auto reduce = w.block == 4 ? k_symv_reduce<T, 4> : w.block == 6 ? k_symv_reduce<T, 6> : k_symv_reduce<T, 8>;
   if (w.nblocks > 0)
     hipLaunchKernelGGL(prod, dim3((unsigned)w.nblocks), dim3(256), 0, s,
                        reinterpret_cast<const SymvBlock*>(w.blocks.p), S, x, RP, CP, done);

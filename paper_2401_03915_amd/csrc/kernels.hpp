@@ -80,8 +80,13 @@ double gnn_loss_grad(tls_ctx* c, const float* w_host, int c_out, float* grad_hos
 void gnn_take_rows(tls_ctx* c, const std::vector<int>& nT, const std::vector<int>& act,
                    const std::vector<int64_t>& off, int c0, double* out);
 
-// tune.hip: workgroup count of the persistent solves (default / timed / cached)
+// tune.hip: autotuned launch shapes (default / timed / cached)
+// workgroup count and task order of the persistent solves
 void choose_solve_grid(tls_ctx* c);
+// block side of the symmetric product with the local inverses (after form_local_inverse)
+void choose_symv_block(tls_ctx* c);
+// the batched factorization with its panel width picked (gathers again per candidate)
+void factor_local_tuned(tls_ctx* c, const DBuf<uint8_t>& dist);
 
 // refine.hip: iterative refinement of the FP32 local solves (option local_refine)
 void build_refine(tls_ctx* c);

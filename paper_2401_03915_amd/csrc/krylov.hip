@@ -16,26 +16,22 @@ namespace tls {
 
 namespace {
 
+// Reductions run on red_grid(n) <= RED_BLOCKS blocks of 256 threads (each
+// thread with four loads in flight): the last block is found with one
+// same-address atomic per block, and on this GPU those serialize at about
+// 10 ns each (4096 of them cost ~37 us), so the grid is kept small.
 constexpr int RED_BLOCKS = 512;
+inline int red_grid(int n) { return std::max(1, std::min(RED_BLOCKS, (n + 2047) / 2048)); }
 
-// y = A x, or y = f - A x when f is given; G lanes per row
-template <int G>
-__global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                              const double* __restrict__ val, const double* __restrict__ x,
-                                              double* __restrict__ y, const int* __restrict__ done,
-                                              const double* __restrict__ f) {
-  if (*done) return;
-  const int lane = threadIdx.x % G;
-  const int row = blockIdx.x * (256 / G) + threadIdx.x / G;
-  double s = 0.0;
-  if (row < n) {
-    const int b = rp[row + 1];
-    for (int j = rp[row] + lane; j < b; j += G) s += val[j] * x[ci[j]];
-  }
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
-  if (row < n && lane == 0) y[row] = f ? f[row] - s : s;
-}
+// SpMV by row blocks: a block of SPMV_ROWS consecutive rows streams its
+// stored entries (values and columns) with consecutive threads on
+// consecutive entries, keeps the products in LDS and then sums each row's
+// products in the stored order; rows whose block holds more than SPMV_CAP
+// entries are done one thread per row instead. Short rows (the 5- and
+// 7-point stencils) are read fully coalesced this way.
+constexpr int SPMV_ROWS = 256;
+constexpr int SPMV_CAP = 2048;
+inline int spmv_blocks(int n) { return (n + SPMV_ROWS - 1) / SPMV_ROWS; }
 
 __device__ inline void block_reduce_store(double v, double* out) {
   __shared__ double red[4];
@@ -45,29 +41,142 @@ __device__ inline void block_reduce_store(double v, double* out) {
   if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Dot products in one launch of RED_BLOCKS blocks: each block stores its
-// partial sum; the last block to finish (counted in *ctr, which it resets)
-// adds the partials in index order and stores the result, so the value
-// does not depend on the order in which the blocks ran.
+// Each reduction is one launch: every block stores its partial sum; the last
+// block to finish (counted in *ctr, which it resets) adds the partials in
+// index order and stores the result, so the value does not depend on the
+// order in which the blocks ran. The partials and the counter are device-
+// coherent accesses (relaxed agent-scope atomics, which bypass the per-XCD
+// L2): a block waits for its partial's store to complete before it counts
+// itself, and the last block reads the partials with coherent loads. No
+// cache write-back or invalidation is needed (an agent-scope fence in every
+// block wrote back the XCD's L2 each time and made a 4096-block SpMV with
+// its dot product five times slower).
+__device__ inline void block_reduce_partial(double v, double* partial) {
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(partial + blockIdx.x, (red[0] + red[1]) + (red[2] + red[3]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);  // the coherent store has completed before the block is counted
+  }
+}
+
 __device__ inline bool last_block(unsigned* ctr) {
   __shared__ bool s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();  // this block's partial is visible before it is counted
-    s_last = atomicAdd(ctr, 1u) == gridDim.x - 1;
+    s_last = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    if (s_last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  if (s_last) {
-    __threadfence();  // every counted partial is visible to the last block
-    if (threadIdx.x == 0) *ctr = 0u;
-  }
   return s_last;
 }
 
-__device__ inline void sum_partials(const double* partial, double* out) {
+// the partials in index order (coherent loads), into *out
+__device__ inline void sum_partials(const double* partial, int count, double* out) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) s += partial[i];
+  for (int i = threadIdx.x; i < count; i += 256) s += __hip_atomic_load(partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   block_reduce_store(s, out);
+}
+
+// y = A x, or y = f - A x when f is given. With pq (PCG): also p.q for
+// x = p, y = q into scal[2] (a non-positive p.q stops the iteration:
+// breakdown), and scal[1] = scal[4] (the r.z of the previous iteration
+// becomes the current one).
+__global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const double* __restrict__ val, const double* __restrict__ x,
+                                              double* __restrict__ y, const int* __restrict__ done,
+                                              const double* __restrict__ f, int pq, double* partial,
+                                              unsigned* ctr, double* scal, int* dflag) {
+  if (*done) return;
+  __shared__ double prod[SPMV_CAP];
+  __shared__ int srp[SPMV_ROWS + 1];
+  double mine = 0.0;  // this thread's rows (pq only)
+  const int nblk = (n + SPMV_ROWS - 1) / SPMV_ROWS;
+  for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int r0 = blk * SPMV_ROWS;
+    const int nr = min(n - r0, SPMV_ROWS);
+    __syncthreads();  // the previous row block is done with srp and prod
+    for (int t = threadIdx.x; t <= nr; t += 256) srp[t] = rp[r0 + t];
+    __syncthreads();
+    const int j0 = srp[0], nz = srp[nr] - j0;
+    if (nz <= SPMV_CAP) {
+      for (int t = threadIdx.x; t < nz; t += 256) {
+        const int j = j0 + t;
+        prod[t] = __builtin_nontemporal_load(val + j) * x[__builtin_nontemporal_load(ci + j)];
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < nr; r += 256) {
+        double s = 0.0;
+        for (int t = srp[r] - j0; t < srp[r + 1] - j0; t++) s += prod[t];
+        const double v = f ? f[r0 + r] - s : s;
+        y[r0 + r] = v;
+        if (pq) mine += x[r0 + r] * v;
+      }
+    } else {
+      for (int r = threadIdx.x; r < nr; r += 256) {
+        double s = 0.0;
+        for (int j = srp[r]; j < srp[r + 1]; j++) s += val[j] * x[ci[j]];
+        const double v = f ? f[r0 + r] - s : s;
+        y[r0 + r] = v;
+        if (pq) mine += x[r0 + r] * v;
+      }
+    }
+  }
+  if (!pq) return;
+  block_reduce_partial(mine, partial);
+  if (last_block(ctr)) {
+    sum_partials(partial, gridDim.x, scal + 2);
+    if (threadIdx.x == 0) {
+      scal[1] = scal[4];
+      if (!(scal[2] > 0.0)) {
+        dflag[0] = 1;
+        dflag[3] = 1;
+      }
+    }
+  }
+}
+
+// Longer rows: G lanes per row and a shuffle reduction.
+template <int G>
+__global__ void __launch_bounds__(256) k_spmv_group(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const double* __restrict__ val, const double* __restrict__ x,
+                                                    double* __restrict__ y, const int* __restrict__ done,
+                                                    const double* __restrict__ f, int pq, double* partial,
+                                                    unsigned* ctr, double* scal, int* dflag) {
+  if (*done) return;
+  const int lane = threadIdx.x % G;
+  const int nrb = (n + 256 / G - 1) / (256 / G);
+  double mine = 0.0;
+  for (int rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+    const int row = rb * (256 / G) + threadIdx.x / G;
+    double s = 0.0;
+    if (row < n) {
+      const int b = rp[row + 1];
+      for (int j = rp[row] + lane; j < b; j += G) s += val[j] * x[ci[j]];
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+    if (row < n && lane == 0) {
+      const double v = f ? f[row] - s : s;
+      y[row] = v;
+      if (pq) mine += x[row] * v;
+    }
+  }
+  if (!pq) return;
+  block_reduce_partial(mine, partial);
+  if (last_block(ctr)) {
+    sum_partials(partial, gridDim.x, scal + 2);
+    if (threadIdx.x == 0) {
+      scal[1] = scal[4];
+      if (!(scal[2] > 0.0)) {
+        dflag[0] = 1;
+        dflag[3] = 1;
+      }
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
@@ -75,45 +184,70 @@ __global__ void __launch_bounds__(256) k_dot(int n, const double* __restrict__ a
                                              const int* __restrict__ done) {
   if (*done) return;
   double s = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) s += a[i] * b[i];
-  block_reduce_store(s, partial + blockIdx.x);
-  if (last_block(ctr)) sum_partials(partial, out);
+  const int st = gridDim.x * 256;
+  for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * st)
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int i = i0 + u * st;
+      if (i < n) s += a[i] * b[i];
+    }
+  block_reduce_partial(s, partial);
+  if (last_block(ctr)) sum_partials(partial, gridDim.x, out);
 }
 
-// pq = p.q into scal[2]; a non-positive pq stops the iteration (breakdown)
-__global__ void __launch_bounds__(256) k_dot_pq(int n, const double* __restrict__ p, const double* __restrict__ q,
-                                                double* partial, unsigned* ctr, double* scal, int* done) {
-  if (done[0]) return;
-  double s = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) s += p[i] * q[i];
-  block_reduce_store(s, partial + blockIdx.x);
-  if (last_block(ctr)) {
-    sum_partials(partial, scal + 2);
-    if (threadIdx.x == 0 && !(scal[2] > 0.0)) {
-      done[0] = 1;
-      done[3] = 1;
+// r.z into scal[4] and, for the flexible variant, r.zold into scal[5], in one pass
+__global__ void __launch_bounds__(256) k_dot_rz(int n, const double* __restrict__ r, const double* __restrict__ z,
+                                                const double* __restrict__ zold, double* partial, unsigned* ctr,
+                                                double* scal, const int* __restrict__ done) {
+  if (*done) return;
+  double s = 0.0, t = 0.0;
+  const int st = gridDim.x * 256;
+  for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * st)
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int i = i0 + u * st;
+      if (i < n) {
+        const double ri = r[i];
+        s += ri * z[i];
+        if (zold) t += ri * zold[i];
+      }
     }
+  block_reduce_partial(s, partial);
+  __syncthreads();
+  if (zold) block_reduce_partial(t, partial + RED_BLOCKS);
+  if (last_block(ctr)) {
+    sum_partials(partial, gridDim.x, scal + 4);
+    __syncthreads();
+    if (zold) sum_partials(partial + RED_BLOCKS, gridDim.x, scal + 5);
   }
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; r.r into scal[3]; then the
-// last block records ||r||/||b|| and stops on the tolerance or the cap
+// alpha = rz / pq; x += alpha p; r -= alpha q; [zold = z]; r.r into scal[3];
+// then the last block records ||r||/||b|| and stops on the tolerance or the cap
 __global__ void __launch_bounds__(256) k_pcg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                     const double* __restrict__ p, const double* __restrict__ q,
+                                                    const double* __restrict__ z, double* __restrict__ zold,
                                                     double* scal, double* partial, unsigned* ctr, int* done,
                                                     double* hist, int maxit, double tol2) {
   if (done[0]) return;
   const double alpha = scal[1] / scal[2];
   double s = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += RED_BLOCKS * 256) {
-    x[i] += alpha * p[i];
-    double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    s += ri * ri;
-  }
-  block_reduce_store(s, partial + blockIdx.x);
+  const int st = gridDim.x * 256;
+  for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * st)
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int i = i0 + u * st;
+      if (i < n) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        s += ri * ri;
+        if (zold) zold[i] = z[i];
+      }
+    }
+  block_reduce_partial(s, partial);
   if (last_block(ctr)) {
-    sum_partials(partial, scal + 3);
+    sum_partials(partial, gridDim.x, scal + 3);
     if (threadIdx.x == 0) {
       const int it = ++done[1];
       const double rr = scal[3], bb = scal[0];
@@ -128,22 +262,12 @@ __global__ void __launch_bounds__(256) k_pcg_update(int n, double* __restrict__ 
   }
 }
 
-__global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b, const int* __restrict__ done) {
-  if (*done) return;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) b[i] = a[i];
-}
-
 // beta = (r.z - [r.zold]) / rz_prev ; p = z + beta p
 __global__ void k_pcg_p(int n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ scal,
                         int flexible, const int* __restrict__ done) {
   if (*done) return;
   const double beta = (scal[4] - (flexible ? scal[5] : 0.0)) / scal[1];
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = z[i] + beta * p[i];
-}
-
-__global__ void k_pcg_shift(double* scal, const int* __restrict__ done) {
-  if (*done) return;
-  scal[1] = scal[4];
 }
 
 __global__ void k_sub(int n, const double* __restrict__ b, const double* __restrict__ q, double* __restrict__ r) {
@@ -163,8 +287,52 @@ bool take_wait_flag(tls_ctx* c) {
 
 namespace {
 
+// blocks of the SpMV launch; with p.q (its number of partial sums) the
+// row-block kernel loops over row blocks on at most RED_BLOCKS blocks
+int spmv_grid(const tls_ctx* c, bool pq) {
+  const int nb = c->spmv_group == 0 ? spmv_blocks(c->n) : div_up(c->n, 256 / c->spmv_group);
+  return pq ? std::min(nb, RED_BLOCKS) : nb;
+}
+
+// y = A x (or f - A x); with w (PCG): also p.q, the breakdown check and the r.z shift
+void spmv_launch(tls_ctx* c, const double* f, const double* x, double* y, const int* done, const KWork* w) {
+  hipStream_t s = c->stream;
+  const int n = c->n;
+  const dim3 grid(spmv_grid(c, w != nullptr));
+  const int pq = w ? 1 : 0;
+  double* partial = w ? w->partial : nullptr;
+  unsigned* ctr = w ? w->redctr : nullptr;
+  double* scal = w ? w->scal : nullptr;
+  int* dflag = w ? w->done : nullptr;
+  const int *rp = c->row_ptr.p, *ci = c->col_idx.p;
+  const double* val = c->val.p;
+  switch (c->spmv_group) {
+    case 0:
+      hipLaunchKernelGGL(k_spmv, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr, scal, dflag);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_spmv_group<8>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr, scal,
+                         dflag);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_spmv_group<16>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr,
+                         scal, dflag);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_spmv_group<32>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr,
+                         scal, dflag);
+      break;
+    default:
+      hipLaunchKernelGGL(k_spmv_group<64>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr,
+                         scal, dflag);
+      break;
+  }
+  TLS_LAUNCH_CHECK();
+}
+
 void dot(tls_ctx* c, const KWork& w, const double* a, const double* b, double* out, const int* done) {
-  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->n, a, b, w.partial, w.redctr, out, done);
+  hipLaunchKernelGGL(k_dot, dim3(red_grid(c->n)), dim3(256), 0, c->stream, c->n, a, b, w.partial, w.redctr, out,
+                     done);
   TLS_LAUNCH_CHECK();
 }
 
@@ -178,22 +346,23 @@ PcgVec vecs(const tls_ctx* c, const KWork& w) {
   return PcgVec{k, k + n, k + 2 * n, k + 3 * n, k + 4 * n, k + 5 * n, k + 6 * n};
 }
 
+// One PCG iteration in five launches besides the preconditioner:
+//   q = A p with p.q (and rz <- rz_new) | alpha, x, r, r.r, convergence [, zold = z]
+//   | z = M^{-1} r | r.z [, r.zold] | p = z + beta p
 void pcg_iteration(tls_ctx* c, const KWork& w, const PcgVec& v, int maxit, double tol2, bool flexible) {
   hipStream_t s = c->stream;
   const int* done = w.done;
   const int n = c->n;
   const int vg = std::min(4096, div_up(n, 256));
-  spmv(c, v.p, v.q, done);
-  hipLaunchKernelGGL(k_dot_pq, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.p, v.q, w.partial, w.redctr, w.scal, w.done);
-  hipLaunchKernelGGL(k_pcg_update, dim3(RED_BLOCKS), dim3(256), 0, s, n, v.x, v.r, v.p, v.q, w.scal, w.partial,
-                     w.redctr, w.done, w.hist, maxit, tol2);
+  const dim3 rg(red_grid(n));
+  spmv_launch(c, nullptr, v.p, v.q, done, &w);
+  hipLaunchKernelGGL(k_pcg_update, rg, dim3(256), 0, s, n, v.x, v.r, v.p, v.q, v.z, flexible ? v.zold : nullptr,
+                     w.scal, w.partial, w.redctr, w.done, w.hist, maxit, tol2);
   TLS_LAUNCH_CHECK();
-  if (flexible) hipLaunchKernelGGL(k_copy, dim3(vg), dim3(256), 0, s, n, v.z, v.zold, done);
   apply_precond(c, v.r, v.z, done);
-  dot(c, w, v.r, v.z, w.scal + 4, done);
-  if (flexible) dot(c, w, v.r, v.zold, w.scal + 5, done);
+  hipLaunchKernelGGL(k_dot_rz, rg, dim3(256), 0, s, n, v.r, v.z, flexible ? v.zold : nullptr, w.partial, w.redctr,
+                     w.scal, done);
   hipLaunchKernelGGL(k_pcg_p, dim3(vg), dim3(256), 0, s, n, v.p, v.z, w.scal, flexible ? 1 : 0, done);
-  hipLaunchKernelGGL(k_pcg_shift, dim3(1), dim3(1), 0, s, w.scal, done);
   TLS_LAUNCH_CHECK();
 }
 
@@ -354,31 +523,7 @@ __global__ void k_gm_update_x(int n, double* x, const double* __restrict__ Zb, c
 }  // namespace
 
 void spmv_residual(tls_ctx* c, const double* f, const double* x, double* y, const int* done) {
-  hipStream_t s = c->stream;
-  const int n = c->n;
-  const int G = c->spmv_group;
-  const unsigned grid = div_up(n, 256 / G);
-  switch (G) {
-    case 4:
-      hipLaunchKernelGGL(k_spmv<4>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done, f);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_spmv<8>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done, f);
-      break;
-    case 16:
-      hipLaunchKernelGGL(k_spmv<16>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done,
-                         f);
-      break;
-    case 32:
-      hipLaunchKernelGGL(k_spmv<32>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done,
-                         f);
-      break;
-    default:
-      hipLaunchKernelGGL(k_spmv<64>, dim3(grid), dim3(256), 0, s, n, c->row_ptr.p, c->col_idx.p, c->val.p, x, y, done,
-                         f);
-      break;
-  }
-  TLS_LAUNCH_CHECK();
+  spmv_launch(c, f, x, y, done, nullptr);
 }
 
 void spmv(tls_ctx* c, const double* x, double* y, const int* done) { spmv_residual(c, nullptr, x, y, done); }
@@ -420,7 +565,7 @@ void pcg_run(tls_ctx* c, const KWork& w, const double* b, double* x, double tol,
     return;
   }
   apply_precond(c, v.r, v.z, w.done);
-  dot(c, w, v.r, v.z, w.scal + 1, w.done);
+  dot(c, w, v.r, v.z, w.scal + 4, w.done);  // the first SpMV makes it the current r.z
   TLS_HIP(hipMemcpyAsync(v.p, v.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   const int chunk = 8;
   // the captured graph refers to the context's own work buffers
@@ -475,7 +620,7 @@ void pcg_run(tls_ctx* c, const KWork& w, const double* b, double* x, double tol,
     TLS_HIP(hipMemsetAsync(w.done + 2, 0, sizeof(int), s));
     TLS_HIP(hipMemsetAsync(v.zold, 0, sizeof(double) * n, s));
     apply_precond(c, v.r, v.z, w.done);
-    dot(c, w, v.r, v.z, w.scal + 1, w.done);
+    dot(c, w, v.r, v.z, w.scal + 4, w.done);
     TLS_HIP(hipMemcpyAsync(v.p, v.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   }
   TLS_HIP(hipMemcpyAsync(x, v.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -603,12 +748,12 @@ KrylovNeeds krylov_needs(const tls_ctx* c) {
   k.hist = krylov_maxit(c);
   if (use_pcg(c)) {
     k.kr = (size_t)7 * c->n;
-    k.partial = RED_BLOCKS;
+    k.partial = (size_t)std::max(2 * RED_BLOCKS, spmv_grid(c, true));
     k.gm = 0;
   } else {
     const int m = gmres_m(c);
     k.kr = (size_t)c->n * (6 + (m + 1) + m);
-    k.partial = (size_t)std::max(RED_BLOCKS, MD_BLOCKS * (m + 1));
+    k.partial = (size_t)std::max({2 * RED_BLOCKS, MD_BLOCKS * (m + 1), spmv_grid(c, true)});
     k.gm = (size_t)GmLayout(m).total;
   }
   return k;

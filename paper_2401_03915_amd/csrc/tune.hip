@@ -1,6 +1,14 @@
-// Launch shape of the persistent triangular solves: workgroup count and
-// task order.
+// Autotuned launch shapes, each picked at setup by timing the candidates
+// (autotune = 1) and kept in a text cache keyed by the problem's shape
+// (tune_cache): a cached pick is reused without timing.
 //
+// 1. Persistent triangular solves: workgroup count and task order.
+// 2. Symmetric product with the explicit local inverses: block side of
+//    4, 6 or 8 tiles (partial sums per block against workgroups in flight).
+// 3. Batched factorization: panel width of 4, 8 or 16 tile columns (the
+//    trailing update's K = 64 x width against the number of launches).
+//
+// Triangular solves:
 // The solves are bound by HBM bandwidth and by how many tiles are in flight,
 // which depends on how many workgroups are resident, and, for uneven
 // subdomains, by the dependency chain of the largest one, which depends on
@@ -14,6 +22,7 @@
 // are appended to a text cache keyed by the problem's shape and reused
 // without timing when the key is present.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <fstream>
 #include <sstream>
@@ -35,6 +44,43 @@ int cu_count() {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   return cus > 0 ? cus : 256;
+}
+
+// the last line of the cache whose key matches, as `count` integers
+bool cache_lookup_ints(const char* path, const std::string& key, int* v, int count) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    auto tab = line.rfind('\t');
+    if (tab == std::string::npos || line.substr(0, tab) != key) continue;
+    std::istringstream in(line.substr(tab + 1));
+    std::vector<int> got(count);
+    bool ok = true;
+    for (int k = 0; k < count && ok; k++) ok = static_cast<bool>(in >> got[k]);
+    if (ok) {
+      std::copy(got.begin(), got.end(), v);
+      found = true;
+    }
+  }
+  return found;
+}
+
+void cache_store_ints(const char* path, const std::string& key, const int* v, int count) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  if (!f) return;
+  f << key << '\t';
+  for (int k = 0; k < count; k++) f << (k ? " " : "") << v[k];
+  f << '\n';
+}
+
+std::string shape_key(const tls_ctx* c, const char* what) {
+  std::ostringstream k;
+  k << what << " prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
+    << " sumM=" << c->sum_M << " maxnt=" << c->max_nt;
+  return k.str();
 }
 
 bool cache_lookup(const char* path, const std::string& key, int* grid, int* order) {
@@ -82,7 +128,90 @@ double time_local_solves(tls_ctx* c, int grid, int reps) {
   return ms / reps;
 }
 
+double time_symv(tls_ctx* c, int reps) {
+  hipEvent_t e0, e1;
+  TLS_HIP(hipEventCreate(&e0));
+  TLS_HIP(hipEventCreate(&e1));
+  local_solve(c, c->zero_int.p);  // warm-up
+  TLS_HIP(hipEventRecord(e0, c->stream));
+  for (int k = 0; k < reps; k++) local_solve(c, c->zero_int.p);
+  TLS_HIP(hipEventRecord(e1, c->stream));
+  TLS_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  TLS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
 }  // namespace
+
+void choose_symv_block(tls_ctx* c) {
+  if (!c->opt.autotune || !c->inv_formed) return;
+  const std::string key = shape_key(c, "symv:v1");
+  int b = 0;
+  if (cache_lookup_ints(c->opt.tune_cache, key, &b, 1) && (b == 4 || b == 6 || b == 8)) {
+    if (b != c->symv_block) {
+      c->symv_block = b;
+      build_symv_work(c->inv_work, c->stream, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32, b);
+    }
+    c->tuned = std::max(c->tuned, 2);
+    return;
+  }
+  double best = 1e300;
+  int best_b = c->symv_block;
+  for (int cand : {4, 6, 8}) {
+    c->symv_block = cand;
+    build_symv_work(c->inv_work, c->stream, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32, cand);
+    const double t = time_symv(c, 5);
+    if (t < best) {
+      best = t;
+      best_b = cand;
+    }
+  }
+  if (best_b != c->symv_block) {
+    c->symv_block = best_b;
+    build_symv_work(c->inv_work, c->stream, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32, best_b);
+  }
+  c->tuned = 1;
+  cache_store_ints(c->opt.tune_cache, key, &best_b, 1);
+}
+
+void factor_local_tuned(tls_ctx* c, const DBuf<uint8_t>& dist) {
+  if (!c->opt.autotune) {
+    factor_local(c);
+    return;
+  }
+  const std::string key = shape_key(c, "factor:v1");
+  int pw = 0;
+  if (cache_lookup_ints(c->opt.tune_cache, key, &pw, 1) && (pw == 4 || pw == 8 || pw == 16)) {
+    c->factor_panel = pw;
+    factor_local(c);
+    return;
+  }
+  // the factorization works in place: the local matrices are gathered again
+  // before each candidate (the default, 8, goes last and is kept if best)
+  double best = 1e300;
+  int best_pw = 8;
+  const int cands[3] = {4, 16, 8};
+  for (int q = 0; q < 3; q++) {
+    if (q > 0) gather_local(c, dist);
+    c->factor_panel = cands[q];
+    const auto t0 = std::chrono::steady_clock::now();
+    factor_local(c);
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (t < best) {
+      best = t;
+      best_pw = cands[q];
+    }
+  }
+  if (best_pw != cands[2]) {
+    gather_local(c, dist);
+    c->factor_panel = best_pw;
+    factor_local(c);
+  }
+  cache_store_ints(c->opt.tune_cache, key, &best_pw, 1);
+}
 
 void choose_solve_grid(tls_ctx* c) {
   const int cus = cu_count();

@@ -961,17 +961,36 @@ def test_grouped_setup_is_bitwise_identical(monkeypatch, precision):
     assert np.array_equal(z0, z1)
 
 
-def test_autotune_cache_reuse(tmp_path):
+@pytest.mark.parametrize("local_inverse", [0, 1])
+def test_autotune_cache_reuse(tmp_path, local_inverse):
+    """Every autotuned shape (factorization panel width; workgroups and task
+    order of the substitutions, or the block side of the product with the
+    explicit inverses) is timed by the first setup, written to the cache,
+    read back by the second without timing, and the two contexts apply the
+    same preconditioner (bitwise, since the picks are equal)."""
+    torch = torch_cuda()
     import paper_2401_03915_amd as tls
     A, part = _hc_problem(96, 3, seed=8)
     cache = str(tmp_path / "tune.txt")
-    say("autotune cache")
-    pc1 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode())
+    say("autotune cache", local_inverse)
+    pc1 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode(), local_inverse=local_inverse)
     i1 = pc1.info()
-    pc2 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode())
+    lines = open(cache).read().splitlines()
+    keys = sorted(line.split(" ")[0] for line in lines)
+    assert keys == (["factor:v1", "symv:v1"] if local_inverse else ["factor:v1", "trsv:v5"])
+    pc2 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode(), local_inverse=local_inverse)
     i2 = pc2.info()
+    assert open(cache).read().splitlines() == lines  # nothing timed or written again
     assert i1["tuned"] == 1 and i2["tuned"] == 2
-    assert i1["solve_wgs"] == i2["solve_wgs"] > 0
+    assert i1["factor_panel"] == i2["factor_panel"] and i1["factor_panel"] in (4, 8, 16)
+    if local_inverse:
+        assert i1["symv_block"] == i2["symv_block"] and i1["symv_block"] in (4, 6, 8)
+    else:
+        assert i1["solve_wgs"] == i2["solve_wgs"] > 0 and i1["solve_order"] == i2["solve_order"]
+    r = to_dev(np.random.default_rng(4).standard_normal(A.shape[0]))
+    z1, z2 = pc1.apply(r), pc2.apply(r)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)
     pc1.close()
     pc2.close()
     del tls

@@ -29,7 +29,8 @@ def test_pool_matches_serial_oracle(spd):
     with pool.Pool(A, part, delta, nev, spd=spd, workers=3) as pl:
         assert pl.n_coarse == h.n_coarse
         Zs = pl.Z.toarray()
-        assert np.array_equal(Zs, h.Z)
+        # the same coarse space (workers use one BLAS thread: equal up to rounding)
+        assert np.linalg.norm(Zs @ (Zs.T @ h.Z) - h.Z) <= 1e-10 * np.linalg.norm(h.Z)
         rng = np.random.default_rng(1)
         for comp in oracle.schwarz.COMPOSITIONS:
             r = rng.standard_normal(A.shape[0])
