@@ -31,6 +31,9 @@ inline int red_grid(int n) { return std::max(1, std::min(RED_BLOCKS, (n + 2047) 
 // 7-point stencils) are read fully coalesced this way.
 constexpr int SPMV_ROWS = 256;
 constexpr int SPMV_CAP = 2048;
+// with p.q (PCG) the SpMV stores one partial per block (at most this many
+// blocks, looping over row blocks beyond); k_pcg_update adds them
+constexpr int SPMV_PQ_BLOCKS = 4096;
 inline int spmv_blocks(int n) { return (n + SPMV_ROWS - 1) / SPMV_ROWS; }
 
 __device__ inline void block_reduce_store(double v, double* out) {
@@ -81,15 +84,13 @@ __device__ inline void sum_partials(const double* partial, int count, double* ou
   block_reduce_store(s, out);
 }
 
-// y = A x, or y = f - A x when f is given. With pq (PCG): also p.q for
-// x = p, y = q into scal[2] (a non-positive p.q stops the iteration:
-// breakdown), and scal[1] = scal[4] (the r.z of the previous iteration
-// becomes the current one).
+// y = A x, or y = f - A x when f is given. With pq (PCG): also each block's
+// part of p.q (x = p, y = q) into partial[blockIdx.x]; the next launch adds
+// the partials (a plain store: no counter, no atomics).
 __global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                               const double* __restrict__ val, const double* __restrict__ x,
                                               double* __restrict__ y, const int* __restrict__ done,
-                                              const double* __restrict__ f, int pq, double* partial,
-                                              unsigned* ctr, double* scal, int* dflag) {
+                                              const double* __restrict__ f, int pq, double* partial) {
   if (*done) return;
   __shared__ double prod[SPMV_CAP];
   __shared__ int srp[SPMV_ROWS + 1];
@@ -125,18 +126,7 @@ __global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp,
       }
     }
   }
-  if (!pq) return;
-  block_reduce_partial(mine, partial);
-  if (last_block(ctr)) {
-    sum_partials(partial, gridDim.x, scal + 2);
-    if (threadIdx.x == 0) {
-      scal[1] = scal[4];
-      if (!(scal[2] > 0.0)) {
-        dflag[0] = 1;
-        dflag[3] = 1;
-      }
-    }
-  }
+  if (pq) block_reduce_store(mine, partial + blockIdx.x);
 }
 
 // Longer rows: G lanes per row and a shuffle reduction.
@@ -144,8 +134,7 @@ template <int G>
 __global__ void __launch_bounds__(256) k_spmv_group(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                     const double* __restrict__ val, const double* __restrict__ x,
                                                     double* __restrict__ y, const int* __restrict__ done,
-                                                    const double* __restrict__ f, int pq, double* partial,
-                                                    unsigned* ctr, double* scal, int* dflag) {
+                                                    const double* __restrict__ f, int pq, double* partial) {
   if (*done) return;
   const int lane = threadIdx.x % G;
   const int nrb = (n + 256 / G - 1) / (256 / G);
@@ -165,18 +154,7 @@ __global__ void __launch_bounds__(256) k_spmv_group(int n, const int* __restrict
       if (pq) mine += x[row] * v;
     }
   }
-  if (!pq) return;
-  block_reduce_partial(mine, partial);
-  if (last_block(ctr)) {
-    sum_partials(partial, gridDim.x, scal + 2);
-    if (threadIdx.x == 0) {
-      scal[1] = scal[4];
-      if (!(scal[2] > 0.0)) {
-        dflag[0] = 1;
-        dflag[3] = 1;
-      }
-    }
-  }
+  if (pq) block_reduce_store(mine, partial + blockIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
@@ -195,7 +173,8 @@ __global__ void __launch_bounds__(256) k_dot(int n, const double* __restrict__ a
   if (last_block(ctr)) sum_partials(partial, gridDim.x, out);
 }
 
-// r.z into scal[4] and, for the flexible variant, r.zold into scal[5], in one pass
+// r.z into scal[4] (its previous value moves to scal[1]) and, for the
+// flexible variant, r.zold into scal[5], in one pass
 __global__ void __launch_bounds__(256) k_dot_rz(int n, const double* __restrict__ r, const double* __restrict__ z,
                                                 const double* __restrict__ zold, double* partial, unsigned* ctr,
                                                 double* scal, const int* __restrict__ done) {
@@ -216,21 +195,42 @@ __global__ void __launch_bounds__(256) k_dot_rz(int n, const double* __restrict_
   __syncthreads();
   if (zold) block_reduce_partial(t, partial + RED_BLOCKS);
   if (last_block(ctr)) {
+    if (threadIdx.x == 0) scal[1] = scal[4];  // the previous r.z, for beta
+    __syncthreads();
     sum_partials(partial, gridDim.x, scal + 4);
     __syncthreads();
     if (zold) sum_partials(partial + RED_BLOCKS, gridDim.x, scal + 5);
   }
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; [zold = z]; r.r into scal[3];
-// then the last block records ||r||/||b|| and stops on the tolerance or the cap
+// p.q = the SpMV's partials added in index order (every block alike; a
+// non-positive p.q stops the iteration: breakdown); alpha = r.z / p.q;
+// x += alpha p; r -= alpha q; [zold = z]; r.r into scal[3]; then the last
+// block records ||r||/||b|| and stops on the tolerance or the cap
 __global__ void __launch_bounds__(256) k_pcg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                     const double* __restrict__ p, const double* __restrict__ q,
                                                     const double* __restrict__ z, double* __restrict__ zold,
-                                                    double* scal, double* partial, unsigned* ctr, int* done,
-                                                    double* hist, int maxit, double tol2) {
+                                                    const double* __restrict__ pqpart, int npq, double* scal,
+                                                    double* partial, unsigned* ctr, int* done, double* hist,
+                                                    int maxit, double tol2) {
   if (done[0]) return;
-  const double alpha = scal[1] / scal[2];
+  __shared__ double s_pq;
+  {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < npq; i += 256) v += pqpart[i];
+    block_reduce_store(v, &s_pq);
+    __syncthreads();
+  }
+  const double pqv = s_pq;
+  if (!(pqv > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      scal[2] = pqv;
+      done[0] = 1;
+      done[3] = 1;
+    }
+    return;
+  }
+  const double alpha = scal[4] / pqv;
   double s = 0.0;
   const int st = gridDim.x * 256;
   for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * st)
@@ -291,7 +291,7 @@ namespace {
 // row-block kernel loops over row blocks on at most RED_BLOCKS blocks
 int spmv_grid(const tls_ctx* c, bool pq) {
   const int nb = c->spmv_group == 0 ? spmv_blocks(c->n) : div_up(c->n, 256 / c->spmv_group);
-  return pq ? std::min(nb, RED_BLOCKS) : nb;
+  return pq ? std::min(nb, SPMV_PQ_BLOCKS) : nb;
 }
 
 // y = A x (or f - A x); with w (PCG): also p.q, the breakdown check and the r.z shift
@@ -300,31 +300,24 @@ void spmv_launch(tls_ctx* c, const double* f, const double* x, double* y, const 
   const int n = c->n;
   const dim3 grid(spmv_grid(c, w != nullptr));
   const int pq = w ? 1 : 0;
-  double* partial = w ? w->partial : nullptr;
-  unsigned* ctr = w ? w->redctr : nullptr;
-  double* scal = w ? w->scal : nullptr;
-  int* dflag = w ? w->done : nullptr;
+  double* partial = w ? w->partial + 2 * RED_BLOCKS : nullptr;  // after the dot partials
   const int *rp = c->row_ptr.p, *ci = c->col_idx.p;
   const double* val = c->val.p;
   switch (c->spmv_group) {
     case 0:
-      hipLaunchKernelGGL(k_spmv, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr, scal, dflag);
+      hipLaunchKernelGGL(k_spmv, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
       break;
     case 8:
-      hipLaunchKernelGGL(k_spmv_group<8>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr, scal,
-                         dflag);
+      hipLaunchKernelGGL(k_spmv_group<8>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
       break;
     case 16:
-      hipLaunchKernelGGL(k_spmv_group<16>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr,
-                         scal, dflag);
+      hipLaunchKernelGGL(k_spmv_group<16>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
       break;
     case 32:
-      hipLaunchKernelGGL(k_spmv_group<32>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr,
-                         scal, dflag);
+      hipLaunchKernelGGL(k_spmv_group<32>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
       break;
     default:
-      hipLaunchKernelGGL(k_spmv_group<64>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial, ctr,
-                         scal, dflag);
+      hipLaunchKernelGGL(k_spmv_group<64>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
       break;
   }
   TLS_LAUNCH_CHECK();
@@ -357,7 +350,8 @@ void pcg_iteration(tls_ctx* c, const KWork& w, const PcgVec& v, int maxit, doubl
   const dim3 rg(red_grid(n));
   spmv_launch(c, nullptr, v.p, v.q, done, &w);
   hipLaunchKernelGGL(k_pcg_update, rg, dim3(256), 0, s, n, v.x, v.r, v.p, v.q, v.z, flexible ? v.zold : nullptr,
-                     w.scal, w.partial, w.redctr, w.done, w.hist, maxit, tol2);
+                     w.partial + 2 * RED_BLOCKS, spmv_grid(c, true), w.scal, w.partial, w.redctr, w.done, w.hist,
+                     maxit, tol2);
   TLS_LAUNCH_CHECK();
   apply_precond(c, v.r, v.z, done);
   hipLaunchKernelGGL(k_dot_rz, rg, dim3(256), 0, s, n, v.r, v.z, flexible ? v.zold : nullptr, w.partial, w.redctr,
@@ -748,12 +742,12 @@ KrylovNeeds krylov_needs(const tls_ctx* c) {
   k.hist = krylov_maxit(c);
   if (use_pcg(c)) {
     k.kr = (size_t)7 * c->n;
-    k.partial = (size_t)std::max(2 * RED_BLOCKS, spmv_grid(c, true));
+    k.partial = (size_t)(2 * RED_BLOCKS + spmv_grid(c, true));
     k.gm = 0;
   } else {
     const int m = gmres_m(c);
     k.kr = (size_t)c->n * (6 + (m + 1) + m);
-    k.partial = (size_t)std::max({2 * RED_BLOCKS, MD_BLOCKS * (m + 1), spmv_grid(c, true)});
+    k.partial = (size_t)std::max(2 * RED_BLOCKS + spmv_grid(c, true), MD_BLOCKS * (m + 1));
     k.gm = (size_t)GmLayout(m).total;
   }
   return k;
