@@ -41,8 +41,10 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # 1 GiB read + 1 GiB write elementwise copy (--copy-probe). None whenever that
 # kernel has changed since the counters were taken.
 TRAFFIC = 16323093978
-# The same for k_symv<float> (explicit local inverses, the default for SPD).
-TRAFFIC_SYMV = 16347135206
+# The same for k_symv<float, 8> (explicit local inverses, the default for SPD)
+# and for the SpMV k_spmv<1280>.
+TRAFFIC_SYMV = 16347116314
+TRAFFIC_SPMV = 86755960
 
 
 def log(*a):
@@ -559,7 +561,8 @@ def main():
     spmv = {"kernel": "k_spmv (y = A x, CSR, FP64)", "bytes_per_launch": spmv_bytes,
             "launch_us": round(spmv_us, 2), "launches_timed": n_spmv,
             "achieved": round(spmv_bytes / (spmv_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(spmv_bytes / (spmv_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac": round(spmv_bytes / (spmv_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": TRAFFIC_SPMV if (args.config == 2 and args.scale is None) else None}
     log(f"spmv {spmv_us:.2f} us, {spmv['achieved']} GB/s")
     info = mixed["info"]
     # dominant kernel: the forward persistent triangular solve of the FP32

@@ -144,6 +144,15 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     double avg = (double)nnz / n;
     // short rows: row blocks streamed through LDS (0); longer ones: G lanes per row
     c->spmv_group = avg <= 12 ? 0 : avg <= 24 ? 16 : avg <= 48 ? 32 : 64;
+    if (c->spmv_group == 0) {
+      // the most entries in one block of 256 rows picks the row-block kernel's LDS size
+      std::vector<int> hrp(n + 1);
+      TLS_HIP(hipMemcpyAsync(hrp.data(), row_ptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s));
+      TLS_HIP(hipStreamSynchronize(s));
+      int most = 0;
+      for (int r0 = 0; r0 < n; r0 += 256) most = std::max(most, hrp[std::min(n, r0 + 256)] - hrp[r0]);
+      c->spmv_cap = most <= 1280 ? 1280 : most <= 1536 ? 1536 : most <= 2048 ? 2048 : 4096;
+    }
 
     auto t = clk::now();
     tls::validate_input(c.get());

@@ -21,6 +21,7 @@ struct tls_ctx {
   tls::DBuf<double> val;
   tls::DBuf<int> trow_ptr, tcol_idx;  // pattern of A^T (general matrices)
   int spmv_group = 0;  // 0: row-block SpMV through LDS; G > 0: G lanes per row
+  int spmv_cap = 2048;  // LDS products per row block of the row-block SpMV
 
   // overlap: Omega_i lists (global ids) in [I, Gamma_1, .., Gamma_delta] order
   std::vector<int> h_sub_ptr;    // N+1

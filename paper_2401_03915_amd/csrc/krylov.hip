@@ -26,11 +26,10 @@ inline int red_grid(int n) { return std::max(1, std::min(RED_BLOCKS, (n + 2047) 
 // SpMV by row blocks: a block of SPMV_ROWS consecutive rows streams its
 // stored entries (values and columns) with consecutive threads on
 // consecutive entries, keeps the products in LDS and then sums each row's
-// products in the stored order; rows whose block holds more than SPMV_CAP
+// products in the stored order; rows whose block holds more than CAP
 // entries are done one thread per row instead. Short rows (the 5- and
 // 7-point stencils) are read fully coalesced this way.
 constexpr int SPMV_ROWS = 256;
-constexpr int SPMV_CAP = 2048;
 // with p.q (PCG) the SpMV stores one partial per block (at most this many
 // blocks, looping over row blocks beyond); k_pcg_update adds them
 constexpr int SPMV_PQ_BLOCKS = 4096;
@@ -87,12 +86,18 @@ __device__ inline void sum_partials(const double* partial, int count, double* ou
 // y = A x, or y = f - A x when f is given. With pq (PCG): also each block's
 // part of p.q (x = p, y = q) into partial[blockIdx.x]; the next launch adds
 // the partials (a plain store: no counter, no atomics).
+// CAP (the LDS products of one row block) is the smallest of 1280, 1536,
+// 2048 and 4096 that holds every row block's entries (chosen at setup): the
+// less LDS, the more blocks per CU; each thread issues all of its CAP / 256
+// value and column loads before its gathers from x.
+template <int CAP>
 __global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                               const double* __restrict__ val, const double* __restrict__ x,
                                               double* __restrict__ y, const int* __restrict__ done,
                                               const double* __restrict__ f, int pq, double* partial) {
   if (*done) return;
-  __shared__ double prod[SPMV_CAP];
+  constexpr int U = CAP / 256;
+  __shared__ double prod[CAP];
   __shared__ int srp[SPMV_ROWS + 1];
   double mine = 0.0;  // this thread's rows (pq only)
   const int nblk = (n + SPMV_ROWS - 1) / SPMV_ROWS;
@@ -103,10 +108,21 @@ __global__ void __launch_bounds__(256) k_spmv(int n, const int* __restrict__ rp,
     for (int t = threadIdx.x; t <= nr; t += 256) srp[t] = rp[r0 + t];
     __syncthreads();
     const int j0 = srp[0], nz = srp[nr] - j0;
-    if (nz <= SPMV_CAP) {
-      for (int t = threadIdx.x; t < nz; t += 256) {
-        const int j = j0 + t;
-        prod[t] = __builtin_nontemporal_load(val + j) * x[__builtin_nontemporal_load(ci + j)];
+    if (nz <= CAP) {
+      double vv[U];
+      int cc[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int t = threadIdx.x + 256 * u;
+        if (t < nz) {
+          vv[u] = __builtin_nontemporal_load(val + j0 + t);
+          cc[u] = __builtin_nontemporal_load(ci + j0 + t);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int t = threadIdx.x + 256 * u;
+        if (t < nz) prod[t] = vv[u] * x[cc[u]];
       }
       __syncthreads();
       for (int r = threadIdx.x; r < nr; r += 256) {
@@ -305,7 +321,20 @@ void spmv_launch(tls_ctx* c, const double* f, const double* x, double* y, const 
   const double* val = c->val.p;
   switch (c->spmv_group) {
     case 0:
-      hipLaunchKernelGGL(k_spmv, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
+      switch (c->spmv_cap) {
+        case 1280:
+          hipLaunchKernelGGL(k_spmv<1280>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
+          break;
+        case 1536:
+          hipLaunchKernelGGL(k_spmv<1536>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
+          break;
+        case 2048:
+          hipLaunchKernelGGL(k_spmv<2048>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
+          break;
+        default:
+          hipLaunchKernelGGL(k_spmv<4096>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);
+          break;
+      }
       break;
     case 8:
       hipLaunchKernelGGL(k_spmv_group<8>, grid, dim3(256), 0, s, n, rp, ci, val, x, y, done, f, pq, partial);

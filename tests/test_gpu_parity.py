@@ -563,6 +563,45 @@ def test_error_paths():
     with pytest.raises(tls.TlsError) as e:
         _pc(A, part, 1, 4, matrix_kind=1, local_inverse=1)
     assert e.value.status == 1
+    import scipy.sparse as sp
+    A = A.tocsr()
+    # a non-finite value
+    nan = A.copy()
+    nan.data[5] = np.nan
+    with pytest.raises(tls.TlsError) as e:
+        _pc(nan, part, 1, 0)
+    assert e.value.status == 1 and "non-finite" in str(e.value)
+    # columns out of order inside a row (row 17 holds 5 entries), a repeated
+    # column, and a column index past n: each is a malformed CSR
+    for bad_cols in ("swap", "repeat", "range"):
+        ind = A.indices.copy()
+        a, b = A.indptr[17], A.indptr[18]
+        if bad_cols == "swap":
+            ind[a], ind[a + 1] = ind[a + 1], ind[a]
+        elif bad_cols == "repeat":
+            ind[a + 1] = ind[a]
+        else:
+            ind[b - 1] = A.shape[0]
+        M = A.copy()
+        M.indices[:] = ind  # set after construction: no canonicalization or format check
+        M.has_sorted_indices = False
+        with pytest.raises(tls.TlsError) as e:
+            _pc(M, part, 1, 0)
+        assert e.value.status == 1 and "malformed CSR" in str(e.value), bad_cols
+    # an empty part (parts 0, 1, 3 used, part 2 empty)
+    gap = part.copy()
+    gap[gap == 2] = 1
+    with pytest.raises(tls.TlsError) as e:
+        _pc(A, gap, 1, 0)
+    assert e.value.status == 1 and "empty" in str(e.value)
+    # a zero pivot in the unpivoted local LU (the first row of subdomain 0)
+    z = A.tolil()
+    z[0, 0] = 0.0
+    z = z.tocsr()
+    z.eliminate_zeros()
+    with pytest.raises(tls.TlsError) as e:
+        _pc(z, part, 1, 0, matrix_kind=1)
+    assert e.value.status == 3
 
 
 # ---------------------------------------------------------------------------
