@@ -157,16 +157,14 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     auto t = clk::now();
     tls::validate_input(c.get());
     if (c->kind == 1) tls::build_transpose(c.get());
-    DBuf<uint8_t> dist;
-    tls::build_overlap(c.get(), dist);
+    tls::build_overlap(c.get());
     tls::build_layout(c.get());
     c->t_setup[0] = ms_since(t);
     t = clk::now();
-    tls::gather_local(c.get(), dist);
+    tls::gather_local(c.get());
     c->t_setup[1] = ms_since(t);
     t = clk::now();
-    tls::factor_local_tuned(c.get(), dist);
-    dist.release();
+    tls::factor_local_tuned(c.get());
     c->t_setup[6] = ms_since(t);
     tls::build_solve_tasks(c.get());
     c->t_setup[2] = ms_since(t);

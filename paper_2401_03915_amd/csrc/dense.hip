@@ -57,10 +57,9 @@ __global__ void k_jacobi_scale(int total, const int* __restrict__ sub_idx, const
 }
 
 template <class T>
-__global__ void k_gather(int total, int n, const int* __restrict__ sub_idx, const int* __restrict__ sub_of_pos,
+__global__ void k_gather(int total, const int* __restrict__ sub_idx, const int* __restrict__ sub_of_pos,
                          const int* __restrict__ sub_ptr, const int* __restrict__ layer_ptr, int stride,
-                         const uint8_t* __restrict__ dist, const int* __restrict__ rp,
-                         const int* __restrict__ ci, const double* __restrict__ val,
+                         const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
                          const double* __restrict__ scale, LocalLayout lay, int kind, T* fac) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= total) return;
@@ -69,23 +68,13 @@ __global__ void k_gather(int total, int n, const int* __restrict__ sub_idx, cons
   int g = sub_idx[p];
   int nt = lay.nt[i];
   T* base = fac + lay.foff[i];
-  const uint8_t* drow = dist + (size_t)i * n;
   const int* lp = layer_ptr + (size_t)i * stride;
   double sa = scale ? scale[lay.voff[i] + a] : 1.0;
   for (int j = rp[g]; j < rp[g + 1]; j++) {
-    int c = ci[j];
-    int d = drow[c];
-    if (d == 0xFF) continue;  // c is not in Omega_i
-    // binary search of c in the (ascending) segment of level d
-    int lo = lp[d], hi = lp[d + 1] - 1;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (sub_idx[mid] < c)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    int b = lo - sub_ptr[i];
+    // position of column c in Omega_i (every layer is ascending), or -1
+    int q = find_local_pos(ci[j], sub_idx, lp, stride - 1);
+    if (q < 0) continue;
+    int b = q - sub_ptr[i];
     if (kind == 0 && b > a) continue;  // Cholesky stores the lower triangle
     double v = val[j];
     if (scale) v *= sa * scale[lay.voff[i] + b];
@@ -1766,7 +1755,7 @@ void solve_begin(hipStream_t s, int* counters, const int* done) {
   TLS_LAUNCH_CHECK();
 }
 
-void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist) {
+void gather_local(tls_ctx* c) {
   hipStream_t s = c->stream;
   const int total = c->h_sub_ptr[c->N];
   LocalLayout lay = c->layout();
@@ -1788,16 +1777,16 @@ void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist) {
     TLS_HIP(hipMemsetAsync(c->fac32.p, 0, sizeof(float) * c->fac_elems, s));
     hipLaunchKernelGGL(k_pad_identity<float>, dim3(c->N), dim3(64), 0, s, c->N, lay, c->kind, c->fac32.p);
     TLS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gather<float>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->n, c->sub_idx.p,
-                       c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, dist.p, c->row_ptr.p, c->col_idx.p,
+    hipLaunchKernelGGL(k_gather<float>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
+                       c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, c->row_ptr.p, c->col_idx.p,
                        c->val.p, scale, lay, c->kind, c->fac32.p);
   } else {
     c->fac64.alloc(c->fac_elems);
     TLS_HIP(hipMemsetAsync(c->fac64.p, 0, sizeof(double) * c->fac_elems, s));
     hipLaunchKernelGGL(k_pad_identity<double>, dim3(c->N), dim3(64), 0, s, c->N, lay, c->kind, c->fac64.p);
     TLS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gather<double>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->n, c->sub_idx.p,
-                       c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, dist.p, c->row_ptr.p, c->col_idx.p,
+    hipLaunchKernelGGL(k_gather<double>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
+                       c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, c->row_ptr.p, c->col_idx.p,
                        c->val.p, scale, lay, c->kind, c->fac64.p);
   }
   TLS_LAUNCH_CHECK();

@@ -8,11 +8,11 @@ namespace tls {
 // setup_index.hip: validation, A^T pattern, overlap layers and maps
 void validate_input(tls_ctx* c);
 void build_transpose(tls_ctx* c);
-void build_overlap(tls_ctx* c, DBuf<uint8_t>& dist);
+void build_overlap(tls_ctx* c);
 void build_layout(tls_ctx* c);
 
 // dense.hip: local matrices, batched factorization, triangular solves
-void gather_local(tls_ctx* c, const DBuf<uint8_t>& dist);
+void gather_local(tls_ctx* c);
 void factor_local(tls_ctx* c);
 void build_solve_tasks(tls_ctx* c);
 // local solves on the padded vector buffer x (fp64 or fp32 per c->fp32)
@@ -86,7 +86,7 @@ void choose_solve_grid(tls_ctx* c);
 // block side of the symmetric product with the local inverses (after form_local_inverse)
 void choose_symv_block(tls_ctx* c);
 // the batched factorization with its panel width picked (gathers again per candidate)
-void factor_local_tuned(tls_ctx* c, const DBuf<uint8_t>& dist);
+void factor_local_tuned(tls_ctx* c);
 
 // refine.hip: iterative refinement of the FP32 local solves (option local_refine)
 void build_refine(tls_ctx* c);

@@ -9,12 +9,11 @@
 #include "context.hpp"
 #include "kernels.hpp"
 #include "scan.hpp"
+#include "sort.hpp"
 
 namespace tls {
 
 namespace {
-
-constexpr uint8_t UNSEEN = 0xFF;
 
 __global__ void k_validate(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
                            const double* __restrict__ v, const int* __restrict__ part, int N,
@@ -58,86 +57,96 @@ __global__ void k_fill_transpose(int n, const int* __restrict__ rp, const int* _
   }
 }
 
-__global__ void k_mark_interior(int n, const int* __restrict__ part, uint8_t* dist) {
+// Level 0 keys: (part[v], v); v ascending on input, so a stable sort on
+// the subdomain bits alone orders them by (subdomain, v).
+__global__ void k_interior_keys(int n, const int* __restrict__ part, int sh, uint64_t* keys) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) dist[(size_t)part[v] * n + v] = 0;
+  if (v < n) keys[v] = ((uint64_t)part[v] << sh) | (uint64_t)v;
 }
 
-// Count entries of row i of dist equal to `level` (one block per subdomain).
-__global__ void k_level_count(int n, const uint8_t* __restrict__ dist, uint8_t level, int* cnt) {
-  const uint8_t* row = dist + (size_t)blockIdx.x * n;
-  int c = 0;
-  for (int v = threadIdx.x; v < n; v += blockDim.x) c += (row[v] == level);
-  __shared__ int sh[256];
-  sh[threadIdx.x] = c;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
+// Is u already in Omega_i at a level below the one being built? Level 0 is
+// part[u] == i; levels 1 .. l-1 are ascending segments of their layer
+// arrays (binary search).
+__device__ inline bool already_in(int u, int i, const int* __restrict__ part, int levels,
+                                  const int* const* __restrict__ lays, const int* const* __restrict__ offs) {
+  if (part[u] == i) return true;
+  for (int lv = 1; lv < levels; lv++) {
+    const int* lay = lays[lv];
+    int lo = offs[lv][i], hi = offs[lv][i + 1] - 1;
+    if (lo > hi || u < lay[lo] || u > lay[hi]) continue;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (lay[mid] < u)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (lay[lo] == u) return true;
   }
-  if (threadIdx.x == 0) cnt[blockIdx.x] = sh[0];
+  return false;
 }
 
-// Ordered compaction of row i of dist: the global ids v with dist == level,
-// ascending, written to out[off[i] ..]; the subdomain id goes to osub.
-__global__ void k_level_fill(int n, const uint8_t* __restrict__ dist, uint8_t level,
-                             const int* __restrict__ off, int* out, int* osub) {
-  const int i = blockIdx.x;
-  const uint8_t* row = dist + (size_t)i * n;
-  constexpr int PER = 16;
-  __shared__ int sh[256];
-  int base_out = off[i];
-  for (int64_t chunk = 0; chunk < n; chunk += 256 * PER) {
-    int64_t start = chunk + (int64_t)threadIdx.x * PER;
-    int c = 0;
-    for (int j = 0; j < PER; j++) {
-      int64_t v = start + j;
-      if (v < n && row[v] == level) c++;
-    }
-    sh[threadIdx.x] = c;
-    __syncthreads();
-    for (int s = 1; s < 256; s <<= 1) {
-      int add = threadIdx.x >= s ? sh[threadIdx.x - s] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += add;
-      __syncthreads();
-    }
-    int pos = base_out + sh[threadIdx.x] - c;
-    int tot = sh[255];
-    __syncthreads();
-    for (int j = 0; j < PER; j++) {
-      int64_t v = start + j;
-      if (v < n && row[v] == level) {
-        out[pos] = (int)v;
-        osub[pos] = i;
-        pos++;
-      }
-    }
-    base_out += tot;
-  }
-}
-
-// One breadth-first step: every neighbor (in A or A^T) of a level-(l-1) node
-// of subdomain i that is still unseen for i gets level l. Concurrent writers
-// store the same value.
-__global__ void k_expand(int count, const int* __restrict__ lay, const int* __restrict__ lsub, int n,
-                         const int* __restrict__ rp, const int* __restrict__ ci,
-                         const int* __restrict__ trp, const int* __restrict__ tci, uint8_t level,
-                         uint8_t* dist) {
+// Breadth-first candidates of level l: every neighbor u (in A, and in A^T
+// for general A) of a level-(l-1) entry (v, i) that is not yet in Omega_i,
+// as the key (i, u). The first pass counts them per entry, the second
+// writes them at the scanned offsets; duplicates are removed after the sort.
+template <bool FILL>
+__global__ void k_candidates(int count, const int* __restrict__ lay, const int* __restrict__ lsub,
+                             const int* __restrict__ rp, const int* __restrict__ ci,
+                             const int* __restrict__ trp, const int* __restrict__ tci,
+                             const int* __restrict__ part, int levels, const int* const* __restrict__ lays,
+                             const int* const* __restrict__ offs, int sh, int64_t* cnt,
+                             const int64_t* __restrict__ cpos, uint64_t* keys) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
-  int v = lay[e];
-  size_t rowbase = (size_t)lsub[e] * n;
+  const int v = lay[e], i = lsub[e];
+  const uint64_t hi = (uint64_t)i << sh;
+  int c = 0;
+  int64_t at = FILL ? cpos[e] : 0;
   for (int j = rp[v]; j < rp[v + 1]; j++) {
     int u = ci[j];
-    if (dist[rowbase + u] == UNSEEN) dist[rowbase + u] = level;
+    if (already_in(u, i, part, levels, lays, offs)) continue;
+    if (FILL) keys[at + c] = hi | (uint64_t)u;
+    c++;
   }
   if (trp) {
     for (int j = trp[v]; j < trp[v + 1]; j++) {
       int u = tci[j];
-      if (dist[rowbase + u] == UNSEEN) dist[rowbase + u] = level;
+      if (already_in(u, i, part, levels, lays, offs)) continue;
+      if (FILL) keys[at + c] = hi | (uint64_t)u;
+      c++;
     }
   }
+  if (!FILL) cnt[e] = c;
+}
+
+// 1 where a sorted key differs from its predecessor
+__global__ void k_first_of_run(int count, const uint64_t* __restrict__ keys, int* flag) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) flag[k] = (k == 0 || keys[k] != keys[k - 1]) ? 1 : 0;
+}
+
+// Distinct sorted keys -> the layer (u ascending within each subdomain) and
+// its subdomain ids.
+__global__ void k_unpack_runs(int count, const uint64_t* __restrict__ keys, const int* __restrict__ pos, int sh,
+                              int* lay, int* lsub) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  if (k == 0 || keys[k] != keys[k - 1]) {
+    lay[pos[k]] = (int)(keys[k] & ((1ull << sh) - 1));
+    lsub[pos[k]] = (int)(keys[k] >> sh);
+  }
+}
+
+// Segment offsets of a layer grouped by ascending subdomain id:
+// off[j] = first position with lsub >= j, off[N] = total.
+__global__ void k_segment_offsets(int total, int N, const int* __restrict__ lsub, int* off) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  int prev = p == 0 ? -1 : lsub[p - 1];
+  for (int j = prev + 1; j <= lsub[p]; j++) off[j] = p;
+  if (p == total - 1)
+    for (int j = lsub[p] + 1; j <= N; j++) off[j] = total;
 }
 
 // Copy level-l entries into their place in sub_idx.
@@ -230,44 +239,109 @@ void build_transpose(tls_ctx* c) {
   TLS_HIP(hipStreamSynchronize(s));
 }
 
-void build_overlap(tls_ctx* c, DBuf<uint8_t>& dist) {
+namespace {
+
+int bit_length(uint64_t x) {
+  int b = 0;
+  while (x) {
+    b++;
+    x >>= 1;
+  }
+  return b;
+}
+
+// Sorted keys -> one layer: distinct entries, their subdomain ids and the
+// per-subdomain segment offsets (off has N + 1 entries). Returns the size.
+int keys_to_layer(const uint64_t* keys, int count, int sh, int N, DBuf<int>& lay, DBuf<int>& lsub,
+                  DBuf<int>& off, hipStream_t s) {
+  off.alloc(N + 1);
+  if (count == 0) {
+    TLS_HIP(hipMemsetAsync(off.p, 0, sizeof(int) * (N + 1), s));
+    lay.alloc(0);
+    lsub.alloc(0);
+    return 0;
+  }
+  DBuf<int> flag, pos;
+  flag.alloc(count);
+  pos.alloc((size_t)count + 1);
+  hipLaunchKernelGGL(k_first_of_run, dim3(div_up(count, 256)), dim3(256), 0, s, count, keys, flag.p);
+  TLS_LAUNCH_CHECK();
+  scan_exclusive_i32(flag.p, pos.p, count, s);
+  int total = 0;
+  read_back(pos.p + count, &total, 1, s);
+  lay.alloc(total);
+  lsub.alloc(total);
+  hipLaunchKernelGGL(k_unpack_runs, dim3(div_up(count, 256)), dim3(256), 0, s, count, keys, pos.p, sh, lay.p,
+                     lsub.p);
+  TLS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_segment_offsets, dim3(div_up(total, 256)), dim3(256), 0, s, total, N, lsub.p, off.p);
+  TLS_LAUNCH_CHECK();
+  TLS_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
+}  // namespace
+
+// Omega_i layer by layer with O(sum_i #Omega_i) work and memory: a layer is
+// the sorted, de-duplicated list of (i, u) keys generated from the previous
+// layer's neighbors, less the entries already in Omega_i.
+void build_overlap(tls_ctx* c) {
   hipStream_t s = c->stream;
   const int n = c->n, N = c->N, L = c->delta;
   const int stride = L + 2;
-  dist.alloc((size_t)N * n);
-  TLS_HIP(hipMemsetAsync(dist.p, UNSEEN, (size_t)N * n, s));
-  hipLaunchKernelGGL(k_mark_interior, dim3(div_up(n, 256)), dim3(256), 0, s, n, c->part.p, dist.p);
-  TLS_LAUNCH_CHECK();
+  const int sh = std::max(1, bit_length((uint64_t)(n - 1)));
+  const int top = sh + std::max(1, bit_length((uint64_t)(N - 1)));
 
   std::vector<std::vector<int>> cnt(L + 1, std::vector<int>(N));
   std::vector<DBuf<int>> lay(L + 1), lsub(L + 1), loff(L + 1);
-  DBuf<int> dcnt;
-  dcnt.alloc(N);
+  std::vector<int> size(L + 1, 0);
+  std::vector<int> h_off;
   const int* trp = c->kind == 1 ? c->trow_ptr.p : nullptr;
   const int* tci = c->kind == 1 ? c->tcol_idx.p : nullptr;
+  // device tables of the layer arrays built so far (entry 0 unused)
+  DBuf<const int*> lays_d, offs_d;
+  std::vector<const int*> lays_h(L + 1, nullptr), offs_h(L + 1, nullptr);
   for (int l = 0; l <= L; l++) {
-    if (l > 0) {
-      int prev = (int)lay[l - 1].n;
-      if (prev > 0 && lay[l - 1].p) {
-        int count = 0;
-        for (int i = 0; i < N; i++) count += cnt[l - 1][i];
-        if (count > 0)
-          hipLaunchKernelGGL(k_expand, dim3(div_up(count, 256)), dim3(256), 0, s, count, lay[l - 1].p,
-                             lsub[l - 1].p, n, c->row_ptr.p, c->col_idx.p, trp, tci, (uint8_t)l, dist.p);
+    DBuf<uint64_t> ka, kb;
+    int count = 0;
+    if (l == 0) {
+      count = n;
+      ka.alloc(n);
+      kb.alloc(n);
+      hipLaunchKernelGGL(k_interior_keys, dim3(div_up(n, 256)), dim3(256), 0, s, n, c->part.p, sh, ka.p);
+      TLS_LAUNCH_CHECK();
+    } else if (size[l - 1] > 0) {
+      const int F = size[l - 1];
+      lays_d.upload(lays_h, s);
+      offs_d.upload(offs_h, s);
+      DBuf<int64_t> ccnt, cpos;
+      ccnt.alloc(F);
+      cpos.alloc((size_t)F + 1);
+      hipLaunchKernelGGL(k_candidates<false>, dim3(div_up(F, 256)), dim3(256), 0, s, F, lay[l - 1].p,
+                         lsub[l - 1].p, c->row_ptr.p, c->col_idx.p, trp, tci, c->part.p, l, lays_d.p, offs_d.p,
+                         sh, ccnt.p, nullptr, nullptr);
+      TLS_LAUNCH_CHECK();
+      scan_exclusive_i64(ccnt.p, cpos.p, F, s);
+      int64_t total = 0;
+      read_back(cpos.p + F, &total, 1, s);
+      if (total >= INT32_MAX) fail(TLS_E_ARG, "overlap candidates exceed 2^31 entries");
+      count = (int)total;
+      ka.alloc(count);
+      kb.alloc(count);
+      if (count > 0) {
+        hipLaunchKernelGGL(k_candidates<true>, dim3(div_up(F, 256)), dim3(256), 0, s, F, lay[l - 1].p,
+                           lsub[l - 1].p, c->row_ptr.p, c->col_idx.p, trp, tci, c->part.p, l, lays_d.p,
+                           offs_d.p, sh, nullptr, cpos.p, ka.p);
         TLS_LAUNCH_CHECK();
       }
     }
-    hipLaunchKernelGGL(k_level_count, dim3(N), dim3(256), 0, s, n, dist.p, (uint8_t)l, dcnt.p);
-    TLS_LAUNCH_CHECK();
-    cnt[l] = download(dcnt.p, N, s);
-    std::vector<int> off(N + 1, 0);
-    for (int i = 0; i < N; i++) off[i + 1] = off[i] + cnt[l][i];
-    lay[l].alloc(off[N]);
-    lsub[l].alloc(off[N]);
-    loff[l].upload(off, s);
-    hipLaunchKernelGGL(k_level_fill, dim3(N), dim3(256), 0, s, n, dist.p, (uint8_t)l, loff[l].p, lay[l].p,
-                       lsub[l].p);
-    TLS_LAUNCH_CHECK();
+    // level 0 is ascending in u already: sort on the subdomain bits only
+    uint64_t* sorted = radix_sort_u64(ka.p, kb.p, count, l == 0 ? sh : 0, top, s);
+    size[l] = keys_to_layer(sorted, count, sh, N, lay[l], lsub[l], loff[l], s);
+    h_off = download(loff[l].p, N + 1, s);
+    for (int i = 0; i < N; i++) cnt[l][i] = h_off[i + 1] - h_off[i];
+    lays_h[l] = lay[l].p;
+    offs_h[l] = loff[l].p;
   }
 
   // layout of Omega_i
@@ -295,13 +369,9 @@ void build_overlap(tls_ctx* c, DBuf<uint8_t>& dist) {
   c->layer_ptr.upload(c->h_layer_ptr, s);
   c->sub_idx.alloc(total);
   for (int l = 0; l <= L; l++) {
-    int count = (int)lay[l].n;
-    int real = 0;
-    for (int i = 0; i < N; i++) real += cnt[l][i];
-    if (real == 0) continue;
-    (void)count;
-    hipLaunchKernelGGL(k_place_level, dim3(div_up(real, 256)), dim3(256), 0, s, real, lay[l].p, lsub[l].p,
-                       loff[l].p, c->layer_ptr.p, stride, l, c->sub_idx.p);
+    if (size[l] == 0) continue;
+    hipLaunchKernelGGL(k_place_level, dim3(div_up(size[l], 256)), dim3(256), 0, s, size[l], lay[l].p,
+                       lsub[l].p, loff[l].p, c->layer_ptr.p, stride, l, c->sub_idx.p);
     TLS_LAUNCH_CHECK();
   }
   TLS_HIP(hipStreamSynchronize(s));

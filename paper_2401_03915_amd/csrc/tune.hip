@@ -177,7 +177,7 @@ void choose_symv_block(tls_ctx* c) {
   cache_store_ints(c->opt.tune_cache, key, &best_b, 1);
 }
 
-void factor_local_tuned(tls_ctx* c, const DBuf<uint8_t>& dist) {
+void factor_local_tuned(tls_ctx* c) {
   if (!c->opt.autotune) {
     factor_local(c);
     return;
@@ -195,7 +195,7 @@ void factor_local_tuned(tls_ctx* c, const DBuf<uint8_t>& dist) {
   int best_pw = 8;
   const int cands[3] = {4, 16, 8};
   for (int q = 0; q < 3; q++) {
-    if (q > 0) gather_local(c, dist);
+    if (q > 0) gather_local(c);
     c->factor_panel = cands[q];
     const auto t0 = std::chrono::steady_clock::now();
     factor_local(c);
@@ -206,7 +206,7 @@ void factor_local_tuned(tls_ctx* c, const DBuf<uint8_t>& dist) {
     }
   }
   if (best_pw != cands[2]) {
-    gather_local(c, dist);
+    gather_local(c);
     c->factor_panel = best_pw;
     factor_local(c);
   }

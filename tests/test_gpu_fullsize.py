@@ -99,6 +99,13 @@ def test_full_size_configuration(cfg):
     say(f"full size cfg{cfg}: setup fp64")
     p64 = _pc(p, 0, **kw)
     ex = p64.export()
+    # -- Omega_i of every subdomain, in order, and its layer sizes
+    sp_, lp_ = ex["sub_ptr"], ex["layer_ptr"].reshape(p.n_parts, p.overlap + 2)
+    for i, s in enumerate(pl.subs):
+        assert np.array_equal(ex["sub_idx"][sp_[i]:sp_[i + 1]], s.idx), i
+        assert lp_[i, 1] - lp_[i, 0] == s.n_interior, i
+        assert list(np.diff(lp_[i, 1:])) == list(s.layer_sizes), i
+    say(f"  Omega_i of all {p.n_parts} subdomains equal to the oracle's")
     picks = _sample(ex)
     G = schwarz.sym_pattern(A)
     subs = {i: schwarz.overlap(A, p.part, i, p.overlap, G) for i in picks}
