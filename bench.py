@@ -39,10 +39,11 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # default workload) from two rocprofv3 counter runs (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch), scaled by what the same counters read for a
 # 1 GiB read + 1 GiB write elementwise copy (--copy-probe). None whenever that
-# kernel has changed since the counters were taken.
-TRAFFIC = 16323093978
-# The same for k_symv<float, 8> (explicit local inverses, the default for SPD)
-# and for the SpMV k_spmv<1280>.
+# kernel has changed since the counters were taken (it now skips the tiles
+# outside the profiles: to be taken again).
+TRAFFIC = None
+# The same for k_symv<float, 8> (explicit local inverses, taken on cfg2 when
+# they were its default) and for the SpMV k_spmv<1280>.
 TRAFFIC_SYMV = 16347116314
 TRAFFIC_SPMV = 86755960
 
@@ -521,7 +522,10 @@ def main():
     import tempfile
     tune_cache = os.path.join(tempfile.mkdtemp(prefix="tls_tune_"), "tune.txt")
     if args.local_inverse is None:
-        args.local_inverse = 1 if prob.spd else 0
+        # SPD: the library chooses (explicit inverses only when the
+        # substitutions inside the tile profiles would read more than half
+        # of what the product reads)
+        args.local_inverse = 2 if prob.spd else 0
     mixed = run_mode(prob, dev_in, 1, args.steps, args.warmup, args.applies, args.graph, tune_cache,
                      args.composition, args.restart, args.local_inverse)
     plain = None
@@ -569,11 +573,13 @@ def main():
     # local factors (the backward one reads the same bytes in about the same
     # time); its launch duration comes from HIP events recorded by the library
     # on the stream the kernel runs on
-    bytes_launch = local_lower_bytes(info, 4)
+    inverse = bool(info["local_inverse"])
+    # the product reads the lower triangles; a substitution reads the tiles
+    # inside the profiles (FP32, 64 x 64 tiles)
+    bytes_launch = local_lower_bytes(info, 4) if inverse else 4.0 * 4096.0 * float(info["solve_tiles_fwd"])
     t_fwd = mixed["local_fwd_ms"]
     t_bwd = mixed["local_solve_ms"] - t_fwd
     achieved = bytes_launch / (t_fwd * 1e-3) / 1e9 if t_fwd > 0 else 0.0
-    inverse = bool(info["local_inverse"])
     default_workload = args.config == 2 and args.scale is None
     if inverse:
         roof = {"bound": "hbm",
@@ -591,22 +597,30 @@ def main():
                 "traffic": TRAFFIC if default_workload else None,
                 "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4),
                 "launches_timed": mixed["n_profiled"], "backward_launch_ms": round(t_bwd, 4),
-                "backward_GBps": round(bytes_launch / (t_bwd * 1e-3) / 1e9, 1) if t_bwd > 0 else None,
+                "backward_bytes": 4.0 * 4096.0 * float(info["solve_tiles_bwd"]),
+                "backward_GBps": round(4.0 * 4096.0 * float(info["solve_tiles_bwd"]) / (t_bwd * 1e-3) / 1e9, 1)
+                if t_bwd > 0 else None,
                 "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"]}
     def mfma(mode, dt):
+        # flops: the library's count of what it ran (SPD: the tiles inside
+        # each local matrix's profile); dense_flops: sum_i m_i^3 / 3 (x2 LU),
+        # the dense factorization of the same matrices
         t = mode["info"]["t_setup"][6] * 1e-3  # batched factorization (+ diagonal-tile inverses), ms -> s
-        ach = mode["factor_flops"] / t / 1e12
-        kern = ("batched tiled Cholesky (k_potrf/k_trsm/k_update_blk)" if prob.spd
+        fl = mode["info"]["factor_flops"] or mode["factor_flops"]
+        ach = fl / t / 1e12
+        kern = ("batched tiled Cholesky inside the tile profile (k_potrf/k_trsm/k_update_blk)" if prob.spd
                 else "batched tiled LU (k_getrf/k_trsm_lu/k_update_lu)")
-        return {"kernel": kern, "flops": mode["factor_flops"],
+        return {"kernel": kern, "flops": fl, "dense_flops": mode["factor_flops"],
                 "ms": round(t * 1e3, 2), "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                 "frac": round(ach / MFMA_PEAK_TFLOPS[dt], 4)}
     def inverse_mfma(mode, dt):
         t = mode["info"]["t_inverse_ms"] * 1e-3
         if t <= 0:
             return None
-        fl = 2.0 * mode["factor_flops"]  # W = L^{-1} and S = W^T W: m^3 / 3 each
-        return {"kernel": "explicit local inverses (k_tinv_row/k_tinv_update/k_tinv_lauum)", "flops": fl,
+        fl = mode["info"]["inverse_flops"] or 2.0 * mode["factor_flops"]
+        return {"kernel": "explicit local inverses (k_tinv_row + k_sinv_row with the profile, "
+                          "else k_tinv_row/k_tinv_update/k_tinv_lauum)", "flops": fl,
+                "dense_flops": 2.0 * mode["factor_flops"],
                 "ms": round(t * 1e3, 2), "achieved": round(fl / t / 1e12, 2), "peak": MFMA_PEAK_TFLOPS[dt],
                 "unit": "TFLOP/s", "frac": round(fl / t / 1e12 / MFMA_PEAK_TFLOPS[dt], 4)}
     apply_err = None

@@ -150,7 +150,12 @@ typedef struct {
    * the stored triangle once instead of two substitutions that read it
    * twice. Costs about 2 #Omega_i^3 / 3 more flops per subdomain at setup.
    * A_0 is inverted the same way, so the coarse solve is one product too.
-   * 0 (default): forward and backward substitution with the factors. */
+   * 0 (default): forward and backward substitution with the factors.
+   * 2 (SPD only): choose. The substitutions read only the tiles inside each
+   * factor's tile profile (twice); the product reads every lower tile once.
+   * The inverse is formed when the two substitutions would read more than
+   * the product (2 P > D, P the profile tiles, D the lower tiles, summed
+   * over the subdomains); tls_info reports the choice. */
   int32_t local_inverse;
   /* FP32 mode (precision 1) only: steps of iterative refinement after each
    * local solve, in [0, 8]. A step forms the residual b_i - A_ii x_i in FP64
@@ -208,6 +213,19 @@ typedef struct {
                                  (4, 6 or 8; autotuned; 0 without local_inverse) */
   int32_t factor_panel;       /* panel width (tiles) of the batched factorization
                                  (4, 8 or 16; autotuned) */
+  double factor_flops;        /* arithmetic of the local factorization as run (2 per
+                                 multiply-add): for SPD matrices only the tiles inside
+                                 each A_ii's tile profile (its envelope, where all fill
+                                 stays), else 2/3 (64 nt_i)^3 per subdomain */
+  double inverse_flops;       /* the same for forming the explicit local inverses
+                                 (0 without local_inverse) */
+  int64_t solve_tiles_fwd;    /* 64 x 64 tiles one forward substitution reads (all
+                                 subdomains; the tiles inside the row profiles) */
+  int64_t solve_tiles_bwd;    /* the same for the backward substitution (Cholesky: the
+                                 same tiles read by columns; LU: the tiles of U inside
+                                 its column profiles) */
+  int64_t lower_tiles;        /* lower tiles of all local factors, sum nt_i (nt_i + 1) / 2
+                                 (what the product with explicit inverses reads) */
 } tls_info_t;
 
 /* Fill *opt with the defaults listed above. */

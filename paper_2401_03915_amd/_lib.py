@@ -106,6 +106,11 @@ class tls_info_t(C.Structure):
         ("local_refine", C.c_int32),
         ("symv_block", C.c_int32),
         ("factor_panel", C.c_int32),
+        ("factor_flops", C.c_double),
+        ("inverse_flops", C.c_double),
+        ("solve_tiles_fwd", C.c_int64),
+        ("solve_tiles_bwd", C.c_int64),
+        ("lower_tiles", C.c_int64),
     ]
 
 

@@ -95,7 +95,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.solve_order < 0 || c->opt.solve_order > 5) tls::fail(TLS_E_ARG, "solve_order must be in [0, 5]");
     if (c->opt.solve_wgs < 0) tls::fail(TLS_E_ARG, "solve_wgs must be >= 0");
     if (c->opt.composition != 0 && c->opt.composition != 1) tls::fail(TLS_E_ARG, "composition must be 0 or 1");
-    if (c->opt.local_inverse != 0 && c->opt.local_inverse != 1) tls::fail(TLS_E_ARG, "local_inverse must be 0 or 1");
+    if (c->opt.local_inverse < 0 || c->opt.local_inverse > 2) tls::fail(TLS_E_ARG, "local_inverse must be 0, 1 or 2");
     if (c->opt.local_inverse && c->opt.matrix_kind != 0)
       tls::fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
     if (c->opt.local_refine < 0 || c->opt.local_refine > 8) tls::fail(TLS_E_ARG, "local_refine must be in [0, 8]");
@@ -178,7 +178,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
       c->ras_t.alloc(n);
       c->ras_u.alloc(n);
     }
-    if (c->opt.local_inverse) {
+    if (c->opt.local_inverse == 1 || (c->opt.local_inverse == 2 && tls::inverse_pays(c.get()))) {
       t = clk::now();
       tls::form_local_inverse(c.get());
       c->t_inverse = ms_since(t);
@@ -276,6 +276,9 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->local_refine = c->refine;
   info->symv_block = c->inv_formed ? c->symv_block : 0;
   info->factor_panel = c->factor_panel;
+  info->factor_flops = c->flops_factor;
+  info->inverse_flops = c->inv_formed ? c->flops_inverse : 0.0;
+  tls::solve_tile_counts(c, &info->solve_tiles_fwd, &info->solve_tiles_bwd, &info->lower_tiles);
   tls_ctx* cm = const_cast<tls_ctx*>(c);
   bool wt = cm->apply_wait_seen;
   if (guard(cm, [&]() { wt = tls::take_wait_flag(cm) || wt; }) != TLS_OK) return TLS_E_HIP;

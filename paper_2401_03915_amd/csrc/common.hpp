@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "tls.h"
@@ -145,6 +146,10 @@ struct DBuf {
     if (p) devmem::release(p, n * sizeof(T));
     p = nullptr;
     n = 0;
+  }
+  void swap(DBuf& o) {
+    std::swap(p, o.p);
+    std::swap(n, o.n);
   }
   void alloc(size_t count) {
     release();

@@ -43,6 +43,12 @@ struct tls_ctx {
   tls::DBuf<double> fac64;
   tls::DBuf<float> fac32;
   tls::DBuf<double> scale;  // Jacobi scaling per padded position (or empty)
+  // tile profile (SPD): first tile column of tile row r of A_ii that holds
+  // a nonzero, at toff_i + r. The Cholesky factor has no fill left of it,
+  // so the factorization, the inverse and the substitutions skip those tiles.
+  tls::DBuf<int> prof;
+  std::vector<int> h_prof;
+  double flops_factor = 0, flops_inverse = 0;  // their arithmetic with the profile (2 per multiply-add)
   // inverses of the diagonal tiles (one per tile row, at (toff_i + r) * 64^2)
   tls::DBuf<double> dinv64;
   tls::DBuf<float> dinv32;

@@ -16,6 +16,7 @@
 // the blocks it reads, streams its tiles through a 256-thread GEMV and
 // finishes with a one-wave substitution on the diagonal tile.
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 
 #include "kernels.hpp"
@@ -56,11 +57,22 @@ __global__ void k_jacobi_scale(int total, const int* __restrict__ sub_idx, const
   scale[voff[i] + (p - sub_ptr[i])] = 1.0 / sqrt(d);
 }
 
+// prof[toff_i + r] = r: the diagonal tile (padding rows hold the identity);
+// for LU also the column profile at prof[sum_nt + toff_i + c] = c
+__global__ void k_prof_init(int N, LocalLayout lay, int64_t colp, int* prof) {
+  const int i = blockIdx.x;
+  for (int r = threadIdx.x; r < lay.nt[i]; r += blockDim.x) {
+    prof[lay.toff[i] + r] = r;
+    if (colp) prof[colp + lay.toff[i] + r] = r;
+  }
+}
+
 template <class T>
 __global__ void k_gather(int total, const int* __restrict__ sub_idx, const int* __restrict__ sub_of_pos,
                          const int* __restrict__ sub_ptr, const int* __restrict__ layer_ptr, int stride,
                          const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
-                         const double* __restrict__ scale, LocalLayout lay, int kind, T* fac) {
+                         const double* __restrict__ scale, LocalLayout lay, int kind, T* fac, int* prof,
+                         int64_t colp) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= total) return;
   int i = sub_of_pos[p];
@@ -76,6 +88,11 @@ __global__ void k_gather(int total, const int* __restrict__ sub_idx, const int* 
     if (q < 0) continue;
     int b = q - sub_ptr[i];
     if (kind == 0 && b > a) continue;  // Cholesky stores the lower triangle
+    if (prof) {
+      // tile profiles: rows of the lower part, and (LU) columns of the upper part
+      if (b <= a) atomicMin(&prof[lay.toff[i] + a / TS], b / TS);
+      if (colp && a <= b) atomicMin(&prof[colp + lay.toff[i] + b / TS], a / TS);
+    }
     double v = val[j];
     if (scale) v *= sa * scale[lay.voff[i] + b];
     *elem_ptr(base, kind, nt, a, b) = (T)v;
@@ -197,15 +214,21 @@ struct KfPitch<double> {
 template <class T>
 __global__ void __launch_bounds__(256) k_trsm(int k, const int64_t* __restrict__ pref, int nact,
                                               const int* __restrict__ order, LocalLayout lay, T* fac,
-                                              const T* __restrict__ dinv) {
+                                              const T* __restrict__ dinv, const int4* __restrict__ tasks) {
   constexpr int LD = LdsLd<T>::v;
   __shared__ T As[TS * LD];
   __shared__ T Bs[TS * LD];
   const int64_t bid = blockIdx.x;
-  const int j = find_slot(pref, nact, bid);
-  const int i = order[j];
+  int i, r;
+  if (tasks) {  // explicit list (tiles inside the profile): x = i, y = r
+    i = tasks[bid].x;
+    r = tasks[bid].y;
+  } else {
+    const int j = find_slot(pref, nact, bid);
+    i = order[j];
+    r = k + 1 + (int)(bid - pref[j]);
+  }
   const int nt = lay.nt[i];
-  const int r = k + 1 + (int)(bid - pref[j]);
   T* A = fac + lay.foff[i] + tile_index(0, nt, r, k) * TS2;
   const T* Li = dinv + (lay.toff[i] + k) * TS2;
   const int tid = threadIdx.x;
@@ -256,31 +279,42 @@ __global__ void __launch_bounds__(256) k_trsm(int k, const int64_t* __restrict__
 template <class T>
 __global__ void __launch_bounds__(256) k_update_blk(int mode, int kb, int kn, int kf, int kl,
                                                     const int64_t* __restrict__ pref, int nact,
-                                                    const int* __restrict__ order, LocalLayout lay, T* fac) {
+                                                    const int* __restrict__ order, LocalLayout lay, T* fac,
+                                                    const int4* __restrict__ tasks) {
   constexpr int LD = LdsLd<T>::v;
   __shared__ T As[TS * LD];
   __shared__ T Bs[TS * LD];
   const int64_t bid = blockIdx.x;
-  const int j = find_slot(pref, nact, bid);
-  const int i = order[j];
-  const int nt = lay.nt[i];
-  int64_t t = bid - pref[j];
-  int r, c;
-  if (mode == 0) {
-    int rr = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((int64_t)(rr + 1) * (rr + 2) / 2 <= t) rr++;
-    while ((int64_t)rr * (rr + 1) / 2 > t) rr--;
-    int cc = (int)(t - (int64_t)rr * (rr + 1) / 2);
-    r = kf + rr;
-    c = kf + cc;
+  int i, r, c;
+  if (tasks) {  // explicit list: tile (y, z) of subdomain x, K tiles [w & 0xFFFFFF, + w >> 24)
+    const int4 q = tasks[bid];
+    i = q.x;
+    r = q.y;
+    c = q.z;
+    kb = q.w & 0xFFFFFF;
+    kn = q.w >> 24;
   } else {
-    c = kf;
-    while (t >= nt - c) {
-      t -= nt - c;
-      c++;
+    const int j = find_slot(pref, nact, bid);
+    i = order[j];
+    int64_t t = bid - pref[j];
+    if (mode == 0) {
+      int rr = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      while ((int64_t)(rr + 1) * (rr + 2) / 2 <= t) rr++;
+      while ((int64_t)rr * (rr + 1) / 2 > t) rr--;
+      int cc = (int)(t - (int64_t)rr * (rr + 1) / 2);
+      r = kf + rr;
+      c = kf + cc;
+    } else {
+      const int nt_ = lay.nt[i];
+      c = kf;
+      while (t >= nt_ - c) {
+        t -= nt_ - c;
+        c++;
+      }
+      r = c + (int)t;
     }
-    r = c + (int)t;
   }
+  const int nt = lay.nt[i];
   T* base = fac + lay.foff[i];
   T* C = base + tile_index(0, nt, r, c) * TS2;
   const int tid = threadIdx.x;
@@ -425,18 +459,26 @@ __global__ void __launch_bounds__(64) k_getrf(int k, const int* __restrict__ ord
 template <class T>
 __global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restrict__ pref, int nact, int64_t half,
                                                  const int* __restrict__ order, LocalLayout lay, T* fac,
-                                                 const T* __restrict__ dinv) {
+                                                 const T* __restrict__ dinv, const int4* __restrict__ tasks) {
   constexpr int LD = LdsLd<T>::v;
   constexpr int LDB = KfPitch<T>::v;  // conflict-free store and MFMA read of Bs
   __shared__ T As[TS * LD];     // As[kk * LD + row] = left operand (row, kk)
   __shared__ T Bs[TS * LDB];    // Bs[col * LDB + kk] = right operand (kk, col)
   int64_t bid = blockIdx.x;
-  const bool colpanel = bid >= half;
-  if (colpanel) bid -= half;
-  const int j = find_slot(pref, nact, bid);
-  const int i = order[j];
+  bool colpanel;
+  int i, o;
+  if (tasks) {  // explicit list (tiles inside the profiles): x = i, y = o, z = 1 for the L tile (o, k)
+    i = tasks[bid].x;
+    o = tasks[bid].y;
+    colpanel = tasks[bid].z != 0;
+  } else {
+    colpanel = bid >= half;
+    if (colpanel) bid -= half;
+    const int j = find_slot(pref, nact, bid);
+    i = order[j];
+    o = k + 1 + (int)(bid - pref[j]);
+  }
   const int nt = lay.nt[i];
-  const int o = k + 1 + (int)(bid - pref[j]);
   T* base = fac + lay.foff[i];
   const T* Di = dinv + (lay.toff[i] + k) * TS2;
   T* X = base + (colpanel ? tile_index(1, nt, o, k) : tile_index(1, nt, k, o)) * TS2;
@@ -495,7 +537,8 @@ __global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restric
 // panel columns k < c < kl.
 template <class T>
 __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int kl, const int64_t* __restrict__ pref,
-                                                   int nact, const int* __restrict__ order, LocalLayout lay, T* fac) {
+                                                   int nact, const int* __restrict__ order, LocalLayout lay, T* fac,
+                                                   const int4* __restrict__ tasks) {
   constexpr int LD = LdsLd<T>::v;
   // U_kc is kept as stored (k fastest), with the conflict-free pitch for
   // both the store and the MFMA read
@@ -503,29 +546,39 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
   __shared__ T As[TS * LD];
   __shared__ T Bs[TS * LDB];
   const int64_t bid = blockIdx.x;
-  const int j = find_slot(pref, nact, bid);
-  const int i = order[j];
-  const int nt = lay.nt[i];
-  const int kli = min(kl, nt);
-  int64_t t = bid - pref[j];
-  int r, c;
-  if (mode == 0) {
-    const int w = nt - kli;
-    r = kli + (int)(t / w);
-    c = kli + (int)(t % w);
+  int i, r, c;
+  if (tasks) {  // explicit list: tile (y, z) of subdomain x, K tiles [w & 0xFFFFFF, + w >> 24)
+    const int4 q = tasks[bid];
+    i = q.x;
+    r = q.y;
+    c = q.z;
+    kb = q.w & 0xFFFFFF;
+    kn = q.w >> 24;
   } else {
-    const int k = kb;
-    const int64_t ra = kli - k - 1, ca = nt - k - 1;
-    if (t < ra * ca) {
-      r = k + 1 + (int)(t / ca);
-      c = k + 1 + (int)(t % ca);
+    const int j = find_slot(pref, nact, bid);
+    i = order[j];
+    const int nt_ = lay.nt[i];
+    const int kli = min(kl, nt_);
+    int64_t t = bid - pref[j];
+    if (mode == 0) {
+      const int w = nt_ - kli;
+      r = kli + (int)(t / w);
+      c = kli + (int)(t % w);
     } else {
-      t -= ra * ca;
-      const int cb = kli - k - 1;
-      r = kli + (int)(t / cb);
-      c = k + 1 + (int)(t % cb);
+      const int k = kb;
+      const int64_t ra = kli - k - 1, ca = nt_ - k - 1;
+      if (t < ra * ca) {
+        r = k + 1 + (int)(t / ca);
+        c = k + 1 + (int)(t % ca);
+      } else {
+        t -= ra * ca;
+        const int cb = kli - k - 1;
+        r = kli + (int)(t / cb);
+        c = k + 1 + (int)(t % cb);
+      }
     }
   }
+  const int nt = lay.nt[i];
   T* base = fac + lay.foff[i];
   T* C = base + tile_index(1, nt, r, c) * TS2;
   const int tid = threadIdx.x;
@@ -597,9 +650,17 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
 // path): for each k of the panel, the diagonal tile (k_getrf), the row and
 // column strips (k_trsm_lu) and the rest of the panel (k_update_lu mode 1);
 // then the trailing square once with K = 64 PW (mode 0).
+// With tile profiles (profile pr of the rows of the lower part, the first
+// tile column of row r holding a nonzero left of or on the diagonal; pc of
+// the columns of the upper part, the first tile row of column c holding one
+// above or on the diagonal), L has no fill left of pr(r) and U none above
+// pc(c), so only the terms L_rk U_kc with k >= max(pr(r), pc(c)) are formed,
+// from explicit task lists. Returns the arithmetic of the tasks (2 per
+// multiply-add; triangular products counted at half).
 template <class T>
-void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
-                     int* err, int PW = 8) {
+double factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
+                       int* err, int PW = 8, const int* pr = nullptr, const int* pc = nullptr,
+                       const std::vector<int64_t>* toff = nullptr) {
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
@@ -610,16 +671,57 @@ void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const Loc
   };
   std::vector<Launch> launches;
   std::vector<int64_t> pref;
+  std::vector<int4> tasks;
+  const bool prof = pr != nullptr;
+  const double t3 = (double)TS * TS * TS;
+  double flops = 0.0;
   auto active = [&](int k) {
     int a = 0;
     while (a < N && nt[order[a]] > k) a++;
     return a;
   };
+  std::vector<int> R, C;
   for (int k0 = 0; k0 < maxnt; k0 += PW) {
     const int kl = k0 + PW;
     for (int k = k0; k < std::min(kl, maxnt); k++) {
       const int act = active(k);
       launches.push_back(Launch{0, k, 0, 0, 0, act, 0, 0, 0});
+      flops += act * 2.0 * t3 / 3.0;
+      if (prof) {
+        // L tiles (o, k) with pr(o) <= k and U tiles (k, o) with pc(o) <= k,
+        // then the panel's part of their products
+        const int64_t off1 = (int64_t)tasks.size();
+        for (int a = 0; a < act; a++) {
+          const int i = order[a];
+          const int *fr = pr + (*toff)[i], *fc = pc + (*toff)[i];
+          for (int o = k + 1; o < nt[i]; o++) {
+            if (fr[o] <= k) tasks.push_back(int4{i, o, 1, 0});
+            if (fc[o] <= k) tasks.push_back(int4{i, o, 0, 0});
+          }
+        }
+        const int64_t n1 = (int64_t)tasks.size() - off1;
+        flops += (double)n1 * t3;
+        if (n1 > 0) launches.push_back(Launch{1, k, 0, 0, 0, act, off1, n1, 0});
+        const int64_t off2 = (int64_t)tasks.size();
+        for (int a = 0; a < act; a++) {
+          const int i = order[a];
+          const int *fr = pr + (*toff)[i], *fc = pc + (*toff)[i];
+          R.clear();
+          C.clear();
+          for (int o = k + 1; o < nt[i]; o++) {
+            if (fr[o] <= k) R.push_back(o);
+            if (fc[o] <= k) C.push_back(o);
+          }
+          // the panel: rows k < r < kl with every column, rows r >= kl with the panel's columns
+          for (int r : R)
+            for (int c : C)
+              if (r < kl || c < kl) tasks.push_back(int4{i, r, c, k | (1 << 24)});
+        }
+        const int64_t n2 = (int64_t)tasks.size() - off2;
+        flops += 2.0 * (double)n2 * t3;
+        if (n2 > 0) launches.push_back(Launch{2, k, k, 1, kl, act, off2, n2, 0});
+        continue;
+      }
       {
         int64_t off = (int64_t)pref.size(), tot = 0;
         for (int a = 0; a < act; a++) {
@@ -627,6 +729,7 @@ void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const Loc
           tot += nt[order[a]] - k - 1;
         }
         pref.push_back(tot);
+        flops += 2.0 * (double)tot * t3;
         if (tot > 0) launches.push_back(Launch{1, k, 0, 0, 0, act, off, 2 * tot, tot});
       }
       {
@@ -637,55 +740,90 @@ void factor_tiles_lu(hipStream_t s, int N, const std::vector<int>& nt, const Loc
           tot += (kli - k - 1) * (n_ - k - 1) + (n_ - kli) * (kli - k - 1);
         }
         pref.push_back(tot);
+        flops += 2.0 * (double)tot * t3;
         if (tot > 0) launches.push_back(Launch{2, k, k, 1, kl, act, off, tot, 0});
       }
     }
     const int act = active(kl);
-    if (act > 0) {
-      int64_t off = (int64_t)pref.size(), tot = 0;
+    if (act <= 0) continue;
+    if (prof) {
+      const int64_t off = (int64_t)tasks.size();
       for (int a = 0; a < act; a++) {
-        pref.push_back(tot);
-        const int64_t w = nt[order[a]] - kl;
-        tot += w * w;
+        const int i = order[a];
+        const int *fr = pr + (*toff)[i], *fc = pc + (*toff)[i];
+        R.clear();
+        C.clear();
+        for (int o = kl; o < nt[i]; o++) {
+          if (fr[o] < kl) R.push_back(o);
+          if (fc[o] < kl) C.push_back(o);
+        }
+        for (int r : R)
+          for (int c : C) {
+            const int kb = std::max(k0, std::max(fr[r], fc[c]));
+            tasks.push_back(int4{i, r, c, kb | ((kl - kb) << 24)});
+            flops += 2.0 * t3 * (kl - kb);
+          }
       }
-      pref.push_back(tot);
-      if (tot > 0) launches.push_back(Launch{3, kl, k0, PW, kl, act, off, tot, 0});
+      const int64_t n3 = (int64_t)tasks.size() - off;
+      if (n3 > 0) launches.push_back(Launch{3, kl, k0, PW, kl, act, off, n3, 0});
+      continue;
     }
+    int64_t off = (int64_t)pref.size(), tot = 0;
+    for (int a = 0; a < act; a++) {
+      pref.push_back(tot);
+      const int64_t w = nt[order[a]] - kl;
+      tot += w * w;
+    }
+    pref.push_back(tot);
+    flops += 2.0 * (double)tot * t3 * PW;
+    if (tot > 0) launches.push_back(Launch{3, kl, k0, PW, kl, act, off, tot, 0});
   }
   DBuf<int> d_order;
   DBuf<int64_t> d_pref;
+  DBuf<int4> d_tasks;
   d_order.upload(order, s);
   d_pref.upload(pref, s);
+  d_tasks.upload(tasks, s);
   for (const Launch& L : launches) {
+    const int4* tk = prof && L.kind > 0 ? d_tasks.p + L.off : nullptr;
+    const int64_t* pf = prof ? nullptr : d_pref.p + L.off;
     switch (L.kind) {
       case 0:
         hipLaunchKernelGGL(k_getrf<T>, dim3(L.nact), dim3(64), 0, s, L.k, d_order.p, lay, fac, dinv, err);
         break;
       case 1:
-        hipLaunchKernelGGL(k_trsm_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.k, d_pref.p + L.off, L.nact,
-                           L.half, d_order.p, lay, fac, dinv);
+        hipLaunchKernelGGL(k_trsm_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.k, pf, L.nact, L.half,
+                           d_order.p, lay, fac, dinv, tk);
         break;
       case 2:
-        hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, 1, L.kb, L.kn, L.kl,
-                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, 1, L.kb, L.kn, L.kl, pf, L.nact,
+                           d_order.p, lay, fac, tk);
         break;
       default:
-        hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, 0, L.kb, L.kn, L.kl,
-                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        hipLaunchKernelGGL(k_update_lu<T>, dim3((unsigned)L.total), dim3(256), 0, s, 0, L.kb, L.kn, L.kl, pf, L.nact,
+                           d_order.p, lay, fac, tk);
         break;
     }
     TLS_LAUNCH_CHECK();
   }
   TLS_HIP(hipStreamSynchronize(s));
+  return flops;
 }
 
 // Right-looking Cholesky blocked by panels of PW tile columns: inside a
 // panel every step updates only the panel's remaining columns; the rest of
 // the trailing matrix is updated once per panel with K = 64 * PW, which cuts
 // its read-modify-write traffic by PW.
+//
+// With a tile profile (prof[toff_i + r] = f_i(r), the first tile column of
+// row r that holds a nonzero of A_ii), the factor has no fill left of f_i(r)
+// (fill stays inside the envelope), so only the terms L_rk L_ck^T with
+// k >= max(f(r), f(c)) are formed: the kernels take explicit task lists,
+// built here, instead of enumerating every tile. Returns the arithmetic of
+// the tasks (2 per multiply-add; triangular products counted at half).
 template <class T>
-void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
-                  int* err, int PW = 8) {
+double factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac, T* dinv,
+                    int* err, int PW = 8, const int* prof = nullptr, const std::vector<int64_t>* toff = nullptr) {
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
@@ -697,15 +835,52 @@ void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalL
   };
   std::vector<Launch> launches;
   std::vector<int64_t> pref;
+  std::vector<int4> tasks;
+  const double t3 = (double)TS * TS * TS;
+  double flops = 0.0;
   auto active = [&](int k) {
     int a = 0;
     while (a < N && nt[order[a]] > k) a++;
     return a;
   };
+  auto fp = [&](int i) { return prof + (*toff)[i]; };
+  std::vector<int> rows;
   for (int k0 = 0; k0 < maxnt; k0 += PW) {
-    for (int k = k0; k < std::min(k0 + PW, maxnt); k++) {
+    const int kl = k0 + PW;
+    for (int k = k0; k < std::min(kl, maxnt); k++) {
       const int act = active(k);
       launches.push_back(Launch{0, k, 0, 0, 0, 0, act, 0, act});
+      flops += act * t3 / 3.0;
+      if (prof) {
+        // rows below k with a nonzero tile in column k: the trsm tiles, and
+        // the panel columns c < kl among them get the term of column k
+        const int64_t off1 = (int64_t)tasks.size();
+        for (int a = 0; a < act; a++) {
+          const int i = order[a];
+          const int* f = fp(i);
+          for (int r = k + 1; r < nt[i]; r++)
+            if (f[r] <= k) tasks.push_back(int4{i, r, k, 0});
+        }
+        const int64_t n1 = (int64_t)tasks.size() - off1;
+        if (n1 > 0) launches.push_back(Launch{1, k, 0, 0, 0, 0, act, off1, n1});
+        flops += (double)n1 * t3;
+        const int64_t off2 = (int64_t)tasks.size();
+        for (int a = 0; a < act; a++) {
+          const int i = order[a];
+          const int* f = fp(i);
+          rows.clear();
+          for (int r = k + 1; r < nt[i]; r++)
+            if (f[r] <= k) rows.push_back(r);
+          for (size_t x = 0; x < rows.size() && rows[x] < kl; x++)
+            for (size_t y = x; y < rows.size(); y++) {
+              tasks.push_back(int4{i, rows[y], rows[x], k | (1 << 24)});
+              flops += (y == x ? 1.0 : 2.0) * t3;
+            }
+        }
+        const int64_t n2 = (int64_t)tasks.size() - off2;
+        if (n2 > 0) launches.push_back(Launch{2, k, k, 1, k + 1, kl, act, off2, n2});
+        continue;
+      }
       // trsm: tiles (r, k), r > k
       {
         int64_t off = (int64_t)pref.size(), tot = 0;
@@ -714,61 +889,87 @@ void factor_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalL
           tot += nt[order[a]] - k - 1;
         }
         pref.push_back(tot);
+        flops += (double)tot * t3;
         if (tot > 0) launches.push_back(Launch{1, k, 0, 0, 0, 0, act, off, tot});
       }
       // panel columns c in (k, k0 + PW): tiles (r, c), c <= r
       {
-        const int kf = k + 1, kl = k0 + PW;
+        const int kf = k + 1;
         int64_t off = (int64_t)pref.size(), tot = 0;
         for (int a = 0; a < act; a++) {
           pref.push_back(tot);
           const int n_ = nt[order[a]];
-          for (int cc = kf; cc < std::min(kl, n_); cc++) tot += n_ - cc;
+          for (int cc = kf; cc < std::min(kl, n_); cc++) {
+            tot += n_ - cc;
+            flops += (2.0 * (n_ - cc) - 1.0) * t3;
+          }
         }
         pref.push_back(tot);
         if (tot > 0) launches.push_back(Launch{2, k, k, 1, kf, kl, act, off, tot});
       }
     }
     // trailing update from column k0 + PW with the whole panel
-    const int kf = k0 + PW;
-    const int act = active(kf);
-    if (act > 0) {
-      int64_t off = (int64_t)pref.size(), tot = 0;
+    const int act = active(kl);
+    if (act <= 0) continue;
+    if (prof) {
+      const int64_t off = (int64_t)tasks.size();
       for (int a = 0; a < act; a++) {
-        pref.push_back(tot);
-        const int64_t T_ = nt[order[a]] - kf;
-        tot += T_ * (T_ + 1) / 2;
+        const int i = order[a];
+        const int* f = fp(i);
+        rows.clear();
+        for (int r = kl; r < nt[i]; r++)
+          if (f[r] < kl) rows.push_back(r);
+        for (size_t x = 0; x < rows.size(); x++)
+          for (size_t y = x; y < rows.size(); y++) {
+            const int kb = std::max(k0, std::max(f[rows[x]], f[rows[y]]));
+            tasks.push_back(int4{i, rows[y], rows[x], kb | ((kl - kb) << 24)});
+            flops += (y == x ? 1.0 : 2.0) * t3 * (kl - kb);
+          }
       }
-      pref.push_back(tot);
-      if (tot > 0) launches.push_back(Launch{3, kf, k0, PW, kf, 0, act, off, tot});
+      const int64_t n3 = (int64_t)tasks.size() - off;
+      if (n3 > 0) launches.push_back(Launch{3, kl, k0, PW, kl, 0, act, off, n3});
+      continue;
     }
+    int64_t off = (int64_t)pref.size(), tot = 0;
+    for (int a = 0; a < act; a++) {
+      pref.push_back(tot);
+      const int64_t T_ = nt[order[a]] - kl;
+      tot += T_ * (T_ + 1) / 2;
+      flops += (double)T_ * T_ * t3 * PW;
+    }
+    pref.push_back(tot);
+    if (tot > 0) launches.push_back(Launch{3, kl, k0, PW, kl, 0, act, off, tot});
   }
-  // the trsm kernel reads its prefix table with the step-local layout
   DBuf<int> d_order;
   DBuf<int64_t> d_pref;
+  DBuf<int4> d_tasks;
   d_order.upload(order, s);
   d_pref.upload(pref, s);
+  d_tasks.upload(tasks, s);
   for (const Launch& L : launches) {
+    const int4* tk = prof && L.kind > 0 ? d_tasks.p + L.off : nullptr;
+    const int64_t* pf = prof ? nullptr : d_pref.p + L.off;
     switch (L.kind) {
       case 0:
         hipLaunchKernelGGL(k_potrf<T>, dim3(L.nact), dim3(64), 0, s, L.k, d_order.p, lay, fac, dinv, err);
         break;
       case 1:
-        hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.k, d_pref.p + L.off, L.nact,
-                           d_order.p, lay, fac, dinv);
+        hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.k, pf, L.nact, d_order.p, lay,
+                           fac, dinv, tk);
         break;
       case 2:
-        hipLaunchKernelGGL(k_update_blk<T>, dim3((unsigned)L.total), dim3(256), 0, s, 1, L.kb, L.kn, L.kf, L.kl,
-                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        hipLaunchKernelGGL(k_update_blk<T>, dim3((unsigned)L.total), dim3(256), 0, s, 1, L.kb, L.kn, L.kf, L.kl, pf,
+                           L.nact, d_order.p, lay, fac, tk);
         break;
       default:
-        hipLaunchKernelGGL(k_update_blk<T>, dim3((unsigned)L.total), dim3(256), 0, s, 0, L.kb, L.kn, L.kf, 0,
-                           d_pref.p + L.off, L.nact, d_order.p, lay, fac);
+        hipLaunchKernelGGL(k_update_blk<T>, dim3((unsigned)L.total), dim3(256), 0, s, 0, L.kb, L.kn, L.kf, 0, pf,
+                           L.nact, d_order.p, lay, fac, tk);
         break;
     }
     TLS_LAUNCH_CHECK();
   }
   TLS_HIP(hipStreamSynchronize(s));
+  return flops;
 }
 
 // ---------------------------------------------------------------------------
@@ -839,7 +1040,7 @@ template <class T, int MODE>
 __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, int ntasks, int* counter,
                                               int* flags, const int* __restrict__ epoch_ptr, LocalLayout lay,
                                               const T* __restrict__ fac, const T* __restrict__ dinv, T* x,
-                                              int* err, const int* __restrict__ done) {
+                                              int* err, const int* __restrict__ done, const int* __restrict__ prof) {
   if (*done) return;
   constexpr bool BWD = (MODE == BWD_LT || MODE == BWD_U);
   constexpr bool TRANS = (MODE == BWD_LT);
@@ -882,8 +1083,13 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
       }
     }
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    // blocks this task reads: forward c = 0 .. r-1, backward c = nt-1 .. r+1
-    int c = BWD ? nt - 1 : 0;
+    // blocks this task reads: forward c = 0 .. r-1, backward c = nt-1 .. r+1;
+    // with tile profiles, forward starts at the row profile f(r), and
+    // backward skips the blocks whose profile entry g(c) exceeds r (they
+    // hold only zeros): for Cholesky g = f (the tile (c, r) of L), for LU g
+    // is the column profile of U (the tile (r, c))
+    const int* fp = prof ? prof + lay.toff[i] : nullptr;
+    int c = BWD ? nt - 1 : (fp ? fp[r] : 0);
     const int step = BWD ? -1 : 1;
     // the block next to the diagonal is almost always the last dependency:
     // load it, and this row's right-hand side, while the task waits
@@ -924,6 +1130,14 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
         for (int u = 0; u < U; u++) {
           const int cc = c + step * (done_tiles + u);
           const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
+          if (BWD && fp && fp[cc] > r) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              v[u][j] = V4{T(0), T(0), T(0), T(0)};
+              xs[u][j] = T(0);
+            }
+            continue;
+          }
           if (cc == c_last) {
 #pragma unroll
             for (int j = 0; j < 4; j++) v[u][j] = vlast[j];
@@ -960,6 +1174,7 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
       }
       for (; done_tiles < cnt; done_tiles++) {
         const int cc = c + step * done_tiles;
+        if (BWD && fp && fp[cc] > r) continue;
         const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
         const T* xc = xi + cc * TS;
         const bool pre = cc == c_last;
@@ -1255,7 +1470,7 @@ template <class T>
 __global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* __restrict__ pref, int nact,
                                                   const int* __restrict__ order, LocalLayout lay,
                                                   const int64_t* __restrict__ woff, const T* __restrict__ fac,
-                                                  const T* __restrict__ dinv, T* W) {
+                                                  const T* __restrict__ dinv, T* W, const int* __restrict__ prof) {
   constexpr int LD = LdsLd<T>::v;  // A operand (row, kk) at [kk * LD + row]
   constexpr int LDB = KfPitch<T>::v;  // B operand (kk, col) at [col * LDB + kk]
   __shared__ T As[TS * LD];
@@ -1279,16 +1494,19 @@ __global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* 
   const int li = lane & 15, lk = lane >> 4;
   typedef typename Mfma<T>::acc_t acc_t;
   acc_t acc[2][2];
-  // start from the accumulated terms of earlier panels
+  // start from the accumulated terms of earlier panels (none with a
+  // profile: every term of the row is added here)
 #pragma unroll
   for (int x = 0; x < 2; x++)
 #pragma unroll
     for (int y = 0; y < 2; y++) {
       const int col = wc + 16 * y + li;
 #pragma unroll
-      for (int q = 0; q < 4; q++) acc[x][y][q] = Wjk[col * TS + wr + 16 * x + Mfma<T>::row(lane, q)];
+      for (int q = 0; q < 4; q++)
+        acc[x][y][q] = prof ? T(0) : Wjk[col * TS + wr + 16 * x + Mfma<T>::row(lane, q)];
     }
-  const int l0 = k > j0 ? k : j0;
+  // L_jl = 0 left of the profile of row j
+  const int l0 = max(max(k, j0), prof ? prof[lay.toff[i] + j] : 0);
   for (int l = l0; l < j; l++) {
     const T* Ljl = Lb + tile_index(0, nt, j, l) * TS2;
     const T* Wlk = Wb + tile_index(0, nt, l, k) * TS2;
@@ -1515,6 +1733,131 @@ __global__ void __launch_bounds__(256) k_tinv_lauum(const int64_t* __restrict__ 
     }
 }
 
+// With a narrow profile, S = A_ii^{-1} = L^{-T} W is formed by a block back
+// substitution rather than by W^T W: L^T S = W gives, for the lower tiles,
+//   S_rk = L_rr^{-T} (W_rk - sum_{c > r, f(c) <= r} L_cr^T S_ck),   k <= r,
+// where only the rows c whose profile reaches column r contribute. Rows are
+// done in descending order (one launch per r, one workgroup per tile
+// (r, k)); S_rk replaces W_rk, which nothing reads afterwards (the terms of
+// later rows read S_ck with c > r). The diagonal tile comes out full
+// (symmetric), as the symmetric product wants it.
+template <class T>
+__global__ void __launch_bounds__(256) k_sinv_row(int r, const int64_t* __restrict__ pref, int nact,
+                                                  const int* __restrict__ order, LocalLayout lay,
+                                                  const int64_t* __restrict__ woff, const int* __restrict__ prof,
+                                                  const T* __restrict__ fac, const T* __restrict__ dinv, T* W) {
+  constexpr int LDA = KfPitch<T>::v;  // A operand (row, kk) at [row * LDA + kk]
+  constexpr int LDB = KfPitch<T>::v;  // B operand (kk, col) at [col * LDB + kk]
+  __shared__ T As[TS * LDA];
+  __shared__ T Bs[TS * LDB];
+  const int64_t bid = blockIdx.x;
+  const int slot = find_slot(pref, nact, bid);
+  const int i = order[slot];
+  const int k = (int)(bid - pref[slot]);
+  const int nt = lay.nt[i];
+  const T* Lb = fac + lay.foff[i];
+  T* Wb = W + woff[i];
+  const int* f = prof + lay.toff[i];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+  constexpr int PER = TS2 / 256;
+  T pa[PER], pb[PER];
+  // the rows c > r with f(c) <= r, in ascending order; operands of the next
+  // one are loaded while the current one is multiplied
+  int c = r + 1;
+  while (c < nt && f[c] > r) c++;
+  if (c < nt) {
+    const T* Lcr = Lb + tile_index(0, nt, c, r) * TS2;
+    const T* Sck = Wb + tile_index(0, nt, c, k) * TS2;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      pa[u] = Lcr[tid + 256 * u];
+      pb[u] = Sck[tid + 256 * u];
+    }
+  }
+  while (c < nt) {
+    int cn = c + 1;
+    while (cn < nt && f[cn] > r) cn++;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      As[(e / TS) * LDA + e % TS] = pa[u];  // A(row = e / TS, kk = e % TS) = L_cr(kk, row)
+      Bs[(e / TS) * LDB + e % TS] = pb[u];  // B(kk = e % TS, col = e / TS) = S_ck(kk, col)
+    }
+    __syncthreads();
+    if (cn < nt) {
+      const T* Lcr = Lb + tile_index(0, nt, cn, r) * TS2;
+      const T* Sck = Wb + tile_index(0, nt, cn, k) * TS2;
+#pragma unroll
+      for (int u = 0; u < PER; u++) {
+        pa[u] = Lcr[tid + 256 * u];
+        pb[u] = Sck[tid + 256 * u];
+      }
+    }
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+      T a0 = As[(wr + li) * LDA + kk + lk];
+      T a1 = As[(wr + 16 + li) * LDA + kk + lk];
+      T b0 = Bs[(wc + li) * LDB + kk + lk];
+      T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+      acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+    c = cn;
+  }
+  // right-hand side W_rk - acc into Bs (B operand layout), L_rr^{-1} into As
+  // read transposed: A(row, kk) = L_rr^{-1}(kk, row)
+  T* Wrk = Wb + tile_index(0, nt, r, k) * TS2;
+  const T* Dr = dinv + (lay.toff[i] + r) * TS2;
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int row = wr + 16 * x + Mfma<T>::row(lane, q);
+        Bs[col * LDB + row] = Wrk[col * TS + row] - acc[x][y][q];
+      }
+    }
+  for (int e = tid; e < TS2; e += 256) As[(e / TS) * LDA + e % TS] = Dr[e];
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) acc[x][y] = Mfma<T>::zero();
+#pragma unroll 4
+  for (int kk = 0; kk < TS; kk += 4) {
+    T a0 = As[(wr + li) * LDA + kk + lk];
+    T a1 = As[(wr + 16 + li) * LDA + kk + lk];
+    T b0 = Bs[(wc + li) * LDB + kk + lk];
+    T b1 = Bs[(wc + 16 + li) * LDB + kk + lk];
+    acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+    acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+    acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+    acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int col = wc + 16 * y + li;
+#pragma unroll
+      for (int q = 0; q < 4; q++) Wrk[col * TS + wr + 16 * x + Mfma<T>::row(lane, q)] = acc[x][y][q];
+    }
+}
+
 // y_i = S_i x_i for every subdomain. The lower tiles are cut into blocks of
 // B x B tiles (block row R, block column C <= R; B = 8 by default, or 4 for
 // a single matrix, which then has enough blocks to fill the GPU; the
@@ -1712,26 +2055,26 @@ __global__ void k_solve_begin(int* counters, const int* done) {
 
 template <class T>
 void trsv(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
-          const T* fac, const T* dinv, T* x, int* err, const int* done, int grid) {
+          const T* fac, const T* dinv, T* x, int* err, const int* done, int grid, const int* prof = nullptr) {
   const int ntasks = p.ntasks;
   if (ntasks == 0) return;
   grid = std::max(1, std::min(grid, ntasks));
   switch (mode) {
     case FWD_L:
       hipLaunchKernelGGL((k_trsv<T, FWD_L>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,
-                         lay, fac, dinv, x, err, done);
+                         lay, fac, dinv, x, err, done, prof);
       break;
     case BWD_LT:
       hipLaunchKernelGGL((k_trsv<T, BWD_LT>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
-                         epoch, lay, fac, dinv, x, err, done);
+                         epoch, lay, fac, dinv, x, err, done, prof);
       break;
     case FWD_UL:
       hipLaunchKernelGGL((k_trsv<T, FWD_UL>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
-                         epoch, lay, fac, dinv, x, err, done);
+                         epoch, lay, fac, dinv, x, err, done, prof);
       break;
     default:
       hipLaunchKernelGGL((k_trsv<T, BWD_U>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,
-                         lay, fac, dinv, x, err, done);
+                         lay, fac, dinv, x, err, done, prof);
       break;
   }
   TLS_LAUNCH_CHECK();
@@ -1772,6 +2115,11 @@ void gather_local(tls_ctx* c) {
     if (download(c->errflag.p, 1, s)[0]) fail(TLS_E_NOT_SPD, "non-positive diagonal entry (Jacobi scaling)");
     scale = c->scale.p;
   }
+  const int64_t colp = c->kind == 1 ? c->sum_nt : 0;
+  c->prof.alloc(c->sum_nt + colp);
+  hipLaunchKernelGGL(k_prof_init, dim3(c->N), dim3(256), 0, s, c->N, lay, colp, c->prof.p);
+  TLS_LAUNCH_CHECK();
+  int* prof = c->prof.p;
   if (c->fp32) {
     c->fac32.alloc(c->fac_elems);
     TLS_HIP(hipMemsetAsync(c->fac32.p, 0, sizeof(float) * c->fac_elems, s));
@@ -1779,7 +2127,7 @@ void gather_local(tls_ctx* c) {
     TLS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gather<float>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
                        c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, c->row_ptr.p, c->col_idx.p,
-                       c->val.p, scale, lay, c->kind, c->fac32.p);
+                       c->val.p, scale, lay, c->kind, c->fac32.p, prof, colp);
   } else {
     c->fac64.alloc(c->fac_elems);
     TLS_HIP(hipMemsetAsync(c->fac64.p, 0, sizeof(double) * c->fac_elems, s));
@@ -1787,9 +2135,10 @@ void gather_local(tls_ctx* c) {
     TLS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gather<double>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
                        c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, c->row_ptr.p, c->col_idx.p,
-                       c->val.p, scale, lay, c->kind, c->fac64.p);
+                       c->val.p, scale, lay, c->kind, c->fac64.p, prof, colp);
   }
   TLS_LAUNCH_CHECK();
+  c->h_prof = download(c->prof.p, c->sum_nt + colp, s);
   TLS_HIP(hipStreamSynchronize(s));
 }
 
@@ -1801,19 +2150,22 @@ void factor_local(tls_ctx* c) {
   else
     c->dinv64.alloc((size_t)c->sum_nt * TS2);
   if (c->kind == 0) {
+    const int* prof = c->h_prof.empty() ? nullptr : c->h_prof.data();
     if (c->fp32)
-      factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p,
-                          c->factor_panel);
+      c->flops_factor = factor_tiles<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p,
+                                            c->errflag.p, c->factor_panel, prof, &c->h_toff);
     else
-      factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p,
-                           c->factor_panel);
+      c->flops_factor = factor_tiles<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p,
+                                             c->errflag.p, c->factor_panel, prof, &c->h_toff);
   } else {
+    const int* pr = c->h_prof.empty() ? nullptr : c->h_prof.data();
+    const int* pc = pr ? pr + c->sum_nt : nullptr;
     if (c->fp32)
-      factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, c->errflag.p,
-                             c->factor_panel);
+      c->flops_factor = factor_tiles_lu<float>(c->stream, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p,
+                                               c->errflag.p, c->factor_panel, pr, pc, &c->h_toff);
     else
-      factor_tiles_lu<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, c->errflag.p,
-                              c->factor_panel);
+      c->flops_factor = factor_tiles_lu<double>(c->stream, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p,
+                                                c->errflag.p, c->factor_panel, pr, pc, &c->h_toff);
   }
   int err = download(c->errflag.p, 1, c->stream)[0];
   if (err & ERR_PIVOT) {
@@ -2045,7 +2397,7 @@ static void inverse_group(hipStream_t s, const std::vector<int>& order, const st
     switch (L.kind) {
       case 0:
         hipLaunchKernelGGL(k_tinv_row<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.j, L.j0, d_pref.p + L.off,
-                           L.nact, d_order.p, lay, woff, fac, dinv, W);
+                           L.nact, d_order.p, lay, woff, fac, dinv, W, nullptr);
         break;
       case 1:
         hipLaunchKernelGGL(k_tinv_update<T>, dim3((unsigned)L.total), dim3(256), 0, s, L.j0, L.j1, d_pref.p + L.off,
@@ -2061,16 +2413,107 @@ static void inverse_group(hipStream_t s, const std::vector<int>& order, const st
   TLS_HIP(hipStreamSynchronize(s));
 }
 
+// The profile variant for one group: W = L^{-1} row by row (each row j
+// needs only the rows l >= f(j) of its profile; one launch per j), then
+// S = L^{-T} W by descending rows (k_sinv_row), then S copied over the
+// factor. prof is the device copy of the profile.
+template <class T>
+static void inverse_group_profile(hipStream_t s, const std::vector<int>& order, const std::vector<int>& nt,
+                                  const LocalLayout& lay, const int64_t* woff_d, const std::vector<int64_t>& woff,
+                                  const std::vector<int64_t>& foff, T* fac, const T* dinv, T* W, const int* prof,
+                                  bool copy_back) {
+  const int N = (int)order.size();
+  const int maxnt = N ? nt[order[0]] : 0;
+  auto active = [&](int j) {
+    int a = 0;
+    while (a < N && nt[order[a]] > j) a++;
+    return a;
+  };
+  std::vector<int64_t> pref;
+  std::vector<std::pair<int64_t, int>> rows;  // prefix offset, active count per row j
+  for (int j = 0; j < maxnt; j++) {
+    const int act = active(j);
+    rows.push_back({(int64_t)pref.size(), act});
+    for (int a = 0; a <= act; a++) pref.push_back((int64_t)a * (j + 1));
+  }
+  DBuf<int> d_order;
+  DBuf<int64_t> d_pref;
+  d_order.upload(order, s);
+  d_pref.upload(pref, s);
+  for (int j = 0; j < maxnt; j++) {
+    const int act = rows[j].second;
+    hipLaunchKernelGGL(k_tinv_row<T>, dim3((unsigned)((int64_t)act * (j + 1))), dim3(256), 0, s, j, 0,
+                       d_pref.p + rows[j].first, act, d_order.p, lay, woff_d, fac, dinv, W, prof);
+    TLS_LAUNCH_CHECK();
+  }
+  for (int r = maxnt - 1; r >= 0; r--) {
+    const int act = rows[r].second;
+    hipLaunchKernelGGL(k_sinv_row<T>, dim3((unsigned)((int64_t)act * (r + 1))), dim3(256), 0, s, r,
+                       d_pref.p + rows[r].first, act, d_order.p, lay, woff_d, prof, fac, dinv, W);
+    TLS_LAUNCH_CHECK();
+  }
+  if (copy_back)
+    for (int i : order)
+      TLS_HIP(hipMemcpyAsync(fac + foff[i], W + woff[i], sizeof(T) * tiles_of(0, nt[i]) * TS2,
+                             hipMemcpyDeviceToDevice, s));
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
+// Arithmetic of the two ways of forming S from L (2 per multiply-add,
+// triangular products at half): with the profile (W row by row, S by the
+// back substitution) and dense (W by panels, S = W^T W).
+struct InverseFlops {
+  double profile = 0.0, dense = 0.0;
+};
+inline InverseFlops inverse_flops(const std::vector<int>& nt, const int* prof, const std::vector<int64_t>& toff) {
+  InverseFlops fl;
+  const double t3 = (double)TS * TS * TS;
+  for (size_t i = 0; i < nt.size(); i++) {
+    const int n = nt[i];
+    fl.dense += 2.0 / 3.0 * std::pow((double)TS * n, 3);
+    if (!prof) continue;
+    const int* f = prof + toff[i];
+    for (int j = 0; j < n; j++)
+      for (int k = 0; k < j; k++) {
+        const int l0 = std::max(k, f[j]);
+        if (j > l0) fl.profile += (2.0 * (j - l0) + 1.0) * t3;
+      }
+    for (int r = 0; r < n; r++) {
+      int cnt = 0;
+      for (int c = r + 1; c < n; c++) cnt += f[c] <= r;
+      fl.profile += (r + 1) * (2.0 * cnt + 1.0) * t3;
+    }
+  }
+  return fl;
+}
+
 // W holds the blocks of one group of subdomains at a time. The groups
 // (largest subdomains first) are cut so that W fits in 90% of the device
 // memory still available; when everything fits there is one group.
+// With a profile (prof, device) and fac_buf, the buffer that holds the
+// factors with offsets foff: when W fits beside the factors it takes their
+// layout, the result is formed there and the two buffers are swapped (no
+// clearing, no copy: the profile variant writes every lower tile of W).
 template <class T>
 void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac,
-                        const T* dinv) {
+                        const T* dinv, const int* prof = nullptr, const std::vector<int64_t>* foff = nullptr,
+                        DBuf<T>* fac_buf = nullptr) {
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
   const int64_t budget = (int64_t)(0.9 * (double)devmem::available() / sizeof(T));
+  if (prof && fac_buf && N > 0) {
+    const int64_t need = (*foff)[N - 1] + tiles_of(0, nt[N - 1]) * TS2;
+    if (need <= budget) {
+      DBuf<int64_t> d_woff;
+      d_woff.upload(*foff, s);
+      DBuf<T> W;
+      W.alloc(need);
+      inverse_group_profile<T>(s, order, nt, lay, d_woff.p, *foff, *foff, fac, dinv, W.p, prof, false);
+      fac_buf->swap(W);
+      return;
+    }
+  }
   std::vector<std::vector<int>> groups;
   std::vector<int64_t> woff(N, 0);
   int64_t wmax = 1, tot = 0;
@@ -2092,7 +2535,10 @@ void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const 
   W.alloc(wmax);
   for (const auto& g : groups) {
     TLS_HIP(hipMemsetAsync(W.p, 0, sizeof(T) * wmax, s));
-    inverse_group<T>(s, g, nt, lay, d_woff.p, fac, dinv, W.p);
+    if (prof)
+      inverse_group_profile<T>(s, g, nt, lay, d_woff.p, woff, *foff, fac, dinv, W.p, prof, true);
+    else
+      inverse_group<T>(s, g, nt, lay, d_woff.p, fac, dinv, W.p);
   }
 }
 
@@ -2162,13 +2608,43 @@ void build_symv_work(SymvWork& w, hipStream_t s, int N, const std::vector<int>& 
   TLS_HIP(hipStreamSynchronize(s));
 }
 
+void solve_tile_counts(const tls_ctx* c, int64_t* fwd, int64_t* bwd, int64_t* lower) {
+  int64_t f = 0, b = 0, d = 0;
+  const bool prof = !c->h_prof.empty();
+  for (int i = 0; i < c->N; i++) {
+    const int nt = c->h_nt[i];
+    const int64_t t0 = c->h_toff[i];
+    d += (int64_t)nt * (nt + 1) / 2;
+    for (int r = 0; r < nt; r++) {
+      f += prof ? r - c->h_prof[t0 + r] + 1 : r + 1;
+      b += prof ? r - c->h_prof[(c->kind == 1 ? c->sum_nt : 0) + t0 + r] + 1 : r + 1;
+    }
+  }
+  *fwd = f;
+  *bwd = b;
+  *lower = d;
+}
+
+bool inverse_pays(const tls_ctx* c) {
+  if (c->kind != 0) return false;
+  int64_t f, b, d;
+  solve_tile_counts(c, &f, &b, &d);
+  return f + b > d;
+}
+
 void form_local_inverse(tls_ctx* c) {
   if (c->kind != 0) fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
   hipStream_t s = c->stream;
+  // the profile variant when it saves at least half of the arithmetic
+  const InverseFlops fl = inverse_flops(c->h_nt, c->h_prof.empty() ? nullptr : c->h_prof.data(), c->h_toff);
+  const bool use_prof = !c->h_prof.empty() && fl.profile < 0.5 * fl.dense;
+  c->flops_inverse = use_prof ? fl.profile : fl.dense;
+  const int* prof = use_prof ? c->prof.p : nullptr;
   if (c->fp32)
-    form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p);
+    form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, prof, &c->h_foff, &c->fac32);
   else
-    form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p);
+    form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, prof, &c->h_foff,
+                               &c->fac64);
   build_symv_work(c->inv_work, s, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32, c->symv_block);
   c->inv_formed = true;
 }
@@ -2214,18 +2690,22 @@ void local_solve(tls_ctx* c, const int* done, hipEvent_t ev_begin, hipEvent_t ev
   solve_begin(s, c->counters.p, done);
   if (ev_begin) TLS_HIP(hipEventRecord(ev_begin, s));
   const int fm = c->kind == 0 ? FWD_L : FWD_UL, bm = c->kind == 0 ? BWD_LT : BWD_U;
+  // forward: row profile; backward: the row profile again (Cholesky, read
+  // by columns) or the column profile of U (LU)
+  const int* prof = c->h_prof.empty() ? nullptr : c->prof.p;
+  const int* profb = prof && c->kind == 1 ? prof + c->sum_nt : prof;
   if (c->fp32) {
     trsv<float>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac32.p, c->dinv32.p, c->xloc32.p,
-                c->errflag.p, done, c->solve_grid);
+                c->errflag.p, done, c->solve_grid, prof);
     if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
     trsv<float>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac32.p, c->dinv32.p, c->xloc32.p,
-                c->errflag.p, done, c->solve_grid);
+                c->errflag.p, done, c->solve_grid, profb);
   } else {
     trsv<double>(s, fm, c->plan_fwd, c->counters.p + 0, c->counters.p + 2, lay, c->fac64.p, c->dinv64.p, c->xloc64.p,
-                 c->errflag.p, done, c->solve_grid);
+                 c->errflag.p, done, c->solve_grid, prof);
     if (ev_mid) TLS_HIP(hipEventRecord(ev_mid, s));
     trsv<double>(s, bm, c->plan_bwd, c->counters.p + 1, c->counters.p + 2, lay, c->fac64.p, c->dinv64.p, c->xloc64.p,
-                 c->errflag.p, done, c->solve_grid);
+                 c->errflag.p, done, c->solve_grid, profb);
   }
   if (ev_end) TLS_HIP(hipEventRecord(ev_end, s));
 }

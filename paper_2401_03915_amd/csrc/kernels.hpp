@@ -23,6 +23,12 @@ void build_solve_tasks(tls_ctx* c);
 // (lower tiles, full symmetric diagonal tiles) and build the symmetric-product
 // work list; local_solve uses it from then on
 void form_local_inverse(tls_ctx* c);
+// tiles read by one forward and one backward substitution (inside the
+// profiles), and the lower tiles of all local factors
+void solve_tile_counts(const tls_ctx* c, int64_t* fwd, int64_t* bwd, int64_t* lower);
+// option local_inverse = 2: form the explicit inverses when the two
+// substitutions would read more tiles than the product (all lower tiles)
+bool inverse_pays(const tls_ctx* c);
 // the same for N FP64 Cholesky factors in any tile layout (A_0), and the
 // work list and product of the symmetric product over them
 void form_inverse_f64(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, double* fac,

@@ -1,7 +1,9 @@
 """GPU parity at the full sizes of the benchmark configurations, in the launch
-configuration bench.py times (explicit local inverses for SPD matrices,
-autotuned persistent solves otherwise, PCG/FGMRES captured in hipGraph
-chunks), in FP64 and in mixed mode, against the FP64 oracle:
+configuration bench.py times (for SPD matrices the library's choice between
+substitutions inside the tile profiles and explicit local inverses, with the
+other variant's apply checked too; autotuned persistent solves; PCG/FGMRES
+captured in hipGraph chunks), in FP64 and in mixed mode, against the FP64
+oracle:
 
 * the whole apply z = M^{-1} r with the library's own coarse basis imported
   into the oracle (oracle.pool: every subdomain's sparse LU, A_00 = Z^T A Z
@@ -42,11 +44,12 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ora
 
 def _pc(p, precision, **kw):
     """The benchmark's settings: graph-captured Krylov chunks, autotuned
-    solves, and explicit local inverses for SPD matrices."""
+    solves, and for SPD matrices the library's choice between substitutions
+    inside the tile profiles and explicit local inverses (local_inverse=2)."""
     import paper_2401_03915_amd as tls
+    kw.setdefault("local_inverse", 2 if p.spd else 0)
     return tls.Preconditioner(p.A, p.part, p.overlap, p.nev, precision=precision,
-                              matrix_kind=0 if p.spd else 1, use_graph=1, autotune=1,
-                              local_inverse=1 if p.spd else 0, **kw)
+                              matrix_kind=0 if p.spd else 1, use_graph=1, autotune=1, **kw)
 
 
 def _sample(ex):
@@ -113,6 +116,15 @@ def test_full_size_configuration(cfg):
     err64 = _apply_error(p64, pl, p, comp, seeds)
     say(f"  apply error fp64 {err64:.2e}")
     assert err64 <= 1e-10
+    # -- SPD: the other local-solve variant than the one chosen, same bound
+    if p.spd:
+        other = 0 if p64.info()["local_inverse"] else 1
+        po = _pc(p, 0, local_inverse=other, **kw)
+        erro = _apply_error(po, pl, p, comp, seeds)
+        say(f"  apply error fp64, local_inverse={other}: {erro:.2e}")
+        assert erro <= 1e-10
+        po.close()
+        pl.with_basis(p64.z_sparse())
     # -- sampled local solves (FP64 context): oracle sparse LU
     rng = np.random.default_rng(30 + cfg)
     conds = {}
@@ -128,8 +140,8 @@ def test_full_size_configuration(cfg):
         fwd = np.linalg.norm(x - xo) / np.linalg.norm(xo)
         say(f"  local solve {i} (m={s.size}): backward {bwd:.1e} forward {fwd:.1e}")
         if p.spd:
-            # product with the explicit inverse: forward error of order
-            # cond(A_ii) u, as for the substitutions; bound 20 cond u
+            # substitutions or the product with the explicit inverse: forward
+            # error of order cond(A_ii) u; bound 20 cond u
             lmax = spla.eigsh(Aii, 1, which="LA", return_eigenvectors=False)[0]
             lmin = spla.eigsh(Aii, 1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
             conds[i] = lmax / lmin

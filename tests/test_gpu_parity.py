@@ -159,7 +159,9 @@ def test_local_solves(precision, refine):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_local_inverse_solves(precision):
     """Option local_inverse: each local solve is one product with the
-    explicit A_ii^{-1} = W^T W, W = L^{-1}. Four subdomains of a few thousand
+    explicit A_ii^{-1} (formed as L^{-T} W, W = L^{-1}, by a block back
+    substitution inside the tile profile, as here, or as W^T W when the
+    profile is wide). Four subdomains of a few thousand
     rows (block rows of up to 70 tiles, so several chunks per row and a
     ragged last tile), against the oracle's sparse LU. The explicit inverse
     carries a forward error of order cond(A_ii) u, as the substitutions do:
@@ -184,6 +186,71 @@ def test_local_inverse_solves(precision):
         say("  subdomain", i, "m", s.size, "cond %.1e" % cond, "err", err)
         assert err <= 20 * cond * u
     pc.close()
+
+
+def _tile_profile_counts(A, part, delta, general):
+    """Tiles one forward and one backward substitution read when each local
+    factor skips the tiles left of its rows' first nonzero (and, for LU,
+    above its columns' first nonzero), from the oracle's Omega_i and A_ii,
+    and the lower tiles of all factors."""
+    G = schwarz.sym_pattern(A)
+    fwd = bwd = lower = 0
+    for i in range(int(part.max()) + 1):
+        s = schwarz.overlap(A, part, i, delta, G)
+        C = schwarz.local_matrix(A, s).tocoo()
+        nt = -(-s.size // 64)
+        fr, fc = np.arange(nt), np.arange(nt)
+        lo, up = C.col <= C.row, C.row <= C.col
+        np.minimum.at(fr, C.row[lo] // 64, C.col[lo] // 64)
+        np.minimum.at(fc, C.col[up] // 64, C.row[up] // 64)
+        r = np.arange(nt)
+        fwd += int(np.sum(r - fr + 1))
+        bwd += int(np.sum(r - (fc if general else fr) + 1))
+        lower += nt * (nt + 1) // 2
+    return fwd, bwd, lower
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_tile_profile_and_local_inverse_choice(general):
+    """The tile profiles the factorizations and substitutions skip by
+    (fill stays inside the envelope of A_ii, so the tiles left of each tile
+    row's first nonzero, and for LU above each tile column's first nonzero,
+    stay zero): the tile counts the library reports equal those of the
+    oracle's local matrices; with local_inverse = 2 the explicit inverse is
+    formed exactly when the two substitutions would read more tiles than the
+    product (all lower tiles); both variants give the same apply (FP64, 1e-10 against
+    the oracle with the library's basis)."""
+    torch = torch_cuda()
+    if general:
+        A = one_way_convection_2d(96, np.random.default_rng(5))
+        part = box_partition_2d(96, 96, 3, 3)
+    else:
+        A, part = _hc_problem(160, 4, seed=7)
+    delta = 2
+    fwd, bwd, lower = _tile_profile_counts(A, part, delta, general)
+    say("tile profile", "general" if general else "spd", fwd, bwd, lower)
+    kind = 1 if general else 0
+    pc = _pc(A, part, delta, 4, matrix_kind=kind, local_inverse=0 if general else 2)
+    inf = pc.info()
+    assert (inf["solve_tiles_fwd"], inf["solve_tiles_bwd"], inf["lower_tiles"]) == (fwd, bwd, lower)
+    assert fwd < lower  # the profile skips tiles here
+    if general:
+        pc.close()
+        return
+    assert inf["local_inverse"] == int(fwd + bwd > lower)
+    other = _pc(A, part, delta, 4, local_inverse=1 - inf["local_inverse"])
+    ex = pc.export()
+    ref = oracle.schwarz.setup(A, part, delta, 0, spd=True, Z=pc.z_sparse(ex).toarray())
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        r = rng.standard_normal(A.shape[0])
+        want = oracle.schwarz.apply(ref, r)
+        for q in (pc, other):
+            z = q.apply(to_dev(r))
+            torch.cuda.synchronize()
+            assert np.linalg.norm(z.cpu().numpy() - want) <= 1e-10 * np.linalg.norm(want)
+    pc.close()
+    other.close()
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
