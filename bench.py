@@ -48,6 +48,9 @@ TRAFFIC_SYMV = 16347116314
 TRAFFIC_SPMV = 86755960
 
 
+SOLVE_ROWS = 0  # --solve-rows
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -109,6 +112,7 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         opt.restart = restart
         opt.local_inverse = local_inverse
         opt.local_refine = local_refine
+        opt.solve_rows = SOLVE_ROWS
         opt.use_graph = use_graph
         opt.profile = profile
         # the first setup times the solve launch shapes and records the pick in
@@ -181,6 +185,7 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         "n_profiled": pinfo["n_profiled"],
         "solve_wgs": pinfo["solve_wgs"],
         "solve_order": pinfo["solve_order"],
+        "solve_rows": pinfo["solve_rows"],
         "tuned": pinfo["tuned"],
         "apply_ms_profiled": pinfo["t_apply_ms"],
         "info": info,
@@ -443,7 +448,10 @@ def main():
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length")
     ap.add_argument("--local-inverse", type=int, default=None,
-                    help="1: local solves through the explicit A_ii^{-1} (SPD only; default for SPD), 0: substitutions")
+                    help="2 (default for SPD): the library chooses; 1: local solves through the explicit A_ii^{-1} "
+                         "(SPD only); 0: substitutions")
+    ap.add_argument("--solve-rows", type=int, default=0,
+                    help="block rows per substitution task (1 or 2; 0: autotuned)")
     ap.add_argument("--composition", type=int, default=None,
                     help="0: additive one-level + coarse (PCG for SPD); 1: RAS + deflated coarse correction (FGMRES); "
                          "default 1 for the saddle-point config 6, else 0")
@@ -464,6 +472,8 @@ def main():
     ap.add_argument("--decay", action="store_true",
                     help="run the eigenvalue / singular value decay study against the overlap instead")
     args = ap.parse_args()
+    global SOLVE_ROWS
+    SOLVE_ROWS = args.solve_rows
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the library has no multi-GPU path",
               file=sys.stderr)
@@ -600,7 +610,8 @@ def main():
                 "backward_bytes": 4.0 * 4096.0 * float(info["solve_tiles_bwd"]),
                 "backward_GBps": round(4.0 * 4096.0 * float(info["solve_tiles_bwd"]) / (t_bwd * 1e-3) / 1e9, 1)
                 if t_bwd > 0 else None,
-                "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"]}
+                "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"],
+                "solve_rows": mixed["solve_rows"]}
     def mfma(mode, dt):
         # flops: the library's count of what it ran (SPD: the tiles inside
         # each local matrix's profile); dense_flops: sum_i m_i^3 / 3 (x2 LU),

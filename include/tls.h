@@ -121,8 +121,8 @@ typedef struct {
   int32_t autotune;     /* 1: at setup, time candidates and keep the fastest: the panel width of
                            the batched factorization (4, 8 or 16 tiles), the block side of the
                            product with the local inverses (4, 6 or 8 tiles), and the workgroup
-                           count and task order of the persistent solves (not when solve_wgs or
-                           solve_order is set) */
+                           count, task order and rows per task of the persistent solves (not
+                           when solve_wgs or solve_order is set) */
   const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
                              NULL = no persistence. A cached pick is reused without timing. */
   /* Learned warm start (SPD only): host array of TLS_GNN_NWEIGHTS(gnn_c_out)
@@ -164,6 +164,12 @@ typedef struct {
    * one more pass over the local factors. 0 (default): none. Ignored in
    * FP64 mode. */
   int32_t local_refine;
+  /* Block rows per task of the persistent substitutions: 1 or 2. A task of
+   * two rows solves the second with the first's values from LDS, so a long
+   * dependency chain makes half as many round trips through memory.
+   * 0 (default): 1, or the autotuner's pick with autotune = 1 (which
+   * still tunes the workgroup count and order for a rows value set here). */
+  int32_t solve_rows;
   void* stream;         /* hipStream_t */
 } tls_options;
 
@@ -226,6 +232,7 @@ typedef struct {
                                  its column profiles) */
   int64_t lower_tiles;        /* lower tiles of all local factors, sum nt_i (nt_i + 1) / 2
                                  (what the product with explicit inverses reads) */
+  int32_t solve_rows;         /* block rows per task of the persistent substitutions */
 } tls_info_t;
 
 /* Fill *opt with the defaults listed above. */

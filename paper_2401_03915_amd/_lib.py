@@ -68,6 +68,7 @@ class tls_options(C.Structure):
         ("composition", C.c_int32),
         ("local_inverse", C.c_int32),
         ("local_refine", C.c_int32),
+        ("solve_rows", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -111,6 +112,7 @@ class tls_info_t(C.Structure):
         ("solve_tiles_fwd", C.c_int64),
         ("solve_tiles_bwd", C.c_int64),
         ("lower_tiles", C.c_int64),
+        ("solve_rows", C.c_int32),
     ]
 
 

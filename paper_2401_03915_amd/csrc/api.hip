@@ -99,6 +99,7 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.local_inverse && c->opt.matrix_kind != 0)
       tls::fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
     if (c->opt.local_refine < 0 || c->opt.local_refine > 8) tls::fail(TLS_E_ARG, "local_refine must be in [0, 8]");
+    if (c->opt.solve_rows < 0 || c->opt.solve_rows > 2) tls::fail(TLS_E_ARG, "solve_rows must be 0, 1 or 2");
     if (c->opt.gnn_weights || c->opt.gnn_train) {
       if (c->opt.matrix_kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");
       if (c->opt.gnn_weights) tls::gnn_check_weights(c->opt.gnn_c_out);
@@ -279,6 +280,7 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->factor_flops = c->flops_factor;
   info->inverse_flops = c->inv_formed ? c->flops_inverse : 0.0;
   tls::solve_tile_counts(c, &info->solve_tiles_fwd, &info->solve_tiles_bwd, &info->lower_tiles);
+  info->solve_rows = c->solve_rows;
   tls_ctx* cm = const_cast<tls_ctx*>(c);
   bool wt = cm->apply_wait_seen;
   if (guard(cm, [&]() { wt = tls::take_wait_flag(cm) || wt; }) != TLS_OK) return TLS_E_HIP;

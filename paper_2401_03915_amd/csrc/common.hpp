@@ -261,6 +261,7 @@ struct SolvePlan {
   int ntasks = 0;
   DBuf<int> flags;
   int order = 0;
+  int rows = 1;  // block rows per task (1: k_trsv, 2: k_trsv_sr)
 };
 
 // Error bits reported by kernels into a device int.

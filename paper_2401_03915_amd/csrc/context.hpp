@@ -73,6 +73,7 @@ struct tls_ctx {
   tls::DBuf<int> counters;  // [0] fwd task counter, [1] bwd task counter, [2] epoch
   int solve_grid = 1024;
   int solve_order = 4;
+  int solve_rows = 1;  // block rows per substitution task (1 or 2)
 
   // work vectors for the apply (padded local layout)
   tls::DBuf<double> xloc64;

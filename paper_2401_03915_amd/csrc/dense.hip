@@ -1025,6 +1025,43 @@ __device__ inline V stream_load(const V* p) {
 
 constexpr long long SPIN_LIMIT = 1ll << 26;
 
+// Run by the 64 lanes of wave 0 of a solve task: from block row c, stepping
+// towards `stop` (exclusive), the first row that is neither ready (its flag
+// holds this epoch) nor skippable (backward with a profile g: g(cc) >
+// need_row, so the task reads nothing of row cc). 64 rows are checked per
+// round, one per lane, so a task whose dependencies are long solved (or
+// skipped) passes them in a few rounds instead of one memory round trip per
+// row. Waits, within SPIN_LIMIT polls, until at least one row is
+// available.
+template <bool BWD>
+__device__ inline int wait_rows(int c, int stop, const int* fl, int epoch, const int* __restrict__ g, int need_row,
+                                int* err) {
+  const int lane = threadIdx.x & 63;
+  constexpr int step = BWD ? -1 : 1;
+  int lim = c;
+  long long spins = 0;
+  for (;;) {
+    for (;;) {
+      const int cc = lim + step * lane;
+      const bool inr = BWD ? (cc > stop) : (cc < stop);
+      bool ok = false;
+      if (inr) ok = (g && g[cc] > need_row) || load_flag(&fl[cc]) == epoch;
+      const uint64_t m = __ballot(ok);
+      const int run = ~m == 0ull ? 64 : __builtin_ctzll(~m);
+      lim += step * run;
+      if (run < 64) break;
+    }
+    if (lim != c) break;
+    if (++spins > SPIN_LIMIT) {
+      if (lane == 0) atomicOr(err, ERR_WAIT);
+      lim += step;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return lim;
+}
+
 // Solve modes of the persistent triangular-solve kernel.
 //   FWD_L : L y = b, L lower with its diagonal (Cholesky), block rows ascending
 //   BWD_LT: L^T x = y (Cholesky), block rows descending, tiles read transposed
@@ -1103,20 +1140,9 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
     }
     const T brow = tid < 64 ? xi[r * TS + tid] : T(0);
     while (BWD ? (c > r) : (c < r)) {
-      if (tid == 0) {
-        int lim = c;
-        long long spins = 0;
-        for (;;) {
-          while ((BWD ? (lim > r) : (lim < r)) && load_flag(&fl[lim]) == epoch) lim += step;
-          if (lim != c) break;
-          if (++spins > SPIN_LIMIT) {
-            atomicOr(err, ERR_WAIT);
-            lim += step;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-        }
-        s_lim = lim;
+      if (tid < 64) {
+        const int lim = wait_rows<BWD>(c, r, fl, epoch, BWD ? fp : nullptr, r, err);
+        if (tid == 0) s_lim = lim;
       }
       __syncthreads();
       const int lim = s_lim;
@@ -2046,6 +2072,253 @@ __global__ void __launch_bounds__(64) k_symv_reduce(const SymvRow* __restrict__ 
 }
 
 
+// The same substitution by tasks of up to S consecutive block rows of one
+// subdomain (S = 2). A task first accumulates, for all its rows, the blocks
+// of the rows solved by earlier tasks (waiting on their flags as k_trsv
+// does), then solves its rows one after the other with the blocks between
+// them, taking the solved values from LDS, and publishes all its rows with
+// one store completion and one flag each. On a long dependency chain this
+// halves the number of round trips through memory (flag, values, store
+// completion) on the chain. Task (x, y, z) = (subdomain, first row, number
+// of rows); rows go up from y forward and down from y backward.
+template <class T, int MODE, int S>
+__global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks, int ntasks, int* counter,
+                                                 int* flags, const int* __restrict__ epoch_ptr, LocalLayout lay,
+                                                 const T* __restrict__ fac, const T* __restrict__ dinv, T* x,
+                                                 int* err, const int* __restrict__ done,
+                                                 const int* __restrict__ prof) {
+  if (*done) return;
+  constexpr bool BWD = (MODE == BWD_LT || MODE == BWD_U);
+  constexpr bool TRANS = (MODE == BWD_LT);
+  constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
+  constexpr int G = TrsvUnroll<T>::v / S > 0 ? TrsvUnroll<T>::v / S : 1;  // columns whose tiles load together
+  constexpr int NIN = S * (S - 1) / 2;
+  constexpr bool PRE = sizeof(T) == 4;  // preload the last dependency's tiles (FP32: registers allow it)
+  typedef typename Vec4<T>::type V4;
+  __shared__ T s_red[16 * TS];
+  __shared__ T s_rhs[TS];
+  __shared__ T s_x[S][TS];
+  __shared__ int s_task, s_lim;
+  const int tid = threadIdx.x;
+  const int rg = tid & 15, cg = tid >> 4;
+  const int epoch = *epoch_ptr;
+  constexpr int step = BWD ? -1 : 1;
+  const V4 zero4 = V4{T(0), T(0), T(0), T(0)};
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_task;
+    if (t >= ntasks) break;
+    const int4 tk = tasks[t];
+    const int i = tk.x, r0 = tk.y, cnt = tk.z;
+    const int nt = lay.nt[i];
+    const T* base = fac + lay.foff[i];
+    T* xi = x + lay.voff[i];
+    int* fl = flags + lay.toff[i];
+    const int* fp = prof ? prof + lay.toff[i] : nullptr;
+    // is the block that row rs takes from block row cc inside the profile?
+    auto live = [&](int rs, int cc) { return !fp || (BWD ? fp[cc] <= rs : fp[rs] <= cc); };
+    auto tile_of = [&](int rs, int cc) {
+      return base + (TRANS ? tile_index(KIND, nt, cc, rs) : tile_index(KIND, nt, rs, cc)) * TS2;
+    };
+    // diagonal-tile inverses and the blocks between the task's rows -> registers
+    V4 dv[S][4];
+#pragma unroll
+    for (int q = 0; q < S; q++) {
+      const int rs = r0 + step * q;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        dv[q][j] = zero4;
+        if (q < cnt) {
+          dv[q][j] = stream_load(reinterpret_cast<const V4*>(dinv + (lay.toff[i] + rs) * TS2 + (cg + 16 * j) * TS +
+                                                             4 * rg));
+          if (MODE == FWD_UL || MODE == BWD_U) {
+            const int col = cg + 16 * j, a0 = 4 * rg;
+            const bool lower = MODE == FWD_UL;
+            if (lower ? !(a0 + 0 > col) : !(a0 + 0 <= col)) dv[q][j].x = T(0);
+            if (lower ? !(a0 + 1 > col) : !(a0 + 1 <= col)) dv[q][j].y = T(0);
+            if (lower ? !(a0 + 2 > col) : !(a0 + 2 <= col)) dv[q][j].z = T(0);
+            if (lower ? !(a0 + 3 > col) : !(a0 + 3 <= col)) dv[q][j].w = T(0);
+          }
+        }
+      }
+    }
+    V4 vin[NIN > 0 ? NIN : 1][4];
+#pragma unroll
+    for (int s = 1; s < S; s++)
+#pragma unroll
+      for (int q = 0; q < s; q++) {
+        const int rs = r0 + step * s, rq = r0 + step * q;
+        const bool on = s < cnt && live(rs, rq);
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          vin[s * (s - 1) / 2 + q][j] =
+              on ? stream_load(reinterpret_cast<const V4*>(tile_of(rs, rq) + (cg + 16 * j) * TS + 4 * rg)) : zero4;
+      }
+    T brow[S];
+#pragma unroll
+    for (int q = 0; q < S; q++) brow[q] = (tid < 64 && q < cnt) ? xi[(r0 + step * q) * TS + tid] : T(0);
+    T acc[S][4];
+#pragma unroll
+    for (int q = 0; q < S; q++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) acc[q][j] = T(0);
+    // rows solved by earlier tasks: forward c in [min f(rs), r0), backward c in (r0, nt)
+    int c = BWD ? nt - 1 : 0;
+    if (!BWD && fp) {
+      c = r0;
+#pragma unroll
+      for (int q = 0; q < S; q++)
+        if (q < cnt) c = min(c, fp[r0 + q]);
+    }
+    const int c_last = r0 - step;  // the previous task's last row: almost always the last dependency
+    V4 vlast[PRE ? S : 1][4];
+    if (PRE) {
+      const bool has = BWD ? (c_last < nt) : (c_last >= 0);
+#pragma unroll
+      for (int q = 0; q < (PRE ? S : 1); q++) {
+        const int rs = r0 + step * q;
+        const bool on = has && q < cnt && live(rs, c_last);
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          vlast[q][j] =
+              on ? stream_load(reinterpret_cast<const V4*>(tile_of(rs, c_last) + (cg + 16 * j) * TS + 4 * rg)) : zero4;
+      }
+    }
+    while (BWD ? (c > r0) : (c < r0)) {
+      if (tid < 64) {
+        // backward: the task's rows are r0 and below, so row cc is read only if g(cc) <= r0
+        const int lim = wait_rows<BWD>(c, r0, fl, epoch, BWD ? fp : nullptr, r0, err);
+        if (tid == 0) s_lim = lim;
+      }
+      __syncthreads();
+      const int lim = s_lim;
+      const int ncol = BWD ? c - lim : lim - c;
+      for (int d = 0; d < ncol; d += G) {
+        V4 v[G][S][4];
+        T xs[G][4];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+          const int cc = c + step * (d + g);
+          const bool col_on = d + g < ncol;
+#pragma unroll
+          for (int q = 0; q < S; q++) {
+            const int rs = r0 + step * q;
+            const bool on = col_on && q < cnt && live(rs, cc);
+            const bool pre = PRE && cc == c_last;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+              v[g][q][j] = !on ? zero4
+                               : (pre ? vlast[PRE ? q : 0][j]
+                                      : stream_load(reinterpret_cast<const V4*>(tile_of(rs, cc) + (cg + 16 * j) * TS +
+                                                                                4 * rg)));
+          }
+          const T* xc = xi + cc * TS;
+#pragma unroll
+          for (int j = 0; j < 4; j++)
+            xs[g][j] = col_on ? load_shared(TRANS ? xc + 4 * rg + j : xc + cg + 16 * j) : T(0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; g++)
+#pragma unroll
+          for (int q = 0; q < S; q++) {
+            if (!TRANS) {
+#pragma unroll
+              for (int j = 0; j < 4; j++) {
+                acc[q][0] += v[g][q][j].x * xs[g][j];
+                acc[q][1] += v[g][q][j].y * xs[g][j];
+                acc[q][2] += v[g][q][j].z * xs[g][j];
+                acc[q][3] += v[g][q][j].w * xs[g][j];
+              }
+            } else {
+#pragma unroll
+              for (int j = 0; j < 4; j++)
+                acc[q][j] += v[g][q][j].x * xs[g][0] + v[g][q][j].y * xs[g][1] + v[g][q][j].z * xs[g][2] +
+                             v[g][q][j].w * xs[g][3];
+            }
+          }
+      }
+      c = lim;
+      __syncthreads();
+    }
+    // the task's rows in order, each with the blocks of the rows solved before it here
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+      if (s >= cnt) break;
+#pragma unroll
+      for (int q = 0; q < s; q++) {
+        if (!TRANS) {
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            const T xv = s_x[q][cg + 16 * j];
+            acc[s][0] += vin[s * (s - 1) / 2 + q][j].x * xv;
+            acc[s][1] += vin[s * (s - 1) / 2 + q][j].y * xv;
+            acc[s][2] += vin[s * (s - 1) / 2 + q][j].z * xv;
+            acc[s][3] += vin[s * (s - 1) / 2 + q][j].w * xv;
+          }
+        } else {
+          const T x0 = s_x[q][4 * rg], x1 = s_x[q][4 * rg + 1], x2 = s_x[q][4 * rg + 2], x3 = s_x[q][4 * rg + 3];
+#pragma unroll
+          for (int j = 0; j < 4; j++)
+            acc[s][j] += vin[s * (s - 1) / 2 + q][j].x * x0 + vin[s * (s - 1) / 2 + q][j].y * x1 +
+                         vin[s * (s - 1) / 2 + q][j].z * x2 + vin[s * (s - 1) / 2 + q][j].w * x3;
+        }
+      }
+      if (!TRANS) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = acc[s][q];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = acc[s][j];
+      }
+      __syncthreads();
+      if (tid < 64) {
+        T sum = T(0);
+#pragma unroll
+        for (int g = 0; g < 16; g++) sum += s_red[g * TS + tid];
+        s_rhs[tid] = brow[s] - sum;
+      }
+      __syncthreads();
+      T a2[4] = {T(0), T(0), T(0), T(0)};
+      if (!TRANS) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const T rv = s_rhs[cg + 16 * j];
+          a2[0] += dv[s][j].x * rv;
+          a2[1] += dv[s][j].y * rv;
+          a2[2] += dv[s][j].z * rv;
+          a2[3] += dv[s][j].w * rv;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = a2[q];
+      } else {
+        const T q0 = s_rhs[4 * rg], q1 = s_rhs[4 * rg + 1], q2 = s_rhs[4 * rg + 2], q3 = s_rhs[4 * rg + 3];
+#pragma unroll
+        for (int j = 0; j < 4; j++) a2[j] = dv[s][j].x * q0 + dv[s][j].y * q1 + dv[s][j].z * q2 + dv[s][j].w * q3;
+#pragma unroll
+        for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = a2[j];
+      }
+      __syncthreads();
+      if (tid < 64) {
+        T val = T(0);
+#pragma unroll
+        for (int g = 0; g < 16; g++) val += s_red[g * TS + tid];
+        if (MODE == FWD_UL) val += s_rhs[tid];  // unit diagonal of L
+        s_x[s][tid] = val;
+        store_shared(xi + (r0 + step * s) * TS + tid, val);
+      }
+      __syncthreads();
+    }
+    if (tid < 64) {
+      __builtin_amdgcn_s_waitcnt(0);  // the coherent stores of every row have completed
+      if (tid == 0)
+        for (int s = 0; s < cnt; s++)
+          __hip_atomic_store(&fl[r0 + step * s], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_solve_begin(int* counters, const int* done) {
   if (*done) return;
   counters[0] = 0;
@@ -2059,6 +2332,29 @@ void trsv(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch,
   const int ntasks = p.ntasks;
   if (ntasks == 0) return;
   grid = std::max(1, std::min(grid, ntasks));
+  if (p.rows == 2) {
+    switch (mode) {
+      case FWD_L:
+        hipLaunchKernelGGL((k_trsv_sr<T, FWD_L, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
+                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
+        break;
+      case BWD_LT:
+        hipLaunchKernelGGL((k_trsv_sr<T, BWD_LT, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
+                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
+        break;
+      case FWD_UL:
+        hipLaunchKernelGGL((k_trsv_sr<T, FWD_UL, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
+                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
+        break;
+      default:
+        hipLaunchKernelGGL((k_trsv_sr<T, BWD_U, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
+                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
+        break;
+    }
+    TLS_LAUNCH_CHECK();
+    return;
+  }
+  if (p.rows != 1) fail(TLS_E_ARG, "triangular-solve tasks of 1 or 2 block rows");
   switch (mode) {
     case FWD_L:
       hipLaunchKernelGGL((k_trsv<T, FWD_L>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,
@@ -2176,11 +2472,13 @@ void factor_local(tls_ctx* c) {
 }
 
 void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::vector<int64_t>& toff, int order,
-                hipStream_t s) {
-  // A task is one block row; row r of subdomain i has "position" r (forward)
-  // or nt_i - 1 - r (backward) in its dependency chain. Every ordering below
-  // sorts a subdomain's rows by position, so a task only ever waits on tasks
-  // handed out before it:
+                hipStream_t s, int S) {
+  // A task is S consecutive block rows (the last task of a subdomain may
+  // hold fewer); task q of subdomain i covers rows qS .. (forward) or
+  // nt_i - 1 - qS down (backward) and has "position" q in its dependency
+  // chain of n_i = ceil(nt_i / S) tasks. Every ordering below sorts a
+  // subdomain's tasks by position, so a task only ever waits on tasks
+  // handed out before it (nt below counts tasks):
   //   1 level order         key = position
   //   2 normalized progress key = position / nt_i
   //   3 longest chain first key = position + (max nt - nt_i)
@@ -2189,35 +2487,41 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
   //         so that the long rows of the largest chains are handed out
   //         before the end and stream most of their tiles early
   const int N = (int)nt.size();
+  std::vector<int> nq(N);
+  for (int i = 0; i < N; i++) nq[i] = (nt[i] + S - 1) / S;
   int maxnt = 0;
-  for (int v : nt) maxnt = std::max(maxnt, v);
+  for (int v : nq) maxnt = std::max(maxnt, v);
   struct Item {
     double key;
     int i, pos;
   };
   std::vector<Item> items;
   for (int i = 0; i < N; i++)
-    for (int pos = 0; pos < nt[i]; pos++) {
+    for (int pos = 0; pos < nq[i]; pos++) {
       double key;
       if (order == 2)
-        key = (pos + 0.5) / nt[i];
+        key = (pos + 0.5) / nq[i];
       else if (order == 3)
-        key = (double)(pos + maxnt - nt[i]);
+        key = (double)(pos + maxnt - nq[i]);
       else if (order >= 4)
-        key = (pos + 0.5) / nt[i] * (1.0 - (order == 4 ? 0.3 : 0.6) * nt[i] / std::max(maxnt, 1));
+        key = (pos + 0.5) / nq[i] * (1.0 - (order == 4 ? 0.3 : 0.6) * nq[i] / std::max(maxnt, 1));
       else
         key = (double)pos;
       items.push_back(Item{key, i, pos});
     }
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
     if (a.key != b.key) return a.key < b.key;
-    if (nt[a.i] != nt[b.i]) return nt[a.i] > nt[b.i];
+    if (nq[a.i] != nq[b.i]) return nq[a.i] > nq[b.i];
     if (a.i != b.i) return a.i < b.i;
     return a.pos < b.pos;
   });
   std::vector<int4> tasks;
   tasks.reserve(items.size());
-  for (const Item& it : items) tasks.push_back(make_int4(it.i, bwd ? nt[it.i] - 1 - it.pos : it.pos, 0, 1));
+  for (const Item& it : items) {
+    const int first = it.pos * S, rows = std::min(S, nt[it.i] - first);
+    tasks.push_back(make_int4(it.i, bwd ? nt[it.i] - 1 - first : first, rows, 0));
+  }
+  p.rows = S;
   const int64_t rows = N ? toff[N] : 0;
   p.tasks.upload(tasks, s);
   p.ntasks = (int)tasks.size();
@@ -2227,16 +2531,17 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
   TLS_HIP(hipStreamSynchronize(s));
 }
 
-void build_local_plans(tls_ctx* c, int order) {
-  build_plan(c->plan_fwd, false, c->h_nt, c->h_toff, order, c->stream);
-  build_plan(c->plan_bwd, true, c->h_nt, c->h_toff, order, c->stream);
+void build_local_plans(tls_ctx* c, int order, int rows) {
+  build_plan(c->plan_fwd, false, c->h_nt, c->h_toff, order, c->stream, rows);
+  build_plan(c->plan_bwd, true, c->h_nt, c->h_toff, order, c->stream, rows);
   c->solve_order = order;
+  c->solve_rows = rows;
 }
 
 void build_solve_tasks(tls_ctx* c) {
   c->counters.alloc(4);
   TLS_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(int) * 4, c->stream));
-  build_local_plans(c, 4);
+  build_local_plans(c, 4, 1);
   // padding entries must stay zero: the padded identity rows then solve to 0
   if (c->fp32) {
     c->xloc32.alloc(c->sum_M);

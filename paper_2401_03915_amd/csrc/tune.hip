@@ -2,7 +2,8 @@
 // (autotune = 1) and kept in a text cache keyed by the problem's shape
 // (tune_cache): a cached pick is reused without timing.
 //
-// 1. Persistent triangular solves: workgroup count and task order.
+// 1. Persistent triangular solves: workgroup count, task order and block
+//    rows per task (1 or 2).
 // 2. Symmetric product with the explicit local inverses: block side of
 //    4, 6 or 8 tiles (partial sums per block against workgroups in flight).
 // 3. Batched factorization: panel width of 4, 8 or 16 tile columns (the
@@ -35,7 +36,7 @@ namespace {
 
 std::string tune_key(const tls_ctx* c) {
   std::ostringstream k;
-  k << "trsv:v5 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
+  k << "trsv:v6 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
     << " sumM=" << c->sum_M << " maxnt=" << c->max_nt;
   return k.str();
 }
@@ -81,32 +82,6 @@ std::string shape_key(const tls_ctx* c, const char* what) {
   k << what << " prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
     << " sumM=" << c->sum_M << " maxnt=" << c->max_nt;
   return k.str();
-}
-
-bool cache_lookup(const char* path, const std::string& key, int* grid, int* order) {
-  if (!path) return false;
-  std::ifstream f(path);
-  std::string line;
-  bool found = false;
-  while (std::getline(f, line)) {
-    auto tab = line.rfind('\t');
-    if (tab == std::string::npos) continue;
-    if (line.substr(0, tab) == key) {
-      int g = 0, ch = 0;
-      if (std::sscanf(line.c_str() + tab + 1, "%d %d", &g, &ch) == 2 && g > 0 && ch >= 1 && ch <= 5) {
-        *grid = g;
-        *order = ch;
-        found = true;
-      }
-    }
-  }
-  return found;
-}
-
-void cache_store(const char* path, const std::string& key, int grid, int order) {
-  if (!path) return;
-  std::ofstream f(path, std::ios::app);
-  if (f) f << key << '\t' << grid << ' ' << order << '\n';
 }
 
 double time_local_solves(tls_ctx* c, int grid, int reps) {
@@ -218,39 +193,47 @@ void choose_solve_grid(tls_ctx* c) {
   const int per_cu = c->fp32 ? 4 : 3;
   c->solve_grid = cus * per_cu;
   c->tuned = 0;
-  if (c->opt.solve_order > 0 && c->opt.solve_order != c->solve_order) build_local_plans(c, c->opt.solve_order);
+  const int rows0 = c->opt.solve_rows > 0 ? c->opt.solve_rows : 1;
+  const int order0 = c->opt.solve_order > 0 ? c->opt.solve_order : c->solve_order;
+  if (order0 != c->solve_order || rows0 != c->solve_rows) build_local_plans(c, order0, rows0);
   if (c->opt.solve_wgs > 0 || c->opt.solve_order > 0) {
     if (c->opt.solve_wgs > 0) c->solve_grid = c->opt.solve_wgs;
     return;
   }
   if (!c->opt.autotune || c->inv_formed) return;  // the symmetric product has no launch shape to tune
-  const std::string key = tune_key(c);
-  int g = 0, ch = 0;
-  if (cache_lookup(c->opt.tune_cache, key, &g, &ch)) {
-    c->solve_grid = g;
-    if (ch != c->solve_order) build_local_plans(c, ch);
+  // a solve_rows option fixes the rows per task; the rest is still tuned
+  const std::string key = tune_key(c) + (c->opt.solve_rows > 0 ? " rows=" + std::to_string(c->opt.solve_rows) : "");
+  int v[3] = {0, 0, 0};
+  if (cache_lookup_ints(c->opt.tune_cache, key, v, 3) && v[0] > 0 && v[1] >= 1 && v[1] <= 5 &&
+      (v[2] == 1 || v[2] == 2)) {
+    c->solve_grid = v[0];
+    if (v[1] != c->solve_order || v[2] != c->solve_rows) build_local_plans(c, v[1], v[2]);
     c->tuned = 2;
     return;
   }
   const int maxper = c->fp32 ? 7 : 3;
   double best = 1e300;
-  int best_g = c->solve_grid, best_ch = c->solve_order;
-  for (int order : {1, 2, 3, 4, 5}) {
-    build_local_plans(c, order);
-    for (int p = 2; p <= maxper; p += 2) {
-      const int cg = cus * std::min(p, maxper);
-      double t = time_local_solves(c, cg, 3);
-      if (t < best) {
-        best = t;
-        best_g = cg;
-        best_ch = order;
+  int best_g = c->solve_grid, best_ch = c->solve_order, best_rows = c->solve_rows;
+  for (int rows : {1, 2})
+    for (int order : {1, 2, 3, 4, 5}) {
+      if (c->opt.solve_rows > 0 && rows != c->opt.solve_rows) continue;
+      build_local_plans(c, order, rows);
+      for (int p = 2; p <= maxper; p += 2) {
+        const int cg = cus * std::min(p, maxper);
+        double t = time_local_solves(c, cg, 3);
+        if (t < best) {
+          best = t;
+          best_g = cg;
+          best_ch = order;
+          best_rows = rows;
+        }
       }
     }
-  }
-  if (best_ch != c->solve_order) build_local_plans(c, best_ch);
+  if (best_ch != c->solve_order || best_rows != c->solve_rows) build_local_plans(c, best_ch, best_rows);
   c->solve_grid = best_g;
   c->tuned = 1;
-  cache_store(c->opt.tune_cache, key, best_g, best_ch);
+  const int pick[3] = {best_g, best_ch, best_rows};
+  cache_store_ints(c->opt.tune_cache, key, pick, 3);
 }
 
 }  // namespace tls

@@ -123,19 +123,22 @@ def test_structurally_nonsymmetric_pattern(delta, precision, tol):
 # local factorization and solves (Section 2.3)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("precision,refine", [(0, 0), (1, 0), (1, 1), (1, 2)])
-def test_local_solves(precision, refine):
+@pytest.mark.parametrize("precision,refine,rows", [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 1), (0, 0, 2), (1, 0, 2),
+                                                   (1, 1, 2)])
+def test_local_solves(precision, refine, rows):
     """Local solves by substitution against the oracle's sparse LU on
     high-contrast subdomains of a few thousand rows (many tiles and a ragged
-    tail). FP64: 1e-11. FP32: the forward error of a backward-stable solve,
+    tail), with tasks of one or two block rows (solve_rows; an odd row count
+    leaves a one-row task at the end). FP64: 1e-11. FP32: the forward error
+    of a backward-stable solve,
     bounded by e_32 = 20 cond(A_ii) u_32. With s local_refine steps (FP64
     residual from the sparse A_ii, FP32 correction) the error contracts by
     at most e_32 per step down to the FP64 floor: the bound is
     e_32^(s+1) + 20 cond(A_ii) u_64, and at most the FP32-mode bar 1e-5."""
     A, part = _hc_problem(128, 2, seed=2)
-    say("local solves", precision, refine)
-    pc = _pc(A, part, 2, 0, precision=precision, local_refine=refine)
-    assert pc.info()["local_refine"] == refine
+    say("local solves", precision, refine, rows)
+    pc = _pc(A, part, 2, 0, precision=precision, local_refine=refine, solve_rows=rows)
+    assert pc.info()["local_refine"] == refine and pc.info()["solve_rows"] == rows
     rng = np.random.default_rng(0)
     for i in range(int(part.max()) + 1):
         s = schwarz.overlap(A, part, i, 2)
@@ -683,15 +686,17 @@ def _cd_problem(m, p, seed):
     return A, part
 
 
-@pytest.mark.parametrize("precision,refine", [(0, 0), (1, 0), (1, 1)])
-def test_general_local_solves(precision, refine):
+@pytest.mark.parametrize("precision,refine,rows", [(0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 0, 2), (1, 0, 2)])
+def test_general_local_solves(precision, refine, rows):
     """LU substitutions (no pivoting) against the oracle's sparse LU on four
-    subdomains of about 2.5k rows (delta 2). FP64: 1e-11. FP32: forward
+    subdomains of about 2.5k rows (delta 2), with tasks of one or two block
+    rows. FP64: 1e-11. FP32: forward
     error within e_32 = 20 cond_2(A_ii) u_32 (cond from a dense SVD); with
     one refinement step within min(1e-5, e_32^2 + 20 cond u_64)."""
     A, part = _cd_problem(96, 2, seed=3)
-    say("general local solves", precision, refine)
-    pc = _pc(A, part, 2, 0, precision=precision, matrix_kind=1, local_refine=refine)
+    say("general local solves", precision, refine, rows)
+    pc = _pc(A, part, 2, 0, precision=precision, matrix_kind=1, local_refine=refine, solve_rows=rows)
+    assert pc.info()["solve_rows"] == rows
     rng = np.random.default_rng(0)
     for i in range(4):
         s = schwarz.overlap(A, part, i, 2)
@@ -1083,7 +1088,7 @@ def test_autotune_cache_reuse(tmp_path, local_inverse):
     i1 = pc1.info()
     lines = open(cache).read().splitlines()
     keys = sorted(line.split(" ")[0] for line in lines)
-    assert keys == (["factor:v1", "symv:v1"] if local_inverse else ["factor:v1", "trsv:v5"])
+    assert keys == (["factor:v1", "symv:v1"] if local_inverse else ["factor:v1", "trsv:v6"])
     pc2 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode(), local_inverse=local_inverse)
     i2 = pc2.info()
     assert open(cache).read().splitlines() == lines  # nothing timed or written again
