@@ -600,11 +600,13 @@ def main():
                 "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4),
                 "launches_timed": mixed["n_profiled"], "reduce_launch_ms": round(t_bwd, 4)}
     else:
-        fwd_kernel = "k_trsv<float, FWD_L>" if prob.spd else "k_trsv<float, FWD_UL>"
+        mode_name = "FWD_L" if prob.spd else "FWD_UL"
+        fwd_kernel = (f"k_trsv_sr<float, {mode_name}, 2>" if mixed["solve_rows"] == 2
+                      else f"k_trsv<float, {mode_name}>")
         roof = {"bound": "hbm", "kernel": f"{fwd_kernel} (forward local solves of one apply, all subdomains)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": TRAFFIC if default_workload else None,
+                "traffic": TRAFFIC if default_workload and mixed["solve_rows"] == 2 else None,
                 "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4),
                 "launches_timed": mixed["n_profiled"], "backward_launch_ms": round(t_bwd, 4),
                 "backward_bytes": 4.0 * 4096.0 * float(info["solve_tiles_bwd"]),
