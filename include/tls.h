@@ -164,9 +164,10 @@ typedef struct {
    * one more pass over the local factors. 0 (default): none. Ignored in
    * FP64 mode. */
   int32_t local_refine;
-  /* Block rows per task of the persistent substitutions: 1 or 2. A task of
-   * two rows solves the second with the first's values from LDS, so a long
-   * dependency chain makes half as many round trips through memory.
+  /* Block rows per task of the persistent substitutions: 1 to 4 with FP32
+   * local solves (precision 1), 1 or 2 in FP64. A task of S rows solves
+   * them in sequence with the earlier rows' values from LDS, so a long
+   * dependency chain makes S times fewer round trips through memory.
    * 0 (default): 1, or the autotuner's pick with autotune = 1 (which
    * still tunes the workgroup count and order for a rows value set here). */
   int32_t solve_rows;

@@ -99,7 +99,8 @@ tls_status tls_setup(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32
     if (c->opt.local_inverse && c->opt.matrix_kind != 0)
       tls::fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
     if (c->opt.local_refine < 0 || c->opt.local_refine > 8) tls::fail(TLS_E_ARG, "local_refine must be in [0, 8]");
-    if (c->opt.solve_rows < 0 || c->opt.solve_rows > 2) tls::fail(TLS_E_ARG, "solve_rows must be 0, 1 or 2");
+    if (c->opt.solve_rows < 0 || c->opt.solve_rows > (c->opt.precision == 1 ? 4 : 2))
+      tls::fail(TLS_E_ARG, "solve_rows must be in [0, 4] (FP32 local solves) or [0, 2] (FP64)");
     if (c->opt.gnn_weights || c->opt.gnn_train) {
       if (c->opt.matrix_kind != 0) tls::fail(TLS_E_ARG, "the learned warm start applies to SPD matrices only");
       if (c->opt.gnn_weights) tls::gnn_check_weights(c->opt.gnn_c_out);

@@ -2073,7 +2073,7 @@ __global__ void __launch_bounds__(64) k_symv_reduce(const SymvRow* __restrict__ 
 
 
 // The same substitution by tasks of up to S consecutive block rows of one
-// subdomain (S = 2). A task first accumulates, for all its rows, the blocks
+// subdomain (S = 2; FP32 also 3 and 4). A task first accumulates, for all its rows, the blocks
 // of the rows solved by earlier tasks (waiting on their flags as k_trsv
 // does), then solves its rows one after the other with the blocks between
 // them, taking the solved values from LDS, and publishes all its rows with
@@ -2093,11 +2093,17 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
   constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
   constexpr int G = TrsvUnroll<T>::v / S > 0 ? TrsvUnroll<T>::v / S : 1;  // columns whose tiles load together
   constexpr int NIN = S * (S - 1) / 2;
-  constexpr bool PRE = sizeof(T) == 4;  // preload the last dependency's tiles (FP32: registers allow it)
+  // the last dependency's tiles preloaded in registers (FP32 up to 3 rows),
+  // the blocks between the task's rows in registers (2 rows) or in LDS
+  // (each thread keeps its own pieces there)
+  constexpr bool PRE = sizeof(T) == 4 && S <= 3;
+  constexpr bool VIN_LDS = S > 2;
+  static_assert(S <= 2 || sizeof(T) == 4, "tasks of more than two rows are built for FP32 only");
   typedef typename Vec4<T>::type V4;
   __shared__ T s_red[16 * TS];
   __shared__ T s_rhs[TS];
   __shared__ T s_x[S][TS];
+  __shared__ T s_in[VIN_LDS ? NIN * TS2 : 1];
   __shared__ int s_task, s_lim;
   const int tid = threadIdx.x;
   const int rg = tid & 15, cg = tid >> 4;
@@ -2143,7 +2149,10 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
         }
       }
     }
-    V4 vin[NIN > 0 ? NIN : 1][4];
+    V4 vin[VIN_LDS || NIN == 0 ? 1 : NIN][4];
+    auto vin_slot = [&](int idx, int j) -> V4* {
+      return reinterpret_cast<V4*>(&s_in[(VIN_LDS ? idx * TS2 : 0) + (cg + 16 * j) * TS + 4 * rg]);
+    };
 #pragma unroll
     for (int s = 1; s < S; s++)
 #pragma unroll
@@ -2151,9 +2160,14 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
         const int rs = r0 + step * s, rq = r0 + step * q;
         const bool on = s < cnt && live(rs, rq);
 #pragma unroll
-        for (int j = 0; j < 4; j++)
-          vin[s * (s - 1) / 2 + q][j] =
-              on ? stream_load(reinterpret_cast<const V4*>(tile_of(rs, rq) + (cg + 16 * j) * TS + 4 * rg)) : zero4;
+        for (int j = 0; j < 4; j++) {
+          const V4 v = on ? stream_load(reinterpret_cast<const V4*>(tile_of(rs, rq) + (cg + 16 * j) * TS + 4 * rg))
+                          : zero4;
+          if (VIN_LDS)
+            *vin_slot(s * (s - 1) / 2 + q, j) = v;
+          else
+            vin[VIN_LDS ? 0 : s * (s - 1) / 2 + q][j] = v;
+        }
       }
     T brow[S];
 #pragma unroll
@@ -2247,21 +2261,23 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
       if (s >= cnt) break;
 #pragma unroll
       for (int q = 0; q < s; q++) {
+        const int idx = s * (s - 1) / 2 + q;
+        V4 w[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) w[j] = VIN_LDS ? *vin_slot(idx, j) : vin[VIN_LDS ? 0 : idx][j];
         if (!TRANS) {
 #pragma unroll
           for (int j = 0; j < 4; j++) {
             const T xv = s_x[q][cg + 16 * j];
-            acc[s][0] += vin[s * (s - 1) / 2 + q][j].x * xv;
-            acc[s][1] += vin[s * (s - 1) / 2 + q][j].y * xv;
-            acc[s][2] += vin[s * (s - 1) / 2 + q][j].z * xv;
-            acc[s][3] += vin[s * (s - 1) / 2 + q][j].w * xv;
+            acc[s][0] += w[j].x * xv;
+            acc[s][1] += w[j].y * xv;
+            acc[s][2] += w[j].z * xv;
+            acc[s][3] += w[j].w * xv;
           }
         } else {
           const T x0 = s_x[q][4 * rg], x1 = s_x[q][4 * rg + 1], x2 = s_x[q][4 * rg + 2], x3 = s_x[q][4 * rg + 3];
 #pragma unroll
-          for (int j = 0; j < 4; j++)
-            acc[s][j] += vin[s * (s - 1) / 2 + q][j].x * x0 + vin[s * (s - 1) / 2 + q][j].y * x1 +
-                         vin[s * (s - 1) / 2 + q][j].z * x2 + vin[s * (s - 1) / 2 + q][j].w * x3;
+          for (int j = 0; j < 4; j++) acc[s][j] += w[j].x * x0 + w[j].y * x1 + w[j].z * x2 + w[j].w * x3;
         }
       }
       if (!TRANS) {
@@ -2326,35 +2342,72 @@ __global__ void k_solve_begin(int* counters, const int* done) {
   counters[2] += 1;
 }
 
+template <class T, int S>
+void trsv_rows_s(hipStream_t s, int mode, SolvePlan& p, int grid, int* counter, const int* epoch,
+                 const LocalLayout& lay, const T* fac, const T* dinv, T* x, int* err, const int* done,
+                 const int* prof) {
+  const int ntasks = p.ntasks;
+  switch (mode) {
+    case FWD_L:
+      hipLaunchKernelGGL((k_trsv_sr<T, FWD_L, S>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
+                         epoch, lay, fac, dinv, x, err, done, prof);
+      break;
+    case BWD_LT:
+      hipLaunchKernelGGL((k_trsv_sr<T, BWD_LT, S>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
+                         epoch, lay, fac, dinv, x, err, done, prof);
+      break;
+    case FWD_UL:
+      hipLaunchKernelGGL((k_trsv_sr<T, FWD_UL, S>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
+                         epoch, lay, fac, dinv, x, err, done, prof);
+      break;
+    default:
+      hipLaunchKernelGGL((k_trsv_sr<T, BWD_U, S>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p,
+                         epoch, lay, fac, dinv, x, err, done, prof);
+      break;
+  }
+  TLS_LAUNCH_CHECK();
+}
+
+template <class T>
+void trsv_rows(hipStream_t s, int mode, SolvePlan& p, int grid, int* counter, const int* epoch,
+               const LocalLayout& lay, const T* fac, const T* dinv, T* x, int* err, const int* done,
+               const int* prof);
+template <>
+void trsv_rows<float>(hipStream_t s, int mode, SolvePlan& p, int grid, int* counter, const int* epoch,
+                      const LocalLayout& lay, const float* fac, const float* dinv, float* x, int* err,
+                      const int* done, const int* prof) {
+  switch (p.rows) {
+    case 2:
+      trsv_rows_s<float, 2>(s, mode, p, grid, counter, epoch, lay, fac, dinv, x, err, done, prof);
+      break;
+    case 3:
+      trsv_rows_s<float, 3>(s, mode, p, grid, counter, epoch, lay, fac, dinv, x, err, done, prof);
+      break;
+    case 4:
+      trsv_rows_s<float, 4>(s, mode, p, grid, counter, epoch, lay, fac, dinv, x, err, done, prof);
+      break;
+    default:
+      fail(TLS_E_ARG, "triangular-solve tasks of 1 to 4 block rows");
+  }
+}
+template <>
+void trsv_rows<double>(hipStream_t s, int mode, SolvePlan& p, int grid, int* counter, const int* epoch,
+                       const LocalLayout& lay, const double* fac, const double* dinv, double* x, int* err,
+                       const int* done, const int* prof) {
+  if (p.rows != 2) fail(TLS_E_ARG, "FP64 triangular-solve tasks of 1 or 2 block rows");
+  trsv_rows_s<double, 2>(s, mode, p, grid, counter, epoch, lay, fac, dinv, x, err, done, prof);
+}
+
 template <class T>
 void trsv(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
           const T* fac, const T* dinv, T* x, int* err, const int* done, int grid, const int* prof = nullptr) {
   const int ntasks = p.ntasks;
   if (ntasks == 0) return;
   grid = std::max(1, std::min(grid, ntasks));
-  if (p.rows == 2) {
-    switch (mode) {
-      case FWD_L:
-        hipLaunchKernelGGL((k_trsv_sr<T, FWD_L, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
-                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
-        break;
-      case BWD_LT:
-        hipLaunchKernelGGL((k_trsv_sr<T, BWD_LT, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
-                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
-        break;
-      case FWD_UL:
-        hipLaunchKernelGGL((k_trsv_sr<T, FWD_UL, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
-                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
-        break;
-      default:
-        hipLaunchKernelGGL((k_trsv_sr<T, BWD_U, 2>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter,
-                           p.flags.p, epoch, lay, fac, dinv, x, err, done, prof);
-        break;
-    }
-    TLS_LAUNCH_CHECK();
+  if (p.rows > 1) {
+    trsv_rows<T>(s, mode, p, grid, counter, epoch, lay, fac, dinv, x, err, done, prof);
     return;
   }
-  if (p.rows != 1) fail(TLS_E_ARG, "triangular-solve tasks of 1 or 2 block rows");
   switch (mode) {
     case FWD_L:
       hipLaunchKernelGGL((k_trsv<T, FWD_L>), dim3(grid), dim3(256), 0, s, p.tasks.p, ntasks, counter, p.flags.p, epoch,

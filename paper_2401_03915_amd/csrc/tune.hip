@@ -3,7 +3,7 @@
 // (tune_cache): a cached pick is reused without timing.
 //
 // 1. Persistent triangular solves: workgroup count, task order and block
-//    rows per task (1 or 2).
+//    rows per task (1 to 4 in FP32, 1 or 2 in FP64).
 // 2. Symmetric product with the explicit local inverses: block side of
 //    4, 6 or 8 tiles (partial sums per block against workgroups in flight).
 // 3. Batched factorization: panel width of 4, 8 or 16 tile columns (the
@@ -204,8 +204,8 @@ void choose_solve_grid(tls_ctx* c) {
   // a solve_rows option fixes the rows per task; the rest is still tuned
   const std::string key = tune_key(c) + (c->opt.solve_rows > 0 ? " rows=" + std::to_string(c->opt.solve_rows) : "");
   int v[3] = {0, 0, 0};
-  if (cache_lookup_ints(c->opt.tune_cache, key, v, 3) && v[0] > 0 && v[1] >= 1 && v[1] <= 5 &&
-      (v[2] == 1 || v[2] == 2)) {
+  if (cache_lookup_ints(c->opt.tune_cache, key, v, 3) && v[0] > 0 && v[1] >= 1 && v[1] <= 5 && v[2] >= 1 &&
+      v[2] <= (c->fp32 ? 4 : 2)) {
     c->solve_grid = v[0];
     if (v[1] != c->solve_order || v[2] != c->solve_rows) build_local_plans(c, v[1], v[2]);
     c->tuned = 2;
@@ -214,9 +214,10 @@ void choose_solve_grid(tls_ctx* c) {
   const int maxper = c->fp32 ? 7 : 3;
   double best = 1e300;
   int best_g = c->solve_grid, best_ch = c->solve_order, best_rows = c->solve_rows;
-  for (int rows : {1, 2})
+  for (int rows : {1, 2, 3, 4})
     for (int order : {1, 2, 3, 4, 5}) {
       if (c->opt.solve_rows > 0 && rows != c->opt.solve_rows) continue;
+      if (!c->fp32 && rows > 2) continue;  // FP64 tasks hold at most two rows
       build_local_plans(c, order, rows);
       for (int p = 2; p <= maxper; p += 2) {
         const int cg = cus * std::min(p, maxper);

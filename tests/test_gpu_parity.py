@@ -124,12 +124,12 @@ def test_structurally_nonsymmetric_pattern(delta, precision, tol):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("precision,refine,rows", [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 1), (0, 0, 2), (1, 0, 2),
-                                                   (1, 1, 2)])
+                                                   (1, 1, 2), (1, 0, 3), (1, 0, 4), (1, 1, 4)])
 def test_local_solves(precision, refine, rows):
     """Local solves by substitution against the oracle's sparse LU on
     high-contrast subdomains of a few thousand rows (many tiles and a ragged
-    tail), with tasks of one or two block rows (solve_rows; an odd row count
-    leaves a one-row task at the end). FP64: 1e-11. FP32: the forward error
+    tail), with tasks of one to four block rows (solve_rows; a row count
+    that the task size does not divide leaves a shorter task at the end). FP64: 1e-11. FP32: the forward error
     of a backward-stable solve,
     bounded by e_32 = 20 cond(A_ii) u_32. With s local_refine steps (FP64
     residual from the sparse A_ii, FP32 correction) the error contracts by
@@ -686,11 +686,12 @@ def _cd_problem(m, p, seed):
     return A, part
 
 
-@pytest.mark.parametrize("precision,refine,rows", [(0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 0, 2), (1, 0, 2)])
+@pytest.mark.parametrize("precision,refine,rows", [(0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 0, 2), (1, 0, 2), (1, 0, 3),
+                                                   (1, 0, 4)])
 def test_general_local_solves(precision, refine, rows):
     """LU substitutions (no pivoting) against the oracle's sparse LU on four
-    subdomains of about 2.5k rows (delta 2), with tasks of one or two block
-    rows. FP64: 1e-11. FP32: forward
+    subdomains of about 2.5k rows (delta 2), with tasks of one to four
+    block rows. FP64: 1e-11. FP32: forward
     error within e_32 = 20 cond_2(A_ii) u_32 (cond from a dense SVD); with
     one refinement step within min(1e-5, e_32^2 + 20 cond u_64)."""
     A, part = _cd_problem(96, 2, seed=3)
