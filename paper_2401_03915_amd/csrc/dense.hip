@@ -1390,19 +1390,37 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
                                                        const int* __restrict__ order, LocalLayout lay,
                                                        const int* __restrict__ nb, const int* __restrict__ nq,
                                                        const int64_t* __restrict__ xoff, int64_t ldx,
-                                                       const T* __restrict__ fac, T* X) {
+                                                       const T* __restrict__ fac, T* X,
+                                                       const int4* __restrict__ tasks, const int* __restrict__ prof) {
   constexpr int LD = LdsLd<T>::v;
   constexpr int LDB = KfPitch<T>::v;
   __shared__ T As[TS * (LD > LDB ? LD : LDB)];  // A = U_jk: LT As[row * LDB + kk], else As[kk * LD + row]
   __shared__ T Bs[TS * LDB];                    // Bs[col * LDB + kk] = X_k(kk, col)
   const int64_t bid = blockIdx.x;
-  const int slot = find_slot(pref, nact, bid);
-  const int i = order[slot];
-  const int64_t t = bid - pref[slot];
-  const BsolveRange rg = bsolve_range(mode, s, s0, pw, nb[i]);
-  const int q = (int)(t % nq[i]);
-  const int j = rg.jlo + (int)(t / nq[i]);
+  int i, j, q;
+  BsolveRange rg;
+  if (tasks) {  // explicit list: subdomain x, row y, column block z, K tiles [w & 0xFFFFFF, + w >> 24)
+    const int4 tk = tasks[bid];
+    i = tk.x;
+    j = tk.y;
+    q = tk.z;
+    rg.klo = tk.w & 0xFFFFFF;
+    rg.khi = rg.klo + (tk.w >> 24);
+  } else {
+    const int slot = find_slot(pref, nact, bid);
+    i = order[slot];
+    const int64_t t = bid - pref[slot];
+    rg = bsolve_range(mode, s, s0, pw, nb[i]);
+    q = (int)(t % nq[i]);
+    j = rg.jlo + (int)(t / nq[i]);
+  }
   const int nt = lay.nt[i];
+  // with a profile g (LT: the rows of L, tile (k, j) is zero when g(k) > j;
+  // LU: the columns of U, tile (j, k) is zero when g(k) > j) zero tiles are skipped
+  const int* g = prof ? prof + lay.toff[i] : nullptr;
+  int k0 = rg.klo;
+  while (k0 < rg.khi && g && g[k0] > j) k0++;
+  if (k0 >= rg.khi) return;
   const int64_t M = ldx > 0 ? ldx : (int64_t)nt * TS;
   const T* base = fac + lay.foff[i];
   T* Xq = X + xoff[i] + (int64_t)q * TS * M;
@@ -1418,8 +1436,8 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
   constexpr int PER = TS2 / 256;
   T pa[PER], pb[PER];
   {
-    const T* U = base + (LT ? tile_index(0, nt, rg.klo, j) : tile_index(1, nt, j, rg.klo)) * TS2;
-    const T* Xk = Xq + (int64_t)rg.klo * TS;
+    const T* U = base + (LT ? tile_index(0, nt, k0, j) : tile_index(1, nt, j, k0)) * TS2;
+    const T* Xk = Xq + (int64_t)k0 * TS;
 #pragma unroll
     for (int u = 0; u < PER; u++) {
       const int e = tid + 256 * u;
@@ -1427,7 +1445,9 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
       pb[u] = Xk[(int64_t)(e / TS) * M + e % TS];
     }
   }
-  for (int k = rg.klo; k < rg.khi; k++) {
+  for (int k = k0; k < rg.khi;) {
+    int kn = k + 1;
+    while (kn < rg.khi && g && g[kn] > j) kn++;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; u++) {
@@ -1440,9 +1460,9 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
       Bs[b * LDB + a] = pb[u];
     }
     __syncthreads();
-    if (k + 1 < rg.khi) {
-      const T* U = base + (LT ? tile_index(0, nt, k + 1, j) : tile_index(1, nt, j, k + 1)) * TS2;
-      const T* Xk = Xq + (int64_t)(k + 1) * TS;
+    if (kn < rg.khi) {
+      const T* U = base + (LT ? tile_index(0, nt, kn, j) : tile_index(1, nt, j, kn)) * TS2;
+      const T* Xk = Xq + (int64_t)kn * TS;
 #pragma unroll
       for (int u = 0; u < PER; u++) {
         const int e = tid + 256 * u;
@@ -1461,6 +1481,7 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
       acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
       acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
     }
+    k = kn;
   }
   T* Xj = Xq + (int64_t)j * TS;
 #pragma unroll
@@ -2623,9 +2644,16 @@ void bsolve_interior_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int
   struct Launch {
     int kind, s, s0, nact;
     int64_t off, total;
+    bool listed;  // explicit task list (tiles inside the profiles)
   };
   std::vector<Launch> launches;
   std::vector<int64_t> pref;
+  std::vector<int4> tasks;
+  // profile of the blocks read: the rows of L (Cholesky, tile (k, j) is
+  // zero when f(k) > j) or the columns of U (LU, tile (j, k) zero when
+  // g(k) > j)
+  const bool use_prof = !c->h_prof.empty();
+  const int* gh = use_prof ? c->h_prof.data() + (c->kind == 1 ? c->sum_nt : 0) : nullptr;
   auto active = [&](int step) {
     int a = 0;
     while (a < (int)order.size() && nb[order[a]] > step) a++;
@@ -2633,6 +2661,23 @@ void bsolve_interior_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int
   };
   auto add_update = [&](int mode, int step, int s0) {
     const int act = active(mode == 0 ? step : s0);
+    if (use_prof) {
+      const int64_t off = (int64_t)tasks.size();
+      for (int a = 0; a < act; a++) {
+        const int i = order[a];
+        const int* g = gh + c->h_toff[i];
+        const BsolveRange rg = bsolve_range(mode, step, s0, PW, nb[i]);
+        for (int j = rg.jlo; j < rg.jhi; j++) {
+          bool any = false;
+          for (int k = rg.klo; k < rg.khi && !any; k++) any = g[k] <= j;
+          if (!any) continue;
+          for (int q = 0; q < nq[i]; q++) tasks.push_back(int4{i, j, q, rg.klo | ((rg.khi - rg.klo) << 24)});
+        }
+      }
+      const int64_t n = (int64_t)tasks.size() - off;
+      if (n > 0) launches.push_back(Launch{1 + mode, step, s0, act, off, n, true});
+      return;
+    }
     const int64_t off = (int64_t)pref.size();
     int64_t tot = 0;
     for (int a = 0; a < act; a++) {
@@ -2642,7 +2687,7 @@ void bsolve_interior_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int
       if (rg.jhi > rg.jlo) tot += (int64_t)(rg.jhi - rg.jlo) * nq[i];
     }
     pref.push_back(tot);
-    if (tot > 0) launches.push_back(Launch{1 + mode, step, s0, act, off, tot});
+    if (tot > 0) launches.push_back(Launch{1 + mode, step, s0, act, off, tot, false});
   };
   for (int s0 = 0; s0 < maxnb; s0 += PW) {
     for (int st = s0; st < std::min(s0 + PW, maxnb); st++) {
@@ -2654,18 +2699,21 @@ void bsolve_interior_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int
         tot += nq[order[a]];
       }
       pref.push_back(tot);
-      launches.push_back(Launch{0, st, s0, act, off, tot});
+      launches.push_back(Launch{0, st, s0, act, off, tot, false});
       add_update(0, st, s0);
     }
     add_update(1, 0, s0);
   }
   DBuf<int> d_order, d_nb, d_nq;
   DBuf<int64_t> d_pref, d_xoff;
+  DBuf<int4> d_tasks;
   d_order.upload(order, s);
   d_nb.upload(nb, s);
   d_nq.upload(nq, s);
   d_pref.upload(pref, s);
   d_xoff.upload(xoff, s);
+  d_tasks.upload(tasks, s);
+  const int* gd = use_prof ? c->prof.p + (c->kind == 1 ? c->sum_nt : 0) : nullptr;
   LocalLayout lay = c->layout();
   const T* fac = c->fp32 ? reinterpret_cast<const T*>(c->fac32.p) : reinterpret_cast<const T*>(c->fac64.p);
   const bool lt = c->kind == 0;
@@ -2677,7 +2725,8 @@ void bsolve_interior_impl(tls_ctx* c, const T* dinv, T* X, const std::vector<int
                          lay, d_nb.p, d_xoff.p, ldx, dinv, X);
     else
       hipLaunchKernelGGL(update, dim3((unsigned)L.total), dim3(256), 0, s, L.kind - 1, L.s, L.s0, PW,
-                         d_pref.p + L.off, L.nact, d_order.p, lay, d_nb.p, d_nq.p, d_xoff.p, ldx, fac, X);
+                         L.listed ? nullptr : d_pref.p + L.off, L.nact, d_order.p, lay, d_nb.p, d_nq.p, d_xoff.p,
+                         ldx, fac, X, L.listed ? d_tasks.p + L.off : nullptr, gd);
     TLS_LAUNCH_CHECK();
   }
   TLS_HIP(hipStreamSynchronize(s));
