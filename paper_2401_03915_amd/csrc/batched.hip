@@ -57,6 +57,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ desc,
   const int64_t t = bid - pref[di];
   const int tm = (g.M + 63) / 64;
   const int bm = (int)(t % tm) * 64, bn = (int)(t / tm) * 64;
+  if (g.syrk && bn > bm) return;  // above the block diagonal of a symmetric C
+  const int kbeg = g.kstart ? max(g.kstart[bm / 64], g.kstart[bn / 64]) / KC * KC : 0;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
@@ -99,8 +101,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ desc,
       rb[q] = w;
     }
   };
-  load(0);
-  for (int k0 = 0; k0 < g.K; k0 += KC) {
+  load(kbeg);
+  for (int k0 = kbeg; k0 < g.K; k0 += KC) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; q++) {

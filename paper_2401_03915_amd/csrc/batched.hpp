@@ -9,11 +9,18 @@ namespace tls {
 
 // C[m + n*ldc] = alpha * sum_k opA(m,k) opB(k,n) + beta * C[m + n*ldc]
 // opA(m,k) = transA ? A[k + m*lda] : A[m + k*lda] (same for B).
+// syrk = 1: only the output tiles on or below the block diagonal are formed
+// (C symmetric; the caller mirrors the rest). kstart (device, optional):
+// per 64-wide block b of the output's rows and columns, the first k with a
+// nonzero in that block's operand column (opA(m, k) = opB(k, m) = 0 for
+// k < kstart[m / 64]); a tile's K loop starts at the larger of its two.
 struct GemmDesc {
   int M, N, K;
   int lda, ldb;
   int64_t a_off, b_off, c_off;
   int64_t ldc;
+  int syrk = 0;
+  const int* kstart = nullptr;
 };
 
 template <class T>

@@ -17,6 +17,7 @@
 // Rayleigh-Ritz.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 
 #include "batched.hpp"
@@ -161,6 +162,46 @@ __global__ void __launch_bounds__(256) k_transpose_blocks(const int* __restrict_
         const double tv = t[x][y];  // in(c, r)
         b[r + (int64_t)c * n] = symmetrize ? 0.5 * (a[r + (int64_t)c * n] + tv) : tv;
       }
+    }
+  }
+}
+
+// out (FP64) = the symmetric nT x nT block whose tiles on and below the
+// block diagonal are in `in` (precision S, column-major, as a syrk GEMM
+// leaves them): those tiles are converted, the ones above are the
+// transposes of their mirror tiles (64 x 64 LDS staging, contiguous reads
+// and writes).
+template <class S>
+__global__ void __launch_bounds__(256) k_sym_from_lower(const int* __restrict__ nT_, const int64_t* __restrict__ off,
+                                                        const int* __restrict__ kreq, const S* __restrict__ in,
+                                                        double* out) {
+  const int i = blockIdx.y;
+  if (kreq[i] <= 0) return;
+  const int n = nT_[i];
+  const int nb = (n + TS - 1) / TS;
+  const S* a = in + off[i];
+  double* b = out + off[i];
+  __shared__ double t[TS][TS + 1];
+  for (int tile = blockIdx.x; tile < nb * nb; tile += gridDim.x) {
+    const int tr = tile % nb, tc = tile / nb;  // output tile: rows tr, columns tc
+    if (tr >= tc) {
+      for (int e = threadIdx.x; e < TS2; e += 256) {
+        const int r = tr * TS + e % TS, c = tc * TS + e / TS;
+        if (r < n && c < n) b[r + (int64_t)c * n] = (double)a[r + (int64_t)c * n];
+      }
+      continue;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS2; e += 256) {
+      const int x = e % TS, y = e / TS;
+      const int r = tc * TS + x, c = tr * TS + y;  // t[y][x] = in(tc 64 + x, tr 64 + y), a lower tile
+      t[y][x] = (r < n && c < n) ? (double)a[r + (int64_t)c * n] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS2; e += 256) {
+      const int x = e % TS, y = e / TS;
+      const int r = tr * TS + x, c = tc * TS + y;
+      if (r < n && c < n) b[r + (int64_t)c * n] = t[x][y];  // in(c, r)
     }
   }
 }
@@ -842,18 +883,41 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
     TG.release();
     GGt.release();
   }
-  // K = F^T F
+  // K = F^T F: only the tiles on and below the block diagonal (K is
+  // symmetric). Without G layers (delta = 1) F = -L_TI^T, and column t of F
+  // is zero above the tile profile of row t of L: each 64-column block of F
+  // starts at the first interior row its profile reaches, and the K loop of
+  // each tile of K starts at the later of its two blocks' starts.
+  DBuf<int> kst;
   {
+    std::vector<int> hk;
+    std::vector<int64_t> kofs(N, -1);
+    if (!c->h_prof.empty())
+      for (int i = 0; i < N; i++) {
+        if (d.kreq[i] <= 0 || d.nG[i] > 0) continue;
+        kofs[i] = (int64_t)hk.size();
+        const int t0 = d.nI[i];  // first T row in Omega_i (no G rows)
+        for (int b = 0; b * TS < d.nT[i]; b++) {
+          const int r0 = t0 + b * TS, r1 = std::min(t0 + d.nT[i], r0 + TS) - 1;
+          int f = INT32_MAX;
+          for (int tile = r0 / TS; tile <= r1 / TS; tile++) f = std::min(f, c->h_prof[c->h_toff[i] + tile]);
+          hk.push_back(std::min(f * TS, d.nI[i]));
+        }
+      }
+    kst.upload(hk, s);
     std::vector<GemmDesc> gd;
     for (int i = 0; i < N; i++)
-      if (d.kreq[i] > 0)
-        gd.push_back(GemmDesc{d.nT[i], d.nT[i], d.nI[i], d.nI[i], d.nI[i], d.oF[i], d.oF[i], d.oTT[i],
-                              (int64_t)d.nT[i]});
+      if (d.kreq[i] > 0) {
+        GemmDesc g{d.nT[i], d.nT[i], d.nI[i], d.nI[i], d.nI[i], d.oF[i], d.oF[i], d.oTT[i], (int64_t)d.nT[i]};
+        g.syrk = 1;
+        g.kstart = kofs[i] >= 0 ? kst.p + kofs[i] : nullptr;
+        gd.push_back(g);
+      }
     batched_gemm<T>(s, gd, true, false, F.p, F.p, K.p, T(1), T(0));
   }
   // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
   C64.alloc(std::max<int64_t>(d.oTT[N], 1));
-  hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)d.oTT[N], K.p, C64.p);
+  hipLaunchKernelGGL(k_sym_from_lower<T>, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, K.p, C64.p);
   TLS_LAUNCH_CHECK();
   K.release();
   C64b.alloc(std::max<int64_t>(d.oTT[N], 1));
