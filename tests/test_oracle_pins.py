@@ -678,3 +678,56 @@ def test_config1_iteration_counts():
     assert it2 < it1 < it_cg
     assert rr1 <= 1e-8 and rr2 <= 1e-8
     assert h2.n_coarse == 128
+
+
+def _unpivoted_lu(M):
+    """Doolittle LU without pivoting (unit lower L, upper U), textbook loops."""
+    n = M.shape[0]
+    U = M.astype(np.float64).copy()
+    L = np.eye(n)
+    for k in range(n - 1):
+        L[k + 1:, k] = U[k + 1:, k] / U[k, k]
+        U[k + 1:, k:] -= np.outer(L[k + 1:, k], U[k, k:])
+        U[k + 1:, k] = 0.0
+    return L, U
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_factor_fill_stays_inside_the_envelope(general):
+    """The GPU factorizations, substitutions and explicit inverses skip
+    the blocks left of each row's first nonzero of A_ii (and, for LU, above
+    each column's first nonzero of its upper part): they rely on Cholesky
+    and unpivoted LU creating no fill outside that envelope. Checked on the
+    oracle's local matrices (Section 2.3) of a high-contrast diffusion
+    problem and of an upwind convection-diffusion problem, whose local
+    matrices have a structurally nonsymmetric pattern: every entry outside
+    the envelope is exactly zero, and inside it the factors are not all
+    zero (the envelope is not trivially the whole triangle)."""
+    rng = np.random.default_rng(11)
+    if general:
+        A = one_way_convection_2d(40, rng)
+        part = box_partition_2d(40, 40, 2, 2)
+    else:
+        A = fv_diffusion_2d(high_contrast_kappa_2d(40, 40, rng))
+        part = box_partition_2d(40, 40, 2, 2)
+    G = schwarz.sym_pattern(A)
+    for i in range(4):
+        s = schwarz.overlap(A, part, i, 2, G)
+        M = schwarz.local_matrix(A, s).toarray()
+        n = M.shape[0]
+        nz = M != 0
+        row_first = np.array([np.flatnonzero(nz[a, :a + 1])[0] for a in range(n)])
+        col_first = np.array([np.flatnonzero(nz[:b + 1, b])[0] for b in range(n)])
+        if general:
+            L, U = _unpivoted_lu(M)
+        else:
+            L = np.linalg.cholesky(M)
+            U = L.T
+        a, b = np.indices((n, n))
+        outside_L = (b < row_first[:, None]) & (b <= a)
+        outside_U = (a < col_first[None, :]) & (a <= b)
+        assert outside_L.any() and outside_U.any()
+        assert np.all(L[outside_L] == 0.0)
+        assert np.all(U[outside_U] == 0.0)
+        # fill does occur inside the envelope
+        assert np.count_nonzero(L[~outside_L & (b <= a)]) > np.count_nonzero(np.tril(M))
