@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <type_traits>
 #include <cmath>
 
 #include "batched.hpp"
@@ -136,58 +137,59 @@ __global__ void k_convert(int64_t count, const S* __restrict__ in, D* out) {
 // out = in^T (symmetrize = 0) or out = (in + in^T) / 2 (symmetrize = 1) for
 // each subdomain's nT x nT column-major block; 64 x 64 tiles staged through
 // LDS so that both the reads and the writes are contiguous.
+template <class U>
 __global__ void __launch_bounds__(256) k_transpose_blocks(const int* __restrict__ nT_, const int64_t* __restrict__ off,
-                                                          const int* __restrict__ kreq, const double* in, double* out,
+                                                          const int* __restrict__ kreq, const U* in, U* out,
                                                           int symmetrize) {
   const int i = blockIdx.y;
   if (kreq[i] <= 0) return;
   const int n = nT_[i];
   const int nb = (n + TS - 1) / TS;
-  const double* a = in + off[i];
-  double* b = out + off[i];
-  __shared__ double t[TS][TS + 1];
+  const U* a = in + off[i];
+  U* b = out + off[i];
+  __shared__ U t[TS][TS + 1];
   for (int tile = blockIdx.x; tile < nb * nb; tile += gridDim.x) {
     const int tr = tile % nb, tc = tile / nb;  // output tile: rows tr, columns tc
     __syncthreads();
     for (int e = threadIdx.x; e < TS2; e += 256) {
       const int x = e % TS, y = e / TS;
       const int r = tc * TS + x, c = tr * TS + y;  // t[y][x] = in(tc 64 + x, tr 64 + y)
-      t[y][x] = (r < n && c < n) ? a[r + (int64_t)c * n] : 0.0;
+      t[y][x] = (r < n && c < n) ? a[r + (int64_t)c * n] : U(0);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < TS2; e += 256) {
       const int x = e % TS, y = e / TS;
       const int r = tr * TS + x, c = tc * TS + y;
       if (r < n && c < n) {
-        const double tv = t[x][y];  // in(c, r)
-        b[r + (int64_t)c * n] = symmetrize ? 0.5 * (a[r + (int64_t)c * n] + tv) : tv;
+        const U tv = t[x][y];  // in(c, r)
+        b[r + (int64_t)c * n] = symmetrize ? U(0.5) * (a[r + (int64_t)c * n] + tv) : tv;
       }
     }
   }
 }
 
-// out (FP64) = the symmetric nT x nT block whose tiles on and below the
+// out (precision D) = the symmetric nT x nT block whose tiles on and below the
 // block diagonal are in `in` (precision S, column-major, as a syrk GEMM
 // leaves them): those tiles are converted, the ones above are the
 // transposes of their mirror tiles (64 x 64 LDS staging, contiguous reads
 // and writes).
-template <class S>
+template <class S, class D>
 __global__ void __launch_bounds__(256) k_sym_from_lower(const int* __restrict__ nT_, const int64_t* __restrict__ off,
                                                         const int* __restrict__ kreq, const S* __restrict__ in,
-                                                        double* out) {
+                                                        D* out) {
   const int i = blockIdx.y;
   if (kreq[i] <= 0) return;
   const int n = nT_[i];
   const int nb = (n + TS - 1) / TS;
   const S* a = in + off[i];
-  double* b = out + off[i];
-  __shared__ double t[TS][TS + 1];
+  D* b = out + off[i];
+  __shared__ D t[TS][TS + 1];
   for (int tile = blockIdx.x; tile < nb * nb; tile += gridDim.x) {
     const int tr = tile % nb, tc = tile / nb;  // output tile: rows tr, columns tc
     if (tr >= tc) {
       for (int e = threadIdx.x; e < TS2; e += 256) {
         const int r = tr * TS + e % TS, c = tc * TS + e / TS;
-        if (r < n && c < n) b[r + (int64_t)c * n] = (double)a[r + (int64_t)c * n];
+        if (r < n && c < n) b[r + (int64_t)c * n] = (D)a[r + (int64_t)c * n];
       }
       continue;
     }
@@ -195,7 +197,7 @@ __global__ void __launch_bounds__(256) k_sym_from_lower(const int* __restrict__ 
     for (int e = threadIdx.x; e < TS2; e += 256) {
       const int x = e % TS, y = e / TS;
       const int r = tc * TS + x, c = tr * TS + y;  // t[y][x] = in(tc 64 + x, tr 64 + y), a lower tile
-      t[y][x] = (r < n && c < n) ? (double)a[r + (int64_t)c * n] : 0.0;
+      t[y][x] = (r < n && c < n) ? (D)a[r + (int64_t)c * n] : D(0);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < TS2; e += 256) {
@@ -856,9 +858,7 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
   // the nT x nT blocks dominate the memory of a pass
   K.alloc(std::max<int64_t>(d.oTT[N], 1));
   F.alloc(std::max<int64_t>(d.oF[N], 1));
-  LTT.alloc(std::max<int64_t>(d.oTT[N], 1));
   hipLaunchKernelGGL(k_extract_f<T>, eg, dim3(256), 0, s, el, fac, F.p);
-  hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
   TLS_LAUNCH_CHECK();
   if (d.oGG[N] > 0) {
     GI.alloc(d.oGI[N]);
@@ -915,21 +915,50 @@ static PassEig spd_pass(tls_ctx* c, const T* fac, const PassDims& d, double thre
       }
     batched_gemm<T>(s, gd, true, false, F.p, F.p, K.p, T(1), T(0));
   }
-  // C = L_TT^{-1} K L_TT^{-T} (fp64): X = L^{-1} K; C = L^{-1} X^T
-  C64.alloc(std::max<int64_t>(d.oTT[N], 1));
-  hipLaunchKernelGGL(k_sym_from_lower<T>, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, K.p, C64.p);
-  TLS_LAUNCH_CHECK();
-  K.release();
-  C64b.alloc(std::max<int64_t>(d.oTT[N], 1));
+  // C = L_TT^{-1} K L_TT^{-T}: X = L^{-1} K; C = L^{-1} X^T, in the local
+  // precision (FP32 in mixed mode, where the factor itself is FP32); the
+  // subspace iteration takes C in FP64
   std::vector<TriDesc> td;
   for (int i = 0; i < N; i++)
     if (d.kreq[i] > 0) td.push_back(TriDesc{d.nT[i], d.nT[i], d.oTT[i], d.oTT[i], (int64_t)d.nT[i]});
-  batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64.p, c->errflag.p);
-  hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, C64.p, C64b.p, 0);
-  TLS_LAUNCH_CHECK();
-  batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64b.p, c->errflag.p);
-  hipLaunchKernelGGL(k_transpose_blocks, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, C64b.p, C64.p, 1);
-  TLS_LAUNCH_CHECK();
+  C64.alloc(std::max<int64_t>(d.oTT[N], 1));
+  if (std::is_same<T, float>::value) {
+    DBuf<T> Cc, Ccb;
+    Cc.alloc(std::max<int64_t>(d.oTT[N], 1));
+    hipLaunchKernelGGL((k_sym_from_lower<T, T>), eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, K.p, Cc.p);
+    TLS_LAUNCH_CHECK();
+    K.release();
+    DBuf<T> LTTc;
+    LTTc.alloc(std::max<int64_t>(d.oTT[N], 1));
+    hipLaunchKernelGGL((k_extract<T, T>), eg, dim3(256), 0, s, 4, el, fac, LTTc.p);
+    TLS_LAUNCH_CHECK();
+    Ccb.alloc(std::max<int64_t>(d.oTT[N], 1));
+    batched_trsm<T>(s, td, LOWER_FWD, LTTc.p, Cc.p, c->errflag.p);
+    hipLaunchKernelGGL(k_transpose_blocks<T>, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, Cc.p, Ccb.p, 0);
+    TLS_LAUNCH_CHECK();
+    batched_trsm<T>(s, td, LOWER_FWD, LTTc.p, Ccb.p, c->errflag.p);
+    hipLaunchKernelGGL(k_transpose_blocks<T>, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, Ccb.p, Cc.p, 1);
+    TLS_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, (int64_t)d.oTT[N], Cc.p, C64.p);
+    TLS_LAUNCH_CHECK();
+    TLS_HIP(hipStreamSynchronize(s));  // Cc, Ccb, LTTc are freed on return from this block
+  } else {
+    hipLaunchKernelGGL((k_sym_from_lower<T, double>), eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, K.p, C64.p);
+    TLS_LAUNCH_CHECK();
+    K.release();
+    LTT.alloc(std::max<int64_t>(d.oTT[N], 1));
+    hipLaunchKernelGGL((k_extract<T, double>), eg, dim3(256), 0, s, 4, el, fac, LTT.p);
+    TLS_LAUNCH_CHECK();
+    C64b.alloc(std::max<int64_t>(d.oTT[N], 1));
+    batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64.p, c->errflag.p);
+    hipLaunchKernelGGL(k_transpose_blocks<double>, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, C64.p, C64b.p,
+                       0);
+    TLS_LAUNCH_CHECK();
+    batched_trsm<double>(s, td, LOWER_FWD, LTT.p, C64b.p, c->errflag.p);
+    hipLaunchKernelGGL(k_transpose_blocks<double>, eg, dim3(256), 0, s, dv.nT.p, dv.oTT.p, dv.kreq.p, C64b.p, C64.p,
+                       1);
+    TLS_LAUNCH_CHECK();
+  }
   if (download(c->errflag.p, 1, s)[0] & ERR_PIVOT) fail(TLS_E_NOT_SPD, "zero pivot in a Schur-complement block");
   LTT.release();
   C64b.release();
