@@ -261,7 +261,8 @@ struct SolvePlan {
   int ntasks = 0;
   DBuf<int> flags;
   int order = 0;
-  int rows = 1;  // block rows per task (1: k_trsv, 2: k_trsv_sr)
+  int rows = 1;   // block rows per task (1: k_trsv, more: k_trsv_sr)
+  int early = 0;  // tasks handed out ahead of their dependencies (the grid exceeds this)
 };
 
 // Error bits reported by kernels into a device int.

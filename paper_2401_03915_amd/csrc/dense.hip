@@ -2424,7 +2424,8 @@ void trsv(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch,
           const T* fac, const T* dinv, T* x, int* err, const int* done, int grid, const int* prof = nullptr) {
   const int ntasks = p.ntasks;
   if (ntasks == 0) return;
-  grid = std::max(1, std::min(grid, ntasks));
+  // more workgroups than tasks handed out ahead of their dependencies
+  grid = std::max(p.early + 1, std::min(grid, ntasks));
   if (p.rows > 1) {
     trsv_rows<T>(s, mode, p, grid, counter, epoch, lay, fac, dinv, x, err, done, prof);
     return;
@@ -2546,7 +2547,7 @@ void factor_local(tls_ctx* c) {
 }
 
 void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::vector<int64_t>& toff, int order,
-                hipStream_t s, int S) {
+                hipStream_t s, int S, const std::vector<int>* width) {
   // A task is S consecutive block rows (the last task of a subdomain may
   // hold fewer); task q of subdomain i covers rows qS .. (forward) or
   // nt_i - 1 - qS down (backward) and has "position" q in its dependency
@@ -2560,18 +2561,52 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
   //         key = position / nt_i * (1 - lead * nt_i / max nt), lead 0.3 / 0.6,
   //         so that the long rows of the largest chains are handed out
   //         before the end and stream most of their tiles early
+  // With the tiles each row reads (width, at toff_i + r), the widest tasks
+  // (at most EARLY of them, each reading at least 64 tiles) are handed out
+  // ahead of their place, by one position per LEAD_TILES tiles, so that they
+  // stream their blocks while the chain catches up instead of after it.
+  // Such a task may wait on tasks handed out after it; with fewer early
+  // tasks than resident workgroups some workgroup is always free to take
+  // those, so every wait still ends.
+  constexpr int EARLY = 64, LEAD_TILES = 24;
   const int N = (int)nt.size();
   std::vector<int> nq(N);
   for (int i = 0; i < N; i++) nq[i] = (nt[i] + S - 1) / S;
   int maxnt = 0;
   for (int v : nq) maxnt = std::max(maxnt, v);
+  std::vector<std::vector<int>> lead(N);
+  if (width) {
+    struct Wide {
+      int64_t w;
+      int i, pos;
+    };
+    std::vector<Wide> wide;
+    for (int i = 0; i < N; i++) {
+      lead[i].assign(nq[i], 0);
+      for (int pos = 0; pos < nq[i]; pos++) {
+        int64_t w = 0;
+        for (int q = 0; q < S && pos * S + q < nt[i]; q++) {
+          const int r = bwd ? nt[i] - 1 - (pos * S + q) : pos * S + q;
+          w += (*width)[toff[i] + r];
+        }
+        if (w >= 64) wide.push_back(Wide{w, i, pos});
+      }
+    }
+    std::stable_sort(wide.begin(), wide.end(), [](const Wide& a, const Wide& b) { return a.w > b.w; });
+    for (size_t k = 0; k < wide.size() && k < (size_t)EARLY; k++)
+      lead[wide[k].i][wide[k].pos] = (int)std::min<int64_t>(wide[k].pos, wide[k].w / LEAD_TILES);
+  }
+  p.early = 0;
+  for (const auto& l : lead)
+    for (int v : l) p.early += v > 0;
   struct Item {
     double key;
     int i, pos;
   };
   std::vector<Item> items;
   for (int i = 0; i < N; i++)
-    for (int pos = 0; pos < nq[i]; pos++) {
+    for (int pos0 = 0; pos0 < nq[i]; pos0++) {
+      const int pos = width ? pos0 - lead[i][pos0] : pos0;  // position the key is computed from
       double key;
       if (order == 2)
         key = (pos + 0.5) / nq[i];
@@ -2581,7 +2616,7 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
         key = (pos + 0.5) / nq[i] * (1.0 - (order == 4 ? 0.3 : 0.6) * nq[i] / std::max(maxnt, 1));
       else
         key = (double)pos;
-      items.push_back(Item{key, i, pos});
+      items.push_back(Item{key, i, pos0});
     }
   std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
     if (a.key != b.key) return a.key < b.key;
@@ -2606,8 +2641,25 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
 }
 
 void build_local_plans(tls_ctx* c, int order, int rows) {
-  build_plan(c->plan_fwd, false, c->h_nt, c->h_toff, order, c->stream, rows);
-  build_plan(c->plan_bwd, true, c->h_nt, c->h_toff, order, c->stream, rows);
+  // tiles each row reads inside the profiles: forward r - f(r), backward
+  // the rows c > r whose profile g reaches r (g = f for Cholesky, the
+  // column profile of U for LU)
+  std::vector<int> wf, wb;
+  if (!c->h_prof.empty()) {
+    wf.assign(c->sum_nt, 0);
+    wb.assign(c->sum_nt, 0);
+    const int* g = c->h_prof.data() + (c->kind == 1 ? c->sum_nt : 0);
+    for (int i = 0; i < c->N; i++) {
+      const int64_t t0 = c->h_toff[i];
+      const int nt = c->h_nt[i];
+      for (int r = 0; r < nt; r++) {
+        wf[t0 + r] = r - c->h_prof[t0 + r];
+        for (int cc = r + 1; cc < nt; cc++) wb[t0 + r] += g[t0 + cc] <= r;
+      }
+    }
+  }
+  build_plan(c->plan_fwd, false, c->h_nt, c->h_toff, order, c->stream, rows, wf.empty() ? nullptr : &wf);
+  build_plan(c->plan_bwd, true, c->h_nt, c->h_toff, order, c->stream, rows, wb.empty() ? nullptr : &wb);
   c->solve_order = order;
   c->solve_rows = rows;
 }

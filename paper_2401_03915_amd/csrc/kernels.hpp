@@ -56,7 +56,7 @@ void factor_tiles_f64(hipStream_t s, int N, const std::vector<int>& nt, const Lo
 // dependency-safe task orderings (1 level, 2 normalized progress,
 // 3 longest chain first)
 void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::vector<int64_t>& toff, int order,
-                hipStream_t s, int rows = 1);
+                hipStream_t s, int rows = 1, const std::vector<int>* width = nullptr);
 // mode: 0 L y = b (Cholesky), 1 L^T x = y, 2 unit-lower L y = b (LU), 3 U x = y
 void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
               const double* fac, const double* dinv, double* x, int* err, const int* done, int grid);
