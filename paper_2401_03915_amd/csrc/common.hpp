@@ -241,7 +241,47 @@ struct LocalLayout {
   const int64_t* foff; // element offset of the factor of i
   const int64_t* voff; // offset of i's padded vector (M_i entries)
   const int64_t* toff; // offset of i's first tile row in the flag arrays (= sum nt_j)
+  // Profile storage (null: every tile of the packed lower triangle, or of
+  // the full square for LU, is stored). With it, tile row r keeps only its
+  // tiles from column prof[toff_i + r] to the diagonal, tile (r, c) at tile
+  // trow[toff_i + r] + c of the subdomain's storage; for LU the tiles
+  // strictly above the diagonal are kept by columns, column c from row
+  // profc[toff_i + c], tile (r, c) at tile tcol[toff_i + c] + r.
+  const int64_t* trow = nullptr;
+  const int64_t* tcol = nullptr;
+  const int* prof = nullptr;
+  const int* profc = nullptr;
 };
+
+// Element offset of tile (r, c) inside subdomain i's factor storage (the
+// tile must be stored: inside the profiles, or any tile without them).
+__device__ inline int64_t tile_off(const LocalLayout& lay, int i, int kind, int nt, int r, int c) {
+  if (!lay.trow) return tile_index(kind, nt, r, c) * TS2;
+  const int64_t t0 = lay.toff[i];
+  if (kind == 0 || r >= c) return (lay.trow[t0 + r] + c) * TS2;
+  return (lay.tcol[t0 + c] + r) * TS2;
+}
+// Tile index of (r, c) = row_tile0(r) + c on and below the diagonal (any
+// storage); above it, for LU, (r, c) = ucol_tile0(c) + r * ucol_stride.
+__device__ inline int64_t row_tile0(const LocalLayout& lay, int i, int kind, int nt, int r) {
+  return lay.trow ? lay.trow[lay.toff[i] + r] : tile_index(kind, nt, r, 0);
+}
+__device__ inline int64_t ucol_tile0(const LocalLayout& lay, int i, int c) {
+  return lay.tcol ? lay.tcol[lay.toff[i] + c] : (int64_t)c;
+}
+__device__ inline int64_t ucol_stride(const LocalLayout& lay, int nt) { return lay.tcol ? 1 : nt; }
+// Is tile (r, c) stored (always, without profile storage)?
+__device__ inline bool tile_in(const LocalLayout& lay, int i, int kind, int r, int c) {
+  if (!lay.trow) return true;
+  const int64_t t0 = lay.toff[i];
+  if (kind == 0 || r >= c) return c >= lay.prof[t0 + r];
+  return r >= lay.profc[t0 + c];
+}
+// element (a, b) of subdomain i's padded local matrix (its tile must be stored)
+template <class T>
+__device__ inline T* elem_ptr_l(T* base, const LocalLayout& lay, int i, int kind, int nt, int a, int b) {
+  return base + tile_off(lay, i, kind, nt, a / TS, b / TS) + (b % TS) * TS + (a % TS);
+}
 
 // Work list of the symmetric product with explicit inverses (block and row
 // descriptors in 16-byte words) and its row and column partial sums.

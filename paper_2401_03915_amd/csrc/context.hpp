@@ -48,6 +48,12 @@ struct tls_ctx {
   // so the factorization, the inverse and the substitutions skip those tiles.
   tls::DBuf<int> prof;
   std::vector<int> h_prof;
+  // profile storage of the local factors: only the tiles inside the
+  // profiles are stored (offsets trow / tcol, see LocalLayout); h_soff keeps
+  // the offsets of the full packed storage, which the explicit inverses use
+  bool prof_store = false;
+  std::vector<int64_t> h_trow, h_tcol, h_soff;
+  tls::DBuf<int64_t> d_trow, d_tcol;
   double flops_factor = 0, flops_inverse = 0;  // their arithmetic with the profile (2 per multiply-add)
   // inverses of the diagonal tiles (one per tile row, at (toff_i + r) * 64^2)
   tls::DBuf<double> dinv64;
@@ -152,7 +158,14 @@ struct tls_ctx {
   double last_relres = 0;
 
   tls::LocalLayout layout() const {
-    return tls::LocalLayout{d_m, d_nI, d_nP, d_nt, d_foff, d_voff, d_toff};
+    tls::LocalLayout l{d_m, d_nI, d_nP, d_nt, d_foff, d_voff, d_toff};
+    if (prof_store) {
+      l.trow = d_trow.p;
+      l.tcol = kind == 1 ? d_tcol.p : nullptr;
+      l.prof = prof.p;
+      l.profc = kind == 1 ? prof.p + sum_nt : nullptr;
+    }
+    return l;
   }
   tls::LocalLayout layout0() const {
     return tls::LocalLayout{one_m, one_nI, one_nP, one_nt, one_foff, one_voff, one_toff};

@@ -35,7 +35,7 @@ __global__ void k_pad_identity(int N, LocalLayout lay, int kind, T* fac) {
   int i = blockIdx.x;
   int m = lay.m[i], nt = lay.nt[i];
   T* base = fac + lay.foff[i];
-  for (int a = m + threadIdx.x; a < nt * TS; a += blockDim.x) *elem_ptr(base, kind, nt, a, a) = T(1);
+  for (int a = m + threadIdx.x; a < nt * TS; a += blockDim.x) *elem_ptr_l(base, lay, i, kind, nt, a, a) = T(1);
 }
 
 // scale[voff_i + a] = 1 / sqrt(A[g][g]) for the Jacobi-scaled variant
@@ -79,23 +79,24 @@ __global__ void k_gather(int total, const int* __restrict__ sub_idx, const int* 
   int a = p - sub_ptr[i];
   int g = sub_idx[p];
   int nt = lay.nt[i];
-  T* base = fac + lay.foff[i];
   const int* lp = layer_ptr + (size_t)i * stride;
-  double sa = scale ? scale[lay.voff[i] + a] : 1.0;
+  double sa = scale && fac ? scale[lay.voff[i] + a] : 1.0;
   for (int j = rp[g]; j < rp[g + 1]; j++) {
     // position of column c in Omega_i (every layer is ascending), or -1
     int q = find_local_pos(ci[j], sub_idx, lp, stride - 1);
     if (q < 0) continue;
     int b = q - sub_ptr[i];
     if (kind == 0 && b > a) continue;  // Cholesky stores the lower triangle
-    if (prof) {
-      // tile profiles: rows of the lower part, and (LU) columns of the upper part
+    if (!fac) {
+      // first pass, the tile profiles: rows of the lower part, and (LU)
+      // columns of the upper part
       if (b <= a) atomicMin(&prof[lay.toff[i] + a / TS], b / TS);
       if (colp && a <= b) atomicMin(&prof[colp + lay.toff[i] + b / TS], a / TS);
+      continue;
     }
     double v = val[j];
     if (scale) v *= sa * scale[lay.voff[i] + b];
-    *elem_ptr(base, kind, nt, a, b) = (T)v;
+    *elem_ptr_l(fac + lay.foff[i], lay, i, kind, nt, a, b) = (T)v;
   }
 }
 
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(64) k_potrf(int k, const int* __restrict__ ord
   __shared__ double Ls[TS * L1];
   const int i = order[blockIdx.x];
   const int nt = lay.nt[i];
-  T* tile = fac + lay.foff[i] + tile_index(0, nt, k, k) * TS2;
+  T* tile = fac + lay.foff[i] + tile_off(lay, i, 0, nt, k, k);
   const int a = threadIdx.x;
   T row[TS];
 #pragma unroll
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(256) k_trsm(int k, const int64_t* __restrict__
     r = k + 1 + (int)(bid - pref[j]);
   }
   const int nt = lay.nt[i];
-  T* A = fac + lay.foff[i] + tile_index(0, nt, r, k) * TS2;
+  T* A = fac + lay.foff[i] + tile_off(lay, i, 0, nt, r, k);
   const T* Li = dinv + (lay.toff[i] + k) * TS2;
   const int tid = threadIdx.x;
   for (int e = tid; e < TS2; e += 256) {
@@ -316,7 +317,7 @@ __global__ void __launch_bounds__(256) k_update_blk(int mode, int kb, int kn, in
   }
   const int nt = lay.nt[i];
   T* base = fac + lay.foff[i];
-  T* C = base + tile_index(0, nt, r, c) * TS2;
+  T* C = base + tile_off(lay, i, 0, nt, r, c);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
@@ -330,8 +331,8 @@ __global__ void __launch_bounds__(256) k_update_blk(int mode, int kb, int kn, in
   constexpr int PER = TS2 / 256;
   T pa[PER], pb[PER];
   {
-    const T* Lr = base + tile_index(0, nt, r, kb) * TS2;
-    const T* Lc = base + tile_index(0, nt, c, kb) * TS2;
+    const T* Lr = base + tile_off(lay, i, 0, nt, r, kb);
+    const T* Lc = base + tile_off(lay, i, 0, nt, c, kb);
 #pragma unroll
     for (int u = 0; u < PER; u++) {
       pa[u] = Lr[tid + 256 * u];
@@ -349,8 +350,8 @@ __global__ void __launch_bounds__(256) k_update_blk(int mode, int kb, int kn, in
     }
     __syncthreads();
     if (k + 1 < kn) {
-      const T* Lr = base + tile_index(0, nt, r, kb + k + 1) * TS2;
-      const T* Lc = base + tile_index(0, nt, c, kb + k + 1) * TS2;
+      const T* Lr = base + tile_off(lay, i, 0, nt, r, kb + k + 1);
+      const T* Lc = base + tile_off(lay, i, 0, nt, c, kb + k + 1);
 #pragma unroll
       for (int u = 0; u < PER; u++) {
         pa[u] = Lr[tid + 256 * u];
@@ -400,7 +401,7 @@ __global__ void __launch_bounds__(64) k_getrf(int k, const int* __restrict__ ord
   __shared__ double Xs[TS * L1];
   const int i = order[blockIdx.x];
   const int nt = lay.nt[i];
-  T* tile = fac + lay.foff[i] + tile_index(1, nt, k, k) * TS2;
+  T* tile = fac + lay.foff[i] + tile_off(lay, i, 1, nt, k, k);
   const int a = threadIdx.x;
   T row[TS];
 #pragma unroll
@@ -481,7 +482,7 @@ __global__ void __launch_bounds__(256) k_trsm_lu(int k, const int64_t* __restric
   const int nt = lay.nt[i];
   T* base = fac + lay.foff[i];
   const T* Di = dinv + (lay.toff[i] + k) * TS2;
-  T* X = base + (colpanel ? tile_index(1, nt, o, k) : tile_index(1, nt, k, o)) * TS2;
+  T* X = base + (colpanel ? tile_off(lay, i, 1, nt, o, k) : tile_off(lay, i, 1, nt, k, o));
   const int tid = threadIdx.x;
   for (int e = tid; e < TS2; e += 256) {
     const int a = e % TS, b = e / TS;  // element (a, b) of a column-major tile
@@ -580,7 +581,7 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
   }
   const int nt = lay.nt[i];
   T* base = fac + lay.foff[i];
-  T* C = base + tile_index(1, nt, r, c) * TS2;
+  T* C = base + tile_off(lay, i, 1, nt, r, c);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
@@ -594,8 +595,8 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
   constexpr int PER = TS2 / 256;
   T pa[PER], pb[PER];
   {
-    const T* Lr = base + tile_index(1, nt, r, kb) * TS2;
-    const T* Uc = base + tile_index(1, nt, kb, c) * TS2;
+    const T* Lr = base + tile_off(lay, i, 1, nt, r, kb);
+    const T* Uc = base + tile_off(lay, i, 1, nt, kb, c);
 #pragma unroll
     for (int u = 0; u < PER; u++) {
       pa[u] = Lr[tid + 256 * u];
@@ -613,8 +614,8 @@ __global__ void __launch_bounds__(256) k_update_lu(int mode, int kb, int kn, int
     }
     __syncthreads();
     if (k + 1 < kn) {
-      const T* Lr = base + tile_index(1, nt, r, kb + k + 1) * TS2;
-      const T* Uc = base + tile_index(1, nt, kb + k + 1, c) * TS2;
+      const T* Lr = base + tile_off(lay, i, 1, nt, r, kb + k + 1);
+      const T* Uc = base + tile_off(lay, i, 1, nt, kb + k + 1, c);
 #pragma unroll
       for (int u = 0; u < PER; u++) {
         pa[u] = Lr[tid + 256 * u];
@@ -1032,8 +1033,9 @@ constexpr long long SPIN_LIMIT = 1ll << 26;
 // round, one per lane, so a task whose dependencies are long solved (or
 // skipped) passes them in a few rounds instead of one memory round trip per
 // row. Waits, within SPIN_LIMIT polls, until at least one row is
-// available.
-template <bool BWD>
+// available. CAP: at most 64 rows are passed (one round), so the caller can
+// keep what the lanes read about those rows in a 64-entry table.
+template <bool BWD, bool CAP = false>
 __device__ inline int wait_rows(int c, int stop, const int* fl, int epoch, const int* __restrict__ g, int need_row,
                                 int* err) {
   const int lane = threadIdx.x & 63;
@@ -1049,7 +1051,7 @@ __device__ inline int wait_rows(int c, int stop, const int* fl, int epoch, const
       const uint64_t m = __ballot(ok);
       const int run = ~m == 0ull ? 64 : __builtin_ctzll(~m);
       lim += step * run;
-      if (run < 64) break;
+      if (CAP || run < 64) break;
     }
     if (lim != c) break;
     if (++spins > SPIN_LIMIT) {
@@ -1087,6 +1089,8 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
   __shared__ T s_red[16 * TS];
   __shared__ T s_rhs[TS];
   __shared__ int s_task, s_lim;
+  __shared__ int s_g[BWD ? 64 : 1];
+  __shared__ int64_t s_cb[BWD ? 64 : 1];
   const int tid = threadIdx.x;
   const int rg = tid & 15, cg = tid >> 4;
   const int epoch = *epoch_ptr;
@@ -1127,21 +1131,45 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
     // is the column profile of U (the tile (r, c))
     const int* fp = prof ? prof + lay.toff[i] : nullptr;
     int c = BWD ? nt - 1 : (fp ? fp[r] : 0);
+    // block this row takes from block row cc: forward (r, cc) = row base + cc;
+    // backward (cc, r) of L (Cholesky) or (r, cc) of U (LU, by columns)
+    // (the subdomain's row and column bases, read without re-reading toff)
+    const int64_t* trw = lay.trow ? lay.trow + lay.toff[i] : nullptr;
+    const int64_t* tcl = lay.tcol ? lay.tcol + lay.toff[i] : nullptr;
+    auto rowb = [&](int q) -> int64_t { return trw ? trw[q] : tile_index(KIND, nt, q, 0); };
+    const int64_t rb0 = BWD ? 0 : rowb(r);
+    auto tile_at = [&](int cc) -> const T* {
+      int64_t t;
+      if (!BWD)
+        t = rb0 + cc;
+      else if (TRANS)
+        t = rowb(cc) + r;
+      else
+        t = tcl ? tcl[cc] + r : (int64_t)r * nt + cc;
+      return base + t * TS2;
+    };
     const int step = BWD ? -1 : 1;
     // the block next to the diagonal is almost always the last dependency:
     // load it, and this row's right-hand side, while the task waits
     const int c_last = BWD ? r + 1 : r - 1;
     const bool has_last = BWD ? (r + 1 < nt) : (r > 0);
     V4 vlast[4];
-    if (has_last) {
-      const T* tile = base + (TRANS ? tile_index(KIND, nt, c_last, r) : tile_index(KIND, nt, r, c_last)) * TS2;
+    // (only if that block is stored: inside the profile, when there is one)
+    if (has_last && (!fp || (BWD ? fp[c_last] <= r : fp[r] <= c_last))) {
+      const T* tile = tile_at(c_last);
 #pragma unroll
       for (int j = 0; j < 4; j++) vlast[j] = stream_load(reinterpret_cast<const V4*>(tile + (cg + 16 * j) * TS + 4 * rg));
     }
     const T brow = tid < 64 ? xi[r * TS + tid] : T(0);
     while (BWD ? (c > r) : (c < r)) {
       if (tid < 64) {
-        const int lim = wait_rows<BWD>(c, r, fl, epoch, BWD ? fp : nullptr, r, err);
+        const int lim = wait_rows<BWD, BWD>(c, r, fl, epoch, BWD ? fp : nullptr, r, err);
+        if (BWD && tid < c - lim) {
+          // each column's profile entry and block base, for all threads
+          const int cc = c - tid;
+          s_g[tid] = fp ? fp[cc] : 0;
+          s_cb[tid] = TRANS ? rowb(cc) + r : (tcl ? tcl[cc] + r : (int64_t)r * nt + cc);
+        }
         if (tid == 0) s_lim = lim;
       }
       __syncthreads();
@@ -1155,8 +1183,7 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
 #pragma unroll
         for (int u = 0; u < U; u++) {
           const int cc = c + step * (done_tiles + u);
-          const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
-          if (BWD && fp && fp[cc] > r) {
+          if (BWD && s_g[done_tiles + u] > r) {
 #pragma unroll
             for (int j = 0; j < 4; j++) {
               v[u][j] = V4{T(0), T(0), T(0), T(0)};
@@ -1164,6 +1191,7 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
             }
             continue;
           }
+          const T* tile = BWD ? base + s_cb[done_tiles + u] * TS2 : tile_at(cc);
           if (cc == c_last) {
 #pragma unroll
             for (int j = 0; j < 4; j++) v[u][j] = vlast[j];
@@ -1200,8 +1228,8 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
       }
       for (; done_tiles < cnt; done_tiles++) {
         const int cc = c + step * done_tiles;
-        if (BWD && fp && fp[cc] > r) continue;
-        const T* tile = base + (TRANS ? tile_index(KIND, nt, cc, r) : tile_index(KIND, nt, r, cc)) * TS2;
+        if (BWD && s_g[done_tiles] > r) continue;
+        const T* tile = BWD ? base + s_cb[done_tiles] * TS2 : tile_at(cc);
         const T* xc = xi + cc * TS;
         const bool pre = cc == c_last;
         if (!TRANS) {
@@ -1436,7 +1464,7 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
   constexpr int PER = TS2 / 256;
   T pa[PER], pb[PER];
   {
-    const T* U = base + (LT ? tile_index(0, nt, k0, j) : tile_index(1, nt, j, k0)) * TS2;
+    const T* U = base + (LT ? tile_off(lay, i, 0, nt, k0, j) : tile_off(lay, i, 1, nt, j, k0));
     const T* Xk = Xq + (int64_t)k0 * TS;
 #pragma unroll
     for (int u = 0; u < PER; u++) {
@@ -1461,7 +1489,7 @@ __global__ void __launch_bounds__(256) k_bsolve_update(int mode, int s, int s0, 
     }
     __syncthreads();
     if (kn < rg.khi) {
-      const T* U = base + (LT ? tile_index(0, nt, kn, j) : tile_index(1, nt, j, kn)) * TS2;
+      const T* U = base + (LT ? tile_off(lay, i, 0, nt, kn, j) : tile_off(lay, i, 1, nt, j, kn));
       const T* Xk = Xq + (int64_t)kn * TS;
 #pragma unroll
       for (int u = 0; u < PER; u++) {
@@ -1555,7 +1583,7 @@ __global__ void __launch_bounds__(256) k_tinv_row(int j, int j0, const int64_t* 
   // L_jl = 0 left of the profile of row j
   const int l0 = max(max(k, j0), prof ? prof[lay.toff[i] + j] : 0);
   for (int l = l0; l < j; l++) {
-    const T* Ljl = Lb + tile_index(0, nt, j, l) * TS2;
+    const T* Ljl = Lb + tile_off(lay, i, 0, nt, j, l);
     const T* Wlk = Wb + tile_index(0, nt, l, k) * TS2;
     __syncthreads();
     for (int e = tid; e < TS2; e += 256) {
@@ -1647,7 +1675,7 @@ __global__ void __launch_bounds__(256) k_tinv_update(int j0, int j1, const int64
   constexpr int PER = TS2 / 256;
   T pa[PER], pb[PER];
   {
-    const T* Lrl = Lb + tile_index(0, nt, r, l0) * TS2;
+    const T* Lrl = Lb + tile_off(lay, i, 0, nt, r, l0);
     const T* Wlk = Wb + tile_index(0, nt, l0, k) * TS2;
 #pragma unroll
     for (int u = 0; u < PER; u++) {
@@ -1665,7 +1693,7 @@ __global__ void __launch_bounds__(256) k_tinv_update(int j0, int j1, const int64
     }
     __syncthreads();
     if (l + 1 < j1) {
-      const T* Lrl = Lb + tile_index(0, nt, r, l + 1) * TS2;
+      const T* Lrl = Lb + tile_off(lay, i, 0, nt, r, l + 1);
       const T* Wlk = Wb + tile_index(0, nt, l + 1, k) * TS2;
 #pragma unroll
       for (int u = 0; u < PER; u++) {
@@ -1821,7 +1849,7 @@ __global__ void __launch_bounds__(256) k_sinv_row(int r, const int64_t* __restri
   int c = r + 1;
   while (c < nt && f[c] > r) c++;
   if (c < nt) {
-    const T* Lcr = Lb + tile_index(0, nt, c, r) * TS2;
+    const T* Lcr = Lb + tile_off(lay, i, 0, nt, c, r);
     const T* Sck = Wb + tile_index(0, nt, c, k) * TS2;
 #pragma unroll
     for (int u = 0; u < PER; u++) {
@@ -1841,7 +1869,7 @@ __global__ void __launch_bounds__(256) k_sinv_row(int r, const int64_t* __restri
     }
     __syncthreads();
     if (cn < nt) {
-      const T* Lcr = Lb + tile_index(0, nt, cn, r) * TS2;
+      const T* Lcr = Lb + tile_off(lay, i, 0, nt, cn, r);
       const T* Sck = Wb + tile_index(0, nt, cn, k) * TS2;
 #pragma unroll
       for (int u = 0; u < PER; u++) {
@@ -2126,6 +2154,10 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
   __shared__ T s_x[S][TS];
   __shared__ T s_in[VIN_LDS ? NIN * TS2 : 1];
   __shared__ int s_task, s_lim;
+  // backward: per column of the current wait round, its profile entry and
+  // block base, read once by wave 0 instead of once per tile load
+  __shared__ int s_g[BWD ? 64 : 1];
+  __shared__ int64_t s_cb[BWD ? 64 : 1];
   const int tid = threadIdx.x;
   const int rg = tid & 15, cg = tid >> 4;
   const int epoch = *epoch_ptr;
@@ -2145,8 +2177,24 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
     const int* fp = prof ? prof + lay.toff[i] : nullptr;
     // is the block that row rs takes from block row cc inside the profile?
     auto live = [&](int rs, int cc) { return !fp || (BWD ? fp[cc] <= rs : fp[rs] <= cc); };
-    auto tile_of = [&](int rs, int cc) {
-      return base + (TRANS ? tile_index(KIND, nt, cc, rs) : tile_index(KIND, nt, rs, cc)) * TS2;
+    // block row rs takes from block row cc: forward (rs, cc) = row base of
+    // rs + cc (row bases of the task's rows kept in registers); backward
+    // (cc, rs) of L or (rs, cc) of U, from the base of cc
+    const int64_t* trw = lay.trow ? lay.trow + lay.toff[i] : nullptr;
+    const int64_t* tcl = lay.tcol ? lay.tcol + lay.toff[i] : nullptr;
+    auto rowb = [&](int q) -> int64_t { return trw ? trw[q] : tile_index(KIND, nt, q, 0); };
+    int64_t rb[S];
+#pragma unroll
+    for (int q = 0; q < S; q++) rb[q] = (!BWD && q < cnt) ? rowb(r0 + step * q) : 0;
+    // base of block row cc for the backward blocks: (cc, rs) of L at
+    // rowb(cc) + rs, (rs, cc) of U at tcol(cc) + rs
+    auto colb = [&](int cc) -> int64_t { return TRANS ? rowb(cc) : (tcl ? tcl[cc] : (int64_t)cc); };
+    const int64_t cstride = TRANS || tcl ? 1 : nt;
+    // q: the row's place in the task (rs = r0 + step q); cb = colb(cc) for backward
+    auto tile_of = [&](int q, int cc, int64_t cb) {
+      const int rs = r0 + step * q;
+      const int64_t t = BWD ? cb + (int64_t)rs * cstride : rb[q] + cc;
+      return base + t * TS2;
     };
     // diagonal-tile inverses and the blocks between the task's rows -> registers
     V4 dv[S][4];
@@ -2182,7 +2230,7 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
         const bool on = s < cnt && live(rs, rq);
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-          const V4 v = on ? stream_load(reinterpret_cast<const V4*>(tile_of(rs, rq) + (cg + 16 * j) * TS + 4 * rg))
+          const V4 v = on ? stream_load(reinterpret_cast<const V4*>(tile_of(s, rq, BWD ? colb(rq) : 0) + (cg + 16 * j) * TS + 4 * rg))
                           : zero4;
           if (VIN_LDS)
             *vin_slot(s * (s - 1) / 2 + q, j) = v;
@@ -2206,6 +2254,9 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
       for (int q = 0; q < S; q++)
         if (q < cnt) c = min(c, fp[r0 + q]);
     }
+    int fr[S];  // forward: the profile entries of the task's rows
+#pragma unroll
+    for (int q = 0; q < S; q++) fr[q] = (!BWD && fp && q < cnt) ? fp[r0 + q] : 0;
     const int c_last = r0 - step;  // the previous task's last row: almost always the last dependency
     V4 vlast[PRE ? S : 1][4];
     if (PRE) {
@@ -2217,13 +2268,18 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
 #pragma unroll
         for (int j = 0; j < 4; j++)
           vlast[q][j] =
-              on ? stream_load(reinterpret_cast<const V4*>(tile_of(rs, c_last) + (cg + 16 * j) * TS + 4 * rg)) : zero4;
+              on ? stream_load(reinterpret_cast<const V4*>(tile_of(q, c_last, BWD ? colb(c_last) : 0) + (cg + 16 * j) * TS + 4 * rg)) : zero4;
       }
     }
     while (BWD ? (c > r0) : (c < r0)) {
       if (tid < 64) {
         // backward: the task's rows are r0 and below, so row cc is read only if g(cc) <= r0
-        const int lim = wait_rows<BWD>(c, r0, fl, epoch, BWD ? fp : nullptr, r0, err);
+        const int lim = wait_rows<BWD, BWD>(c, r0, fl, epoch, BWD ? fp : nullptr, r0, err);
+        if (BWD && tid < c - lim) {
+          const int cc = c - tid;
+          s_g[tid] = fp ? fp[cc] : 0;
+          s_cb[tid] = colb(cc);
+        }
         if (tid == 0) s_lim = lim;
       }
       __syncthreads();
@@ -2236,16 +2292,18 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
         for (int g = 0; g < G; g++) {
           const int cc = c + step * (d + g);
           const bool col_on = d + g < ncol;
+          const int64_t cb = BWD && col_on ? s_cb[d + g] : 0;
+          const int gc = BWD && col_on ? s_g[d + g] : 0;
 #pragma unroll
           for (int q = 0; q < S; q++) {
             const int rs = r0 + step * q;
-            const bool on = col_on && q < cnt && live(rs, cc);
+            const bool on = col_on && q < cnt && (BWD ? gc <= rs : fr[q] <= cc);
             const bool pre = PRE && cc == c_last;
 #pragma unroll
             for (int j = 0; j < 4; j++)
               v[g][q][j] = !on ? zero4
                                : (pre ? vlast[PRE ? q : 0][j]
-                                      : stream_load(reinterpret_cast<const V4*>(tile_of(rs, cc) + (cg + 16 * j) * TS +
+                                      : stream_load(reinterpret_cast<const V4*>(tile_of(q, cc, cb) + (cg + 16 * j) * TS +
                                                                                 4 * rg)));
           }
           const T* xc = xi + cc * TS;
@@ -2469,6 +2527,53 @@ void solve_begin(hipStream_t s, int* counters, const int* done) {
   TLS_LAUNCH_CHECK();
 }
 
+// The tile profiles of every A_ii (a pass of the gather loop that only
+// records, per tile row, the first tile column holding a nonzero of the
+// lower part, and for LU per tile column the first tile row of the upper
+// part), then the storage of the factors: the tiles inside the profiles,
+// row by row (for LU the strictly upper tiles column by column after the
+// rows). The full packed offsets are kept for the explicit inverses.
+static void profile_storage(tls_ctx* c, int stride) {
+  hipStream_t s = c->stream;
+  const int total = c->h_sub_ptr[c->N];
+  const LocalLayout lay = c->layout();
+  const int64_t colp = c->kind == 1 ? c->sum_nt : 0;
+  c->prof.alloc(c->sum_nt + colp);
+  hipLaunchKernelGGL(k_prof_init, dim3(c->N), dim3(256), 0, s, c->N, lay, colp, c->prof.p);
+  TLS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gather<float>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
+                     c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, c->row_ptr.p, c->col_idx.p, c->val.p,
+                     nullptr, lay, c->kind, (float*)nullptr, c->prof.p, colp);
+  TLS_LAUNCH_CHECK();
+  c->h_prof = download(c->prof.p, c->sum_nt + colp, s);
+  const int N = c->N;
+  c->h_soff = c->h_foff;
+  c->h_trow.assign(c->sum_nt, 0);
+  if (c->kind == 1) c->h_tcol.assign(c->sum_nt, 0);
+  for (int i = 0; i < N; i++) {
+    const int64_t t0 = c->h_toff[i];
+    int64_t cnt = 0;
+    // tile (r, c) at trow[r] + c (row storage), (r, c) above the diagonal
+    // at tcol[c] + r (LU, column storage)
+    for (int r = 0; r < c->h_nt[i]; r++) {
+      c->h_trow[t0 + r] = cnt - c->h_prof[t0 + r];
+      cnt += r - c->h_prof[t0 + r] + 1;
+    }
+    if (c->kind == 1)
+      for (int cc = 0; cc < c->h_nt[i]; cc++) {
+        c->h_tcol[t0 + cc] = cnt - c->h_prof[c->sum_nt + t0 + cc];
+        cnt += cc - c->h_prof[c->sum_nt + t0 + cc];
+      }
+    c->h_foff[i + 1] = c->h_foff[i] + cnt * TS2;
+  }
+  c->fac_elems = c->h_foff[N];
+  c->d_foff.upload(c->h_foff, s);
+  c->d_trow.upload(c->h_trow, s);
+  if (c->kind == 1) c->d_tcol.upload(c->h_tcol, s);
+  c->prof_store = true;
+  TLS_HIP(hipStreamSynchronize(s));
+}
+
 void gather_local(tls_ctx* c) {
   hipStream_t s = c->stream;
   const int total = c->h_sub_ptr[c->N];
@@ -2486,11 +2591,9 @@ void gather_local(tls_ctx* c) {
     if (download(c->errflag.p, 1, s)[0]) fail(TLS_E_NOT_SPD, "non-positive diagonal entry (Jacobi scaling)");
     scale = c->scale.p;
   }
+  if (!c->prof_store) profile_storage(c, stride);
+  lay = c->layout();
   const int64_t colp = c->kind == 1 ? c->sum_nt : 0;
-  c->prof.alloc(c->sum_nt + colp);
-  hipLaunchKernelGGL(k_prof_init, dim3(c->N), dim3(256), 0, s, c->N, lay, colp, c->prof.p);
-  TLS_LAUNCH_CHECK();
-  int* prof = c->prof.p;
   if (c->fp32) {
     c->fac32.alloc(c->fac_elems);
     TLS_HIP(hipMemsetAsync(c->fac32.p, 0, sizeof(float) * c->fac_elems, s));
@@ -2498,7 +2601,7 @@ void gather_local(tls_ctx* c) {
     TLS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gather<float>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
                        c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, c->row_ptr.p, c->col_idx.p,
-                       c->val.p, scale, lay, c->kind, c->fac32.p, prof, colp);
+                       c->val.p, scale, lay, c->kind, c->fac32.p, c->prof.p, colp);
   } else {
     c->fac64.alloc(c->fac_elems);
     TLS_HIP(hipMemsetAsync(c->fac64.p, 0, sizeof(double) * c->fac_elems, s));
@@ -2506,10 +2609,9 @@ void gather_local(tls_ctx* c) {
     TLS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gather<double>, dim3(div_up(total, 256)), dim3(256), 0, s, total, c->sub_idx.p,
                        c->sub_of_pos.p, c->sub_ptr.p, c->layer_ptr.p, stride, c->row_ptr.p, c->col_idx.p,
-                       c->val.p, scale, lay, c->kind, c->fac64.p, prof, colp);
+                       c->val.p, scale, lay, c->kind, c->fac64.p, c->prof.p, colp);
   }
   TLS_LAUNCH_CHECK();
-  c->h_prof = download(c->prof.p, c->sum_nt + colp, s);
   TLS_HIP(hipStreamSynchronize(s));
 }
 
@@ -2956,11 +3058,39 @@ inline InverseFlops inverse_flops(const std::vector<int>& nt, const int* prof, c
 template <class T>
 void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const LocalLayout& lay, T* fac,
                         const T* dinv, const int* prof = nullptr, const std::vector<int64_t>* foff = nullptr,
-                        DBuf<T>* fac_buf = nullptr) {
+                        DBuf<T>* fac_buf = nullptr, bool must_swap = false) {
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
   const int64_t budget = (int64_t)(0.9 * (double)devmem::available() / sizeof(T));
+  if (prof && fac_buf && N > 0 && must_swap) {
+    // profile storage: the factors cannot hold the full inverses, which are
+    // formed in a buffer of their own with the full packed offsets (the
+    // result's layout) and then take the factors' place; the subdomains go
+    // in groups that fit the memory budget, each straight into its place
+    const int64_t need = (*foff)[N - 1] + tiles_of(0, nt[N - 1]) * TS2;
+    DBuf<int64_t> d_woff;
+    d_woff.upload(*foff, s);
+    DBuf<T> W;
+    W.alloc(need);
+    const int64_t room = std::max<int64_t>((int64_t)(0.9 * (double)devmem::available() / sizeof(T)), 1);
+    std::vector<int> g;
+    int64_t tot = 0;
+    for (int a = 0; a <= N; a++) {
+      const int64_t e = a < N ? tiles_of(0, nt[order[a]]) * TS2 : 0;
+      if (a == N || (!g.empty() && tot + e > room)) {
+        inverse_group_profile<T>(s, g, nt, lay, d_woff.p, *foff, *foff, fac, dinv, W.p, prof, false);
+        g.clear();
+        tot = 0;
+      }
+      if (a < N) {
+        g.push_back(order[a]);
+        tot += e;
+      }
+    }
+    fac_buf->swap(W);
+    return;
+  }
   if (prof && fac_buf && N > 0) {
     const int64_t need = (*foff)[N - 1] + tiles_of(0, nt[N - 1]) * TS2;
     if (need <= budget) {
@@ -3088,22 +3218,34 @@ bool inverse_pays(const tls_ctx* c) {
   if (c->kind != 0) return false;
   int64_t f, b, d;
   solve_tile_counts(c, &f, &b, &d);
-  return f + b > d;
+  // the inverses need a full packed buffer beside the profile-stored factors
+  const double need = (double)d * TS2 * (c->fp32 ? 4 : 8);
+  return f + b > d && need <= 0.9 * (double)devmem::available();
 }
 
 void form_local_inverse(tls_ctx* c) {
   if (c->kind != 0) fail(TLS_E_ARG, "local_inverse applies to SPD matrices only");
   hipStream_t s = c->stream;
-  // the profile variant when it saves at least half of the arithmetic
+  // the profile variant when the factors are stored by profile, or when it
+  // saves at least half of the arithmetic
+  const bool ps = c->prof_store;
   const InverseFlops fl = inverse_flops(c->h_nt, c->h_prof.empty() ? nullptr : c->h_prof.data(), c->h_toff);
-  const bool use_prof = !c->h_prof.empty() && fl.profile < 0.5 * fl.dense;
+  const bool use_prof = ps || (!c->h_prof.empty() && fl.profile < 0.5 * fl.dense);
   c->flops_inverse = use_prof ? fl.profile : fl.dense;
   const int* prof = use_prof ? c->prof.p : nullptr;
+  // the inverses fill the full packed triangles (offsets h_soff with profile storage)
+  const std::vector<int64_t>* so = ps ? &c->h_soff : &c->h_foff;
   if (c->fp32)
-    form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, prof, &c->h_foff, &c->fac32);
+    form_inverse_tiles<float>(s, c->N, c->h_nt, c->layout(), c->fac32.p, c->dinv32.p, prof, so, &c->fac32, ps);
   else
-    form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, prof, &c->h_foff,
-                               &c->fac64);
+    form_inverse_tiles<double>(s, c->N, c->h_nt, c->layout(), c->fac64.p, c->dinv64.p, prof, so, &c->fac64, ps);
+  if (ps) {
+    // the storage now holds the inverses, in the full packed layout
+    c->prof_store = false;
+    c->h_foff = c->h_soff;
+    c->fac_elems = c->h_foff[c->N];
+    c->d_foff.upload(c->h_foff, s);
+  }
   build_symv_work(c->inv_work, s, c->N, c->h_nt, c->h_foff, c->h_voff, c->fp32, c->symv_block);
   c->inv_formed = true;
 }

@@ -46,6 +46,7 @@ struct EigLayout {
   const int64_t* o_TT;   // nT*nT
   const int64_t* o_X;    // M_i x 64 nq_i right-hand-side blocks (general: H)
   const int* kreq;
+  LocalLayout fl;        // the factors' storage (tile profiles)
 };
 
 // Blocks of the local factor copied to dense column-major buffers.
@@ -81,18 +82,22 @@ __global__ void k_extract(int mode, EigLayout e, const S* __restrict__ fac, D* o
   const int64_t total = (int64_t)rows * cols;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     int a = (int)(x % rows), b = (int)(x / rows);
+    // element (r, q) of the factor, zero where its tile is not stored
+    auto el = [&](int r, int q) -> S {
+      return tile_in(e.fl, i, kind, r / TS, q / TS) ? *elem_ptr_l(base, e.fl, i, kind, nt, r, q) : S(0);
+    };
     S v = S(0);
     switch (mode) {
-      case 0: v = -*elem_ptr(base, kind, nt, nP + b, a); break;
-      case 1: v = *elem_ptr(base, kind, nt, nP + b, nI + a); break;
-      case 2: v = b >= a ? *elem_ptr(base, kind, nt, nI + b, nI + a) : S(0); break;
-      case 3: v = *elem_ptr(base, kind, nt, nI + a, b); break;
-      case 4: v = a >= b ? *elem_ptr(base, kind, nt, nP + a, nP + b) : S(0); break;
-      case 5: v = b >= a ? *elem_ptr(base, kind, nt, nP + b, nP + a) : S(0); break;
-      case 6: v = *elem_ptr(base, kind, nt, nI + a, nP + b); break;
-      case 7: v = b >= a ? *elem_ptr(base, kind, nt, nI + a, nI + b) : S(0); break;
-      case 8: v = *elem_ptr(base, kind, nt, a, nI + b); break;
-      default: v = -*elem_ptr(base, kind, nt, a, nP + b); break;
+      case 0: v = -el(nP + b, a); break;
+      case 1: v = el(nP + b, nI + a); break;
+      case 2: v = b >= a ? el(nI + b, nI + a) : S(0); break;
+      case 3: v = el(nI + a, b); break;
+      case 4: v = a >= b ? el(nP + a, nP + b) : S(0); break;
+      case 5: v = b >= a ? el(nP + b, nP + a) : S(0); break;
+      case 6: v = el(nI + a, nP + b); break;
+      case 7: v = b >= a ? el(nI + a, nI + b) : S(0); break;
+      case 8: v = el(a, nI + b); break;
+      default: v = -el(a, nP + b); break;
     }
     out[off + a + (int64_t)b * ld] = (D)v;
   }
@@ -117,7 +122,9 @@ __global__ void __launch_bounds__(256) k_extract_f(EigLayout e, const T* __restr
     for (int x = threadIdx.x; x < TS2; x += 256) {
       const int bb = x % TS, aa = x / TS;  // factor element (nP + B0 + bb, A0 + aa)
       const int a = A0 + aa, b = B0 + bb;
-      t[aa][bb] = (a < nI && b < nT) ? -*elem_ptr(base, 0, nt, nP + b, a) : T(0);
+      t[aa][bb] = (a < nI && b < nT && tile_in(e.fl, i, 0, (nP + b) / TS, a / TS))
+                      ? -*elem_ptr_l(base, e.fl, i, 0, nt, nP + b, a)
+                      : T(0);
     }
     __syncthreads();
     for (int x = threadIdx.x; x < TS2; x += 256) {
@@ -681,7 +688,7 @@ struct PassDev {
   }
   EigLayout layout(const tls_ctx* c) const {
     return EigLayout{nI.p, nG.p, nT.p, c->d_m.p, c->d_nt.p, c->d_foff.p, oF.p, oGI.p, oTG.p, oGG.p, oTT.p, oXH.p,
-                     kreq.p};
+                     kreq.p, c->layout()};
   }
 };
 
