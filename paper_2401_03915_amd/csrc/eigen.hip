@@ -1193,19 +1193,13 @@ static void basis_spd(tls_ctx* c, T* fac) {
   finish_basis<T>(c, ncols, colval, colsrc, coff, c->d_voff, c->sum_M, XV.p);
 }
 
-// General A (Section 6): H = rows I of -A_{O'O'}^{-1} A_{O'T}; the dominant
-// right singular vectors v of H from the Gram H^T H, coarse vectors H v.
+// One pass of the general basis over the subdomains with kreq > 0: H, its
+// Gram, the subspace iteration, and V = H v into XV at oXV[i].
 template <class T>
-static void basis_general(tls_ctx* c, T* fac) {
+static PassEig general_pass(tls_ctx* c, T* fac, const PassDims& d, double tau2, const std::vector<int64_t>& oXV,
+                            T* XV) {
   hipStream_t s = c->stream;
   const int N = c->N;
-  std::vector<int> nGv(N);
-  for (int i = 0; i < N; i++) nGv[i] = c->h_nP[i] - c->h_nI[i];
-  const PassDims d = pass_dims(c, nGv, c->nev, true);
-  if (d.kmax == 0) {
-    empty_basis(c);
-    return;
-  }
   const std::vector<int>& nI = d.nI;
   const std::vector<int>& nG = d.nG;
   const std::vector<int>& nT = d.nT;
@@ -1216,17 +1210,14 @@ static void basis_general(tls_ctx* c, T* fac) {
   const std::vector<int64_t>& oTT = d.oTT;
   const std::vector<int64_t>& oZv = d.oZv;
   std::vector<int> nqH(N, 0);
-  std::vector<int64_t> oXH(N + 1, 0), oXV(N + 1, 0);
+  std::vector<int64_t> oXH(N + 1, 0);
   for (int i = 0; i < N; i++) {
     const int64_t M = (int64_t)c->h_nt[i] * TS;
     nqH[i] = kreq[i] > 0 ? (nT[i] + TS - 1) / TS : 0;
     oXH[i + 1] = oXH[i] + M * TS * nqH[i];
-    oXV[i + 1] = oXV[i] + M * TS * (kreq[i] > 0 ? 1 : 0);
   }
   PassDev dv;
   dv.upload(d, oXH, s);
-  DBuf<int64_t> d_oXV;
-  d_oXV.upload(oXV, s);
   const EigLayout el = dv.layout(c);
   const dim3 eg(64, N);
   TLS_HIP(hipMemsetAsync(c->errflag.p, 0, sizeof(int), s));
@@ -1276,19 +1267,12 @@ static void basis_general(tls_ctx* c, T* fac) {
   GI.release();
   TG.release();
   GGt.release();
-  // sigma^2 > tau^2 when a threshold is given
-  const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;
   DBuf<double> zv;
   PassEig e = run_subspace(c, d, dv, C64, zv, tau2);
   C64.release();
-  c->eig_resid_max = e.resid_max;
-  c->eig_iters_max = e.iters_max;
-  c->eig_iters_mean = e.iters_sum / std::max(1, e.n_solved);
   // left singular directions: V = H v
-  DBuf<T> wT, XV;
+  DBuf<T> wT;
   wT.alloc(std::max<int64_t>(oZv[N], 1));
-  XV.alloc(std::max<int64_t>(oXV[N], 1));
-  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
   hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, (int64_t)oZv[N], zv.p, wT.p);
   TLS_LAUNCH_CHECK();
   std::vector<GemmDesc> gv;
@@ -1296,8 +1280,78 @@ static void basis_general(tls_ctx* c, T* fac) {
     const int M = c->h_nt[i] * TS;
     if (e.kf[i] > 0) gv.push_back(GemmDesc{nI[i], e.kf[i], nT[i], M, nT[i], oXH[i], oZv[i], oXV[i], (int64_t)M});
   }
-  batched_gemm<T>(s, gv, false, false, XH.p, wT.p, XV.p, T(1), T(0));
-  XH.release();
+  batched_gemm<T>(s, gv, false, false, XH.p, wT.p, XV, T(1), T(0));
+  TLS_HIP(hipStreamSynchronize(s));
+  return e;
+}
+
+// Peak device bytes of subdomain i in a general pass: H (M x nT rounded up
+// to whole tiles), the nT x nT Gram in T and FP64 with the subspace
+// iteration's working copy, the G blocks, the subspace blocks and the
+// singular vectors.
+static int64_t general_pass_bytes(const PassDims& d, int i, int64_t M, int64_t tsz) {
+  if (d.kreq[i] <= 0) return 0;
+  const int64_t tt = (int64_t)d.nT[i] * d.nT[i], nG = d.nG[i];
+  const int64_t nqH = (d.nT[i] + TS - 1) / TS;
+  return M * TS * nqH * tsz + tt * (24 + tsz) + nG * (nG + d.nI[i] + d.nT[i]) * tsz +
+         (d.oY[i + 1] - d.oY[i]) * 4 * 8 + (d.oZv[i + 1] - d.oZv[i]) * (8 + tsz);
+}
+
+// General A (Section 6): H = rows I of -A_{O'O'}^{-1} A_{O'T}; the dominant
+// right singular vectors v of H from the Gram H^T H, coarse vectors H v.
+// The passes run on groups of consecutive subdomains whose buffers fit in
+// 90% of the device memory still available (one group when all fit).
+template <class T>
+static void basis_general(tls_ctx* c, T* fac) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  std::vector<int> nGv(N);
+  for (int i = 0; i < N; i++) nGv[i] = c->h_nP[i] - c->h_nI[i];
+  const PassDims d = pass_dims(c, nGv, c->nev, true);
+  if (d.kmax == 0) {
+    empty_basis(c);
+    return;
+  }
+  std::vector<int64_t> oXV(N + 1, 0);
+  for (int i = 0; i < N; i++) oXV[i + 1] = oXV[i] + (int64_t)c->h_nt[i] * TS * TS * (d.kreq[i] > 0 ? 1 : 0);
+  DBuf<int64_t> d_oXV;
+  d_oXV.upload(oXV, s);
+  DBuf<T> XV;
+  XV.alloc(std::max<int64_t>(oXV[N], 1));
+  TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
+  // sigma^2 > tau^2 when a threshold is given
+  const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;
+  const int64_t budget = (int64_t)(0.9 * (double)devmem::available());
+  std::vector<std::pair<int, int>> groups;
+  int64_t acc = 0;
+  for (int i = 0; i < N; i++) {
+    const int64_t b = general_pass_bytes(d, i, (int64_t)c->h_nt[i] * TS, sizeof(T));
+    if (groups.empty() || acc + b > budget) {
+      groups.push_back({i, i});
+      acc = 0;
+    }
+    groups.back().second = i + 1;
+    acc += b;
+  }
+  PassEig e;
+  e.kf.assign(N, 0);
+  e.theta.assign(std::max(d.oth[N], 1), 0.0);
+  for (const auto& g : groups) {
+    const PassDims dg = groups.size() == 1 ? d : pass_restrict(d, g.first, g.second);
+    if (dg.kmax == 0) continue;
+    const PassEig eg = general_pass<T>(c, fac, dg, tau2, oXV, XV.p);
+    for (int i = g.first; i < g.second; i++) {
+      e.kf[i] = eg.kf[i];
+      for (int j = 0; j < eg.kf[i]; j++) e.theta[d.oth[i] + j] = eg.theta[dg.oth[i] + j];
+    }
+    e.resid_max = std::max(e.resid_max, eg.resid_max);
+    e.iters_max = std::max(e.iters_max, eg.iters_max);
+    e.iters_sum += eg.iters_sum;
+    e.n_solved += eg.n_solved;
+  }
+  c->eig_resid_max = e.resid_max;
+  c->eig_iters_max = e.iters_max;
+  c->eig_iters_mean = e.iters_sum / std::max(1, e.n_solved);
   // the reported value of a column is sigma = sqrt(eigenvalue of H^T H)
   std::vector<double> colval;
   std::vector<int> colsrc;

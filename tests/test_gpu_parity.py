@@ -1073,6 +1073,34 @@ def test_grouped_setup_is_bitwise_identical(monkeypatch, precision):
     assert np.array_equal(z0, z1)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_grouped_general_basis_is_bitwise_identical(monkeypatch, precision):
+    """With TLS_MEMORY_LIMIT=1 the Section 6 basis (H, its Gram, the
+    subspace iteration and V = H v) runs one subdomain at a time; the coarse
+    basis, its singular values and the preconditioner are bit for bit those
+    of the set-up that does all subdomains at once."""
+    torch = torch_cuda()
+    A, part = _cd_problem(96, 3, seed=5)
+    r = to_dev(np.random.default_rng(6).standard_normal(A.shape[0]))
+    out = []
+    for lim in (None, "1"):
+        if lim:
+            monkeypatch.setenv("TLS_MEMORY_LIMIT", lim)
+        say(f"grouped general basis: precision {precision}, limit {lim}")
+        pc = _pc(A, part, 2, 5, matrix_kind=1, precision=precision)
+        ex = pc.export(Z=True)
+        z = pc.apply(r)
+        torch.cuda.synchronize()
+        out.append((ex, z.cpu().numpy()))
+        pc.close()
+        monkeypatch.delenv("TLS_MEMORY_LIMIT", raising=False)
+    (e0, z0), (e1, z1) = out
+    assert e0["zcol_ptr"][-1] > 0
+    for key in ("zcol_ptr", "zsrc", "eigvals", "Z"):
+        assert np.array_equal(e0[key], e1[key]), key
+    assert np.array_equal(z0, z1)
+
+
 @pytest.mark.parametrize("local_inverse", [0, 1])
 def test_autotune_cache_reuse(tmp_path, local_inverse):
     """Every autotuned shape (factorization panel width; workgroups and task
