@@ -41,10 +41,15 @@ struct TlsError {
 // Freeing and allocating again the tens of GB a setup uses slowed the
 // kernels of the following setups several-fold (freed device memory is
 // cleared in the background and mapped again on the next allocation). The
-// blocks are kept per device; when an allocation fails, all kept blocks are
-// freed and the allocation is tried once more. Releasing a large block
-// waits for the device, as freeing it would, so no queued work still uses
-// it when it is handed out again.
+// blocks are kept per device. A request takes the smallest kept block that
+// holds it and is at most 1.25 times its size, else new memory; when the
+// device has no room left it takes any kept block that holds it (the set-up
+// that freed the blocks of one size often asks for slightly different
+// sizes next time), and only then are kept blocks freed, the largest first,
+// until the allocation succeeds. Each block handed out remembers its real
+// size, so a larger block returns to the pool whole. Releasing a large
+// block waits for the device, as freeing it would, so no queued work still
+// uses it when it is handed out again.
 // ---------------------------------------------------------------------------
 namespace devmem {
 constexpr size_t kMin = size_t(32) << 20;
@@ -53,6 +58,7 @@ constexpr size_t kGrain = size_t(2) << 20;
 struct Pool {
   std::mutex mu;
   std::map<int, std::multimap<size_t, void*>> free;  // device -> (size, block)
+  std::map<void*, size_t> used;                      // large block in use -> its real size
 };
 inline Pool& pool() {
   static Pool* p = new Pool;  // never destroyed: buffers may be released during process teardown
@@ -73,22 +79,36 @@ inline hipError_t alloc(void** p, size_t bytes) {
   const size_t want = rounded(bytes);
   int dev = 0;
   (void)hipGetDevice(&dev);
-  {
-    Pool& pl = pool();
-    std::lock_guard<std::mutex> lock(pl.mu);
+  Pool& pl = pool();
+  // a kept block of at least `want` bytes and at most `most` (under the lock)
+  auto take = [&](size_t most) {
     auto& fl = pl.free[dev];
     auto it = fl.lower_bound(want);
-    if (it != fl.end() && it->first <= want + want / 4) {  // no large block for a much smaller request
-      *p = it->second;
-      fl.erase(it);
-      return hipSuccess;
-    }
+    if (it == fl.end() || it->first > most) return false;
+    *p = it->second;
+    pl.used[it->second] = it->first;
+    fl.erase(it);
+    return true;
+  };
+  {
+    std::lock_guard<std::mutex> lock(pl.mu);
+    if (take(want + want / 4)) return hipSuccess;  // no large block for a much smaller request
   }
   hipError_t e = hipMalloc(p, want);
-  if (e != hipSuccess) {
+  while (e != hipSuccess) {
     (void)hipGetLastError();
-    trim();
+    std::lock_guard<std::mutex> lock(pl.mu);
+    if (take(SIZE_MAX)) return hipSuccess;
+    auto& fl = pl.free[dev];
+    if (fl.empty()) break;
+    auto last = std::prev(fl.end());
+    (void)hipFree(last->second);
+    fl.erase(last);
     e = hipMalloc(p, want);
+  }
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lock(pl.mu);
+    pl.used[*p] = want;
   }
   return e;
 }
@@ -127,7 +147,13 @@ inline void release(void* p, size_t bytes) {
   (void)hipGetDevice(&dev);
   Pool& pl = pool();
   std::lock_guard<std::mutex> lock(pl.mu);
-  pl.free[dev].insert({rounded(bytes), p});  // never more than the block holds
+  auto it = pl.used.find(p);
+  size_t size = rounded(bytes);
+  if (it != pl.used.end()) {
+    size = it->second;
+    pl.used.erase(it);
+  }
+  pl.free[dev].insert({size, p});
 }
 }  // namespace devmem
 
