@@ -41,7 +41,9 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # what the same counters read for a 1 GiB read + 1 GiB write elementwise copy
 # (--copy-probe). None whenever that kernel has changed since the counters
 # were taken.
-TRAFFIC = 1762249272
+# Keyed by the block rows per substitution task (the kernel the autotuner
+# picked: 1 -> k_trsv, 2..4 -> k_trsv_sr<float, MODE, rows>).
+TRAFFIC = {}
 # The same for k_symv<float, 8> (explicit local inverses, taken on cfg2 when
 # they were its default) and for the SpMV k_spmv<1280>.
 TRAFFIC_SYMV = 16347116314
@@ -298,6 +300,8 @@ def weak_scaling(N, steps, warmup, local_inverse):
         torch.cuda.synchronize()
         inf = pc.info()
         pc.close()
+        log(f"  setup {inf['t_setup'][7]:.1f} ms (factor {inf['t_setup'][2]:.1f}, basis {inf['t_setup'][3]:.1f}), "
+            f"solve {inf['t_solve']:.1f} ms, {it} its")
         return it, rr, st, inf
 
     tau = float(np.sqrt(WEAK_TAU2))
@@ -608,12 +612,12 @@ def main():
                 "launches_timed": mixed["n_profiled"], "reduce_launch_ms": round(t_bwd, 4)}
     else:
         mode_name = "FWD_L" if prob.spd else "FWD_UL"
-        fwd_kernel = (f"k_trsv_sr<float, {mode_name}, 2>" if mixed["solve_rows"] == 2
-                      else f"k_trsv<float, {mode_name}>")
+        rows = mixed["solve_rows"]
+        fwd_kernel = f"k_trsv_sr<float, {mode_name}, {rows}>" if rows > 1 else f"k_trsv<float, {mode_name}>"
         roof = {"bound": "hbm", "kernel": f"{fwd_kernel} (forward local solves of one apply, all subdomains)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": TRAFFIC if default_workload and mixed["solve_rows"] == 2 else None,
+                "traffic": TRAFFIC.get(rows) if default_workload else None,
                 "bytes_per_launch": bytes_launch, "launch_ms": round(t_fwd, 4),
                 "launches_timed": mixed["n_profiled"], "backward_launch_ms": round(t_bwd, 4),
                 "backward_bytes": 4.0 * 4096.0 * float(info["solve_tiles_bwd"]),

@@ -351,7 +351,10 @@ tls_status tls_gnn_loss_grad(tls_ctx* c, const float* weights, int32_t c_out, fl
 /* Free everything the context owns. NULL is ignored. Device blocks of
  * 32 MiB and more are not handed back to the driver but kept for the next
  * contexts of the process (freeing and mapping tens of GB per setup slowed
- * the following setups several-fold); tls_trim hands them back. */
+ * the following setups several-fold), except that the smallest kept blocks
+ * are handed back until 5% of the device's memory is free, so that other
+ * allocators of the process still find room; tls_trim hands them all
+ * back. */
 void tls_destroy(tls_ctx* c);
 
 /* Free the device blocks kept for reuse (all devices). Safe at any time:

@@ -426,6 +426,7 @@ void tls_destroy(tls_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   delete c;
+  tls::devmem::keep_headroom(0.05);
 }
 
 void tls_trim(void) { tls::devmem::trim(); }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -64,7 +65,13 @@ inline Pool& pool() {
   static Pool* p = new Pool;  // never destroyed: buffers may be released during process teardown
   return *p;
 }
-inline size_t rounded(size_t bytes) { return (bytes + kGrain - 1) / kGrain * kGrain; }
+// Sizes of 1 GiB and more are rounded up to whole 256 MiB: a set-up run
+// again asks for sizes that differ by a fraction of a percent (its groups
+// of subdomains can shift by one), which then still match the kept blocks.
+inline size_t rounded(size_t bytes) {
+  const size_t g = bytes >= (size_t(1) << 30) ? size_t(256) << 20 : kGrain;
+  return (bytes + g - 1) / g * g;
+}
 
 inline void trim() {
   Pool& pl = pool();
@@ -113,6 +120,28 @@ inline hipError_t alloc(void** p, size_t bytes) {
   return e;
 }
 
+// Free kept blocks of the current device, the smallest first, until the
+// driver has `frac` of the device's memory free again (or none are kept):
+// other allocators of the process (the framework that holds the inputs)
+// must still find room after a context is gone.
+inline void keep_headroom(double frac) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  Pool& pl = pool();
+  std::lock_guard<std::mutex> lock(pl.mu);
+  auto& fl = pl.free[dev];
+  while (!fl.empty()) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+    if ((double)fr >= frac * (double)tot) return;
+    (void)hipFree(fl.begin()->second);
+    fl.erase(fl.begin());
+  }
+}
+
 // Bytes that allocations on the current device can still obtain: what the
 // driver reports free plus the blocks kept here for reuse, capped by the
 // environment variable TLS_MEMORY_LIMIT (bytes) when it is set. Set-up steps
@@ -135,6 +164,16 @@ inline size_t available() {
     if (v > 0 && v < fr) fr = (size_t)v;
   }
   return fr;
+}
+
+// The memory a step that works on groups of subdomains may plan for: 90%
+// of available(), rounded down to whole 8 GiB once that is 64 GiB or more,
+// so that a set-up run again in the same process cuts the same groups
+// (and finds its kept blocks) though other allocators hold a little more.
+inline size_t budget() {
+  const double b = 0.9 * (double)available();
+  const double q = (double)(size_t(8) << 30);
+  return b >= 8.0 * q ? (size_t)(std::floor(b / q) * q) : (size_t)b;
 }
 
 inline void release(void* p, size_t bytes) {

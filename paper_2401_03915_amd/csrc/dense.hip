@@ -3049,8 +3049,9 @@ inline InverseFlops inverse_flops(const std::vector<int>& nt, const int* prof, c
 }
 
 // W holds the blocks of one group of subdomains at a time. The groups
-// (largest subdomains first) are cut so that W fits in 90% of the device
-// memory still available; when everything fits there is one group.
+// (largest subdomains first) are cut so that W fits in the memory budget
+// (devmem::budget, 90% of what is still available); when everything fits
+// there is one group.
 // With a profile (prof, device) and fac_buf, the buffer that holds the
 // factors with offsets foff: when W fits beside the factors it takes their
 // layout, the result is formed there and the two buffers are swapped (no
@@ -3062,7 +3063,7 @@ void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const 
   std::vector<int> order(N);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nt[a] > nt[b]; });
-  const int64_t budget = (int64_t)(0.9 * (double)devmem::available() / sizeof(T));
+  const int64_t budget = (int64_t)(devmem::budget() / sizeof(T));
   if (prof && fac_buf && N > 0 && must_swap) {
     // profile storage: the factors cannot hold the full inverses, which are
     // formed in a buffer of their own with the full packed offsets (the
@@ -3073,7 +3074,7 @@ void form_inverse_tiles(hipStream_t s, int N, const std::vector<int>& nt, const 
     d_woff.upload(*foff, s);
     DBuf<T> W;
     W.alloc(need);
-    const int64_t room = std::max<int64_t>((int64_t)(0.9 * (double)devmem::available() / sizeof(T)), 1);
+    const int64_t room = std::max<int64_t>((int64_t)(devmem::budget() / sizeof(T)), 1);
     std::vector<int> g;
     int64_t tot = 0;
     for (int a = 0; a <= N; a++) {

@@ -1030,8 +1030,8 @@ static int64_t spd_pass_bytes(const PassDims& d, int i, int64_t tsz) {
          (d.oY[i + 1] - d.oY[i]) * 4 * tsz + (d.oZv[i + 1] - d.oZv[i]) * (8 + tsz);
 }
 
-// spd_pass over groups of consecutive subdomains whose buffers fit in 90%
-// of the device memory still available (one group when all fit). The
+// spd_pass over groups of consecutive subdomains whose buffers fit in the
+// memory budget (devmem::budget; one group when all fit). The
 // learned warm start and its training targets work on all subdomains at
 // once, so a pass that uses them is not split.
 template <class T>
@@ -1039,7 +1039,7 @@ static PassEig spd_pass_grouped(tls_ctx* c, const T* fac, const PassDims& d, dou
                                 const std::vector<int>& colbase, T* XV, bool gevp2) {
   const int N = c->N;
   const bool whole = gevp2 && (c->opt.gnn_weights || c->opt.gnn_train);
-  const int64_t budget = (int64_t)(0.9 * (double)devmem::available());
+  const int64_t budget = (int64_t)devmem::budget();
   std::vector<std::pair<int, int>> groups;
   int64_t acc = 0;
   for (int i = 0; i < N; i++) {
@@ -1300,7 +1300,7 @@ static int64_t general_pass_bytes(const PassDims& d, int i, int64_t M, int64_t t
 // General A (Section 6): H = rows I of -A_{O'O'}^{-1} A_{O'T}; the dominant
 // right singular vectors v of H from the Gram H^T H, coarse vectors H v.
 // The passes run on groups of consecutive subdomains whose buffers fit in
-// 90% of the device memory still available (one group when all fit).
+// the memory budget (devmem::budget; one group when all fit).
 template <class T>
 static void basis_general(tls_ctx* c, T* fac) {
   hipStream_t s = c->stream;
@@ -1321,7 +1321,7 @@ static void basis_general(tls_ctx* c, T* fac) {
   TLS_HIP(hipMemsetAsync(XV.p, 0, sizeof(T) * std::max<int64_t>(oXV[N], 1), s));
   // sigma^2 > tau^2 when a threshold is given
   const double tau2 = c->opt.tau > 0 ? c->opt.tau * c->opt.tau : -1.0;
-  const int64_t budget = (int64_t)(0.9 * (double)devmem::available());
+  const int64_t budget = (int64_t)devmem::budget();
   std::vector<std::pair<int, int>> groups;
   int64_t acc = 0;
   for (int i = 0; i < N; i++) {
