@@ -35,15 +35,15 @@ if ROOT not in sys.path:
 METRIC = "time-to-solve (rel res 1e-8) + precond applies/s: mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
-# HBM bytes per launch of the dominant kernel (the forward substitution
-# k_trsv_sr<float, FWD_L, 2> on the default workload) from two rocprofv3
-# counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by
-# what the same counters read for a 1 GiB read + 1 GiB write elementwise copy
-# (--copy-probe). None whenever that kernel has changed since the counters
-# were taken.
-# Keyed by the block rows per substitution task (the kernel the autotuner
-# picked: 1 -> k_trsv, 2..4 -> k_trsv_sr<float, MODE, rows>).
-TRAFFIC = {}
+# HBM bytes per launch of the dominant kernel (the forward substitution on
+# the default workload) from two rocprofv3 counter runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), scaled by what the same counters read for a
+# 1 GiB read + 1 GiB write elementwise copy (--copy-probe). Keyed by the
+# block rows per substitution task, i.e. by the kernel the autotuner picked
+# (1 -> k_trsv, 2..4 -> k_trsv_sr<float, FWD_L, rows>); None for a kernel
+# without counters, and whenever that kernel has changed since they were
+# taken.
+TRAFFIC = {3: 1759081295, 2: 1763030123}
 # The same for k_symv<float, 8> (explicit local inverses, taken on cfg2 when
 # they were its default) and for the SpMV k_spmv<1280>.
 TRAFFIC_SYMV = 16347116314

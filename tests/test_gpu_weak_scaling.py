@@ -56,3 +56,22 @@ def test_weak_scaling_iterations_match_oracle():
             it_g, _ = _solve(p, nev, precision=0)
             say(f"weak scaling N={N} nev={nev}: oracle {it_o}, GPU {it_g}")
             assert abs(it_g - it_o) <= 1
+
+
+def test_weak_scaling_largest_grid_fits_and_stays_flat():
+    """N = 512 (197^3, 7.6M unknowns): its dense lower factor tiles would
+    need about 340 GB in FP32; stored inside the tile profiles they fit,
+    and the two-level count stays within 1.4 times that of N = 64 while the
+    eigen passes run on groups of subdomains."""
+    its, infs = {}, {}
+    for N in (64, 512):
+        p = weak_scaling_poisson_3d(N)
+        say(f"weak scaling N={N} n={p.A.shape[0]}")
+        its[N], infs[N] = _solve(p, CAP, tau=float(np.sqrt(TAU2)), precision=1, local_inverse=0)
+        say(f"  two-level {its[N]} (n_C {infs[N]['n_coarse']}, GC {infs[N]['gc']:.4f}), "
+            f"profile tiles {infs[N]['solve_tiles_fwd']} of {infs[N]['lower_tiles']} lower tiles")
+    inf = infs[512]
+    assert inf["lower_tiles"] * 64 * 64 * 4 > 300e9  # the dense lower triangles would not fit
+    assert inf["solve_tiles_fwd"] < 0.3 * inf["lower_tiles"]
+    assert its[512] <= 1.4 * its[64]
+    assert 1.0 < inf["gc"] < 1.01
