@@ -1086,7 +1086,10 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
   constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
   constexpr int U = TrsvUnroll<T>::v;
   typedef typename Vec4<T>::type V4;
-  __shared__ T s_red[16 * TS];
+  // partial sums: 16 rows of RP; the transposed modes store down a column
+  // (16 lanes, one per row), so their rows are padded to spread the banks
+  constexpr int RP = (MODE == BWD_LT) ? TS + 4 : TS;
+  __shared__ T s_red[16 * RP];
   __shared__ T s_rhs[TS];
   __shared__ int s_task, s_lim;
   __shared__ int s_g[BWD ? 64 : 1];
@@ -1261,16 +1264,16 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
     // reduce the partial sums into the right-hand side of the diagonal block
     if (!TRANS) {
 #pragma unroll
-      for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = acc[q];
+      for (int q = 0; q < 4; q++) s_red[cg * RP + 4 * rg + q] = acc[q];
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = acc[j];
+      for (int j = 0; j < 4; j++) s_red[rg * RP + cg + 16 * j] = acc[j];
     }
     __syncthreads();
     if (tid < 64) {
       T sum = T(0);
 #pragma unroll
-      for (int g = 0; g < 16; g++) sum += s_red[g * TS + tid];
+      for (int g = 0; g < 16; g++) sum += s_red[g * RP + tid];
       s_rhs[tid] = brow - sum;
     }
     __syncthreads();
@@ -1286,20 +1289,20 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
         a2[3] += dv[j].w * rv;
       }
 #pragma unroll
-      for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = a2[q];
+      for (int q = 0; q < 4; q++) s_red[cg * RP + 4 * rg + q] = a2[q];
     } else {
       const T r0 = s_rhs[4 * rg], r1 = s_rhs[4 * rg + 1], r2 = s_rhs[4 * rg + 2], r3 = s_rhs[4 * rg + 3];
 #pragma unroll
       for (int j = 0; j < 4; j++) a2[j] = dv[j].x * r0 + dv[j].y * r1 + dv[j].z * r2 + dv[j].w * r3;
 #pragma unroll
-      for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = a2[j];
+      for (int j = 0; j < 4; j++) s_red[rg * RP + cg + 16 * j] = a2[j];
     }
     __syncthreads();
     if (tid < 64) {
       const int lane = tid;
       T val = T(0);
 #pragma unroll
-      for (int g = 0; g < 16; g++) val += s_red[g * TS + lane];
+      for (int g = 0; g < 16; g++) val += s_red[g * RP + lane];
       if (MODE == FWD_UL) val += s_rhs[lane];  // unit diagonal of L
       store_shared(xi + r * TS + lane, val);
       __builtin_amdgcn_s_waitcnt(0);  // the coherent stores above have completed
@@ -2149,7 +2152,10 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
   constexpr bool VIN_LDS = S > 2;
   static_assert(S <= 2 || sizeof(T) == 4, "tasks of more than two rows are built for FP32 only");
   typedef typename Vec4<T>::type V4;
-  __shared__ T s_red[16 * TS];
+  // partial sums: 16 rows of RP; the transposed modes store down a column
+  // (16 lanes, one per row), so their rows are padded to spread the banks
+  constexpr int RP = (MODE == BWD_LT) ? TS + 4 : TS;
+  __shared__ T s_red[16 * RP];
   __shared__ T s_rhs[TS];
   __shared__ T s_x[S][TS];
   __shared__ T s_in[VIN_LDS ? NIN * TS2 : 1];
@@ -2361,16 +2367,16 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
       }
       if (!TRANS) {
 #pragma unroll
-        for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = acc[s][q];
+        for (int q = 0; q < 4; q++) s_red[cg * RP + 4 * rg + q] = acc[s][q];
       } else {
 #pragma unroll
-        for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = acc[s][j];
+        for (int j = 0; j < 4; j++) s_red[rg * RP + cg + 16 * j] = acc[s][j];
       }
       __syncthreads();
       if (tid < 64) {
         T sum = T(0);
 #pragma unroll
-        for (int g = 0; g < 16; g++) sum += s_red[g * TS + tid];
+        for (int g = 0; g < 16; g++) sum += s_red[g * RP + tid];
         s_rhs[tid] = brow[s] - sum;
       }
       __syncthreads();
@@ -2385,19 +2391,19 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
           a2[3] += dv[s][j].w * rv;
         }
 #pragma unroll
-        for (int q = 0; q < 4; q++) s_red[cg * TS + 4 * rg + q] = a2[q];
+        for (int q = 0; q < 4; q++) s_red[cg * RP + 4 * rg + q] = a2[q];
       } else {
         const T q0 = s_rhs[4 * rg], q1 = s_rhs[4 * rg + 1], q2 = s_rhs[4 * rg + 2], q3 = s_rhs[4 * rg + 3];
 #pragma unroll
         for (int j = 0; j < 4; j++) a2[j] = dv[s][j].x * q0 + dv[s][j].y * q1 + dv[s][j].z * q2 + dv[s][j].w * q3;
 #pragma unroll
-        for (int j = 0; j < 4; j++) s_red[rg * TS + cg + 16 * j] = a2[j];
+        for (int j = 0; j < 4; j++) s_red[rg * RP + cg + 16 * j] = a2[j];
       }
       __syncthreads();
       if (tid < 64) {
         T val = T(0);
 #pragma unroll
-        for (int g = 0; g < 16; g++) val += s_red[g * TS + tid];
+        for (int g = 0; g < 16; g++) val += s_red[g * RP + tid];
         if (MODE == FWD_UL) val += s_rhs[tid];  // unit diagonal of L
         s_x[s][tid] = val;
         store_shared(xi + (r0 + step * s) * TS + tid, val);
