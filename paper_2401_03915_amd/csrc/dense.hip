@@ -1046,8 +1046,10 @@ __device__ inline int wait_rows(int c, int stop, const int* fl, int epoch, const
     for (;;) {
       const int cc = lim + step * lane;
       const bool inr = BWD ? (cc > stop) : (cc < stop);
-      bool ok = false;
-      if (inr) ok = (g && g[cc] > need_row) || load_flag(&fl[cc]) == epoch;
+      // the profile entry and the flag are loaded together (one round trip)
+      const int gv = (inr && g) ? g[cc] : need_row;
+      const int fv = inr ? load_flag(&fl[cc]) : 0;
+      const bool ok = inr && (gv > need_row || fv == epoch);
       const uint64_t m = __ballot(ok);
       const int run = ~m == 0ull ? 64 : __builtin_ctzll(~m);
       lim += step * run;
