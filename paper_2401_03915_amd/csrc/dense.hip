@@ -1035,9 +1035,14 @@ constexpr long long SPIN_LIMIT = 1ll << 26;
 // row. Waits, within SPIN_LIMIT polls, until at least one row is
 // available. CAP: at most 64 rows are passed (one round), so the caller can
 // keep what the lanes read about those rows in a 64-entry table.
+// With CAP each lane also returns, for its row c + step * lane, the
+// profile entry (g_out; 0 without g) and the entry of the per-row table cb
+// (cb_out; 0 without cb), read in the same polls as the flags, so that
+// nothing more is loaded once the rows are ready.
 template <bool BWD, bool CAP = false>
 __device__ inline int wait_rows(int c, int stop, const int* fl, int epoch, const int* __restrict__ g, int need_row,
-                                int* err) {
+                                int* err, const int64_t* __restrict__ cb = nullptr, int* g_out = nullptr,
+                                int64_t* cb_out = nullptr) {
   const int lane = threadIdx.x & 63;
   constexpr int step = BWD ? -1 : 1;
   int lim = c;
@@ -1046,10 +1051,15 @@ __device__ inline int wait_rows(int c, int stop, const int* fl, int epoch, const
     for (;;) {
       const int cc = lim + step * lane;
       const bool inr = BWD ? (cc > stop) : (cc < stop);
-      // the profile entry and the flag are loaded together (one round trip)
-      const int gv = (inr && g) ? g[cc] : need_row;
+      // the profile entry, the table entry and the flag are loaded together (one round trip)
+      const int gv = (inr && g) ? g[cc] : 0;
+      const int64_t bv = (CAP && inr && cb) ? cb[cc] : 0;
       const int fv = inr ? load_flag(&fl[cc]) : 0;
-      const bool ok = inr && (gv > need_row || fv == epoch);
+      const bool ok = inr && ((g && gv > need_row) || fv == epoch);
+      if (CAP) {
+        if (g_out) *g_out = gv;
+        if (cb_out) *cb_out = bv;
+      }
       const uint64_t m = __ballot(ok);
       const int run = ~m == 0ull ? 64 : __builtin_ctzll(~m);
       lim += step * run;
@@ -1168,12 +1178,16 @@ __global__ void __launch_bounds__(256) k_trsv(const int4* __restrict__ tasks, in
     const T brow = tid < 64 ? xi[r * TS + tid] : T(0);
     while (BWD ? (c > r) : (c < r)) {
       if (tid < 64) {
-        const int lim = wait_rows<BWD, BWD>(c, r, fl, epoch, BWD ? fp : nullptr, r, err);
+        int gq = 0;
+        int64_t bq = 0;
+        const int lim =
+            wait_rows<BWD, BWD>(c, r, fl, epoch, BWD ? fp : nullptr, r, err, BWD ? (TRANS ? trw : tcl) : nullptr,
+                                &gq, &bq);
         if (BWD && tid < c - lim) {
           // each column's profile entry and block base, for all threads
           const int cc = c - tid;
-          s_g[tid] = fp ? fp[cc] : 0;
-          s_cb[tid] = TRANS ? rowb(cc) + r : (tcl ? tcl[cc] + r : (int64_t)r * nt + cc);
+          s_g[tid] = gq;
+          s_cb[tid] = TRANS ? (trw ? bq : tile_index(KIND, nt, cc, 0)) + r : (tcl ? bq + r : (int64_t)r * nt + cc);
         }
         if (tid == 0) s_lim = lim;
       }
@@ -2282,11 +2296,15 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
     while (BWD ? (c > r0) : (c < r0)) {
       if (tid < 64) {
         // backward: the task's rows are r0 and below, so row cc is read only if g(cc) <= r0
-        const int lim = wait_rows<BWD, BWD>(c, r0, fl, epoch, BWD ? fp : nullptr, r0, err);
+        int gq = 0;
+        int64_t bq = 0;
+        const int lim =
+            wait_rows<BWD, BWD>(c, r0, fl, epoch, BWD ? fp : nullptr, r0, err, BWD ? (TRANS ? trw : tcl) : nullptr,
+                                &gq, &bq);
         if (BWD && tid < c - lim) {
           const int cc = c - tid;
-          s_g[tid] = fp ? fp[cc] : 0;
-          s_cb[tid] = colb(cc);
+          s_g[tid] = gq;
+          s_cb[tid] = TRANS ? (trw ? bq : tile_index(KIND, nt, cc, 0)) : (tcl ? bq : (int64_t)cc);
         }
         if (tid == 0) s_lim = lim;
       }
