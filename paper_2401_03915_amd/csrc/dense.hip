@@ -2159,12 +2159,16 @@ __global__ void __launch_bounds__(256) k_trsv_sr(const int4* __restrict__ tasks,
   constexpr bool BWD = (MODE == BWD_LT || MODE == BWD_U);
   constexpr bool TRANS = (MODE == BWD_LT);
   constexpr int KIND = (MODE == FWD_UL || MODE == BWD_U) ? 1 : 0;
-  constexpr int G = TrsvUnroll<T>::v / S > 0 ? TrsvUnroll<T>::v / S : 1;  // columns whose tiles load together
+  // columns whose tiles load together: with three FP32 rows a task takes
+  // the previous task's three rows (its last dependencies) in one group, so
+  // that their tiles and values arrive in one round trip
+  constexpr int G = (sizeof(T) == 4 && S == 3) ? 3 : (TrsvUnroll<T>::v / S > 0 ? TrsvUnroll<T>::v / S : 1);
   constexpr int NIN = S * (S - 1) / 2;
-  // the last dependency's tiles preloaded in registers (FP32 up to 3 rows),
-  // the blocks between the task's rows in registers (2 rows) or in LDS
-  // (each thread keeps its own pieces there)
-  constexpr bool PRE = sizeof(T) == 4 && S <= 3;
+  // the last dependency's tiles preloaded in registers (FP32, 2 rows; with
+  // 3 rows that dependency loads in one group with the two before it), the
+  // blocks between the task's rows in registers (2 rows) or in LDS (each
+  // thread keeps its own pieces there)
+  constexpr bool PRE = sizeof(T) == 4 && S <= 2;
   constexpr bool VIN_LDS = S > 2;
   static_assert(S <= 2 || sizeof(T) == 4, "tasks of more than two rows are built for FP32 only");
   typedef typename Vec4<T>::type V4;
