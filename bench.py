@@ -43,7 +43,7 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 # (1 -> k_trsv, 2..4 -> k_trsv_sr<float, FWD_L, rows>); None for a kernel
 # without counters, and whenever that kernel has changed since they were
 # taken.
-TRAFFIC = {3: 1759081295, 2: 1763030123}
+TRAFFIC = {3: 1759144898, 2: 1763033267}
 # The same for k_symv<float, 8> (explicit local inverses, taken on cfg2 when
 # they were its default) and for the SpMV k_spmv<1280>.
 TRAFFIC_SYMV = 16347116314
