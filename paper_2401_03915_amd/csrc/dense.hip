@@ -149,9 +149,16 @@ __global__ void __launch_bounds__(64) k_potrf(int k, const int* __restrict__ ord
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < TS; j++) {
-    T v = row[j];
+    // four partial sums, so that the products of a row do not wait on each other
+    T v0 = row[j], v1 = T(0), v2 = T(0), v3 = T(0);
 #pragma unroll
-    for (int l = 0; l < j; l++) v -= row[l] * bcast(row[l], j);
+    for (int l = 0; l < j; l += 4) {
+      v0 -= row[l] * bcast(row[l], j);
+      if (l + 1 < j) v1 -= row[l + 1] * bcast(row[l + 1], j);
+      if (l + 2 < j) v2 -= row[l + 2] * bcast(row[l + 2], j);
+      if (l + 3 < j) v3 -= row[l + 3] * bcast(row[l + 3], j);
+    }
+    const T v = (v0 + v1) + (v2 + v3);
     T d = bcast(v, j);
     if (!(d > T(0))) {
       bad = true;
@@ -166,16 +173,24 @@ __global__ void __launch_bounds__(64) k_potrf(int k, const int* __restrict__ ord
     tile[b * TS + a] = row[b];
     Ls[a + b * L1] = (double)row[b];
   }
+  __shared__ double rdiag[TS];
+  __syncthreads();
+  rdiag[a] = 1.0 / Ls[a + a * L1];  // reciprocals of the diagonal, one per lane
   __syncthreads();
   const int j = a;
   T* out = dinv + (lay.toff[i] + k) * TS2 + (int64_t)j * TS;
   double x[TS];
 #pragma unroll
   for (int r = 0; r < TS; r++) {
-    double v = (r == j) ? 1.0 : 0.0;
+    double v0 = (r == j) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
 #pragma unroll
-    for (int l = 0; l < r; l++) v -= Ls[r + l * L1] * x[l];
-    x[r] = r < j ? 0.0 : v / Ls[r + r * L1];
+    for (int l = 0; l < r; l += 4) {
+      v0 -= Ls[r + l * L1] * x[l];
+      if (l + 1 < r) v1 -= Ls[r + (l + 1) * L1] * x[l + 1];
+      if (l + 2 < r) v2 -= Ls[r + (l + 2) * L1] * x[l + 2];
+      if (l + 3 < r) v3 -= Ls[r + (l + 3) * L1] * x[l + 3];
+    }
+    x[r] = r < j ? 0.0 : ((v0 + v1) + (v2 + v3)) * rdiag[r];
   }
 #pragma unroll
   for (int r = 0; r < TS; r++) out[r] = (T)x[r];
