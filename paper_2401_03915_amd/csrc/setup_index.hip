@@ -18,27 +18,40 @@ namespace {
 __global__ void k_validate(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
                            const double* __restrict__ v, const int* __restrict__ part, int N,
                            int* err, int* part_count) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (i == 0 && rp[0] != 0) atomicOr(err, ERR_CSR);
-  if (i == n - 1 && rp[n] != nnz) atomicOr(err, ERR_CSR);
-  int a = rp[i], b = rp[i + 1];
-  if (a < 0 || b < a || b > nnz) {
-    atomicOr(err, ERR_CSR);
-  } else {
-    int prev = -1;
-    for (int j = a; j < b; j++) {
-      int c = ci[j];
-      if (c < 0 || c >= n || c <= prev) atomicOr(err, ERR_CSR);
-      prev = c;
-      if (!isfinite(v[j])) atomicOr(err, ERR_NAN);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int p = -1;
+  if (i < n) {
+    if (i == 0 && rp[0] != 0) atomicOr(err, ERR_CSR);
+    if (i == n - 1 && rp[n] != nnz) atomicOr(err, ERR_CSR);
+    int a = rp[i], b = rp[i + 1];
+    if (a < 0 || b < a || b > nnz) {
+      atomicOr(err, ERR_CSR);
+    } else {
+      int prev = -1;
+      for (int j = a; j < b; j++) {
+        int c = ci[j];
+        if (c < 0 || c >= n || c <= prev) atomicOr(err, ERR_CSR);
+        prev = c;
+        if (!isfinite(v[j])) atomicOr(err, ERR_NAN);
+      }
+    }
+    p = part[i];
+    if (p < 0 || p >= N) {
+      atomicOr(err, ERR_PART);
+      p = -1;
     }
   }
-  int p = part[i];
-  if (p < 0 || p >= N)
-    atomicOr(err, ERR_PART);
-  else
-    atomicAdd(&part_count[p], 1);
+  // rows of one wave mostly share their part: one atomic per distinct part
+  // of the wave instead of one per row (the counters are few and hot)
+  const int lane = threadIdx.x & 63;
+  uint64_t left = __ballot(p >= 0);
+  while (left) {
+    const int lead = __builtin_ctzll(left);
+    const int pl = __shfl(p, lead);
+    const uint64_t same = __ballot(p == pl) & left;
+    if (lane == lead) atomicAdd(&part_count[pl], __popcll(same));
+    left &= ~same;
+  }
 }
 
 __global__ void k_count_cols(int nnz, const int* __restrict__ ci, int* cnt) {
