@@ -236,6 +236,23 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// Eight sums at once over the 256 threads of the block (red: 32 values);
+// every thread gets the totals.
+__device__ inline void block_sum8(double (&v)[8], double* red) {
+#pragma unroll
+  for (int m = 0; m < 8; m++)
+    for (int o = 32; o > 0; o >>= 1) v[m] += __shfl_xor(v[m], o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int m = 0; m < 8; m++) red[w * 8 + m] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 8; m++) v[m] = red[m] + red[8 + m] + red[16 + m] + red[24 + m];
+  __syncthreads();
+}
+
 // Cyclic Jacobi on the symmetric p x p matrix H (LDS, leading dim PMAX) with
 // round-robin parallel ordering; S accumulates the rotations.
 __device__ void jacobi_eig(double* H, double* S, int p, double* cs, double* red) {
@@ -564,12 +581,15 @@ __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const
                                               const double* __restrict__ scale,
                                               const int64_t* __restrict__ zoff, double* Z, int* kfinal,
                                               int* keep_idx) {
-  __shared__ double red[16];
+  __shared__ double red[32];
+  __shared__ double dsh[KMAX];
   const int i = blockIdx.x;
   const int nI = nI_[i], k = kf_[i];
   double* Zi = Z + zoff[i];
   const int tid = threadIdx.x;
   int kept = 0;
+  // every thread reads and writes only its own rows r = tid + 256 m of the
+  // columns, so only the reductions need barriers
   for (int a = 0; a < k; a++) {
     double* v = Zi + (int64_t)kept * nI;
     double n0 = 0.0;
@@ -580,15 +600,33 @@ __global__ void __launch_bounds__(256) k_orth(const int* __restrict__ nI_, const
       n0 += x * x;
     }
     n0 = sqrt(block_sum(n0, red));
-    for (int pass = 0; pass < 2; pass++) {
-      for (int b = 0; b < kept; b++) {
-        const double* q = Zi + (int64_t)b * nI;
-        double d = 0.0;
-        for (int r = tid; r < nI; r += 256) d += q[r] * v[r];
-        d = block_sum(d, red);
-        for (int r = tid; r < nI; r += 256) v[r] -= d * q[r];
-        __syncthreads();
+    // classical Gram-Schmidt, twice: all projections of a pass from one set
+    // of dot products (eight per sweep and reduction), then one update sweep
+    for (int pass = 0; pass < 2 && kept > 0; pass++) {
+      for (int b0 = 0; b0 < kept; b0 += 8) {
+        double pd[8];
+#pragma unroll
+        for (int m = 0; m < 8; m++) pd[m] = 0.0;
+        for (int r = tid; r < nI; r += 256) {
+          const double vr = v[r];
+#pragma unroll
+          for (int m = 0; m < 8; m++)
+            if (b0 + m < kept) pd[m] += Zi[(int64_t)(b0 + m) * nI + r] * vr;
+        }
+        block_sum8(pd, red);
+        if (tid == 0)
+#pragma unroll
+          for (int m = 0; m < 8; m++)
+            if (b0 + m < kept) dsh[b0 + m] = pd[m];
       }
+      __syncthreads();
+      for (int r = tid; r < nI; r += 256) {
+        double acc = v[r];
+#pragma unroll 4
+        for (int b = 0; b < kept; b++) acc -= dsh[b] * Zi[(int64_t)b * nI + r];
+        v[r] = acc;
+      }
+      __syncthreads();
     }
     double nr = 0.0;
     for (int r = tid; r < nI; r += 256) nr += v[r] * v[r];
