@@ -326,15 +326,6 @@ __device__ inline int64_t tile_off(const LocalLayout& lay, int i, int kind, int 
   if (kind == 0 || r >= c) return (lay.trow[t0 + r] + c) * TS2;
   return (lay.tcol[t0 + c] + r) * TS2;
 }
-// Tile index of (r, c) = row_tile0(r) + c on and below the diagonal (any
-// storage); above it, for LU, (r, c) = ucol_tile0(c) + r * ucol_stride.
-__device__ inline int64_t row_tile0(const LocalLayout& lay, int i, int kind, int nt, int r) {
-  return lay.trow ? lay.trow[lay.toff[i] + r] : tile_index(kind, nt, r, 0);
-}
-__device__ inline int64_t ucol_tile0(const LocalLayout& lay, int i, int c) {
-  return lay.tcol ? lay.tcol[lay.toff[i] + c] : (int64_t)c;
-}
-__device__ inline int64_t ucol_stride(const LocalLayout& lay, int nt) { return lay.tcol ? 1 : nt; }
 // Is tile (r, c) stored (always, without profile storage)?
 __device__ inline bool tile_in(const LocalLayout& lay, int i, int kind, int r, int c) {
   if (!lay.trow) return true;
