@@ -187,6 +187,7 @@ def run_mode(prob, dev_in, precision, steps, warmup, n_applies, use_graph, tune_
         "n_profiled": pinfo["n_profiled"],
         "solve_wgs": pinfo["solve_wgs"],
         "solve_order": pinfo["solve_order"],
+        "solve_order_bwd": pinfo["solve_order_bwd"],
         "solve_rows": pinfo["solve_rows"],
         "tuned": pinfo["tuned"],
         "apply_ms_profiled": pinfo["t_apply_ms"],
@@ -624,6 +625,7 @@ def main():
                 "backward_GBps": round(4.0 * 4096.0 * float(info["solve_tiles_bwd"]) / (t_bwd * 1e-3) / 1e9, 1)
                 if t_bwd > 0 else None,
                 "solve_wgs": mixed["solve_wgs"], "solve_order": mixed["solve_order"],
+                "solve_order_bwd": mixed["solve_order_bwd"],
                 "solve_rows": mixed["solve_rows"]}
     def mfma(mode, dt):
         # flops: the library's count of what it ran (SPD: the tiles inside

@@ -117,12 +117,13 @@ typedef struct {
   int32_t solve_wgs;    /* workgroups of the persistent triangular solves (0 = default) */
   int32_t solve_order;  /* task order of those solves: 1 level by level, 2 by the fraction of
                            the subdomain's rows done, 3 longest chain first, 4 / 5 as 2 with a
-                           lead of 0.3 / 0.6 x nt_i / max nt for large subdomains; 0 = default (4) */
+                           lead of 0.3 / 0.6 x nt_i / max nt for large subdomains; 0 = default (4);
+                           when set, both directions use it */
   int32_t autotune;     /* 1: at setup, time candidates and keep the fastest: the panel width of
                            the batched factorization (4, 8 or 16 tiles), the block side of the
                            product with the local inverses (4, 6 or 8 tiles), and the workgroup
-                           count, task order and rows per task of the persistent solves (not
-                           when solve_wgs or solve_order is set) */
+                           count, rows per task and, per direction, the task order of the
+                           persistent solves (not when solve_wgs or solve_order is set) */
   const char* tune_cache; /* text file of earlier autotune picks (read, then appended);
                              NULL = no persistence. A cached pick is reused without timing. */
   /* Learned warm start (SPD only): host array of TLS_GNN_NWEIGHTS(gnn_c_out)
@@ -205,7 +206,7 @@ typedef struct {
   double t_local_fwd_ms;      /* mean duration of their forward-substitution (or
                                  symmetric-product) kernel alone             */
   int32_t solve_wgs;          /* workgroups used by the persistent solves     */
-  int32_t solve_order;        /* task order used by those solves (1 .. 5)     */
+  int32_t solve_order;        /* task order of the forward solves (1 .. 5)    */
   int32_t tuned;              /* 0 default, 1 timed at setup, 2 read from the cache */
   const double* res_history;  /* host array: ||r_k|| / ||b|| per iteration   */
   int32_t local_inverse;      /* 1 if the local solves use explicit inverses  */
@@ -234,6 +235,8 @@ typedef struct {
   int64_t lower_tiles;        /* lower tiles of all local factors, sum nt_i (nt_i + 1) / 2
                                  (what the product with explicit inverses reads) */
   int32_t solve_rows;         /* block rows per task of the persistent substitutions */
+  int32_t solve_order_bwd;    /* task order of the backward solves (1 .. 5; the
+                                 autotuner picks each direction's own)        */
 } tls_info_t;
 
 /* Fill *opt with the defaults listed above. */

@@ -113,6 +113,7 @@ class tls_info_t(C.Structure):
         ("solve_tiles_bwd", C.c_int64),
         ("lower_tiles", C.c_int64),
         ("solve_rows", C.c_int32),
+        ("solve_order_bwd", C.c_int32),
     ]
 
 

@@ -282,6 +282,7 @@ tls_status tls_info(const tls_ctx* c, tls_info_t* info) {
   info->inverse_flops = c->inv_formed ? c->flops_inverse : 0.0;
   tls::solve_tile_counts(c, &info->solve_tiles_fwd, &info->solve_tiles_bwd, &info->lower_tiles);
   info->solve_rows = c->solve_rows;
+  info->solve_order_bwd = c->solve_order_b;
   tls_ctx* cm = const_cast<tls_ctx*>(c);
   bool wt = cm->apply_wait_seen;
   if (guard(cm, [&]() { wt = tls::take_wait_flag(cm) || wt; }) != TLS_OK) return TLS_E_HIP;

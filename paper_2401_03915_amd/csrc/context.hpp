@@ -78,8 +78,9 @@ struct tls_ctx {
   tls::SolvePlan plan_fwd, plan_bwd;
   tls::DBuf<int> counters;  // [0] fwd task counter, [1] bwd task counter, [2] epoch
   int solve_grid = 1024;
-  int solve_order = 4;
-  int solve_rows = 1;  // block rows per substitution task (1 or 2)
+  int solve_order = 4;    // task order of the forward plan
+  int solve_order_b = 4;  // and of the backward plan
+  int solve_rows = 1;     // block rows per substitution task
 
   // work vectors for the apply (padded local layout)
   tls::DBuf<double> xloc64;

@@ -2787,7 +2787,8 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
   TLS_HIP(hipStreamSynchronize(s));
 }
 
-void build_local_plans(tls_ctx* c, int order, int rows) {
+void build_local_plans(tls_ctx* c, int order, int rows, int order_b) {
+  if (order_b <= 0) order_b = order;
   // tiles each row reads inside the profiles: forward r - f(r), backward
   // the rows c > r whose profile g reaches r (g = f for Cholesky, the
   // column profile of U for LU)
@@ -2806,8 +2807,9 @@ void build_local_plans(tls_ctx* c, int order, int rows) {
     }
   }
   build_plan(c->plan_fwd, false, c->h_nt, c->h_toff, order, c->stream, rows, wf.empty() ? nullptr : &wf);
-  build_plan(c->plan_bwd, true, c->h_nt, c->h_toff, order, c->stream, rows, wb.empty() ? nullptr : &wb);
+  build_plan(c->plan_bwd, true, c->h_nt, c->h_toff, order_b, c->stream, rows, wb.empty() ? nullptr : &wb);
   c->solve_order = order;
+  c->solve_order_b = order_b;
   c->solve_rows = rows;
 }
 

@@ -60,8 +60,9 @@ void build_plan(SolvePlan& p, bool bwd, const std::vector<int>& nt, const std::v
 // mode: 0 L y = b (Cholesky), 1 L^T x = y, 2 unit-lower L y = b (LU), 3 U x = y
 void trsv_f64(hipStream_t s, int mode, SolvePlan& p, int* counter, const int* epoch, const LocalLayout& lay,
               const double* fac, const double* dinv, double* x, int* err, const int* done, int grid);
-// (re)build the local plans for a task ordering
-void build_local_plans(tls_ctx* c, int order, int rows);
+// (re)build the local plans for a task ordering (order_b: the backward
+// plan's, 0 = the same as the forward's)
+void build_local_plans(tls_ctx* c, int order, int rows, int order_b = 0);
 void solve_begin(hipStream_t s, int* counters, const int* done);
 
 // eigen.hip: coarse basis (eq. gevpsvd / Section 6)

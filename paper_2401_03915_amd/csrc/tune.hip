@@ -36,7 +36,7 @@ namespace {
 
 std::string tune_key(const tls_ctx* c) {
   std::ostringstream k;
-  k << "trsv:v6 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
+  k << "trsv:v7 prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
     << " sumM=" << c->sum_M << " maxnt=" << c->max_nt;
   return k.str();
 }
@@ -82,6 +82,33 @@ std::string shape_key(const tls_ctx* c, const char* what) {
   k << what << " prec=" << (c->fp32 ? 32 : 64) << " kind=" << c->kind << " N=" << c->N << " n=" << c->n
     << " sumM=" << c->sum_M << " maxnt=" << c->max_nt;
   return k.str();
+}
+
+// Mean forward and backward times (ms) of reps local solves.
+void time_local_dirs(tls_ctx* c, int grid, int reps, double* tf, double* tb) {
+  const int keep = c->solve_grid;
+  c->solve_grid = grid;
+  hipEvent_t e0, e1, e2;
+  TLS_HIP(hipEventCreate(&e0));
+  TLS_HIP(hipEventCreate(&e1));
+  TLS_HIP(hipEventCreate(&e2));
+  local_solve(c, c->zero_int.p);  // warm-up
+  double f = 0.0, b = 0.0;
+  for (int k = 0; k < reps; k++) {
+    local_solve(c, c->zero_int.p, e0, e1, e2);
+    TLS_HIP(hipEventSynchronize(e2));
+    float m1 = 0.f, m2 = 0.f;
+    TLS_HIP(hipEventElapsedTime(&m1, e0, e1));
+    TLS_HIP(hipEventElapsedTime(&m2, e1, e2));
+    f += m1;
+    b += m2;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  c->solve_grid = keep;
+  *tf = f / reps;
+  *tb = b / reps;
 }
 
 double time_local_solves(tls_ctx* c, int grid, int reps) {
@@ -195,7 +222,8 @@ void choose_solve_grid(tls_ctx* c) {
   c->tuned = 0;
   const int rows0 = c->opt.solve_rows > 0 ? c->opt.solve_rows : 1;
   const int order0 = c->opt.solve_order > 0 ? c->opt.solve_order : c->solve_order;
-  if (order0 != c->solve_order || rows0 != c->solve_rows) build_local_plans(c, order0, rows0);
+  if (order0 != c->solve_order || order0 != c->solve_order_b || rows0 != c->solve_rows)
+    build_local_plans(c, order0, rows0);
   if (c->opt.solve_wgs > 0 || c->opt.solve_order > 0) {
     if (c->opt.solve_wgs > 0) c->solve_grid = c->opt.solve_wgs;
     return;
@@ -203,38 +231,54 @@ void choose_solve_grid(tls_ctx* c) {
   if (!c->opt.autotune || c->inv_formed) return;  // the symmetric product has no launch shape to tune
   // a solve_rows option fixes the rows per task; the rest is still tuned
   const std::string key = tune_key(c) + (c->opt.solve_rows > 0 ? " rows=" + std::to_string(c->opt.solve_rows) : "");
-  int v[3] = {0, 0, 0};
-  if (cache_lookup_ints(c->opt.tune_cache, key, v, 3) && v[0] > 0 && v[1] >= 1 && v[1] <= 5 && v[2] >= 1 &&
-      v[2] <= (c->fp32 ? 4 : 2)) {
+  int v[4] = {0, 0, 0, 0};
+  if (cache_lookup_ints(c->opt.tune_cache, key, v, 4) && v[0] > 0 && v[1] >= 1 && v[1] <= 5 && v[2] >= 1 &&
+      v[2] <= (c->fp32 ? 4 : 2) && v[3] >= 1 && v[3] <= 5) {
     c->solve_grid = v[0];
-    if (v[1] != c->solve_order || v[2] != c->solve_rows) build_local_plans(c, v[1], v[2]);
+    if (v[1] != c->solve_order || v[3] != c->solve_order_b || v[2] != c->solve_rows)
+      build_local_plans(c, v[1], v[2], v[3]);
     c->tuned = 2;
     return;
   }
+  // rows per task and workgroups are shared by both directions; each
+  // direction takes the task order that is fastest for it
   const int maxper = c->fp32 ? 7 : 3;
+  constexpr int NORD = 5;
   double best = 1e300;
-  int best_g = c->solve_grid, best_ch = c->solve_order, best_rows = c->solve_rows;
-  for (int rows : {1, 2, 3, 4})
-    for (int order : {1, 2, 3, 4, 5}) {
-      if (c->opt.solve_rows > 0 && rows != c->opt.solve_rows) continue;
-      if (!c->fp32 && rows > 2) continue;  // FP64 tasks hold at most two rows
+  int best_g = c->solve_grid, best_f = c->solve_order, best_b = c->solve_order_b, best_rows = c->solve_rows;
+  for (int rows : {1, 2, 3, 4}) {
+    if (c->opt.solve_rows > 0 && rows != c->opt.solve_rows) continue;
+    if (!c->fp32 && rows > 2) continue;  // FP64 tasks hold at most two rows
+    std::vector<int> grids;
+    for (int p = 2; p <= maxper; p += 2) grids.push_back(cus * std::min(p, maxper));
+    std::vector<double> tf(grids.size() * NORD, 1e300), tb(grids.size() * NORD, 1e300);
+    for (int order = 1; order <= NORD; order++) {
       build_local_plans(c, order, rows);
-      for (int p = 2; p <= maxper; p += 2) {
-        const int cg = cus * std::min(p, maxper);
-        double t = time_local_solves(c, cg, 3);
-        if (t < best) {
-          best = t;
-          best_g = cg;
-          best_ch = order;
-          best_rows = rows;
-        }
+      for (size_t g = 0; g < grids.size(); g++)
+        time_local_dirs(c, grids[g], 3, &tf[g * NORD + order - 1], &tb[g * NORD + order - 1]);
+    }
+    for (size_t g = 0; g < grids.size(); g++) {
+      int of = 1, ob = 1;
+      for (int o = 2; o <= NORD; o++) {
+        if (tf[g * NORD + o - 1] < tf[g * NORD + of - 1]) of = o;
+        if (tb[g * NORD + o - 1] < tb[g * NORD + ob - 1]) ob = o;
+      }
+      const double t = tf[g * NORD + of - 1] + tb[g * NORD + ob - 1];
+      if (t < best) {
+        best = t;
+        best_g = grids[g];
+        best_f = of;
+        best_b = ob;
+        best_rows = rows;
       }
     }
-  if (best_ch != c->solve_order || best_rows != c->solve_rows) build_local_plans(c, best_ch, best_rows);
+  }
+  if (best_f != c->solve_order || best_b != c->solve_order_b || best_rows != c->solve_rows)
+    build_local_plans(c, best_f, best_rows, best_b);
   c->solve_grid = best_g;
   c->tuned = 1;
-  const int pick[3] = {best_g, best_ch, best_rows};
-  cache_store_ints(c->opt.tune_cache, key, pick, 3);
+  const int pick[4] = {best_g, best_f, best_rows, best_b};
+  cache_store_ints(c->opt.tune_cache, key, pick, 4);
 }
 
 }  // namespace tls

@@ -1117,7 +1117,7 @@ def test_autotune_cache_reuse(tmp_path, local_inverse):
     i1 = pc1.info()
     lines = open(cache).read().splitlines()
     keys = sorted(line.split(" ")[0] for line in lines)
-    assert keys == (["factor:v1", "symv:v1"] if local_inverse else ["factor:v1", "trsv:v6"])
+    assert keys == (["factor:v1", "symv:v1"] if local_inverse else ["factor:v1", "trsv:v7"])
     pc2 = _pc(A, part, 2, 4, autotune=1, tune_cache=cache.encode(), local_inverse=local_inverse)
     i2 = pc2.info()
     assert open(cache).read().splitlines() == lines  # nothing timed or written again
@@ -1127,6 +1127,7 @@ def test_autotune_cache_reuse(tmp_path, local_inverse):
         assert i1["symv_block"] == i2["symv_block"] and i1["symv_block"] in (4, 6, 8)
     else:
         assert i1["solve_wgs"] == i2["solve_wgs"] > 0 and i1["solve_order"] == i2["solve_order"]
+        assert i1["solve_order_bwd"] == i2["solve_order_bwd"]
     r = to_dev(np.random.default_rng(4).standard_normal(A.shape[0]))
     z1, z2 = pc1.apply(r), pc2.apply(r)
     torch.cuda.synchronize()
